@@ -1,0 +1,985 @@
+/*
+ * dmr_oracle.c -- FP64 CPU oracle (test infrastructure only; see oracle.h).
+ *
+ * Plain loops, one array per quantity, no blocking or fusion.  Every
+ * function names the part of the paper it follows.  Where the paper is
+ * silent the reading used is stated at the function.
+ *
+ * Storage (private to this file): column-major in the sense a[i][j] with j
+ * fastest; Hz[nx][ny], Ex[nx][ny+1], Ey[nx+1][ny], nodes [nx+1][ny+1].
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* CODATA 2018 SI constants (the paper prints none). */
+static const double Q_E = 1.602176634e-19;
+static const double M_E = 9.1093837015e-31;
+static const double EPS_0 = 8.8541878128e-12;
+static const double C_0 = 299792458.0;
+static const double PI_ = 3.14159265358979323846;
+
+#define NRING 8 /* blocks per period in the E_rms window */
+
+typedef struct {
+  int nx, ny;
+  double dx, dt;
+  int spp, spb; /* steps per period, steps per window block */
+  /* update coefficients */
+  double ch, ce, a, b, kn, cmur;
+  double *hz, *ex, *ey, *jx, *jy, *n, *acc, *ring;
+} level_t;
+
+struct orc_sim {
+  orc_params p;
+  double omega, lambda, nu_m, n_c, eeff_fac, e0, d_e, d_a, n_amb, ktil, eta0;
+  double nu_att; /* nu_m*A*(E_cr/p)^beta */
+  level_t L0, L1;
+  int has_patch;
+  int ext[4]; /* I0, J0, I1, J1 base cells */
+  int64_t step;
+  int64_t blocks; /* window blocks closed so far */
+  double *ex_old, *ey_old, *hz_prev, *hz_sub1;
+  int NBx, NBy;
+  uint8_t *bflag;
+  int32_t *bscan, *blist, bcount;
+};
+
+/* ---- indexing ---------------------------------------------------------- */
+#define HZ(L, i, j) ((L)->hz[(size_t)(i) * (L)->ny + (j)])
+#define EX(L, i, j) ((L)->ex[(size_t)(i) * ((L)->ny + 1) + (j)])
+#define JX(L, i, j) ((L)->jx[(size_t)(i) * ((L)->ny + 1) + (j)])
+#define EY(L, i, j) ((L)->ey[(size_t)(i) * (L)->ny + (j)])
+#define JY(L, i, j) ((L)->jy[(size_t)(i) * (L)->ny + (j)])
+#define NODE(L, arr, i, j) ((L)->arr[(size_t)(i) * ((L)->ny + 1) + (j)])
+#define RING(L, s, i, j)                                                       \
+  ((L)->ring[(size_t)(s) * ((L)->nx + 1) * ((L)->ny + 1) +                    \
+             (size_t)(i) * ((L)->ny + 1) + (j)])
+
+static size_t n_hz(const level_t *L) { return (size_t)L->nx * L->ny; }
+static size_t n_ex(const level_t *L) { return (size_t)L->nx * (L->ny + 1); }
+static size_t n_ey(const level_t *L) { return (size_t)(L->nx + 1) * L->ny; }
+static size_t n_nd(const level_t *L) { return (size_t)(L->nx + 1) * (L->ny + 1); }
+
+/* ---- derived scalars (Sec. II.A, Sec. III.A, Sec. IV.D) ---------------- */
+static double mu0(void) { return 1.0 / (EPS_0 * C_0 * C_0); }
+
+static void derive(orc_sim *s) {
+  const orc_params *p = &s->p;
+  s->omega = 2.0 * PI_ * p->freq_hz;
+  s->lambda = C_0 / p->freq_hz;
+  /* collision frequency for air, Sec. II.A: nu_m = 5.3e9 p[Torr] */
+  s->nu_m = 5.3e9 * p->p_torr;
+  /* critical density m eps0 omega^2 / e^2 (Sec. III.A prints it without
+   * the square; the cutoff value of Sec. IV.D fixes the square) */
+  s->n_c = M_E * EPS_0 * s->omega * s->omega / (Q_E * Q_E);
+  /* effective field: E_eff^2 = E_rms^2 / (1 + omega^2/nu_m^2) */
+  s->eeff_fac = 1.0 / (1.0 + (s->omega * s->omega) / (s->nu_m * s->nu_m));
+  /* breakdown: incident rms field at which E_eff equals E_cr(p) */
+  {
+    double e_cr = p->ecr_over_p * 100.0 * p->p_torr; /* V/m */
+    double e_bd = e_cr / sqrt(s->eeff_fac);
+    double e_rms = p->erms_over_ebd * e_bd;
+    s->e0 = sqrt(2.0) * e_rms; /* peak amplitude */
+  }
+  /* free diffusion D_e = e T_e / (m nu_m); ambipolar D_a = mu_i (T_e+T_i) */
+  s->d_e = Q_E * p->te_ev / (M_E * s->nu_m);
+  s->d_a = p->mu_i_760 * (760.0 / p->p_torr) * (p->te_ev + p->ti_ev);
+  /* alpha = (L / lambda_D)^2 = n / n_amb */
+  s->n_amb = EPS_0 * p->te_ev / (Q_E * p->L_amb * p->L_amb);
+  s->nu_att = s->nu_m * p->A_ion * pow(p->ecr_over_p, p->beta_ion);
+  s->eta0 = mu0() * C_0;
+}
+
+static int level_init(level_t *L, int nx, int ny, double dx, double dt,
+                      int spp, double nu_m, double S) {
+  memset(L, 0, sizeof(*L));
+  L->nx = nx;
+  L->ny = ny;
+  L->dx = dx;
+  L->dt = dt;
+  L->spp = spp;
+  L->spb = spp / NRING;
+  L->ch = dt / (mu0() * dx);
+  L->ce = dt / EPS_0;
+  /* exponential integrator of dJ/dt = -nu_m J + (e^2 n / m) E over one step
+   * with E taken as the mean of its end values */
+  L->a = exp(-nu_m * dt);
+  L->b = Q_E * Q_E * (1.0 - L->a) / (M_E * nu_m);
+  L->kn = dt * L->b / (4.0 * EPS_0);
+  /* first-order Mur coefficient */
+  L->cmur = (S - 1.0) / (S + 1.0);
+  L->hz = calloc(n_hz(L), sizeof(double));
+  L->ex = calloc(n_ex(L), sizeof(double));
+  L->jx = calloc(n_ex(L), sizeof(double));
+  L->ey = calloc(n_ey(L), sizeof(double));
+  L->jy = calloc(n_ey(L), sizeof(double));
+  L->n = calloc(n_nd(L), sizeof(double));
+  L->acc = calloc(n_nd(L), sizeof(double));
+  L->ring = calloc(n_nd(L) * NRING, sizeof(double));
+  if (!L->hz || !L->ex || !L->jx || !L->ey || !L->jy || !L->n || !L->acc ||
+      !L->ring)
+    return -2;
+  return 0;
+}
+
+static void level_free(level_t *L) {
+  free(L->hz);
+  free(L->ex);
+  free(L->jx);
+  free(L->ey);
+  free(L->jy);
+  free(L->n);
+  free(L->acc);
+  free(L->ring);
+  memset(L, 0, sizeof(*L));
+}
+
+/* ---- incident plane wave (Sec. II.B: Ey-polarised, k along x, from the
+ * left), as an exact 1-D Yee solution after a sin^2 ramp ------------------ */
+static double ramp(const orc_sim *s, double tau) {
+  double tr = s->p.ramp_periods / s->p.freq_hz;
+  if (tau <= 0.0) return 0.0;
+  if (tau >= tr) return 1.0;
+  double sn = sin(0.5 * PI_ * tau / tr);
+  return sn * sn;
+}
+
+static double ey_inc(const orc_sim *s, double x, double t) {
+  return s->e0 * ramp(s, t - x / C_0) * sin(s->omega * t - s->ktil * x);
+}
+
+static double hz_inc(const orc_sim *s, double x, double t) {
+  return ey_inc(s, x, t) / s->eta0;
+}
+
+/* ---- Eqs. (1) and (3): one edge of the coupled E-J update -------------- */
+/* E^{n+1}(1+k) = (1-k)E^n + (dt/eps0)(curl H - (1+a)J^n/2),
+ * J^{n+1} = a J^n + (b n_e / 2)(E^n + E^{n+1}),  k = dt b n_e / (4 eps0).   */
+static void ej_edge(const level_t *L, double *e, double *j, double curl,
+                    double ne) {
+  double kap = L->kn * ne;
+  double en = ((1.0 - kap) * (*e) + L->ce * (curl - 0.5 * (1.0 + L->a) * (*j))) /
+              (1.0 + kap);
+  *j = L->a * (*j) + 0.5 * L->b * ne * (*e + en);
+  *e = en;
+}
+
+static void j_only(const level_t *L, double *j, double eo, double en,
+                   double ne) {
+  *j = L->a * (*j) + 0.5 * L->b * ne * (eo + en);
+}
+
+/* squared field at a node: mean of the squares of the edges that exist on
+ * each axis (the one-period average of Sec. II.A is taken of these) */
+static double node_e2(const level_t *L, int i, int j, int perx, int pery) {
+  double sx = 0.0, sy = 0.0;
+  int cx = 0, cy = 0;
+  if (i > 0) {
+    sx += EX(L, i - 1, j) * EX(L, i - 1, j);
+    cx++;
+  } else if (perx) {
+    sx += EX(L, L->nx - 1, j) * EX(L, L->nx - 1, j);
+    cx++;
+  }
+  if (i < L->nx) {
+    sx += EX(L, i, j) * EX(L, i, j);
+    cx++;
+  }
+  if (j > 0) {
+    sy += EY(L, i, j - 1) * EY(L, i, j - 1);
+    cy++;
+  } else if (pery) {
+    sy += EY(L, i, L->ny - 1) * EY(L, i, L->ny - 1);
+    cy++;
+  }
+  if (j < L->ny) {
+    sy += EY(L, i, j) * EY(L, i, j);
+    cy++;
+  }
+  return (cx ? sx / cx : 0.0) + (cy ? sy / cy : 0.0);
+}
+
+static void accumulate(level_t *L, int perx, int pery) {
+  for (int i = 0; i <= L->nx; i++)
+    for (int j = 0; j <= L->ny; j++) {
+      if ((perx && i == L->nx) || (pery && j == L->ny)) continue;
+      NODE(L, acc, i, j) += node_e2(L, i, j, perx, pery);
+    }
+  if (perx)
+    for (int j = 0; j <= L->ny; j++) NODE(L, acc, L->nx, j) = NODE(L, acc, 0, j);
+  if (pery)
+    for (int i = 0; i <= L->nx; i++) NODE(L, acc, i, L->ny) = NODE(L, acc, i, 0);
+}
+
+/* ---- one EM step of the base (coarse or uniform) level, Eqs. (1)-(3),
+ * total-field/scattered-field source, outer boundary ---------------------- */
+static void em_step_base(orc_sim *s) {
+  level_t *L = &s->L0;
+  const int nx = L->nx, ny = L->ny;
+  const int perx = s->p.bc_x == ORC_BC_PERIODIC;
+  const int pery = s->p.bc_y == ORC_BC_PERIODIC;
+  const int is = s->p.tfsf_i;
+  const double t = (double)s->step * L->dt;
+  const double xs = is * L->dx;
+
+  /* E^n and Hz^{n-1/2} are kept: Mur needs E^n, the coarse/fine transfer
+   * needs the old coarse E, a regrid extrapolates Hz in time */
+  memcpy(s->ex_old, L->ex, n_ex(L) * sizeof(double));
+  memcpy(s->ey_old, L->ey, n_ey(L) * sizeof(double));
+  memcpy(s->hz_prev, L->hz, n_hz(L) * sizeof(double));
+
+  /* Faraday, Eq. (2): dHz/dt = -(dEy/dx - dEx/dy)/mu0 */
+  for (int i = 0; i < nx; i++)
+    for (int j = 0; j < ny; j++)
+      HZ(L, i, j) -= L->ch * ((EY(L, i + 1, j) - EY(L, i, j)) -
+                              (EX(L, i, j + 1) - EX(L, i, j)));
+  if (is > 0) /* scattered-field cells left of the source line */
+    for (int j = 0; j < ny; j++) HZ(L, is - 1, j) += L->ch * ey_inc(s, xs, t);
+
+  /* Ampere with current, Eq. (1), and Drude current, Eq. (3) */
+  for (int i = 0; i < nx; i++)
+    for (int j = (pery ? 0 : 1); j < ny; j++) {
+      int jm = j > 0 ? j - 1 : ny - 1;
+      double curl = (HZ(L, i, j) - HZ(L, i, jm)) / L->dx;
+      double ne = 0.5 * (NODE(L, n, i, j) + NODE(L, n, i + 1, j));
+      ej_edge(L, &EX(L, i, j), &JX(L, i, j), curl, ne);
+    }
+  for (int i = (perx ? 0 : 1); i < nx; i++)
+    for (int j = 0; j < ny; j++) {
+      int im = i > 0 ? i - 1 : nx - 1;
+      double curl = -(HZ(L, i, j) - HZ(L, im, j)) / L->dx;
+      if (is > 0 && i == is) /* total-field edge next to the source line */
+        curl += hz_inc(s, xs - 0.5 * L->dx, t + 0.5 * L->dt) / L->dx;
+      double ne = 0.5 * (NODE(L, n, i, j) + NODE(L, n, i, j + 1));
+      ej_edge(L, &EY(L, i, j), &JY(L, i, j), curl, ne);
+    }
+
+  /* outer boundary on the tangential edges */
+  if (perx) {
+    for (int j = 0; j < ny; j++) {
+      EY(L, nx, j) = EY(L, 0, j);
+      JY(L, nx, j) = JY(L, 0, j);
+    }
+  } else {
+    for (int j = 0; j < ny; j++) {
+      const int ib[2] = {0, nx}, in[2] = {1, nx - 1};
+      for (int k = 0; k < 2; k++) {
+        int i = ib[k];
+        double eo = s->ey_old[(size_t)i * ny + j];
+        double en = 0.0;
+        if (s->p.bc_x == ORC_BC_MUR) /* first-order Mur */
+          en = s->ey_old[(size_t)in[k] * ny + j] +
+               L->cmur * (EY(L, in[k], j) - eo);
+        double ne = 0.5 * (NODE(L, n, i, j) + NODE(L, n, i, j + 1));
+        j_only(L, &JY(L, i, j), eo, en, ne);
+        EY(L, i, j) = en;
+      }
+    }
+  }
+  if (pery) {
+    for (int i = 0; i < nx; i++) {
+      EX(L, i, ny) = EX(L, i, 0);
+      JX(L, i, ny) = JX(L, i, 0);
+    }
+  } else {
+    for (int i = 0; i < nx; i++) {
+      const int jb[2] = {0, ny}, jn[2] = {1, ny - 1};
+      for (int k = 0; k < 2; k++) {
+        int j = jb[k];
+        double eo = s->ex_old[(size_t)i * (ny + 1) + j];
+        double en = 0.0;
+        if (s->p.bc_y == ORC_BC_MUR)
+          en = s->ex_old[(size_t)i * (ny + 1) + jn[k]] +
+               L->cmur * (EX(L, i, jn[k]) - eo);
+        double ne = 0.5 * (NODE(L, n, i, j) + NODE(L, n, i + 1, j));
+        j_only(L, &JX(L, i, j), eo, en, ne);
+        EX(L, i, j) = en;
+      }
+    }
+  }
+  accumulate(L, perx, pery);
+}
+
+/* ---- coarse -> fine transfer on the coarse/fine boundary, Eq. (5b) ------ */
+/* linear in time between the old and new coarse values (frac), linear in
+ * space along the boundary line; coarse Ey lies at j+1/2, coarse Ex at i+1/2.
+ * A fine y-edge at global fine row Q sits at coarse y-index Q/2 - 1/4. */
+static double cfb_ey(const orc_sim *s, int I, int Q, double frac) {
+  const level_t *C = &s->L0;
+  double v = 0.5 * Q - 0.25;
+  int j = (int)floor(v);
+  double xp = v - j;
+  double o = (1.0 - xp) * s->ey_old[(size_t)I * C->ny + j] +
+             xp * s->ey_old[(size_t)I * C->ny + j + 1];
+  double nw = (1.0 - xp) * EY(C, I, j) + xp * EY(C, I, j + 1);
+  return (1.0 - frac) * o + frac * nw;
+}
+
+static double cfb_ex(const orc_sim *s, int P, int J, double frac) {
+  const level_t *C = &s->L0;
+  double u = 0.5 * P - 0.25;
+  int i = (int)floor(u);
+  double xp = u - i;
+  double o = (1.0 - xp) * s->ex_old[(size_t)i * (C->ny + 1) + J] +
+             xp * s->ex_old[(size_t)(i + 1) * (C->ny + 1) + J];
+  double nw = (1.0 - xp) * EX(C, i, J) + xp * EX(C, i + 1, J);
+  return (1.0 - frac) * o + frac * nw;
+}
+
+/* ---- one fine substep m (1..r) on the patch, Sec. III.C ---------------- */
+static void em_step_fine(orc_sim *s, int m) {
+  level_t *F = &s->L1;
+  const int fw = F->nx, fh = F->ny;
+  const int P0 = s->ext[0] * s->p.r, Q0 = s->ext[1] * s->p.r;
+  const int I0 = s->ext[0], I1 = s->ext[2], J0 = s->ext[1], J1 = s->ext[3];
+  const double frac = (double)m / s->p.r;
+
+  for (int i = 0; i < fw; i++)
+    for (int j = 0; j < fh; j++)
+      HZ(F, i, j) -= F->ch * ((EY(F, i + 1, j) - EY(F, i, j)) -
+                              (EX(F, i, j + 1) - EX(F, i, j)));
+  if (m == 1) memcpy(s->hz_sub1, F->hz, n_hz(F) * sizeof(double));
+
+  for (int i = 0; i < fw; i++)
+    for (int j = 1; j < fh; j++) {
+      double curl = (HZ(F, i, j) - HZ(F, i, j - 1)) / F->dx;
+      double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i + 1, j));
+      ej_edge(F, &EX(F, i, j), &JX(F, i, j), curl, ne);
+    }
+  for (int i = 1; i < fw; i++)
+    for (int j = 0; j < fh; j++) {
+      double curl = -(HZ(F, i, j) - HZ(F, i - 1, j)) / F->dx;
+      double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i, j + 1));
+      ej_edge(F, &EY(F, i, j), &JY(F, i, j), curl, ne);
+    }
+  /* tangential E on the patch boundary from the coarse mesh, Eq. (5b);
+   * the boundary current follows Eq. (3) with that field */
+  for (int j = 0; j < fh; j++) {
+    const int ib[2] = {0, fw}, Ic[2] = {I0, I1};
+    for (int k = 0; k < 2; k++) {
+      int i = ib[k];
+      double eo = EY(F, i, j);
+      double en = cfb_ey(s, Ic[k], Q0 + j, frac);
+      double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i, j + 1));
+      j_only(F, &JY(F, i, j), eo, en, ne);
+      EY(F, i, j) = en;
+    }
+  }
+  for (int i = 0; i < fw; i++) {
+    const int jb[2] = {0, fh}, Jc[2] = {J0, J1};
+    for (int k = 0; k < 2; k++) {
+      int j = jb[k];
+      double eo = EX(F, i, j);
+      double en = cfb_ex(s, P0 + i, Jc[k], frac);
+      double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i + 1, j));
+      j_only(F, &JX(F, i, j), eo, en, ne);
+      EX(F, i, j) = en;
+    }
+  }
+  accumulate(F, 0, 0);
+}
+
+/* ---- fine -> coarse transfer after the last substep (Sec. III.C: "the
+ * fine mesh updated quantities are transferred back"): edge means for E and
+ * J, cell and half-level mean for Hz (coarse n+1/2 lies midway between the
+ * two fine H levels of the interval) ---------------------------------- */
+static void restrict_patch(orc_sim *s) {
+  level_t *C = &s->L0, *F = &s->L1;
+  const int I0 = s->ext[0], J0 = s->ext[1], I1 = s->ext[2], J1 = s->ext[3];
+  const int fh = F->ny;
+  for (int i = I0; i < I1; i++)
+    for (int j = J0; j < J1; j++) {
+      int p = 2 * (i - I0), q = 2 * (j - J0);
+      double sum = 0.0;
+      for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+          sum += 0.5 * (s->hz_sub1[(size_t)(p + a) * fh + q + b] +
+                        HZ(F, p + a, q + b));
+      HZ(C, i, j) = 0.25 * sum;
+    }
+  for (int i = I0; i < I1; i++)
+    for (int j = J0 + 1; j < J1; j++) {
+      int p = 2 * (i - I0), q = 2 * (j - J0);
+      EX(C, i, j) = 0.5 * (EX(F, p, q) + EX(F, p + 1, q));
+      JX(C, i, j) = 0.5 * (JX(F, p, q) + JX(F, p + 1, q));
+    }
+  for (int i = I0 + 1; i < I1; i++)
+    for (int j = J0; j < J1; j++) {
+      int p = 2 * (i - I0), q = 2 * (j - J0);
+      EY(C, i, j) = 0.5 * (EY(F, p, q) + EY(F, p, q + 1));
+      JY(C, i, j) = 0.5 * (JY(F, p, q) + JY(F, p, q + 1));
+    }
+}
+
+/* ---- continuity, Eq. (4) ----------------------------------------------- */
+double orc_nu_net(const orc_params *p, double erms2) {
+  double omega = 2.0 * PI_ * p->freq_hz;
+  double nu_m = 5.3e9 * p->p_torr;
+  double eeff2 = erms2 / (1.0 + (omega * omega) / (nu_m * nu_m));
+  /* (E_eff / p)^beta with E_eff/p in V/(cm Torr), via the square */
+  double x = eeff2 / (1.0e4 * p->p_torr * p->p_torr);
+  return nu_m * p->A_ion *
+         (pow(x, 0.5 * p->beta_ion) - pow(p->ecr_over_p, p->beta_ion));
+}
+
+double orc_d_eff(const orc_params *p, double n) {
+  if (p->d_mode == ORC_D_CONST) return p->d_const;
+  double nu_m = 5.3e9 * p->p_torr;
+  double d_e = Q_E * p->te_ev / (M_E * nu_m);
+  double d_a = p->mu_i_760 * (760.0 / p->p_torr) * (p->te_ev + p->ti_ev);
+  double n_amb = EPS_0 * p->te_ev / (Q_E * p->L_amb * p->L_amb);
+  double alpha = n / n_amb;
+  return (alpha * d_a + d_e) / (1.0 + alpha);
+}
+
+/* close one window block: its mean square field goes into the ring */
+static void close_block(level_t *L, int slot) {
+  for (int i = 0; i <= L->nx; i++)
+    for (int j = 0; j <= L->ny; j++) {
+      RING(L, slot, i, j) = NODE(L, acc, i, j) / L->spp;
+      NODE(L, acc, i, j) = 0.0;
+    }
+}
+
+static double erms2_at(const level_t *L, int i, int j) {
+  double e2 = 0.0;
+  for (int k = 0; k < NRING; k++) e2 += RING(L, k, i, j);
+  return e2;
+}
+
+/* forward Euler, flux form with face D = mean of the two node values,
+ * zero flux through the outer faces (or periodic wrap).  Arrays are node
+ * arrays [nx+1][ny+1] (j fastest); nodes in [ilo,ihi]x[jlo,jhi] are
+ * updated, the rest copied. */
+static void continuity_core(const orc_params *p, int nx, int ny, double dx,
+                            double dtn, int ilo, int ihi, int jlo, int jhi,
+                            int perx, int pery, const double *nold,
+                            const double *e2, double *nout) {
+#define AT(arr, i, j) arr[(size_t)(i) * (ny + 1) + (j)]
+  memcpy(nout, nold, (size_t)(nx + 1) * (ny + 1) * sizeof(double));
+  for (int i = ilo; i <= ihi; i++)
+    for (int j = jlo; j <= jhi; j++) {
+      if ((perx && i == nx) || (pery && j == ny)) continue;
+      double ni = AT(nold, i, j);
+      double di = orc_d_eff(p, ni);
+      double flux = 0.0;
+      int nb[4][2] = {{i - 1, j}, {i + 1, j}, {i, j - 1}, {i, j + 1}};
+      for (int k = 0; k < 4; k++) {
+        int a = nb[k][0], b = nb[k][1];
+        if (a < 0 || a > nx) {
+          if (!perx) continue;
+          a = (a + nx) % nx;
+        }
+        if (b < 0 || b > ny) {
+          if (!pery) continue;
+          b = (b + ny) % ny;
+        }
+        double nn = AT(nold, a, b);
+        flux += 0.5 * (di + orc_d_eff(p, nn)) * (nn - ni);
+      }
+      double nu = orc_nu_net(p, AT(e2, i, j));
+      double nnew = ni + dtn * (flux / (dx * dx) + nu * ni);
+      AT(nout, i, j) = nnew > 0.0 ? nnew : 0.0;
+    }
+  if (perx)
+    for (int j = 0; j <= ny; j++) AT(nout, nx, j) = AT(nout, 0, j);
+  if (pery)
+    for (int i = 0; i <= nx; i++) AT(nout, i, ny) = AT(nout, i, 0);
+#undef AT
+}
+
+/* interior_only leaves the patch boundary nodes (they carry coarse values)
+ * untouched */
+static void continuity(orc_sim *s, level_t *L, int interior_only, int perx,
+                       int pery) {
+  const int nx = L->nx, ny = L->ny;
+  const double dtn = L->spb * L->dt;
+  double *nold = malloc(n_nd(L) * sizeof(double));
+  double *e2 = malloc(n_nd(L) * sizeof(double));
+  memcpy(nold, L->n, n_nd(L) * sizeof(double));
+  for (int i = 0; i <= nx; i++)
+    for (int j = 0; j <= ny; j++) e2[(size_t)i * (ny + 1) + j] = erms2_at(L, i, j);
+  if (interior_only)
+    continuity_core(&s->p, nx, ny, L->dx, dtn, 1, nx - 1, 1, ny - 1, 0, 0,
+                    nold, e2, L->n);
+  else
+    continuity_core(&s->p, nx, ny, L->dx, dtn, 0, nx, 0, ny, perx, pery, nold,
+                    e2, L->n);
+  free(nold);
+  free(e2);
+}
+
+int orc_continuity_apply(const orc_params *p, int nx, int ny, double dx,
+                         double dtn, int perx, int pery, const double *n_in,
+                         const double *erms2, double *n_out) {
+  size_t nn = (size_t)(nx + 1) * (ny + 1);
+  double *a = malloc(nn * sizeof(double)), *e = malloc(nn * sizeof(double)),
+         *o = malloc(nn * sizeof(double));
+  if (!a || !e || !o) {
+    free(a); free(e); free(o);
+    return -2;
+  }
+  for (int j = 0; j <= ny; j++)
+    for (int i = 0; i <= nx; i++) {
+      a[(size_t)i * (ny + 1) + j] = n_in[(size_t)j * (nx + 1) + i];
+      e[(size_t)i * (ny + 1) + j] = erms2[(size_t)j * (nx + 1) + i];
+    }
+  continuity_core(p, nx, ny, dx, dtn, 0, nx, 0, ny, perx, pery, a, e, o);
+  for (int j = 0; j <= ny; j++)
+    for (int i = 0; i <= nx; i++)
+      n_out[(size_t)j * (nx + 1) + i] = o[(size_t)i * (ny + 1) + j];
+  free(a); free(e); free(o);
+  return 0;
+}
+
+/* ---- bilinear sampling of a coarse array, Eq. (5a) area weights -------- */
+/* arr has (ni x nj) entries with j fastest; (u, v) in that array's index
+ * space; only entries with non-zero weight are touched */
+static double bilin(const double *arr, int nj, double u, double v) {
+  int i = (int)floor(u), j = (int)floor(v);
+  double fu = u - i, fv = v - j, val = 0.0;
+  for (int di = 0; di < 2; di++) {
+    double wu = di ? fu : 1.0 - fu;
+    if (wu == 0.0) continue;
+    for (int dj = 0; dj < 2; dj++) {
+      double wv = dj ? fv : 1.0 - fv;
+      if (wv == 0.0) continue;
+      val += wu * wv * arr[(size_t)(i + di) * nj + (j + dj)];
+    }
+  }
+  return val;
+}
+
+/* coarse n -> fine patch boundary nodes, then fine -> coarse injection at
+ * the coarse nodes strictly inside the patch (Sec. III.C transfers) */
+static void transfer_density(orc_sim *s) {
+  level_t *C = &s->L0, *F = &s->L1;
+  const int P0 = 2 * s->ext[0], Q0 = 2 * s->ext[1];
+  const int fw = F->nx, fh = F->ny;
+  for (int i = 0; i <= fw; i++)
+    for (int j = 0; j <= fh; j++) {
+      if (i != 0 && i != fw && j != 0 && j != fh) continue;
+      NODE(F, n, i, j) = bilin(C->n, C->ny + 1, 0.5 * (P0 + i), 0.5 * (Q0 + j));
+    }
+  for (int i = s->ext[0] + 1; i < s->ext[2]; i++)
+    for (int j = s->ext[1] + 1; j < s->ext[3]; j++)
+      NODE(C, n, i, j) = NODE(F, n, 2 * (i - s->ext[0]), 2 * (j - s->ext[1]));
+}
+
+/* ---- self-aware expansion, Sec. III.A/B/D ------------------------------ */
+/* node flag: threshold density, or (above a floor) a density gradient
+ * length n/|grad n| below dx/grad_thr.  Decided in binary32 on
+ * n * 2^-60 (an exact scaling that keeps n^2 in range):
+ *   n > n_thr  or  (n > n_floor and gx*gx + gy*gy > g2 * (n*n)),
+ * g = central difference in cell units, zero on the domain boundary. */
+static int node_flag(const orc_sim *s, int i, int j, float thr, float flo,
+                     float g2) {
+  const level_t *L = &s->L0;
+  float nv = (float)NODE(L, n, i, j);
+  if (nv > thr) return 1;
+  if (!(nv > flo)) return 0;
+  float ns = ldexpf(nv, -60);
+  float gx = 0.0f, gy = 0.0f;
+  if (i > 0 && i < L->nx) {
+    float r = ldexpf((float)NODE(L, n, i + 1, j), -60);
+    float l = ldexpf((float)NODE(L, n, i - 1, j), -60);
+    gx = (r - l) * 0.5f;
+  }
+  if (j > 0 && j < L->ny) {
+    float u = ldexpf((float)NODE(L, n, i, j + 1), -60);
+    float d = ldexpf((float)NODE(L, n, i, j - 1), -60);
+    gy = (u - d) * 0.5f;
+  }
+  float gx2 = gx * gx;
+  float gy2 = gy * gy;
+  float lhs = gx2 + gy2;
+  float n2 = ns * ns;
+  float rhs = g2 * n2;
+  return lhs > rhs;
+}
+
+/* flags -> block flags -> exclusive prefix sum -> compacted block list ->
+ * bounding box of old patch and flagged blocks, clipped to the margins */
+static void regrid_test(orc_sim *s, int newext[4]) {
+  const level_t *L = &s->L0;
+  const int B = s->p.block, NBx = s->NBx, NBy = s->NBy;
+  const float thr = (float)(s->p.n_thr_over_nc * s->n_c);
+  const float flo = (float)(s->p.n_floor_over_nc * s->n_c);
+  const float g2 = (float)(s->p.grad_thr * s->p.grad_thr);
+  memset(s->bflag, 0, (size_t)NBx * NBy);
+  for (int i = 0; i <= L->nx; i++)
+    for (int j = 0; j <= L->ny; j++) {
+      int bx = i / B < NBx - 1 ? i / B : NBx - 1;
+      int by = j / B < NBy - 1 ? j / B : NBy - 1;
+      if (node_flag(s, i, j, thr, flo, g2)) s->bflag[by * NBx + bx] = 1;
+    }
+  int32_t run = 0;
+  for (int b = 0; b < NBx * NBy; b++) {
+    s->bscan[b] = run;
+    if (s->bflag[b]) s->blist[run] = b;
+    run += s->bflag[b];
+  }
+  s->bcount = run;
+  int bx0 = NBx, by0 = NBy, bx1 = 0, by1 = 0;
+  for (int k = 0; k < s->bcount; k++) {
+    int bx = s->blist[k] % NBx, by = s->blist[k] / NBx;
+    if (bx < bx0) bx0 = bx;
+    if (by < by0) by0 = by;
+    if (bx + 1 > bx1) bx1 = bx + 1;
+    if (by + 1 > by1) by1 = by + 1;
+  }
+  if (s->has_patch) { /* the patch only grows (Sec. III.D) */
+    int o0 = s->ext[0] / B, o1 = s->ext[1] / B, o2 = s->ext[2] / B,
+        o3 = s->ext[3] / B;
+    if (o0 < bx0) bx0 = o0;
+    if (o1 < by0) by0 = o1;
+    if (o2 > bx1) bx1 = o2;
+    if (o3 > by1) by1 = o3;
+  }
+  /* keep one block clear of the outer boundary and of the source line */
+  int xmin = 1;
+  if (s->p.tfsf_i > 0) {
+    int m = (s->p.tfsf_i + 2 * B - 1) / B;
+    if (m > xmin) xmin = m;
+  }
+  if (bx0 < xmin) bx0 = xmin;
+  if (by0 < 1) by0 = 1;
+  if (bx1 > NBx - 1) bx1 = NBx - 1;
+  if (by1 > NBy - 1) by1 = NBy - 1;
+  if (bx0 >= bx1 || by0 >= by1) {
+    newext[0] = newext[1] = newext[2] = newext[3] = 0;
+  } else {
+    newext[0] = bx0 * B;
+    newext[1] = by0 * B;
+    newext[2] = bx1 * B;
+    newext[3] = by1 * B;
+  }
+}
+
+/* Build the fine patch for new extents: data of the old patch is copied
+ * where it exists, the rest is interpolated from the coarse mesh
+ * (Sec. III.D), bilinearly with the area weights of Eq. (5a).  E, J, n and
+ * the window use the current coarse values (frac = 1); fine Hz must sit at
+ * coarse time n+3/4, so Eq. (5a) is applied with frac = 5/4 between coarse
+ * Hz^{n-1/2} and Hz^{n+1/2}. */
+static int build_patch(orc_sim *s, const int ne[4], const double *seed_fine) {
+  const level_t *C = &s->L0;
+  const int r = s->p.r;
+  level_t F;
+  int rc = level_init(&F, r * (ne[2] - ne[0]), r * (ne[3] - ne[1]), C->dx / r,
+                      C->dt / r, C->spp * r, s->nu_m, s->p.courant);
+  if (rc) {
+    level_free(&F);
+    return rc;
+  }
+  const int P0 = r * ne[0], Q0 = r * ne[1];
+  const level_t *O = s->has_patch ? &s->L1 : NULL;
+  const int oP0 = O ? r * s->ext[0] : 0, oQ0 = O ? r * s->ext[1] : 0;
+  const int oP1 = O ? r * s->ext[2] : 0, oQ1 = O ? r * s->ext[3] : 0;
+  const double fr = 1.25; /* frac for Hz */
+  const int fgx = r * s->p.nx + 1;
+
+  for (int i = 0; i < F.nx; i++)
+    for (int j = 0; j < F.ny; j++) {
+      int P = P0 + i, Q = Q0 + j;
+      if (O && P >= oP0 && P < oP1 && Q >= oQ0 && Q < oQ1) {
+        HZ(&F, i, j) = HZ(O, P - oP0, Q - oQ0);
+      } else {
+        double u = 0.5 * P - 0.25, v = 0.5 * Q - 0.25;
+        HZ(&F, i, j) = (1.0 - fr) * bilin(s->hz_prev, C->ny, u, v) +
+                       fr * bilin(C->hz, C->ny, u, v);
+      }
+    }
+  for (int i = 0; i < F.nx; i++)
+    for (int j = 0; j <= F.ny; j++) {
+      int P = P0 + i, Q = Q0 + j;
+      if (O && P >= oP0 && P < oP1 && Q >= oQ0 && Q <= oQ1) {
+        EX(&F, i, j) = EX(O, P - oP0, Q - oQ0);
+        JX(&F, i, j) = JX(O, P - oP0, Q - oQ0);
+      } else {
+        double u = 0.5 * P - 0.25, v = 0.5 * Q;
+        EX(&F, i, j) = bilin(C->ex, C->ny + 1, u, v);
+        JX(&F, i, j) = bilin(C->jx, C->ny + 1, u, v);
+      }
+    }
+  for (int i = 0; i <= F.nx; i++)
+    for (int j = 0; j < F.ny; j++) {
+      int P = P0 + i, Q = Q0 + j;
+      if (O && P >= oP0 && P <= oP1 && Q >= oQ0 && Q < oQ1) {
+        EY(&F, i, j) = EY(O, P - oP0, Q - oQ0);
+        JY(&F, i, j) = JY(O, P - oP0, Q - oQ0);
+      } else {
+        double u = 0.5 * P, v = 0.5 * Q - 0.25;
+        EY(&F, i, j) = bilin(C->ey, C->ny, u, v);
+        JY(&F, i, j) = bilin(C->jy, C->ny, u, v);
+      }
+    }
+  for (int i = 0; i <= F.nx; i++)
+    for (int j = 0; j <= F.ny; j++) {
+      int P = P0 + i, Q = Q0 + j;
+      if (O && P >= oP0 && P <= oP1 && Q >= oQ0 && Q <= oQ1) {
+        int a = P - oP0, b = Q - oQ0;
+        NODE(&F, n, i, j) = NODE(O, n, a, b);
+        NODE(&F, acc, i, j) = NODE(O, acc, a, b);
+        for (int k = 0; k < NRING; k++) RING(&F, k, i, j) = RING(O, k, a, b);
+      } else {
+        double u = 0.5 * P, v = 0.5 * Q;
+        NODE(&F, n, i, j) = seed_fine ? seed_fine[(size_t)Q * fgx + P]
+                                      : bilin(C->n, C->ny + 1, u, v);
+        NODE(&F, acc, i, j) = bilin(C->acc, C->ny + 1, u, v);
+        for (int k = 0; k < NRING; k++)
+          RING(&F, k, i, j) = bilin(C->ring + (size_t)k * n_nd(C), C->ny + 1, u, v);
+      }
+    }
+  if (s->has_patch) level_free(&s->L1);
+  free(s->hz_sub1);
+  s->L1 = F;
+  s->hz_sub1 = calloc(n_hz(&F), sizeof(double));
+  memcpy(s->ext, ne, sizeof(s->ext));
+  s->has_patch = 1;
+  return s->hz_sub1 ? 0 : -2;
+}
+
+static int do_regrid(orc_sim *s, const double *seed_fine) {
+  int ne[4];
+  regrid_test(s, ne);
+  if (ne[2] <= ne[0]) return 0; /* nothing to refine */
+  if (s->has_patch && !memcmp(ne, s->ext, sizeof(ne))) return 0;
+  return build_patch(s, ne, seed_fine);
+}
+
+int orc_regrid(orc_sim *s) {
+  if (!s || s->p.mode == ORC_UNIFORM) return -1;
+  return do_regrid(s, NULL);
+}
+
+/* ---- driver: one base step with subcycling, Sec. III.C ----------------- */
+static void sync_point(orc_sim *s) {
+  const int perx = s->p.bc_x == ORC_BC_PERIODIC;
+  const int pery = s->p.bc_y == ORC_BC_PERIODIC;
+  int slot = (int)(s->blocks % NRING);
+  close_block(&s->L0, slot);
+  if (s->has_patch) close_block(&s->L1, slot);
+  s->blocks++;
+  if (s->blocks < NRING) return; /* the first period only fills the window */
+  continuity(s, &s->L0, 0, perx, pery);
+  if (s->has_patch) {
+    continuity(s, &s->L1, 1, 0, 0);
+    transfer_density(s);
+  }
+}
+
+static int base_step(orc_sim *s) {
+  em_step_base(s);
+  if (s->has_patch) {
+    for (int m = 1; m <= s->p.r; m++) em_step_fine(s, m);
+    restrict_patch(s);
+  }
+  s->step++;
+  if (s->p.continuity_on && s->step % s->L0.spb == 0) sync_point(s);
+  if (s->p.mode == ORC_DYNAMIC && s->step % s->p.regrid_every == 0)
+    return do_regrid(s, NULL);
+  return 0;
+}
+
+int orc_step(orc_sim *s, int64_t n) {
+  if (!s || n < 0) return -1;
+  for (int64_t k = 0; k < n; k++) {
+    int rc = base_step(s);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+/* ---- create / destroy --------------------------------------------------- */
+int orc_create(const orc_params *p, const double *seed_base,
+               const double *seed_fine, orc_sim **out) {
+  *out = NULL;
+  if (p->nx < 2 || p->ny < 2 || p->cells_per_lambda < 1 || p->courant <= 0.0)
+    return -1;
+  double sppd = p->cells_per_lambda / p->courant;
+  int spp = (int)floor(sppd + 0.5);
+  if (fabs(sppd - spp) > 1e-9 || spp % NRING) return -1;
+  if (p->mode != ORC_UNIFORM) {
+    if (p->r != 2 || p->block < 1 || p->nx % p->block || p->ny % p->block)
+      return -1;
+    if (p->bc_x == ORC_BC_PERIODIC || p->bc_y == ORC_BC_PERIODIC) return -1;
+    if (p->mode == ORC_DYNAMIC && p->regrid_every % (spp / NRING)) return -1;
+  }
+  if (p->tfsf_i > 0 && (p->tfsf_i >= p->nx || p->bc_x == ORC_BC_PERIODIC))
+    return -1;
+  orc_sim *s = calloc(1, sizeof(*s));
+  if (!s) return -2;
+  s->p = *p;
+  derive(s);
+  double dx = s->lambda / p->cells_per_lambda;
+  double dt = p->courant * dx / C_0;
+  /* numerical wavenumber of the 1-D Yee wave: sin(w dt/2)/(c dt) =
+   * sin(k dx/2)/dx */
+  s->ktil = 2.0 / dx * asin(sin(0.5 * s->omega * dt) / p->courant);
+  int rc = level_init(&s->L0, p->nx, p->ny, dx, dt, spp, s->nu_m, p->courant);
+  s->ex_old = calloc(n_ex(&s->L0), sizeof(double));
+  s->ey_old = calloc(n_ey(&s->L0), sizeof(double));
+  s->hz_prev = calloc(n_hz(&s->L0), sizeof(double));
+  if (rc || !s->ex_old || !s->ey_old || !s->hz_prev) {
+    orc_destroy(s);
+    return -2;
+  }
+  if (seed_base)
+    for (int j = 0; j <= p->ny; j++)
+      for (int i = 0; i <= p->nx; i++)
+        NODE(&s->L0, n, i, j) = seed_base[(size_t)j * (p->nx + 1) + i];
+  if (p->mode != ORC_UNIFORM) {
+    s->NBx = p->nx / p->block;
+    s->NBy = p->ny / p->block;
+    s->bflag = calloc((size_t)s->NBx * s->NBy, 1);
+    s->bscan = calloc((size_t)s->NBx * s->NBy, sizeof(int32_t));
+    s->blist = calloc((size_t)s->NBx * s->NBy, sizeof(int32_t));
+    if (!s->bflag || !s->bscan || !s->blist) {
+      orc_destroy(s);
+      return -2;
+    }
+    if (p->mode == ORC_STATIC) {
+      const int *e = p->static_ext;
+      if (e[0] < 1 || e[1] < 1 || e[2] > p->nx - 1 || e[3] > p->ny - 1 ||
+          e[0] >= e[2] || e[1] >= e[3] ||
+          (p->tfsf_i > 0 && e[0] <= p->tfsf_i)) {
+        orc_destroy(s);
+        return -1;
+      }
+      rc = build_patch(s, e, seed_fine);
+    } else {
+      rc = do_regrid(s, seed_fine); /* the patch at t = 0 */
+    }
+    if (rc) {
+      orc_destroy(s);
+      return rc;
+    }
+  }
+  *out = s;
+  return 0;
+}
+
+void orc_destroy(orc_sim *s) {
+  if (!s) return;
+  level_free(&s->L0);
+  if (s->has_patch) level_free(&s->L1);
+  free(s->ex_old);
+  free(s->ey_old);
+  free(s->hz_prev);
+  free(s->hz_sub1);
+  free(s->bflag);
+  free(s->bscan);
+  free(s->blist);
+  free(s);
+}
+
+/* ---- field access ------------------------------------------------------- */
+static const level_t *level_of(const orc_sim *s, int level) {
+  if (level == 0) return &s->L0;
+  if (level == 1 && s->has_patch) return &s->L1;
+  return NULL;
+}
+
+int orc_field_dims(const orc_sim *s, int field, int level, int32_t dims[2]) {
+  const level_t *L = level_of(s, level);
+  if (!L) return -1;
+  switch (field) {
+  case ORC_HZ: dims[0] = L->ny; dims[1] = L->nx; break;
+  case ORC_EX: case ORC_JX: dims[0] = L->ny + 1; dims[1] = L->nx; break;
+  case ORC_EY: case ORC_JY: dims[0] = L->ny; dims[1] = L->nx + 1; break;
+  case ORC_N: case ORC_ACC: case ORC_ERMS2:
+    dims[0] = L->ny + 1; dims[1] = L->nx + 1; break;
+  case ORC_RING: dims[0] = NRING * (L->ny + 1); dims[1] = L->nx + 1; break;
+  default: return -1;
+  }
+  return 0;
+}
+
+/* visit every entry of a field in output order, handing out its address */
+static double *field_ptr(const level_t *L, int field, int i, int j, int k) {
+  switch (field) {
+  case ORC_HZ: return &HZ(L, i, j);
+  case ORC_EX: return &EX(L, i, j);
+  case ORC_JX: return &JX(L, i, j);
+  case ORC_EY: return &EY(L, i, j);
+  case ORC_JY: return &JY(L, i, j);
+  case ORC_N: return &NODE(L, n, i, j);
+  case ORC_ACC: return &NODE(L, acc, i, j);
+  case ORC_RING: return &RING(L, k, i, j);
+  }
+  return NULL;
+}
+
+int orc_get_field(const orc_sim *s, int field, int level, double *dst) {
+  const level_t *L = level_of(s, level);
+  int32_t d[2];
+  if (!L || orc_field_dims(s, field, level, d)) return -1;
+  int planes = field == ORC_RING ? NRING : 1;
+  int rows = d[0] / planes, cols = d[1];
+  for (int k = 0; k < planes; k++)
+    for (int j = 0; j < rows; j++)
+      for (int i = 0; i < cols; i++) {
+        double v = field == ORC_ERMS2 ? erms2_at(L, i, j)
+                                      : *field_ptr(L, field, i, j, k);
+        dst[((size_t)k * rows + j) * cols + i] = v;
+      }
+  return 0;
+}
+
+int orc_set_field(orc_sim *s, int field, int level, const double *src) {
+  const level_t *L = level_of(s, level);
+  int32_t d[2];
+  if (!L || field == ORC_ERMS2 || orc_field_dims(s, field, level, d)) return -1;
+  int planes = field == ORC_RING ? NRING : 1;
+  int rows = d[0] / planes, cols = d[1];
+  for (int k = 0; k < planes; k++)
+    for (int j = 0; j < rows; j++)
+      for (int i = 0; i < cols; i++)
+        *field_ptr(L, field, i, j, k) = src[((size_t)k * rows + j) * cols + i];
+  return 0;
+}
+
+int orc_get_patch(const orc_sim *s, int32_t ext[4]) {
+  for (int k = 0; k < 4; k++) ext[k] = s->has_patch ? s->ext[k] : 0;
+  return 0;
+}
+
+int orc_get_regrid(const orc_sim *s, uint8_t *flags, int32_t *scan,
+                   int32_t *list, int32_t *count) {
+  if (s->p.mode == ORC_UNIFORM) return -1;
+  size_t nb = (size_t)s->NBx * s->NBy;
+  if (flags) memcpy(flags, s->bflag, nb);
+  if (scan) memcpy(scan, s->bscan, nb * sizeof(int32_t));
+  if (list) memcpy(list, s->blist, (size_t)s->bcount * sizeof(int32_t));
+  if (count) *count = s->bcount;
+  return 0;
+}
+
+int orc_time(const orc_sim *s, double *t, int64_t *step) {
+  if (t) *t = (double)s->step * s->L0.dt;
+  if (step) *step = s->step;
+  return 0;
+}
+
+/* out: omega, lambda, dx, dt, nu_m, n_c, eeff_fac, E_bd, E0, D_e, D_a, n_amb,
+ * a, b, ktilde, nu_att, steps_per_period */
+int orc_derived(const orc_params *p, double *out, int n_out) {
+  orc_sim s;
+  memset(&s, 0, sizeof(s));
+  s.p = *p;
+  derive(&s);
+  double dx = s.lambda / p->cells_per_lambda;
+  double dt = p->courant * dx / C_0;
+  double a = exp(-s.nu_m * dt);
+  double v[17] = {s.omega, s.lambda, dx, dt, s.nu_m, s.n_c, s.eeff_fac,
+                  s.e0 / sqrt(2.0) / p->erms_over_ebd, s.e0, s.d_e, s.d_a,
+                  s.n_amb, a, Q_E * Q_E * (1.0 - a) / (M_E * s.nu_m),
+                  2.0 / dx * asin(sin(0.5 * s.omega * dt) / p->courant),
+                  s.nu_att, p->cells_per_lambda / p->courant};
+  for (int k = 0; k < n_out && k < 17; k++) out[k] = v[k];
+  return 0;
+}

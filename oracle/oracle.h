@@ -1,0 +1,111 @@
+/*
+ * oracle.h -- FP64 CPU oracle of the coupled EM / plasma-fluid update with
+ * dynamic mesh refinement (Ghosh & Chaudhury, "Efficient Dynamic Mesh
+ * Refinement Technique for Simulation of HPM Breakdown induced Plasma Pattern
+ * Formation").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library
+ * against a plain, slow, obviously correct implementation.  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may load it.
+ * It shares no code, header, table or constant with the GPU library.
+ *
+ * What it computes (paper section / equation in brackets):
+ *   - Maxwell TE_z on a Yee grid, Eqs. (1)-(2) [Sec. II.B]
+ *   - electron momentum in current form, J = -e n v, Eq. (3), with a
+ *     semi-implicit exponential-trapezoid E-J coupling
+ *   - a one-period sliding E_rms window and the continuity step, Eq. (4),
+ *     with effective-field ionisation and an effective-diffusion blend
+ *   - one r = 2 fine patch with time subcycling, Eq. (5b) boundary transfer,
+ *     restriction back to the coarse mesh, and the self-aware expansion of
+ *     Sec. III.D (threshold + gradient-length flags on 16x16 blocks, prefix
+ *     sum compaction, bounding-box growth, Eq. (5a) prolongation).
+ * All floating-point state is double.  The regrid flag decision is taken in
+ * binary32 (the precision of the GPU kernels) so that both sides decide on
+ * identical inputs identically.
+ *
+ * Field layout returned by orc_get_field / taken by orc_set_field:
+ * row-major, y rows, x fastest, no padding:
+ *   HZ  [ny  ][nx  ]   cell centres (i+1/2, j+1/2)
+ *   EX  [ny+1][nx  ]   x-edges      (i+1/2, j)      (JX likewise)
+ *   EY  [ny  ][nx+1]   y-edges      (i, j+1/2)      (JY likewise)
+ *   N, ACC, ERMS2 [ny+1][nx+1] nodes (i, j); RING = 8 node planes.
+ * For level 1 (the fine patch) nx, ny are the patch size in fine cells.
+ * Units are SI.  Functions return 0 on success and a negative code on error.
+ */
+#ifndef DMR_ORACLE_H
+#define DMR_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_BC_MUR = 0, ORC_BC_PEC = 1, ORC_BC_PERIODIC = 2 };
+enum { ORC_UNIFORM = 0, ORC_STATIC = 1, ORC_DYNAMIC = 2 };
+enum { ORC_D_BLEND = 0, ORC_D_CONST = 1 };
+enum {
+  ORC_HZ = 0, ORC_EX = 1, ORC_EY = 2, ORC_JX = 3, ORC_JY = 4,
+  ORC_N = 5, ORC_ACC = 6, ORC_ERMS2 = 7, ORC_RING = 8
+};
+
+typedef struct orc_params {
+  /* wave and gas */
+  double freq_hz;          /* incident frequency f */
+  double erms_over_ebd;    /* incident rms field / breakdown field */
+  double p_torr;           /* gas pressure */
+  /* ionisation fit: nu_net = nu_m*A*[(E_eff/p)^beta - (E_cr/p)^beta] */
+  double A_ion, beta_ion, ecr_over_p; /* E/p in V/(cm Torr) */
+  /* diffusion */
+  double te_ev, ti_ev, mu_i_760, L_amb, d_const;
+  /* refinement criteria */
+  double n_thr_over_nc, grad_thr, n_floor_over_nc;
+  double courant;          /* S = c dt / dx on every level */
+  int32_t nx, ny;          /* base-level cells */
+  int32_t cells_per_lambda;/* base-level N_lambda */
+  int32_t r;               /* refinement factor (2) */
+  int32_t block;           /* regrid block edge in base cells */
+  int32_t regrid_every;    /* base steps between regrids */
+  int32_t tfsf_i;          /* TF/SF node column on the base level; <=0: off */
+  int32_t ramp_periods;    /* sin^2 ramp length */
+  int32_t bc_x, bc_y;      /* ORC_BC_* */
+  int32_t mode;            /* ORC_UNIFORM / ORC_STATIC / ORC_DYNAMIC */
+  int32_t static_ext[4];   /* I0, J0, I1, J1 in base cells (ORC_STATIC) */
+  int32_t d_mode;          /* ORC_D_* */
+  int32_t continuity_on;   /* 0 freezes n (and skips the window) */
+} orc_params;
+
+typedef struct orc_sim orc_sim;
+
+/* seed_base: node densities of the base level, [ny+1][nx+1] (NULL: zero).
+ * seed_fine: node densities on the full-domain fine grid [r*ny+1][r*nx+1],
+ * used for the fine patch built at t = 0 (NULL: prolong from seed_base). */
+int orc_create(const orc_params *p, const double *seed_base,
+               const double *seed_fine, orc_sim **out);
+void orc_destroy(orc_sim *s);
+int orc_step(orc_sim *s, int64_t n_base_steps);
+int orc_regrid(orc_sim *s);
+int orc_get_patch(const orc_sim *s, int32_t ext[4]);
+int orc_field_dims(const orc_sim *s, int field, int level, int32_t dims[2]);
+int orc_get_field(const orc_sim *s, int field, int level, double *dst);
+int orc_set_field(orc_sim *s, int field, int level, const double *src);
+/* block flags [NBy][NBx], exclusive scan, compacted list, count of the last
+ * regrid test */
+int orc_get_regrid(const orc_sim *s, uint8_t *flags, int32_t *scan,
+                   int32_t *list, int32_t *count);
+int orc_time(const orc_sim *s, double *t, int64_t *step);
+/* derived scalars, for pins: see orc_derived in the source */
+int orc_derived(const orc_params *p, double *out, int n_out);
+/* net ionisation rate for a given E_rms^2 (V^2/m^2) */
+double orc_nu_net(const orc_params *p, double erms2);
+double orc_d_eff(const orc_params *p, double n);
+/* one continuity step on given node arrays (layout as the fields above),
+ * zero-flux or periodic outer faces */
+int orc_continuity_apply(const orc_params *p, int nx, int ny, double dx,
+                         double dtn, int perx, int pery, const double *n_in,
+                         const double *erms2, double *n_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,85 @@
+"""Pins of the refined run (Sec. III.C, III.D, IV.B): a coarse mesh with one
+r = 2 patch must behave like the uniform fine mesh.  The paper reports front
+velocity and filament length within 1-2% of the uniform fine run (Sec. IV.B);
+a vacuum plane wave must cross a patch without visible reflection, and a
+long run must stay bounded."""
+import numpy as np
+import pytest
+
+from paper_2105_13276_amd import workloads as W
+
+LAM = 299792458.0 / 110e9
+
+
+def test_vacuum_patch_reflection_and_stability(oracle_mod):
+    cfg = W.make(128, 64, 32, "static", 1, static_ext=(48, 16, 96, 48),
+                 continuity_on=False)
+    E0 = oracle_mod.derived(cfg)["E0"]
+    s = oracle_mod.Sim(cfg, np.zeros((cfg["ny"] + 1, cfg["nx"] + 1)))
+    spp = cfg["steps_per_period"]
+    peaks = []
+    for per in range(1, 61):
+        s.step(spp)
+        if per >= 10 and per % 5 == 0:
+            ey = s.get("ey")
+            # the scattered-field strip sees only what the patch reflects
+            assert np.abs(ey[:, :cfg["tfsf_i"]]).max() < 0.01 * E0
+            peaks.append(np.abs(s.get("ey", 1)).max() / E0)
+    peaks = np.array(peaks)
+    assert peaks.max() < 1.01 and np.ptp(peaks) < 1e-3
+
+
+def test_pec_cavity_with_patch_bounded(oracle_mod):
+    """Lossless cavity holding a patch: the interface adds no energy over
+    8000 coarse steps (the known weak spot of subgridding is late-time
+    growth)."""
+    cfg = W.make(64, 64, 32, "static", 1, bc_x="pec", bc_y="pec", tfsf_i=0,
+                 static_ext=(16, 16, 48, 48), continuity_on=False)
+    nx, ny = cfg["nx"], cfg["ny"]
+    s = oracle_mod.Sim(cfg, np.zeros((ny + 1, nx + 1)))
+    mode = lambda x, y: 1e6 * np.sin(np.pi * x) * np.sin(np.pi * y)
+    I, J = np.meshgrid(np.arange(nx + 1.0), np.arange(ny) + 0.5)
+    s.set("ey", 0, mode(I / nx, J / ny))
+    r, c = s.dims("ey", 1)
+    I, J = np.meshgrid(32 + np.arange(c), 32 + np.arange(r) + 0.5)
+    s.set("ey", 1, mode(I / (2 * nx), J / (2 * ny)))
+
+    def energy():
+        return ((s.get("ex") ** 2).sum() + (s.get("ey") ** 2).sum()
+                + ((376.73 * s.get("hz")) ** 2).sum())
+
+    e0 = energy()
+    for _ in range(40):
+        s.step(200)
+        assert energy() < 1.5 * e0
+    assert np.isfinite(s.get("hz", 1)).all()
+
+
+def _grow_case(ratio=2.5):
+    dxc = LAM / 32
+    cfgd = W.make(96, 48, 32, "dynamic", 1, erms_over_ebd=ratio)
+    cfgu = W.make(192, 96, 64, "uniform", 1, erms_over_ebd=ratio)
+    cen, pk = [(59.5 * dxc, 24 * dxc)], [1e17]
+    return cfgd, cfgu, W.seeds(cfgd, cen, pk), W.seeds(cfgu, cen, pk)[0]
+
+
+def test_dmr_matches_uniform_fine_with_growth(oracle_mod):
+    cfgd, cfgu, (sb, sf), su = _grow_case()
+    d = oracle_mod.Sim(cfgd, sb, sf)
+    u = oracle_mod.Sim(cfgu, su)
+    p0 = d.patch()
+    spp = cfgd["steps_per_period"]
+    d.step(60 * spp)
+    u.step(120 * spp)
+    p1 = d.patch()
+    assert p1 != p0 and p1[0] <= p0[0] and p1[2] > p0[2]   # it grew
+    P0, Q0, P1, Q1 = (2 * v for v in p1)
+    nf, nu = d.get("n", 1), u.get("n")[Q0:Q1 + 1, P0:P1 + 1]
+    ef, eu = d.get("erms2", 1), u.get("erms2")[Q0:Q1 + 1, P0:P1 + 1]
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert nu.max() > 5e17                      # the plasma grew ~10x
+    assert rel(nf, nu) < 0.02 and rel(ef, eu) < 0.02
+    assert abs(nf.sum() / nu.sum() - 1) < 0.02
+    # the coarse mesh carries the fine solution back (injection at sync)
+    nc = d.get("n", 0)[p1[1] + 1:p1[3], p1[0] + 1:p1[2]]
+    assert np.array_equal(nc, nf[2:-1:2, 2:-1:2])
