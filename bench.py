@@ -1,0 +1,201 @@
+"""Benchmark: DMR vs uniform-fine time to t_final on one MI355X.
+
+Workload (the configuration the metric is quoted on): coarse 512x256 cells
+at lambda/32 with one r = 2 patch grown by the regrid test every 4 periods,
+200 wave periods of a 110 GHz incident wave (12800 coarse steps); beside it
+the uniform-fine 1024x512 run at lambda/64 of the same case (25600 steps).
+
+One benchmark "step" = one regrid interval = 256 coarse steps (4 periods):
+every part of the update runs in it (EM steps on both levels, subcycling,
+boundary transfer, restriction, window, continuity every 8 steps, growth
+test).  --steps 50 (the default) is the whole run to t_final.  Inputs are
+synthetic (Gaussian seed of the paper's form) and resident in HBM before the
+timed region starts.
+
+Prints one JSON line.  value = cell-updates actually performed by the DMR
+run (sum over levels of cells x steps) per second; the uniform-fine run, the
+uniform-fine-equivalent rate of the DMR run and the speedup are extra keys.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+INTERVAL = 256  # coarse steps per benchmark step
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 4096x2048 bandwidth-bound kernel measurement")
+    ap.add_argument("--cpu-steps", type=int, default=1024,
+                    help="coarse steps of the oracle sample")
+    return ap.parse_args()
+
+
+def em_bytes_per_cell():
+    # base EM kernel: read Hz, Ex, Ey, Jx, Jy, n, acc; write Hz, Ex, Ey, Jx,
+    # Jy, acc (float32) -- the minimum with halos reused on chip
+    return 13 * 4
+
+
+def run_case(B, cfg, seeds, chunks, chunk, warmup, timing):
+    """Fresh simulation at t = 0, `chunks` x `chunk` base steps timed.
+    Returns the handle, the wall time and the cell-updates performed (the
+    patch changes only at the regrid that ends a chunk)."""
+    import torch
+    sb, sf = seeds
+    if warmup:  # a throw-away instance runs the same kernels first
+        w = B.Sim(cfg, sb, sf)
+        w.step(warmup * chunk)
+        w.sync()
+        w.close()
+    sim = B.Sim(cfg, sb, sf)
+    if timing:
+        sim.set_timing(True)
+    r = cfg["r"] if cfg["mode"] != "uniform" else 1
+    base_cells = cfg["nx"] * cfg["ny"]
+    work = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(chunks):
+        e = sim.patch() if cfg["mode"] != "uniform" else (0, 0, 0, 0)
+        fine_cells = r * r * (e[2] - e[0]) * (e[3] - e[1])
+        work += chunk * (base_cells + r * fine_cells)  # r fine steps per base step
+        sim.step(chunk)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.sync()
+    return sim, wall, work
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2105_13276_amd import binding as B
+    from paper_2105_13276_amd import workloads as W
+
+    torch.cuda.init()
+    K, Wm = args.steps, args.warmup
+    periods = K * INTERVAL // 64
+
+    # ---- DMR run --------------------------------------------------------
+    cfg_d = W.config1_dmr(periods=periods)
+    seeds_d = W.seeds(cfg_d)
+    n_coarse = K * INTERVAL
+    sim_d, wall_d, work_d = run_case(B, cfg_d, seeds_d, K, INTERVAL, Wm, False)
+    ext = sim_d.patch()
+    fine_cells = 4 * (ext[2] - ext[0]) * (ext[3] - ext[1])
+    coarse_cells = cfg_d["nx"] * cfg_d["ny"]
+    sim_d.close()
+
+    # same run again with per-kernel HIP events (roofline of the base kernel)
+    sim_t, _, _ = run_case(B, cfg_d, seeds_d, K, INTERVAL, 0, True)
+    ms, cnt = sim_t.timing()
+    sim_t.close()
+
+    # ---- uniform-fine run -------------------------------------------------
+    cfg_u = W.config1_uniform(periods=periods)
+    seeds_u = W.seeds(cfg_u)
+    sim_u, wall_u, work_u = run_case(B, cfg_u, seeds_u, K, 2 * INTERVAL, Wm, False)
+    sim_u.close()
+    sim_ut, _, _ = run_case(B, cfg_u, seeds_u, K, 2 * INTERVAL, 0, True)
+    ms_u, cnt_u = sim_ut.timing()
+    sim_ut.close()
+
+    # dominant kernel of the DMR workload
+    cls_names = ["base_em", "fine_em", "continuity", "regrid"]
+    dom = int(np.argmax(ms))
+    per_launch_ms = ms[dom] / max(cnt[dom], 1)
+    if dom == 0:
+        alg_bytes = em_bytes_per_cell() * coarse_cells
+    elif dom == 1:
+        alg_bytes = em_bytes_per_cell() * fine_cells
+    else:
+        alg_bytes = None
+    achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9 if alg_bytes else None
+    roofline = {"bound": "hbm", "kernel": "k_em<base>" if dom == 0 else cls_names[dom],
+                "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                "frac": (achieved / 8000.0) if achieved else None, "traffic": None,
+                "alg_bytes_per_launch": alg_bytes, "avg_launch_us": per_launch_ms * 1e3,
+                "note": "config-1 state (7.9 MB) is cache resident; HBM-bound "
+                        "figures are in roofline_large"}
+
+    out = {
+        "metric": "Mcell-updates/s & time-to-t_final: DMR vs uniform-fine, same MI355X",
+        "value": work_d / wall_d / 1e6,
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1, "steps": K, "warmup": Wm,
+        "ms_per_step": wall_d / K * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "DMR config 1: coarse 512x256 @ lambda/32 + r=2 patch, "
+                               "%d periods (%d coarse steps), vs uniform-fine 1024x512"
+                               % (periods, n_coarse),
+                   "global_batch": 1, "seq_len": None, "parallelism": "none"},
+        "time_to_t_final_s": wall_d,
+        "patch_final": list(ext),
+        "uniform_fine_equiv_mcell_updates_per_s": work_u / wall_d / 1e6,
+        "uniform_fine": {"time_to_t_final_s": wall_u,
+                         "mcell_updates_per_s": work_u / wall_u / 1e6,
+                         "kernel_ms": ms_u, "launches": cnt_u},
+        "speedup_vs_uniform_fine": wall_u / wall_d,
+        "kernel_ms": dict(zip(cls_names, ms)),
+        "kernel_launches": dict(zip(cls_names, cnt)),
+        "roofline": roofline,
+    }
+
+    # ---- bandwidth-bound shape: 4096x2048 coarse (added large row) --------
+    if not args.no_large:
+        cfg_l = W.config_large(periods=1)
+        seeds_l = W.seeds(cfg_l, fine=False)
+        sim_l = B.Sim(cfg_l, seeds_l[0], None)
+        sim_l.step(64)
+        sim_l.set_timing(True)
+        sim_l.step(128)
+        ms_l, cnt_l = sim_l.timing()
+        sim_l.close()
+        cells_l = cfg_l["nx"] * cfg_l["ny"]
+        per_l = ms_l[0] / max(cnt_l[0], 1)
+        ach_l = em_bytes_per_cell() * cells_l / (per_l * 1e-3) / 1e9
+        out["roofline_large"] = {"bound": "hbm", "kernel": "k_em<base> 4096x2048",
+                                 "achieved": ach_l, "peak": 8000.0, "unit": "GB/s",
+                                 "frac": ach_l / 8000.0, "avg_launch_us": per_l * 1e3,
+                                 "alg_bytes_per_launch": em_bytes_per_cell() * cells_l}
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample ---------------
+    if not args.no_cpu:
+        from oracle import oracle as O
+        o = O.Sim(cfg_d, *seeds_d)
+        e0 = o.patch()
+        t0 = time.perf_counter()
+        o.step(args.cpu_steps)
+        cw = time.perf_counter() - t0
+        e1 = o.patch()
+        fc = 4 * (e1[2] - e1[0]) * (e1[3] - e1[1])
+        work_c = coarse_cells * args.cpu_steps + fc * 2 * args.cpu_steps
+        out["cpu_baseline"] = {"value": work_c / cw / 1e6, "unit": "Mcell-updates/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "FP64 oracle, DMR config 1, first %d coarse "
+                                         "steps (%.0f periods), %.1f s, single thread"
+                                         % (args.cpu_steps, args.cpu_steps / 64.0, cw)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * dmr.h -- C ABI of the MI355X (gfx950) library for the coupled EM / plasma
+ * fluid update with dynamic mesh refinement of Ghosh & Chaudhury,
+ * "Efficient Dynamic Mesh Refinement Technique for Simulation of HPM
+ * Breakdown induced Plasma Pattern Formation".
+ *
+ * The library advances, on one GPU and one HIP stream:
+ *   - the Yee TE_z update of Hz, Ex, Ey (Eqs. (1)-(2), Sec. II.B), with a
+ *     total-field/scattered-field plane-wave source entering from the left
+ *     and first-order Mur outer boundaries (Sec. II.B, Fig. 1 caption);
+ *   - the electron current dJ/dt = -nu_m J + (e^2 n/m) E (Eq. (3) in current
+ *     form, J = -e n v), coupled semi-implicitly to E;
+ *   - the one-period E_rms window and the continuity step
+ *     dn/dt = div(D_eff grad n) + nu(E_eff) n (Eq. (4), Sec. II.A), every 1/8
+ *     of a wave period;
+ *   - one r = 2 fine patch over the plasma (Sec. III): two fine substeps per
+ *     coarse step, tangential E on the coarse/fine boundary by Eq. (5b),
+ *     fine -> coarse transfer after the second substep, density transfers at
+ *     each continuity step, and the self-aware growth test of Sec. III.A-D
+ *     (threshold and gradient-length flags on square blocks, prefix-sum
+ *     compaction, bounding-box growth, Eq. (5a) prolongation).
+ *
+ * Conventions for every call:
+ *   - Return value: DMR_OK (0) or a negative DMR_E* code; the text of the
+ *     last error of a handle is in dmr_last_error().  Nothing aborts or
+ *     throws across the ABI.  A handle is not thread-safe.
+ *   - The library allocates no device memory.  The caller passes one device
+ *     workspace of at least dmr_workspace_bytes() bytes that must outlive the
+ *     handle, and the HIP stream (hipStream_t as void*, NULL = default
+ *     stream) on which all work is queued.
+ *   - Calls that only queue work (dmr_step) return before it ends; calls
+ *     that hand data to the host synchronise the stream.
+ *   - Fields are float32, SI units, row-major with y rows and x fastest,
+ *     no padding:
+ *        DMR_HZ        [ny  ][nx  ]  cell centres (i+1/2, j+1/2)   A/m
+ *        DMR_EX/JX     [ny+1][nx  ]  x-edges      (i+1/2, j)   V/m, A/m^2
+ *        DMR_EY/JY     [ny  ][nx+1]  y-edges      (i, j+1/2)   V/m, A/m^2
+ *        DMR_N, DMR_ACC, DMR_ERMS2 [ny+1][nx+1] nodes (i, j)  m^-3, V^2/m^2
+ *        DMR_RING      8 planes of nodes (mean E^2 of each 1/8 period)
+ *     Level 0 is the base (coarse, or the only) mesh; level 1 is the fine
+ *     patch, whose nx, ny are its size in fine cells (dmr_field_dims).
+ */
+#ifndef DMR_H
+#define DMR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DMR_OK 0
+#define DMR_EINVAL (-1)    /* bad argument, or a stability/shape rule broken */
+#define DMR_ENOMEM (-2)    /* workspace too small */
+#define DMR_EHIP (-3)      /* a HIP call failed (also late async errors) */
+#define DMR_EUNSTABLE (-4) /* non-finite density or window detected */
+
+enum { DMR_BC_MUR = 0, DMR_BC_PEC = 1 };
+enum { DMR_UNIFORM = 0, DMR_STATIC = 1, DMR_DYNAMIC = 2 };
+enum { DMR_D_BLEND = 0, DMR_D_CONST = 1 };
+enum {
+  DMR_HZ = 0, DMR_EX = 1, DMR_EY = 2, DMR_JX = 3, DMR_JY = 4,
+  DMR_N = 5, DMR_ACC = 6, DMR_ERMS2 = 7, DMR_RING = 8
+};
+
+/* The problem statement of Sec. II.B / Sec. IV: domain, incident wave, gas,
+ * seed, resolution, refinement factor and refinement thresholds.  Plain old
+ * data, copied at dmr_create; struct_size must be sizeof(dmr_params). */
+typedef struct dmr_params {
+  uint32_t struct_size;
+  int32_t nx, ny;            /* base-level cells (domain = nx*dx by ny*dx) */
+  int32_t cells_per_lambda;  /* base-level N_lambda (dx = lambda/N) */
+  int32_t r;                 /* refinement factor; only 2 is supported */
+  int32_t block;             /* regrid block edge in base cells (divides nx, ny) */
+  int32_t regrid_every;      /* base steps between growth tests */
+  int32_t tfsf_i;            /* source node column (base cells), 1..nx-1 */
+  int32_t ramp_periods;      /* sin^2 turn-on of the incident wave */
+  int32_t bc_x, bc_y;        /* DMR_BC_MUR or DMR_BC_PEC */
+  int32_t mode;              /* DMR_UNIFORM, DMR_STATIC, DMR_DYNAMIC */
+  int32_t static_ext[4];     /* I0, J0, I1, J1 base cells (DMR_STATIC) */
+  int32_t d_mode;            /* DMR_D_BLEND (default) or DMR_D_CONST */
+  int32_t continuity_on;     /* 0: density and window frozen */
+  int32_t pad_;
+  double freq_hz;            /* incident frequency */
+  double erms_over_ebd;      /* incident rms field / breakdown field */
+  double p_torr;             /* gas pressure; nu_m = 5.3e9 p (Sec. II.A) */
+  double A_ion, beta_ion;    /* nu = nu_m A [(E_eff/p)^beta - (E_cr/p)^beta] */
+  double ecr_over_p;         /* E_cr/p, V/(cm Torr) */
+  double te_ev, ti_ev;       /* electron / ion temperature, eV */
+  double mu_i_760;           /* ion mobility at 760 Torr, m^2/(V s) */
+  double L_amb;              /* ambipolar transition length, m */
+  double d_const;            /* D for DMR_D_CONST, m^2/s */
+  double n_thr_over_nc;      /* threshold density / critical density */
+  double grad_thr;           /* flag where |grad n| dx / n > grad_thr */
+  double n_floor_over_nc;    /* gradient test only above this density */
+  double courant;            /* S = c dt/dx, same on both levels, <= 1/sqrt 2 */
+} dmr_params;
+
+typedef struct dmr_sim dmr_sim;
+
+/* Bytes of device workspace the problem needs, sized for a patch covering
+ * the whole domain so that growth never reallocates.  EINVAL on bad params. */
+int dmr_workspace_bytes(const dmr_params *p, size_t *bytes);
+
+/* Create a simulation at t = 0: fields and current zero, density from the
+ * seeds (the Gaussian of Sec. IV, or any field), and for DMR_DYNAMIC the
+ * growth test run once to place the initial patch (Sec. III.D).
+ *   seed_base  host float64 node densities of level 0, [ny+1][nx+1]; NULL = 0
+ *   seed_fine  host float64 densities on the full-domain fine grid
+ *              [r*ny+1][r*nx+1], used for the patch built at t = 0;
+ *              NULL = interpolate from seed_base (Eq. (5a))
+ *   d_workspace, bytes  caller-owned device memory, see above
+ *   stream     hipStream_t (void*), used by every later call
+ * On success *out owns host memory only; free it with dmr_destroy. */
+int dmr_create(const dmr_params *p, const double *seed_base,
+               const double *seed_fine, void *d_workspace, size_t bytes,
+               void *stream, dmr_sim **out);
+
+/* Release the handle (not the workspace).  Waits for queued work. */
+void dmr_destroy(dmr_sim *s);
+
+/* Queue n base (coarse) steps: per step the coarse EM update, two fine
+ * substeps with boundary transfer and the fine -> coarse transfer
+ * (Sec. III.C), every 1/8 period the window and continuity step on both
+ * levels plus density transfers, and every regrid_every steps the growth
+ * test (which synchronises the stream to read back 16 bytes of extents). */
+int dmr_step(dmr_sim *s, int64_t n);
+
+/* Run the growth test now (Sec. III.A-D); grows the patch if needed. */
+int dmr_regrid(dmr_sim *s);
+
+/* Patch extents in base cells {I0, J0, I1, J1}; all zero when there is no
+ * patch.  Synchronises the stream. */
+int dmr_get_patch(dmr_sim *s, int32_t ext[4]);
+
+/* Result of the last growth test: block flags [NBy][NBx] (uint8), their
+ * exclusive prefix sum, the compacted list of flagged block ids (row-major
+ * block index by*NBx+bx, ascending) and its length.  Any pointer may be
+ * NULL; list must hold NBx*NBy entries.  Synchronises the stream. */
+int dmr_get_regrid(dmr_sim *s, uint8_t *flags, int32_t *scan, int32_t *list,
+                   int32_t *count);
+
+/* Rows and columns of a field on a level (RING: 8*(ny+1) rows). */
+int dmr_field_dims(dmr_sim *s, int field, int level, int32_t dims[2]);
+
+/* Copy a field into dst (host or device memory, bytes >= rows*cols*4),
+ * converted to SI.  Synchronises the stream. */
+int dmr_read_field(dmr_sim *s, int field, int level, float *dst,
+                   size_t bytes, int dst_on_device);
+
+/* Overwrite a field (tests, fault injection, restarts); ERMS2 is read-only.
+ * Synchronises the stream. */
+int dmr_write_field(dmr_sim *s, int field, int level, const float *src,
+                    size_t bytes, int src_on_device);
+
+/* Simulated time (s) and base steps taken. */
+int dmr_time(dmr_sim *s, double *t, int64_t *step);
+
+/* Wait for queued work; returns DMR_EUNSTABLE if a continuity step saw a
+ * non-finite density or window value, DMR_EHIP on a HIP error. */
+int dmr_sync(dmr_sim *s);
+
+/* Per-kernel timing with HIP events on the handle's stream (off by
+ * default).  Classes: 0 base-level EM step, 1 fine EM substep,
+ * 2 continuity (both levels), 3 growth test and prolongation.
+ * dmr_get_timing fills total milliseconds and launch counts per class since
+ * the last reset and synchronises the stream. */
+int dmr_set_timing(dmr_sim *s, int on);
+int dmr_get_timing(dmr_sim *s, double ms[4], int64_t launches[4]);
+
+/* Text of the last error on this handle (never NULL). */
+const char *dmr_last_error(const dmr_sim *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -516,8 +516,8 @@ int orc_continuity_apply(const orc_params *p, int nx, int ny, double dx,
                          double dtn, int perx, int pery, const double *n_in,
                          const double *erms2, double *n_out) {
   size_t nn = (size_t)(nx + 1) * (ny + 1);
-  double *a = malloc(nn * sizeof(double)), *e = malloc(nn * sizeof(double)),
-         *o = malloc(nn * sizeof(double));
+  double *a = calloc(nn, sizeof(double)), *e = calloc(nn, sizeof(double)),
+         *o = calloc(nn, sizeof(double));
   if (!a || !e || !o) {
     free(a); free(e); free(o);
     return -2;

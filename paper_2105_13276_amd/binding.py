@@ -1,0 +1,234 @@
+"""Thin ctypes binding of libdmr.so (include/dmr.h).
+
+Argument marshalling only: every step of the update runs in the HIP kernels
+of libdmr.so.  PyTorch provides the device workspace and the stream.  If the
+library has not been built this module raises on use; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(PKG, "libdmr.so")
+
+BC = {"mur": 0, "pec": 1}
+MODE = {"uniform": 0, "static": 1, "dynamic": 2}
+DMODE = {"blend": 0, "const": 1}
+FIELD = {"hz": 0, "ex": 1, "ey": 2, "jx": 3, "jy": 4, "n": 5, "acc": 6,
+         "erms2": 7, "ring": 8}
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSTABLE"}
+
+SYMBOLS = ["dmr_workspace_bytes", "dmr_create", "dmr_destroy", "dmr_step",
+           "dmr_regrid", "dmr_get_patch", "dmr_get_regrid", "dmr_field_dims",
+           "dmr_read_field", "dmr_write_field", "dmr_time", "dmr_sync",
+           "dmr_set_timing", "dmr_get_timing", "dmr_last_error"]
+
+
+class DmrParams(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32),
+        ("cells_per_lambda", C.c_int32), ("r", C.c_int32),
+        ("block", C.c_int32), ("regrid_every", C.c_int32),
+        ("tfsf_i", C.c_int32), ("ramp_periods", C.c_int32),
+        ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("mode", C.c_int32),
+        ("static_ext", C.c_int32 * 4), ("d_mode", C.c_int32),
+        ("continuity_on", C.c_int32), ("pad_", C.c_int32),
+        ("freq_hz", C.c_double), ("erms_over_ebd", C.c_double),
+        ("p_torr", C.c_double), ("A_ion", C.c_double),
+        ("beta_ion", C.c_double), ("ecr_over_p", C.c_double),
+        ("te_ev", C.c_double), ("ti_ev", C.c_double),
+        ("mu_i_760", C.c_double), ("L_amb", C.c_double),
+        ("d_const", C.c_double), ("n_thr_over_nc", C.c_double),
+        ("grad_thr", C.c_double), ("n_floor_over_nc", C.c_double),
+        ("courant", C.c_double),
+    ]
+
+
+class DmrError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libdmr.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise ImportError(
+                "libdmr.so is not built; run `python -m paper_2105_13276_amd.build` "
+                "(or __graft_entry__.build()) first")
+        L = C.CDLL(LIB)
+        P, V = C.POINTER, C.c_void_p
+        L.dmr_workspace_bytes.argtypes = [P(DmrParams), P(C.c_size_t)]
+        L.dmr_create.argtypes = [P(DmrParams), V, V, V, C.c_size_t, V, P(V)]
+        L.dmr_destroy.argtypes = [V]
+        L.dmr_destroy.restype = None
+        L.dmr_step.argtypes = [V, C.c_int64]
+        L.dmr_regrid.argtypes = [V]
+        L.dmr_get_patch.argtypes = [V, P(C.c_int32)]
+        L.dmr_get_regrid.argtypes = [V, V, V, V, P(C.c_int32)]
+        L.dmr_field_dims.argtypes = [V, C.c_int, C.c_int, P(C.c_int32)]
+        L.dmr_read_field.argtypes = [V, C.c_int, C.c_int, V, C.c_size_t, C.c_int]
+        L.dmr_write_field.argtypes = [V, C.c_int, C.c_int, V, C.c_size_t, C.c_int]
+        L.dmr_time.argtypes = [V, P(C.c_double), P(C.c_int64)]
+        L.dmr_sync.argtypes = [V]
+        L.dmr_set_timing.argtypes = [V, C.c_int]
+        L.dmr_get_timing.argtypes = [V, P(C.c_double), P(C.c_int64)]
+        L.dmr_last_error.argtypes = [V]
+        L.dmr_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def make_params(cfg: dict) -> DmrParams:
+    p = DmrParams()
+    p.struct_size = C.sizeof(DmrParams)
+    for name, _ in DmrParams._fields_:
+        if name in ("struct_size", "pad_"):
+            continue
+        if name in ("bc_x", "bc_y"):
+            setattr(p, name, BC[cfg[name]])
+        elif name == "mode":
+            p.mode = MODE[cfg["mode"]]
+        elif name == "d_mode":
+            p.d_mode = DMODE[cfg["d_mode"]]
+        elif name == "static_ext":
+            for k, v in enumerate(cfg.get("static_ext", (0, 0, 0, 0))):
+                p.static_ext[k] = int(v)
+        elif name == "continuity_on":
+            p.continuity_on = int(bool(cfg["continuity_on"]))
+        else:
+            setattr(p, name, cfg[name])
+    return p
+
+
+def workspace_bytes(cfg: dict) -> int:
+    p = make_params(cfg)
+    n = C.c_size_t()
+    rc = lib().dmr_workspace_bytes(C.byref(p), C.byref(n))
+    if rc:
+        raise DmrError("dmr_workspace_bytes: %s" % ERRORS.get(rc, rc))
+    return n.value
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Sim:
+    """One simulation on one GPU.  The workspace is a torch uint8 tensor and
+    work is queued on torch's current stream of ``device``."""
+
+    def __init__(self, cfg: dict, seed_base=None, seed_fine=None,
+                 device: str = "cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise DmrError("no HIP device available")
+        self.cfg = dict(cfg)
+        self.device = torch.device(device)
+        self._p = make_params(cfg)
+        nbytes = workspace_bytes(cfg)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream or torch.cuda.current_stream(self.device)
+        sb = None if seed_base is None else np.ascontiguousarray(seed_base, np.float64)
+        sf = None if seed_fine is None else np.ascontiguousarray(seed_fine, np.float64)
+        if sb is not None and sb.shape != (cfg["ny"] + 1, cfg["nx"] + 1):
+            raise ValueError("seed_base shape %s" % (sb.shape,))
+        if sf is not None and sf.shape != (cfg["r"] * cfg["ny"] + 1, cfg["r"] * cfg["nx"] + 1):
+            raise ValueError("seed_fine shape %s" % (sf.shape,))
+        h = C.c_void_p()
+        rc = lib().dmr_create(C.byref(self._p), _ptr(sb), _ptr(sf),
+                              C.c_void_p(self.workspace.data_ptr()), nbytes,
+                              C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc:
+            raise DmrError("dmr_create failed: %s" % ERRORS.get(rc, rc))
+        self._h = h
+
+    def _check(self, rc, what):
+        if rc:
+            msg = lib().dmr_last_error(self._h).decode()
+            raise DmrError("%s: %s (%s)" % (what, ERRORS.get(rc, rc), msg))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dmr_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def step(self, n: int):
+        self._check(lib().dmr_step(self._h, int(n)), "dmr_step")
+
+    def regrid(self):
+        self._check(lib().dmr_regrid(self._h), "dmr_regrid")
+
+    def sync(self):
+        self._check(lib().dmr_sync(self._h), "dmr_sync")
+
+    def patch(self):
+        e = (C.c_int32 * 4)()
+        self._check(lib().dmr_get_patch(self._h, e), "dmr_get_patch")
+        return tuple(e)
+
+    def regrid_info(self):
+        nbx = self.cfg["nx"] // self.cfg["block"]
+        nby = self.cfg["ny"] // self.cfg["block"]
+        flags = np.zeros((nby, nbx), np.uint8)
+        scan = np.zeros(nbx * nby, np.int32)
+        lst = np.zeros(nbx * nby, np.int32)
+        cnt = C.c_int32()
+        self._check(lib().dmr_get_regrid(self._h, _ptr(flags), _ptr(scan),
+                                         _ptr(lst), C.byref(cnt)), "dmr_get_regrid")
+        return flags, scan, lst[:cnt.value].copy(), cnt.value
+
+    def dims(self, field: str, level: int = 0):
+        d = (C.c_int32 * 2)()
+        self._check(lib().dmr_field_dims(self._h, FIELD[field], level, d), "dmr_field_dims")
+        return (d[0], d[1])
+
+    def get(self, field: str, level: int = 0) -> np.ndarray:
+        r, c = self.dims(field, level)
+        out = np.empty((r, c), np.float32)
+        self._check(lib().dmr_read_field(self._h, FIELD[field], level, _ptr(out),
+                                         out.nbytes, 0), "dmr_read_field")
+        if field == "ring":
+            out = out.reshape(8, r // 8, c)
+        return out
+
+    def get_device(self, field: str, level: int = 0):
+        import torch
+        r, c = self.dims(field, level)
+        out = torch.empty((r, c), dtype=torch.float32, device=self.device)
+        self._check(lib().dmr_read_field(self._h, FIELD[field], level,
+                                         C.c_void_p(out.data_ptr()),
+                                         out.numel() * 4, 1), "dmr_read_field")
+        return out
+
+    def set(self, field: str, level: int, arr):
+        r, c = self.dims(field, level)
+        a = np.ascontiguousarray(arr, np.float32).reshape(-1)
+        if a.size != r * c:
+            raise ValueError("size mismatch")
+        self._check(lib().dmr_write_field(self._h, FIELD[field], level, _ptr(a),
+                                          a.nbytes, 0), "dmr_write_field")
+
+    def time(self):
+        t = C.c_double()
+        st = C.c_int64()
+        self._check(lib().dmr_time(self._h, C.byref(t), C.byref(st)), "dmr_time")
+        return t.value, st.value
+
+    def set_timing(self, on: bool):
+        self._check(lib().dmr_set_timing(self._h, int(on)), "dmr_set_timing")
+
+    def timing(self):
+        ms = (C.c_double * 4)()
+        n = (C.c_int64 * 4)()
+        self._check(lib().dmr_get_timing(self._h, ms, n), "dmr_get_timing")
+        return list(ms), list(n)

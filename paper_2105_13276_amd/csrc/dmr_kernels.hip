@@ -1,0 +1,607 @@
+// dmr_kernels.hip -- gfx950 kernels of the DMR EM / plasma-fluid update.
+//
+// All kernels work on SoA float32 arrays laid out row-major on the node grid
+// of their level: element (i, j) of any entity sits at j*pitch + i, pitch a
+// multiple of 64 floats, so one 64-lane wavefront reads one 256-byte row
+// segment.  Hz uses cells (i<NX, j<NY), Ex edges (i<NX, j<=NY), Ey edges
+// (i<=NX, j<NY), density/window nodes (i<=NX, j<=NY).  The fine level uses
+// the same layout on the full-domain fine grid, so the patch can grow without
+// moving data; only the patch region is ever touched.
+//
+// Scaled variables (chosen so the vacuum Yee coefficients are exact in
+// float32 at S = 1/2):  H~ = eta0 Hz,  J~ = (dt/eps0) J, with dt the step of
+// the level.  Then, per Eqs. (1)-(3):
+//   H~ -= S [(Ey_{i+1}-Ey_i) - (Ex_{j+1}-Ex_j)]
+//   E+ = [(1-k) E + S dH~ - (1+a)/2 J~] / (1+k),   k = kn n_e
+//   J~+ = a J~ + 2k (E + E+)
+// E, J, Hz are ping-ponged (read buffer 0, write buffer 1) so a tile can
+// recompute its halo without racing its neighbours; the window accumulator
+// is updated in place by the tile owning the node.
+#include "dmr_kernels.h"
+
+namespace dmr {
+
+// ---------------------------------------------------------------------------
+// EM step of one level (Eqs. (1)-(3)), one TX x TY tile of nodes per block.
+// The tile owns Hz(i,j), Ex(i,j), Ey(i,j) and node (i,j) for (i,j) in the
+// tile.  It stages old E over [i0-2, i0+TX] x [j0-2, j0+TY] in LDS, computes
+// new Hz over [i0-2, i0+TX) x [j0-2, j0+TY), new E over [i0-1, i0+TX) x
+// [j0-1, j0+TY) (the halo feeds the node window and the Mur boundary), and
+// then the nodes' E^2.
+//   FINE = false: the base level; outer tangential edges by Mur/PEC, the
+//                 TF/SF source on column is.
+//   FINE = true:  the patch; tangential E on its boundary from the coarse
+//                 mesh by Eq. (5b); with restrict_on, the fine -> coarse
+//                 transfer of the coarse entities strictly inside the patch.
+// ---------------------------------------------------------------------------
+template <bool FINE, int TY>
+__global__ __launch_bounds__(kThreads) void k_em(EMArgs A) {
+  constexpr int EW = kTX + 3, EH = TY + 3;  // old E
+  constexpr int HW = kTX + 2, HH = TY + 2;  // new Hz
+  constexpr int NW = kTX + 1, NH = TY + 1;  // new E
+  constexpr int DW = kTX + 2, DH = TY + 2;  // density
+  __shared__ float sExo[EH][EW], sEyo[EH][EW];
+  __shared__ float sH[HH][HW];
+  __shared__ float sExn[NH][NW], sEyn[NH][NW];
+  __shared__ float sN[DH][DW];
+  __shared__ float sJx[FINE ? TY : 1][FINE ? kTX : 1];
+  __shared__ float sJy[FINE ? TY : 1][FINE ? kTX : 1];
+
+  const int i0 = A.L + blockIdx.x * kTX;
+  const int j0 = A.B + blockIdx.y * TY;
+  const int tid = threadIdx.x;
+  const int L = A.L, R = A.R, B = A.B, T = A.T;
+  const int pitch = A.pitch;
+  auto hz_ok = [&](int i, int j) { return i >= L && i < R && j >= B && j < T; };
+  auto ex_ok = [&](int i, int j) { return i >= L && i < R && j >= B && j <= T; };
+  auto ey_ok = [&](int i, int j) { return i >= L && i <= R && j >= B && j < T; };
+  auto nd_ok = [&](int i, int j) { return i >= L && i <= R && j >= B && j <= T; };
+
+  // -- stage old E and density ----------------------------------------------
+  for (int k = tid; k < EH * EW; k += kThreads) {
+    const int ci = k % EW, cj = k / EW;
+    const int i = i0 - 2 + ci, j = j0 - 2 + cj;
+    float ex = 0.f, ey = 0.f;
+    if (ex_ok(i, j)) ex = A.ex0[(size_t)j * pitch + i];
+    if (ey_ok(i, j)) ey = A.ey0[(size_t)j * pitch + i];
+    sExo[cj][ci] = ex;
+    sEyo[cj][ci] = ey;
+  }
+  for (int k = tid; k < DH * DW; k += kThreads) {
+    const int ci = k % DW, cj = k / DW;
+    const int i = i0 - 1 + ci, j = j0 - 1 + cj;
+    sN[cj][ci] = nd_ok(i, j) ? A.n[(size_t)j * pitch + i] : 0.f;
+  }
+  __syncthreads();
+
+  // -- Faraday, Eq. (2) -------------------------------------------------------
+  for (int k = tid; k < HH * HW; k += kThreads) {
+    const int ci = k % HW, cj = k / HW;
+    const int i = i0 - 2 + ci, j = j0 - 2 + cj;
+    float h = 0.f;
+    if (hz_ok(i, j)) {
+      const size_t o = (size_t)j * pitch + i;
+      const float dey = sEyo[cj][ci + 1] - sEyo[cj][ci];
+      const float dex = sExo[cj + 1][ci] - sExo[cj][ci];
+      h = A.hz0[o] - A.S * (dey - dex);
+      if (!FINE && i == A.is - 1) h += A.S * A.ey_src;  // scattered-field side
+      if (ci >= 2 && cj >= 2) A.hz1[o] = h;
+    }
+    sH[cj][ci] = h;
+  }
+  __syncthreads();
+
+  // -- Ampere + Drude, Eqs. (1), (3) ------------------------------------------
+  for (int k = tid; k < NH * NW; k += kThreads) {
+    const int ci = k % NW, cj = k / NW;
+    const int i = i0 - 1 + ci, j = j0 - 1 + cj;
+    const bool own = ci >= 1 && cj >= 1;
+    const size_t o = (size_t)j * pitch + i;
+    float exn = 0.f, eyn = 0.f;
+    if (ex_ok(i, j)) {
+      const float e = sExo[cj + 1][ci + 1];
+      const float ne = 0.5f * (sN[cj][ci] + sN[cj][ci + 1]);
+      const float kap = A.kn * ne;
+      const bool bnd = (j == B || j == T);
+      if (!bnd) {
+        const float jo = A.jx0[o];
+        const float dh = sH[cj + 1][ci + 1] - sH[cj][ci + 1];
+        exn = ((1.f - kap) * e + A.S * dh - A.c1 * jo) / (1.f + kap);
+        if (own) {
+          const float jn = A.a * jo + 2.f * kap * (e + exn);
+          A.ex1[o] = exn;
+          A.jx1[o] = jn;
+          if (FINE) sJx[cj - 1][ci - 1] = jn;
+        }
+      } else if (FINE) {
+        // Eq. (5b): coarse row J = j/2, fine x-edge i at coarse x-index
+        // i/2 - 1/4, linear in time between the old and new coarse E
+        const int J = j >> 1;
+        int ic;
+        float w0, w1;
+        if ((i & 1) == 0) { ic = (i >> 1) - 1; w0 = 0.25f; w1 = 0.75f; }
+        else              { ic = i >> 1;       w0 = 0.75f; w1 = 0.25f; }
+        const size_t co = (size_t)J * A.cpitch + ic;
+        const float vo = w0 * A.cex0[co] + w1 * A.cex0[co + 1];
+        const float vn = w0 * A.cex1[co] + w1 * A.cex1[co + 1];
+        exn = (1.f - A.frac) * vo + A.frac * vn;
+        if (own) {
+          const float jn = A.a * A.jx0[o] + 2.f * kap * (e + exn);
+          A.ex1[o] = exn;
+          A.jx1[o] = jn;
+          sJx[cj - 1][ci - 1] = jn;
+        }
+      }
+    }
+    if (ey_ok(i, j)) {
+      const float e = sEyo[cj + 1][ci + 1];
+      const float ne = 0.5f * (sN[cj][ci] + sN[cj + 1][ci]);
+      const float kap = A.kn * ne;
+      const bool bnd = (i == L || i == R);
+      if (!bnd) {
+        const float jo = A.jy0[o];
+        const float dh = sH[cj + 1][ci + 1] - sH[cj + 1][ci];
+        float curl = -A.S * dh;
+        if (!FINE && i == A.is) curl += A.S * A.hz_src;  // total-field side
+        eyn = ((1.f - kap) * e + curl - A.c1 * jo) / (1.f + kap);
+        if (own) {
+          const float jn = A.a * jo + 2.f * kap * (e + eyn);
+          A.ey1[o] = eyn;
+          A.jy1[o] = jn;
+          if (FINE) sJy[cj - 1][ci - 1] = jn;
+        }
+      } else if (FINE) {
+        const int I = i >> 1;
+        int jc;
+        float w0, w1;
+        if ((j & 1) == 0) { jc = (j >> 1) - 1; w0 = 0.25f; w1 = 0.75f; }
+        else              { jc = j >> 1;       w0 = 0.75f; w1 = 0.25f; }
+        const size_t co = (size_t)jc * A.cpitch + I;
+        const float vo = w0 * A.cey0[co] + w1 * A.cey0[co + A.cpitch];
+        const float vn = w0 * A.cey1[co] + w1 * A.cey1[co + A.cpitch];
+        eyn = (1.f - A.frac) * vo + A.frac * vn;
+        if (own) {
+          const float jn = A.a * A.jy0[o] + 2.f * kap * (e + eyn);
+          A.ey1[o] = eyn;
+          A.jy1[o] = jn;
+          sJy[cj - 1][ci - 1] = jn;
+        }
+      }
+    }
+    sExn[cj][ci] = exn;
+    sEyn[cj][ci] = eyn;
+  }
+  __syncthreads();
+
+  // -- outer boundary of the base level: first-order Mur or PEC ---------------
+  if (!FINE && (i0 == 0 || i0 + kTX > R || j0 == 0 || j0 + TY > T)) {
+    for (int k = tid; k < NH * NW; k += kThreads) {
+      const int ci = k % NW, cj = k / NW;
+      const int i = i0 - 1 + ci, j = j0 - 1 + cj;
+      const bool own = ci >= 1 && cj >= 1;
+      const size_t o = (size_t)j * pitch + i;
+      if (ey_ok(i, j) && (i == L || i == R)) {
+        const float eo = sEyo[cj + 1][ci + 1];
+        float en = 0.f;
+        if (A.bc_x == kBcMur) {
+          const int d = (i == L) ? 1 : -1;  // interior neighbour
+          en = sEyo[cj + 1][ci + 1 + d] + A.cmur * (sEyn[cj][ci + d] - eo);
+        }
+        sEyn[cj][ci] = en;
+        if (own) {
+          const float ne = 0.5f * (sN[cj][ci] + sN[cj + 1][ci]);
+          const float kap = A.kn * ne;
+          A.ey1[o] = en;
+          A.jy1[o] = A.a * A.jy0[o] + 2.f * kap * (eo + en);
+        }
+      }
+      if (ex_ok(i, j) && (j == B || j == T)) {
+        const float eo = sExo[cj + 1][ci + 1];
+        float en = 0.f;
+        if (A.bc_y == kBcMur) {
+          const int d = (j == B) ? 1 : -1;
+          en = sExo[cj + 1 + d][ci + 1] + A.cmur * (sExn[cj + d][ci] - eo);
+        }
+        sExn[cj][ci] = en;
+        if (own) {
+          const float ne = 0.5f * (sN[cj][ci] + sN[cj][ci + 1]);
+          const float kap = A.kn * ne;
+          A.ex1[o] = en;
+          A.jx1[o] = A.a * A.jx0[o] + 2.f * kap * (eo + en);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // -- window accumulation at the tile's nodes ---------------------------------
+  const int tx = tid % kTX, ty = tid / kTX;
+  for (int r = ty; r < TY; r += kThreads / kTX) {
+    const int i = i0 + tx, j = j0 + r;
+    if (!nd_ok(i, j)) continue;
+    const int ci = tx + 1, cj = r + 1;
+    float sx = 0.f, sy = 0.f;
+    int cx = 0, cy = 0;
+    if (i > L) { const float v = sExn[cj][ci - 1]; sx += v * v; cx++; }
+    if (i < R) { const float v = sExn[cj][ci]; sx += v * v; cx++; }
+    if (j > B) { const float v = sEyn[cj - 1][ci]; sy += v * v; cy++; }
+    if (j < T) { const float v = sEyn[cj][ci]; sy += v * v; cy++; }
+    const float e2 = (cx == 2 ? 0.5f * sx : sx) + (cy == 2 ? 0.5f * sy : sy);
+    const size_t o = (size_t)j * pitch + i;
+    A.acc[o] += e2;
+  }
+
+  // -- fine -> coarse transfer after the last substep ------------------------
+  if (FINE && A.restrict_on) {
+    __syncthreads();
+    for (int r = ty; r < TY; r += kThreads / kTX) {
+      const int i = i0 + tx, j = j0 + r;
+      if (((i - L) | (j - B)) & 1) continue;
+      const int a = i >> 1, b = j >> 1;
+      const size_t co = (size_t)b * A.cpitch + a;
+      const int ci = tx + 1, cj = r + 1;   // new-E coordinates of (i, j)
+      if (hz_ok(i, j)) {
+        float s = 0.f;
+        for (int da = 0; da < 2; da++)
+          for (int db = 0; db < 2; db++) {
+            const float hold = A.hz0[(size_t)(j + db) * pitch + i + da];
+            s += 0.5f * (hold + sH[r + 2 + db][tx + 2 + da]);
+          }
+        A.chz[co] = 0.25f * s;
+      }
+      if (ex_ok(i, j) && j > B && j < T) {
+        A.cex[co] = 0.5f * (sExn[cj][ci] + sExn[cj][ci + 1]);
+        A.cjx[co] = sJx[r][tx] + sJx[r][tx + 1];  // J~ scales with dt
+      }
+      if (ey_ok(i, j) && i > L && i < R) {
+        A.cey[co] = 0.5f * (sEyn[cj][ci] + sEyn[cj + 1][ci]);
+        A.cjy[co] = sJy[r][tx] + sJy[r + 1][tx];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Window block close and continuity step (Eq. (4)), one thread per node of
+// the region [L..R] x [B..T].  ring[slot] <- acc / steps_per_period,
+// acc <- 0; with `update`, E_rms^2 = sum of the 8 ring slots,
+// nu = nu_m A [(E_eff^2/(100p)^2)^(beta/2) - (E_cr/p)^beta],
+// n+ = n + dt_n [dx^-2 sum_faces (D_i+D_nb)/2 (n_nb - n) + nu n]  (>= 0).
+// Fine level: interior nodes are updated; boundary nodes take the new coarse
+// density (copy / mean along the boundary line); the coarse nodes strictly
+// inside the patch take the new fine density (injection).
+// ---------------------------------------------------------------------------
+__device__ inline float d_eff(const ContArgs &A, float n) {
+  if (A.d_const_mode) return A.d_const;
+  const float al = n * A.inv_namb;
+  return (al * A.Da + A.De) / (1.f + al);
+}
+
+template <bool FINE>
+__global__ __launch_bounds__(kThreads) void k_cont(ContArgs A) {
+  const int i = A.L + blockIdx.x * kTX + (threadIdx.x % kTX);
+  const int j = A.B + blockIdx.y * (kThreads / kTX) + (threadIdx.x / kTX);
+  if (i > A.R || j > A.T) return;
+  const int pitch = A.pitch;
+  const size_t o = (size_t)j * pitch + i;
+  const float sv = A.acc[o] * A.inv_spp;
+  A.ring[(size_t)A.slot * A.plane + o] = sv;
+  A.acc[o] = 0.f;
+  if (!A.update) {
+    if (!isfinite(sv)) A.err[threadIdx.x & 63] = 1;
+    return;
+  }
+  float e2 = 0.f;
+  for (int s = 0; s < kRing; s++)
+    e2 += (s == A.slot) ? sv : A.ring[(size_t)s * A.plane + o];
+  float nn;
+  if (FINE && (i == A.L || i == A.R || j == A.B || j == A.T)) {
+    const int a = i >> 1, b = j >> 1, cp = A.cpitch;
+    if (((i | j) & 1) == 0) nn = A.cn1[(size_t)b * cp + a];
+    else if (i & 1) nn = 0.5f * (A.cn1[(size_t)b * cp + a] + A.cn1[(size_t)b * cp + a + 1]);
+    else nn = 0.5f * (A.cn1[(size_t)b * cp + a] + A.cn1[(size_t)(b + 1) * cp + a]);
+  } else {
+    const float ni = A.n0[o];
+    const float di = d_eff(A, ni);
+    float flux = 0.f;
+    if (i > A.L) { const float v = A.n0[o - 1]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
+    if (i < A.R) { const float v = A.n0[o + 1]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
+    if (j > A.B) { const float v = A.n0[o - pitch]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
+    if (j < A.T) { const float v = A.n0[o + pitch]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
+    const float nu = A.nuA * (powf(e2 * A.eeff_p2, A.half_beta) - A.att);
+    nn = ni + A.dtn * (flux * A.inv_dx2 + nu * ni);
+    nn = nn > 0.f ? nn : 0.f;
+    if (FINE && (((i - A.L) | (j - A.B)) & 1) == 0) {
+      const int a = i >> 1, b = j >> 1;  // strictly inside: interior even node
+      A.cn1[(size_t)b * A.cpitch + a] = nn;
+    }
+  }
+  A.n1[o] = nn;
+  if (!isfinite(nn) || !isfinite(e2)) A.err[threadIdx.x & 63] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Growth test, part 1: node flags (Sec. III.A threshold density, Sec. III.B
+// gradient length) OR-reduced over each block.  Node (i, j) belongs to block
+// (min(i/Bk, NBx-1), min(j/Bk, NBy-1)).  The decision is float32, without
+// contraction, on n * 2^-60 (exact scaling keeping n^2 in range):
+//   n > thr  or  (n > floor and gx*gx + gy*gy > g2 * (n*n)).
+// ---------------------------------------------------------------------------
+__device__ inline int node_flag(const FlagArgs &A, int i, int j) {
+#pragma clang fp contract(off)
+  const size_t o = (size_t)j * A.pitch + i;
+  const float nv = A.n[o];
+  if (nv > A.thr) return 1;
+  if (!(nv > A.flo)) return 0;
+  const float sc = 0x1p-60f;
+  const float ns = nv * sc;
+  float gx = 0.f, gy = 0.f;
+  if (i > 0 && i < A.NX) gx = (A.n[o + 1] * sc - A.n[o - 1] * sc) * 0.5f;
+  if (j > 0 && j < A.NY) gy = (A.n[o + A.pitch] * sc - A.n[o - A.pitch] * sc) * 0.5f;
+  const float gx2 = gx * gx;
+  const float gy2 = gy * gy;
+  const float lhs = gx2 + gy2;
+  const float n2 = ns * ns;
+  const float rhs = A.g2 * n2;
+  return lhs > rhs;
+}
+
+__global__ __launch_bounds__(256) void k_flag_blocks(FlagArgs A) {
+  const int bx = blockIdx.x, by = blockIdx.y;
+  const int ib = bx * A.Bk, jb = by * A.Bk;
+  const int w = (bx == A.NBx - 1) ? A.NX + 1 - ib : A.Bk;
+  const int h = (by == A.NBy - 1) ? A.NY + 1 - jb : A.Bk;
+  int f = 0;
+  for (int k = threadIdx.x; k < w * h; k += blockDim.x)
+    f |= node_flag(A, ib + k % w, jb + k / w);
+  f = __syncthreads_or(f);
+  if (threadIdx.x == 0) A.bflag[by * A.NBx + bx] = (uint8_t)(f ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// Growth test, part 2 (one block of 1024 threads): exclusive prefix sum of
+// the block flags with wavefront shuffles, compaction of flagged block ids,
+// bounding box, union with the current patch (growth only, Sec. III.D),
+// clip to the margins, new extents into desc.
+// desc: [0..3] current ext (blocks), [4..7] new ext (blocks), [8] count,
+//       [9] changed, [10..13] margins xmin, ymin, xmax, ymax (blocks).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_scan_bbox(ScanArgs A) {
+  constexpr int NW = 1024 / 64;
+  __shared__ int sTot[NW];
+  __shared__ int sMin[2][NW], sMax[2][NW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int carry = 0;
+  int mnx = 1 << 30, mny = 1 << 30, mxx = -1, mxy = -1;
+  for (int base = 0; base < A.NB; base += 1024) {
+    const int b = base + tid;
+    const int f = (b < A.NB) ? (int)A.bflag[b] : 0;
+    int x = f;  // inclusive scan within the wavefront
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d, 64);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) sTot[wv] = x;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < NW; k++) {
+      const int t = sTot[k];
+      if (k < wv) before += t;
+      total += t;
+    }
+    const int excl = carry + before + x - f;
+    if (b < A.NB) {
+      A.scan[b] = excl;
+      if (f) {
+        A.list[excl] = b;
+        const int bx = b % A.NBx, by = b / A.NBx;
+        mnx = min(mnx, bx); mny = min(mny, by);
+        mxx = max(mxx, bx); mxy = max(mxy, by);
+      }
+    }
+    carry += total;
+    __syncthreads();
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    mnx = min(mnx, __shfl_xor(mnx, d, 64));
+    mny = min(mny, __shfl_xor(mny, d, 64));
+    mxx = max(mxx, __shfl_xor(mxx, d, 64));
+    mxy = max(mxy, __shfl_xor(mxy, d, 64));
+  }
+  if (lane == 0) {
+    sMin[0][wv] = mnx; sMin[1][wv] = mny;
+    sMax[0][wv] = mxx; sMax[1][wv] = mxy;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    int a = (lane < NW) ? sMin[0][lane] : (1 << 30);
+    int c = (lane < NW) ? sMin[1][lane] : (1 << 30);
+    int e = (lane < NW) ? sMax[0][lane] : -1;
+    int g = (lane < NW) ? sMax[1][lane] : -1;
+    for (int d = 32; d >= 1; d >>= 1) {
+      a = min(a, __shfl_xor(a, d, 64));
+      c = min(c, __shfl_xor(c, d, 64));
+      e = max(e, __shfl_xor(e, d, 64));
+      g = max(g, __shfl_xor(g, d, 64));
+    }
+    if (lane == 0) {
+      int* D = A.desc;
+      int x0 = a, y0 = c, x1 = e + 1, y1 = g + 1;
+      if (carry == 0) { x0 = A.NBx; y0 = A.NBy; x1 = 0; y1 = 0; }
+      if (D[2] > D[0]) {  // the patch only grows
+        x0 = min(x0, D[0]); y0 = min(y0, D[1]);
+        x1 = max(x1, D[2]); y1 = max(y1, D[3]);
+      }
+      x0 = max(x0, D[10]); y0 = max(y0, D[11]);
+      x1 = min(x1, D[12]); y1 = min(y1, D[13]);
+      if (x0 >= x1 || y0 >= y1) { x0 = y0 = x1 = y1 = 0; }
+      D[4] = x0; D[5] = y0; D[6] = x1; D[7] = y1;
+      D[8] = carry;
+      D[9] = (x0 != D[0] || y0 != D[1] || x1 != D[2] || y1 != D[3]) ? 1 : 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Prolongation into the new part of the patch (Sec. III.D, Eq. (5a) area
+// weights), one thread per fine node position of the new extents.  Entities
+// that existed in the old patch keep their data.  E, J, n, window at the
+// current coarse time; Hz at frac = 5/4 between coarse Hz^{n-1/2} and
+// Hz^{n+1/2} (fine Hz lives at coarse n+3/4).  Positions are in quarter
+// coarse units: fine index P -> 2P (on a coarse line) or 2P - 1 (a quarter
+// below the next coarse half-point).
+// ---------------------------------------------------------------------------
+__device__ inline float bilin4(const float* a, int pitch, int U4, int V4) {
+  const int i = U4 >> 2, j = V4 >> 2;
+  const float fu = (U4 & 3) * 0.25f, fv = (V4 & 3) * 0.25f;
+  float v = 0.f;
+  for (int di = 0; di < 2; di++) {
+    const float wu = di ? fu : 1.f - fu;
+    if (wu == 0.f) continue;
+    for (int dj = 0; dj < 2; dj++) {
+      const float wv = dj ? fv : 1.f - fv;
+      if (wv == 0.f) continue;
+      v += wu * wv * a[(size_t)(j + dj) * pitch + i + di];
+    }
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_prolong(ProlongArgs A) {
+  const int i = A.L + blockIdx.x * kTX + (threadIdx.x % kTX);
+  const int j = A.B + blockIdx.y * (kThreads / kTX) + (threadIdx.x / kTX);
+  if (i > A.R || j > A.T) return;
+  const size_t o = (size_t)j * A.pitch + i;
+  const int cp = A.cpitch;
+  const bool old = A.oR > A.oL;
+  auto in_old = [&](int hx, int hy) {  // hx/hy: entity ends one short
+    return old && i >= A.oL && i <= A.oR - hx && j >= A.oB && j <= A.oT - hy;
+  };
+  if (i < A.R && j < A.T && !in_old(1, 1)) {
+    const float hp = bilin4(A.chz_prev, cp, 2 * i - 1, 2 * j - 1);
+    const float hn = bilin4(A.chz, cp, 2 * i - 1, 2 * j - 1);
+    A.hz[o] = (1.f - 1.25f) * hp + 1.25f * hn;
+  }
+  if (i < A.R && !in_old(1, 0)) {
+    A.ex[o] = bilin4(A.cex, cp, 2 * i - 1, 2 * j);
+    A.jx[o] = 0.5f * bilin4(A.cjx, cp, 2 * i - 1, 2 * j);  // J~ scales with dt
+  }
+  if (j < A.T && !in_old(0, 1)) {
+    A.ey[o] = bilin4(A.cey, cp, 2 * i, 2 * j - 1);
+    A.jy[o] = 0.5f * bilin4(A.cjy, cp, 2 * i, 2 * j - 1);
+  }
+  if (!in_old(0, 0)) {
+    if (!A.keep_n) A.n[o] = bilin4(A.cn, cp, 2 * i, 2 * j);
+    A.acc[o] = bilin4(A.cacc, cp, 2 * i, 2 * j);
+    for (int s = 0; s < kRing; s++)
+      A.ring[(size_t)s * A.plane + o] = bilin4(A.cring + (size_t)s * A.cplane, cp, 2 * i, 2 * j);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pitched <-> dense copy with a scale factor (field read-out / write-in).
+// ---------------------------------------------------------------------------
+__global__ void k_gather(const float* src, int pitch, int i0, int j0, int cols,
+                         int rows, float scale, float* dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= cols || j >= rows) return;
+  dst[(size_t)j * cols + i] = scale * src[(size_t)(j + j0) * pitch + i0 + i];
+}
+
+__global__ void k_scatter(const float* src, int cols, int rows, float scale,
+                          float* dst, int pitch, int i0, int j0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= cols || j >= rows) return;
+  dst[(size_t)(j + j0) * pitch + i0 + i] = scale * src[(size_t)j * cols + i];
+}
+
+// sum of the 8 ring planes (E_rms^2 read-out)
+__global__ void k_ring_sum(const float* ring, size_t plane, int pitch, int i0,
+                           int j0, int cols, int rows, float* dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= cols || j >= rows) return;
+  const size_t o = (size_t)(j + j0) * pitch + i0 + i;
+  float s = 0.f;
+  for (int k = 0; k < kRing; k++) s += ring[(size_t)k * plane + o];
+  dst[(size_t)j * cols + i] = s;
+}
+
+// ---- host-side launchers ----------------------------------------------------
+template <bool FINE>
+static hipError_t launch_em_t(const EMArgs& A, int ty, hipStream_t st) {
+  const int nx = A.R - A.L + 1, ny = A.T - A.B + 1;
+  dim3 blk(kThreads);
+  switch (ty) {
+  case 4: {
+    dim3 g((nx + kTX - 1) / kTX, (ny + 3) / 4);
+    hipLaunchKernelGGL((k_em<FINE, 4>), g, blk, 0, st, A);
+    break;
+  }
+  case 8: {
+    dim3 g((nx + kTX - 1) / kTX, (ny + 7) / 8);
+    hipLaunchKernelGGL((k_em<FINE, 8>), g, blk, 0, st, A);
+    break;
+  }
+  default: {
+    dim3 g((nx + kTX - 1) / kTX, (ny + 15) / 16);
+    hipLaunchKernelGGL((k_em<FINE, 16>), g, blk, 0, st, A);
+    break;
+  }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_em(const EMArgs& A, bool fine, int ty, hipStream_t st) {
+  return fine ? launch_em_t<true>(A, ty, st) : launch_em_t<false>(A, ty, st);
+}
+
+hipError_t launch_cont(const ContArgs& A, bool fine, hipStream_t st) {
+  const int nx = A.R - A.L + 1, ny = A.T - A.B + 1;
+  dim3 g((nx + kTX - 1) / kTX, (ny + kThreads / kTX - 1) / (kThreads / kTX));
+  if (fine) hipLaunchKernelGGL(k_cont<true>, g, dim3(kThreads), 0, st, A);
+  else hipLaunchKernelGGL(k_cont<false>, g, dim3(kThreads), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_regrid_test(const FlagArgs& F, const ScanArgs& S, hipStream_t st) {
+  hipLaunchKernelGGL(k_flag_blocks, dim3(F.NBx, F.NBy), dim3(256), 0, st, F);
+  hipLaunchKernelGGL(k_scan_bbox, dim3(1), dim3(1024), 0, st, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(const ProlongArgs& A, hipStream_t st) {
+  const int nx = A.R - A.L + 1, ny = A.T - A.B + 1;
+  dim3 g((nx + kTX - 1) / kTX, (ny + kThreads / kTX - 1) / (kThreads / kTX));
+  hipLaunchKernelGGL(k_prolong, g, dim3(kThreads), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const float* src, int pitch, int i0, int j0, int cols,
+                         int rows, float scale, float* dst, hipStream_t st) {
+  dim3 g((cols + 255) / 256, rows);
+  hipLaunchKernelGGL(k_gather, g, dim3(256), 0, st, src, pitch, i0, j0, cols,
+                     rows, scale, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const float* src, int cols, int rows, float scale,
+                          float* dst, int pitch, int i0, int j0, hipStream_t st) {
+  dim3 g((cols + 255) / 256, rows);
+  hipLaunchKernelGGL(k_scatter, g, dim3(256), 0, st, src, cols, rows, scale,
+                     dst, pitch, i0, j0);
+  return hipGetLastError();
+}
+
+hipError_t launch_ring_sum(const float* ring, size_t plane, int pitch, int i0,
+                           int j0, int cols, int rows, float* dst,
+                           hipStream_t st) {
+  dim3 g((cols + 255) / 256, rows);
+  hipLaunchKernelGGL(k_ring_sum, g, dim3(256), 0, st, ring, plane, pitch, i0,
+                     j0, cols, rows, dst);
+  return hipGetLastError();
+}
+
+}  // namespace dmr

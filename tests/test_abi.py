@@ -1,0 +1,78 @@
+"""The C-ABI library loads, exports every entry point include/dmr.h declares,
+and its host-side parameter checks behave (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2105_13276_amd import binding as B
+from paper_2105_13276_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dmr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmr_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 15
+    lib = C.CDLL(B.LIB)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(B.SYMBOLS) == names
+
+
+def test_params_struct_layout():
+    # the binding's struct must match the C struct: a wrong size is refused
+    cfg = W.config0()
+    p = B.make_params(cfg)
+    n = C.c_size_t()
+    assert B.lib().dmr_workspace_bytes(C.byref(p), C.byref(n)) == 0
+    assert n.value > 0
+    p.struct_size += 8
+    assert B.lib().dmr_workspace_bytes(C.byref(p), C.byref(n)) == -1
+
+
+@pytest.mark.parametrize("over", [
+    dict(courant=0.75),                 # beyond the 2-D Yee limit 1/sqrt(2)
+    dict(courant=0.3),                  # N/S not a multiple of 8
+    dict(nx=2),
+    dict(tfsf_i=10_000),
+    dict(bc_x="periodic"),
+])
+def test_invalid_params_rejected(over):
+    cfg = dict(W.config0())
+    cfg.update(over)
+    if cfg["bc_x"] not in B.BC:
+        cfg["bc_x"] = "mur"
+        p = B.make_params(cfg)
+        p.bc_x = 2
+    else:
+        p = B.make_params(cfg)
+    n = C.c_size_t()
+    assert B.lib().dmr_workspace_bytes(C.byref(p), C.byref(n)) == -1
+
+
+@pytest.mark.parametrize("over", [
+    dict(block=12),                     # does not divide 512
+    dict(r=3),
+    dict(regrid_every=100),             # not a multiple of 8 steps
+])
+def test_invalid_refinement_rejected(over):
+    cfg = dict(W.config1_dmr())
+    cfg.update(over)
+    with pytest.raises(B.DmrError):
+        B.workspace_bytes(cfg)
+
+
+def test_workspace_covers_full_domain_patch():
+    cfg = W.config1_dmr()
+    nb = B.workspace_bytes(cfg)
+    # 21 planes per level, fine level r^2 larger: > 21*4*(1+4)*nodes bytes
+    nodes = (cfg["nx"] + 1) * (cfg["ny"] + 1)
+    assert nb >= 21 * 4 * 5 * nodes

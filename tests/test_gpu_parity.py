@@ -1,0 +1,104 @@
+"""GPU (float32, HIP) against the FP64 oracle on the same seeded inputs.
+
+Tolerance (stated in the benchmark spec): relative L2 <= 1e-4 per
+field group (E = (Ex, Ey), Hz, J = (Jx, Jy), E_rms^2) per level, <= 1e-3 on
+log(max(n, 1e-12 n_c)); integer regrid results (block flags, prefix sum,
+compacted list, patch extents) equal.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2105_13276_amd import workloads as W
+
+from gpu_helpers import assert_parity, both
+
+pytestmark = pytest.mark.gpu
+
+LAM = 299792458.0 / 110e9
+
+
+def _nc(cfg):
+    return O.derived(cfg)["n_c"]
+
+
+def test_uniform_config0():
+    """Plain method: 256x128 at lambda/64, 40 periods (5120 steps)."""
+    cfg = W.config0()
+    sb, _ = W.seeds(cfg)
+    g, o = both(cfg, sb)
+    g.step(cfg["steps"])
+    o.step(cfg["steps"])
+    g.sync()
+    assert g.time()[1] == o.time()[1] == cfg["steps"]
+    assert_parity(g, o, _nc(cfg), levels=(0,), tag="config0")
+
+
+@pytest.mark.parametrize("nx,ny,bc", [(200, 72, "mur"), (130, 66, "pec")])
+def test_uniform_ragged(nx, ny, bc):
+    """Grids that are not multiples of the 64 x TY tile: ragged tails on both
+    axes; PEC walls; a stronger field so density and current evolve."""
+    cfg = W.make(nx, ny, 32, "uniform", 12, bc_x=bc, bc_y=bc, erms_over_ebd=2.0)
+    dx = LAM / 32
+    sb = W.gaussian_seed(nx, ny, dx, [(0.6 * nx * dx, 0.45 * ny * dx)], [3e18], LAM / 20)
+    g, o = both(cfg, sb)
+    g.step(cfg["steps"])
+    o.step(cfg["steps"])
+    assert_parity(g, o, _nc(cfg), levels=(0,), tag="ragged %dx%d %s" % (nx, ny, bc))
+
+
+def test_static_patch():
+    cfg = W.make(128, 64, 32, "static", 20, static_ext=(48, 16, 96, 48),
+                 erms_over_ebd=2.0)
+    sb, sf = W.seeds(cfg)
+    g, o = both(cfg, sb, sf)
+    g.step(cfg["steps"])
+    o.step(cfg["steps"])
+    assert g.patch() == o.patch() == (48, 16, 96, 48)
+    assert_parity(g, o, _nc(cfg), tag="static")
+
+
+def test_dynamic_growth():
+    """The patch grows from 1x1 to 2x1 blocks during the run (seed half a cell
+    off a block edge, strong field)."""
+    dxc = LAM / 32
+    cfg = W.make(96, 48, 32, "dynamic", 60, erms_over_ebd=2.5)
+    sb, sf = W.seeds(cfg, [(59.5 * dxc, 24 * dxc)], [1e17])
+    g, o = both(cfg, sb, sf)
+    p0 = g.patch()
+    assert p0 == o.patch()
+    g.step(cfg["steps"])
+    o.step(cfg["steps"])
+    assert g.patch() == o.patch() != p0
+    fg, sg, lg, cg = g.regrid_info()
+    fo, so, lo, co = o.regrid_info()
+    assert (fg == fo).all() and (sg == so).all() and cg == co and (lg == lo).all()
+    assert_parity(g, o, _nc(cfg), tag="growth")
+
+
+def test_config1_dmr_full():
+    """Config 1 as benchmarked: coarse 512x256 at lambda/32, r = 2 patch,
+    regrid every 4 periods, 200 periods (12800 coarse steps)."""
+    cfg = W.config1_dmr()
+    sb, sf = W.seeds(cfg)
+    g, o = both(cfg, sb, sf)
+    assert g.patch() == o.patch() == (240, 112, 272, 144)
+    g.step(cfg["steps"])
+    o.step(cfg["steps"])
+    g.sync()
+    assert g.patch() == o.patch()
+    fg, sg, lg, cg = g.regrid_info()
+    fo, so, lo, co = o.regrid_info()
+    assert (fg == fo).all() and (sg == so).all() and cg == co and (lg == lo).all()
+    assert_parity(g, o, _nc(cfg), tag="config1")
+
+
+def test_config1_uniform_fine_prefix():
+    """The uniform-fine 1024x512 run of config 1 at full size (the launch
+    shape the benchmark times) over its first 16 periods."""
+    cfg = W.config1_uniform(periods=16)
+    sb, _ = W.seeds(cfg)
+    g, o = both(cfg, sb)
+    g.step(cfg["steps"])
+    o.step(cfg["steps"])
+    assert_parity(g, o, _nc(cfg), levels=(0,), tag="config1-uniform")
