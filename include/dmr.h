@@ -95,6 +95,11 @@ typedef struct dmr_params {
   double grad_thr;           /* flag where |grad n| dx / n > grad_thr */
   double n_floor_over_nc;    /* gradient test only above this density */
   double courant;            /* S = c dt/dx, same on both levels, <= 1/sqrt 2 */
+  double fine_filter;        /* gamma of the weak 4th-order hyper-diffusion of
+                                the patch's interior E, applied before each
+                                fine substep (1e-4 suppresses the slow growth
+                                of sub-coarse modes at the interface; 0: off;
+                                at most 1/64) */
 } dmr_params;
 
 typedef struct dmr_sim dmr_sim;

@@ -61,6 +61,7 @@ typedef struct orc_params {
   /* refinement criteria */
   double n_thr_over_nc, grad_thr, n_floor_over_nc;
   double courant;          /* S = c dt / dx on every level */
+  double fine_filter;      /* gamma of the fine-patch E hyper-diffusion */
   int32_t nx, ny;          /* base-level cells */
   int32_t cells_per_lambda;/* base-level N_lambda */
   int32_t r;               /* refinement factor (2) */

@@ -34,7 +34,7 @@ class OrcParams(C.Structure):
         ("mu_i_760", C.c_double), ("L_amb", C.c_double),
         ("d_const", C.c_double), ("n_thr_over_nc", C.c_double),
         ("grad_thr", C.c_double), ("n_floor_over_nc", C.c_double),
-        ("courant", C.c_double),
+        ("courant", C.c_double), ("fine_filter", C.c_double),
         ("nx", C.c_int32), ("ny", C.c_int32), ("cells_per_lambda", C.c_int32),
         ("r", C.c_int32), ("block", C.c_int32), ("regrid_every", C.c_int32),
         ("tfsf_i", C.c_int32), ("ramp_periods", C.c_int32),

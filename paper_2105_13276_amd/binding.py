@@ -43,7 +43,7 @@ class DmrParams(C.Structure):
         ("mu_i_760", C.c_double), ("L_amb", C.c_double),
         ("d_const", C.c_double), ("n_thr_over_nc", C.c_double),
         ("grad_thr", C.c_double), ("n_floor_over_nc", C.c_double),
-        ("courant", C.c_double),
+        ("courant", C.c_double), ("fine_filter", C.c_double),
     ]
 
 

@@ -92,6 +92,8 @@ int check_params(const dmr_params* p, std::string* why) {
   if (std::fabs(sppd - spp) > 1e-9 || spp % kRing)
     return bad("cells_per_lambda/courant must be an integer multiple of 8");
   if (!(p->freq_hz > 0) || !(p->p_torr > 0)) return bad("freq_hz, p_torr > 0");
+  if (!(p->fine_filter >= 0.0) || p->fine_filter > 1.0 / 64.0)
+    return bad("fine_filter must be in [0, 1/64]");
   if (p->bc_x < 0 || p->bc_x > 1 || p->bc_y < 0 || p->bc_y > 1)
     return bad("bc must be DMR_BC_MUR or DMR_BC_PEC");
   if (p->mode < 0 || p->mode > 2) return bad("bad mode");
@@ -376,6 +378,7 @@ int base_step(dmr_sim* s) {
       G.cex1 = C.ex[1 - c]; G.cey1 = C.ey[1 - c];
       G.cpitch = C.pitch;
       G.frac = (float)m / (float)r;
+      G.gamma = (float)p.fine_filter;
       if (m == r) {
         G.restrict_on = 1;
         G.chz = C.hz[1 - c]; G.cex = C.ex[1 - c]; G.cey = C.ey[1 - c];

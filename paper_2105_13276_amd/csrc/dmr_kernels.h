@@ -31,6 +31,7 @@ struct EMArgs {
   const float *cex0, *cey0, *cex1, *cey1;
   int cpitch;
   float frac;
+  float gamma;  // fine-patch E hyper-diffusion coefficient (<= 0: off)
   // fine level, last substep: coarse targets of the fine -> coarse transfer
   int restrict_on;
   float *chz, *cex, *cey, *cjx, *cjy;

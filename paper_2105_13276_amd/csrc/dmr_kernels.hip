@@ -46,6 +46,12 @@ __global__ __launch_bounds__(kThreads) void k_em(EMArgs A) {
   __shared__ float sN[DH][DW];
   __shared__ float sJx[FINE ? TY : 1][FINE ? kTX : 1];
   __shared__ float sJy[FINE ? TY : 1][FINE ? kTX : 1];
+  // fine level: raw old E over [i0-4, i0+TX+2] x [j0-4, j0+TY+2] and its
+  // Laplacian over [i0-3, i0+TX+1] x [j0-3, j0+TY+1] for the filter
+  constexpr int RW = FINE ? kTX + 7 : 1, RH = FINE ? TY + 7 : 1;
+  constexpr int QW = FINE ? kTX + 5 : 1, QH = FINE ? TY + 5 : 1;
+  __shared__ float rEx[RH][RW], rEy[RH][RW];
+  __shared__ float qEx[QH][QW], qEy[QH][QW];
 
   const int i0 = A.L + blockIdx.x * kTX;
   const int j0 = A.B + blockIdx.y * TY;
@@ -58,14 +64,80 @@ __global__ __launch_bounds__(kThreads) void k_em(EMArgs A) {
   auto nd_ok = [&](int i, int j) { return i >= L && i <= R && j >= B && j <= T; };
 
   // -- stage old E and density ----------------------------------------------
-  for (int k = tid; k < EH * EW; k += kThreads) {
-    const int ci = k % EW, cj = k / EW;
-    const int i = i0 - 2 + ci, j = j0 - 2 + cj;
-    float ex = 0.f, ey = 0.f;
-    if (ex_ok(i, j)) ex = A.ex0[(size_t)j * pitch + i];
-    if (ey_ok(i, j)) ey = A.ey0[(size_t)j * pitch + i];
-    sExo[cj][ci] = ex;
-    sEyo[cj][ci] = ey;
+  if (!FINE || A.gamma <= 0.f) {
+    for (int k = tid; k < EH * EW; k += kThreads) {
+      const int ci = k % EW, cj = k / EW;
+      const int i = i0 - 2 + ci, j = j0 - 2 + cj;
+      float ex = 0.f, ey = 0.f;
+      if (ex_ok(i, j)) ex = A.ex0[(size_t)j * pitch + i];
+      if (ey_ok(i, j)) ey = A.ey0[(size_t)j * pitch + i];
+      sExo[cj][ci] = ex;
+      sEyo[cj][ci] = ey;
+    }
+  } else {
+    // Fine patch: weak fourth-order hyper-diffusion of the interior E before
+    // the substep, E <- E - gamma L(L(E)) per component on its own grid,
+    // neighbours outside the patch replaced by the centre value; the
+    // coarse-driven boundary edges are left as they are.
+    for (int k = tid; k < RH * RW; k += kThreads) {
+      const int ci = k % RW, cj = k / RW;
+      const int i = i0 - 4 + ci, j = j0 - 4 + cj;
+      float ex = 0.f, ey = 0.f;
+      if (ex_ok(i, j)) ex = A.ex0[(size_t)j * pitch + i];
+      if (ey_ok(i, j)) ey = A.ey0[(size_t)j * pitch + i];
+      rEx[cj][ci] = ex;
+      rEy[cj][ci] = ey;
+    }
+    __syncthreads();
+    for (int k = tid; k < QH * QW; k += kThreads) {
+      const int ci = k % QW, cj = k / QW;
+      const int i = i0 - 3 + ci, j = j0 - 3 + cj;
+      const int a = ci + 1, b = cj + 1;  // raw coordinates
+      float lx = 0.f, ly = 0.f;
+      if (ex_ok(i, j)) {
+        const float c = rEx[b][a];
+        lx = (ex_ok(i - 1, j) ? rEx[b][a - 1] : c) + (ex_ok(i + 1, j) ? rEx[b][a + 1] : c) +
+             (ex_ok(i, j - 1) ? rEx[b - 1][a] : c) + (ex_ok(i, j + 1) ? rEx[b + 1][a] : c) -
+             4.f * c;
+      }
+      if (ey_ok(i, j)) {
+        const float c = rEy[b][a];
+        ly = (ey_ok(i - 1, j) ? rEy[b][a - 1] : c) + (ey_ok(i + 1, j) ? rEy[b][a + 1] : c) +
+             (ey_ok(i, j - 1) ? rEy[b - 1][a] : c) + (ey_ok(i, j + 1) ? rEy[b + 1][a] : c) -
+             4.f * c;
+      }
+      qEx[cj][ci] = lx;
+      qEy[cj][ci] = ly;
+    }
+    __syncthreads();
+    for (int k = tid; k < EH * EW; k += kThreads) {
+      const int ci = k % EW, cj = k / EW;
+      const int i = i0 - 2 + ci, j = j0 - 2 + cj;
+      const int a = ci + 1, b = cj + 1;  // Laplacian coordinates
+      float ex = 0.f, ey = 0.f;
+      if (ex_ok(i, j)) {
+        ex = rEx[cj + 2][ci + 2];
+        if (j != B && j != T) {
+          const float c = qEx[b][a];
+          const float l2 = (ex_ok(i - 1, j) ? qEx[b][a - 1] : c) + (ex_ok(i + 1, j) ? qEx[b][a + 1] : c) +
+                           (ex_ok(i, j - 1) ? qEx[b - 1][a] : c) + (ex_ok(i, j + 1) ? qEx[b + 1][a] : c) -
+                           4.f * c;
+          ex -= A.gamma * l2;
+        }
+      }
+      if (ey_ok(i, j)) {
+        ey = rEy[cj + 2][ci + 2];
+        if (i != L && i != R) {
+          const float c = qEy[b][a];
+          const float l2 = (ey_ok(i - 1, j) ? qEy[b][a - 1] : c) + (ey_ok(i + 1, j) ? qEy[b][a + 1] : c) +
+                           (ey_ok(i, j - 1) ? qEy[b - 1][a] : c) + (ey_ok(i, j + 1) ? qEy[b + 1][a] : c) -
+                           4.f * c;
+          ey -= A.gamma * l2;
+        }
+      }
+      sExo[cj][ci] = ex;
+      sEyo[cj][ci] = ey;
+    }
   }
   for (int k = tid; k < DH * DW; k += kThreads) {
     const int ci = k % DW, cj = k / DW;

@@ -83,3 +83,40 @@ def test_dmr_matches_uniform_fine_with_growth(oracle_mod):
     # the coarse mesh carries the fine solution back (injection at sync)
     nc = d.get("n", 0)[p1[1] + 1:p1[3], p1[0] + 1:p1[2]]
     assert np.array_equal(nc, nf[2:-1:2, 2:-1:2])
+
+
+def _perturbation_growth(oracle_mod, gamma, periods=120):
+    """Norm of the difference between a run and the same run perturbed at
+    1e-7 after 10 periods, every 20 periods: a stable interface keeps it
+    bounded, a weakly unstable one lets it grow."""
+    cfg = W.make(128, 64, 32, "static", 1, static_ext=(48, 16, 80, 48),
+                 continuity_on=False, fine_filter=gamma)
+    z = np.zeros((65, 129))
+    a, b = oracle_mod.Sim(cfg, z), oracle_mod.Sim(cfg, z)
+    spp = cfg["steps_per_period"]
+    a.step(10 * spp)
+    b.step(10 * spp)
+    rng = np.random.default_rng(0)
+    for lv in (0, 1):
+        for f in ("hz", "ex", "ey"):
+            v = b.get(f, lv)
+            sc = 1e6 / 376.73 if f == "hz" else 1e6
+            b.set(f, lv, v + 1e-7 * sc * rng.standard_normal(v.shape))
+    norms = []
+    for _ in range(periods // 20):
+        a.step(20 * spp)
+        b.step(20 * spp)
+        norms.append(np.sqrt(sum((((b.get(f, 1) - a.get(f, 1)) * (376.73 if f == "hz" else 1.0)) ** 2).sum()
+                                 for f in ("hz", "ex", "ey"))))
+    return np.array(norms)
+
+
+def test_interface_stable_with_fine_filter(oracle_mod):
+    n = _perturbation_growth(oracle_mod, 1e-4)
+    assert n[-1] < 1.2 * n[0]
+
+
+def test_interface_grows_without_fine_filter(oracle_mod):
+    # the reason for the filter: sub-coarse modes trapped in the patch grow
+    n = _perturbation_growth(oracle_mod, 0.0)
+    assert n[-1] > 5.0 * n[0]
