@@ -62,6 +62,9 @@ def lib():
             raise ImportError(
                 "libdmr.so is not built; run `python -m paper_2105_13276_amd.build` "
                 "(or __graft_entry__.build()) first")
+        # torch ships its own HIP runtime (same soname); load it first so that
+        # libdmr.so binds to the runtime that owns the workspace and stream
+        import torch  # noqa: F401
         L = C.CDLL(LIB)
         P, V = C.POINTER, C.c_void_p
         L.dmr_workspace_bytes.argtypes = [P(DmrParams), P(C.c_size_t)]
