@@ -40,7 +40,30 @@ def parse():
                     help="skip the 4096x2048 bandwidth-bound kernel measurement")
     ap.add_argument("--cpu-steps", type=int, default=1024,
                     help="coarse steps of the oracle sample")
+    ap.add_argument("--only-large", action="store_true",
+                    help="profiling aid: run only 4096x2048 base steps and a "
+                         "256 MiB device copy (counter calibration), no JSON")
     return ap.parse_args()
+
+
+def only_large(steps=48):
+    """Profiling aid: base-level EM steps on the 4096x2048 coarse grid and one
+    device-to-device copy of 256 MiB whose byte counts calibrate the HBM
+    counters (FETCH_SIZE / WRITE_SIZE) of the same run."""
+    import torch
+    from paper_2105_13276_amd import binding as B
+    from paper_2105_13276_amd import workloads as W
+    cfg = W.config_large(periods=1)
+    sim = B.Sim(cfg, W.seeds(cfg, fine=False)[0], None)
+    sim.step(steps)
+    sim.sync()
+    a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print("only-large: %d steps of %dx%d, copy of %d MiB" % (steps, cfg["nx"], cfg["ny"], a.numel() * 4 >> 20), flush=True)
 
 
 def em_bytes_per_cell():
@@ -85,6 +108,9 @@ def main():
         print("bench.py: this build runs on one GPU only (no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.only_large:
+        only_large()
+        return
     import numpy as np
     import torch
     from paper_2105_13276_amd import binding as B
