@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -134,7 +135,7 @@ struct dmr_sim {
   int ext[4] = {0, 0, 0, 0};  // base cells
   int64_t step = 0, blocks = 0;
   int ccur = 0, ncur = 0;
-  int ty0 = 16, ty1 = 16;
+  int seg0 = 16, ty1 = 16;
   uint8_t* d_flag = nullptr;
   int32_t *d_scan = nullptr, *d_list = nullptr;
   int* d_desc = nullptr;
@@ -265,6 +266,19 @@ void ev_end(dmr_sim* s) {
   if (s->ev_used >= 4096) harvest(s);
 }
 
+// rows per segment of the streaming base kernel: long segments for
+// bandwidth, short ones when the grid is too small to fill the chip
+int stream_rows(int NX, int NY) {
+  if (const char* e = getenv("DMR_SEG")) {
+    const int v = atoi(e);
+    if (v >= 2) return v;
+  }
+  const long waves_x = (NX + 1 + 61) / 62;
+  int seg = 64;
+  while (seg > 8 && waves_x * ((NY + seg) / seg) < 4096) seg >>= 1;
+  return seg;
+}
+
 int tile_rows(int NX, int NY) {
   // enough tiles to cover the 256 compute units several times over
   const long tiles16 = (long)((NX + kTX) / kTX) * ((NY + 16) / 16);
@@ -363,7 +377,7 @@ int base_step(dmr_sim* s) {
     A.hz_src = (float)ey_inc(s, xs - 0.5 * C.dx, t + 0.5 * C.dt);
   }
   ev_begin(s, 0);
-  hipError_t e = launch_em(A, false, s->ty0, s->st);
+  hipError_t e = launch_em_stream(A, s->seg0, s->st);
   ev_end(s);
   if (e != hipSuccess) return hipfail(s, e, "base EM launch");
   if (s->has_patch) {  // two fine substeps (Sec. III.C)
@@ -538,7 +552,7 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   s->d_desc = (int*)(s->ws + lay.off_desc);
   s->d_err = (int*)(s->ws + lay.off_err);
   s->stage = (float*)(s->ws + lay.off_stage);
-  s->ty0 = tile_rows(p->nx, p->ny);
+  s->seg0 = stream_rows(p->nx, p->ny);
   hipError_t e = hipMemsetAsync(s->ws, 0, lay.total, s->st);
   if (e != hipSuccess) { rc = hipfail(s, e, "workspace clear"); delete s; return rc; }
   // seeds: float32 on the pitched node grid

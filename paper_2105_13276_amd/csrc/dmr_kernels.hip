@@ -601,6 +601,165 @@ __global__ void k_ring_sum(const float* ring, size_t plane, int pitch, int i0,
   dst[(size_t)j * cols + i] = s;
 }
 
+// ---------------------------------------------------------------------------
+// Base-level EM step, column-streaming form (Eqs. (1)-(3), Mur/PEC, TF/SF).
+// One lane per node column: lanes 0-1 of each wavefront recompute the two
+// columns left of the wave's 62 own columns, so x neighbours come from
+// wavefront shuffles; the wave marches up a segment of rows keeping the
+// previous row's new Hz / Ey / Ex in registers and the next two rows' loads
+// in flight, so every plane is read once per row (a 1-row halo per segment,
+// 2 of 64 columns per wave).  Own entities: Hz(i,j), Ex(i,j), Ey(i,j),
+// node (i,j) for the own columns and the segment's rows.
+// ---------------------------------------------------------------------------
+struct RowData {
+  float ex, ey, ey1, hz, jx, jy, n, n1, acc;
+};
+
+__device__ inline RowData load_row(const EMArgs& A, int i, int j, bool own) {
+  RowData r;
+  const int NX = A.R, NY = A.T;
+  const size_t o = (size_t)j * A.pitch + i;
+  const bool row_ok = j >= 0 && j <= NY;
+  const bool exv = row_ok && i >= 0 && i < NX;
+  const bool eyv = row_ok && j < NY && i >= 0 && i <= NX;
+  const bool ey1v = row_ok && j < NY && i + 1 >= 0 && i + 1 <= NX;
+  const bool ndv = row_ok && i >= 0 && i <= NX;
+  const bool nd1v = row_ok && i + 1 >= 0 && i + 1 <= NX;
+  r.ex = exv ? A.ex0[o] : 0.f;
+  r.jx = exv ? A.jx0[o] : 0.f;
+  r.ey = eyv ? A.ey0[o] : 0.f;
+  r.jy = eyv ? A.jy0[o] : 0.f;
+  r.ey1 = ey1v ? A.ey0[o + 1] : 0.f;
+  r.hz = (eyv && i < NX) ? A.hz0[o] : 0.f;
+  r.n = ndv ? A.n[o] : 0.f;
+  r.n1 = nd1v ? A.n[o + 1] : 0.f;
+  r.acc = (ndv && own) ? A.acc[o] : 0.f;
+  return r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int nseg) {
+  const int NX = A.R, NY = A.T;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c0 = (blockIdx.x * (kThreads / 64) + wv) * 62;
+  const int i = c0 - 2 + lane;
+  const bool own = lane >= 2 && i <= NX;
+  const int k = blockIdx.y;
+  const int j0 = k * seg;
+  const int j1 = (k == nseg - 1) ? NY + 1 : j0 + seg;
+  const bool wave_has_left = c0 - 2 <= 0 && 0 <= c0 + 61;   // column 0 in the wave
+  const bool wave_has_right = c0 - 2 <= NX && NX <= c0 + 61;
+  const bool exv = i >= 0 && i < NX;
+  const bool eyc = i >= 0 && i <= NX;
+  const float S = A.S, c1 = A.c1, a = A.a, kn = A.kn, cm = A.cmur;
+  const bool mur_x = A.bc_x == kBcMur, mur_y = A.bc_y == kBcMur;
+
+  const int js = j0 > 0 ? j0 - 1 : 0;
+  RowData cur = load_row(A, i, js, own);
+  RowData nxt = load_row(A, i, js + 1, own);
+  float hzn_p = 0.f, eyn_p = 0.f, exn_p = 0.f, exo_p = 0.f;
+  // row-0 Mur edge Ex(i,0) waits for Ex(i,1): its old value, current, density
+  float ex0_old = 0.f, jx0_old = 0.f, kap0 = 0.f, acc0 = 0.f;
+
+  for (int j = js; j < j1; j++) {
+    const RowData fut = load_row(A, i, j + 2, own);
+    const bool store = j >= j0;
+    const size_t o = (size_t)j * A.pitch + i;
+
+    // Faraday, Eq. (2)
+    float hzn = 0.f;
+    if (exv && j < NY) {
+      hzn = cur.hz - S * ((cur.ey1 - cur.ey) - (nxt.ex - cur.ex));
+      if (i == A.is - 1) hzn += S * A.ey_src;
+      if (store && own) A.hz1[o] = hzn;
+    }
+    const float hzl = __shfl_up(hzn, 1, 64);  // Hz(i-1, j)
+
+    // Ampere + Drude, Eqs. (1), (3): x-edges
+    float exn = 0.f;
+    const float kapx = kn * (0.5f * (cur.n + cur.n1));
+    if (exv) {
+      if (j > 0 && j < NY) {
+        exn = ((1.f - kapx) * cur.ex + S * (hzn - hzn_p) - c1 * cur.jx) / (1.f + kapx);
+        if (store && own) {
+          A.ex1[o] = exn;
+          A.jx1[o] = a * cur.jx + 2.f * kapx * (cur.ex + exn);
+        }
+      } else if (j == NY) {
+        exn = mur_y ? exo_p + cm * (exn_p - cur.ex) : 0.f;
+        if (store && own) {
+          A.ex1[o] = exn;
+          A.jx1[o] = a * cur.jx + 2.f * kapx * (cur.ex + exn);
+        }
+      } else {  // j == 0: finished with row 1
+        ex0_old = cur.ex;
+        jx0_old = cur.jx;
+        kap0 = kapx;
+      }
+    }
+    // y-edges
+    float eyn = 0.f;
+    const float kapy = kn * (0.5f * (cur.n + nxt.n));
+    if (eyc && j < NY && i > 0 && i < NX) {
+      float curl = -S * (hzn - hzl);
+      if (i == A.is) curl += S * A.hz_src;
+      eyn = ((1.f - kapy) * cur.ey + curl - c1 * cur.jy) / (1.f + kapy);
+    }
+    if (j < NY && (wave_has_left || wave_has_right)) {
+      const float nr = __shfl_down(eyn, 1, 64), orr = __shfl_down(cur.ey, 1, 64);
+      const float nl = __shfl_up(eyn, 1, 64), ol = __shfl_up(cur.ey, 1, 64);
+      if (i == 0) eyn = mur_x ? orr + cm * (nr - cur.ey) : 0.f;
+      if (i == NX) eyn = mur_x ? ol + cm * (nl - cur.ey) : 0.f;
+    }
+    if (eyc && j < NY && store && own) {
+      A.ey1[o] = eyn;
+      A.jy1[o] = a * cur.jy + 2.f * kapy * (cur.ey + eyn);
+    }
+
+    // deferred bottom row: Mur edge Ex(i,0) and the window at node row 0
+    if (j == 1 && j0 == 0) {
+      float ex0 = 0.f;
+      if (exv) {
+        ex0 = mur_y ? cur.ex + cm * (exn - ex0_old) : 0.f;
+        if (own) {
+          A.ex1[i] = ex0;
+          A.jx1[i] = a * jx0_old + 2.f * kap0 * (ex0_old + ex0);
+        }
+      }
+      const float exl0 = __shfl_up(ex0, 1, 64);
+      if (own && eyc) {
+        float sx = 0.f, e2;
+        int cx = 0;
+        if (i > 0) { sx += exl0 * exl0; cx++; }
+        if (i < NX) { sx += ex0 * ex0; cx++; }
+        e2 = (cx == 2 ? 0.5f * sx : sx) + eyn_p * eyn_p;
+        A.acc[i] = acc0 + e2;
+      }
+    }
+    // window at node (i, j)
+    const float exl = __shfl_up(exn, 1, 64);
+    if (j > 0) {
+      if (store && own) {
+        float sx = 0.f, sy = 0.f;
+        int cx = 0, cy = 0;
+        if (i > 0) { sx += exl * exl; cx++; }
+        if (i < NX) { sx += exn * exn; cx++; }
+        sy += eyn_p * eyn_p; cy++;
+        if (j < NY) { sy += eyn * eyn; cy++; }
+        const float e2 = (cx == 2 ? 0.5f * sx : sx) + (cy == 2 ? 0.5f * sy : sy);
+        A.acc[o] = cur.acc + e2;
+      }
+    } else {
+      acc0 = cur.acc;
+    }
+    hzn_p = hzn;
+    eyn_p = eyn;
+    exn_p = exn;
+    exo_p = cur.ex;
+    cur = nxt;
+    nxt = fut;
+  }
+}
+
 // ---- host-side launchers ----------------------------------------------------
 template <bool FINE>
 static hipError_t launch_em_t(const EMArgs& A, int ty, hipStream_t st) {
@@ -628,6 +787,20 @@ static hipError_t launch_em_t(const EMArgs& A, int ty, hipStream_t st) {
 
 hipError_t launch_em(const EMArgs& A, bool fine, int ty, hipStream_t st) {
   return fine ? launch_em_t<true>(A, ty, st) : launch_em_t<false>(A, ty, st);
+}
+
+int stream_segments(int NY, int seg) {
+  int nseg = (NY + 1 + seg - 1) / seg;
+  if (nseg > 1 && (NY + 1) - (nseg - 1) * seg < 2) nseg--;  // no 1-row tail
+  return nseg;
+}
+
+hipError_t launch_em_stream(const EMArgs& A, int seg, hipStream_t st) {
+  const int waves = (A.R + 1 + 61) / 62;
+  const int nseg = stream_segments(A.T, seg);
+  dim3 g((waves + kThreads / 64 - 1) / (kThreads / 64), nseg);
+  hipLaunchKernelGGL(k_em_stream, g, dim3(kThreads), 0, st, A, seg, nseg);
+  return hipGetLastError();
 }
 
 hipError_t launch_cont(const ContArgs& A, bool fine, hipStream_t st) {
