@@ -199,10 +199,24 @@ def main():
         cells_l = cfg_l["nx"] * cfg_l["ny"]
         per_l = ms_l[0] / max(cnt_l[0], 1)
         ach_l = em_bytes_per_cell() * cells_l / (per_l * 1e-3) / 1e9
-        out["roofline_large"] = {"bound": "hbm", "kernel": "k_em<base> 4096x2048",
+        out["roofline_large"] = {"bound": "hbm", "kernel": "k_em_stream 4096x2048",
                                  "achieved": ach_l, "peak": 8000.0, "unit": "GB/s",
                                  "frac": ach_l / 8000.0, "avg_launch_us": per_l * 1e3,
                                  "alg_bytes_per_launch": em_bytes_per_cell() * cells_l}
+        # DMR vs uniform-fine where the step is bandwidth-bound: config-1
+        # physics on 4096x2048 coarse (8192x4096 uniform-fine), one interval
+        cfg_ld = W.config_large(periods=4)
+        cfg_lu = W.config_large_uniform(periods=4)
+        sl_d, wl_d, kl_d = run_case(B, cfg_ld, W.seeds(cfg_ld), 1, INTERVAL, 0, False)
+        sl_d.close()
+        sl_u, wl_u, kl_u = run_case(B, cfg_lu, W.seeds(cfg_lu), 1, 2 * INTERVAL, 0, False)
+        sl_u.close()
+        out["large_dmr_vs_uniform"] = {
+            "workload": "coarse 4096x2048 @ lambda/32 + r=2 patch vs uniform-fine "
+                        "8192x4096 @ lambda/64, 4 periods (256 coarse steps)",
+            "dmr_s": wl_d, "uniform_fine_s": wl_u, "speedup": wl_u / wl_d,
+            "dmr_mcell_updates_per_s": kl_d / wl_d / 1e6,
+            "uniform_mcell_updates_per_s": kl_u / wl_u / 1e6}
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample ---------------
     if not args.no_cpu:

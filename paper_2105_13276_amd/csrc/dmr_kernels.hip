@@ -615,25 +615,33 @@ struct RowData {
   float ex, ey, ey1, hz, jx, jy, n, n1, acc;
 };
 
-__device__ inline RowData load_row(const EMArgs& A, int i, int j, bool own) {
+__device__ inline RowData load_row(const EMArgs& A, int i, int j) {
+  // straight-line loads from clamped (always valid) addresses; entries
+  // that do not exist are replaced by zero afterwards
   RowData r;
   const int NX = A.R, NY = A.T;
-  const size_t o = (size_t)j * A.pitch + i;
+  const int ic = min(max(i, 0), NX), jc = min(max(j, 0), NY);
+  const int ic1 = min(max(i + 1, 0), NX);
+  const size_t o = (size_t)jc * A.pitch + ic;
+  const size_t o1 = (size_t)jc * A.pitch + ic1;
   const bool row_ok = j >= 0 && j <= NY;
   const bool exv = row_ok && i >= 0 && i < NX;
   const bool eyv = row_ok && j < NY && i >= 0 && i <= NX;
   const bool ey1v = row_ok && j < NY && i + 1 >= 0 && i + 1 <= NX;
   const bool ndv = row_ok && i >= 0 && i <= NX;
   const bool nd1v = row_ok && i + 1 >= 0 && i + 1 <= NX;
-  r.ex = exv ? A.ex0[o] : 0.f;
-  r.jx = exv ? A.jx0[o] : 0.f;
-  r.ey = eyv ? A.ey0[o] : 0.f;
-  r.jy = eyv ? A.jy0[o] : 0.f;
-  r.ey1 = ey1v ? A.ey0[o + 1] : 0.f;
-  r.hz = (eyv && i < NX) ? A.hz0[o] : 0.f;
-  r.n = ndv ? A.n[o] : 0.f;
-  r.n1 = nd1v ? A.n[o + 1] : 0.f;
-  r.acc = (ndv && own) ? A.acc[o] : 0.f;
+  const float ex = A.ex0[o], jx = A.jx0[o], ey = A.ey0[o], jy = A.jy0[o];
+  const float ey1 = A.ey0[o1], hz = A.hz0[o], n = A.n[o], n1 = A.n[o1];
+  const float acc = A.acc[o];
+  r.ex = exv ? ex : 0.f;
+  r.jx = exv ? jx : 0.f;
+  r.ey = eyv ? ey : 0.f;
+  r.jy = eyv ? jy : 0.f;
+  r.ey1 = ey1v ? ey1 : 0.f;
+  r.hz = (eyv && i < NX) ? hz : 0.f;
+  r.n = ndv ? n : 0.f;
+  r.n1 = nd1v ? n1 : 0.f;
+  r.acc = ndv ? acc : 0.f;
   return r;
 }
 
@@ -654,14 +662,14 @@ __global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int n
   const bool mur_x = A.bc_x == kBcMur, mur_y = A.bc_y == kBcMur;
 
   const int js = j0 > 0 ? j0 - 1 : 0;
-  RowData cur = load_row(A, i, js, own);
-  RowData nxt = load_row(A, i, js + 1, own);
+  RowData cur = load_row(A, i, js);
+  RowData nxt = load_row(A, i, js + 1);
   float hzn_p = 0.f, eyn_p = 0.f, exn_p = 0.f, exo_p = 0.f;
   // row-0 Mur edge Ex(i,0) waits for Ex(i,1): its old value, current, density
   float ex0_old = 0.f, jx0_old = 0.f, kap0 = 0.f, acc0 = 0.f;
 
   for (int j = js; j < j1; j++) {
-    const RowData fut = load_row(A, i, j + 2, own);
+    const RowData fut = load_row(A, i, j + 2);
     const bool store = j >= j0;
     const size_t o = (size_t)j * A.pitch + i;
 
@@ -679,7 +687,7 @@ __global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int n
     const float kapx = kn * (0.5f * (cur.n + cur.n1));
     if (exv) {
       if (j > 0 && j < NY) {
-        exn = ((1.f - kapx) * cur.ex + S * (hzn - hzn_p) - c1 * cur.jx) / (1.f + kapx);
+        exn = ((1.f - kapx) * cur.ex + S * (hzn - hzn_p) - c1 * cur.jx) * __builtin_amdgcn_rcpf(1.f + kapx);
         if (store && own) {
           A.ex1[o] = exn;
           A.jx1[o] = a * cur.jx + 2.f * kapx * (cur.ex + exn);
@@ -702,7 +710,7 @@ __global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int n
     if (eyc && j < NY && i > 0 && i < NX) {
       float curl = -S * (hzn - hzl);
       if (i == A.is) curl += S * A.hz_src;
-      eyn = ((1.f - kapy) * cur.ey + curl - c1 * cur.jy) / (1.f + kapy);
+      eyn = ((1.f - kapy) * cur.ey + curl - c1 * cur.jy) * __builtin_amdgcn_rcpf(1.f + kapy);
     }
     if (j < NY && (wave_has_left || wave_has_right)) {
       const float nr = __shfl_down(eyn, 1, 64), orr = __shfl_down(cur.ey, 1, 64);
