@@ -135,7 +135,7 @@ struct dmr_sim {
   int ext[4] = {0, 0, 0, 0};  // base cells
   int64_t step = 0, blocks = 0;
   int ccur = 0, ncur = 0;
-  int seg0 = 16, ty1 = 16;
+  int seg0 = 16, depth0 = 2, ty1 = 16;
   bool fused_fine = false;
   uint8_t* d_flag = nullptr;
   int32_t *d_scan = nullptr, *d_list = nullptr;
@@ -276,8 +276,14 @@ int stream_rows(int NX, int NY) {
   }
   const long waves_x = (NX + 1 + 61) / 62;
   int seg = 64;
-  while (seg > 8 && waves_x * ((NY + seg) / seg) < 4096) seg >>= 1;
+  while (seg > 4 && waves_x * ((NY + seg) / seg) < 4096) seg >>= 1;
   return seg;
+}
+
+// rows in flight per wave: deep for short (latency-bound) segments
+int stream_depth(int seg) {
+  if (const char* e = getenv("DMR_DEPTH")) return atoi(e) >= 4 ? 4 : 2;
+  return seg <= 8 ? 4 : 2;
 }
 
 int tile_rows(int NX, int NY) {
@@ -380,7 +386,7 @@ int base_step(dmr_sim* s) {
     A.hz_src = (float)ey_inc(s, xs - 0.5 * C.dx, t + 0.5 * C.dt);
   }
   ev_begin(s, 0);
-  hipError_t e = launch_em_stream(A, s->seg0, s->st);
+  hipError_t e = launch_em_stream(A, s->seg0, s->depth0, s->st);
   ev_end(s);
   if (e != hipSuccess) return hipfail(s, e, "base EM launch");
   if (s->has_patch && s->fused_fine) {  // both substeps in one workgroup
@@ -572,6 +578,7 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   s->d_err = (int*)(s->ws + lay.off_err);
   s->stage = (float*)(s->ws + lay.off_stage);
   s->seg0 = stream_rows(p->nx, p->ny);
+  s->depth0 = stream_depth(s->seg0);
   hipError_t e = hipMemsetAsync(s->ws, 0, lay.total, s->st);
   if (e != hipSuccess) { rc = hipfail(s, e, "workspace clear"); delete s; return rc; }
   // seeds: float32 on the pitched node grid

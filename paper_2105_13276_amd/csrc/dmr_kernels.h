@@ -85,7 +85,7 @@ struct ProlongArgs {
 
 hipError_t launch_em(const EMArgs& A, bool fine, int ty, hipStream_t st);
 // base level, column-streaming kernel; seg = rows per segment (>= 2)
-hipError_t launch_em_stream(const EMArgs& A, int seg, hipStream_t st);
+hipError_t launch_em_stream(const EMArgs& A, int seg, int depth, hipStream_t st);
 int stream_segments(int NY, int seg);
 // both fine substeps + transfer in one workgroup when the patch fits in LDS
 bool fine_fused_fits(int fw, int fh);

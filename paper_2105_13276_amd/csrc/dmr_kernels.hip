@@ -645,6 +645,7 @@ __device__ inline RowData load_row(const EMArgs& A, int i, int j) {
   return r;
 }
 
+template <int DEPTH>
 __global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int nseg) {
   const int NX = A.R, NY = A.T;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -662,14 +663,17 @@ __global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int n
   const bool mur_x = A.bc_x == kBcMur, mur_y = A.bc_y == kBcMur;
 
   const int js = j0 > 0 ? j0 - 1 : 0;
-  RowData cur = load_row(A, i, js);
-  RowData nxt = load_row(A, i, js + 1);
+  // rows js .. js+DEPTH in flight; buf[0] is the current row
+  RowData buf[DEPTH + 1];
+#pragma unroll
+  for (int d = 0; d <= DEPTH; d++) buf[d] = load_row(A, i, js + d);
   float hzn_p = 0.f, eyn_p = 0.f, exn_p = 0.f, exo_p = 0.f;
   // row-0 Mur edge Ex(i,0) waits for Ex(i,1): its old value, current, density
   float ex0_old = 0.f, jx0_old = 0.f, kap0 = 0.f, acc0 = 0.f;
 
   for (int j = js; j < j1; j++) {
-    const RowData fut = load_row(A, i, j + 2);
+    const RowData& cur = buf[0];
+    const RowData& nxt = buf[1];
     const bool store = j >= j0;
     const size_t o = (size_t)j * A.pitch + i;
 
@@ -763,8 +767,9 @@ __global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int n
     eyn_p = eyn;
     exn_p = exn;
     exo_p = cur.ex;
-    cur = nxt;
-    nxt = fut;
+#pragma unroll
+    for (int d = 0; d < DEPTH; d++) buf[d] = buf[d + 1];
+    buf[DEPTH] = load_row(A, i, j + DEPTH + 1);
   }
 }
 
@@ -777,8 +782,13 @@ __global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int n
 // written back once (buffer 0 in, buffer 0 out).
 // ---------------------------------------------------------------------------
 constexpr int kFusedThreads = 1024;
-constexpr int kFusedMaxNodesPerThread = 6;
+constexpr int kFusedMaxNodesPerThread = 9;  // 3 x 3 per 32 x 32 threads
 
+// loop over the patch nodes in a fixed 2-D order (no integer division);
+// each thread visits at most kFusedMaxNodesPerThread nodes
+#define FOR_PQ                                              \
+  for (int q = ty; q < H; q += 32)                          \
+    for (int p = tx, k = q * W + tx; p < W; p += 32, k += 32)
 __global__ __launch_bounds__(kFusedThreads) void k_fine_fused(EMArgs A) {
   extern __shared__ float sm[];
   const int L = A.L, B = A.B, R = A.R, T = A.T;
@@ -793,10 +803,10 @@ __global__ __launch_bounds__(kFusedThreads) void k_fine_fused(EMArgs A) {
   float* hs = nn + N;   // Hz after the first substep (for the transfer)
   float* tmp = hs + N;  // Laplacian scratch of the filter
   const int tid = threadIdx.x;
+  const int tx = tid & 31, ty = tid >> 5;  // 32 x 32 threads
   const int pitch = A.pitch;
   auto g = [&](int p, int q) { return (size_t)(B + q) * pitch + (L + p); };
-  for (int k = tid; k < N; k += kFusedThreads) {
-    const int p = k % W, q = k / W;
+  FOR_PQ {
     const size_t o = g(p, q);
     hz[k] = (p < fw && q < fh) ? A.hz0[o] : 0.f;
     ex[k] = (p < fw) ? A.ex0[o] : 0.f;
@@ -806,9 +816,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_fine_fused(EMArgs A) {
     nn[k] = A.n[o];
   }
   float acc[kFusedMaxNodesPerThread];
-  for (int u = 0; u < kFusedMaxNodesPerThread; u++) {
-    const int k = tid + u * kFusedThreads;
-    acc[u] = (k < N) ? A.acc[g(k % W, k / W)] : 0.f;
+  {
+    int u = 0;
+    FOR_PQ {
+      acc[u++] = A.acc[g(p, q)];
+    }
   }
   __syncthreads();
   const float S = A.S, c1 = A.c1, a = A.a, kn = A.kn, gam = A.gamma;
@@ -820,8 +832,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fine_fused(EMArgs A) {
       for (int comp = 0; comp < 2; comp++) {
         float* e = comp ? ey : ex;
         const int pe = comp ? fw : fw - 1, qe = comp ? fh - 1 : fh;  // last index
-        for (int k = tid; k < N; k += kFusedThreads) {
-          const int p = k % W, q = k / W;
+        FOR_PQ {
           float l = 0.f;
           if (p <= pe && q <= qe) {
             const float c = e[k];
@@ -831,8 +842,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fine_fused(EMArgs A) {
           tmp[k] = l;
         }
         __syncthreads();
-        for (int k = tid; k < N; k += kFusedThreads) {
-          const int p = k % W, q = k / W;
+        FOR_PQ {
           const bool interior = comp ? (p > 0 && p < fw && q < fh) : (q > 0 && q < fh && p < fw);
           if (interior) {
             const float c = tmp[k];
@@ -845,8 +855,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fine_fused(EMArgs A) {
       }
     }
     // Faraday
-    for (int k = tid; k < N; k += kFusedThreads) {
-      const int p = k % W, q = k / W;
+    FOR_PQ {
       if (p < fw && q < fh) {
         const float h = hz[k] - S * ((ey[k + 1] - ey[k]) - (ex[k + W] - ex[k]));
         hz[k] = h;
@@ -855,8 +864,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fine_fused(EMArgs A) {
     }
     __syncthreads();
     // Ampere + Drude; boundary edges from the coarse mesh (Eq. (5b))
-    for (int k = tid; k < N; k += kFusedThreads) {
-      const int p = k % W, q = k / W;
+    FOR_PQ {
       const int i = L + p, j = B + q;  // global fine indices
       if (p < fw) {
         const float e = ex[k];
@@ -901,35 +909,33 @@ __global__ __launch_bounds__(kFusedThreads) void k_fine_fused(EMArgs A) {
     }
     __syncthreads();
     // window
-    for (int u = 0; u < kFusedMaxNodesPerThread; u++) {
-      const int k = tid + u * kFusedThreads;
-      if (k >= N) break;
-      const int p = k % W, q = k / W;
+    int u = 0;
+    FOR_PQ {
       float sx = 0.f, sy = 0.f;
       int cx = 0, cy = 0;
       if (p > 0) { const float v = ex[k - 1]; sx += v * v; cx++; }
       if (p < fw) { const float v = ex[k]; sx += v * v; cx++; }
       if (q > 0) { const float v = ey[k - W]; sy += v * v; cy++; }
       if (q < fh) { const float v = ey[k]; sy += v * v; cy++; }
-      acc[u] += (cx == 2 ? 0.5f * sx : sx) + (cy == 2 ? 0.5f * sy : sy);
+      acc[u++] += (cx == 2 ? 0.5f * sx : sx) + (cy == 2 ? 0.5f * sy : sy);
     }
     __syncthreads();
   }
   // write back the fine state and the window
-  for (int k = tid; k < N; k += kFusedThreads) {
-    const int p = k % W, q = k / W;
+  FOR_PQ {
     const size_t o = g(p, q);
     if (p < fw && q < fh) A.hz1[o] = hz[k];
     if (p < fw) { A.ex1[o] = ex[k]; A.jx1[o] = jx[k]; }
     if (q < fh) { A.ey1[o] = ey[k]; A.jy1[o] = jy[k]; }
   }
-  for (int u = 0; u < kFusedMaxNodesPerThread; u++) {
-    const int k = tid + u * kFusedThreads;
-    if (k < N) A.acc[g(k % W, k / W)] = acc[u];
+  {
+    int u = 0;
+    FOR_PQ {
+      A.acc[g(p, q)] = acc[u++];
+    }
   }
   // fine -> coarse transfer for the coarse entities strictly inside
-  for (int k = tid; k < N; k += kFusedThreads) {
-    const int p = k % W, q = k / W;
+  FOR_PQ {
     if ((p | q) & 1) continue;
     const int ca = (L + p) >> 1, cb = (B + q) >> 1;
     const size_t co = (size_t)cb * A.cpitch + ca;
@@ -984,7 +990,7 @@ hipError_t launch_em(const EMArgs& A, bool fine, int ty, hipStream_t st) {
 
 bool fine_fused_fits(int fw, int fh) {
   const long n = (long)(fw + 1) * (fh + 1);
-  return n <= (long)kFusedThreads * kFusedMaxNodesPerThread && n * 8 * 4 <= 160 * 1024;
+  return fw + 1 <= 96 && fh + 1 <= 96 && n * 8 * 4 <= 160 * 1024;
 }
 
 hipError_t launch_fine_fused(const EMArgs& A, hipStream_t st) {
@@ -1008,11 +1014,12 @@ int stream_segments(int NY, int seg) {
   return nseg;
 }
 
-hipError_t launch_em_stream(const EMArgs& A, int seg, hipStream_t st) {
+hipError_t launch_em_stream(const EMArgs& A, int seg, int depth, hipStream_t st) {
   const int waves = (A.R + 1 + 61) / 62;
   const int nseg = stream_segments(A.T, seg);
   dim3 g((waves + kThreads / 64 - 1) / (kThreads / 64), nseg);
-  hipLaunchKernelGGL(k_em_stream, g, dim3(kThreads), 0, st, A, seg, nseg);
+  if (depth >= 4) hipLaunchKernelGGL(k_em_stream<4>, g, dim3(kThreads), 0, st, A, seg, nseg);
+  else hipLaunchKernelGGL(k_em_stream<2>, g, dim3(kThreads), 0, st, A, seg, nseg);
   return hipGetLastError();
 }
 
