@@ -136,7 +136,6 @@ struct dmr_sim {
   int64_t step = 0, blocks = 0;
   int ccur = 0, ncur = 0;
   int seg0 = 16, depth0 = 2, ty1 = 16;
-  bool fused_fine = false;
   uint8_t* d_flag = nullptr;
   int32_t *d_scan = nullptr, *d_list = nullptr;
   int* d_desc = nullptr;
@@ -321,8 +320,7 @@ int prolong(dmr_sim* s, const int ne[4], bool keep_n) {
   s->has_patch = true;
   const int fw = r * (ne[2] - ne[0]), fh = r * (ne[3] - ne[1]);
   s->ty1 = tile_rows(fw, fh);
-  const char* ff = getenv("DMR_FUSED_FINE");
-  s->fused_fine = fine_fused_fits(fw, fh) && !(ff && ff[0] == '0');
+
   return DMR_OK;
 }
 
@@ -389,23 +387,7 @@ int base_step(dmr_sim* s) {
   hipError_t e = launch_em_stream(A, s->seg0, s->depth0, s->st);
   ev_end(s);
   if (e != hipSuccess) return hipfail(s, e, "base EM launch");
-  if (s->has_patch && s->fused_fine) {  // both substeps in one workgroup
-    const int r = p.r;
-    EMArgs G{};
-    em_args_level(&G, F, 0, 0, F.n[s->ncur], F.acc);
-    G.L = r * s->ext[0]; G.B = r * s->ext[1];
-    G.R = r * s->ext[2]; G.T = r * s->ext[3];
-    G.cex0 = C.ex[c]; G.cey0 = C.ey[c];
-    G.cex1 = C.ex[1 - c]; G.cey1 = C.ey[1 - c];
-    G.cpitch = C.pitch;
-    G.gamma = (float)p.fine_filter;
-    G.chz = C.hz[1 - c]; G.cex = C.ex[1 - c]; G.cey = C.ey[1 - c];
-    G.cjx = C.jx[1 - c]; G.cjy = C.jy[1 - c];
-    ev_begin(s, 1);
-    e = launch_fine_fused(G, s->st);
-    ev_end(s);
-    if (e != hipSuccess) return hipfail(s, e, "fused fine launch");
-  } else if (s->has_patch) {  // two fine substeps (Sec. III.C)
+  if (s->has_patch) {  // two fine substeps (Sec. III.C)
     const int r = p.r;
     for (int m = 1; m <= r; m++) {
       EMArgs G{};

@@ -87,9 +87,6 @@ hipError_t launch_em(const EMArgs& A, bool fine, int ty, hipStream_t st);
 // base level, column-streaming kernel; seg = rows per segment (>= 2)
 hipError_t launch_em_stream(const EMArgs& A, int seg, int depth, hipStream_t st);
 int stream_segments(int NY, int seg);
-// both fine substeps + transfer in one workgroup when the patch fits in LDS
-bool fine_fused_fits(int fw, int fh);
-hipError_t launch_fine_fused(const EMArgs& A, hipStream_t st);
 hipError_t launch_cont(const ContArgs& A, bool fine, hipStream_t st);
 hipError_t launch_regrid_test(const FlagArgs& F, const ScanArgs& S, hipStream_t st);
 hipError_t launch_prolong(const ProlongArgs& A, hipStream_t st);

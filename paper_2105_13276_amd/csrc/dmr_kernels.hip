@@ -773,192 +773,6 @@ __global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int n
   }
 }
 
-// ---------------------------------------------------------------------------
-// Both fine substeps of one coarse step in one workgroup, for patches whose
-// state fits in LDS ((fw+1)(fh+1) nodes x 8 planes).  Same arithmetic as
-// k_em<true> applied twice (filter, Faraday, Ampere + Drude with the
-// Eq. (5b) boundary at frac = 1/2 then 1, window), then the fine -> coarse
-// transfer; the patch's Hz, E and J stay in LDS between the substeps and are
-// written back once (buffer 0 in, buffer 0 out).
-// ---------------------------------------------------------------------------
-constexpr int kFusedThreads = 1024;
-constexpr int kFusedMaxNodesPerThread = 9;  // 3 x 3 per 32 x 32 threads
-
-// loop over the patch nodes in a fixed 2-D order (no integer division);
-// each thread visits at most kFusedMaxNodesPerThread nodes
-#define FOR_PQ                                              \
-  for (int q = ty; q < H; q += 32)                          \
-    for (int p = tx, k = q * W + tx; p < W; p += 32, k += 32)
-__global__ __launch_bounds__(kFusedThreads) void k_fine_fused(EMArgs A) {
-  extern __shared__ float sm[];
-  const int L = A.L, B = A.B, R = A.R, T = A.T;
-  const int fw = R - L, fh = T - B;
-  const int W = fw + 1, H = fh + 1, N = W * H;
-  float* hz = sm;
-  float* ex = hz + N;
-  float* ey = ex + N;
-  float* jx = ey + N;
-  float* jy = jx + N;
-  float* nn = jy + N;
-  float* hs = nn + N;   // Hz after the first substep (for the transfer)
-  float* tmp = hs + N;  // Laplacian scratch of the filter
-  const int tid = threadIdx.x;
-  const int tx = tid & 31, ty = tid >> 5;  // 32 x 32 threads
-  const int pitch = A.pitch;
-  auto g = [&](int p, int q) { return (size_t)(B + q) * pitch + (L + p); };
-  FOR_PQ {
-    const size_t o = g(p, q);
-    hz[k] = (p < fw && q < fh) ? A.hz0[o] : 0.f;
-    ex[k] = (p < fw) ? A.ex0[o] : 0.f;
-    jx[k] = (p < fw) ? A.jx0[o] : 0.f;
-    ey[k] = (q < fh) ? A.ey0[o] : 0.f;
-    jy[k] = (q < fh) ? A.jy0[o] : 0.f;
-    nn[k] = A.n[o];
-  }
-  float acc[kFusedMaxNodesPerThread];
-  {
-    int u = 0;
-    FOR_PQ {
-      acc[u++] = A.acc[g(p, q)];
-    }
-  }
-  __syncthreads();
-  const float S = A.S, c1 = A.c1, a = A.a, kn = A.kn, gam = A.gamma;
-
-  for (int m = 1; m <= 2; m++) {
-    const float frac = 0.5f * m;
-    if (gam > 0.f) {
-      // hyper-diffusion of the interior E, one component at a time
-      for (int comp = 0; comp < 2; comp++) {
-        float* e = comp ? ey : ex;
-        const int pe = comp ? fw : fw - 1, qe = comp ? fh - 1 : fh;  // last index
-        FOR_PQ {
-          float l = 0.f;
-          if (p <= pe && q <= qe) {
-            const float c = e[k];
-            l = (p > 0 ? e[k - 1] : c) + (p < pe ? e[k + 1] : c) +
-                (q > 0 ? e[k - W] : c) + (q < qe ? e[k + W] : c) - 4.f * c;
-          }
-          tmp[k] = l;
-        }
-        __syncthreads();
-        FOR_PQ {
-          const bool interior = comp ? (p > 0 && p < fw && q < fh) : (q > 0 && q < fh && p < fw);
-          if (interior) {
-            const float c = tmp[k];
-            const float l2 = (p > 0 ? tmp[k - 1] : c) + (p < pe ? tmp[k + 1] : c) +
-                             (q > 0 ? tmp[k - W] : c) + (q < qe ? tmp[k + W] : c) - 4.f * c;
-            e[k] -= gam * l2;
-          }
-        }
-        __syncthreads();
-      }
-    }
-    // Faraday
-    FOR_PQ {
-      if (p < fw && q < fh) {
-        const float h = hz[k] - S * ((ey[k + 1] - ey[k]) - (ex[k + W] - ex[k]));
-        hz[k] = h;
-        if (m == 1) hs[k] = h;
-      }
-    }
-    __syncthreads();
-    // Ampere + Drude; boundary edges from the coarse mesh (Eq. (5b))
-    FOR_PQ {
-      const int i = L + p, j = B + q;  // global fine indices
-      if (p < fw) {
-        const float e = ex[k];
-        const float kap = kn * (0.5f * (nn[k] + nn[k + 1]));
-        float en;
-        if (q > 0 && q < fh) {
-          en = ((1.f - kap) * e + S * (hz[k] - hz[k - W]) - c1 * jx[k]) / (1.f + kap);
-        } else {
-          const int J = j >> 1;
-          int ic;
-          float w0, w1;
-          if ((i & 1) == 0) { ic = (i >> 1) - 1; w0 = 0.25f; w1 = 0.75f; }
-          else              { ic = i >> 1;       w0 = 0.75f; w1 = 0.25f; }
-          const size_t co = (size_t)J * A.cpitch + ic;
-          const float vo = w0 * A.cex0[co] + w1 * A.cex0[co + 1];
-          const float vn = w0 * A.cex1[co] + w1 * A.cex1[co + 1];
-          en = (1.f - frac) * vo + frac * vn;
-        }
-        jx[k] = a * jx[k] + 2.f * kap * (e + en);
-        ex[k] = en;
-      }
-      if (q < fh) {
-        const float e = ey[k];
-        const float kap = kn * (0.5f * (nn[k] + nn[k + W]));
-        float en;
-        if (p > 0 && p < fw) {
-          en = ((1.f - kap) * e - S * (hz[k] - hz[k - 1]) - c1 * jy[k]) / (1.f + kap);
-        } else {
-          const int I = i >> 1;
-          int jc;
-          float w0, w1;
-          if ((j & 1) == 0) { jc = (j >> 1) - 1; w0 = 0.25f; w1 = 0.75f; }
-          else              { jc = j >> 1;       w0 = 0.75f; w1 = 0.25f; }
-          const size_t co = (size_t)jc * A.cpitch + I;
-          const float vo = w0 * A.cey0[co] + w1 * A.cey0[co + A.cpitch];
-          const float vn = w0 * A.cey1[co] + w1 * A.cey1[co + A.cpitch];
-          en = (1.f - frac) * vo + frac * vn;
-        }
-        jy[k] = a * jy[k] + 2.f * kap * (e + en);
-        ey[k] = en;
-      }
-    }
-    __syncthreads();
-    // window
-    int u = 0;
-    FOR_PQ {
-      float sx = 0.f, sy = 0.f;
-      int cx = 0, cy = 0;
-      if (p > 0) { const float v = ex[k - 1]; sx += v * v; cx++; }
-      if (p < fw) { const float v = ex[k]; sx += v * v; cx++; }
-      if (q > 0) { const float v = ey[k - W]; sy += v * v; cy++; }
-      if (q < fh) { const float v = ey[k]; sy += v * v; cy++; }
-      acc[u++] += (cx == 2 ? 0.5f * sx : sx) + (cy == 2 ? 0.5f * sy : sy);
-    }
-    __syncthreads();
-  }
-  // write back the fine state and the window
-  FOR_PQ {
-    const size_t o = g(p, q);
-    if (p < fw && q < fh) A.hz1[o] = hz[k];
-    if (p < fw) { A.ex1[o] = ex[k]; A.jx1[o] = jx[k]; }
-    if (q < fh) { A.ey1[o] = ey[k]; A.jy1[o] = jy[k]; }
-  }
-  {
-    int u = 0;
-    FOR_PQ {
-      A.acc[g(p, q)] = acc[u++];
-    }
-  }
-  // fine -> coarse transfer for the coarse entities strictly inside
-  FOR_PQ {
-    if ((p | q) & 1) continue;
-    const int ca = (L + p) >> 1, cb = (B + q) >> 1;
-    const size_t co = (size_t)cb * A.cpitch + ca;
-    if (p < fw && q < fh) {
-      float s2 = 0.f;
-      for (int da = 0; da < 2; da++)
-        for (int db = 0; db < 2; db++) {
-          const int kk = k + db * W + da;
-          s2 += 0.5f * (hs[kk] + hz[kk]);
-        }
-      A.chz[co] = 0.25f * s2;
-    }
-    if (p < fw && q > 0 && q < fh) {
-      A.cex[co] = 0.5f * (ex[k] + ex[k + 1]);
-      A.cjx[co] = jx[k] + jx[k + 1];
-    }
-    if (q < fh && p > 0 && p < fw) {
-      A.cey[co] = 0.5f * (ey[k] + ey[k + W]);
-      A.cjy[co] = jy[k] + jy[k + W];
-    }
-  }
-}
-
 // ---- host-side launchers ----------------------------------------------------
 template <bool FINE>
 static hipError_t launch_em_t(const EMArgs& A, int ty, hipStream_t st) {
@@ -986,26 +800,6 @@ static hipError_t launch_em_t(const EMArgs& A, int ty, hipStream_t st) {
 
 hipError_t launch_em(const EMArgs& A, bool fine, int ty, hipStream_t st) {
   return fine ? launch_em_t<true>(A, ty, st) : launch_em_t<false>(A, ty, st);
-}
-
-bool fine_fused_fits(int fw, int fh) {
-  const long n = (long)(fw + 1) * (fh + 1);
-  return fw + 1 <= 96 && fh + 1 <= 96 && n * 8 * 4 <= 160 * 1024;
-}
-
-hipError_t launch_fine_fused(const EMArgs& A, hipStream_t st) {
-  const int fw = A.R - A.L, fh = A.T - A.B;
-  const size_t lds = (size_t)(fw + 1) * (fh + 1) * 8 * sizeof(float);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_fine_fused,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  hipLaunchKernelGGL(k_fine_fused, dim3(1), dim3(kFusedThreads), lds, st, A);
-  return hipGetLastError();
 }
 
 int stream_segments(int NY, int seg) {

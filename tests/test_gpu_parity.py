@@ -102,18 +102,3 @@ def test_config1_uniform_fine_prefix():
     g.step(cfg["steps"])
     o.step(cfg["steps"])
     assert_parity(g, o, _nc(cfg), levels=(0,), tag="config1-uniform")
-
-
-@pytest.mark.parametrize("fused", ["1", "0"])
-def test_fine_kernel_variants(fused, monkeypatch):
-    """Both implementations of the fine substeps (single-workgroup LDS kernel
-    for small patches, tiled kernel otherwise) against the oracle."""
-    monkeypatch.setenv("DMR_FUSED_FINE", fused)
-    cfg = W.config1_dmr(periods=24)
-    cfg["erms_over_ebd"] = 2.0
-    sb, sf = W.seeds(cfg)
-    g, o = both(cfg, sb, sf)
-    g.step(cfg["steps"])
-    o.step(cfg["steps"])
-    assert g.patch() == o.patch()
-    assert_parity(g, o, _nc(cfg), tag="fine fused=%s" % fused)
