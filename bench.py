@@ -40,6 +40,9 @@ def parse():
                     help="skip the 4096x2048 bandwidth-bound kernel measurement")
     ap.add_argument("--cpu-steps", type=int, default=1024,
                     help="coarse steps of the oracle sample")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched 64-instance comparison")
+    ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--only-large", action="store_true",
                     help="profiling aid: run only 4096x2048 base steps and a "
                          "256 MiB device copy (counter calibration), no JSON")
@@ -217,6 +220,47 @@ def main():
             "dmr_s": wl_d, "uniform_fine_s": wl_u, "speedup": wl_u / wl_d,
             "dmr_mcell_updates_per_s": kl_d / wl_d / 1e6,
             "uniform_mcell_updates_per_s": kl_u / wl_u / 1e6}
+
+    # ---- batched form: 64 independent DMR runs (config-3 draw) -----------
+    if not args.no_batch:
+        cfgs, seeds3 = W.config3(args.batch_count, periods=16)
+        warm, timed = 2 * INTERVAL, 2 * INTERVAL
+        bt = B.Batch(cfgs, seeds3)
+        bt.step(warm)           # launch-shape timing + first graph capture
+        bt.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bt.step(timed)
+        bt.sync()
+        torch.cuda.synchronize()
+        wall_b = time.perf_counter() - t0
+        shape = bt.config()
+        work_b = 0
+        for inst, c in zip(bt.instances, cfgs):
+            e = inst.patch()
+            work_b += timed * (c["nx"] * c["ny"] + 8 * (e[2] - e[0]) * (e[3] - e[1]))
+        bt.close()
+        wall_s = 0.0
+        for c, sd in zip(cfgs, seeds3):
+            g = B.Sim(c, *sd)
+            g.step(warm)
+            g.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.step(timed)
+            g.sync()
+            torch.cuda.synchronize()
+            wall_s += time.perf_counter() - t0
+            g.close()
+        out["batched"] = {
+            "workload": "%d DMR instances (coarse sides 256/512/1024 x half, "
+                        "35/110/170 GHz, 100-760 Torr), %d coarse steps timed after %d"
+                        % (len(cfgs), timed, warm),
+            "batched_s": wall_b, "sequential_plain_s": wall_s,
+            "speedup": wall_s / wall_b,
+            "mcell_updates_per_s": work_b / wall_b / 1e6,
+            "launch_shape": {"seg": shape[0], "depth": shape[1], "fine_ty": shape[2],
+                             "graph": shape[3]}}
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample ---------------
     if not args.no_cpu:

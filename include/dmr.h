@@ -177,6 +177,46 @@ int dmr_get_timing(dmr_sim *s, double ms[4], int64_t launches[4]);
 /* Text of the last error on this handle (never NULL). */
 const char *dmr_last_error(const dmr_sim *s);
 
+/* ---- batched form -------------------------------------------------------
+ * count independent simulations (grid sizes and physical parameters may
+ * differ; steps per period, mode, continuity switch and regrid cadence must
+ * agree) advanced in lockstep: each per-step kernel is one launch over the
+ * tiles of all instances, the steps of every steady 256-step interval are
+ * replayed from one captured HIP graph, and the streaming segment length,
+ * load depth and fine tile height are chosen by timing real steps (all
+ * choices give bit-identical results; choices are cached per size key).
+ * The batch runs on a private stream ordered after / before the caller's
+ * stream with events.  Results per instance equal those of dmr_step on a
+ * dmr_create'd simulation with the same inputs, bit for bit. */
+typedef struct dmr_batch dmr_batch;
+
+/* Workspace for count instances p[0..count-1] (instances + launch tables). */
+int dmr_batch_workspace_bytes(const dmr_params *p, int count, size_t *bytes);
+
+/* seed_base / seed_fine: arrays of count host pointers as in dmr_create (the
+ * arrays themselves or any entry may be NULL). */
+int dmr_batch_create(const dmr_params *p, int count, const double *const *seed_base,
+                     const double *const *seed_fine, void *d_workspace, size_t bytes,
+                     void *stream, dmr_batch **out);
+
+/* Queue n base steps of every instance (growth tests every regrid_every). */
+int dmr_batch_step(dmr_batch *b, int64_t n);
+
+/* Borrowed handle of instance k for dmr_read_field, dmr_get_patch, dmr_time
+ * and the like; do not dmr_step or dmr_destroy it. */
+int dmr_batch_instance(dmr_batch *b, int k, dmr_sim **out);
+
+/* Wait; DMR_EUNSTABLE if any instance saw a non-finite value. */
+int dmr_batch_sync(dmr_batch *b);
+
+/* Launch configuration {segment rows, load depth, fine tile rows, graph on};
+ * set_config forces one (and disables the timing-based choice). */
+int dmr_batch_config(dmr_batch *b, int32_t cfg[4]);
+int dmr_batch_set_config(dmr_batch *b, const int32_t cfg[4]);
+
+void dmr_batch_destroy(dmr_batch *b);
+const char *dmr_batch_last_error(const dmr_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

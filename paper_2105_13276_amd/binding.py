@@ -24,7 +24,10 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSTABLE"}
 SYMBOLS = ["dmr_workspace_bytes", "dmr_create", "dmr_destroy", "dmr_step",
            "dmr_regrid", "dmr_get_patch", "dmr_get_regrid", "dmr_field_dims",
            "dmr_read_field", "dmr_write_field", "dmr_time", "dmr_sync",
-           "dmr_set_timing", "dmr_get_timing", "dmr_last_error"]
+           "dmr_set_timing", "dmr_get_timing", "dmr_last_error",
+           "dmr_batch_workspace_bytes", "dmr_batch_create", "dmr_batch_step",
+           "dmr_batch_instance", "dmr_batch_sync", "dmr_batch_config",
+           "dmr_batch_set_config", "dmr_batch_destroy", "dmr_batch_last_error"]
 
 
 class DmrParams(C.Structure):
@@ -84,6 +87,17 @@ def lib():
         L.dmr_get_timing.argtypes = [V, P(C.c_double), P(C.c_int64)]
         L.dmr_last_error.argtypes = [V]
         L.dmr_last_error.restype = C.c_char_p
+        L.dmr_batch_workspace_bytes.argtypes = [V, C.c_int, P(C.c_size_t)]
+        L.dmr_batch_create.argtypes = [V, C.c_int, V, V, V, C.c_size_t, V, P(V)]
+        L.dmr_batch_step.argtypes = [V, C.c_int64]
+        L.dmr_batch_instance.argtypes = [V, C.c_int, P(V)]
+        L.dmr_batch_sync.argtypes = [V]
+        L.dmr_batch_config.argtypes = [V, P(C.c_int32)]
+        L.dmr_batch_set_config.argtypes = [V, P(C.c_int32)]
+        L.dmr_batch_destroy.argtypes = [V]
+        L.dmr_batch_destroy.restype = None
+        L.dmr_batch_last_error.argtypes = [V]
+        L.dmr_batch_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -123,53 +137,17 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 
 
-class Sim:
-    """One simulation on one GPU.  The workspace is a torch uint8 tensor and
-    work is queued on torch's current stream of ``device``."""
+class _Handle:
+    """Methods shared by owned simulations and batch instances."""
 
-    def __init__(self, cfg: dict, seed_base=None, seed_fine=None,
-                 device: str = "cuda:0", stream=None):
-        import torch
-        if not torch.cuda.is_available():
-            raise DmrError("no HIP device available")
-        self.cfg = dict(cfg)
-        self.device = torch.device(device)
-        self._p = make_params(cfg)
-        nbytes = workspace_bytes(cfg)
-        with torch.cuda.device(self.device):
-            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-            self.stream = stream or torch.cuda.current_stream(self.device)
-        sb = None if seed_base is None else np.ascontiguousarray(seed_base, np.float64)
-        sf = None if seed_fine is None else np.ascontiguousarray(seed_fine, np.float64)
-        if sb is not None and sb.shape != (cfg["ny"] + 1, cfg["nx"] + 1):
-            raise ValueError("seed_base shape %s" % (sb.shape,))
-        if sf is not None and sf.shape != (cfg["r"] * cfg["ny"] + 1, cfg["r"] * cfg["nx"] + 1):
-            raise ValueError("seed_fine shape %s" % (sf.shape,))
-        h = C.c_void_p()
-        rc = lib().dmr_create(C.byref(self._p), _ptr(sb), _ptr(sf),
-                              C.c_void_p(self.workspace.data_ptr()), nbytes,
-                              C.c_void_p(self.stream.cuda_stream), C.byref(h))
-        if rc:
-            raise DmrError("dmr_create failed: %s" % ERRORS.get(rc, rc))
-        self._h = h
+    _h = None
+    cfg: dict = {}
+    device = None
 
     def _check(self, rc, what):
         if rc:
             msg = lib().dmr_last_error(self._h).decode()
             raise DmrError("%s: %s (%s)" % (what, ERRORS.get(rc, rc), msg))
-
-    def close(self):
-        if getattr(self, "_h", None):
-            lib().dmr_destroy(self._h)
-            self._h = None
-
-    __del__ = close
-
-    def step(self, n: int):
-        self._check(lib().dmr_step(self._h, int(n)), "dmr_step")
-
-    def regrid(self):
-        self._check(lib().dmr_regrid(self._h), "dmr_regrid")
 
     def sync(self):
         self._check(lib().dmr_sync(self._h), "dmr_sync")
@@ -204,6 +182,138 @@ class Sim:
             out = out.reshape(8, r // 8, c)
         return out
 
+    def time(self):
+        t = C.c_double()
+        st = C.c_int64()
+        self._check(lib().dmr_time(self._h, C.byref(t), C.byref(st)), "dmr_time")
+        return t.value, st.value
+
+
+class BatchInstance(_Handle):
+    """Borrowed view of one instance of a Batch (reads only)."""
+
+    def __init__(self, batch, k):
+        h = C.c_void_p()
+        rc = lib().dmr_batch_instance(batch._h, k, C.byref(h))
+        if rc:
+            raise DmrError("dmr_batch_instance: %s" % ERRORS.get(rc, rc))
+        self._h = h
+        self.cfg = batch.cfgs[k]
+        self._batch = batch  # keeps the batch alive
+
+
+class Batch:
+    """Many independent simulations advanced in lockstep by batched launches
+    (graph-replayed intervals, tuned launch shapes)."""
+
+    def __init__(self, cfgs, seeds, device: str = "cuda:0"):
+        import torch
+        if not torch.cuda.is_available():
+            raise DmrError("no HIP device available")
+        self.cfgs = [dict(c) for c in cfgs]
+        n = len(cfgs)
+        self._params = (DmrParams * n)(*[make_params(c) for c in cfgs])
+        nbytes = C.c_size_t()
+        rc = lib().dmr_batch_workspace_bytes(self._params, n, C.byref(nbytes))
+        if rc:
+            raise DmrError("dmr_batch_workspace_bytes: %s" % ERRORS.get(rc, rc))
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+        self._seed_arrays = []
+        sb = (C.c_void_p * n)()
+        sf = (C.c_void_p * n)()
+        for k, (b, f) in enumerate(seeds):
+            if b is not None:
+                b = np.ascontiguousarray(b, np.float64)
+                self._seed_arrays.append(b)
+                sb[k] = b.ctypes.data
+            if f is not None:
+                f = np.ascontiguousarray(f, np.float64)
+                self._seed_arrays.append(f)
+                sf[k] = f.ctypes.data
+        h = C.c_void_p()
+        rc = lib().dmr_batch_create(self._params, n, sb, sf,
+                                    C.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                                    C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc:
+            raise DmrError("dmr_batch_create failed: %s" % ERRORS.get(rc, rc))
+        self._h = h
+        self.instances = [BatchInstance(self, k) for k in range(n)]
+
+    def _check(self, rc, what):
+        if rc:
+            msg = lib().dmr_batch_last_error(self._h).decode()
+            raise DmrError("%s: %s (%s)" % (what, ERRORS.get(rc, rc), msg))
+
+    def step(self, n: int):
+        self._check(lib().dmr_batch_step(self._h, int(n)), "dmr_batch_step")
+
+    def sync(self):
+        self._check(lib().dmr_batch_sync(self._h), "dmr_batch_sync")
+
+    def config(self):
+        c = (C.c_int32 * 4)()
+        self._check(lib().dmr_batch_config(self._h, c), "dmr_batch_config")
+        return tuple(c)
+
+    def set_config(self, seg, depth, ty, graph):
+        c = (C.c_int32 * 4)(seg, depth, ty, int(graph))
+        self._check(lib().dmr_batch_set_config(self._h, c), "dmr_batch_set_config")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.instances = []
+            lib().dmr_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+class Sim(_Handle):
+    """One simulation on one GPU.  The workspace is a torch uint8 tensor and
+    work is queued on torch's current stream of ``device``."""
+
+    def __init__(self, cfg: dict, seed_base=None, seed_fine=None,
+                 device: str = "cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise DmrError("no HIP device available")
+        self.cfg = dict(cfg)
+        self.device = torch.device(device)
+        self._p = make_params(cfg)
+        nbytes = workspace_bytes(cfg)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream or torch.cuda.current_stream(self.device)
+        sb = None if seed_base is None else np.ascontiguousarray(seed_base, np.float64)
+        sf = None if seed_fine is None else np.ascontiguousarray(seed_fine, np.float64)
+        if sb is not None and sb.shape != (cfg["ny"] + 1, cfg["nx"] + 1):
+            raise ValueError("seed_base shape %s" % (sb.shape,))
+        if sf is not None and sf.shape != (cfg["r"] * cfg["ny"] + 1, cfg["r"] * cfg["nx"] + 1):
+            raise ValueError("seed_fine shape %s" % (sf.shape,))
+        h = C.c_void_p()
+        rc = lib().dmr_create(C.byref(self._p), _ptr(sb), _ptr(sf),
+                              C.c_void_p(self.workspace.data_ptr()), nbytes,
+                              C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc:
+            raise DmrError("dmr_create failed: %s" % ERRORS.get(rc, rc))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dmr_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def step(self, n: int):
+        self._check(lib().dmr_step(self._h, int(n)), "dmr_step")
+
+    def regrid(self):
+        self._check(lib().dmr_regrid(self._h), "dmr_regrid")
+
     def get_device(self, field: str, level: int = 0):
         import torch
         r, c = self.dims(field, level)
@@ -220,12 +330,6 @@ class Sim:
             raise ValueError("size mismatch")
         self._check(lib().dmr_write_field(self._h, FIELD[field], level, _ptr(a),
                                           a.nbytes, 0), "dmr_write_field")
-
-    def time(self):
-        t = C.c_double()
-        st = C.c_int64()
-        self._check(lib().dmr_time(self._h, C.byref(t), C.byref(st)), "dmr_time")
-        return t.value, st.value
 
     def set_timing(self, on: bool):
         self._check(lib().dmr_set_timing(self._h, int(on)), "dmr_set_timing")

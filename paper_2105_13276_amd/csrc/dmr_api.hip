@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -368,43 +369,107 @@ void em_args_level(EMArgs* A, const Level& L, int src, int dst, const float* n,
   A->S = L.S; A->c1 = L.c1; A->a = L.a; A->kn = L.kn; A->cmur = L.cmur;
 }
 
+int stream_blocks_x(int NX) { return ((NX + 1 + 61) / 62 + kThreads / 64 - 1) / (kThreads / 64); }
+
+// argument blocks of the four per-step launches, for buffer parities c
+// (E/H/J) and nc (density); shared by the plain and the batched schedules
+void make_base_em(const dmr_sim* s, int c, int nc, EMArgs* A) {
+  const Level& C = s->L0;
+  const dmr_params& p = s->p;
+  *A = EMArgs{};
+  em_args_level(A, C, c, 1 - c, C.n[nc], C.acc);
+  A->L = 0; A->B = 0; A->R = p.nx; A->T = p.ny;
+  A->bc_x = p.bc_x; A->bc_y = p.bc_y;
+  A->is = p.tfsf_i;
+  A->seg = s->seg0;
+  A->nseg = stream_segments(p.ny, s->seg0);
+  A->nbx = stream_blocks_x(p.nx);
+}
+
+void incident_values(const dmr_sim* s, int64_t step, float* ey, float* hz) {
+  const Level& C = s->L0;
+  *ey = *hz = 0.f;
+  if (s->p.tfsf_i <= 0) return;
+  const double t = (double)step * C.dt, xs = s->p.tfsf_i * C.dx;
+  *ey = (float)ey_inc(s, xs, t);
+  *hz = (float)ey_inc(s, xs - 0.5 * C.dx, t + 0.5 * C.dt);
+}
+
+void make_fine_em(const dmr_sim* s, int m, int c, int nc, int ty, EMArgs* G) {
+  const Level &C = s->L0, &F = s->L1;
+  const dmr_params& p = s->p;
+  const int r = p.r;
+  *G = EMArgs{};
+  const int src = (m - 1) & 1, dst = m & 1;
+  em_args_level(G, F, src, dst, F.n[nc], F.acc);
+  G->L = r * s->ext[0]; G->B = r * s->ext[1];
+  G->R = r * s->ext[2]; G->T = r * s->ext[3];
+  G->cex0 = C.ex[c]; G->cey0 = C.ey[c];
+  G->cex1 = C.ex[1 - c]; G->cey1 = C.ey[1 - c];
+  G->cpitch = C.pitch;
+  G->frac = (float)m / (float)r;
+  G->gamma = (float)p.fine_filter;
+  if (m == r) {
+    G->restrict_on = 1;
+    G->chz = C.hz[1 - c]; G->cex = C.ex[1 - c]; G->cey = C.ey[1 - c];
+    G->cjx = C.jx[1 - c]; G->cjy = C.jy[1 - c];
+  }
+  G->nbx = (G->R - G->L + 1 + kTX - 1) / kTX;
+  (void)ty;
+}
+
+void make_base_cont(const dmr_sim* s, int nc, ContArgs* K) {
+  const Level& C = s->L0;
+  const dmr_params& p = s->p;
+  *K = ContArgs{};
+  K->n0 = C.n[nc]; K->n1 = C.n[1 - nc];
+  K->acc = C.acc; K->ring = C.ring; K->plane = C.plane; K->pitch = C.pitch;
+  K->L = 0; K->B = 0; K->R = p.nx; K->T = p.ny;
+  K->inv_spp = (float)(1.0 / C.spp);
+  K->dtn = (float)(C.spb * C.dt);
+  K->inv_dx2 = (float)(1.0 / (C.dx * C.dx));
+  K->eeff_p2 = (float)(s->eeff / (1.0e4 * p.p_torr * p.p_torr));
+  K->half_beta = (float)(0.5 * p.beta_ion);
+  K->att = (float)std::pow(p.ecr_over_p, p.beta_ion);
+  K->nuA = (float)(s->nu_m * p.A_ion);
+  K->inv_namb = (float)(1.0 / s->n_amb);
+  K->De = (float)s->De; K->Da = (float)s->Da;
+  K->d_const_mode = p.d_mode == DMR_D_CONST;
+  K->d_const = (float)p.d_const;
+  K->err = s->d_err;
+  K->nbx = (p.nx + 1 + kTX - 1) / kTX;
+}
+
+void make_fine_cont(const dmr_sim* s, int nc, ContArgs* G) {
+  const Level &C = s->L0, &F = s->L1;
+  const dmr_params& p = s->p;
+  make_base_cont(s, nc, G);
+  G->n0 = F.n[nc]; G->n1 = F.n[1 - nc];
+  G->acc = F.acc; G->ring = F.ring; G->plane = F.plane; G->pitch = F.pitch;
+  G->L = p.r * s->ext[0]; G->B = p.r * s->ext[1];
+  G->R = p.r * s->ext[2]; G->T = p.r * s->ext[3];
+  G->inv_spp = (float)(1.0 / F.spp);
+  G->dtn = (float)(F.spb * F.dt);
+  G->inv_dx2 = (float)(1.0 / (F.dx * F.dx));
+  G->cn1 = C.n[1 - nc]; G->cpitch = C.pitch;
+  G->nbx = (G->R - G->L + 1 + kTX - 1) / kTX;
+}
+
 int base_step(dmr_sim* s) {
-  Level &C = s->L0, &F = s->L1;
   const dmr_params& p = s->p;
   const int c = s->ccur;
   // coarse (or uniform) EM step n -> n+1
-  EMArgs A{};
-  em_args_level(&A, C, c, 1 - c, C.n[s->ncur], C.acc);
-  A.L = 0; A.B = 0; A.R = p.nx; A.T = p.ny;
-  A.bc_x = p.bc_x; A.bc_y = p.bc_y;
-  A.is = p.tfsf_i;
-  if (p.tfsf_i > 0) {
-    const double t = (double)s->step * C.dt, xs = p.tfsf_i * C.dx;
-    A.ey_src = (float)ey_inc(s, xs, t);
-    A.hz_src = (float)ey_inc(s, xs - 0.5 * C.dx, t + 0.5 * C.dt);
-  }
+  EMArgs A;
+  make_base_em(s, c, s->ncur, &A);
+  incident_values(s, s->step, &A.ey_src, &A.hz_src);
   ev_begin(s, 0);
   hipError_t e = launch_em_stream(A, s->seg0, s->depth0, s->st);
   ev_end(s);
   if (e != hipSuccess) return hipfail(s, e, "base EM launch");
   if (s->has_patch) {  // two fine substeps (Sec. III.C)
-    const int r = p.r;
-    for (int m = 1; m <= r; m++) {
-      EMArgs G{};
-      const int src = (m - 1) & 1, dst = m & 1;
-      em_args_level(&G, F, src, dst, F.n[s->ncur], F.acc);
-      G.L = r * s->ext[0]; G.B = r * s->ext[1];
-      G.R = r * s->ext[2]; G.T = r * s->ext[3];
-      G.cex0 = C.ex[c]; G.cey0 = C.ey[c];
-      G.cex1 = C.ex[1 - c]; G.cey1 = C.ey[1 - c];
-      G.cpitch = C.pitch;
-      G.frac = (float)m / (float)r;
-      G.gamma = (float)p.fine_filter;
-      if (m == r) {
-        G.restrict_on = 1;
-        G.chz = C.hz[1 - c]; G.cex = C.ex[1 - c]; G.cey = C.ey[1 - c];
-        G.cjx = C.jx[1 - c]; G.cjy = C.jy[1 - c];
-      }
+    for (int m = 1; m <= p.r; m++) {
+      EMArgs G;
+      make_fine_em(s, m, c, s->ncur, s->ty1, &G);
       ev_begin(s, 1);
       e = launch_em(G, true, s->ty1, s->st);
       ev_end(s);
@@ -413,41 +478,21 @@ int base_step(dmr_sim* s) {
   }
   s->ccur = 1 - c;
   s->step++;
-  if (p.continuity_on && s->step % C.spb == 0) {
+  if (p.continuity_on && s->step % s->L0.spb == 0) {
     const int slot = (int)(s->blocks % kRing);
     s->blocks++;
     const int update = s->blocks >= kRing;
-    ContArgs K{};
-    K.n0 = C.n[s->ncur]; K.n1 = C.n[1 - s->ncur];
-    K.acc = C.acc; K.ring = C.ring; K.plane = C.plane; K.pitch = C.pitch;
-    K.L = 0; K.B = 0; K.R = p.nx; K.T = p.ny;
+    ContArgs K;
+    make_base_cont(s, s->ncur, &K);
     K.slot = slot; K.update = update;
-    K.inv_spp = (float)(1.0 / C.spp);
-    K.dtn = (float)(C.spb * C.dt);
-    K.inv_dx2 = (float)(1.0 / (C.dx * C.dx));
-    K.eeff_p2 = (float)(s->eeff / (1.0e4 * p.p_torr * p.p_torr));
-    K.half_beta = (float)(0.5 * p.beta_ion);
-    K.att = (float)std::pow(p.ecr_over_p, p.beta_ion);
-    K.nuA = (float)(s->nu_m * p.A_ion);
-    K.inv_namb = (float)(1.0 / s->n_amb);
-    K.De = (float)s->De; K.Da = (float)s->Da;
-    K.d_const_mode = p.d_mode == DMR_D_CONST;
-    K.d_const = (float)p.d_const;
-    K.err = s->d_err;
     ev_begin(s, 2);
     e = launch_cont(K, false, s->st);
     ev_end(s);
     if (e != hipSuccess) return hipfail(s, e, "continuity launch");
     if (s->has_patch) {
-      ContArgs G = K;
-      G.n0 = F.n[s->ncur]; G.n1 = F.n[1 - s->ncur];
-      G.acc = F.acc; G.ring = F.ring; G.plane = F.plane; G.pitch = F.pitch;
-      G.L = p.r * s->ext[0]; G.B = p.r * s->ext[1];
-      G.R = p.r * s->ext[2]; G.T = p.r * s->ext[3];
-      G.inv_spp = (float)(1.0 / F.spp);
-      G.dtn = (float)(F.spb * F.dt);
-      G.inv_dx2 = (float)(1.0 / (F.dx * F.dx));
-      G.cn1 = C.n[1 - s->ncur]; G.cpitch = C.pitch;
+      ContArgs G;
+      make_fine_cont(s, s->ncur, &G);
+      G.slot = slot; G.update = update;
       ev_begin(s, 2);
       e = launch_cont(G, true, s->st);
       ev_end(s);
@@ -763,6 +808,488 @@ int dmr_get_timing(dmr_sim* s, double ms[4], int64_t launches[4]) {
 
 const char* dmr_last_error(const dmr_sim* s) {
   return s ? s->err.c_str() : "no handle";
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched form: many independent simulations advanced in lockstep.  Every
+// per-step launch (base EM, two fine substeps, continuity on both levels)
+// covers all instances through a block table; the steps of a steady regrid
+// interval are captured once in a HIP graph and replayed.  Growth tests run
+// per instance between intervals.
+// ===========================================================================
+struct dmr_batch {
+  std::vector<dmr_sim*> sims;
+  int count = 0;
+  hipStream_t user = nullptr, st = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  char* ws = nullptr;
+  std::string err;
+  EMArgs* d_em = nullptr;      // [4 parities][count]
+  EMArgs* d_fem = nullptr;     // [2 substeps][4 parities][count]
+  ContArgs* d_cont = nullptr;  // [2 density parities][count]
+  ContArgs* d_fcont = nullptr; // [2][count]
+  int2 *d_blk_base = nullptr, *d_blk_fine = nullptr, *d_blk_cont = nullptr,
+       *d_blk_fcont = nullptr;
+  int nblk_base = 0, nblk_fine = 0, nblk_cont = 0, nblk_fcont = 0;
+  float2* d_src = nullptr;
+  float2* h_src = nullptr;
+  int64_t src_base = -1;
+  int seg = 8, depth = 4, ty = 8;
+  bool use_graph = true, tuned = false, forced = false;
+  hipGraphExec_t gexec = nullptr;
+  bool graph_ok = false;
+  // host copies of the tables (kept alive until their upload completes)
+  std::vector<EMArgs> h_em, h_fem;
+  std::vector<ContArgs> h_cont, h_fcont;
+  std::vector<int2> h_blk_base, h_blk_fine, h_blk_cont, h_blk_fcont;
+};
+
+namespace {
+
+constexpr int kSegCand[] = {4, 8, 16, 32, 64};
+constexpr int kTyCand[] = {4, 8, 16};
+
+struct BatchLayout {
+  std::vector<size_t> off, size;
+  size_t off_em = 0, off_fem = 0, off_cont = 0, off_fcont = 0, off_blk_base = 0,
+         off_blk_fine = 0, off_blk_cont = 0, off_blk_fcont = 0, off_src = 0, total = 0;
+  size_t cap_base = 0, cap_fine = 0, cap_cont = 0, cap_fcont = 0;
+};
+
+int batch_layout(const dmr_params* p, int count, BatchLayout* L, std::string* why) {
+  if (!p || count < 1) { *why = "count must be >= 1"; return DMR_EINVAL; }
+  size_t off = 0;
+  for (int k = 0; k < count; k++) {
+    int rc = check_params(&p[k], why);
+    if (rc) return rc;
+    const double spp0 = p[0].cells_per_lambda / p[0].courant;
+    const double sppk = p[k].cells_per_lambda / p[k].courant;
+    if (std::fabs(spp0 - sppk) > 1e-9 || p[k].mode != p[0].mode ||
+        p[k].continuity_on != p[0].continuity_on ||
+        (p[k].mode == DMR_DYNAMIC && p[k].regrid_every != p[0].regrid_every)) {
+      *why = "instances must share steps per period, mode, continuity and regrid cadence";
+      return DMR_EINVAL;
+    }
+    const size_t b = layout_of(&p[k]).total;
+    L->off.push_back(off);
+    L->size.push_back(b);
+    off += align256(b);
+    const int nx = p[k].nx, ny = p[k].ny, r = refined(&p[k]) ? p[k].r : 1;
+    L->cap_base += (size_t)stream_blocks_x(nx) * stream_segments(ny, 4);
+    L->cap_cont += (size_t)((nx + 1 + kTX - 1) / kTX) * ((ny + 1 + 3) / 4);
+    if (refined(&p[k])) {
+      const size_t t = (size_t)((r * nx + 1 + kTX - 1) / kTX) * ((r * ny + 1 + 3) / 4);
+      L->cap_fine += t;
+      L->cap_fcont += t;
+    }
+  }
+  L->off_em = off;    off += align256(sizeof(EMArgs) * 4 * count);
+  L->off_fem = off;   off += align256(sizeof(EMArgs) * 8 * count);
+  L->off_cont = off;  off += align256(sizeof(ContArgs) * 2 * count);
+  L->off_fcont = off; off += align256(sizeof(ContArgs) * 2 * count);
+  L->off_blk_base = off;  off += align256(sizeof(int2) * std::max<size_t>(L->cap_base, 1));
+  L->off_blk_fine = off;  off += align256(sizeof(int2) * std::max<size_t>(L->cap_fine, 1));
+  L->off_blk_cont = off;  off += align256(sizeof(int2) * std::max<size_t>(L->cap_cont, 1));
+  L->off_blk_fcont = off; off += align256(sizeof(int2) * std::max<size_t>(L->cap_fcont, 1));
+  L->off_src = off;       off += align256(sizeof(float2) * kSrcSteps * count);
+  L->total = off;
+  return DMR_OK;
+}
+
+int bfail(dmr_batch* b, int code, const char* what) {
+  if (b) b->err = what;
+  return code;
+}
+
+// rebuild block tables and argument arrays for the current configuration,
+// parities and patches; uploads on the batch stream and waits
+int batch_tables(dmr_batch* b) {
+  const int n = b->count;
+  b->h_em.assign(4 * n, EMArgs{});
+  b->h_fem.assign(8 * n, EMArgs{});
+  b->h_cont.assign(2 * n, ContArgs{});
+  b->h_fcont.assign(2 * n, ContArgs{});
+  b->h_blk_base.clear(); b->h_blk_fine.clear();
+  b->h_blk_cont.clear(); b->h_blk_fcont.clear();
+  for (int k = 0; k < n; k++) {
+    dmr_sim* s = b->sims[k];
+    s->seg0 = b->seg;
+    s->depth0 = b->depth;
+    s->ty1 = b->ty;
+    for (int v = 0; v < 4; v++) {
+      make_base_em(s, v & 1, v >> 1, &b->h_em[v * n + k]);
+      if (s->has_patch)
+        for (int m = 1; m <= 2; m++)
+          make_fine_em(s, m, v & 1, v >> 1, b->ty, &b->h_fem[((m - 1) * 4 + v) * n + k]);
+    }
+    for (int nc = 0; nc < 2; nc++) {
+      make_base_cont(s, nc, &b->h_cont[nc * n + k]);
+      if (s->has_patch) make_fine_cont(s, nc, &b->h_fcont[nc * n + k]);
+    }
+    const EMArgs& A = b->h_em[k];
+    for (int t = 0; t < A.nbx * A.nseg; t++) b->h_blk_base.push_back(make_int2(k, t));
+    const ContArgs& K = b->h_cont[k];
+    const int cny = (K.T - K.B + 1 + 3) / 4;
+    for (int t = 0; t < K.nbx * cny; t++) b->h_blk_cont.push_back(make_int2(k, t));
+    if (s->has_patch) {
+      const EMArgs& G = b->h_fem[k];
+      const int fny = (G.T - G.B + 1 + b->ty - 1) / b->ty;
+      for (int t = 0; t < G.nbx * fny; t++) b->h_blk_fine.push_back(make_int2(k, t));
+      const ContArgs& H = b->h_fcont[k];
+      const int hny = (H.T - H.B + 1 + 3) / 4;
+      for (int t = 0; t < H.nbx * hny; t++) b->h_blk_fcont.push_back(make_int2(k, t));
+    }
+  }
+  b->nblk_base = (int)b->h_blk_base.size();
+  b->nblk_fine = (int)b->h_blk_fine.size();
+  b->nblk_cont = (int)b->h_blk_cont.size();
+  b->nblk_fcont = (int)b->h_blk_fcont.size();
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->st) : hipSuccess;
+  };
+  if (up(b->d_em, b->h_em.data(), b->h_em.size() * sizeof(EMArgs)) ||
+      up(b->d_fem, b->h_fem.data(), b->h_fem.size() * sizeof(EMArgs)) ||
+      up(b->d_cont, b->h_cont.data(), b->h_cont.size() * sizeof(ContArgs)) ||
+      up(b->d_fcont, b->h_fcont.data(), b->h_fcont.size() * sizeof(ContArgs)) ||
+      up(b->d_blk_base, b->h_blk_base.data(), b->h_blk_base.size() * sizeof(int2)) ||
+      up(b->d_blk_fine, b->h_blk_fine.data(), b->h_blk_fine.size() * sizeof(int2)) ||
+      up(b->d_blk_cont, b->h_blk_cont.data(), b->h_blk_cont.size() * sizeof(int2)) ||
+      up(b->d_blk_fcont, b->h_blk_fcont.data(), b->h_blk_fcont.size() * sizeof(int2)) ||
+      hipStreamSynchronize(b->st))
+    return bfail(b, DMR_EHIP, "batch table upload failed");
+  b->graph_ok = false;
+  return DMR_OK;
+}
+
+// incident values of steps [base, base + kSrcSteps) for every instance
+int batch_sources(dmr_batch* b, int64_t base) {
+  if (hipStreamSynchronize(b->st) != hipSuccess) return bfail(b, DMR_EHIP, "sync");
+  for (int k = 0; k < b->count; k++)
+    for (int q = 0; q < kSrcSteps; q++) {
+      float ey, hz;
+      incident_values(b->sims[k], base + q, &ey, &hz);
+      b->h_src[(size_t)k * kSrcSteps + q] = make_float2(ey, hz);
+    }
+  if (hipMemcpyAsync(b->d_src, b->h_src, sizeof(float2) * kSrcSteps * b->count,
+                     hipMemcpyHostToDevice, b->st) != hipSuccess)
+    return bfail(b, DMR_EHIP, "source upload failed");
+  b->src_base = base;
+  return DMR_OK;
+}
+
+// host bookkeeping of one base step (parities, counters), shared by the
+// eager and the graph paths; returns the continuity slot/update of the step
+void batch_advance(dmr_batch* b, int* slot, int* update) {
+  *slot = -1;
+  *update = 0;
+  for (dmr_sim* s : b->sims) {
+    s->ccur = 1 - s->ccur;
+    s->step++;
+    if (s->p.continuity_on && s->step % s->L0.spb == 0) {
+      *slot = (int)(s->blocks % kRing);
+      s->blocks++;
+      *update = s->blocks >= kRing;
+      if (*update) s->ncur = 1 - s->ncur;
+    }
+  }
+}
+
+// queue one base step of every instance (no growth test)
+int batch_launch_step(dmr_batch* b, hipEvent_t* tb, hipEvent_t* tf) {
+  const int n = b->count;
+  dmr_sim* s0 = b->sims[0];
+  const int v = s0->ccur + 2 * s0->ncur;
+  const int nc = s0->ncur;
+  const int k = (int)(s0->step - b->src_base);
+  if (tb) (void)hipEventRecord(tb[0], b->st);
+  hipError_t e = launch_em_stream_batch(b->d_em + v * n, b->d_blk_base, b->nblk_base,
+                                        b->d_src, k, b->depth, b->st);
+  if (tb) (void)hipEventRecord(tb[1], b->st);
+  if (e != hipSuccess) return bfail(b, DMR_EHIP, "batched base EM launch");
+  if (tf) (void)hipEventRecord(tf[0], b->st);
+  for (int m = 1; m <= 2 && b->nblk_fine; m++) {
+    e = launch_em_batch(b->d_fem + ((m - 1) * 4 + v) * n, b->d_blk_fine, b->nblk_fine,
+                        b->ty, b->st);
+    if (e != hipSuccess) return bfail(b, DMR_EHIP, "batched fine EM launch");
+  }
+  if (tf) (void)hipEventRecord(tf[1], b->st);
+  int slot, update;
+  batch_advance(b, &slot, &update);
+  if (slot >= 0) {
+    e = launch_cont_batch(b->d_cont + nc * n, b->d_blk_cont, b->nblk_cont, false, slot,
+                          update, b->st);
+    if (e == hipSuccess)
+      e = launch_cont_batch(b->d_fcont + nc * n, b->d_blk_fcont, b->nblk_fcont, true, slot,
+                            update, b->st);
+    if (e != hipSuccess) return bfail(b, DMR_EHIP, "batched continuity launch");
+  }
+  return DMR_OK;
+}
+
+int batch_regrid(dmr_batch* b) {
+  bool changed = false;
+  for (dmr_sim* s : b->sims) {
+    int old[4] = {s->ext[0], s->ext[1], s->ext[2], s->ext[3]};
+    const bool had = s->has_patch;
+    const int rc = regrid(s, false);
+    if (rc) return bfail(b, rc, s->err.c_str());
+    if (s->has_patch != had || memcmp(old, s->ext, sizeof(old))) changed = true;
+  }
+  return changed ? batch_tables(b) : DMR_OK;
+}
+
+// pick the streaming segment/depth and the fine tile height by timing real
+// steps (all candidates give bit-identical results)
+std::vector<std::pair<std::string, std::array<int, 3>>>& tune_cache() {
+  static std::vector<std::pair<std::string, std::array<int, 3>>> c;
+  return c;
+}
+
+std::string batch_key(const dmr_batch* b) {
+  std::string k;
+  for (const dmr_sim* s : b->sims) {
+    char buf[64];
+    snprintf(buf, sizeof(buf), "%dx%d:%d,%d,%d,%d;", s->p.nx, s->p.ny, s->ext[0], s->ext[1],
+             s->ext[2], s->ext[3]);
+    k += buf;
+  }
+  return k;
+}
+
+int batch_tune(dmr_batch* b, int64_t* used) {
+  *used = 0;
+  const std::string key = batch_key(b);
+  for (auto& kv : tune_cache())
+    if (kv.first == key) {
+      b->seg = kv.second[0]; b->depth = kv.second[1]; b->ty = kv.second[2];
+      b->tuned = true;
+      return batch_tables(b);
+    }
+  hipEvent_t tb[2], tf[2];
+  for (int q = 0; q < 2; q++) {
+    (void)hipEventCreate(&tb[q]);
+    (void)hipEventCreate(&tf[q]);
+  }
+  double best_b = 1e30, best_f = 1e30;
+  int bseg = b->seg, bdep = b->depth, bty = b->ty;
+  const int nseg = sizeof(kSegCand) / sizeof(int), nty = sizeof(kTyCand) / sizeof(int);
+  const int ncand = std::max(nseg, nty);
+  int rc = DMR_OK;
+  for (int c = 0; c < ncand && !rc; c++) {
+    b->seg = kSegCand[c % nseg];
+    b->depth = b->seg <= 8 ? 4 : 2;
+    b->ty = kTyCand[c % nty];
+    rc = batch_tables(b);
+    float tbase = 0.f, tfine = 0.f;
+    for (int rep = 0; rep < 2 && !rc; rep++) {  // two timed steps per candidate
+      if (b->sims[0]->step - b->src_base >= kSrcSteps) rc = batch_sources(b, b->sims[0]->step);
+      if (!rc) rc = batch_launch_step(b, tb, tf);
+      if (!rc) (*used)++;
+      if (!rc && hipStreamSynchronize(b->st) != hipSuccess) rc = DMR_EHIP;
+      float x = 0.f, y = 0.f;
+      (void)hipEventElapsedTime(&x, tb[0], tb[1]);
+      (void)hipEventElapsedTime(&y, tf[0], tf[1]);
+      tbase += x;
+      tfine += y;
+    }
+    if (c < nseg && tbase < best_b) { best_b = tbase; bseg = b->seg; bdep = b->depth; }
+    if (c < nty && tfine < best_f) { best_f = tfine; bty = b->ty; }
+  }
+  for (int q = 0; q < 2; q++) {
+    (void)hipEventDestroy(tb[q]);
+    (void)hipEventDestroy(tf[q]);
+  }
+  if (rc) return rc;
+  b->seg = bseg; b->depth = bdep; b->ty = bty;
+  b->tuned = true;
+  tune_cache().push_back({key, {bseg, bdep, bty}});
+  return batch_tables(b);
+}
+
+int batch_step(dmr_batch* b, int64_t n) {
+  dmr_sim* s0 = b->sims[0];
+  const dmr_params& p = s0->p;
+  const bool dyn = p.mode == DMR_DYNAMIC;
+  while (n > 0) {
+    const int64_t step = s0->step;
+    const int64_t base = step - step % kSrcSteps;
+    int rc = DMR_OK;
+    if (b->src_base != base) rc = batch_sources(b, base);
+    if (rc) return rc;
+    if (!b->tuned && !b->forced && step % kSrcSteps == 0 && n >= kSrcSteps &&
+        (!dyn || p.regrid_every >= kSrcSteps)) {
+      int64_t used = 0;
+      rc = batch_tune(b, &used);  // times real steps of the run
+      if (rc) return rc;
+      n -= used;
+      continue;
+    }
+    int64_t chunk = std::min<int64_t>(n, base + kSrcSteps - step);
+    if (dyn) chunk = std::min<int64_t>(chunk, p.regrid_every - step % p.regrid_every);
+    const bool steady = s0->blocks >= kRing || !p.continuity_on;
+    const bool whole = step % kSrcSteps == 0 && chunk == kSrcSteps &&
+                       (!dyn || p.regrid_every % kSrcSteps == 0);
+    if (b->use_graph && whole && steady) {
+      if (!b->graph_ok) {
+        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+          return bfail(b, DMR_EHIP, "graph capture begin");
+        for (int q = 0; q < kSrcSteps && !rc; q++) rc = batch_launch_step(b, nullptr, nullptr);
+        hipError_t e = hipStreamEndCapture(b->st, &g);
+        if (rc) return rc;
+        if (e != hipSuccess || hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0) != hipSuccess)
+          return bfail(b, DMR_EHIP, "graph capture");
+        (void)hipGraphDestroy(g);
+        b->graph_ok = true;
+        if (hipGraphLaunch(b->gexec, b->st) != hipSuccess) return bfail(b, DMR_EHIP, "graph launch");
+      } else {
+        if (hipGraphLaunch(b->gexec, b->st) != hipSuccess) return bfail(b, DMR_EHIP, "graph launch");
+        int slot, update;
+        for (int q = 0; q < kSrcSteps; q++) batch_advance(b, &slot, &update);
+      }
+    } else {
+      for (int64_t q = 0; q < chunk && !rc; q++) rc = batch_launch_step(b, nullptr, nullptr);
+      if (rc) return rc;
+    }
+    n -= chunk;
+    if (dyn && s0->step % p.regrid_every == 0) {
+      rc = batch_regrid(b);
+      if (rc) return rc;
+    }
+  }
+  return hipGetLastError() == hipSuccess ? DMR_OK : bfail(b, DMR_EHIP, "batch step");
+}
+
+}  // namespace
+
+extern "C" {
+
+int dmr_batch_workspace_bytes(const dmr_params* p, int count, size_t* bytes) {
+  BatchLayout L;
+  std::string why;
+  const int rc = batch_layout(p, count, &L, &why);
+  if (rc) return rc;
+  if (!bytes) return DMR_EINVAL;
+  *bytes = L.total;
+  return DMR_OK;
+}
+
+int dmr_batch_create(const dmr_params* p, int count, const double* const* seed_base,
+                     const double* const* seed_fine, void* d_workspace, size_t bytes,
+                     void* stream, dmr_batch** out) {
+  if (!out) return DMR_EINVAL;
+  *out = nullptr;
+  BatchLayout L;
+  std::string why;
+  int rc = batch_layout(p, count, &L, &why);
+  if (rc) {
+    fprintf(stderr, "dmr_batch_create: %s\n", why.c_str());
+    return rc;
+  }
+  if (!d_workspace || bytes < L.total) return DMR_ENOMEM;
+  dmr_batch* b = new (std::nothrow) dmr_batch();
+  if (!b) return DMR_ENOMEM;
+  b->count = count;
+  b->user = (hipStream_t)stream;
+  b->ws = (char*)d_workspace;
+  if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc((void**)&b->h_src, sizeof(float2) * kSrcSteps * count) != hipSuccess) {
+    dmr_batch_destroy(b);
+    return DMR_EHIP;
+  }
+  // the caller's earlier work (e.g. the workspace allocation) comes first
+  (void)hipEventRecord(b->ev_in, b->user);
+  (void)hipStreamWaitEvent(b->st, b->ev_in, 0);
+  for (int k = 0; k < count; k++) {
+    dmr_sim* s = nullptr;
+    rc = dmr_create(&p[k], seed_base ? seed_base[k] : nullptr,
+                    seed_fine ? seed_fine[k] : nullptr, b->ws + L.off[k], L.size[k], b->st, &s);
+    if (rc) {
+      dmr_batch_destroy(b);
+      return rc;
+    }
+    b->sims.push_back(s);
+  }
+  b->d_em = (EMArgs*)(b->ws + L.off_em);
+  b->d_fem = (EMArgs*)(b->ws + L.off_fem);
+  b->d_cont = (ContArgs*)(b->ws + L.off_cont);
+  b->d_fcont = (ContArgs*)(b->ws + L.off_fcont);
+  b->d_blk_base = (int2*)(b->ws + L.off_blk_base);
+  b->d_blk_fine = (int2*)(b->ws + L.off_blk_fine);
+  b->d_blk_cont = (int2*)(b->ws + L.off_blk_cont);
+  b->d_blk_fcont = (int2*)(b->ws + L.off_blk_fcont);
+  b->d_src = (float2*)(b->ws + L.off_src);
+  rc = batch_tables(b);
+  if (rc) {
+    fprintf(stderr, "dmr_batch_create: %s\n", b->err.c_str());
+    dmr_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return DMR_OK;
+}
+
+void dmr_batch_destroy(dmr_batch* b) {
+  if (!b) return;
+  if (b->st) (void)hipStreamSynchronize(b->st);
+  for (dmr_sim* s : b->sims) dmr_destroy(s);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->h_src) (void)hipHostFree(b->h_src);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->st) (void)hipStreamDestroy(b->st);
+  delete b;
+}
+
+int dmr_batch_step(dmr_batch* b, int64_t n) {
+  if (!b || n < 0) return DMR_EINVAL;
+  (void)hipEventRecord(b->ev_in, b->user);
+  (void)hipStreamWaitEvent(b->st, b->ev_in, 0);
+  const int rc = batch_step(b, n);
+  (void)hipEventRecord(b->ev_out, b->st);
+  (void)hipStreamWaitEvent(b->user, b->ev_out, 0);
+  return rc;
+}
+
+int dmr_batch_instance(dmr_batch* b, int k, dmr_sim** out) {
+  if (!b || !out || k < 0 || k >= b->count) return DMR_EINVAL;
+  *out = b->sims[k];
+  return DMR_OK;
+}
+
+int dmr_batch_sync(dmr_batch* b) {
+  if (!b) return DMR_EINVAL;
+  if (hipStreamSynchronize(b->st) != hipSuccess) return bfail(b, DMR_EHIP, "sync");
+  for (dmr_sim* s : b->sims) {
+    const int rc = dmr_sync(s);
+    if (rc) return bfail(b, rc, s->err.c_str());
+  }
+  return DMR_OK;
+}
+
+int dmr_batch_config(dmr_batch* b, int32_t cfg[4]) {
+  if (!b || !cfg) return DMR_EINVAL;
+  cfg[0] = b->seg; cfg[1] = b->depth; cfg[2] = b->ty; cfg[3] = b->use_graph;
+  return DMR_OK;
+}
+
+int dmr_batch_set_config(dmr_batch* b, const int32_t cfg[4]) {
+  if (!b || !cfg || cfg[0] < 2 || (cfg[1] != 2 && cfg[1] != 4) ||
+      (cfg[2] != 4 && cfg[2] != 8 && cfg[2] != 16))
+    return DMR_EINVAL;
+  b->seg = cfg[0]; b->depth = cfg[1]; b->ty = cfg[2]; b->use_graph = cfg[3] != 0;
+  b->forced = true;
+  return batch_tables(b);
+}
+
+const char* dmr_batch_last_error(const dmr_batch* b) {
+  return b ? b->err.c_str() : "no handle";
 }
 
 }  // extern "C"

@@ -10,6 +10,7 @@ constexpr int kTX = 64;        // tile width in nodes: one wavefront per row
 constexpr int kThreads = 256;  // threads per tile
 constexpr int kRing = 8;       // window blocks per period
 constexpr int kBcMur = 0;
+constexpr int kSrcSteps = 256;  // incident-value table length of the batched form
 
 struct EMArgs {
   const float *hz0, *ex0, *ey0, *jx0, *jy0;  // state at step n (read)
@@ -35,6 +36,8 @@ struct EMArgs {
   // fine level, last substep: coarse targets of the fine -> coarse transfer
   int restrict_on;
   float *chz, *cex, *cey, *cjx, *cjy;
+  // batched launches: tiles per row of tiles, and the streaming segments
+  int nbx, seg, nseg;
 };
 
 struct ContArgs {
@@ -57,6 +60,7 @@ struct ContArgs {
   int* err;        // 64 flags, set on non-finite values
   float* cn1;      // fine level: coarse density after its update
   int cpitch;
+  int nbx;         // batched launches: blocks per row of blocks
 };
 
 struct FlagArgs {
@@ -87,6 +91,13 @@ hipError_t launch_em(const EMArgs& A, bool fine, int ty, hipStream_t st);
 // base level, column-streaming kernel; seg = rows per segment (>= 2)
 hipError_t launch_em_stream(const EMArgs& A, int seg, int depth, hipStream_t st);
 int stream_segments(int NY, int seg);
+// batched forms: blk[b] = (instance, block index within the instance)
+hipError_t launch_em_stream_batch(const EMArgs* args, const int2* blk, int nblk,
+                                  const float2* src, int k, int depth, hipStream_t st);
+hipError_t launch_em_batch(const EMArgs* args, const int2* blk, int nblk, int ty,
+                           hipStream_t st);
+hipError_t launch_cont_batch(const ContArgs* args, const int2* blk, int nblk, bool fine,
+                             int slot, int update, hipStream_t st);
 hipError_t launch_cont(const ContArgs& A, bool fine, hipStream_t st);
 hipError_t launch_regrid_test(const FlagArgs& F, const ScanArgs& S, hipStream_t st);
 hipError_t launch_prolong(const ProlongArgs& A, hipStream_t st);

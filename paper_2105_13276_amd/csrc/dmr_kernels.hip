@@ -35,7 +35,7 @@ namespace dmr {
 //                 transfer of the coarse entities strictly inside the patch.
 // ---------------------------------------------------------------------------
 template <bool FINE, int TY>
-__global__ __launch_bounds__(kThreads) void k_em(EMArgs A) {
+__device__ __forceinline__ void em_tile(const EMArgs& A, int bx, int by) {
   constexpr int EW = kTX + 3, EH = TY + 3;  // old E
   constexpr int HW = kTX + 2, HH = TY + 2;  // new Hz
   constexpr int NW = kTX + 1, NH = TY + 1;  // new E
@@ -53,8 +53,8 @@ __global__ __launch_bounds__(kThreads) void k_em(EMArgs A) {
   __shared__ float rEx[RH][RW], rEy[RH][RW];
   __shared__ float qEx[QH][QW], qEy[QH][QW];
 
-  const int i0 = A.L + blockIdx.x * kTX;
-  const int j0 = A.B + blockIdx.y * TY;
+  const int i0 = A.L + bx * kTX;
+  const int j0 = A.B + by * TY;
   const int tid = threadIdx.x;
   const int L = A.L, R = A.R, B = A.B, T = A.T;
   const int pitch = A.pitch;
@@ -333,6 +333,21 @@ __global__ __launch_bounds__(kThreads) void k_em(EMArgs A) {
   }
 }
 
+template <bool FINE, int TY>
+__global__ __launch_bounds__(kThreads) void k_em(EMArgs A) {
+  em_tile<FINE, TY>(A, blockIdx.x, blockIdx.y);
+}
+
+// batched form: one launch over the tiles of many independent instances;
+// blk[b] = (instance, tile index within it)
+template <bool FINE, int TY>
+__global__ __launch_bounds__(kThreads) void k_em_batch(const EMArgs* __restrict__ args,
+                                                       const int2* __restrict__ blk) {
+  const int2 bi = blk[blockIdx.x];
+  const EMArgs& A = args[bi.x];
+  em_tile<FINE, TY>(A, bi.y % A.nbx, bi.y / A.nbx);
+}
+
 // ---------------------------------------------------------------------------
 // Window block close and continuity step (Eq. (4)), one thread per node of
 // the region [L..R] x [B..T].  ring[slot] <- acc / steps_per_period,
@@ -350,22 +365,23 @@ __device__ inline float d_eff(const ContArgs &A, float n) {
 }
 
 template <bool FINE>
-__global__ __launch_bounds__(kThreads) void k_cont(ContArgs A) {
-  const int i = A.L + blockIdx.x * kTX + (threadIdx.x % kTX);
-  const int j = A.B + blockIdx.y * (kThreads / kTX) + (threadIdx.x / kTX);
+__device__ __forceinline__ void cont_body(const ContArgs& A, int bx, int by, int slot,
+                                          int update) {
+  const int i = A.L + bx * kTX + (threadIdx.x % kTX);
+  const int j = A.B + by * (kThreads / kTX) + (threadIdx.x / kTX);
   if (i > A.R || j > A.T) return;
   const int pitch = A.pitch;
   const size_t o = (size_t)j * pitch + i;
   const float sv = A.acc[o] * A.inv_spp;
-  A.ring[(size_t)A.slot * A.plane + o] = sv;
+  A.ring[(size_t)slot * A.plane + o] = sv;
   A.acc[o] = 0.f;
-  if (!A.update) {
+  if (!update) {
     if (!isfinite(sv)) A.err[threadIdx.x & 63] = 1;
     return;
   }
   float e2 = 0.f;
   for (int s = 0; s < kRing; s++)
-    e2 += (s == A.slot) ? sv : A.ring[(size_t)s * A.plane + o];
+    e2 += (s == slot) ? sv : A.ring[(size_t)s * A.plane + o];
   float nn;
   if (FINE && (i == A.L || i == A.R || j == A.B || j == A.T)) {
     const int a = i >> 1, b = j >> 1, cp = A.cpitch;
@@ -390,6 +406,20 @@ __global__ __launch_bounds__(kThreads) void k_cont(ContArgs A) {
   }
   A.n1[o] = nn;
   if (!isfinite(nn) || !isfinite(e2)) A.err[threadIdx.x & 63] = 1;
+}
+
+template <bool FINE>
+__global__ __launch_bounds__(kThreads) void k_cont(ContArgs A) {
+  cont_body<FINE>(A, blockIdx.x, blockIdx.y, A.slot, A.update);
+}
+
+template <bool FINE>
+__global__ __launch_bounds__(kThreads) void k_cont_batch(const ContArgs* __restrict__ args,
+                                                         const int2* __restrict__ blk,
+                                                         int slot, int update) {
+  const int2 bi = blk[blockIdx.x];
+  const ContArgs& A = args[bi.x];
+  cont_body<FINE>(A, bi.y % A.nbx, bi.y / A.nbx, slot, update);
 }
 
 // ---------------------------------------------------------------------------
@@ -646,13 +676,13 @@ __device__ inline RowData load_row(const EMArgs& A, int i, int j) {
 }
 
 template <int DEPTH>
-__global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int nseg) {
+__device__ __forceinline__ void em_stream_body(const EMArgs& A, int bx, int k, int seg,
+                                               int nseg, float ey_src, float hz_src) {
   const int NX = A.R, NY = A.T;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int c0 = (blockIdx.x * (kThreads / 64) + wv) * 62;
+  const int c0 = (bx * (kThreads / 64) + wv) * 62;
   const int i = c0 - 2 + lane;
   const bool own = lane >= 2 && i <= NX;
-  const int k = blockIdx.y;
   const int j0 = k * seg;
   const int j1 = (k == nseg - 1) ? NY + 1 : j0 + seg;
   const bool wave_has_left = c0 - 2 <= 0 && 0 <= c0 + 61;   // column 0 in the wave
@@ -681,7 +711,7 @@ __global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int n
     float hzn = 0.f;
     if (exv && j < NY) {
       hzn = cur.hz - S * ((cur.ey1 - cur.ey) - (nxt.ex - cur.ex));
-      if (i == A.is - 1) hzn += S * A.ey_src;
+      if (i == A.is - 1) hzn += S * ey_src;
       if (store && own) A.hz1[o] = hzn;
     }
     const float hzl = __shfl_up(hzn, 1, 64);  // Hz(i-1, j)
@@ -713,7 +743,7 @@ __global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int n
     const float kapy = kn * (0.5f * (cur.n + nxt.n));
     if (eyc && j < NY && i > 0 && i < NX) {
       float curl = -S * (hzn - hzl);
-      if (i == A.is) curl += S * A.hz_src;
+      if (i == A.is) curl += S * hz_src;
       eyn = ((1.f - kapy) * cur.ey + curl - c1 * cur.jy) * __builtin_amdgcn_rcpf(1.f + kapy);
     }
     if (j < NY && (wave_has_left || wave_has_right)) {
@@ -773,6 +803,24 @@ __global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int n
   }
 }
 
+template <int DEPTH>
+__global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int nseg) {
+  em_stream_body<DEPTH>(A, blockIdx.x, blockIdx.y, seg, nseg, A.ey_src, A.hz_src);
+}
+
+// batched form; the incident values of step k of the current interval come
+// from src[instance * kSrcSteps + k]
+template <int DEPTH>
+__global__ __launch_bounds__(kThreads) void k_em_stream_batch(const EMArgs* __restrict__ args,
+                                                              const int2* __restrict__ blk,
+                                                              const float2* __restrict__ src,
+                                                              int k) {
+  const int2 bi = blk[blockIdx.x];
+  const EMArgs& A = args[bi.x];
+  const float2 sv = src[(size_t)bi.x * kSrcSteps + k];
+  em_stream_body<DEPTH>(A, bi.y % A.nbx, bi.y / A.nbx, A.seg, A.nseg, sv.x, sv.y);
+}
+
 // ---- host-side launchers ----------------------------------------------------
 template <bool FINE>
 static hipError_t launch_em_t(const EMArgs& A, int ty, hipStream_t st) {
@@ -800,6 +848,35 @@ static hipError_t launch_em_t(const EMArgs& A, int ty, hipStream_t st) {
 
 hipError_t launch_em(const EMArgs& A, bool fine, int ty, hipStream_t st) {
   return fine ? launch_em_t<true>(A, ty, st) : launch_em_t<false>(A, ty, st);
+}
+
+hipError_t launch_em_stream_batch(const EMArgs* args, const int2* blk, int nblk,
+                                  const float2* src, int k, int depth, hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  if (depth >= 4)
+    hipLaunchKernelGGL(k_em_stream_batch<4>, dim3(nblk), dim3(kThreads), 0, st, args, blk, src, k);
+  else
+    hipLaunchKernelGGL(k_em_stream_batch<2>, dim3(nblk), dim3(kThreads), 0, st, args, blk, src, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_em_batch(const EMArgs* args, const int2* blk, int nblk, int ty,
+                           hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  switch (ty) {
+  case 4: hipLaunchKernelGGL((k_em_batch<true, 4>), dim3(nblk), dim3(kThreads), 0, st, args, blk); break;
+  case 8: hipLaunchKernelGGL((k_em_batch<true, 8>), dim3(nblk), dim3(kThreads), 0, st, args, blk); break;
+  default: hipLaunchKernelGGL((k_em_batch<true, 16>), dim3(nblk), dim3(kThreads), 0, st, args, blk); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cont_batch(const ContArgs* args, const int2* blk, int nblk, bool fine,
+                             int slot, int update, hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  if (fine) hipLaunchKernelGGL(k_cont_batch<true>, dim3(nblk), dim3(kThreads), 0, st, args, blk, slot, update);
+  else hipLaunchKernelGGL(k_cont_batch<false>, dim3(nblk), dim3(kThreads), 0, st, args, blk, slot, update);
+  return hipGetLastError();
 }
 
 int stream_segments(int NY, int seg) {

@@ -149,3 +149,22 @@ def config2_seed_layout(cfg, rng_seed=2105):
         peaks.append(10.0 ** lp)
         centres.append((x, y))
     return centres, peaks
+
+
+def config3_instance(i, periods=200):
+    """Instance i of the batched workload: numpy PCG64 seed 13276+i, drawing
+    E_rms/E_bd ~ U(1, 2), p ~ U(100, 760) Torr, f ~ {35, 110, 170} GHz and the
+    coarse side ~ {256, 512, 1024} (grid side x side/2 at lambda/32), in that
+    order; seed as in config 0 (centred Gaussian, 1e17, sigma = lambda/20)."""
+    g = np.random.Generator(np.random.PCG64(13276 + i))
+    ratio = g.uniform(1.0, 2.0)
+    p = g.uniform(100.0, 760.0)
+    f = [35e9, 110e9, 170e9][int(g.integers(0, 3))]
+    side = [256, 512, 1024][int(g.integers(0, 3))]
+    return make(side, side // 2, 32, "dynamic", periods, erms_over_ebd=ratio,
+                p_torr=p, freq_hz=f, L_amb=C0 / f / 20.0)
+
+
+def config3(count=64, periods=200):
+    cfgs = [config3_instance(i, periods) for i in range(count)]
+    return cfgs, [seeds(c) for c in cfgs]

@@ -1,0 +1,77 @@
+"""Batched form: every instance of one batched run equals its own plain run
+bit for bit, whatever launch shape the batch uses (segment rows, load depth,
+fine tile rows, graph replay or not); and one instance checked against the
+FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2105_13276_amd import binding as B
+from paper_2105_13276_amd import workloads as W
+
+from gpu_helpers import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("hz", "ex", "ey", "jx", "jy", "n", "acc", "ring")
+
+
+def _mixed(count=6, periods=12):
+    cfgs, seeds = W.config3(count, periods)
+    # smaller grids than the benchmark's so the plain runs stay quick
+    out_c, out_s = [], []
+    for k, c in enumerate(cfgs):
+        side = [128, 192, 256][k % 3]
+        c2 = W.make(side, side // 2, 32, "dynamic", periods, erms_over_ebd=c["erms_over_ebd"],
+                    p_torr=c["p_torr"], freq_hz=c["freq_hz"], L_amb=c["L_amb"])
+        out_c.append(c2)
+        out_s.append(W.seeds(c2))
+    return out_c, out_s
+
+
+def _same(a, b):
+    for lv in (0, 1):
+        for f in FIELDS:
+            x, y = a.get(f, lv), b.get(f, lv)
+            assert x.shape == y.shape and np.array_equal(x, y), (lv, f)
+
+
+def test_batch_equals_plain_runs():
+    cfgs, seeds = _mixed()
+    steps = cfgs[0]["steps"]
+    bt = B.Batch(cfgs, seeds)
+    bt.step(steps)            # tunes on real steps, then replays graphs
+    bt.sync()
+    print("batch config", bt.config(), flush=True)
+    for k, (c, s) in enumerate(zip(cfgs, seeds)):
+        g = B.Sim(c, *s)
+        g.step(steps)
+        inst = bt.instances[k]
+        assert inst.time()[1] == steps
+        assert inst.patch() == g.patch()
+        _same(inst, g)
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4, 0), (32, 2, 16, 1), (8, 4, 8, 1)])
+def test_batch_launch_shape_invariance(shape):
+    cfgs, seeds = _mixed(count=4, periods=8)
+    steps = cfgs[0]["steps"]
+    ref = B.Batch(cfgs, seeds)
+    ref.set_config(16, 2, 4, 0)
+    ref.step(steps)
+    bt = B.Batch(cfgs, seeds)
+    bt.set_config(*shape)
+    bt.step(steps)
+    for k in range(len(cfgs)):
+        _same(bt.instances[k], ref.instances[k])
+
+
+def test_batch_instance_vs_oracle():
+    cfgs, seeds = _mixed(count=3, periods=12)
+    bt = B.Batch(cfgs, seeds)
+    bt.step(cfgs[0]["steps"])
+    k = 1
+    o = O.Sim(cfgs[k], *seeds[k])
+    o.step(cfgs[k]["steps"])
+    assert bt.instances[k].patch() == o.patch()
+    assert_parity(bt.instances[k], o, O.derived(cfgs[k])["n_c"], tag="batch[1]")
