@@ -18,6 +18,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",
     "--offload-arch=" + ARCH,
     "-fno-gpu-flush-denormals-to-zero",
+    # contract only a*b+c written in one expression, so that every
+    # instantiation of a kernel body rounds identically
+    "-ffp-contract=on",
     # packed fp32 instructions stay off (see the design notes)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
