@@ -21,7 +21,7 @@ FLAGS = [
     # contract only a*b+c written in one expression, so that every
     # instantiation of a kernel body rounds identically
     "-ffp-contract=on",
-    # packed fp32 instructions stay off (see the design notes)
+    # keep the compiler from emitting packed fp32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
