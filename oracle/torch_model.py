@@ -9,8 +9,12 @@ E0, the ionisation coefficients A and beta and the coarse seed density.
 The forward is checked against the C oracle (test_oracle_adjoint.py); the
 gradients against central finite differences of the C oracle.
 
-Scope: uniform runs, and refined runs whose patch is fixed after t = 0 (the
-fine seed is the Eq. (5a) prolongation of the coarse seed).
+Scope: uniform runs and refined runs.  The patch extents over time are
+given (the regrid decisions are integer and have no derivative): the patch
+present at t = 0 and a schedule of growths, each applied after the base step
+that ends on a regrid point, as the forward run decided them.  The fine seed
+and every newly covered fine entity are the Eq. (5a) prolongation of the
+coarse data (Sec. III.D).
 """
 from __future__ import annotations
 
@@ -118,7 +122,9 @@ def _bilin(arr, U4, V4):
 class Model:
     """One run with parameters (scale of E0, A, beta) and a coarse seed."""
 
-    def __init__(self, cfg, ext=None):
+    def __init__(self, cfg, ext=None, growth=None):
+        """ext: patch at t = 0 (coarse cells I0, J0, I1, J1) or None;
+        growth: {base steps completed: new ext} for the growths of the run."""
         assert cfg["mode"] in ("uniform", "static", "dynamic")
         assert cfg["bc_x"] == "mur" and cfg["bc_y"] == "mur"
         self.cfg = cfg
@@ -129,8 +135,16 @@ class Model:
         self.ext = tuple(ext) if (self.refined and ext is not None) else None
         if self.ext is not None and self.ext[2] <= self.ext[0]:
             self.ext = None
-        if self.ext is not None:
-            self.L1 = Level(d, d["dx"] / 2, d["dt"] / 2, 2 * d["spp"])
+        self.growth = {int(k): tuple(v) for k, v in (growth or {}).items()} if self.refined else {}
+        self.L1 = Level(d, d["dx"] / 2, d["dt"] / 2, 2 * d["spp"])
+
+    def ext_at(self, k):
+        """Patch extents during base step k (after the growths of steps <= k)."""
+        e = self.ext
+        for q in sorted(self.growth):
+            if q <= k:
+                e = self.growth[q]
+        return e
 
     # ---- ionisation and diffusion (Eq. (4), Sec. II.A) ------------------
     def nu(self, e2, A, beta):
@@ -203,11 +217,11 @@ class Model:
         out.update(hz=hz, ex=ex_n, ey=ey_n, jx=jx_n, jy=jy_n, acc=st["acc"] + _node_e2(ex_n, ey_n))
         return out
 
-    def em_fine(self, fs, ex_old, ey_old, ex_new, ey_new, m, gamma):
+    def em_fine(self, fs, ex_old, ey_old, ex_new, ey_new, m, gamma, ext):
         """One fine substep; coarse E before/after the coarse step for the
         boundary (Eq. (5b))."""
         L = self.L1
-        I0, J0, I1, J1 = self.ext
+        I0, J0, I1, J1 = ext
         hz, ex, ey, jx, jy, n = fs["hz"], fs["ex"], fs["ey"], fs["jx"], fs["jy"], fs["n"]
         if gamma > 0:
             dx_ = gamma * _lap_rep(_lap_rep(ex))
@@ -256,8 +270,8 @@ class Model:
         out.update(hz=hz, ex=ex_n, ey=ey_n, jx=jx_n, jy=jy_n, acc=fs["acc"] + _node_e2(ex_n, ey_n))
         return out
 
-    def restrict(self, cs, hz1, fs):
-        I0, J0, I1, J1 = self.ext
+    def restrict(self, cs, hz1, fs, ext):
+        I0, J0, I1, J1 = ext
         h = 0.5 * (hz1 + fs["hz"])
         hr = 0.25 * (h[0::2, 0::2] + h[0::2, 1::2] + h[1::2, 0::2] + h[1::2, 1::2])
         hz = cs["hz"].clone()
@@ -271,7 +285,7 @@ class Model:
         out.update(hz=hz, ex=ex, jx=jx, ey=ey, jy=jy)
         return out
 
-    def sync(self, cs, fs, blocks, A, beta):
+    def sync(self, cs, fs, blocks, A, beta, ext):
         """Window block close, continuity on both levels, density transfers."""
         slot = blocks % 8
 
@@ -293,7 +307,7 @@ class Model:
         if fs is not None:
             fs = dict(fs)
             nf = self.continuity(self.L1, fs["n"], fs["ring"].sum(0), A, beta, True)
-            I0, J0, I1, J1 = self.ext
+            I0, J0, I1, J1 = ext
             nc = cs["n"]
             # boundary nodes from the new coarse density (copy / mean)
             edge = nc[J0:J1 + 1, I0:I1 + 1]
@@ -320,18 +334,64 @@ class Model:
                   jy=z(ny, nx + 1), n=seed, acc=z(ny + 1, nx + 1),
                   ring=torch.zeros(8, ny + 1, nx + 1, dtype=torch.float64))
         fs = None
-        if self.ext is not None:
-            I0, J0, I1, J1 = self.ext
-            fw, fh = 2 * (I1 - I0), 2 * (J1 - J0)
-            P = torch.arange(fw + 1) + 2 * I0
-            Q = torch.arange(fh + 1) + 2 * J0
-            U4 = (2 * P)[None, :].expand(fh + 1, -1)
-            V4 = (2 * Q)[:, None].expand(-1, fw + 1)
-            nf = _bilin(seed, U4, V4)   # Eq. (5a): fine seed from coarse seed
-            fs = dict(hz=z(fh, fw), ex=z(fh + 1, fw), ey=z(fh, fw + 1), jx=z(fh + 1, fw),
-                      jy=z(fh, fw + 1), n=nf, acc=z(fh + 1, fw + 1),
-                      ring=torch.zeros(8, fh + 1, fw + 1, dtype=torch.float64))
+        if self.ext is not None:   # Eq. (5a): fine seed from the coarse seed
+            fs = self.grow(cs, None, cs["hz"], None, self.ext)
         return cs, fs
+
+    def grow(self, cs, fs, hz_prev, old, new):
+        """New patch `new`: entities of the old patch keep their values, the
+        others are the Eq. (5a) bilinear prolongation of the coarse data at
+        the current coarse time; Hz at 5/4 of the way from the coarse
+        Hz^{n-1/2} (hz_prev) to Hz^{n+1/2}, where fine Hz lives."""
+        I0, J0, I1, J1 = new
+        fw, fh = 2 * (I1 - I0), 2 * (J1 - J0)
+        P = torch.arange(fw + 1) + 2 * I0
+        Q = torch.arange(fh + 1) + 2 * J0
+
+        def grid(rows, cols, du, dv):
+            # quarter-unit positions: 2P (+du) across, 2Q (+dv) up
+            U4 = (2 * P[:cols] + du)[None, :].expand(rows, -1)
+            V4 = (2 * Q[:rows] + dv)[:, None].expand(-1, cols)
+            return U4, V4
+
+        def keep(rows, cols, hx, hy):
+            m = torch.zeros(rows, cols, dtype=torch.bool)
+            if fs is None:
+                return m, None
+            oI0, oJ0, oI1, oJ1 = old
+            pp, qq = P[:cols], Q[:rows]
+            inx = (pp >= 2 * oI0) & (pp <= 2 * oI1 - hx)
+            iny = (qq >= 2 * oJ0) & (qq <= 2 * oJ1 - hy)
+            m = iny[:, None] & inx[None, :]
+            return m, (2 * (oI0 - I0), 2 * (oJ0 - J0))
+
+        def place(new_val, key, hx, hy):
+            rows, cols = new_val.shape[-2:]
+            m, off = keep(rows, cols, hx, hy)
+            if off is None:
+                return new_val
+            old_val = fs[key]
+            pad = torch.zeros_like(new_val)
+            r0, c0 = off[1], off[0]
+            pad[..., r0:r0 + old_val.shape[-2], c0:c0 + old_val.shape[-1]] = old_val
+            return torch.where(m, pad, new_val)
+
+        out = {}
+        U, V = grid(fh, fw, -1, -1)
+        h = -0.25 * _bilin(hz_prev, U, V) + 1.25 * _bilin(cs["hz"], U, V)
+        out["hz"] = place(h, "hz", 1, 1)
+        U, V = grid(fh + 1, fw, -1, 0)
+        out["ex"] = place(_bilin(cs["ex"], U, V), "ex", 1, 0)
+        out["jx"] = place(_bilin(cs["jx"], U, V), "jx", 1, 0)
+        U, V = grid(fh, fw + 1, 0, -1)
+        out["ey"] = place(_bilin(cs["ey"], U, V), "ey", 0, 1)
+        out["jy"] = place(_bilin(cs["jy"], U, V), "jy", 0, 1)
+        U, V = grid(fh + 1, fw + 1, 0, 0)
+        out["n"] = place(_bilin(cs["n"], U, V), "n", 0, 0)
+        out["acc"] = place(_bilin(cs["acc"], U, V), "acc", 0, 0)
+        out["ring"] = place(torch.stack([_bilin(cs["ring"][q], U, V) for q in range(8)]),
+                            "ring", 0, 0)
+        return out
 
     # ---- run ---------------------------------------------------------------
     def run(self, seed, e0_scale, A, beta, steps, seg=45, grad=True):
@@ -348,16 +408,21 @@ class Model:
 
         def segment(k0, k1, blocks, *flat):
             c = dict(zip(keys, flat[:8]))
-            f = dict(zip(keys, flat[8:])) if fs is not None else None
+            f = dict(zip(keys, flat[8:])) if len(flat) > 8 else None
+            ext = self.ext_at(k0)
             for k in range(k0, k1):
-                ex_old, ey_old = c["ex"], c["ey"]
+                ex_old, ey_old, hz_prev = c["ex"], c["ey"], c["hz"]
                 c = self.em_base(c, E0 * ey_u[k], E0 * hz_u[k])
                 if f is not None:
-                    f1 = self.em_fine(f, ex_old, ey_old, c["ex"], c["ey"], 1, gamma)
-                    f = self.em_fine(f1, ex_old, ey_old, c["ex"], c["ey"], 2, gamma)
-                    c = self.restrict(c, f1["hz"], f)
+                    f1 = self.em_fine(f, ex_old, ey_old, c["ex"], c["ey"], 1, gamma, ext)
+                    f = self.em_fine(f1, ex_old, ey_old, c["ex"], c["ey"], 2, gamma, ext)
+                    c = self.restrict(c, f1["hz"], f, ext)
                 if self.cfg["continuity_on"] and (k + 1) % self.L0.spb == 0:
-                    c, f, blocks = self.sync(c, f, blocks, A, beta)
+                    c, f, blocks = self.sync(c, f, blocks, A, beta, ext)
+                if (k + 1) in self.growth:
+                    new = self.growth[k + 1]
+                    f = self.grow(c, f, hz_prev, ext, new)
+                    ext = new
             out = [c[k] for k in keys] + ([f[k] for k in keys] if f is not None else [])
             return tuple(out)
 
