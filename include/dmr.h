@@ -177,6 +177,56 @@ int dmr_get_timing(dmr_sim *s, double ms[4], int64_t launches[4]);
 /* Text of the last error on this handle (never NULL). */
 const char *dmr_last_error(const dmr_sim *s);
 
+/* ---- adjoint (reverse mode) ----------------------------------------------
+ * Gradients of a linear functional of the final density,
+ *   F = sum_nodes w_c n_c(t_final) + sum_nodes w_f n_f(t_final)
+ * (e.g. the integral of n over a window: w = dx^2 on the window's nodes),
+ * with respect to the incident amplitude E0 (Sec. II.C), the ionisation
+ * coefficients A and beta of nu_i in Eq. (4), and the seed density, through
+ * the whole refined update (Eqs. (1)-(5), Sec. III): the exact discrete
+ * adjoint of the float32 forward, in float32 with float64 accumulation of
+ * the scalar gradients.  The patch layout of the recorded run (its extents
+ * at t = 0 and each growth) is held fixed: growth decisions are integer and
+ * have no derivative, the Eq. (5a) prolongations they trigger are
+ * differentiated.  Checkpoints every ckpt_every steps, recomputation of one
+ * segment at a time (sqrt(N) checkpointing for ckpt_every ~ sqrt(steps)).
+ *
+ * Tape: caller-owned device memory (256-byte aligned) of
+ * dmr_adjoint_tape_bytes; it holds the checkpoints, one segment of stored
+ * forward values and the adjoint state, and must stay untouched between
+ * dmr_forward_record and dmr_backward. */
+int dmr_adjoint_tape_bytes(const dmr_params *p, int64_t steps, int ckpt_every,
+                           size_t *bytes);
+
+/* Advance a fresh handle (t = 0) by `steps` base steps exactly as dmr_step
+ * does, recording checkpoints and the patch history into the tape.
+ * EINVAL if the handle has already stepped; ENOMEM if the tape is small. */
+int dmr_forward_record(dmr_sim *s, int64_t steps, int ckpt_every, void *d_tape,
+                       size_t bytes);
+
+/* Reverse sweep over the recorded run.
+ *   d_w_coarse  device float32 weights on the base nodes [ny+1][nx+1]
+ *   d_w_fine    device float32 weights on the full-domain fine nodes
+ *               [r*ny+1][r*nx+1] (entries outside the final patch unused),
+ *               or NULL
+ *   d_grad_seed       out, device float32 [ny+1][nx+1]: dF/d(base seed),
+ *                     through the Eq. (5a) fine seed when the t = 0 patch
+ *                     interpolated it; may be NULL
+ *   d_grad_seed_fine  out, device float32 [r*ny+1][r*nx+1]: dF/d(fine
+ *                     seed) when dmr_create was given one (else zeros); may
+ *                     be NULL
+ *   grad        out, host: dF/dE0 (per V/m of peak amplitude), dF/dA,
+ *               dF/dbeta
+ * The handle is left at t_final, as after the record.  Synchronises. */
+int dmr_backward(dmr_sim *s, const void *d_tape, const float *d_w_coarse,
+                 const float *d_w_fine, float *d_grad_seed, float *d_grad_seed_fine,
+                 double grad[3]);
+
+/* sum over the nodes of a level (fine: full-domain grid) of w * n, with w
+ * device float32 [rows][cols] of that grid; float64 sum in a fixed order.
+ * Synchronises. */
+int dmr_weighted_sum(dmr_sim *s, int level, const float *d_w, double *out);
+
 /* ---- batched form -------------------------------------------------------
  * count independent simulations (grid sizes and physical parameters may
  * differ; steps per period, mode, continuity switch and regrid cadence must

@@ -1,0 +1,51 @@
+"""torch.autograd.Function over the library's recorded forward and adjoint.
+
+WindowDensity.apply(seed, e0_scale, A, beta, cfg, weights, steps, ckpt_every)
+returns F = sum_nodes w n(t_final) (float64 scalar tensor) of a refined run
+started from the base-level seed density; its backward calls the
+library's hand-written adjoint kernels (dmr_backward) and returns dF/dseed,
+dF/de0_scale (the incident amplitude is e0_scale times the one cfg gives),
+dF/dA and dF/dbeta.  Every step of both sweeps runs in libdmr.so.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+class WindowDensity(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, seed, e0_scale, A, beta, cfg, weights, steps, ckpt_every=45,
+                device="cuda:0"):
+        run = dict(cfg)
+        run["erms_over_ebd"] = float(cfg["erms_over_ebd"]) * float(e0_scale)
+        run["A_ion"] = float(A)
+        run["beta_ion"] = float(beta)
+        sim = B.Sim(run, seed.detach().to("cpu", torch.float64).numpy(), None, device=device)
+        sim.record(int(steps), int(ckpt_every))
+        F = sim.weighted_sum(weights, 0)
+        ctx.sim, ctx.weights = sim, weights
+        ctx.seed_dtype, ctx.seed_device = seed.dtype, seed.device
+        # E0 of this run per unit e0_scale
+        ctx.e0_unit = e0_of(cfg)
+        return torch.tensor(F, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gF):
+        g = ctx.sim.backward(ctx.weights)
+        s = float(gF)
+        gseed = (g["seed"].to(torch.float64) * s).to(ctx.seed_device, ctx.seed_dtype)
+        f64 = lambda v: torch.tensor(v * s, dtype=torch.float64)
+        return (gseed, f64(g["E0"] * ctx.e0_unit), f64(g["A"]), f64(g["beta"]),
+                None, None, None, None, None)
+
+
+def e0_of(cfg) -> float:
+    """Peak incident amplitude (V/m) of cfg: sqrt(2) E_rms with
+    E_rms = ratio * E_cr sqrt(1 + w^2/nu_m^2) (Sec. II.A, II.C)."""
+    w = 2 * np.pi * cfg["freq_hz"]
+    num = 5.3e9 * cfg["p_torr"]
+    ecr = cfg["ecr_over_p"] * 100.0 * cfg["p_torr"]
+    return float(np.sqrt(2.0) * cfg["erms_over_ebd"] * ecr * np.sqrt(1.0 + (w / num) ** 2))

@@ -27,7 +27,9 @@ SYMBOLS = ["dmr_workspace_bytes", "dmr_create", "dmr_destroy", "dmr_step",
            "dmr_set_timing", "dmr_get_timing", "dmr_last_error",
            "dmr_batch_workspace_bytes", "dmr_batch_create", "dmr_batch_step",
            "dmr_batch_instance", "dmr_batch_sync", "dmr_batch_config",
-           "dmr_batch_set_config", "dmr_batch_destroy", "dmr_batch_last_error"]
+           "dmr_batch_set_config", "dmr_batch_destroy", "dmr_batch_last_error",
+           "dmr_adjoint_tape_bytes", "dmr_forward_record", "dmr_backward",
+           "dmr_weighted_sum"]
 
 
 class DmrParams(C.Structure):
@@ -98,6 +100,10 @@ def lib():
         L.dmr_batch_destroy.restype = None
         L.dmr_batch_last_error.argtypes = [V]
         L.dmr_batch_last_error.restype = C.c_char_p
+        L.dmr_adjoint_tape_bytes.argtypes = [P(DmrParams), C.c_int64, C.c_int, P(C.c_size_t)]
+        L.dmr_forward_record.argtypes = [V, C.c_int64, C.c_int, V, C.c_size_t]
+        L.dmr_backward.argtypes = [V, V, V, V, V, V, P(C.c_double)]
+        L.dmr_weighted_sum.argtypes = [V, C.c_int, V, P(C.c_double)]
         _lib = L
     return _lib
 
@@ -333,6 +339,56 @@ class Sim(_Handle):
 
     def set_timing(self, on: bool):
         self._check(lib().dmr_set_timing(self._h, int(on)), "dmr_set_timing")
+
+    # ---- adjoint -----------------------------------------------------------
+    def _dev_f32(self, a):
+        import torch
+        return torch.as_tensor(np.asarray(a, np.float32) if not torch.is_tensor(a) else a,
+                               dtype=torch.float32, device=self.device).contiguous()
+
+    def record(self, steps: int, ckpt_every: int = 45):
+        """Advance `steps` base steps from t = 0, recording for backward()."""
+        import torch
+        n = C.c_size_t()
+        rc = lib().dmr_adjoint_tape_bytes(C.byref(self._p), int(steps), int(ckpt_every),
+                                          C.byref(n))
+        if rc:
+            raise DmrError("dmr_adjoint_tape_bytes: %s" % ERRORS.get(rc, rc))
+        with torch.cuda.device(self.device):
+            self.tape = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        self._check(lib().dmr_forward_record(self._h, int(steps), int(ckpt_every),
+                                             C.c_void_p(self.tape.data_ptr()), n.value),
+                    "dmr_forward_record")
+
+    def weighted_sum(self, w, level: int = 0) -> float:
+        """sum of w * n over the nodes of a level (fine: full-domain grid)."""
+        wd = self._dev_f32(w)
+        out = C.c_double()
+        self._check(lib().dmr_weighted_sum(self._h, level, C.c_void_p(wd.data_ptr()),
+                                           C.byref(out)), "dmr_weighted_sum")
+        return out.value
+
+    def backward(self, w_coarse, w_fine=None):
+        """Gradients of F = sum w_c n_c + sum w_f n_f at the recorded t_final:
+        dict(seed=[ny+1][nx+1] device tensor, seed_fine=(full-domain fine
+        grid or None), E0=dF/dE0, A=dF/dA, beta=dF/dbeta)."""
+        import torch
+        cfg = self.cfg
+        wc = self._dev_f32(w_coarse)
+        wf = None if w_fine is None else self._dev_f32(w_fine)
+        g = torch.empty((cfg["ny"] + 1, cfg["nx"] + 1), dtype=torch.float32, device=self.device)
+        gf = None
+        if cfg["mode"] != "uniform":
+            r = cfg["r"]
+            gf = torch.empty((r * cfg["ny"] + 1, r * cfg["nx"] + 1), dtype=torch.float32,
+                             device=self.device)
+        out = (C.c_double * 3)()
+        self._check(lib().dmr_backward(
+            self._h, C.c_void_p(self.tape.data_ptr()), C.c_void_p(wc.data_ptr()),
+            None if wf is None else C.c_void_p(wf.data_ptr()),
+            C.c_void_p(g.data_ptr()), None if gf is None else C.c_void_p(gf.data_ptr()),
+            out), "dmr_backward")
+        return dict(seed=g, seed_fine=gf, E0=out[0], A=out[1], beta=out[2])
 
     def timing(self):
         ms = (C.c_double * 4)()

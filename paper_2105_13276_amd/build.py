@@ -10,7 +10,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = [os.path.join(PKG, "csrc", f) for f in ("dmr_kernels.hip", "dmr_api.hip")]
+SRC = [os.path.join(PKG, "csrc", f) for f in ("dmr_kernels.hip", "dmr_adjoint.hip", "dmr_api.hip")]
 LIB = os.path.join(PKG, "libdmr.so")
 ARCH = os.environ.get("DMR_OFFLOAD_ARCH", "gfx950")
 

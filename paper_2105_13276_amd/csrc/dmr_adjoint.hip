@@ -1,0 +1,786 @@
+// dmr_adjoint.hip -- reverse-mode (discrete adjoint) kernels of one base step
+// of the DMR update: the EM (sub)step of a level (Eqs. (1)-(3) with Mur and
+// the TF/SF columns, the window accumulation and, on the patch, the E filter
+// and the Eq. (5b) boundary), the fine -> coarse transfer, the window close
+// and the continuity step (Eq. (4)) with the density transfers, and the
+// Eq. (5a) prolongation of patch growth.
+//
+// Every kernel is written in gather form: each thread owns the adjoint
+// entries it writes and reads whatever it needs, so the results do not
+// depend on scheduling.  Forward values come from the recorded tape; the
+// E filter and the clamp of the continuity step are recomputed with the
+// forward's own expressions.
+//
+// Notation: for a forward statement y = f(x), lam_x += (df/dx)^T lam_y.
+// EM step in the scaled variables of the forward (H~ = eta0 Hz, J~ =
+// (dt/eps0) J, k = kn n_e):
+//   H'  = H - S[(Ey_{i+1}-Ey_i) - (Ex_{j+1}-Ex_j)]
+//   E'  = [(1-k)E + S dH' - c1 J]/(1+k),  J' = aJ + 2k(E+E')
+// With G = (lam E' total) + 2k lam J' and g = G/(1+k):
+//   lam E += (1-k) g + 2k lam J',   lam J = a lam J' - c1 g,
+//   lam k = (E+E')(2 lam J' - g),   lam H' += S g on the two cells of dH'.
+#include "dmr_kernels.h"
+
+namespace dmr {
+
+namespace {
+
+constexpr int kAT = 64, kAR = kThreads / 64;  // node tile: 64 x 4
+
+__device__ inline size_t at(int i, int j, int p) { return (size_t)j * p + i; }
+
+// weight of the window sum of a node w.r.t. one squared edge: 1/2 where the
+// node has two edges along that axis, 1 where it has one
+__device__ inline float wwin(int q, int lo, int hi) { return (q > lo && q < hi) ? 0.5f : 1.f; }
+
+// ---- fine-patch E filter, forward expressions ------------------------------
+// Laplacian of an edge component at (i, j) with neighbours outside the
+// component's patch grid replaced by the centre value
+template <class OK>
+__device__ inline float lap_at(const float* e, int p, int i, int j, OK ok) {
+  const float c = e[at(i, j, p)];
+  return (ok(i - 1, j) ? e[at(i - 1, j, p)] : c) + (ok(i + 1, j) ? e[at(i + 1, j, p)] : c) +
+         (ok(i, j - 1) ? e[at(i, j - 1, p)] : c) + (ok(i, j + 1) ? e[at(i, j + 1, p)] : c) -
+         4.f * c;
+}
+
+template <class OK>
+__device__ inline float lap2_at(const float* e, int p, int i, int j, OK ok) {
+  const float c = lap_at(e, p, i, j, ok);
+  return (ok(i - 1, j) ? lap_at(e, p, i - 1, j, ok) : c) +
+         (ok(i + 1, j) ? lap_at(e, p, i + 1, j, ok) : c) +
+         (ok(i, j - 1) ? lap_at(e, p, i, j - 1, ok) : c) +
+         (ok(i, j + 1) ? lap_at(e, p, i, j + 1, ok) : c) - 4.f * c;
+}
+
+// Laplacian of the masked field m(i,j) = filtered(i,j) ? t(i,j) : 0
+template <class OK, class MASK>
+__device__ inline float lapm_at(const float* t, int p, int i, int j, OK ok, MASK msk) {
+  auto v = [&](int a, int b) { return msk(a, b) ? t[at(a, b, p)] : 0.f; };
+  const float c = v(i, j);
+  return (ok(i - 1, j) ? v(i - 1, j) : c) + (ok(i + 1, j) ? v(i + 1, j) : c) +
+         (ok(i, j - 1) ? v(i, j - 1) : c) + (ok(i, j + 1) ? v(i, j + 1) : c) - 4.f * c;
+}
+
+template <class OK, class MASK>
+__device__ inline float lap2m_at(const float* t, int p, int i, int j, OK ok, MASK msk) {
+  const float c = lapm_at(t, p, i, j, ok, msk);
+  return (ok(i - 1, j) ? lapm_at(t, p, i - 1, j, ok, msk) : c) +
+         (ok(i + 1, j) ? lapm_at(t, p, i + 1, j, ok, msk) : c) +
+         (ok(i, j - 1) ? lapm_at(t, p, i, j - 1, ok, msk) : c) +
+         (ok(i, j + 1) ? lapm_at(t, p, i, j + 1, ok, msk) : c) - 4.f * c;
+}
+
+// ---------------------------------------------------------------------------
+// EM adjoint, pass 1 (edges): G / g, lam k per edge.  gx/gy hold g on
+// interior edges and, on boundary edges, G (Mur: feeds the interior
+// neighbour and the old values; patch: lam of the coarse-driven value).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_adj_em_a(AdjEMArgs A) {
+  const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
+  const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
+  if (i > A.R || j > A.T) return;
+  const int L = A.L, R = A.R, B = A.B, T = A.T, p = A.pitch;
+  auto ex_ok = [&](int a, int b) { return a >= L && a < R && b >= B && b <= T; };
+  auto ey_ok = [&](int a, int b) { return a >= L && a <= R && b >= B && b < T; };
+  const bool filt = A.fine && A.gamma > 0.f;
+
+  // total lam of a new x-edge value through the window (and its own lam)
+  auto ax = [&](int a, int b) {
+    const size_t o = at(a, b, p);
+    const float e = A.exo[o];
+    return A.lex[o] + 2.f * e * (wwin(a, L, R) * A.lacc[o] + wwin(a + 1, L, R) * A.lacc[o + 1]);
+  };
+  auto ay = [&](int a, int b) {
+    const size_t o = at(a, b, p);
+    const float e = A.eyo[o];
+    return A.ley[o] + 2.f * e * (wwin(b, B, T) * A.lacc[o] + wwin(b + 1, B, T) * A.lacc[o + p]);
+  };
+  auto kapx = [&](int a, int b) {
+    const size_t o = at(a, b, p);
+    return A.kn * (0.5f * (A.n[o] + A.n[o + 1]));
+  };
+  auto kapy = [&](int a, int b) {
+    const size_t o = at(a, b, p);
+    return A.kn * (0.5f * (A.n[o] + A.n[o + p]));
+  };
+
+  if (ex_ok(i, j)) {
+    const size_t o = at(i, j, p);
+    const float kap = kapx(i, j);
+    const float lj = A.ljx[o];
+    const float en = A.exo[o];
+    float eo = A.exi[o];
+    const bool bnd = (j == B || j == T);
+    if (filt && !bnd) eo -= A.gamma * lap2_at(A.exi, p, i, j, ex_ok);
+    float tot = ax(i, j);
+    if (!bnd) {
+      if (!A.fine && A.bc_y == kBcMur && (j == B + 1 || j == T - 1)) {
+        const int b = (j == B + 1) ? B : T;
+        tot += A.cmur * (ax(i, b) + 2.f * kapx(i, b) * A.ljx[at(i, b, p)]);
+      }
+      const float g = (tot + 2.f * kap * lj) / (1.f + kap);
+      A.gx[o] = g;
+      A.kx[o] = (eo + en) * (2.f * lj - g);
+    } else {
+      A.gx[o] = tot + 2.f * kap * lj;
+      A.kx[o] = 2.f * (eo + en) * lj;
+    }
+  }
+  if (ey_ok(i, j)) {
+    const size_t o = at(i, j, p);
+    const float kap = kapy(i, j);
+    const float lj = A.ljy[o];
+    const float en = A.eyo[o];
+    float eo = A.eyi[o];
+    const bool bnd = (i == L || i == R);
+    if (filt && !bnd) eo -= A.gamma * lap2_at(A.eyi, p, i, j, ey_ok);
+    float tot = ay(i, j);
+    if (!bnd) {
+      if (!A.fine && A.bc_x == kBcMur && (i == L + 1 || i == R - 1)) {
+        const int a = (i == L + 1) ? L : R;
+        tot += A.cmur * (ay(a, j) + 2.f * kapy(a, j) * A.ljy[at(a, j, p)]);
+      }
+      const float g = (tot + 2.f * kap * lj) / (1.f + kap);
+      A.gy[o] = g;
+      A.ky[o] = (eo + en) * (2.f * lj - g);
+    } else {
+      A.gy[o] = tot + 2.f * kap * lj;
+      A.ky[o] = 2.f * (eo + en) * lj;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// EM adjoint, pass 2 (cells, edges, nodes): lam H entering the step, lam E
+// and lam J entering it, lam n, and the source-column sensitivities.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_adj_em_bc(AdjEMArgs A) {
+  const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
+  const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
+  if (i > A.R || j > A.T) return;
+  const int L = A.L, R = A.R, B = A.B, T = A.T, p = A.pitch;
+  auto hz_ok = [&](int a, int b) { return a >= L && a < R && b >= B && b < T; };
+  auto ex_ok = [&](int a, int b) { return a >= L && a < R && b >= B && b <= T; };
+  auto ey_ok = [&](int a, int b) { return a >= L && a <= R && b >= B && b < T; };
+  const float S = A.S;
+  // g of interior edges (boundary E' does not depend on H')
+  auto gxi = [&](int a, int b) { return (b == B || b == T) ? 0.f : A.gx[at(a, b, p)]; };
+  auto gyi = [&](int a, int b) { return (a == L || a == R) ? 0.f : A.gy[at(a, b, p)]; };
+  // lam of H' at a cell: its own plus the curl terms of the four edges
+  auto hcell = [&](int a, int b) {
+    return A.lhz_in[at(a, b, p)] + S * (gxi(a, b) - gxi(a, b + 1)) +
+           S * (gyi(a + 1, b) - gyi(a, b));
+  };
+  const size_t o = at(i, j, p);
+  const bool filt = A.fine && A.gamma > 0.f;
+
+  if (hz_ok(i, j)) {
+    const float h = hcell(i, j);
+    if (A.src_e && i == A.is - 1) A.src_e[j] = S * h;
+    float v = h;
+    if (A.hz_extra) {
+      v += A.hz_extra[o];
+      A.hz_extra[o] = 0.f;
+    }
+    A.lhz_out[o] = v;
+  }
+  if (ex_ok(i, j)) {
+    const float kap = A.kn * (0.5f * (A.n[o] + A.n[o + 1]));
+    const float lj = A.ljx[o];
+    float le = (hz_ok(i, j - 1) ? S * hcell(i, j - 1) : 0.f) - (hz_ok(i, j) ? S * hcell(i, j) : 0.f);
+    const bool bnd = (j == B || j == T);
+    float ljn;
+    if (!bnd) {
+      const float g = A.gx[o];
+      le += (1.f - kap) * g + 2.f * kap * lj;
+      ljn = A.a * lj - A.c1 * g;
+      if (!A.fine && A.bc_y == kBcMur) {
+        if (j == B + 1) le += A.gx[at(i, B, p)];
+        if (j == T - 1) le += A.gx[at(i, T, p)];
+      }
+    } else {
+      le += 2.f * kap * lj;
+      if (!A.fine && A.bc_y == kBcMur) le -= A.cmur * A.gx[o];
+      ljn = A.a * lj;
+    }
+    if (A.pex) {
+      le += A.pex[o];
+      A.pex[o] = 0.f;
+    }
+    if (filt) A.tex[o] = le; else A.lex[o] = le;
+    A.ljx[o] = ljn;
+  }
+  if (ey_ok(i, j)) {
+    const float kap = A.kn * (0.5f * (A.n[o] + A.n[o + p]));
+    const float lj = A.ljy[o];
+    float le = (hz_ok(i, j) ? S * hcell(i, j) : 0.f) - (hz_ok(i - 1, j) ? S * hcell(i - 1, j) : 0.f);
+    const bool bnd = (i == L || i == R);
+    float ljn;
+    if (!bnd) {
+      const float g = A.gy[o];
+      if (A.src_h && i == A.is) A.src_h[j] = S * g;
+      le += (1.f - kap) * g + 2.f * kap * lj;
+      ljn = A.a * lj - A.c1 * g;
+      if (!A.fine && A.bc_x == kBcMur) {
+        if (i == L + 1) le += A.gy[at(L, j, p)];
+        if (i == R - 1) le += A.gy[at(R, j, p)];
+      }
+    } else {
+      le += 2.f * kap * lj;
+      if (!A.fine && A.bc_x == kBcMur) le -= A.cmur * A.gy[o];
+      ljn = A.a * lj;
+    }
+    if (A.pey) {
+      le += A.pey[o];
+      A.pey[o] = 0.f;
+    }
+    if (filt) A.tey[o] = le; else A.ley[o] = le;
+    A.ljy[o] = ljn;
+  }
+  // node: k of the (up to four) edges that average this node's density
+  float s = 0.f;
+  if (ex_ok(i - 1, j)) s += A.kx[o - 1];
+  if (ex_ok(i, j)) s += A.kx[o];
+  if (ey_ok(i, j - 1)) s += A.ky[o - p];
+  if (ey_ok(i, j)) s += A.ky[o];
+  A.ln[o] += 0.5f * A.kn * s;
+}
+
+// ---------------------------------------------------------------------------
+// Fine patch: adjoint of the E filter E~ = E - gamma P L(L(E)) (P: the
+// filtered edges), with L symmetric:  lam E = lam E~ - gamma L(L(P lam E~)).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_adj_filter(AdjEMArgs A) {
+  const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
+  const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
+  if (i > A.R || j > A.T) return;
+  const int L = A.L, R = A.R, B = A.B, T = A.T, p = A.pitch;
+  auto ex_ok = [&](int a, int b) { return a >= L && a < R && b >= B && b <= T; };
+  auto ey_ok = [&](int a, int b) { return a >= L && a <= R && b >= B && b < T; };
+  auto fx = [&](int a, int b) { return b != B && b != T; };
+  auto fy = [&](int a, int b) { return a != L && a != R; };
+  const size_t o = at(i, j, p);
+  if (ex_ok(i, j)) A.lex[o] = A.tex[o] - A.gamma * lap2m_at(A.tex, p, i, j, ex_ok, fx);
+  if (ey_ok(i, j)) A.ley[o] = A.tey[o] - A.gamma * lap2m_at(A.tey, p, i, j, ey_ok, fy);
+}
+
+// ---------------------------------------------------------------------------
+// Eq. (5a) prolongation of growth, transposed: each coarse entity gathers
+// the lam of the newly covered fine entities that interpolated from it.
+// ---------------------------------------------------------------------------
+// weight of coarse index a in the 1-D linear interpolation at quarter-unit
+// position U4 (the forward skips zero weights)
+__device__ inline float w1(int U4, int a) {
+  const int c = U4 >> 2;
+  const float f = (U4 & 3) * 0.25f;
+  if (c == a) return 1.f - f;
+  if (c + 1 == a && f != 0.f) return f;
+  return 0.f;
+}
+
+__global__ __launch_bounds__(kThreads) void k_adj_grow(AdjGrowArgs A) {
+  const int a = A.cL + blockIdx.x * kAT + (threadIdx.x % kAT);
+  const int b = A.cB + blockIdx.y * kAR + (threadIdx.x / kAT);
+  if (a > A.cR || b > A.cT) return;
+  const int p = A.pitch;
+  const bool old = A.oR > A.oL;
+  auto in_old = [&](int i, int j, int hx, int hy) {
+    return old && i >= A.oL && i <= A.oR - hx && j >= A.oB && j <= A.oT - hy;
+  };
+  auto in_new = [&](int i, int j, int hx, int hy) {
+    return i >= A.L && i <= A.R - hx && j >= A.B && j <= A.T - hy;
+  };
+  // sum over fine entities (offsets dx, dy of their quarter positions)
+  auto gather = [&](const float* f, int hx, int hy, int du, int dv) {
+    float s = 0.f;
+    for (int j = 2 * b - 2; j <= 2 * b + 2; j++) {
+      const float wv = w1(2 * j + dv, b);
+      if (wv == 0.f) continue;
+      for (int i = 2 * a - 2; i <= 2 * a + 2; i++) {
+        const float wu = w1(2 * i + du, a);
+        if (wu == 0.f) continue;
+        if (!in_new(i, j, hx, hy) || in_old(i, j, hx, hy)) continue;
+        s += wu * wv * f[at(i, j, p)];
+      }
+    }
+    return s;
+  };
+  const size_t co = at(a, b, A.cpitch);
+  if (a < A.cNX && b < A.cNY) {
+    const float s = gather(A.lhz, 1, 1, -1, -1);
+    A.chz[co] += 1.25f * s;
+    A.chz_prev[co] += (1.f - 1.25f) * s;
+  }
+  if (a < A.cNX) {
+    A.cex[co] += gather(A.lex, 1, 0, -1, 0);
+    A.cjx[co] += 0.5f * gather(A.ljx, 1, 0, -1, 0);
+  }
+  if (b < A.cNY) {
+    A.cey[co] += gather(A.ley, 0, 1, 0, -1);
+    A.cjy[co] += 0.5f * gather(A.ljy, 0, 1, 0, -1);
+  }
+  if (A.with_n) A.cn[co] += gather(A.ln, 0, 0, 0, 0);
+  A.cacc[co] += gather(A.lacc, 0, 0, 0, 0);
+  for (int s = 0; s < kRing; s++)
+    A.cring[(size_t)s * A.cplane + co] += gather(A.lring + (size_t)s * A.plane, 0, 0, 0, 0);
+}
+
+// the newly covered fine entities had no value before the growth: clear
+// their lam once the coarse side has gathered it
+__global__ __launch_bounds__(kThreads) void k_adj_grow_clear(AdjGrowArgs A, float* lhz,
+                                                             float* lex, float* ley,
+                                                             float* ljx, float* ljy,
+                                                             float* ln, float* lacc,
+                                                             float* lring) {
+  const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
+  const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
+  if (i > A.R || j > A.T) return;
+  const bool old = A.oR > A.oL;
+  auto fresh = [&](int hx, int hy) {
+    if (i > A.R - hx || j > A.T - hy) return false;
+    return !(old && i >= A.oL && i <= A.oR - hx && j >= A.oB && j <= A.oT - hy);
+  };
+  const size_t o = at(i, j, A.pitch);
+  if (fresh(1, 1)) lhz[o] = 0.f;
+  if (fresh(1, 0)) { lex[o] = 0.f; ljx[o] = 0.f; }
+  if (fresh(0, 1)) { ley[o] = 0.f; ljy[o] = 0.f; }
+  if (fresh(0, 0)) {
+    if (A.with_n) ln[o] = 0.f;
+    lacc[o] = 0.f;
+    for (int s = 0; s < kRing; s++) lring[(size_t)s * A.plane + o] = 0.f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Eq. (5b) transposed: coarse edges on the patch boundary lines gather the
+// lam of the fine boundary values that interpolated them (space weights
+// 1/4, 3/4; time weights 1-frac on E^n, frac on E^{n+1}).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_adj_cfb(AdjCfbArgs A) {
+  const int nx = A.I1 - A.I0 + 2, ny = A.J1 - A.J0 + 2;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * nx + 2 * ny) return;
+  float s = 0.f;
+  size_t co;
+  bool xline;
+  if (t < 2 * nx) {  // Ex on coarse rows J0, J1
+    xline = true;
+    const int J = (t < nx) ? A.J0 : A.J1;
+    const int c = A.I0 - 1 + (t % nx);
+    const int jf = 2 * J;
+    const int fi[4] = {2 * c - 1, 2 * c, 2 * c + 1, 2 * c + 2};
+    const float fw[4] = {0.25f, 0.75f, 0.75f, 0.25f};
+    for (int q = 0; q < 4; q++)
+      if (fi[q] >= A.L && fi[q] < A.R) s += fw[q] * A.gx[at(fi[q], jf, A.pitch)];
+    co = at(c, J, A.cpitch);
+  } else {           // Ey on coarse columns I0, I1
+    xline = false;
+    const int u = t - 2 * nx;
+    const int I = (u < ny) ? A.I0 : A.I1;
+    const int c = A.J0 - 1 + (u % ny);
+    const int iff = 2 * I;
+    const int fj[4] = {2 * c - 1, 2 * c, 2 * c + 1, 2 * c + 2};
+    const float fw[4] = {0.25f, 0.75f, 0.75f, 0.25f};
+    for (int q = 0; q < 4; q++)
+      if (fj[q] >= A.B && fj[q] < A.T) s += fw[q] * A.gy[at(iff, fj[q], A.pitch)];
+    co = at(I, c, A.cpitch);
+  }
+  float* ln = xline ? A.lcex : A.lcey;
+  float* lo = xline ? A.pcex : A.pcey;
+  ln[co] += A.frac * s;
+  lo[co] += (1.f - A.frac) * s;
+}
+
+// ---------------------------------------------------------------------------
+// Fine -> coarse transfer transposed, one thread per coarse node position
+// of the patch: the coarse entities strictly inside hand their lam to the
+// fine entities they were averaged from and drop it (they were overwritten).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_adj_restrict(AdjRestrictArgs A) {
+  const int a = A.I0 + blockIdx.x * kAT + (threadIdx.x % kAT);
+  const int b = A.J0 + blockIdx.y * kAR + (threadIdx.x / kAT);
+  if (a > A.I1 || b > A.J1) return;
+  const size_t co = at(a, b, A.cpitch);
+  const int p = A.pitch;
+  const int i = 2 * a, j = 2 * b;
+  if (a < A.I1 && b < A.J1) {
+    const float v = 0.125f * A.lchz[co];
+    for (int db = 0; db < 2; db++)
+      for (int da = 0; da < 2; da++) {
+        const size_t o = at(i + da, j + db, p);
+        A.lfhz[o] += v;
+        A.hz_extra[o] = v;
+      }
+    A.lchz[co] = 0.f;
+  }
+  if (a < A.I1 && b > A.J0 && b < A.J1) {
+    const float v = 0.5f * A.lcex[co], w = A.lcjx[co];
+    const size_t o = at(i, j, p);
+    A.lfex[o] += v; A.lfex[o + 1] += v;
+    A.lfjx[o] += w; A.lfjx[o + 1] += w;
+    A.lcex[co] = 0.f; A.lcjx[co] = 0.f;
+  }
+  if (a > A.I0 && a < A.I1 && b < A.J1) {
+    const float v = 0.5f * A.lcey[co], w = A.lcjy[co];
+    const size_t o = at(i, j, p);
+    A.lfey[o] += v; A.lfey[o + p] += v;
+    A.lfjy[o] += w; A.lfjy[o + p] += w;
+    A.lcey[co] = 0.f; A.lcjy[co] = 0.f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Density transfers transposed (one thread per coarse node of the patch):
+// injection (coarse nodes strictly inside took the fine value) and the
+// patch boundary nodes (copy at coincident fine nodes, mean of the two
+// coarse neighbours at mid nodes).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_adj_inj(AdjInjArgs A) {
+  const int a = A.I0 + blockIdx.x * kAT + (threadIdx.x % kAT);
+  const int b = A.J0 + blockIdx.y * kAR + (threadIdx.x / kAT);
+  if (a > A.I1 || b > A.J1) return;
+  const size_t co = at(a, b, A.cpitch);
+  const int p = A.pitch, i = 2 * a, j = 2 * b;
+  const int L = 2 * A.I0, R = 2 * A.I1, B = 2 * A.J0, T = 2 * A.J1;
+  if (a > A.I0 && a < A.I1 && b > A.J0 && b < A.J1) {
+    A.lfn[at(i, j, p)] += A.lcn[co];
+    A.lcn[co] = 0.f;
+    return;
+  }
+  float s = A.lfn[at(i, j, p)];
+  if (b == A.J0 || b == A.J1) {  // horizontal line
+    if (i - 1 >= L) s += 0.5f * A.lfn[at(i - 1, j, p)];
+    if (i + 1 <= R) s += 0.5f * A.lfn[at(i + 1, j, p)];
+  }
+  if (a == A.I0 || a == A.I1) {  // vertical line
+    if (j - 1 >= B) s += 0.5f * A.lfn[at(i, j - 1, p)];
+    if (j + 1 <= T) s += 0.5f * A.lfn[at(i, j + 1, p)];
+  }
+  A.lcn[co] += s;
+}
+
+// ---------------------------------------------------------------------------
+// Window close and continuity step (Eq. (4)) transposed.
+// Pass 1 (per node): clamp mask, ell = mask * lam n', the E_rms^2 lam into
+// the ring and the accumulator (close transposed), and the dF/dA, dF/dbeta
+// partial sums of the block.  Patch boundary nodes took coarse values, so
+// their ell is zero.
+// ---------------------------------------------------------------------------
+__device__ inline float d_eff_a(const AdjContArgs& A, float n) {
+  if (A.d_const_mode) return A.d_const;
+  const float al = n * A.inv_namb;
+  return (al * A.Da + A.De) / (1.f + al);
+}
+
+__device__ inline float d_eff_prime(const AdjContArgs& A, float n) {
+  if (A.d_const_mode) return 0.f;
+  const float al = n * A.inv_namb;
+  return A.inv_namb * (A.Da - A.De) / ((1.f + al) * (1.f + al));
+}
+
+__global__ __launch_bounds__(kThreads) void k_adj_cont_a(AdjContArgs A) {
+  const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
+  const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
+  double dA = 0.0, dB = 0.0;
+  if (i <= A.R && j <= A.T) {
+    const int p = A.pitch;
+    const size_t o = at(i, j, p);
+    const bool edge = A.fine && (i == A.L || i == A.R || j == A.B || j == A.T);
+    float lE2 = 0.f;
+    float ell = 0.f;
+    if (!edge) {
+      // forward, as the continuity kernel evaluates it
+      const float e2 = A.e2[o];
+      const float ni = A.n[o];
+      const float di = d_eff_a(A, ni);
+      float flux = 0.f;
+      if (i > A.L) { const float v = A.n[o - 1]; flux += 0.5f * (di + d_eff_a(A, v)) * (v - ni); }
+      if (i < A.R) { const float v = A.n[o + 1]; flux += 0.5f * (di + d_eff_a(A, v)) * (v - ni); }
+      if (j > A.B) { const float v = A.n[o - p]; flux += 0.5f * (di + d_eff_a(A, v)) * (v - ni); }
+      if (j < A.T) { const float v = A.n[o + p]; flux += 0.5f * (di + d_eff_a(A, v)) * (v - ni); }
+      const float x = e2 * A.eeff_p2;
+      const float pw = powf(x, A.half_beta);
+      const float nu = A.nuA * (pw - A.att);
+      float nn = ni + A.dtn * (flux * A.inv_dx2 + nu * ni);
+      // max(0, .): right derivative at 0 (a zero density is perturbed upward)
+      ell = nn >= 0.f ? A.ln[o] : 0.f;
+      // nu = nu_m A (x^(beta/2) - c^beta),  x = E_rms^2 E_eff-factor/(100 p)^2
+      const float lnu = ell * A.dtn * ni;
+      if (x > 0.f) {
+        lE2 = lnu * A.nuA * A.half_beta * (pw / x) * A.eeff_p2;
+        dB = (double)lnu * (double)A.nuA * ((double)pw * 0.5 * (double)logf(x) - (double)A.att * (double)A.ln_c);
+      } else {
+        dB = (double)lnu * (double)A.nuA * (-(double)A.att * (double)A.ln_c);
+      }
+      dA = (double)lnu * (double)A.nu_m * ((double)pw - (double)A.att);
+    }
+    A.ell[o] = ell;
+    // close: ring[slot] = acc / spp, acc = 0; E_rms^2 = sum of the ring
+    float* rs = A.lring + (size_t)A.slot * A.plane + o;
+    const float lsv = *rs + lE2;
+    for (int s = 0; s < kRing; s++)
+      if (s != A.slot) A.lring[(size_t)s * A.plane + o] += lE2;
+    *rs = 0.f;
+    A.lacc[o] = lsv * A.inv_spp;
+  }
+  // block partial sums, fixed order
+  __shared__ double sA[kThreads / 64], sB[kThreads / 64];
+  for (int d = 32; d >= 1; d >>= 1) {
+    dA += __shfl_xor(dA, d, 64);
+    dB += __shfl_xor(dB, d, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { sA[w] = dA; sB[w] = dB; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < kThreads / 64; k++) { a += sA[k]; b += sB[k]; }
+    const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    A.part[2 * blk] = a;
+    A.part[2 * blk + 1] = b;
+  }
+}
+
+// Pass 2 (per node): lam n entering the step,
+//   lam n_j = ell_j (1 + dt_n nu_j)
+//           + c sum_f (ell_j - ell_f) [D'_j (n_f - n_j)/2 - (D_j + D_f)/2],
+// c = dt_n/dx^2, over the neighbours f the forward's flux used.
+__global__ __launch_bounds__(kThreads) void k_adj_cont_b(AdjContArgs A) {
+  const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
+  const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
+  if (i > A.R || j > A.T) return;
+  const int p = A.pitch;
+  const size_t o = at(i, j, p);
+  const float nj = A.n[o];
+  const float dj = d_eff_a(A, nj);
+  const float dpj = d_eff_prime(A, nj);
+  const float lj = A.ell[o];
+  float s = 0.f;
+  auto face = [&](size_t q) {
+    const float nf = A.n[q];
+    s += (lj - A.ell[q]) * (0.5f * dpj * (nf - nj) - 0.5f * (dj + d_eff_a(A, nf)));
+  };
+  if (i > A.L) face(o - 1);
+  if (i < A.R) face(o + 1);
+  if (j > A.B) face(o - p);
+  if (j < A.T) face(o + p);
+  float self = 0.f;
+  if (lj != 0.f) {
+    const float x = A.e2[o] * A.eeff_p2;
+    const float nu = A.nuA * (powf(x, A.half_beta) - A.att);
+    self = lj * (1.f + A.dtn * nu);
+  }
+  A.ln[o] = self + A.dtn * A.inv_dx2 * s;
+}
+
+// window close without a continuity step: lam acc = lam ring[slot] / spp
+__global__ __launch_bounds__(kThreads) void k_adj_close(AdjContArgs A) {
+  const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
+  const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
+  if (i > A.R || j > A.T) return;
+  const size_t o = at(i, j, A.pitch);
+  float* rs = A.lring + (size_t)A.slot * A.plane + o;
+  A.lacc[o] = *rs * A.inv_spp;
+  *rs = 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// Tape plumbing and reductions.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_copy(CopyJobs J) {
+  const CopyJob jb = J.job[blockIdx.y];
+  const size_t n4 = jb.n / 4;
+  const float4* s = reinterpret_cast<const float4*>(jb.src);
+  float4* d = reinterpret_cast<float4*>(jb.dst);
+  for (size_t k = (size_t)blockIdx.x * kThreads + threadIdx.x; k < n4;
+       k += (size_t)gridDim.x * kThreads)
+    d[k] = s[k];
+}
+
+// sum of the 8 window slots in the order the continuity step adds them
+__global__ __launch_bounds__(kThreads) void k_ring_e2(const float* ring, size_t plane,
+                                                      int pitch, int L, int B, int R, int T,
+                                                      float* dst) {
+  const int i = L + blockIdx.x * kAT + (threadIdx.x % kAT);
+  const int j = B + blockIdx.y * kAR + (threadIdx.x / kAT);
+  if (i > R || j > T) return;
+  const size_t o = at(i, j, pitch);
+  float e2 = 0.f;
+  for (int s = 0; s < kRing; s++) e2 += ring[(size_t)s * plane + o];
+  dst[o] = e2;
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); k++) t += sh[k];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(1024) void k_adj_reduce(const float* src, int nsteps,
+                                                     int step_pitch, int rows,
+                                                     const double* u, const double* part,
+                                                     int nparts, double* out) {
+  __shared__ double sh[16];
+  double e0 = 0.0;
+  for (int k = 0; k < nsteps; k++) {
+    const float* se = src + (size_t)k * step_pitch;
+    const float* sh_ = se + rows;
+    double a = 0.0, b = 0.0;
+    for (int q = threadIdx.x; q < rows; q += blockDim.x) {
+      a += (double)se[q];
+      b += (double)sh_[q];
+    }
+    e0 += u[2 * k] * a + u[2 * k + 1] * b;
+  }
+  double pa = 0.0, pb = 0.0;
+  for (int q = threadIdx.x; q < nparts; q += blockDim.x) {
+    pa += part[2 * q];
+    pb += part[2 * q + 1];
+  }
+  e0 = block_sum(e0, sh);
+  pa = block_sum(pa, sh);
+  pb = block_sum(pb, sh);
+  if (threadIdx.x == 0) {
+    out[0] += e0;
+    out[1] += pa;
+    out[2] += pb;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_wdot_part(const float* w, const float* a,
+                                                        int pitch, int i0, int j0, int cols,
+                                                        int rows, double* part) {
+  __shared__ double sh[kThreads / 64];
+  double v = 0.0;
+  const size_t n = (size_t)cols * rows;
+  for (size_t k = (size_t)blockIdx.x * kThreads + threadIdx.x; k < n;
+       k += (size_t)gridDim.x * kThreads) {
+    const int c = (int)(k % cols), r = (int)(k / cols);
+    v += (double)w[k] * (double)a[(size_t)(r + j0) * pitch + i0 + c];
+  }
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_wdot_sum(const double* part, int n, double* out) {
+  __shared__ double sh[kThreads / 64];
+  double v = 0.0;
+  for (int k = threadIdx.x; k < n; k += kThreads) v += part[k];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) out[0] = v;
+}
+
+__global__ void k_copy2d(const float* src, int spitch, int si0, int sj0, float* dst,
+                         int dpitch, int di0, int dj0, int cols, int rows) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= cols || j >= rows) return;
+  dst[(size_t)(j + dj0) * dpitch + di0 + i] = src[(size_t)(j + sj0) * spitch + si0 + i];
+}
+
+dim3 node_grid(int L, int B, int R, int T) {
+  return dim3((unsigned)((R - L + 1 + kAT - 1) / kAT), (unsigned)((T - B + 1 + kAR - 1) / kAR));
+}
+
+}  // namespace
+
+hipError_t launch_adj_em(const AdjEMArgs& A, hipStream_t st) {
+  const dim3 g = node_grid(A.L, A.B, A.R, A.T);
+  k_adj_em_a<<<g, kThreads, 0, st>>>(A);
+  k_adj_em_bc<<<g, kThreads, 0, st>>>(A);
+  if (A.fine && A.gamma > 0.f) k_adj_filter<<<g, kThreads, 0, st>>>(A);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_grow(const AdjGrowArgs& A, hipStream_t st) {
+  k_adj_grow<<<node_grid(A.cL, A.cB, A.cR, A.cT), kThreads, 0, st>>>(A);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_grow_clear(const AdjGrowArgs& A, float* lhz, float* lex, float* ley,
+                                 float* ljx, float* ljy, float* ln, float* lacc,
+                                 float* lring, hipStream_t st) {
+  k_adj_grow_clear<<<node_grid(A.L, A.B, A.R, A.T), kThreads, 0, st>>>(A, lhz, lex, ley, ljx,
+                                                                         ljy, ln, lacc, lring);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_cfb(const AdjCfbArgs& A, hipStream_t st) {
+  const int n = 2 * (A.I1 - A.I0 + 2) + 2 * (A.J1 - A.J0 + 2);
+  k_adj_cfb<<<(n + kThreads - 1) / kThreads, kThreads, 0, st>>>(A);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_restrict(const AdjRestrictArgs& A, hipStream_t st) {
+  k_adj_restrict<<<node_grid(A.I0, A.J0, A.I1, A.J1), kThreads, 0, st>>>(A);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_inj(const AdjInjArgs& A, hipStream_t st) {
+  k_adj_inj<<<node_grid(A.I0, A.J0, A.I1, A.J1), kThreads, 0, st>>>(A);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_cont(const AdjContArgs& A, int* nparts, hipStream_t st) {
+  const dim3 g = node_grid(A.L, A.B, A.R, A.T);
+  k_adj_cont_a<<<g, kThreads, 0, st>>>(A);
+  k_adj_cont_b<<<g, kThreads, 0, st>>>(A);
+  *nparts = (int)(g.x * g.y);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_close(const AdjContArgs& A, hipStream_t st) {
+  k_adj_close<<<node_grid(A.L, A.B, A.R, A.T), kThreads, 0, st>>>(A);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const CopyJobs& J, hipStream_t st) {
+  if (J.count <= 0) return hipSuccess;
+  size_t mx = 0;
+  for (int k = 0; k < J.count; k++) mx = J.job[k].n > mx ? J.job[k].n : mx;
+  size_t bx = (mx / 4 + kThreads - 1) / kThreads;
+  if (bx > 1024) bx = 1024;
+  if (bx < 1) bx = 1;
+  k_copy<<<dim3((unsigned)bx, (unsigned)J.count), kThreads, 0, st>>>(J);
+  return hipGetLastError();
+}
+
+hipError_t launch_ring_e2(const float* ring, size_t plane, int pitch, int L, int B, int R,
+                          int T, float* dst, hipStream_t st) {
+  k_ring_e2<<<node_grid(L, B, R, T), kThreads, 0, st>>>(ring, plane, pitch, L, B, R, T, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_reduce(const float* src, int nsteps, int step_pitch, int rows,
+                             const double* u, const double* part, int nparts, double* out,
+                             hipStream_t st) {
+  k_adj_reduce<<<1, 1024, 0, st>>>(src, nsteps, step_pitch, rows, u, part, nparts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy2d(const float* src, int spitch, int si0, int sj0, float* dst,
+                         int dpitch, int di0, int dj0, int cols, int rows, hipStream_t st) {
+  if (cols <= 0 || rows <= 0) return hipSuccess;
+  k_copy2d<<<dim3((unsigned)((cols + 255) / 256), (unsigned)rows), 256, 0, st>>>(
+      src, spitch, si0, sj0, dst, dpitch, di0, dj0, cols, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_wdot(const float* w, const float* a, int pitch, int i0, int j0, int cols,
+                       int rows, double* part, double* out, hipStream_t st) {
+  const size_t n = (size_t)cols * rows;
+  int nb = (int)((n + kThreads - 1) / kThreads);
+  if (nb > 1024) nb = 1024;
+  if (nb < 1) nb = 1;
+  k_wdot_part<<<nb, kThreads, 0, st>>>(w, a, pitch, i0, j0, cols, rows, part);
+  k_wdot_sum<<<1, kThreads, 0, st>>>(part, nb, out);
+  return hipGetLastError();
+}
+
+}  // namespace dmr

@@ -120,6 +120,44 @@ int check_params(const dmr_params* p, std::string* why) {
   return DMR_OK;
 }
 
+// Adjoint recording (the adjoint section below): what one replayed base step
+// stores, and what it did.
+struct StepStore {
+  float *cexi, *ceyi, *cexp, *ceyp, *cn, *ce2;             // coarse
+  float *fex0, *fey0, *fex1, *fey1, *fex2, *fey2, *fn, *fe2;  // patch
+};
+struct StepMeta {
+  int has = 0, ext[4] = {0, 0, 0, 0};  // patch during the step
+  int sync = 0, update = 0, slot = 0;  // window block closed after it
+  int grow = 0, gnew[4] = {0, 0, 0, 0};  // growth after it
+};
+struct StepCtx {
+  bool store = false;  // copy the step's forward values into ss
+  StepStore ss{};
+  bool forced = false;  // replay: apply force_ext instead of the growth test
+  bool force_grow = false;
+  int force_ext[4] = {0, 0, 0, 0};
+  StepMeta meta;
+};
+struct Ckpt {
+  int64_t step = 0, blocks = 0;
+  int ccur = 0, ncur = 0, has = 0, ext[4] = {0, 0, 0, 0}, ty1 = 16;
+};
+struct Growth {
+  int64_t after = 0;  // base steps completed when it happened
+  int ext[4] = {0, 0, 0, 0};
+};
+struct AdjTape {
+  char* base = nullptr;
+  size_t bytes = 0;
+  int64_t steps = 0;
+  int every = 0, nck = 0;
+  std::vector<Ckpt> ck;
+  Ckpt fin;
+  std::vector<Growth> grow;
+  bool valid = false;
+};
+
 }  // namespace
 
 struct dmr_sim {
@@ -143,6 +181,10 @@ struct dmr_sim {
   int* d_err = nullptr;
   float* stage = nullptr;
   int h_desc[16] = {};
+  // patch built at t = 0, and whether its density came from a fine seed
+  bool had0 = false, keep_n0 = false;
+  int ext0[4] = {0, 0, 0, 0};
+  AdjTape tape;
   // timing
   bool timing = false;
   struct Ev { int cls; hipEvent_t a, b; };
@@ -455,9 +497,49 @@ void make_fine_cont(const dmr_sim* s, int nc, ContArgs* G) {
   G->nbx = (G->R - G->L + 1 + kTX - 1) / kTX;
 }
 
-int base_step(dmr_sim* s) {
+// copy jobs of one stored plane: whole coarse planes, patch rows of fine ones
+void job(CopyJobs* J, const float* src, float* dst, size_t n) {
+  J->job[J->count++] = CopyJob{src, dst, n};
+}
+
+void job_rows(CopyJobs* J, const dmr_sim* s, const float* src, float* dst) {
+  const Level& F = s->L1;
+  const size_t off = (size_t)(s->p.r * s->ext[1]) * F.pitch;
+  const size_t n = (size_t)(s->p.r * (s->ext[3] - s->ext[1]) + 1) * F.pitch;
+  job(J, src + off, dst + off, n);
+}
+
+int run_copies(dmr_sim* s, const CopyJobs& J) {
+  const hipError_t e = launch_copy(J, s->st);
+  return e == hipSuccess ? DMR_OK : hipfail(s, e, "tape copy");
+}
+
+// One base step with subcycling (Sec. III.C), the window/continuity cadence
+// and the regrid cadence.  With cx, the step also reports what it did and,
+// for the adjoint's replay, stores its forward values and applies a
+// recorded growth instead of running the growth test.
+int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
   const dmr_params& p = s->p;
   const int c = s->ccur;
+  const bool st = cx && cx->store;
+  if (cx) {
+    cx->meta = StepMeta{};
+    cx->meta.has = s->has_patch;
+    for (int q = 0; q < 4; q++) cx->meta.ext[q] = s->ext[q];
+  }
+  if (st) {
+    CopyJobs J{};
+    const size_t n0 = s->L0.plane;
+    job(&J, s->L0.ex[c], cx->ss.cexi, n0);
+    job(&J, s->L0.ey[c], cx->ss.ceyi, n0);
+    job(&J, s->L0.n[s->ncur], cx->ss.cn, n0);
+    if (s->has_patch) {
+      job_rows(&J, s, s->L1.ex[0], cx->ss.fex0);
+      job_rows(&J, s, s->L1.ey[0], cx->ss.fey0);
+      job_rows(&J, s, s->L1.n[s->ncur], cx->ss.fn);
+    }
+    if (int rc = run_copies(s, J)) return rc;
+  }
   // coarse (or uniform) EM step n -> n+1
   EMArgs A;
   make_base_em(s, c, s->ncur, &A);
@@ -466,6 +548,12 @@ int base_step(dmr_sim* s) {
   hipError_t e = launch_em_stream(A, s->seg0, s->depth0, s->st);
   ev_end(s);
   if (e != hipSuccess) return hipfail(s, e, "base EM launch");
+  if (st) {
+    CopyJobs J{};
+    job(&J, s->L0.ex[1 - c], cx->ss.cexp, s->L0.plane);
+    job(&J, s->L0.ey[1 - c], cx->ss.ceyp, s->L0.plane);
+    if (int rc = run_copies(s, J)) return rc;
+  }
   if (s->has_patch) {  // two fine substeps (Sec. III.C)
     for (int m = 1; m <= p.r; m++) {
       EMArgs G;
@@ -474,6 +562,12 @@ int base_step(dmr_sim* s) {
       e = launch_em(G, true, s->ty1, s->st);
       ev_end(s);
       if (e != hipSuccess) return hipfail(s, e, "fine EM launch");
+      if (st) {
+        CopyJobs J{};
+        job_rows(&J, s, s->L1.ex[m & 1], m == 1 ? cx->ss.fex1 : cx->ss.fex2);
+        job_rows(&J, s, s->L1.ey[m & 1], m == 1 ? cx->ss.fey1 : cx->ss.fey2);
+        if (int rc = run_copies(s, J)) return rc;
+      }
     }
   }
   s->ccur = 1 - c;
@@ -482,6 +576,11 @@ int base_step(dmr_sim* s) {
     const int slot = (int)(s->blocks % kRing);
     s->blocks++;
     const int update = s->blocks >= kRing;
+    if (cx) {
+      cx->meta.sync = 1;
+      cx->meta.update = update;
+      cx->meta.slot = slot;
+    }
     ContArgs K;
     make_base_cont(s, s->ncur, &K);
     K.slot = slot; K.update = update;
@@ -498,10 +597,35 @@ int base_step(dmr_sim* s) {
       ev_end(s);
       if (e != hipSuccess) return hipfail(s, e, "fine continuity launch");
     }
+    if (st && update) {  // the E_rms^2 each continuity step used
+      const Level& C = s->L0;
+      e = launch_ring_e2(C.ring, C.plane, C.pitch, 0, 0, p.nx, p.ny, cx->ss.ce2, s->st);
+      if (e == hipSuccess && s->has_patch) {
+        const Level& F = s->L1;
+        const int r = p.r;
+        e = launch_ring_e2(F.ring, F.plane, F.pitch, r * s->ext[0], r * s->ext[1],
+                           r * s->ext[2], r * s->ext[3], cx->ss.fe2, s->st);
+      }
+      if (e != hipSuccess) return hipfail(s, e, "window sum launch");
+    }
     if (update) s->ncur = 1 - s->ncur;
   }
-  if (p.mode == DMR_DYNAMIC && s->step % p.regrid_every == 0)
-    return regrid(s, false);
+  if (p.mode == DMR_DYNAMIC && s->step % p.regrid_every == 0) {
+    if (cx && cx->forced) {
+      if (!cx->force_grow) return DMR_OK;
+      if (int rc = prolong(s, cx->force_ext, false)) return rc;
+    } else {
+      const bool had = s->has_patch;
+      int before[4];
+      for (int q = 0; q < 4; q++) before[q] = s->ext[q];
+      if (int rc = regrid(s, false)) return rc;
+      bool grew = s->has_patch != had;
+      for (int q = 0; q < 4; q++) grew = grew || s->ext[q] != before[q];
+      if (!grew || !cx) return DMR_OK;
+    }
+    cx->meta.grow = 1;
+    for (int q = 0; q < 4; q++) cx->meta.gnew[q] = s->ext[q];
+  }
   return DMR_OK;
 }
 
@@ -633,6 +757,9 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   }
   if (p->mode == DMR_STATIC) rc = prolong(s, p->static_ext, keep_n);
   else if (p->mode == DMR_DYNAMIC) rc = regrid(s, keep_n);
+  s->had0 = s->has_patch;
+  s->keep_n0 = keep_n;
+  for (int k = 0; k < 4; k++) s->ext0[k] = s->ext[k];
   if (!rc) {
     e = hipStreamSynchronize(s->st);
     if (e != hipSuccess) rc = hipfail(s, e, "create");
@@ -808,6 +935,450 @@ int dmr_get_timing(dmr_sim* s, double ms[4], int64_t launches[4]) {
 
 const char* dmr_last_error(const dmr_sim* s) {
   return s ? s->err.c_str() : "no handle";
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Adjoint: reverse mode of a recorded run.  dmr_forward_record advances the
+// simulation from t = 0 like dmr_step, keeping a checkpoint of the state
+// every ckpt_every base steps and the patch history.  dmr_backward walks the
+// checkpoint segments from the last to the first: it restores the segment's
+// checkpoint, replays its steps (same kernels, recorded growths applied
+// instead of the growth test) storing the values the adjoint kernels need,
+// then runs the adjoint of each step in reverse order.  Memory: checkpoints
+// plus one segment of stored steps (sqrt(N) checkpointing when ckpt_every is
+// about sqrt(steps)).
+// ===========================================================================
+namespace {
+
+constexpr int kAdjPlanes = 26;       // lam state + temporaries per level
+constexpr int kCkC = 16, kCkF = 15;  // planes per checkpoint (coarse, patch)
+constexpr int kStC = 6, kStF = 8;    // planes stored per replayed step
+
+struct TapeLayout {
+  size_t adj_c = 0, adj_f = 0, ck = 0, ck_size = 0, store = 0, st_size = 0, src = 0,
+         src_size = 0, u = 0, part = 0, part_per_step = 0, gsum = 0, wpart = 0, total = 0;
+  int nck = 0;
+};
+
+size_t node_blocks(int w, int h) {
+  return (size_t)((w + 1 + 63) / 64) * (size_t)((h + 1 + 3) / 4);
+}
+
+TapeLayout tape_layout(const dmr_params* p, int64_t steps, int every) {
+  const Layout L = layout_of(p);
+  const size_t f = sizeof(float);
+  TapeLayout T;
+  size_t off = 0;
+  T.adj_c = off; off += align256(L.plane0 * kAdjPlanes * f);
+  T.adj_f = off; off += align256(L.plane1 * kAdjPlanes * f);
+  T.nck = (int)((steps + every - 1) / every);
+  T.ck_size = align256((L.plane0 * kCkC + L.plane1 * kCkF) * f);
+  T.ck = off; off += T.ck_size * (size_t)(T.nck + 1);
+  T.st_size = align256((L.plane0 * kStC + L.plane1 * kStF) * f);
+  T.store = off; off += T.st_size * (size_t)every;
+  T.src_size = align256((size_t)2 * p->ny * f);
+  T.src = off; off += T.src_size * (size_t)every;
+  T.u = off; off += align256((size_t)2 * steps * sizeof(double));
+  T.part_per_step = node_blocks(p->nx, p->ny) +
+                    (refined(p) ? node_blocks(p->r * p->nx, p->r * p->ny) : 0);
+  T.part = off; off += align256(T.part_per_step * 2 * sizeof(double) * (size_t)every);
+  T.gsum = off; off += 256;
+  T.wpart = off; off += align256(1024 * sizeof(double));
+  T.total = off;
+  return T;
+}
+
+struct AdjLevel {
+  float* hz[2] = {nullptr, nullptr};
+  float *ex = nullptr, *ey = nullptr, *jx = nullptr, *jy = nullptr, *n = nullptr,
+        *acc = nullptr, *ring = nullptr;
+  float *gx = nullptr, *gy = nullptr, *kx = nullptr, *ky = nullptr, *tex = nullptr,
+        *tey = nullptr, *ell = nullptr, *hx = nullptr, *pex = nullptr, *pey = nullptr;
+  int cur = 0;
+};
+
+AdjLevel adj_carve(char* base, size_t plane) {
+  AdjLevel a;
+  float* q = (float*)base;
+  auto take = [&](size_t k) { float* r = q; q += k * plane; return r; };
+  a.hz[0] = take(1); a.hz[1] = take(1);
+  a.ex = take(1); a.ey = take(1); a.jx = take(1); a.jy = take(1);
+  a.n = take(1); a.acc = take(1); a.ring = take(kRing);
+  a.gx = take(1); a.gy = take(1); a.kx = take(1); a.ky = take(1);
+  a.tex = take(1); a.tey = take(1); a.ell = take(1); a.hx = take(1);
+  a.pex = take(1); a.pey = take(1);
+  return a;
+}
+
+StepStore store_slot(const dmr_sim* s, const TapeLayout& T, int k) {
+  float* b = (float*)(s->tape.base + T.store + T.st_size * (size_t)k);
+  const size_t p0 = s->L0.plane, p1 = s->L1.plane;
+  StepStore ss;
+  ss.cexi = b; ss.ceyi = b + p0; ss.cexp = b + 2 * p0; ss.ceyp = b + 3 * p0;
+  ss.cn = b + 4 * p0; ss.ce2 = b + 5 * p0;
+  float* f = b + kStC * p0;
+  ss.fex0 = f; ss.fey0 = f + p1; ss.fex1 = f + 2 * p1; ss.fey1 = f + 3 * p1;
+  ss.fex2 = f + 4 * p1; ss.fey2 = f + 5 * p1; ss.fn = f + 6 * p1; ss.fe2 = f + 7 * p1;
+  return ss;
+}
+
+float* ck_base(const dmr_sim* s, const TapeLayout& T, int idx) {
+  return (float*)(s->tape.base + T.ck + T.ck_size * (size_t)idx);
+}
+
+// live planes of a checkpoint, in slot order
+void ck_planes(dmr_sim* s, float* live_c[9], float* live_f[15]) {
+  Level &C = s->L0, &F = s->L1;
+  const int c = s->ccur, nc = s->ncur;
+  float* cs[9] = {C.hz[c], C.hz[1 - c], C.ex[c], C.ey[c], C.jx[c], C.jy[c], C.n[nc], C.acc,
+                  C.ring};
+  for (int q = 0; q < 9; q++) live_c[q] = cs[q];
+  float* fs[7] = {F.hz[0], F.ex[0], F.ey[0], F.jx[0], F.jy[0], F.n[nc], F.acc};
+  for (int q = 0; q < 7; q++) live_f[q] = fs[q];
+  for (int k = 0; k < kRing; k++) live_f[7 + k] = F.ring ? F.ring + (size_t)k * F.plane : nullptr;
+}
+
+int ck_copy(dmr_sim* s, float* b, bool save) {
+  float *lc[9], *lf[15];
+  ck_planes(s, lc, lf);
+  const size_t p0 = s->L0.plane, p1 = s->L1.plane;
+  CopyJobs J{};
+  for (int q = 0; q < 9; q++) {
+    const size_t n = q == 8 ? kRing * p0 : p0;
+    if (save) job(&J, lc[q], b + q * p0, n);
+    else job(&J, b + q * p0, lc[q], n);
+  }
+  if (s->has_patch) {
+    float* fb = b + kCkC * p0;
+    for (int q = 0; q < kCkF; q++) {
+      if (save) job_rows(&J, s, lf[q], fb + q * p1);
+      else job_rows(&J, s, fb + q * p1, lf[q]);
+    }
+  }
+  return run_copies(s, J);
+}
+
+int ck_save(dmr_sim* s, const TapeLayout& T, int idx, Ckpt* k) {
+  k->step = s->step; k->blocks = s->blocks; k->ccur = s->ccur; k->ncur = s->ncur;
+  k->has = s->has_patch; k->ty1 = s->ty1;
+  for (int q = 0; q < 4; q++) k->ext[q] = s->ext[q];
+  return ck_copy(s, ck_base(s, T, idx), true);
+}
+
+int ck_restore(dmr_sim* s, const TapeLayout& T, int idx, const Ckpt& k) {
+  s->step = k.step; s->blocks = k.blocks; s->ccur = k.ccur; s->ncur = k.ncur;
+  s->has_patch = k.has != 0; s->ty1 = k.ty1;
+  for (int q = 0; q < 4; q++) s->ext[q] = k.ext[q];
+  return ck_copy(s, ck_base(s, T, idx), false);
+}
+
+AdjEMArgs adj_em_args(const dmr_sim* s, const Level& Lv, AdjLevel& a, bool fine,
+                      const int reg[4]) {
+  const dmr_params& p = s->p;
+  AdjEMArgs A{};
+  A.L = reg[0]; A.B = reg[1]; A.R = reg[2]; A.T = reg[3];
+  A.pitch = Lv.pitch;
+  A.S = Lv.S; A.c1 = Lv.c1; A.a = Lv.a; A.kn = Lv.kn; A.cmur = Lv.cmur;
+  A.gamma = fine ? (float)p.fine_filter : 0.f;
+  A.fine = fine ? 1 : 0;
+  A.bc_x = p.bc_x; A.bc_y = p.bc_y;
+  A.is = fine ? -1 : p.tfsf_i;
+  A.lhz_in = a.hz[a.cur]; A.lhz_out = a.hz[1 - a.cur];
+  A.lex = a.ex; A.ley = a.ey; A.ljx = a.jx; A.ljy = a.jy; A.lacc = a.acc;
+  A.gx = a.gx; A.gy = a.gy; A.kx = a.kx; A.ky = a.ky; A.tex = a.tex; A.tey = a.tey;
+  A.ln = a.n;
+  return A;
+}
+
+AdjContArgs adj_cont_args(const dmr_sim* s, const Level& Lv, AdjLevel& a, bool fine,
+                          const int reg[4]) {
+  const dmr_params& p = s->p;
+  AdjContArgs K{};
+  K.L = reg[0]; K.B = reg[1]; K.R = reg[2]; K.T = reg[3];
+  K.pitch = Lv.pitch; K.plane = Lv.plane; K.fine = fine ? 1 : 0;
+  K.inv_spp = (float)(1.0 / Lv.spp);
+  K.dtn = (float)(Lv.spb * Lv.dt);
+  K.inv_dx2 = (float)(1.0 / (Lv.dx * Lv.dx));
+  K.eeff_p2 = (float)(s->eeff / (1.0e4 * p.p_torr * p.p_torr));
+  K.half_beta = (float)(0.5 * p.beta_ion);
+  K.att = (float)std::pow(p.ecr_over_p, p.beta_ion);
+  K.nuA = (float)(s->nu_m * p.A_ion);
+  K.nu_m = (float)s->nu_m;
+  K.ln_c = (float)std::log(p.ecr_over_p);
+  K.inv_namb = (float)(1.0 / s->n_amb);
+  K.De = (float)s->De; K.Da = (float)s->Da;
+  K.d_const_mode = p.d_mode == DMR_D_CONST;
+  K.d_const = (float)p.d_const;
+  K.ln = a.n; K.lacc = a.acc; K.lring = a.ring; K.ell = a.ell;
+  return K;
+}
+
+AdjGrowArgs adj_grow_args(const dmr_sim* s, AdjLevel& ac, AdjLevel& af, bool had,
+                          const int old[4], const int neu[4], bool with_n) {
+  const dmr_params& p = s->p;
+  const int r = p.r;
+  AdjGrowArgs G{};
+  G.L = r * neu[0]; G.B = r * neu[1]; G.R = r * neu[2]; G.T = r * neu[3];
+  if (had) { G.oL = r * old[0]; G.oB = r * old[1]; G.oR = r * old[2]; G.oT = r * old[3]; }
+  G.cL = std::max(0, neu[0] - 1); G.cB = std::max(0, neu[1] - 1);
+  G.cR = std::min(p.nx, neu[2] + 1); G.cT = std::min(p.ny, neu[3] + 1);
+  G.cNX = p.nx; G.cNY = p.ny;
+  G.pitch = s->L1.pitch; G.cpitch = s->L0.pitch;
+  G.plane = s->L1.plane; G.cplane = s->L0.plane;
+  G.with_n = with_n ? 1 : 0;
+  G.lhz = af.hz[af.cur]; G.lex = af.ex; G.ley = af.ey; G.ljx = af.jx; G.ljy = af.jy;
+  G.ln = af.n; G.lacc = af.acc; G.lring = af.ring;
+  G.chz = ac.hz[ac.cur]; G.chz_prev = ac.hx; G.cex = ac.ex; G.cey = ac.ey;
+  G.cjx = ac.jx; G.cjy = ac.jy; G.cn = ac.n; G.cacc = ac.acc; G.cring = ac.ring;
+  return G;
+}
+
+// adjoint of base step k (meta: what the replay did; ss: its stored values)
+int adj_step(dmr_sim* s, const TapeLayout& T, AdjLevel& ac, AdjLevel& af, int kk,
+             const StepMeta& m, const StepStore& ss, size_t* npart) {
+  const dmr_params& p = s->p;
+  const Level &C = s->L0, &F = s->L1;
+  const int r = p.r;
+  const int creg[4] = {0, 0, p.nx, p.ny};
+  const int freg[4] = {r * m.ext[0], r * m.ext[1], r * m.ext[2], r * m.ext[3]};
+  double* part = (double*)(s->tape.base + T.part);
+  hipError_t e = hipSuccess;
+  if (m.grow) {  // Eq. (5a) prolongation after the step
+    const AdjGrowArgs G = adj_grow_args(s, ac, af, m.has, m.ext, m.gnew, true);
+    e = launch_adj_grow(G, s->st);
+    if (e == hipSuccess)
+      e = launch_adj_grow_clear(G, af.hz[af.cur], af.ex, af.ey, af.jx, af.jy, af.n, af.acc,
+                                af.ring, s->st);
+    if (e != hipSuccess) return hipfail(s, e, "adjoint growth launch");
+  }
+  if (m.sync) {  // window close, continuity, density transfers
+    AdjContArgs K = adj_cont_args(s, C, ac, false, creg);
+    K.slot = m.slot; K.update = m.update;
+    AdjContArgs G{};
+    if (m.has) {
+      G = adj_cont_args(s, F, af, true, freg);
+      G.slot = m.slot; G.update = m.update;
+    }
+    if (m.update) {
+      if (m.has) {
+        AdjInjArgs I{m.ext[0], m.ext[1], m.ext[2], m.ext[3], F.pitch, C.pitch, ac.n, af.n};
+        e = launch_adj_inj(I, s->st);
+        if (e != hipSuccess) return hipfail(s, e, "adjoint transfer launch");
+      }
+      int np = 0;
+      K.n = ss.cn; K.e2 = ss.ce2; K.part = part + 2 * *npart;
+      e = launch_adj_cont(K, &np, s->st);
+      *npart += (size_t)np;
+      if (e == hipSuccess && m.has) {
+        G.n = ss.fn; G.e2 = ss.fe2; G.part = part + 2 * *npart;
+        e = launch_adj_cont(G, &np, s->st);
+        *npart += (size_t)np;
+      }
+    } else {
+      e = launch_adj_close(K, s->st);
+      if (e == hipSuccess && m.has) e = launch_adj_close(G, s->st);
+    }
+    if (e != hipSuccess) return hipfail(s, e, "adjoint continuity launch");
+  }
+  if (m.has) {  // fine -> coarse transfer, substeps 2 and 1, Eq. (5b)
+    AdjRestrictArgs X{m.ext[0], m.ext[1], m.ext[2], m.ext[3], F.pitch, C.pitch,
+                      ac.hz[ac.cur], ac.ex, ac.ey, ac.jx, ac.jy,
+                      af.hz[af.cur], af.ex, af.ey, af.jx, af.jy, af.hx};
+    e = launch_adj_restrict(X, s->st);
+    if (e != hipSuccess) return hipfail(s, e, "adjoint transfer launch");
+    for (int sub = r; sub >= 1; sub--) {
+      AdjEMArgs A = adj_em_args(s, F, af, true, freg);
+      A.exi = sub == 2 ? ss.fex1 : ss.fex0;
+      A.eyi = sub == 2 ? ss.fey1 : ss.fey0;
+      A.exo = sub == 2 ? ss.fex2 : ss.fex1;
+      A.eyo = sub == 2 ? ss.fey2 : ss.fey1;
+      A.n = ss.fn;
+      A.hz_extra = sub == 2 ? af.hx : nullptr;
+      e = launch_adj_em(A, s->st);
+      if (e != hipSuccess) return hipfail(s, e, "adjoint fine EM launch");
+      af.cur = 1 - af.cur;
+      AdjCfbArgs Q{freg[0], freg[1], freg[2], freg[3], m.ext[0], m.ext[1], m.ext[2], m.ext[3],
+                   F.pitch, C.pitch, (float)sub / (float)r, af.gx, af.gy,
+                   ac.ex, ac.ey, ac.pex, ac.pey};
+      e = launch_adj_cfb(Q, s->st);
+      if (e != hipSuccess) return hipfail(s, e, "adjoint boundary launch");
+    }
+  }
+  AdjEMArgs A = adj_em_args(s, C, ac, false, creg);
+  A.exi = ss.cexi; A.eyi = ss.ceyi; A.exo = ss.cexp; A.eyo = ss.ceyp; A.n = ss.cn;
+  A.hz_extra = ac.hx; A.pex = ac.pex; A.pey = ac.pey;
+  if (p.tfsf_i > 0) {
+    float* src = (float*)(s->tape.base + T.src + T.src_size * (size_t)kk);
+    A.src_e = src;
+    A.src_h = src + p.ny;
+  }
+  e = launch_adj_em(A, s->st);
+  if (e != hipSuccess) return hipfail(s, e, "adjoint base EM launch");
+  ac.cur = 1 - ac.cur;
+  return DMR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dmr_adjoint_tape_bytes(const dmr_params* p, int64_t steps, int ckpt_every, size_t* bytes) {
+  std::string why;
+  const int rc = check_params(p, &why);
+  if (rc) return rc;
+  if (!bytes || steps < 1 || ckpt_every < 1) return DMR_EINVAL;
+  *bytes = tape_layout(p, steps, ckpt_every).total;
+  return DMR_OK;
+}
+
+int dmr_forward_record(dmr_sim* s, int64_t steps, int ckpt_every, void* d_tape, size_t bytes) {
+  if (!s) return DMR_EINVAL;
+  if (steps < 1 || ckpt_every < 1) return fail(s, DMR_EINVAL, "steps and ckpt_every must be >= 1");
+  if (s->step != 0) return fail(s, DMR_EINVAL, "recording starts at t = 0 (fresh handle)");
+  if (!d_tape || ((uintptr_t)d_tape & 255)) return fail(s, DMR_EINVAL, "tape must be 256-byte aligned");
+  const TapeLayout T = tape_layout(&s->p, steps, ckpt_every);
+  if (bytes < T.total) return fail(s, DMR_ENOMEM, "tape needs %zu bytes", T.total);
+  AdjTape& tp = s->tape;
+  tp = AdjTape{};
+  tp.base = (char*)d_tape;
+  tp.bytes = bytes;
+  tp.steps = steps;
+  tp.every = ckpt_every;
+  tp.nck = T.nck;
+  tp.ck.resize(T.nck);
+  for (int64_t k = 0; k < steps; k++) {
+    if (k % ckpt_every == 0) {
+      const int idx = (int)(k / ckpt_every);
+      if (int rc = ck_save(s, T, idx, &tp.ck[idx])) return rc;
+    }
+    StepCtx cx;
+    if (int rc = base_step(s, &cx)) return rc;
+    if (cx.meta.grow) {
+      Growth g;
+      g.after = k + 1;
+      for (int q = 0; q < 4; q++) g.ext[q] = cx.meta.gnew[q];
+      tp.grow.push_back(g);
+    }
+  }
+  if (int rc = ck_save(s, T, T.nck, &tp.fin)) return rc;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hipfail(s, e, "record");
+  tp.valid = true;
+  return DMR_OK;
+}
+
+int dmr_backward(dmr_sim* s, const void* d_tape, const float* d_w_coarse,
+                 const float* d_w_fine, float* d_grad_seed, float* d_grad_seed_fine,
+                 double grad[3]) {
+  if (!s) return DMR_EINVAL;
+  AdjTape& tp = s->tape;
+  if (!tp.valid || d_tape != (const void*)tp.base)
+    return fail(s, DMR_EINVAL, "no recorded run on this tape");
+  if (!d_w_coarse) return fail(s, DMR_EINVAL, "coarse weights are required");
+  const dmr_params& p = s->p;
+  const TapeLayout T = tape_layout(&p, tp.steps, tp.every);
+  const Level &C = s->L0, &F = s->L1;
+  const int r = p.r;
+  const bool ref = refined(&p);
+  AdjLevel ac = adj_carve(tp.base + T.adj_c, C.plane);
+  AdjLevel af = ref ? adj_carve(tp.base + T.adj_f, F.plane) : AdjLevel{};
+  HIPCHK(s, hipMemsetAsync(tp.base + T.adj_c, 0, T.ck - T.adj_c, s->st));
+  HIPCHK(s, hipMemsetAsync(tp.base + T.gsum, 0, 256, s->st));
+  HIPCHK(s, hipMemsetAsync(tp.base + T.src, 0, T.src_size * (size_t)tp.every, s->st));
+  // objective: lam n at t_final = the weights
+  hipError_t e = launch_scatter(d_w_coarse, p.nx + 1, p.ny + 1, 1.f, ac.n, C.pitch, 0, 0, s->st);
+  if (e == hipSuccess && ref && d_w_fine)
+    e = launch_scatter(d_w_fine, r * p.nx + 1, r * p.ny + 1, 1.f, af.n, F.pitch, 0, 0, s->st);
+  if (e != hipSuccess) return hipfail(s, e, "weights launch");
+  // incident values per unit amplitude, E0 g sin(...) / E0 (Sec. II.C)
+  {
+    std::vector<double> u((size_t)2 * tp.steps, 0.0);
+    if (p.tfsf_i > 0) {
+      const double xs = p.tfsf_i * C.dx;
+      for (int64_t k = 0; k < tp.steps; k++) {
+        u[2 * k] = ey_inc(s, xs, (double)k * C.dt) / s->e0;
+        u[2 * k + 1] = ey_inc(s, xs - 0.5 * C.dx, ((double)k + 0.5) * C.dt) / s->e0;
+      }
+    }
+    HIPCHK(s, hipMemcpyAsync(tp.base + T.u, u.data(), u.size() * sizeof(double),
+                             hipMemcpyHostToDevice, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+  }
+  std::vector<StepMeta> meta((size_t)tp.every);
+  for (int seg = tp.nck - 1; seg >= 0; seg--) {
+    const int64_t k0 = (int64_t)seg * tp.every;
+    const int64_t k1 = std::min(tp.steps, k0 + tp.every);
+    if (int rc = ck_restore(s, T, seg, tp.ck[seg])) return rc;
+    for (int64_t k = k0; k < k1; k++) {
+      StepCtx cx;
+      cx.store = true;
+      cx.ss = store_slot(s, T, (int)(k - k0));
+      cx.forced = true;
+      for (const Growth& g : tp.grow)
+        if (g.after == k + 1) {
+          cx.force_grow = true;
+          for (int q = 0; q < 4; q++) cx.force_ext[q] = g.ext[q];
+        }
+      if (int rc = base_step(s, &cx)) return rc;
+      meta[(size_t)(k - k0)] = cx.meta;
+    }
+    size_t npart = 0;
+    for (int64_t k = k1 - 1; k >= k0; k--) {
+      const int kk = (int)(k - k0);
+      if (int rc = adj_step(s, T, ac, af, kk, meta[kk], store_slot(s, T, kk), &npart)) return rc;
+    }
+    e = launch_adj_reduce((const float*)(tp.base + T.src), (int)(k1 - k0),
+                          (int)(T.src_size / sizeof(float)), p.ny,
+                          (const double*)(tp.base + T.u) + 2 * k0,
+                          (const double*)(tp.base + T.part), (int)npart,
+                          (double*)(tp.base + T.gsum), s->st);
+    if (e != hipSuccess) return hipfail(s, e, "adjoint reduction launch");
+  }
+  // t = 0: the patch seeded from the coarse density (Eq. (5a))
+  if (ref && s->had0) {
+    const AdjGrowArgs G = adj_grow_args(s, ac, af, false, s->ext0, s->ext0, !s->keep_n0);
+    e = launch_adj_grow(G, s->st);
+    if (e != hipSuccess) return hipfail(s, e, "adjoint seed launch");
+  }
+  if (d_grad_seed) {
+    e = launch_gather(ac.n, C.pitch, 0, 0, p.nx + 1, p.ny + 1, 1.f, d_grad_seed, s->st);
+    if (e != hipSuccess) return hipfail(s, e, "gradient read-out");
+  }
+  if (d_grad_seed_fine && ref) {
+    const int fw = r * p.nx + 1, fh = r * p.ny + 1;
+    HIPCHK(s, hipMemsetAsync(d_grad_seed_fine, 0, (size_t)fw * fh * sizeof(float), s->st));
+    if (s->had0 && s->keep_n0) {
+      const int* x = s->ext0;
+      e = launch_copy2d(af.n, F.pitch, r * x[0], r * x[1], d_grad_seed_fine, fw, r * x[0],
+                        r * x[1], r * (x[2] - x[0]) + 1, r * (x[3] - x[1]) + 1, s->st);
+      if (e != hipSuccess) return hipfail(s, e, "gradient read-out");
+    }
+  }
+  double g3[3] = {0, 0, 0};
+  HIPCHK(s, hipMemcpyAsync(g3, tp.base + T.gsum, sizeof(g3), hipMemcpyDeviceToHost, s->st));
+  // back to t_final
+  if (int rc = ck_restore(s, T, T.nck, tp.fin)) return rc;
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  if (grad) for (int q = 0; q < 3; q++) grad[q] = g3[q];
+  return DMR_OK;
+}
+
+int dmr_weighted_sum(dmr_sim* s, int level, const float* d_w, double* out) {
+  if (!s || !d_w || !out) return DMR_EINVAL;
+  if (level != 0 && !(level == 1 && refined(&s->p)))
+    return fail(s, DMR_EINVAL, "level %d not present", level);
+  const Level& L = level == 0 ? s->L0 : s->L1;
+  double* part = (double*)s->stage;  // 1024 partials + the result
+  if (s->lay.off_stage + 1025 * sizeof(double) > s->lay.total)
+    return fail(s, DMR_ENOMEM, "staging area too small");
+  hipError_t e = launch_wdot(d_w, L.n[s->ncur], L.pitch, 0, 0, L.NX + 1, L.NY + 1, part,
+                             part + 1024, s->st);
+  if (e != hipSuccess) return hipfail(s, e, "weighted sum launch");
+  HIPCHK(s, hipMemcpyAsync(out, part + 1024, sizeof(double), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  return DMR_OK;
 }
 
 }  // extern "C"

@@ -109,4 +109,115 @@ hipError_t launch_ring_sum(const float* ring, size_t plane, int pitch, int i0,
                            int j0, int cols, int rows, float* dst,
                            hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Adjoint (reverse-mode) kernels.  Adjoint planes share the layout of the
+// level they belong to.  "lam" = dF/d(value) for the objective F.
+// ---------------------------------------------------------------------------
+struct AdjEMArgs {
+  int L, B, R, T, pitch;
+  float S, c1, a, kn, cmur, gamma;
+  int fine, bc_x, bc_y, is;
+  const float *exi, *eyi;  // E entering the (sub)step (fine: before the filter)
+  const float *exo, *eyo;  // E leaving it (base: before the fine -> coarse transfer)
+  const float* n;
+  const float* lhz_in;     // lam of Hz leaving the step
+  float* lhz_out;          // lam of Hz entering it
+  float *lex, *ley, *ljx, *ljy;  // lam of E, J: leaving in, entering out
+  const float* lacc;
+  float* hz_extra;         // added to lam Hz entering, then cleared (nullable)
+  float *pex, *pey;        // added to lam E entering, then cleared (nullable)
+  float *gx, *gy, *kx, *ky;  // per-edge temporaries
+  float *tex, *tey;        // fine with filter: lam of the filtered E
+  float* ln;               // lam n (accumulated)
+  float *src_e, *src_h;    // base: per-row source sensitivities (nullable)
+};
+
+struct AdjGrowArgs {
+  int L, B, R, T;      // new patch, fine cells
+  int oL, oB, oR, oT;  // old patch (oR <= oL: none)
+  int cL, cB, cR, cT;  // coarse node positions to gather into
+  int cNX, cNY;        // coarse cells
+  int pitch, cpitch;
+  size_t plane, cplane;
+  int with_n;
+  const float *lhz, *lex, *ley, *ljx, *ljy, *ln, *lacc, *lring;   // fine lam
+  float *chz, *chz_prev, *cex, *cey, *cjx, *cjy, *cn, *cacc, *cring;  // coarse lam
+};
+
+struct AdjCfbArgs {
+  int L, B, R, T;        // fine patch (fine cells)
+  int I0, J0, I1, J1;    // coarse patch
+  int pitch, cpitch;
+  float frac;
+  const float *gx, *gy;  // fine: lam of the boundary E values
+  float *lcex, *lcey;    // coarse lam E after the coarse step
+  float *pcex, *pcey;    // coarse lam E before it (pending)
+};
+
+struct AdjRestrictArgs {
+  int I0, J0, I1, J1, pitch, cpitch;
+  float *lchz, *lcex, *lcey, *lcjx, *lcjy;
+  float *lfhz, *lfex, *lfey, *lfjx, *lfjy, *hz_extra;
+};
+
+struct AdjContArgs {
+  int L, B, R, T, pitch;
+  size_t plane;
+  int fine, slot, update;
+  float inv_spp, dtn, inv_dx2, eeff_p2, half_beta, att, nuA, nu_m, ln_c;
+  float inv_namb, De, Da;
+  int d_const_mode;
+  float d_const;
+  const float* n;   // density entering the continuity step
+  const float* e2;  // E_rms^2 the step used
+  float* ln;        // lam n: leaving in, entering out
+  float* lacc;
+  float* lring;
+  float* ell;       // temporary: clamp mask times lam n leaving
+  double* part;     // per-block (dF/dA, dF/dbeta) partial sums
+};
+
+struct AdjInjArgs {
+  int I0, J0, I1, J1, pitch, cpitch;
+  float *lcn, *lfn;
+};
+
+struct CopyJob {
+  const float* src;
+  float* dst;
+  size_t n;  // floats, a multiple of 4
+};
+constexpr int kMaxCopyJobs = 40;
+struct CopyJobs {
+  CopyJob job[kMaxCopyJobs];
+  int count;
+};
+
+hipError_t launch_adj_em(const AdjEMArgs& A, hipStream_t st);
+hipError_t launch_adj_grow(const AdjGrowArgs& A, hipStream_t st);
+hipError_t launch_adj_grow_clear(const AdjGrowArgs& A, float* lhz, float* lex, float* ley,
+                                 float* ljx, float* ljy, float* ln, float* lacc,
+                                 float* lring, hipStream_t st);
+// rows x cols block between two pitched arrays
+hipError_t launch_copy2d(const float* src, int spitch, int si0, int sj0, float* dst,
+                         int dpitch, int di0, int dj0, int cols, int rows, hipStream_t st);
+hipError_t launch_adj_cfb(const AdjCfbArgs& A, hipStream_t st);
+hipError_t launch_adj_restrict(const AdjRestrictArgs& A, hipStream_t st);
+hipError_t launch_adj_inj(const AdjInjArgs& A, hipStream_t st);
+// continuity adjoint; returns the number of partial pairs written
+hipError_t launch_adj_cont(const AdjContArgs& A, int* nparts, hipStream_t st);
+hipError_t launch_adj_close(const AdjContArgs& A, hipStream_t st);
+hipError_t launch_copy(const CopyJobs& J, hipStream_t st);
+hipError_t launch_ring_e2(const float* ring, size_t plane, int pitch, int L, int B,
+                          int R, int T, float* dst, hipStream_t st);
+// out[0] += sum_k u[2k] sum_j src_e[k][j] + u[2k+1] sum_j src_h[k][j]
+// (src_e of step k at src + k*step_pitch, src_h rows floats after it);
+// out[1..2] += sum of the (dF/dA, dF/dbeta) partial pairs
+hipError_t launch_adj_reduce(const float* src, int nsteps, int step_pitch, int rows,
+                             const double* u, const double* part, int nparts, double* out,
+                             hipStream_t st);
+// sum over a pitched region of w (dense, cols x rows) times a (pitched)
+hipError_t launch_wdot(const float* w, const float* a, int pitch, int i0, int j0,
+                       int cols, int rows, double* part, double* out, hipStream_t st);
+
 }  // namespace dmr

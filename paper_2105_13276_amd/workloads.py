@@ -168,3 +168,26 @@ def config3_instance(i, periods=200):
 def config3(count=64, periods=200):
     cfgs = [config3_instance(i, periods) for i in range(count)]
     return cfgs, [seeds(c) for c in cfgs]
+
+
+def config4(steps=2000):
+    """Adjoint form: the config-1 refined case (512 x 256 coarse, r = 2,
+    growing patch) for `steps` coarse steps; objective = integral of n over
+    a wavelength-square window centred on the seed."""
+    cfg = make(512, 256, 32, "dynamic", 1)
+    cfg["steps"] = steps
+    return cfg
+
+
+def window_weights(cfg, centre=None, side=None):
+    """Quadrature weights dx^2 on the coarse nodes within |x - x0| <= side/2,
+    |y - y0| <= side/2 (default: one wavelength around the domain centre,
+    where the config seeds sit)."""
+    lam = C0 / cfg["freq_hz"]
+    dx = lam / cfg["cells_per_lambda"]
+    if centre is None:
+        centre = (0.5 * cfg["nx"] * dx, 0.5 * cfg["ny"] * dx)
+    side = lam if side is None else side
+    X, Y = node_coords(cfg["nx"], cfg["ny"], dx)
+    inside = (np.abs(X - centre[0]) <= side / 2) & (np.abs(Y - centre[1]) <= side / 2)
+    return inside.astype(np.float64) * dx * dx

@@ -76,3 +76,15 @@ def test_workspace_covers_full_domain_patch():
     # 21 planes per level, fine level r^2 larger: > 21*4*(1+4)*nodes bytes
     nodes = (cfg["nx"] + 1) * (cfg["ny"] + 1)
     assert nb >= 21 * 4 * 5 * nodes
+
+
+def test_adjoint_tape_sizing():
+    cfg = W.config4(steps=2000)
+    p = B.make_params(cfg)
+    n = C.c_size_t()
+    assert B.lib().dmr_adjoint_tape_bytes(C.byref(p), 2000, 45, C.byref(n)) == 0
+    big = n.value
+    assert B.lib().dmr_adjoint_tape_bytes(C.byref(p), 2000, 200, C.byref(n)) == 0
+    assert n.value != big
+    assert B.lib().dmr_adjoint_tape_bytes(C.byref(p), 0, 45, C.byref(n)) == -1
+    assert B.lib().dmr_adjoint_tape_bytes(C.byref(p), 2000, 0, C.byref(n)) == -1

@@ -1,0 +1,116 @@
+"""GPU adjoint (hand-written reverse-mode kernels behind dmr_forward_record /
+dmr_backward) against the FP64 reference adjoint (torch float64 model of the
+update with autograd, itself pinned to central differences of the C oracle).
+
+Bar: FP32 forward/adjoint vs FP64 adjoint <= 1e-3 relative on dF/dE0,
+dF/dA, dF/dbeta and in relative L2 on dF/dseed.  FP32 finite differences
+are noise-limited (~eps32/h), so they are reported with a loose bound."""
+import numpy as np
+import pytest
+
+from paper_2105_13276_amd import binding as B
+from paper_2105_13276_amd import workloads as W
+
+from adjoint_cases import CENTRE, case, history, reference_gradients, window
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-3
+
+
+def _gpu(cfg, sb, w, every):
+    g = B.Sim(cfg, sb, None)
+    g.record(cfg["steps"], every)
+    F = g.weighted_sum(w)
+    out = g.backward(w)
+    out = dict(out, seed=out["seed"].cpu().numpy().astype(np.float64), F=F,
+               patch=g.patch())
+    return g, out
+
+
+def _rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("mode", ["uniform", "static", "dynamic"])
+def test_adjoint_matches_fp64_reference(mode):
+    cfg, sb = case(mode)
+    w = window(cfg, CENTRE[mode])
+    o, ext0, growth = history(cfg, sb)
+    print("case %s: %d steps, patch at t=0 %s, growth %s" % (mode, cfg["steps"], ext0, growth),
+          flush=True)
+    g, got = _gpu(cfg, sb, w, every=17)
+    if mode != "uniform":
+        assert got["patch"] == o.patch()
+    ref = reference_gradients(cfg, sb, w, ext0, growth)
+    errs = {"F": _rel(got["F"], ref["F"]), "E0": _rel(got["E0"], ref["E0"]),
+            "A": _rel(got["A"], ref["A"]), "beta": _rel(got["beta"], ref["beta"]),
+            "seed": _rel_l2(got["seed"], ref["seed"])}
+    print("case %s: relative errors vs FP64 %s" % (mode, errs), flush=True)
+    for k, v in errs.items():
+        assert v <= TOL, (k, v, errs)
+
+
+def test_segments_do_not_change_the_result():
+    """Checkpoint spacing changes only the order of the scalar sums."""
+    cfg, sb = case("dynamic")
+    w = window(cfg, CENTRE["dynamic"])
+    g1, a = _gpu(cfg, sb, w, every=17)
+    g2, b = _gpu(cfg, sb, w, every=cfg["steps"])
+    assert np.array_equal(a["seed"], b["seed"])
+    for k in ("E0", "A", "beta"):
+        assert a[k] == pytest.approx(b[k], rel=1e-12)
+    # the handle is back at t_final after the reverse sweep
+    n1 = g1.get("n")
+    g3 = B.Sim(cfg, sb, None)
+    g3.step(cfg["steps"])
+    assert np.array_equal(n1, g3.get("n"))
+    assert np.array_equal(g1.get("ey", 1), g3.get("ey", 1))
+
+
+def test_central_differences_fp32_reported():
+    """dF/dA and dF/dbeta against 4th-order central differences of the FP32
+    forward (relative step 1e-3): reported; bounded loosely (FP32 noise)."""
+    cfg, sb = case("static")
+    w = window(cfg, CENTRE["static"])
+    _, got = _gpu(cfg, sb, w, every=45)
+
+    def F(over):
+        s = B.Sim(dict(cfg, **over), sb, None)
+        s.step(cfg["steps"])
+        return s.weighted_sum(w)
+
+    h = 1e-3
+    for name, key in (("A", "A_ion"), ("beta", "beta_ion"), ("E0", "erms_over_ebd")):
+        f = {q: F({key: cfg[key] * (1 + q * h)}) for q in (-2, -1, 1, 2)}
+        fd = (8 * (f[1] - f[-1]) - (f[2] - f[-2])) / (12 * h * cfg[key])
+        ad = got[name]
+        if name == "E0":
+            from paper_2105_13276_amd.adjoint import e0_of
+            ad = got["E0"] * e0_of(cfg) / cfg["erms_over_ebd"]
+        print("FD %s: adjoint %.6e  FP32 central difference %.6e  rel %.2e"
+              % (name, ad, fd, _rel(ad, fd)), flush=True)
+        assert _rel(ad, fd) < 5e-2
+
+
+def test_autograd_function():
+    import torch
+    from paper_2105_13276_amd.adjoint import WindowDensity
+    cfg, sb = case("static")
+    w = window(cfg, CENTRE["static"])
+    seed = torch.tensor(sb, requires_grad=True)
+    s = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    A = torch.tensor(cfg["A_ion"], dtype=torch.float64, requires_grad=True)
+    beta = torch.tensor(cfg["beta_ion"], dtype=torch.float64, requires_grad=True)
+    F = WindowDensity.apply(seed, s, A, beta, cfg, w, cfg["steps"], 45)
+    F.backward()
+    _, got = _gpu(cfg, sb, w, every=45)
+    assert F.item() == pytest.approx(got["F"], rel=1e-12)
+    assert np.array_equal(seed.grad.numpy(), got["seed"])
+    from paper_2105_13276_amd.adjoint import e0_of
+    assert s.grad.item() == pytest.approx(got["E0"] * e0_of(cfg), rel=1e-12)
+    assert A.grad.item() == pytest.approx(got["A"], rel=1e-12)
+    assert beta.grad.item() == pytest.approx(got["beta"], rel=1e-12)

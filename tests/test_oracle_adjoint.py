@@ -7,58 +7,13 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import oracle as O
 from oracle import torch_model as TM
-from paper_2105_13276_amd import workloads as W
 
-LAM = 299792458.0 / 110e9
-
-
-CENTRE = {"static": (57 * LAM / 32, 24 * LAM / 32), "uniform": (57 * LAM / 32, 24 * LAM / 32),
-          "dynamic": (96 * 0.62 * LAM / 32, 24 * LAM / 32)}
-
-
-def _case(mode="static", periods=10):
-    if mode == "static":
-        cfg = W.make(96, 48, 32, "static", periods, static_ext=(48, 16, 64, 32),
-                     erms_over_ebd=2.5)
-        sb, _ = W.seeds(cfg, [CENTRE[mode]], [3e17])
-    elif mode == "dynamic":
-        # grows once, after 8 of the 10 periods (regrid every 2 periods)
-        cfg = W.make(96, 48, 32, "dynamic", periods, erms_over_ebd=3.0)
-        cfg["regrid_every"] = 2 * cfg["steps_per_period"]
-        sb, _ = W.seeds(cfg, [CENTRE[mode]], [3e17])
-    else:
-        cfg = W.make(64, 32, 32, "uniform", periods, erms_over_ebd=2.5)
-        sb, _ = W.seeds(cfg, [CENTRE[mode]], [3e17])
-    return cfg, sb
-
-
-def history(cfg, sb):
-    """C oracle run to t_final: (sim, patch at t = 0, {steps done: new patch})."""
-    o = O.Sim(cfg, sb)
-    if cfg["mode"] == "uniform":
-        o.step(cfg["steps"])
-        return o, None, {}
-    ext0 = o.patch()
-    growth, cur, k = {}, ext0, 0
-    every = cfg["regrid_every"] if cfg["mode"] == "dynamic" else cfg["steps"]
-    while k < cfg["steps"]:
-        q = min(every, cfg["steps"] - k)
-        o.step(q)
-        k += q
-        if o.patch() != cur:
-            growth[k] = cur = o.patch()
-    return o, ext0, growth
+from adjoint_cases import CENTRE, case as _case, history, window
 
 
 def _window(cfg, centre):
-    dx = LAM / cfg["cells_per_lambda"]
-    x = np.arange(cfg["nx"] + 1) * dx
-    y = np.arange(cfg["ny"] + 1) * dx
-    X, Y = np.meshgrid(x, y)
-    w = ((np.abs(X - centre[0]) <= LAM / 2) & (np.abs(Y - centre[1]) <= LAM / 2)).astype(float)
-    return w * dx * dx
+    return window(cfg, centre)
 
 
 def _c_objective(cfg, sb, w, layout):
