@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched 64-instance comparison")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint (record + reverse sweep) measurement")
     ap.add_argument("--only-large", action="store_true",
                     help="profiling aid: run only 4096x2048 base steps and a "
                          "256 MiB device copy (counter calibration), no JSON")
@@ -105,6 +107,51 @@ def run_case(B, cfg, seeds, chunks, chunk, warmup, timing):
     return sim, wall, work
 
 
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def adjoint_leg(B, W, torch, steps=2000, every=45):
+    """Plain forward vs recorded forward + reverse sweep of the adjoint
+    workload (gradients of the window density w.r.t. seed, E0, A, beta)."""
+    cfg = W.config4(steps=steps)
+    sb, _ = W.seeds(cfg, fine=False)
+    w = W.window_weights(cfg)
+    warm = B.Sim(cfg, sb, None)          # same kernels once, untimed
+    warm.record(2 * every, every)
+    warm.backward(w)
+    warm.close()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    plain = B.Sim(cfg, sb, None)
+    t_plain = timed(lambda: (plain.step(steps), plain.sync()))
+    ext = plain.patch()
+    plain.close()
+    g = B.Sim(cfg, sb, None)
+    t_rec = timed(lambda: g.record(steps, every))
+    res = {}
+    t_bwd = timed(lambda: res.update(g.backward(w)))
+    tape_gb = g.tape.numel() / 1e9
+    g.close()
+    fine = 4 * (ext[2] - ext[0]) * (ext[3] - ext[1])
+    work = steps * (cfg["nx"] * cfg["ny"] + 2 * fine)
+    return {"workload": "adjoint: coarse 512x256 @ lambda/32 + r=2 patch, %d coarse steps, "
+                        "checkpoint every %d, window lambda x lambda at the seed"
+                        % (steps, every),
+            "forward_s": t_plain, "record_s": t_rec, "backward_s": t_bwd,
+            "gradient_over_forward": (t_rec + t_bwd) / t_plain,
+            "forward_mcell_updates_per_s": work / t_plain / 1e6,
+            "gradient_mcell_updates_per_s": work / (t_rec + t_bwd) / 1e6,
+            "tape_GB": tape_gb,
+            "dF_dE0": res["E0"], "dF_dA": res["A"], "dF_dbeta": res["beta"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -124,6 +171,7 @@ def main():
     periods = K * INTERVAL // 64
 
     # ---- DMR run --------------------------------------------------------
+    log("DMR config 1, %d periods" % periods)
     cfg_d = W.config1_dmr(periods=periods)
     seeds_d = W.seeds(cfg_d)
     n_coarse = K * INTERVAL
@@ -139,6 +187,7 @@ def main():
     sim_t.close()
 
     # ---- uniform-fine run -------------------------------------------------
+    log("uniform-fine 1024x512")
     cfg_u = W.config1_uniform(periods=periods)
     seeds_u = W.seeds(cfg_u)
     sim_u, wall_u, work_u = run_case(B, cfg_u, seeds_u, K, 2 * INTERVAL, Wm, False)
@@ -191,6 +240,7 @@ def main():
 
     # ---- bandwidth-bound shape: 4096x2048 coarse (added large row) --------
     if not args.no_large:
+        log("4096x2048 kernel and DMR vs uniform-fine")
         cfg_l = W.config_large(periods=1)
         seeds_l = W.seeds(cfg_l, fine=False)
         sim_l = B.Sim(cfg_l, seeds_l[0], None)
@@ -223,6 +273,7 @@ def main():
 
     # ---- batched form: 64 independent DMR runs (config-3 draw) -----------
     if not args.no_batch:
+        log("batched %d instances" % args.batch_count)
         cfgs, seeds3 = W.config3(args.batch_count, periods=16)
         warm, timed = 2 * INTERVAL, 2 * INTERVAL
         bt = B.Batch(cfgs, seeds3)
@@ -262,8 +313,14 @@ def main():
             "launch_shape": {"seg": shape[0], "depth": shape[1], "fine_ty": shape[2],
                              "graph": shape[3]}}
 
+    # ---- adjoint form: config-1 setup, 2000 coarse steps, checkpoint 45 ----
+    if not args.no_adjoint:
+        log("adjoint config 4")
+        out["adjoint"] = adjoint_leg(B, W, torch)
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample ---------------
     if not args.no_cpu:
+        log("CPU oracle sample")
         from oracle import oracle as O
         o = O.Sim(cfg_d, *seeds_d)
         e0 = o.patch()

@@ -316,16 +316,19 @@ int stream_rows(int NX, int NY) {
     const int v = atoi(e);
     if (v >= 2) return v;
   }
+  // a wave walks its rows one memory round trip (over the load depth) apart:
+  // small grids take short segments and many waves
   const long waves_x = (NX + 1 + 61) / 62;
   int seg = 64;
-  while (seg > 4 && waves_x * ((NY + seg) / seg) < 4096) seg >>= 1;
+  while (seg > 2 && waves_x * ((NY + seg) / seg) < 8192) seg >>= 1;
   return seg;
 }
 
-// rows in flight per wave: deep for short (latency-bound) segments
+// rows in flight per wave (measured: 2 for segments of up to 4 rows and for
+// long bandwidth-bound ones, 4 in between)
 int stream_depth(int seg) {
   if (const char* e = getenv("DMR_DEPTH")) return atoi(e) >= 4 ? 4 : 2;
-  return seg <= 8 ? 4 : 2;
+  return (seg >= 8 && seg <= 16) ? 4 : 2;
 }
 
 int tile_rows(int NX, int NY) {
@@ -1419,7 +1422,7 @@ struct dmr_batch {
 
 namespace {
 
-constexpr int kSegCand[] = {4, 8, 16, 32, 64};
+constexpr int kSegCand[] = {2, 4, 8, 16, 32, 64};
 constexpr int kTyCand[] = {4, 8, 16};
 
 struct BatchLayout {
@@ -1650,7 +1653,7 @@ int batch_tune(dmr_batch* b, int64_t* used) {
   int rc = DMR_OK;
   for (int c = 0; c < ncand && !rc; c++) {
     b->seg = kSegCand[c % nseg];
-    b->depth = b->seg <= 8 ? 4 : 2;
+    b->depth = stream_depth(b->seg);
     b->ty = kTyCand[c % nty];
     rc = batch_tables(b);
     float tbase = 0.f, tfine = 0.f;

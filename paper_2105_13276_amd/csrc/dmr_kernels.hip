@@ -22,71 +22,158 @@
 namespace dmr {
 
 // ---------------------------------------------------------------------------
-// EM step of one level (Eqs. (1)-(3)), one TX x TY tile of nodes per block.
-// The tile owns Hz(i,j), Ex(i,j), Ey(i,j) and node (i,j) for (i,j) in the
-// tile.  It stages old E over [i0-2, i0+TX] x [j0-2, j0+TY] in LDS, computes
-// new Hz over [i0-2, i0+TX) x [j0-2, j0+TY), new E over [i0-1, i0+TX) x
-// [j0-1, j0+TY) (the halo feeds the node window and the Mur boundary), and
-// then the nodes' E^2.
-//   FINE = false: the base level; outer tangential edges by Mur/PEC, the
-//                 TF/SF source on column is.
-//   FINE = true:  the patch; tangential E on its boundary from the coarse
-//                 mesh by Eq. (5b); with restrict_on, the fine -> coarse
-//                 transfer of the coarse entities strictly inside the patch.
+// EM substep of the fine patch (Eqs. (1)-(3)), one TX x TY tile of nodes per
+// block.  The tile owns Hz(i,j), Ex(i,j), Ey(i,j) and node (i,j) for (i,j)
+// in the tile.  It needs old E over [i0-2, i0+TX] x [j0-2, j0+TY] (after the
+// patch's E filter, which reads raw E two further out), computes new Hz over
+// [i0-2, i0+TX) x [j0-2, j0+TY) and new E over [i0-1, i0+TX) x
+// [j0-1, j0+TY) (the halo feeds the node window), then the nodes' E^2.
+// Tangential E on the patch boundary comes from the coarse mesh by Eq. (5b);
+// with restrict_on, the tile also writes the fine -> coarse transfer of the
+// coarse entities strictly inside the patch.
+//
+// Every global value the tile reads is requested in one batch at the start
+// (registers), so the block waits for memory once; the phases after that
+// run from LDS and registers.
 // ---------------------------------------------------------------------------
-template <bool FINE, int TY>
-__device__ __forceinline__ void em_tile(const EMArgs& A, int bx, int by) {
-  constexpr int EW = kTX + 3, EH = TY + 3;  // old E
+template <int TY>
+__device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
+  constexpr int EW = kTX + 3, EH = TY + 3;  // old E (filtered)
   constexpr int HW = kTX + 2, HH = TY + 2;  // new Hz
   constexpr int NW = kTX + 1, NH = TY + 1;  // new E
   constexpr int DW = kTX + 2, DH = TY + 2;  // density
-  __shared__ float sExo[EH][EW], sEyo[EH][EW];
-  __shared__ float sH[HH][HW];
-  __shared__ float sExn[NH][NW], sEyn[NH][NW];
-  __shared__ float sN[DH][DW];
-  __shared__ float sJx[FINE ? TY : 1][FINE ? kTX : 1];
-  __shared__ float sJy[FINE ? TY : 1][FINE ? kTX : 1];
-  // fine level: raw old E over [i0-4, i0+TX+2] x [j0-4, j0+TY+2] and its
-  // Laplacian over [i0-3, i0+TX+1] x [j0-3, j0+TY+1] for the filter
-  constexpr int RW = FINE ? kTX + 7 : 1, RH = FINE ? TY + 7 : 1;
-  constexpr int QW = FINE ? kTX + 5 : 1, QH = FINE ? TY + 5 : 1;
+  constexpr int RW = kTX + 7, RH = TY + 7;  // raw E for the filter
+  constexpr int QW = kTX + 5, QH = TY + 5;  // Laplacian of raw E
+  constexpr int NR = (RH * RW + kThreads - 1) / kThreads;
+  constexpr int NO = (EH * EW + kThreads - 1) / kThreads;
+  constexpr int ND = (DH * DW + kThreads - 1) / kThreads;
+  constexpr int NHZ = (HH * HW + kThreads - 1) / kThreads;
+  constexpr int NE = (NH * NW + kThreads - 1) / kThreads;
+  constexpr int NA = TY / (kThreads / kTX);
   __shared__ float rEx[RH][RW], rEy[RH][RW];
   __shared__ float qEx[QH][QW], qEy[QH][QW];
+  __shared__ float sExo[EH][EW], sEyo[EH][EW];
+  __shared__ float sH[HH][HW], sHo[HH][HW];
+  __shared__ float sExn[NH][NW], sEyn[NH][NW];
+  __shared__ float sN[DH][DW];
+  __shared__ float sJx[TY][kTX], sJy[TY][kTX];
+  __shared__ float sB[5][NW > NH ? NW : NH];  // Eq. (5b) values: Ex rows B, T; Ey columns L, R
 
   const int i0 = A.L + bx * kTX;
   const int j0 = A.B + by * TY;
   const int tid = threadIdx.x;
   const int L = A.L, R = A.R, B = A.B, T = A.T;
   const int pitch = A.pitch;
+  const bool filt = A.gamma > 0.f;
   auto hz_ok = [&](int i, int j) { return i >= L && i < R && j >= B && j < T; };
   auto ex_ok = [&](int i, int j) { return i >= L && i < R && j >= B && j <= T; };
   auto ey_ok = [&](int i, int j) { return i >= L && i <= R && j >= B && j < T; };
   auto nd_ok = [&](int i, int j) { return i >= L && i <= R && j >= B && j <= T; };
+  // clamped (always valid) addresses of each entity kind
+  auto cl = [&](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
+  auto o_hz = [&](int i, int j) { return (size_t)cl(j, B, T - 1) * pitch + cl(i, L, R - 1); };
+  auto o_ex = [&](int i, int j) { return (size_t)cl(j, B, T) * pitch + cl(i, L, R - 1); };
+  auto o_ey = [&](int i, int j) { return (size_t)cl(j, B, T - 1) * pitch + cl(i, L, R); };
+  auto o_nd = [&](int i, int j) { return (size_t)cl(j, B, T) * pitch + cl(i, L, R); };
 
-  // -- stage old E and density ----------------------------------------------
-  if (!FINE || A.gamma <= 0.f) {
-    for (int k = tid; k < EH * EW; k += kThreads) {
-      const int ci = k % EW, cj = k / EW;
-      const int i = i0 - 2 + ci, j = j0 - 2 + cj;
-      float ex = 0.f, ey = 0.f;
-      if (ex_ok(i, j)) ex = A.ex0[(size_t)j * pitch + i];
-      if (ey_ok(i, j)) ey = A.ey0[(size_t)j * pitch + i];
-      sExo[cj][ci] = ex;
-      sEyo[cj][ci] = ey;
+  // -- one batch of global loads ------------------------------------------------
+  constexpr int NP = NR > NO ? NR : NO;
+  float pex[NP], pey[NP];
+  if (filt) {
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
+      const int k = min(tid + q * kThreads, RH * RW - 1);
+      const int i = i0 - 4 + k % RW, j = j0 - 4 + k / RW;
+      pex[q] = A.ex0[o_ex(i, j)];
+      pey[q] = A.ey0[o_ey(i, j)];
     }
   } else {
-    // Fine patch: weak fourth-order hyper-diffusion of the interior E before
-    // the substep, E <- E - gamma L(L(E)) per component on its own grid,
-    // neighbours outside the patch replaced by the centre value; the
-    // coarse-driven boundary edges are left as they are.
-    for (int k = tid; k < RH * RW; k += kThreads) {
-      const int ci = k % RW, cj = k / RW;
-      const int i = i0 - 4 + ci, j = j0 - 4 + cj;
-      float ex = 0.f, ey = 0.f;
-      if (ex_ok(i, j)) ex = A.ex0[(size_t)j * pitch + i];
-      if (ey_ok(i, j)) ey = A.ey0[(size_t)j * pitch + i];
-      rEx[cj][ci] = ex;
-      rEy[cj][ci] = ey;
+#pragma unroll
+    for (int q = 0; q < NO; q++) {
+      const int k = min(tid + q * kThreads, EH * EW - 1);
+      const int i = i0 - 2 + k % EW, j = j0 - 2 + k / EW;
+      pex[q] = A.ex0[o_ex(i, j)];
+      pey[q] = A.ey0[o_ey(i, j)];
+    }
+  }
+  float pn[ND];
+#pragma unroll
+  for (int q = 0; q < ND; q++) {
+    const int k = min(tid + q * kThreads, DH * DW - 1);
+    pn[q] = A.n[o_nd(i0 - 1 + k % DW, j0 - 1 + k / DW)];
+  }
+  float phz[NHZ];
+#pragma unroll
+  for (int q = 0; q < NHZ; q++) {
+    const int k = min(tid + q * kThreads, HH * HW - 1);
+    phz[q] = A.hz0[o_hz(i0 - 2 + k % HW, j0 - 2 + k / HW)];
+  }
+  float pjx[NE], pjy[NE];
+#pragma unroll
+  for (int q = 0; q < NE; q++) {
+    const int k = min(tid + q * kThreads, NH * NW - 1);
+    const int i = i0 - 1 + k % NW, j = j0 - 1 + k / NW;
+    pjx[q] = A.jx0[o_ex(i, j)];
+    pjy[q] = A.jy0[o_ey(i, j)];
+  }
+  const int tx = tid % kTX, ty = tid / kTX;
+  float pacc[NA];
+#pragma unroll
+  for (int q = 0; q < NA; q++) pacc[q] = A.acc[o_nd(i0 + tx, j0 + ty + q * (kThreads / kTX))];
+  // Eq. (5b) boundary values: x-edges of rows B and T, y-edges of columns L
+  // and R inside this tile's new-E region, linear in space between the two
+  // nearest coarse edges (weights w0, w1) and in time between the old and
+  // new coarse E.  Loads are unconditional (address 0 where unused).
+  int bg = -1, bc = 0;
+  if (tid < NW) { bg = 0; bc = tid; }
+  else if (tid < 2 * NW) { bg = 1; bc = tid - NW; }
+  else if (tid < 2 * NW + NH) { bg = 2; bc = tid - 2 * NW; }
+  else if (tid < 2 * NW + 2 * NH) { bg = 3; bc = tid - 2 * NW - NH; }
+  size_t bco = 0, bco2 = 0;
+  float bw0 = 0.f, bw1 = 0.f;
+  bool bvalid = false;
+  if (bg == 0 || bg == 1) {
+    const int i = i0 - 1 + bc, j = bg == 0 ? B : T;
+    if (ex_ok(i, j) && j >= j0 - 1 && j < j0 + TY) {
+      const int J = j >> 1;
+      int ic;
+      if ((i & 1) == 0) { ic = (i >> 1) - 1; bw0 = 0.25f; bw1 = 0.75f; }
+      else              { ic = i >> 1;       bw0 = 0.75f; bw1 = 0.25f; }
+      bco = (size_t)J * A.cpitch + ic;
+      bco2 = bco + 1;
+      bvalid = true;
+    }
+  } else if (bg >= 2) {
+    const int j = j0 - 1 + bc, i = bg == 2 ? L : R;
+    if (ey_ok(i, j) && i >= i0 - 1 && i < i0 + kTX) {
+      const int I = i >> 1;
+      int jc;
+      if ((j & 1) == 0) { jc = (j >> 1) - 1; bw0 = 0.25f; bw1 = 0.75f; }
+      else              { jc = j >> 1;       bw0 = 0.75f; bw1 = 0.25f; }
+      bco = (size_t)jc * A.cpitch + I;
+      bco2 = bco + A.cpitch;
+      bvalid = true;
+    }
+  }
+  const float* bp0 = bg >= 2 ? A.cey0 : A.cex0;
+  const float* bp1 = bg >= 2 ? A.cey1 : A.cex1;
+  const float bo0 = bp0[bco], bo1 = bp0[bco2], bn0 = bp1[bco], bn1 = bp1[bco2];
+
+  // -- old E: raw, Laplacian, filtered ----------------------------------------
+  // Weak fourth-order hyper-diffusion of the patch's interior E before the
+  // substep, E <- E - gamma L(L(E)) per component on its own grid, with
+  // neighbours outside the patch replaced by the centre value; the
+  // coarse-driven boundary edges are left as they are.
+  if (filt) {
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
+      const int k = tid + q * kThreads;
+      if (k < RH * RW) {
+        const int ci = k % RW, cj = k / RW;
+        const int i = i0 - 4 + ci, j = j0 - 4 + cj;
+        rEx[cj][ci] = ex_ok(i, j) ? pex[q] : 0.f;
+        rEy[cj][ci] = ey_ok(i, j) ? pey[q] : 0.f;
+      }
     }
     __syncthreads();
     for (int k = tid; k < QH * QW; k += kThreads) {
@@ -138,157 +225,112 @@ __device__ __forceinline__ void em_tile(const EMArgs& A, int bx, int by) {
       sExo[cj][ci] = ex;
       sEyo[cj][ci] = ey;
     }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NO; q++) {
+      const int k = tid + q * kThreads;
+      if (k < EH * EW) {
+        const int ci = k % EW, cj = k / EW;
+        const int i = i0 - 2 + ci, j = j0 - 2 + cj;
+        sExo[cj][ci] = ex_ok(i, j) ? pex[q] : 0.f;
+        sEyo[cj][ci] = ey_ok(i, j) ? pey[q] : 0.f;
+      }
+    }
   }
-  for (int k = tid; k < DH * DW; k += kThreads) {
-    const int ci = k % DW, cj = k / DW;
-    const int i = i0 - 1 + ci, j = j0 - 1 + cj;
-    sN[cj][ci] = nd_ok(i, j) ? A.n[(size_t)j * pitch + i] : 0.f;
+#pragma unroll
+  for (int q = 0; q < ND; q++) {
+    const int k = tid + q * kThreads;
+    if (k < DH * DW) {
+      const int ci = k % DW, cj = k / DW;
+      sN[cj][ci] = nd_ok(i0 - 1 + ci, j0 - 1 + cj) ? pn[q] : 0.f;
+    }
+  }
+  {  // every thread writes (row 4 is a dummy), so the loads above stay put
+    const float vo = bw0 * bo0 + bw1 * bo1;
+    const float vn = bw0 * bn0 + bw1 * bn1;
+    sB[bg < 0 ? 4 : bg][bg < 0 ? 0 : bc] = bvalid ? (1.f - A.frac) * vo + A.frac * vn : 0.f;
   }
   __syncthreads();
 
   // -- Faraday, Eq. (2) -------------------------------------------------------
-  for (int k = tid; k < HH * HW; k += kThreads) {
-    const int ci = k % HW, cj = k / HW;
-    const int i = i0 - 2 + ci, j = j0 - 2 + cj;
-    float h = 0.f;
-    if (hz_ok(i, j)) {
-      const size_t o = (size_t)j * pitch + i;
-      const float dey = sEyo[cj][ci + 1] - sEyo[cj][ci];
-      const float dex = sExo[cj + 1][ci] - sExo[cj][ci];
-      h = A.hz0[o] - A.S * (dey - dex);
-      if (!FINE && i == A.is - 1) h += A.S * A.ey_src;  // scattered-field side
-      if (ci >= 2 && cj >= 2) A.hz1[o] = h;
+#pragma unroll
+  for (int q = 0; q < NHZ; q++) {
+    const int k = tid + q * kThreads;
+    if (k < HH * HW) {
+      const int ci = k % HW, cj = k / HW;
+      const int i = i0 - 2 + ci, j = j0 - 2 + cj;
+      float h = 0.f, ho = 0.f;
+      if (hz_ok(i, j)) {
+        const size_t o = (size_t)j * pitch + i;
+        const float dey = sEyo[cj][ci + 1] - sEyo[cj][ci];
+        const float dex = sExo[cj + 1][ci] - sExo[cj][ci];
+        ho = phz[q];
+        h = ho - A.S * (dey - dex);
+        if (ci >= 2 && cj >= 2) A.hz1[o] = h;
+      }
+      sH[cj][ci] = h;
+      sHo[cj][ci] = ho;
     }
-    sH[cj][ci] = h;
   }
   __syncthreads();
 
-  // -- Ampere + Drude, Eqs. (1), (3) ------------------------------------------
-  for (int k = tid; k < NH * NW; k += kThreads) {
-    const int ci = k % NW, cj = k / NW;
-    const int i = i0 - 1 + ci, j = j0 - 1 + cj;
-    const bool own = ci >= 1 && cj >= 1;
-    const size_t o = (size_t)j * pitch + i;
-    float exn = 0.f, eyn = 0.f;
-    if (ex_ok(i, j)) {
-      const float e = sExo[cj + 1][ci + 1];
-      const float ne = 0.5f * (sN[cj][ci] + sN[cj][ci + 1]);
-      const float kap = A.kn * ne;
-      const bool bnd = (j == B || j == T);
-      if (!bnd) {
-        const float jo = A.jx0[o];
-        const float dh = sH[cj + 1][ci + 1] - sH[cj][ci + 1];
-        exn = ((1.f - kap) * e + A.S * dh - A.c1 * jo) / (1.f + kap);
+  // -- Ampere + Drude, Eqs. (1), (3); Eq. (5b) on the boundary ------------------
+#pragma unroll
+  for (int q = 0; q < NE; q++) {
+    const int k = tid + q * kThreads;
+    if (k < NH * NW) {
+      const int ci = k % NW, cj = k / NW;
+      const int i = i0 - 1 + ci, j = j0 - 1 + cj;
+      const bool own = ci >= 1 && cj >= 1;
+      const size_t o = (size_t)j * pitch + i;
+      float exn = 0.f, eyn = 0.f;
+      if (ex_ok(i, j)) {
+        const float e = sExo[cj + 1][ci + 1];
+        const float ne = 0.5f * (sN[cj][ci] + sN[cj][ci + 1]);
+        const float kap = A.kn * ne;
+        const float jo = pjx[q];
+        if (j != B && j != T) {
+          const float dh = sH[cj + 1][ci + 1] - sH[cj][ci + 1];
+          exn = ((1.f - kap) * e + A.S * dh - A.c1 * jo) / (1.f + kap);
+        } else {
+          exn = sB[j == B ? 0 : 1][ci];
+        }
         if (own) {
           const float jn = A.a * jo + 2.f * kap * (e + exn);
-          A.ex1[o] = exn;
-          A.jx1[o] = jn;
-          if (FINE) sJx[cj - 1][ci - 1] = jn;
-        }
-      } else if (FINE) {
-        // Eq. (5b): coarse row J = j/2, fine x-edge i at coarse x-index
-        // i/2 - 1/4, linear in time between the old and new coarse E
-        const int J = j >> 1;
-        int ic;
-        float w0, w1;
-        if ((i & 1) == 0) { ic = (i >> 1) - 1; w0 = 0.25f; w1 = 0.75f; }
-        else              { ic = i >> 1;       w0 = 0.75f; w1 = 0.25f; }
-        const size_t co = (size_t)J * A.cpitch + ic;
-        const float vo = w0 * A.cex0[co] + w1 * A.cex0[co + 1];
-        const float vn = w0 * A.cex1[co] + w1 * A.cex1[co + 1];
-        exn = (1.f - A.frac) * vo + A.frac * vn;
-        if (own) {
-          const float jn = A.a * A.jx0[o] + 2.f * kap * (e + exn);
           A.ex1[o] = exn;
           A.jx1[o] = jn;
           sJx[cj - 1][ci - 1] = jn;
         }
       }
-    }
-    if (ey_ok(i, j)) {
-      const float e = sEyo[cj + 1][ci + 1];
-      const float ne = 0.5f * (sN[cj][ci] + sN[cj + 1][ci]);
-      const float kap = A.kn * ne;
-      const bool bnd = (i == L || i == R);
-      if (!bnd) {
-        const float jo = A.jy0[o];
-        const float dh = sH[cj + 1][ci + 1] - sH[cj + 1][ci];
-        float curl = -A.S * dh;
-        if (!FINE && i == A.is) curl += A.S * A.hz_src;  // total-field side
-        eyn = ((1.f - kap) * e + curl - A.c1 * jo) / (1.f + kap);
+      if (ey_ok(i, j)) {
+        const float e = sEyo[cj + 1][ci + 1];
+        const float ne = 0.5f * (sN[cj][ci] + sN[cj + 1][ci]);
+        const float kap = A.kn * ne;
+        const float jo = pjy[q];
+        if (i != L && i != R) {
+          const float dh = sH[cj + 1][ci + 1] - sH[cj + 1][ci];
+          const float curl = -A.S * dh;
+          eyn = ((1.f - kap) * e + curl - A.c1 * jo) / (1.f + kap);
+        } else {
+          eyn = sB[i == L ? 2 : 3][cj];
+        }
         if (own) {
           const float jn = A.a * jo + 2.f * kap * (e + eyn);
-          A.ey1[o] = eyn;
-          A.jy1[o] = jn;
-          if (FINE) sJy[cj - 1][ci - 1] = jn;
-        }
-      } else if (FINE) {
-        const int I = i >> 1;
-        int jc;
-        float w0, w1;
-        if ((j & 1) == 0) { jc = (j >> 1) - 1; w0 = 0.25f; w1 = 0.75f; }
-        else              { jc = j >> 1;       w0 = 0.75f; w1 = 0.25f; }
-        const size_t co = (size_t)jc * A.cpitch + I;
-        const float vo = w0 * A.cey0[co] + w1 * A.cey0[co + A.cpitch];
-        const float vn = w0 * A.cey1[co] + w1 * A.cey1[co + A.cpitch];
-        eyn = (1.f - A.frac) * vo + A.frac * vn;
-        if (own) {
-          const float jn = A.a * A.jy0[o] + 2.f * kap * (e + eyn);
           A.ey1[o] = eyn;
           A.jy1[o] = jn;
           sJy[cj - 1][ci - 1] = jn;
         }
       }
+      sExn[cj][ci] = exn;
+      sEyn[cj][ci] = eyn;
     }
-    sExn[cj][ci] = exn;
-    sEyn[cj][ci] = eyn;
   }
   __syncthreads();
 
-  // -- outer boundary of the base level: first-order Mur or PEC ---------------
-  if (!FINE && (i0 == 0 || i0 + kTX > R || j0 == 0 || j0 + TY > T)) {
-    for (int k = tid; k < NH * NW; k += kThreads) {
-      const int ci = k % NW, cj = k / NW;
-      const int i = i0 - 1 + ci, j = j0 - 1 + cj;
-      const bool own = ci >= 1 && cj >= 1;
-      const size_t o = (size_t)j * pitch + i;
-      if (ey_ok(i, j) && (i == L || i == R)) {
-        const float eo = sEyo[cj + 1][ci + 1];
-        float en = 0.f;
-        if (A.bc_x == kBcMur) {
-          const int d = (i == L) ? 1 : -1;  // interior neighbour
-          en = sEyo[cj + 1][ci + 1 + d] + A.cmur * (sEyn[cj][ci + d] - eo);
-        }
-        sEyn[cj][ci] = en;
-        if (own) {
-          const float ne = 0.5f * (sN[cj][ci] + sN[cj + 1][ci]);
-          const float kap = A.kn * ne;
-          A.ey1[o] = en;
-          A.jy1[o] = A.a * A.jy0[o] + 2.f * kap * (eo + en);
-        }
-      }
-      if (ex_ok(i, j) && (j == B || j == T)) {
-        const float eo = sExo[cj + 1][ci + 1];
-        float en = 0.f;
-        if (A.bc_y == kBcMur) {
-          const int d = (j == B) ? 1 : -1;
-          en = sExo[cj + 1 + d][ci + 1] + A.cmur * (sExn[cj + d][ci] - eo);
-        }
-        sExn[cj][ci] = en;
-        if (own) {
-          const float ne = 0.5f * (sN[cj][ci] + sN[cj][ci + 1]);
-          const float kap = A.kn * ne;
-          A.ex1[o] = en;
-          A.jx1[o] = A.a * A.jx0[o] + 2.f * kap * (eo + en);
-        }
-      }
-    }
-    __syncthreads();
-  }
-
   // -- window accumulation at the tile's nodes ---------------------------------
-  const int tx = tid % kTX, ty = tid / kTX;
-  for (int r = ty; r < TY; r += kThreads / kTX) {
+#pragma unroll
+  for (int q = 0; q < NA; q++) {
+    const int r = ty + q * (kThreads / kTX);
     const int i = i0 + tx, j = j0 + r;
     if (!nd_ok(i, j)) continue;
     const int ci = tx + 1, cj = r + 1;
@@ -300,12 +342,11 @@ __device__ __forceinline__ void em_tile(const EMArgs& A, int bx, int by) {
     if (j < T) { const float v = sEyn[cj][ci]; sy += v * v; cy++; }
     const float e2 = (cx == 2 ? 0.5f * sx : sx) + (cy == 2 ? 0.5f * sy : sy);
     const size_t o = (size_t)j * pitch + i;
-    A.acc[o] += e2;
+    A.acc[o] = pacc[q] + e2;
   }
 
   // -- fine -> coarse transfer after the last substep ------------------------
-  if (FINE && A.restrict_on) {
-    __syncthreads();
+  if (A.restrict_on) {
     for (int r = ty; r < TY; r += kThreads / kTX) {
       const int i = i0 + tx, j = j0 + r;
       if (((i - L) | (j - B)) & 1) continue;
@@ -316,7 +357,7 @@ __device__ __forceinline__ void em_tile(const EMArgs& A, int bx, int by) {
         float s = 0.f;
         for (int da = 0; da < 2; da++)
           for (int db = 0; db < 2; db++) {
-            const float hold = A.hz0[(size_t)(j + db) * pitch + i + da];
+            const float hold = sHo[r + 2 + db][tx + 2 + da];
             s += 0.5f * (hold + sH[r + 2 + db][tx + 2 + da]);
           }
         A.chz[co] = 0.25f * s;
@@ -333,19 +374,19 @@ __device__ __forceinline__ void em_tile(const EMArgs& A, int bx, int by) {
   }
 }
 
-template <bool FINE, int TY>
-__global__ __launch_bounds__(kThreads) void k_em(EMArgs A) {
-  em_tile<FINE, TY>(A, blockIdx.x, blockIdx.y);
+template <int TY>
+__global__ __launch_bounds__(kThreads) void k_fine(EMArgs A) {
+  fine_tile<TY>(A, blockIdx.x, blockIdx.y);
 }
 
 // batched form: one launch over the tiles of many independent instances;
 // blk[b] = (instance, tile index within it)
-template <bool FINE, int TY>
-__global__ __launch_bounds__(kThreads) void k_em_batch(const EMArgs* __restrict__ args,
-                                                       const int2* __restrict__ blk) {
+template <int TY>
+__global__ __launch_bounds__(kThreads) void k_fine_batch(const EMArgs* __restrict__ args,
+                                                         const int2* __restrict__ blk) {
   const int2 bi = blk[blockIdx.x];
   const EMArgs& A = args[bi.x];
-  em_tile<FINE, TY>(A, bi.y % A.nbx, bi.y / A.nbx);
+  fine_tile<TY>(A, bi.y % A.nbx, bi.y / A.nbx);
 }
 
 // ---------------------------------------------------------------------------
@@ -645,33 +686,42 @@ struct RowData {
   float ex, ey, ey1, hz, jx, jy, n, n1, acc;
 };
 
+// Raw loads from clamped (always valid) addresses: nothing depends on the
+// values until the row is consumed DEPTH rows later, so the loads stay in
+// flight across iterations.
 __device__ inline RowData load_row(const EMArgs& A, int i, int j) {
-  // straight-line loads from clamped (always valid) addresses; entries
-  // that do not exist are replaced by zero afterwards
   RowData r;
   const int NX = A.R, NY = A.T;
   const int ic = min(max(i, 0), NX), jc = min(max(j, 0), NY);
   const int ic1 = min(max(i + 1, 0), NX);
   const size_t o = (size_t)jc * A.pitch + ic;
   const size_t o1 = (size_t)jc * A.pitch + ic1;
+  r.ex = A.ex0[o]; r.jx = A.jx0[o]; r.ey = A.ey0[o]; r.jy = A.jy0[o];
+  r.ey1 = A.ey0[o1]; r.hz = A.hz0[o]; r.n = A.n[o]; r.n1 = A.n[o1];
+  r.acc = A.acc[o];
+  return r;
+}
+
+// entries of row j that do not exist (outside the grid, or beyond the
+// entity's own extent) read as zero
+__device__ inline RowData mask_row(const EMArgs& A, const RowData& q, int i, int j) {
+  const int NX = A.R, NY = A.T;
   const bool row_ok = j >= 0 && j <= NY;
   const bool exv = row_ok && i >= 0 && i < NX;
   const bool eyv = row_ok && j < NY && i >= 0 && i <= NX;
   const bool ey1v = row_ok && j < NY && i + 1 >= 0 && i + 1 <= NX;
   const bool ndv = row_ok && i >= 0 && i <= NX;
   const bool nd1v = row_ok && i + 1 >= 0 && i + 1 <= NX;
-  const float ex = A.ex0[o], jx = A.jx0[o], ey = A.ey0[o], jy = A.jy0[o];
-  const float ey1 = A.ey0[o1], hz = A.hz0[o], n = A.n[o], n1 = A.n[o1];
-  const float acc = A.acc[o];
-  r.ex = exv ? ex : 0.f;
-  r.jx = exv ? jx : 0.f;
-  r.ey = eyv ? ey : 0.f;
-  r.jy = eyv ? jy : 0.f;
-  r.ey1 = ey1v ? ey1 : 0.f;
-  r.hz = (eyv && i < NX) ? hz : 0.f;
-  r.n = ndv ? n : 0.f;
-  r.n1 = nd1v ? n1 : 0.f;
-  r.acc = ndv ? acc : 0.f;
+  RowData r;
+  r.ex = exv ? q.ex : 0.f;
+  r.jx = exv ? q.jx : 0.f;
+  r.ey = eyv ? q.ey : 0.f;
+  r.jy = eyv ? q.jy : 0.f;
+  r.ey1 = ey1v ? q.ey1 : 0.f;
+  r.hz = (eyv && i < NX) ? q.hz : 0.f;
+  r.n = ndv ? q.n : 0.f;
+  r.n1 = nd1v ? q.n1 : 0.f;
+  r.acc = ndv ? q.acc : 0.f;
   return r;
 }
 
@@ -701,10 +751,11 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int bx, int k, i
   // row-0 Mur edge Ex(i,0) waits for Ex(i,1): its old value, current, density
   float ex0_old = 0.f, jx0_old = 0.f, kap0 = 0.f, acc0 = 0.f;
 
-  for (int j = js; j < j1; j++) {
-    const RowData& cur = buf[0];
-    const RowData& nxt = buf[1];
-    const bool store = j >= j0;
+  // one row of the segment; rc/rn: raw rows j and j+1
+  auto row = [&](int j, const RowData& rc, const RowData& rn) {
+    const RowData cur = mask_row(A, rc, i, j);
+    const RowData nxt = mask_row(A, rn, i, j + 1);
+    const bool store = j >= j0 && j < j1;
     const size_t o = (size_t)j * A.pitch + i;
 
     // Faraday, Eq. (2)
@@ -732,7 +783,7 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int bx, int k, i
           A.ex1[o] = exn;
           A.jx1[o] = a * cur.jx + 2.f * kapx * (cur.ex + exn);
         }
-      } else {  // j == 0: finished with row 1
+      } else if (j == 0) {  // finished with row 1
         ex0_old = cur.ex;
         jx0_old = cur.jx;
         kap0 = kapx;
@@ -797,15 +848,35 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int bx, int k, i
     eyn_p = eyn;
     exn_p = exn;
     exo_p = cur.ex;
+  };
+  // unrolled by DEPTH+1 so the pipeline slots rotate by index: slot u holds
+  // row jb+u until it is consumed, then takes row jb+u+DEPTH+1
+  // the loads stay unconditional (rows past the segment are computed
+  // from clamped reads and not stored), so the wait for a slot's loads is
+  // exact rather than a drain of everything in flight
+  for (int jb = js; jb < j1; jb += DEPTH + 1) {
 #pragma unroll
-    for (int d = 0; d < DEPTH; d++) buf[d] = buf[d + 1];
-    buf[DEPTH] = load_row(A, i, j + DEPTH + 1);
+    for (int u = 0; u <= DEPTH; u++) {
+      const int j = jb + u;
+      row(j, buf[u], buf[u == DEPTH ? 0 : u + 1]);
+      buf[u] = load_row(A, i, j + DEPTH + 1);
+    }
   }
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin by linear id, and each
+// XCD has its own L2.  Hand XCD x a contiguous band of the row-major
+// (column block, segment) grid so that neighbouring blocks, which read the
+// same cache lines at their common columns and rows, share an L2.
+__device__ inline int xcd_band(int L, int N) {
+  const int x = L & 7, k = L >> 3, q = N >> 3, r = N & 7;
+  return x * q + min(x, r) + k;
+}
+
 template <int DEPTH>
-__global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int nseg) {
-  em_stream_body<DEPTH>(A, blockIdx.x, blockIdx.y, seg, nseg, A.ey_src, A.hz_src);
+__global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int nseg, int nbx) {
+  const int b = xcd_band(blockIdx.x, nbx * nseg);
+  em_stream_body<DEPTH>(A, b % nbx, b / nbx, seg, nseg, A.ey_src, A.hz_src);
 }
 
 // batched form; the incident values of step k of the current interval come
@@ -822,32 +893,16 @@ __global__ __launch_bounds__(kThreads) void k_em_stream_batch(const EMArgs* __re
 }
 
 // ---- host-side launchers ----------------------------------------------------
-template <bool FINE>
-static hipError_t launch_em_t(const EMArgs& A, int ty, hipStream_t st) {
+hipError_t launch_em(const EMArgs& A, bool fine, int ty, hipStream_t st) {
+  if (!fine) return hipErrorInvalidValue;  // the base level uses the streaming kernel
   const int nx = A.R - A.L + 1, ny = A.T - A.B + 1;
   dim3 blk(kThreads);
   switch (ty) {
-  case 4: {
-    dim3 g((nx + kTX - 1) / kTX, (ny + 3) / 4);
-    hipLaunchKernelGGL((k_em<FINE, 4>), g, blk, 0, st, A);
-    break;
-  }
-  case 8: {
-    dim3 g((nx + kTX - 1) / kTX, (ny + 7) / 8);
-    hipLaunchKernelGGL((k_em<FINE, 8>), g, blk, 0, st, A);
-    break;
-  }
-  default: {
-    dim3 g((nx + kTX - 1) / kTX, (ny + 15) / 16);
-    hipLaunchKernelGGL((k_em<FINE, 16>), g, blk, 0, st, A);
-    break;
-  }
+  case 4: hipLaunchKernelGGL(k_fine<4>, dim3((nx + kTX - 1) / kTX, (ny + 3) / 4), blk, 0, st, A); break;
+  case 8: hipLaunchKernelGGL(k_fine<8>, dim3((nx + kTX - 1) / kTX, (ny + 7) / 8), blk, 0, st, A); break;
+  default: hipLaunchKernelGGL(k_fine<16>, dim3((nx + kTX - 1) / kTX, (ny + 15) / 16), blk, 0, st, A); break;
   }
   return hipGetLastError();
-}
-
-hipError_t launch_em(const EMArgs& A, bool fine, int ty, hipStream_t st) {
-  return fine ? launch_em_t<true>(A, ty, st) : launch_em_t<false>(A, ty, st);
 }
 
 hipError_t launch_em_stream_batch(const EMArgs* args, const int2* blk, int nblk,
@@ -864,9 +919,9 @@ hipError_t launch_em_batch(const EMArgs* args, const int2* blk, int nblk, int ty
                            hipStream_t st) {
   if (nblk <= 0) return hipSuccess;
   switch (ty) {
-  case 4: hipLaunchKernelGGL((k_em_batch<true, 4>), dim3(nblk), dim3(kThreads), 0, st, args, blk); break;
-  case 8: hipLaunchKernelGGL((k_em_batch<true, 8>), dim3(nblk), dim3(kThreads), 0, st, args, blk); break;
-  default: hipLaunchKernelGGL((k_em_batch<true, 16>), dim3(nblk), dim3(kThreads), 0, st, args, blk); break;
+  case 4: hipLaunchKernelGGL(k_fine_batch<4>, dim3(nblk), dim3(kThreads), 0, st, args, blk); break;
+  case 8: hipLaunchKernelGGL(k_fine_batch<8>, dim3(nblk), dim3(kThreads), 0, st, args, blk); break;
+  default: hipLaunchKernelGGL(k_fine_batch<16>, dim3(nblk), dim3(kThreads), 0, st, args, blk); break;
   }
   return hipGetLastError();
 }
@@ -888,9 +943,10 @@ int stream_segments(int NY, int seg) {
 hipError_t launch_em_stream(const EMArgs& A, int seg, int depth, hipStream_t st) {
   const int waves = (A.R + 1 + 61) / 62;
   const int nseg = stream_segments(A.T, seg);
-  dim3 g((waves + kThreads / 64 - 1) / (kThreads / 64), nseg);
-  if (depth >= 4) hipLaunchKernelGGL(k_em_stream<4>, g, dim3(kThreads), 0, st, A, seg, nseg);
-  else hipLaunchKernelGGL(k_em_stream<2>, g, dim3(kThreads), 0, st, A, seg, nseg);
+  const int nbx = (waves + kThreads / 64 - 1) / (kThreads / 64);
+  dim3 g(nbx * nseg);
+  if (depth >= 4) hipLaunchKernelGGL(k_em_stream<4>, g, dim3(kThreads), 0, st, A, seg, nseg, nbx);
+  else hipLaunchKernelGGL(k_em_stream<2>, g, dim3(kThreads), 0, st, A, seg, nseg, nbx);
   return hipGetLastError();
 }
 

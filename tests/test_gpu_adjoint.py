@@ -114,3 +114,26 @@ def test_autograd_function():
     assert s.grad.item() == pytest.approx(got["E0"] * e0_of(cfg), rel=1e-12)
     assert A.grad.item() == pytest.approx(got["A"], rel=1e-12)
     assert beta.grad.item() == pytest.approx(got["beta"], rel=1e-12)
+
+
+def test_config4_full_size():
+    """The adjoint workload at full size (512 x 256 refined, 2000 base steps,
+    checkpoint every 45) against the stored FP64 reference adjoint
+    (tests/golden/make_adjoint_config4.py, oracle/ only)."""
+    import os
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "adjoint_config4.npz"))
+    cfg = W.config4(steps=int(ref["steps"]))
+    sb, _ = W.seeds(cfg, fine=False)
+    w = W.window_weights(cfg)
+    g = B.Sim(cfg, sb, None)
+    assert g.patch() == tuple(int(v) for v in ref["ext0"])
+    g.record(cfg["steps"], 45)
+    F = g.weighted_sum(w)
+    got = g.backward(w)
+    seed = got["seed"].cpu().numpy().astype(np.float64)
+    errs = {"F": _rel(F, float(ref["F"])), "E0": _rel(got["E0"], float(ref["E0"])),
+            "A": _rel(got["A"], float(ref["A"])), "beta": _rel(got["beta"], float(ref["beta"])),
+            "seed": _rel_l2(seed, ref["seed"].astype(np.float64))}
+    print("config 4: relative errors vs FP64 %s" % errs, flush=True)
+    for k, v in errs.items():
+        assert v <= TOL, (k, v, errs)
