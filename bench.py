@@ -71,6 +71,28 @@ def only_large(steps=48):
     print("only-large: %d steps of %dx%d, copy of %d MiB" % (steps, cfg["nx"], cfg["ny"], a.numel() * 4 >> 20), flush=True)
 
 
+def traffic_records():
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE scaled by the copy
+    calibration) from the committed rocprofv3 counter summary -- only while
+    the kernel source is the one that was profiled; else {}."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_em_stream_4096x2048_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_2105_13276_amd", "csrc", "dmr_kernels.hip")
+    if not (os.path.exists(path) and os.path.exists(src)):
+        return {}
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    pat = re.compile(r"traffic-record kernel=(\S+) fetch_kib=(\S+) write_kib=(\S+) "
+                     r"fetch_factor=(\S+) write_factor=(\S+) source_sha1=(\S+)")
+    out = {}
+    for line in open(path):
+        m = pat.search(line)
+        if m and m.group(6) == sha:
+            f, w, ff, wf = (float(m.group(k)) for k in (2, 3, 4, 5))
+            out[m.group(1)] = (f * ff + w * wf) * 1024.0
+    return out
+
+
 def em_bytes_per_cell():
     # base EM kernel: read Hz, Ex, Ey, Jx, Jy, n, acc; write Hz, Ex, Ey, Jx,
     # Jy, acc (float32) -- the minimum with halos reused on chip
@@ -207,12 +229,16 @@ def main():
     else:
         alg_bytes = None
     achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9 if alg_bytes else None
-    roofline = {"bound": "hbm", "kernel": "k_em<base>" if dom == 0 else cls_names[dom],
+    rec = traffic_records()
+    roofline = {"bound": "hbm", "kernel": "k_em_stream (base)" if dom == 0 else
+                ("k_fine (patch substep)" if dom == 1 else cls_names[dom]),
                 "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                "frac": (achieved / 8000.0) if achieved else None, "traffic": None,
+                "frac": (achieved / 8000.0) if achieved else None,
+                "traffic": rec.get("k_fine@64x64") if (dom == 1 and fine_cells == 64 * 64) else None,
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_us": per_launch_ms * 1e3,
-                "note": "config-1 state (7.9 MB) is cache resident; HBM-bound "
-                        "figures are in roofline_large"}
+                "note": "config-1 state (7.9 MB) is cache resident and its kernels are "
+                        "latency-bound (per-launch HIP events add ~2 us to the ~7.7 us "
+                        "kernel); HBM-bound figures are in roofline_large"}
 
     out = {
         "metric": "Mcell-updates/s & time-to-t_final: DMR vs uniform-fine, same MI355X",
@@ -255,6 +281,7 @@ def main():
         out["roofline_large"] = {"bound": "hbm", "kernel": "k_em_stream 4096x2048",
                                  "achieved": ach_l, "peak": 8000.0, "unit": "GB/s",
                                  "frac": ach_l / 8000.0, "avg_launch_us": per_l * 1e3,
+                                 "traffic": rec.get("k_em_stream@4096x2048"),
                                  "alg_bytes_per_launch": em_bytes_per_cell() * cells_l}
         # DMR vs uniform-fine where the step is bandwidth-bound: config-1
         # physics on 4096x2048 coarse (8192x4096 uniform-fine), one interval

@@ -320,12 +320,12 @@ int stream_rows(int NX, int NY) {
   // small grids take short segments and many waves
   const long waves_x = (NX + 1 + 61) / 62;
   int seg = 64;
-  while (seg > 2 && waves_x * ((NY + seg) / seg) < 8192) seg >>= 1;
+  while (seg > 2 && waves_x * ((NY + seg) / seg) < 16384) seg >>= 1;
   return seg;
 }
 
-// rows in flight per wave (measured: 2 for segments of up to 4 rows and for
-// long bandwidth-bound ones, 4 in between)
+// rows in flight per wave (measured on 512x256 ... 4096x2048: 2 for
+// segments of up to 4 rows and for long ones, 4 in between)
 int stream_depth(int seg) {
   if (const char* e = getenv("DMR_DEPTH")) return atoi(e) >= 4 ? 4 : 2;
   return (seg >= 8 && seg <= 16) ? 4 : 2;

@@ -746,7 +746,7 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int bx, int k, i
   // rows js .. js+DEPTH in flight; buf[0] is the current row
   RowData buf[DEPTH + 1];
 #pragma unroll
-  for (int d = 0; d <= DEPTH; d++) buf[d] = load_row(A, i, js + d);
+  for (int d = 0; d <= DEPTH; d++) buf[d] = load_row(A, i, min(js + d, j1));
   float hzn_p = 0.f, eyn_p = 0.f, exn_p = 0.f, exo_p = 0.f;
   // row-0 Mur edge Ex(i,0) waits for Ex(i,1): its old value, current, density
   float ex0_old = 0.f, jx0_old = 0.f, kap0 = 0.f, acc0 = 0.f;
@@ -859,7 +859,8 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int bx, int k, i
     for (int u = 0; u <= DEPTH; u++) {
       const int j = jb + u;
       row(j, buf[u], buf[u == DEPTH ? 0 : u + 1]);
-      buf[u] = load_row(A, i, j + DEPTH + 1);
+      // rows past j1 are not needed: re-read row j1 (a cache hit)
+      buf[u] = load_row(A, i, min(j + DEPTH + 1, j1));
     }
   }
 }
