@@ -102,3 +102,24 @@ def test_config1_uniform_fine_prefix():
     g.step(cfg["steps"])
     o.step(cfg["steps"])
     assert_parity(g, o, _nc(cfg), levels=(0,), tag="config1-uniform")
+
+
+def test_config2_full_size_prefix():
+    """Config 2 at full size (coarse 4096x2048, r = 2 patch over the 8-seed
+    layout, E_rms/E_bd = 1.5) in the launch shape the large benchmark rows
+    use, over its first 2 periods: the initial regrid, one period of window
+    filling and one of continuity steps on both levels.  (The full 2000
+    periods are out of the FP64 oracle's reach.)"""
+    cfg = W.config2(periods=2)
+    centres, peaks = W.config2_seed_layout(cfg)
+    sb, sf = W.seeds(cfg, centres, peaks)
+    g, o = both(cfg, sb, sf)
+    print("config 2 prefix: patch %s" % (g.patch(),), flush=True)
+    assert g.patch() == o.patch()
+    fg, sg, lg, cg = g.regrid_info()
+    fo, so, lo, co = o.regrid_info()
+    assert (fg == fo).all() and (sg == so).all() and cg == co and (lg == lo).all()
+    g.step(cfg["steps"])
+    o.step(cfg["steps"])
+    g.sync()
+    assert_parity(g, o, _nc(cfg), tag="config2-prefix")
