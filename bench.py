@@ -225,19 +225,21 @@ def main():
     if dom == 0:
         alg_bytes = em_bytes_per_cell() * coarse_cells
     elif dom == 1:
-        alg_bytes = em_bytes_per_cell() * fine_cells
+        # one launch per coarse step runs both substeps (two cell-updates per cell)
+        subs = 2 if cnt[1] == cnt[0] else 1
+        alg_bytes = em_bytes_per_cell() * fine_cells * subs
     else:
         alg_bytes = None
     achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9 if alg_bytes else None
     rec = traffic_records()
     roofline = {"bound": "hbm", "kernel": "k_em_stream (base)" if dom == 0 else
-                ("k_fine (patch substep)" if dom == 1 else cls_names[dom]),
+                ("k_fine2 (both patch substeps)" if dom == 1 else cls_names[dom]),
                 "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                 "frac": (achieved / 8000.0) if achieved else None,
-                "traffic": rec.get("k_fine@64x64") if (dom == 1 and fine_cells == 64 * 64) else None,
+                "traffic": rec.get("k_fine2@64x64") if (dom == 1 and fine_cells == 64 * 64) else None,
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_us": per_launch_ms * 1e3,
                 "note": "config-1 state (7.9 MB) is cache resident and its kernels are "
-                        "latency-bound (per-launch HIP events add ~2 us to the ~7.7 us "
+                        "latency-bound (per-launch HIP events add ~2 us to the ~9 us "
                         "kernel); HBM-bound figures are in roofline_large"}
 
     out = {

@@ -175,6 +175,10 @@ struct dmr_sim {
   int64_t step = 0, blocks = 0;
   int ccur = 0, ncur = 0;
   int seg0 = 16, depth0 = 2, ty1 = 16;
+  // both patch substeps in one launch (dmr_step only; the adjoint's record and
+  // replay and the batched form run them one launch each, bit-identically)
+  bool fuse_fine = true;
+  int nt1 = 1024;  // threads per patch tile
   uint8_t* d_flag = nullptr;
   int32_t *d_scan = nullptr, *d_list = nullptr;
   int* d_desc = nullptr;
@@ -332,6 +336,10 @@ int stream_depth(int seg) {
 }
 
 int tile_rows(int NX, int NY) {
+  if (const char* e = getenv("DMR_TY")) {
+    const int v = atoi(e);
+    if (v == 4 || v == 8 || v == 16) return v;
+  }
   // enough tiles to cover the 256 compute units several times over
   const long tiles16 = (long)((NX + kTX) / kTX) * ((NY + 16) / 16);
   if (tiles16 >= 2048) return 16;
@@ -557,12 +565,28 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
     job(&J, s->L0.ey[1 - c], cx->ss.ceyp, s->L0.plane);
     if (int rc = run_copies(s, J)) return rc;
   }
-  if (s->has_patch) {  // two fine substeps (Sec. III.C)
+  if (s->has_patch && s->fuse_fine && !cx) {  // both substeps, one launch
+    Level& F = s->L1;
+    EMArgs G;
+    make_fine_em(s, p.r, c, s->ncur, s->ty1, &G);  // restriction targets
+    em_args_level(&G, F, 0, 1, F.n[s->ncur], F.acc);
+    G.frac = 1.f / (float)p.r;  // time fraction of substep 1
+    ev_begin(s, 1);
+    e = launch_fine2(G, s->ty1, s->nt1, s->st);
+    ev_end(s);
+    if (e != hipSuccess) return hipfail(s, e, "fine EM launch");
+    // the new state is in buffer 1: make it buffer 0
+    std::swap(F.hz[0], F.hz[1]);
+    std::swap(F.ex[0], F.ex[1]);
+    std::swap(F.ey[0], F.ey[1]);
+    std::swap(F.jx[0], F.jx[1]);
+    std::swap(F.jy[0], F.jy[1]);
+  } else if (s->has_patch) {  // two fine substeps (Sec. III.C)
     for (int m = 1; m <= p.r; m++) {
       EMArgs G;
       make_fine_em(s, m, c, s->ncur, s->ty1, &G);
       ev_begin(s, 1);
-      e = launch_em(G, true, s->ty1, s->st);
+      e = launch_em(G, true, s->ty1, s->nt1, s->st);
       ev_end(s);
       if (e != hipSuccess) return hipfail(s, e, "fine EM launch");
       if (st) {
@@ -732,6 +756,8 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   s->d_err = (int*)(s->ws + lay.off_err);
   s->stage = (float*)(s->ws + lay.off_stage);
   s->seg0 = stream_rows(p->nx, p->ny);
+  if (const char* f = getenv("DMR_FUSE")) s->fuse_fine = atoi(f) != 0;
+  if (const char* f = getenv("DMR_FNT")) s->nt1 = atoi(f) >= 1024 ? 1024 : 256;
   s->depth0 = stream_depth(s->seg0);
   hipError_t e = hipMemsetAsync(s->ws, 0, lay.total, s->st);
   if (e != hipSuccess) { rc = hipfail(s, e, "workspace clear"); delete s; return rc; }
@@ -1788,6 +1814,7 @@ int dmr_batch_create(const dmr_params* p, int count, const double* const* seed_b
       dmr_batch_destroy(b);
       return rc;
     }
+    s->fuse_fine = false;  // the batch's tables name fixed patch buffers
     b->sims.push_back(s);
   }
   b->d_em = (EMArgs*)(b->ws + L.off_em);

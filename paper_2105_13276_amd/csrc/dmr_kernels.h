@@ -8,6 +8,7 @@ namespace dmr {
 
 constexpr int kTX = 64;        // tile width in nodes: one wavefront per row
 constexpr int kThreads = 256;  // threads per tile
+constexpr int kFineThreads = 1024;  // threads per patch tile (phases run from LDS)
 constexpr int kRing = 8;       // window blocks per period
 constexpr int kBcMur = 0;
 constexpr int kSrcSteps = 256;  // incident-value table length of the batched form
@@ -87,7 +88,11 @@ struct ProlongArgs {
   float *hz, *ex, *ey, *jx, *jy, *n, *acc, *ring;
 };
 
-hipError_t launch_em(const EMArgs& A, bool fine, int ty, hipStream_t st);
+// patch substep kernel, 64 x ty tiles of nt threads (256 or 1024)
+hipError_t launch_em(const EMArgs& A, bool fine, int ty, int nt, hipStream_t st);
+// both patch substeps of a coarse step in one launch: reads buffer 0 (hz0..),
+// writes buffer 1 (hz1..), A.frac = time fraction of substep 1, restriction on
+hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st);
 // base level, column-streaming kernel; seg = rows per segment (>= 2)
 hipError_t launch_em_stream(const EMArgs& A, int seg, int depth, hipStream_t st);
 int stream_segments(int NY, int seg);

@@ -22,6 +22,40 @@
 namespace dmr {
 
 // ---------------------------------------------------------------------------
+// Per-entity arithmetic of the patch substep, shared by the one-substep and
+// the two-substep kernels so that both round identically.
+// ---------------------------------------------------------------------------
+// 5-point Laplacian; neighbours outside the patch already replaced by c
+__device__ inline float lap5(float c, float l, float r, float d, float u) {
+  return l + r + d + u - 4.f * c;
+}
+// E filter of the patch interior: E - gamma L(L(E))
+__device__ inline float filter_e(float e, float gamma, float l2) { return e - gamma * l2; }
+// Faraday, Eq. (2), scaled: H~ - S [(Ey_{i+1}-Ey_i) - (Ex_{j+1}-Ex_j)]
+__device__ inline float faraday(float ho, float S, float dey, float dex) {
+  return ho - S * (dey - dex);
+}
+// Ampere + Drude, Eqs. (1), (3): new E from the old E, the curl term and J~
+__device__ inline float ampere(float e, float kap, float curl, float c1, float jo) {
+  return ((1.f - kap) * e + curl - c1 * jo) / (1.f + kap);
+}
+// new J~ = a J~ + 2k (E + E+)
+__device__ inline float drude(float a, float jo, float kap, float e, float en) {
+  return a * jo + 2.f * kap * (e + en);
+}
+// Eq. (5b): space weights w0, w1 on two coarse edges, time fraction frac
+__device__ inline float cfb(float w0, float w1, float o0, float o1, float n0, float n1,
+                            float frac) {
+  const float vo = w0 * o0 + w1 * o1;
+  const float vn = w0 * n0 + w1 * n1;
+  return (1.f - frac) * vo + frac * vn;
+}
+// window increment of a node from its existing edges (mean per axis)
+__device__ inline float win_e2(float sx, int cx, float sy, int cy) {
+  return (cx == 2 ? 0.5f * sx : sx) + (cy == 2 ? 0.5f * sy : sy);
+}
+
+// ---------------------------------------------------------------------------
 // EM substep of the fine patch (Eqs. (1)-(3)), one TX x TY tile of nodes per
 // block.  The tile owns Hz(i,j), Ex(i,j), Ey(i,j) and node (i,j) for (i,j)
 // in the tile.  It needs old E over [i0-2, i0+TX] x [j0-2, j0+TY] (after the
@@ -36,7 +70,7 @@ namespace dmr {
 // (registers), so the block waits for memory once; the phases after that
 // run from LDS and registers.
 // ---------------------------------------------------------------------------
-template <int TY>
+template <int TY, int NT>
 __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   constexpr int EW = kTX + 3, EH = TY + 3;  // old E (filtered)
   constexpr int HW = kTX + 2, HH = TY + 2;  // new Hz
@@ -44,12 +78,13 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   constexpr int DW = kTX + 2, DH = TY + 2;  // density
   constexpr int RW = kTX + 7, RH = TY + 7;  // raw E for the filter
   constexpr int QW = kTX + 5, QH = TY + 5;  // Laplacian of raw E
-  constexpr int NR = (RH * RW + kThreads - 1) / kThreads;
-  constexpr int NO = (EH * EW + kThreads - 1) / kThreads;
-  constexpr int ND = (DH * DW + kThreads - 1) / kThreads;
-  constexpr int NHZ = (HH * HW + kThreads - 1) / kThreads;
-  constexpr int NE = (NH * NW + kThreads - 1) / kThreads;
-  constexpr int NA = TY / (kThreads / kTX);
+  constexpr int NR = (RH * RW + NT - 1) / NT;
+  constexpr int NO = (EH * EW + NT - 1) / NT;
+  constexpr int ND = (DH * DW + NT - 1) / NT;
+  constexpr int NHZ = (HH * HW + NT - 1) / NT;
+  constexpr int NE = (NH * NW + NT - 1) / NT;
+  constexpr int RP = NT / kTX;  // tile rows per pass of the block
+  constexpr int NA = (TY + RP - 1) / RP;
   __shared__ float rEx[RH][RW], rEy[RH][RW];
   __shared__ float qEx[QH][QW], qEy[QH][QW];
   __shared__ float sExo[EH][EW], sEyo[EH][EW];
@@ -82,7 +117,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   if (filt) {
 #pragma unroll
     for (int q = 0; q < NR; q++) {
-      const int k = min(tid + q * kThreads, RH * RW - 1);
+      const int k = min(tid + q * NT, RH * RW - 1);
       const int i = i0 - 4 + k % RW, j = j0 - 4 + k / RW;
       pex[q] = A.ex0[o_ex(i, j)];
       pey[q] = A.ey0[o_ey(i, j)];
@@ -90,7 +125,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   } else {
 #pragma unroll
     for (int q = 0; q < NO; q++) {
-      const int k = min(tid + q * kThreads, EH * EW - 1);
+      const int k = min(tid + q * NT, EH * EW - 1);
       const int i = i0 - 2 + k % EW, j = j0 - 2 + k / EW;
       pex[q] = A.ex0[o_ex(i, j)];
       pey[q] = A.ey0[o_ey(i, j)];
@@ -99,19 +134,19 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   float pn[ND];
 #pragma unroll
   for (int q = 0; q < ND; q++) {
-    const int k = min(tid + q * kThreads, DH * DW - 1);
+    const int k = min(tid + q * NT, DH * DW - 1);
     pn[q] = A.n[o_nd(i0 - 1 + k % DW, j0 - 1 + k / DW)];
   }
   float phz[NHZ];
 #pragma unroll
   for (int q = 0; q < NHZ; q++) {
-    const int k = min(tid + q * kThreads, HH * HW - 1);
+    const int k = min(tid + q * NT, HH * HW - 1);
     phz[q] = A.hz0[o_hz(i0 - 2 + k % HW, j0 - 2 + k / HW)];
   }
   float pjx[NE], pjy[NE];
 #pragma unroll
   for (int q = 0; q < NE; q++) {
-    const int k = min(tid + q * kThreads, NH * NW - 1);
+    const int k = min(tid + q * NT, NH * NW - 1);
     const int i = i0 - 1 + k % NW, j = j0 - 1 + k / NW;
     pjx[q] = A.jx0[o_ex(i, j)];
     pjy[q] = A.jy0[o_ey(i, j)];
@@ -119,7 +154,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   const int tx = tid % kTX, ty = tid / kTX;
   float pacc[NA];
 #pragma unroll
-  for (int q = 0; q < NA; q++) pacc[q] = A.acc[o_nd(i0 + tx, j0 + ty + q * (kThreads / kTX))];
+  for (int q = 0; q < NA; q++) pacc[q] = A.acc[o_nd(i0 + tx, j0 + ty + q * RP)];
   // Eq. (5b) boundary values: x-edges of rows B and T, y-edges of columns L
   // and R inside this tile's new-E region, linear in space between the two
   // nearest coarse edges (weights w0, w1) and in time between the old and
@@ -155,8 +190,8 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
       bvalid = true;
     }
   }
-  const float* bp0 = bg >= 2 ? A.cey0 : A.cex0;
-  const float* bp1 = bg >= 2 ? A.cey1 : A.cex1;
+  const float* bp0 = (const float*)(bg >= 2 ? (uintptr_t)A.cey0 : (uintptr_t)A.cex0);
+  const float* bp1 = (const float*)(bg >= 2 ? (uintptr_t)A.cey1 : (uintptr_t)A.cex1);
   const float bo0 = bp0[bco], bo1 = bp0[bco2], bn0 = bp1[bco], bn1 = bp1[bco2];
 
   // -- old E: raw, Laplacian, filtered ----------------------------------------
@@ -167,7 +202,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   if (filt) {
 #pragma unroll
     for (int q = 0; q < NR; q++) {
-      const int k = tid + q * kThreads;
+      const int k = tid + q * NT;
       if (k < RH * RW) {
         const int ci = k % RW, cj = k / RW;
         const int i = i0 - 4 + ci, j = j0 - 4 + cj;
@@ -176,28 +211,26 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
       }
     }
     __syncthreads();
-    for (int k = tid; k < QH * QW; k += kThreads) {
+    for (int k = tid; k < QH * QW; k += NT) {
       const int ci = k % QW, cj = k / QW;
       const int i = i0 - 3 + ci, j = j0 - 3 + cj;
       const int a = ci + 1, b = cj + 1;  // raw coordinates
       float lx = 0.f, ly = 0.f;
       if (ex_ok(i, j)) {
         const float c = rEx[b][a];
-        lx = (ex_ok(i - 1, j) ? rEx[b][a - 1] : c) + (ex_ok(i + 1, j) ? rEx[b][a + 1] : c) +
-             (ex_ok(i, j - 1) ? rEx[b - 1][a] : c) + (ex_ok(i, j + 1) ? rEx[b + 1][a] : c) -
-             4.f * c;
+        lx = lap5(c, ex_ok(i - 1, j) ? rEx[b][a - 1] : c, ex_ok(i + 1, j) ? rEx[b][a + 1] : c,
+                  ex_ok(i, j - 1) ? rEx[b - 1][a] : c, ex_ok(i, j + 1) ? rEx[b + 1][a] : c);
       }
       if (ey_ok(i, j)) {
         const float c = rEy[b][a];
-        ly = (ey_ok(i - 1, j) ? rEy[b][a - 1] : c) + (ey_ok(i + 1, j) ? rEy[b][a + 1] : c) +
-             (ey_ok(i, j - 1) ? rEy[b - 1][a] : c) + (ey_ok(i, j + 1) ? rEy[b + 1][a] : c) -
-             4.f * c;
+        ly = lap5(c, ey_ok(i - 1, j) ? rEy[b][a - 1] : c, ey_ok(i + 1, j) ? rEy[b][a + 1] : c,
+                  ey_ok(i, j - 1) ? rEy[b - 1][a] : c, ey_ok(i, j + 1) ? rEy[b + 1][a] : c);
       }
       qEx[cj][ci] = lx;
       qEy[cj][ci] = ly;
     }
     __syncthreads();
-    for (int k = tid; k < EH * EW; k += kThreads) {
+    for (int k = tid; k < EH * EW; k += NT) {
       const int ci = k % EW, cj = k / EW;
       const int i = i0 - 2 + ci, j = j0 - 2 + cj;
       const int a = ci + 1, b = cj + 1;  // Laplacian coordinates
@@ -206,20 +239,18 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
         ex = rEx[cj + 2][ci + 2];
         if (j != B && j != T) {
           const float c = qEx[b][a];
-          const float l2 = (ex_ok(i - 1, j) ? qEx[b][a - 1] : c) + (ex_ok(i + 1, j) ? qEx[b][a + 1] : c) +
-                           (ex_ok(i, j - 1) ? qEx[b - 1][a] : c) + (ex_ok(i, j + 1) ? qEx[b + 1][a] : c) -
-                           4.f * c;
-          ex -= A.gamma * l2;
+          const float l2 = lap5(c, ex_ok(i - 1, j) ? qEx[b][a - 1] : c, ex_ok(i + 1, j) ? qEx[b][a + 1] : c,
+                                ex_ok(i, j - 1) ? qEx[b - 1][a] : c, ex_ok(i, j + 1) ? qEx[b + 1][a] : c);
+          ex = filter_e(ex, A.gamma, l2);
         }
       }
       if (ey_ok(i, j)) {
         ey = rEy[cj + 2][ci + 2];
         if (i != L && i != R) {
           const float c = qEy[b][a];
-          const float l2 = (ey_ok(i - 1, j) ? qEy[b][a - 1] : c) + (ey_ok(i + 1, j) ? qEy[b][a + 1] : c) +
-                           (ey_ok(i, j - 1) ? qEy[b - 1][a] : c) + (ey_ok(i, j + 1) ? qEy[b + 1][a] : c) -
-                           4.f * c;
-          ey -= A.gamma * l2;
+          const float l2 = lap5(c, ey_ok(i - 1, j) ? qEy[b][a - 1] : c, ey_ok(i + 1, j) ? qEy[b][a + 1] : c,
+                                ey_ok(i, j - 1) ? qEy[b - 1][a] : c, ey_ok(i, j + 1) ? qEy[b + 1][a] : c);
+          ey = filter_e(ey, A.gamma, l2);
         }
       }
       sExo[cj][ci] = ex;
@@ -228,7 +259,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   } else {
 #pragma unroll
     for (int q = 0; q < NO; q++) {
-      const int k = tid + q * kThreads;
+      const int k = tid + q * NT;
       if (k < EH * EW) {
         const int ci = k % EW, cj = k / EW;
         const int i = i0 - 2 + ci, j = j0 - 2 + cj;
@@ -239,23 +270,21 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   }
 #pragma unroll
   for (int q = 0; q < ND; q++) {
-    const int k = tid + q * kThreads;
+    const int k = tid + q * NT;
     if (k < DH * DW) {
       const int ci = k % DW, cj = k / DW;
       sN[cj][ci] = nd_ok(i0 - 1 + ci, j0 - 1 + cj) ? pn[q] : 0.f;
     }
   }
   {  // every thread writes (row 4 is a dummy), so the loads above stay put
-    const float vo = bw0 * bo0 + bw1 * bo1;
-    const float vn = bw0 * bn0 + bw1 * bn1;
-    sB[bg < 0 ? 4 : bg][bg < 0 ? 0 : bc] = bvalid ? (1.f - A.frac) * vo + A.frac * vn : 0.f;
+    sB[bg < 0 ? 4 : bg][bg < 0 ? 0 : bc] = bvalid ? cfb(bw0, bw1, bo0, bo1, bn0, bn1, A.frac) : 0.f;
   }
   __syncthreads();
 
   // -- Faraday, Eq. (2) -------------------------------------------------------
 #pragma unroll
   for (int q = 0; q < NHZ; q++) {
-    const int k = tid + q * kThreads;
+    const int k = tid + q * NT;
     if (k < HH * HW) {
       const int ci = k % HW, cj = k / HW;
       const int i = i0 - 2 + ci, j = j0 - 2 + cj;
@@ -265,7 +294,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
         const float dey = sEyo[cj][ci + 1] - sEyo[cj][ci];
         const float dex = sExo[cj + 1][ci] - sExo[cj][ci];
         ho = phz[q];
-        h = ho - A.S * (dey - dex);
+        h = faraday(ho, A.S, dey, dex);
         if (ci >= 2 && cj >= 2) A.hz1[o] = h;
       }
       sH[cj][ci] = h;
@@ -277,7 +306,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   // -- Ampere + Drude, Eqs. (1), (3); Eq. (5b) on the boundary ------------------
 #pragma unroll
   for (int q = 0; q < NE; q++) {
-    const int k = tid + q * kThreads;
+    const int k = tid + q * NT;
     if (k < NH * NW) {
       const int ci = k % NW, cj = k / NW;
       const int i = i0 - 1 + ci, j = j0 - 1 + cj;
@@ -291,12 +320,12 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
         const float jo = pjx[q];
         if (j != B && j != T) {
           const float dh = sH[cj + 1][ci + 1] - sH[cj][ci + 1];
-          exn = ((1.f - kap) * e + A.S * dh - A.c1 * jo) / (1.f + kap);
+          exn = ampere(e, kap, A.S * dh, A.c1, jo);
         } else {
           exn = sB[j == B ? 0 : 1][ci];
         }
         if (own) {
-          const float jn = A.a * jo + 2.f * kap * (e + exn);
+          const float jn = drude(A.a, jo, kap, e, exn);
           A.ex1[o] = exn;
           A.jx1[o] = jn;
           sJx[cj - 1][ci - 1] = jn;
@@ -309,13 +338,12 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
         const float jo = pjy[q];
         if (i != L && i != R) {
           const float dh = sH[cj + 1][ci + 1] - sH[cj + 1][ci];
-          const float curl = -A.S * dh;
-          eyn = ((1.f - kap) * e + curl - A.c1 * jo) / (1.f + kap);
+          eyn = ampere(e, kap, -A.S * dh, A.c1, jo);
         } else {
           eyn = sB[i == L ? 2 : 3][cj];
         }
         if (own) {
-          const float jn = A.a * jo + 2.f * kap * (e + eyn);
+          const float jn = drude(A.a, jo, kap, e, eyn);
           A.ey1[o] = eyn;
           A.jy1[o] = jn;
           sJy[cj - 1][ci - 1] = jn;
@@ -330,9 +358,9 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   // -- window accumulation at the tile's nodes ---------------------------------
 #pragma unroll
   for (int q = 0; q < NA; q++) {
-    const int r = ty + q * (kThreads / kTX);
+    const int r = ty + q * RP;
     const int i = i0 + tx, j = j0 + r;
-    if (!nd_ok(i, j)) continue;
+    if (r >= TY || !nd_ok(i, j)) continue;
     const int ci = tx + 1, cj = r + 1;
     float sx = 0.f, sy = 0.f;
     int cx = 0, cy = 0;
@@ -340,14 +368,14 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
     if (i < R) { const float v = sExn[cj][ci]; sx += v * v; cx++; }
     if (j > B) { const float v = sEyn[cj - 1][ci]; sy += v * v; cy++; }
     if (j < T) { const float v = sEyn[cj][ci]; sy += v * v; cy++; }
-    const float e2 = (cx == 2 ? 0.5f * sx : sx) + (cy == 2 ? 0.5f * sy : sy);
+    const float e2 = win_e2(sx, cx, sy, cy);
     const size_t o = (size_t)j * pitch + i;
     A.acc[o] = pacc[q] + e2;
   }
 
   // -- fine -> coarse transfer after the last substep ------------------------
   if (A.restrict_on) {
-    for (int r = ty; r < TY; r += kThreads / kTX) {
+    for (int r = ty; r < TY; r += RP) {
       const int i = i0 + tx, j = j0 + r;
       if (((i - L) | (j - B)) & 1) continue;
       const int a = i >> 1, b = j >> 1;
@@ -374,19 +402,488 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   }
 }
 
-template <int TY>
-__global__ __launch_bounds__(kThreads) void k_fine(EMArgs A) {
-  fine_tile<TY>(A, blockIdx.x, blockIdx.y);
+template <int TY, int NT>
+__global__ __launch_bounds__(NT) void k_fine(EMArgs A) {
+  fine_tile<TY, NT>(A, blockIdx.x, blockIdx.y);
+}
+
+// Eq. (5b) source of thread tid for one substep's new-E region (origin orig
+// relative to the tile corner, NW_ x NH_): group g (x-edges of row B / T,
+// y-edges of column L / R, -1 none), position c, the two coarse edges o, o2
+// with weights w0, w1; ok = the edge exists and lies in the region.
+__device__ __forceinline__ void bnd_src(int tid, int orig, int NW_, int NH_, int i0, int j0,
+                                        int L, int R, int B, int T, int cpitch, int& g,
+                                        int& c, size_t& o, size_t& o2, float& w0, float& w1,
+                                        bool& ok) {
+  g = -1; c = 0; o = 0; o2 = 0; w0 = 0.f; w1 = 0.f; ok = false;
+  if (tid < NW_) { g = 0; c = tid; }
+  else if (tid < 2 * NW_) { g = 1; c = tid - NW_; }
+  else if (tid < 2 * NW_ + NH_) { g = 2; c = tid - 2 * NW_; }
+  else if (tid < 2 * NW_ + 2 * NH_) { g = 3; c = tid - 2 * NW_ - NH_; }
+  if (g == 0 || g == 1) {
+    const int i = i0 + orig + c, j = g == 0 ? B : T;
+    if (i >= L && i < R && j >= j0 + orig && j < j0 + orig + NH_) {
+      int ic;
+      if ((i & 1) == 0) { ic = (i >> 1) - 1; w0 = 0.25f; w1 = 0.75f; }
+      else              { ic = i >> 1;       w0 = 0.75f; w1 = 0.25f; }
+      o = (size_t)(j >> 1) * cpitch + ic;
+      o2 = o + 1;
+      ok = true;
+    }
+  } else if (g >= 2) {
+    const int j = j0 + orig + c, i = g == 2 ? L : R;
+    if (j >= B && j < T && i >= i0 + orig && i < i0 + orig + NW_) {
+      int jc;
+      if ((j & 1) == 0) { jc = (j >> 1) - 1; w0 = 0.25f; w1 = 0.75f; }
+      else              { jc = j >> 1;       w0 = 0.75f; w1 = 0.25f; }
+      o = (size_t)jc * cpitch + (i >> 1);
+      o2 = o + cpitch;
+      ok = true;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Both patch substeps of a coarse step in one launch (temporal blocking).
+// Substep 1 runs over the tile grown by 3 cells on every side and stays in
+// LDS; substep 2 runs over the tile from those values and is the only one
+// written (fields, window, fine -> coarse transfer).  Reads the patch state
+// from buffer 0 and writes buffer 1.  Each entity is computed with the same
+// operations as by the two one-substep launches (the helpers above), so the
+// results are identical.  Region origins are relative to the tile corner
+// (i0, j0):  raw E0 -7, L(E0) -6, filtered E0 and H1 -5, E1/J1 and n -4;
+// then as in fine_tile: L(E1) -3, filtered E1 and H2 -2, E2/J2 -1.
+// ---------------------------------------------------------------------------
+template <int TY, int NT>
+__device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
+  constexpr int R1W = kTX + 13, R1H = TY + 13;
+  constexpr int Q1W = kTX + 11, Q1H = TY + 11;
+  constexpr int F1W = kTX + 9, F1H = TY + 9;
+  constexpr int H1W = kTX + 8, H1H = TY + 8;
+  constexpr int N1W = kTX + 7, N1H = TY + 7;
+  constexpr int D1W = kTX + 8, D1H = TY + 8;
+  constexpr int Q2W = kTX + 5, Q2H = TY + 5;
+  constexpr int F2W = kTX + 3, F2H = TY + 3;
+  constexpr int H2W = kTX + 2, H2H = TY + 2;
+  constexpr int N2W = kTX + 1, N2H = TY + 1;
+  constexpr int NR = (R1H * R1W + NT - 1) / NT;
+  constexpr int NH0 = (H1H * H1W + NT - 1) / NT;
+  constexpr int NJ0 = (N1H * N1W + NT - 1) / NT;
+  constexpr int ND = (D1H * D1W + NT - 1) / NT;
+  constexpr int RP = NT / kTX;  // tile rows per pass of the block
+  constexpr int NA = (TY + RP - 1) / RP;
+  __shared__ float rX[R1H][R1W], rY[R1H][R1W];  // raw E0
+  __shared__ float qX[Q1H][Q1W], qY[Q1H][Q1W];  // L(E0), then L(E1)
+  __shared__ float fX[F1H][F1W], fY[F1H][F1W];  // filtered E0, then filtered E1
+  __shared__ float sH1[H1H][H1W];
+  __shared__ float e1X[N1H][N1W], e1Y[N1H][N1W];
+  __shared__ float j1X[N2H][N2W], j1Y[N2H][N2W];
+  __shared__ float sN[D1H][D1W];
+  __shared__ float sH2[H2H][H2W];
+  __shared__ float e2X[N2H][N2W], e2Y[N2H][N2W];
+  __shared__ float j2X[TY][kTX], j2Y[TY][kTX];
+  __shared__ float sB1[5][N1W], sB2[5][N2W];  // Eq. (5b) values of substeps 1 and 2
+
+  const int i0 = A.L + bx * kTX;
+  const int j0 = A.B + by * TY;
+  const int tid = threadIdx.x;
+  const int L = A.L, R = A.R, B = A.B, T = A.T;
+  const int pitch = A.pitch;
+  const bool filt = A.gamma > 0.f;
+  const float frac1 = A.frac, frac2 = 1.f;
+  auto hz_ok = [=](int i, int j) { return i >= L && i < R && j >= B && j < T; };
+  auto ex_ok = [=](int i, int j) { return i >= L && i < R && j >= B && j <= T; };
+  auto ey_ok = [=](int i, int j) { return i >= L && i <= R && j >= B && j < T; };
+  auto nd_ok = [=](int i, int j) { return i >= L && i <= R && j >= B && j <= T; };
+  auto cl = [=](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
+  auto o_hz = [=](int i, int j) { return (size_t)cl(j, B, T - 1) * pitch + cl(i, L, R - 1); };
+  auto o_ex = [=](int i, int j) { return (size_t)cl(j, B, T) * pitch + cl(i, L, R - 1); };
+  auto o_ey = [=](int i, int j) { return (size_t)cl(j, B, T - 1) * pitch + cl(i, L, R); };
+  auto o_nd = [=](int i, int j) { return (size_t)cl(j, B, T) * pitch + cl(i, L, R); };
+
+  // -- one batch of global loads ------------------------------------------------
+  float pex[NR], pey[NR];
+#pragma unroll
+  for (int q = 0; q < NR; q++) {
+    const int k = min(tid + q * NT, R1H * R1W - 1);
+    const int i = i0 - 7 + k % R1W, j = j0 - 7 + k / R1W;
+    pex[q] = A.ex0[o_ex(i, j)];
+    pey[q] = A.ey0[o_ey(i, j)];
+  }
+  float phz[NH0];
+#pragma unroll
+  for (int q = 0; q < NH0; q++) {
+    const int k = min(tid + q * NT, H1H * H1W - 1);
+    phz[q] = A.hz0[o_hz(i0 - 5 + k % H1W, j0 - 5 + k / H1W)];
+  }
+  float pjx[NJ0], pjy[NJ0];
+#pragma unroll
+  for (int q = 0; q < NJ0; q++) {
+    const int k = min(tid + q * NT, N1H * N1W - 1);
+    const int i = i0 - 4 + k % N1W, j = j0 - 4 + k / N1W;
+    pjx[q] = A.jx0[o_ex(i, j)];
+    pjy[q] = A.jy0[o_ey(i, j)];
+  }
+  float pn[ND];
+#pragma unroll
+  for (int q = 0; q < ND; q++) {
+    const int k = min(tid + q * NT, D1H * D1W - 1);
+    pn[q] = A.n[o_nd(i0 - 4 + k % D1W, j0 - 4 + k / D1W)];
+  }
+  const int tx = tid % kTX, ty = tid / kTX;
+  float pacc[NA];
+#pragma unroll
+  for (int q = 0; q < NA; q++) pacc[q] = A.acc[o_nd(i0 + tx, j0 + ty + q * RP)];
+  // Eq. (5b) sources of both substeps: boundary x-edges of rows B, T and
+  // y-edges of columns L, R inside each substep's new-E region (origin
+  // -4 of width N1W x N1H for substep 1, -1 of N2W x N2H for substep 2)
+  int g1, c1_, g2, c2;
+  size_t o1a, o1b, o2a, o2b;
+  float w1a, w1b, w2a, w2b;
+  bool ok1, ok2;
+  bnd_src(tid, -4, N1W, N1H, i0, j0, L, R, B, T, A.cpitch, g1, c1_, o1a, o1b, w1a, w1b, ok1);
+  bnd_src(tid, -1, N2W, N2H, i0, j0, L, R, B, T, A.cpitch, g2, c2, o2a, o2b, w2a, w2b, ok2);
+  // addresses selected as integers (a select of two argument pointers can
+  // otherwise be lowered through private memory)
+  const float* b1o = (const float*)(g1 >= 2 ? (uintptr_t)A.cey0 : (uintptr_t)A.cex0);
+  const float* b1n = (const float*)(g1 >= 2 ? (uintptr_t)A.cey1 : (uintptr_t)A.cex1);
+  const float* b2o = (const float*)(g2 >= 2 ? (uintptr_t)A.cey0 : (uintptr_t)A.cex0);
+  const float* b2n = (const float*)(g2 >= 2 ? (uintptr_t)A.cey1 : (uintptr_t)A.cex1);
+  const float b1v0 = b1o[o1a], b1v1 = b1o[o1b], b1v2 = b1n[o1a], b1v3 = b1n[o1b];
+  const float b2v0 = b2o[o2a], b2v1 = b2o[o2b], b2v2 = b2n[o2a], b2v3 = b2n[o2b];
+
+  // -- substep 1: raw E0, n, boundary values ----------------------------------
+#pragma unroll
+  for (int q = 0; q < NR; q++) {
+    const int k = tid + q * NT;
+    if (k < R1H * R1W) {
+      const int ci = k % R1W, cj = k / R1W;
+      const int i = i0 - 7 + ci, j = j0 - 7 + cj;
+      rX[cj][ci] = ex_ok(i, j) ? pex[q] : 0.f;
+      rY[cj][ci] = ey_ok(i, j) ? pey[q] : 0.f;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < ND; q++) {
+    const int k = tid + q * NT;
+    if (k < D1H * D1W) {
+      const int ci = k % D1W, cj = k / D1W;
+      sN[cj][ci] = nd_ok(i0 - 4 + ci, j0 - 4 + cj) ? pn[q] : 0.f;
+    }
+  }
+  {  // every thread writes (row 4 is a dummy), so the loads above stay put
+    sB1[g1 < 0 ? 4 : g1][g1 < 0 ? 0 : c1_] = ok1 ? cfb(w1a, w1b, b1v0, b1v1, b1v2, b1v3, frac1) : 0.f;
+    sB2[g2 < 0 ? 4 : g2][g2 < 0 ? 0 : c2] = ok2 ? cfb(w2a, w2b, b2v0, b2v1, b2v2, b2v3, frac2) : 0.f;
+  }
+  __syncthreads();
+
+  // filter of E0: L over origin -6, filtered over origin -5
+  auto laplace = [&](const float (*rx)[R1W], const float (*ry)[R1W], int rorg, int qorg, int QW,
+                     int QH) {
+    for (int k = tid; k < QH * QW; k += NT) {
+      const int ci = k % QW, cj = k / QW;
+      const int i = i0 + qorg + ci, j = j0 + qorg + cj;
+      const int a = ci + (qorg - rorg), b = cj + (qorg - rorg);  // raw coordinates
+      float lx = 0.f, ly = 0.f;
+      if (ex_ok(i, j)) {
+        const float c = rx[b][a];
+        lx = lap5(c, ex_ok(i - 1, j) ? rx[b][a - 1] : c, ex_ok(i + 1, j) ? rx[b][a + 1] : c,
+                  ex_ok(i, j - 1) ? rx[b - 1][a] : c, ex_ok(i, j + 1) ? rx[b + 1][a] : c);
+      }
+      if (ey_ok(i, j)) {
+        const float c = ry[b][a];
+        ly = lap5(c, ey_ok(i - 1, j) ? ry[b][a - 1] : c, ey_ok(i + 1, j) ? ry[b][a + 1] : c,
+                  ey_ok(i, j - 1) ? ry[b - 1][a] : c, ey_ok(i, j + 1) ? ry[b + 1][a] : c);
+      }
+      qX[cj][ci] = lx;
+      qY[cj][ci] = ly;
+    }
+  };
+  auto filtered = [&](const float (*rx)[R1W], const float (*ry)[R1W], int rorg, int forg, int FW,
+                      int FH) {
+    for (int k = tid; k < FH * FW; k += NT) {
+      const int ci = k % FW, cj = k / FW;
+      const int i = i0 + forg + ci, j = j0 + forg + cj;
+      const int a = ci + 1, b = cj + 1;                          // Laplacian coordinates
+      const int ra = ci + (forg - rorg), rb = cj + (forg - rorg);  // raw coordinates
+      float ex = 0.f, ey = 0.f;
+      if (ex_ok(i, j)) {
+        ex = rx[rb][ra];
+        if (filt && j != B && j != T) {
+          const float c = qX[b][a];
+          const float l2 = lap5(c, ex_ok(i - 1, j) ? qX[b][a - 1] : c, ex_ok(i + 1, j) ? qX[b][a + 1] : c,
+                                ex_ok(i, j - 1) ? qX[b - 1][a] : c, ex_ok(i, j + 1) ? qX[b + 1][a] : c);
+          ex = filter_e(ex, A.gamma, l2);
+        }
+      }
+      if (ey_ok(i, j)) {
+        ey = ry[rb][ra];
+        if (filt && i != L && i != R) {
+          const float c = qY[b][a];
+          const float l2 = lap5(c, ey_ok(i - 1, j) ? qY[b][a - 1] : c, ey_ok(i + 1, j) ? qY[b][a + 1] : c,
+                                ey_ok(i, j - 1) ? qY[b - 1][a] : c, ey_ok(i, j + 1) ? qY[b + 1][a] : c);
+          ey = filter_e(ey, A.gamma, l2);
+        }
+      }
+      fX[cj][ci] = ex;
+      fY[cj][ci] = ey;
+    }
+  };
+  if (filt) {
+    laplace(rX, rY, -7, -6, Q1W, Q1H);
+    __syncthreads();
+  }
+  filtered(rX, rY, -7, -5, F1W, F1H);
+  __syncthreads();
+
+  // Faraday, H1 over origin -5
+#pragma unroll
+  for (int q = 0; q < NH0; q++) {
+    const int k = tid + q * NT;
+    if (k < H1H * H1W) {
+      const int ci = k % H1W, cj = k / H1W;
+      const int i = i0 - 5 + ci, j = j0 - 5 + cj;
+      float h = 0.f;
+      if (hz_ok(i, j)) {
+        const float dey = fY[cj][ci + 1] - fY[cj][ci];
+        const float dex = fX[cj + 1][ci] - fX[cj][ci];
+        h = faraday(phz[q], A.S, dey, dex);
+      }
+      sH1[cj][ci] = h;
+    }
+  }
+  __syncthreads();
+
+  // Ampere + Drude, E1 / J1 over origin -4
+#pragma unroll
+  for (int q = 0; q < NJ0; q++) {
+    const int k = tid + q * NT;
+    if (k < N1H * N1W) {
+      const int ci = k % N1W, cj = k / N1W;
+      const int i = i0 - 4 + ci, j = j0 - 4 + cj;
+      // J1 is kept over substep 2's new-E region (origin -1)
+      const bool keep = ci >= 3 && cj >= 3 && ci - 3 < N2W && cj - 3 < N2H;
+      float exn = 0.f, eyn = 0.f;
+      if (ex_ok(i, j)) {
+        const float e = fX[cj + 1][ci + 1];
+        const float ne = 0.5f * (sN[cj][ci] + sN[cj][ci + 1]);
+        const float kap = A.kn * ne;
+        const float jo = pjx[q];
+        if (j != B && j != T) {
+          const float dh = sH1[cj + 1][ci + 1] - sH1[cj][ci + 1];
+          exn = ampere(e, kap, A.S * dh, A.c1, jo);
+        } else {
+          exn = sB1[j == B ? 0 : 1][ci];
+        }
+        if (keep) j1X[cj - 3][ci - 3] = drude(A.a, jo, kap, e, exn);
+      }
+      if (ey_ok(i, j)) {
+        const float e = fY[cj + 1][ci + 1];
+        const float ne = 0.5f * (sN[cj][ci] + sN[cj + 1][ci]);
+        const float kap = A.kn * ne;
+        const float jo = pjy[q];
+        if (i != L && i != R) {
+          const float dh = sH1[cj + 1][ci + 1] - sH1[cj + 1][ci];
+          eyn = ampere(e, kap, -A.S * dh, A.c1, jo);
+        } else {
+          eyn = sB1[i == L ? 2 : 3][cj];
+        }
+        if (keep) j1Y[cj - 3][ci - 3] = drude(A.a, jo, kap, e, eyn);
+      }
+      e1X[cj][ci] = exn;
+      e1Y[cj][ci] = eyn;
+    }
+  }
+  __syncthreads();
+
+  // window after substep 1 at the tile's nodes (E1 origin -4)
+  float acc1[NA];
+#pragma unroll
+  for (int q = 0; q < NA; q++) {
+    const int r = min(ty + q * RP, TY - 1);  // rows past the tile: discarded
+    const int i = i0 + tx, j = j0 + r;
+    const int ci = tx + 4, cj = r + 4;
+    float sx = 0.f, sy = 0.f;
+    int cx = 0, cy = 0;
+    if (i > L) { const float v = e1X[cj][ci - 1]; sx += v * v; cx++; }
+    if (i < R) { const float v = e1X[cj][ci]; sx += v * v; cx++; }
+    if (j > B) { const float v = e1Y[cj - 1][ci]; sy += v * v; cy++; }
+    if (j < T) { const float v = e1Y[cj][ci]; sy += v * v; cy++; }
+    acc1[q] = pacc[q] + win_e2(sx, cx, sy, cy);
+  }
+
+  // -- substep 2: filter of E1 (raw = E1 at origin -4) -------------------------
+  auto laplace2 = [&]() {
+    for (int k = tid; k < Q2H * Q2W; k += NT) {
+      const int ci = k % Q2W, cj = k / Q2W;
+      const int i = i0 - 3 + ci, j = j0 - 3 + cj;
+      const int a = ci + 1, b = cj + 1;
+      float lx = 0.f, ly = 0.f;
+      if (ex_ok(i, j)) {
+        const float c = e1X[b][a];
+        lx = lap5(c, ex_ok(i - 1, j) ? e1X[b][a - 1] : c, ex_ok(i + 1, j) ? e1X[b][a + 1] : c,
+                  ex_ok(i, j - 1) ? e1X[b - 1][a] : c, ex_ok(i, j + 1) ? e1X[b + 1][a] : c);
+      }
+      if (ey_ok(i, j)) {
+        const float c = e1Y[b][a];
+        ly = lap5(c, ey_ok(i - 1, j) ? e1Y[b][a - 1] : c, ey_ok(i + 1, j) ? e1Y[b][a + 1] : c,
+                  ey_ok(i, j - 1) ? e1Y[b - 1][a] : c, ey_ok(i, j + 1) ? e1Y[b + 1][a] : c);
+      }
+      qX[cj][ci] = lx;
+      qY[cj][ci] = ly;
+    }
+  };
+  if (filt) {
+    laplace2();
+    __syncthreads();
+  }
+  for (int k = tid; k < F2H * F2W; k += NT) {
+    const int ci = k % F2W, cj = k / F2W;
+    const int i = i0 - 2 + ci, j = j0 - 2 + cj;
+    const int a = ci + 1, b = cj + 1;  // Laplacian coordinates (origin -3)
+    float ex = 0.f, ey = 0.f;
+    if (ex_ok(i, j)) {
+      ex = e1X[cj + 2][ci + 2];
+      if (filt && j != B && j != T) {
+        const float c = qX[b][a];
+        const float l2 = lap5(c, ex_ok(i - 1, j) ? qX[b][a - 1] : c, ex_ok(i + 1, j) ? qX[b][a + 1] : c,
+                              ex_ok(i, j - 1) ? qX[b - 1][a] : c, ex_ok(i, j + 1) ? qX[b + 1][a] : c);
+        ex = filter_e(ex, A.gamma, l2);
+      }
+    }
+    if (ey_ok(i, j)) {
+      ey = e1Y[cj + 2][ci + 2];
+      if (filt && i != L && i != R) {
+        const float c = qY[b][a];
+        const float l2 = lap5(c, ey_ok(i - 1, j) ? qY[b][a - 1] : c, ey_ok(i + 1, j) ? qY[b][a + 1] : c,
+                              ey_ok(i, j - 1) ? qY[b - 1][a] : c, ey_ok(i, j + 1) ? qY[b + 1][a] : c);
+        ey = filter_e(ey, A.gamma, l2);
+      }
+    }
+    fX[cj][ci] = ex;
+    fY[cj][ci] = ey;
+  }
+  __syncthreads();
+
+  // Faraday, H2 over origin -2 (H1 there at offset 3 in sH1)
+  for (int k = tid; k < H2H * H2W; k += NT) {
+    const int ci = k % H2W, cj = k / H2W;
+    const int i = i0 - 2 + ci, j = j0 - 2 + cj;
+    float h = 0.f;
+    if (hz_ok(i, j)) {
+      const float dey = fY[cj][ci + 1] - fY[cj][ci];
+      const float dex = fX[cj + 1][ci] - fX[cj][ci];
+      h = faraday(sH1[cj + 3][ci + 3], A.S, dey, dex);
+      if (ci >= 2 && cj >= 2) A.hz1[(size_t)j * pitch + i] = h;
+    }
+    sH2[cj][ci] = h;
+  }
+  __syncthreads();
+
+  // Ampere + Drude, E2 / J2 over origin -1 (n at offset 3, J1 at offset 0)
+  for (int k = tid; k < N2H * N2W; k += NT) {
+    const int ci = k % N2W, cj = k / N2W;
+    const int i = i0 - 1 + ci, j = j0 - 1 + cj;
+    const bool own = ci >= 1 && cj >= 1;
+    const size_t o = (size_t)j * pitch + i;
+    float exn = 0.f, eyn = 0.f;
+    if (ex_ok(i, j)) {
+      const float e = fX[cj + 1][ci + 1];
+      const float ne = 0.5f * (sN[cj + 3][ci + 3] + sN[cj + 3][ci + 4]);
+      const float kap = A.kn * ne;
+      const float jo = j1X[cj][ci];
+      if (j != B && j != T) {
+        const float dh = sH2[cj + 1][ci + 1] - sH2[cj][ci + 1];
+        exn = ampere(e, kap, A.S * dh, A.c1, jo);
+      } else {
+        exn = sB2[j == B ? 0 : 1][ci];
+      }
+      if (own) {
+        const float jn = drude(A.a, jo, kap, e, exn);
+        A.ex1[o] = exn;
+        A.jx1[o] = jn;
+        j2X[cj - 1][ci - 1] = jn;
+      }
+    }
+    if (ey_ok(i, j)) {
+      const float e = fY[cj + 1][ci + 1];
+      const float ne = 0.5f * (sN[cj + 3][ci + 3] + sN[cj + 4][ci + 3]);
+      const float kap = A.kn * ne;
+      const float jo = j1Y[cj][ci];
+      if (i != L && i != R) {
+        const float dh = sH2[cj + 1][ci + 1] - sH2[cj + 1][ci];
+        eyn = ampere(e, kap, -A.S * dh, A.c1, jo);
+      } else {
+        eyn = sB2[i == L ? 2 : 3][cj];
+      }
+      if (own) {
+        const float jn = drude(A.a, jo, kap, e, eyn);
+        A.ey1[o] = eyn;
+        A.jy1[o] = jn;
+        j2Y[cj - 1][ci - 1] = jn;
+      }
+    }
+    e2X[cj][ci] = exn;
+    e2Y[cj][ci] = eyn;
+  }
+  __syncthreads();
+
+  // window after substep 2
+#pragma unroll
+  for (int q = 0; q < NA; q++) {
+    const int r = ty + q * RP;
+    const int i = i0 + tx, j = j0 + r;
+    if (r >= TY || !nd_ok(i, j)) continue;
+    const int ci = tx + 1, cj = r + 1;
+    float sx = 0.f, sy = 0.f;
+    int cx = 0, cy = 0;
+    if (i > L) { const float v = e2X[cj][ci - 1]; sx += v * v; cx++; }
+    if (i < R) { const float v = e2X[cj][ci]; sx += v * v; cx++; }
+    if (j > B) { const float v = e2Y[cj - 1][ci]; sy += v * v; cy++; }
+    if (j < T) { const float v = e2Y[cj][ci]; sy += v * v; cy++; }
+    A.acc[(size_t)j * pitch + i] = acc1[q] + win_e2(sx, cx, sy, cy);
+  }
+
+  // fine -> coarse transfer (H1 at origin -5, H2 at origin -2)
+  for (int r = ty; r < TY; r += RP) {
+    const int i = i0 + tx, j = j0 + r;
+    if (((i - L) | (j - B)) & 1) continue;
+    const int a = i >> 1, b = j >> 1;
+    const size_t co = (size_t)b * A.cpitch + a;
+    const int ci = tx + 1, cj = r + 1;
+    if (hz_ok(i, j)) {
+      float s = 0.f;
+      for (int da = 0; da < 2; da++)
+        for (int db = 0; db < 2; db++) {
+          const float hold = sH1[r + 5 + db][tx + 5 + da];
+          s += 0.5f * (hold + sH2[r + 2 + db][tx + 2 + da]);
+        }
+      A.chz[co] = 0.25f * s;
+    }
+    if (ex_ok(i, j) && j > B && j < T) {
+      A.cex[co] = 0.5f * (e2X[cj][ci] + e2X[cj][ci + 1]);
+      A.cjx[co] = j2X[r][tx] + j2X[r][tx + 1];  // J~ scales with dt
+    }
+    if (ey_ok(i, j) && i > L && i < R) {
+      A.cey[co] = 0.5f * (e2Y[cj][ci] + e2Y[cj + 1][ci]);
+      A.cjy[co] = j2Y[r][tx] + j2Y[r + 1][tx];
+    }
+  }
+}
+
+template <int TY, int NT>
+__global__ __launch_bounds__(NT) void k_fine2(EMArgs A) {
+  fine2_tile<TY, NT>(A, blockIdx.x, blockIdx.y);
 }
 
 // batched form: one launch over the tiles of many independent instances;
 // blk[b] = (instance, tile index within it)
 template <int TY>
-__global__ __launch_bounds__(kThreads) void k_fine_batch(const EMArgs* __restrict__ args,
-                                                         const int2* __restrict__ blk) {
+__global__ __launch_bounds__(kFineThreads) void k_fine_batch(const EMArgs* __restrict__ args,
+                                                             const int2* __restrict__ blk) {
   const int2 bi = blk[blockIdx.x];
   const EMArgs& A = args[bi.x];
-  fine_tile<TY>(A, bi.y % A.nbx, bi.y / A.nbx);
+  fine_tile<TY, kFineThreads>(A, bi.y % A.nbx, bi.y / A.nbx);
 }
 
 // ---------------------------------------------------------------------------
@@ -894,14 +1391,29 @@ __global__ __launch_bounds__(kThreads) void k_em_stream_batch(const EMArgs* __re
 }
 
 // ---- host-side launchers ----------------------------------------------------
-hipError_t launch_em(const EMArgs& A, bool fine, int ty, hipStream_t st) {
+// patch kernels: 64 x TY node tiles, NT threads per tile
+#define DMR_LAUNCH_TILE(KERNEL, TY_, nt, A, st)                                          \
+  do {                                                                                  \
+    const dim3 g_((A.R - A.L + 1 + kTX - 1) / kTX, (A.T - A.B + 1 + (TY_)-1) / (TY_));  \
+    if ((nt) >= 1024) hipLaunchKernelGGL((KERNEL<TY_, 1024>), g_, dim3(1024), 0, st, A); \
+    else hipLaunchKernelGGL((KERNEL<TY_, 256>), g_, dim3(256), 0, st, A);                \
+  } while (0)
+
+hipError_t launch_em(const EMArgs& A, bool fine, int ty, int nt, hipStream_t st) {
   if (!fine) return hipErrorInvalidValue;  // the base level uses the streaming kernel
-  const int nx = A.R - A.L + 1, ny = A.T - A.B + 1;
-  dim3 blk(kThreads);
   switch (ty) {
-  case 4: hipLaunchKernelGGL(k_fine<4>, dim3((nx + kTX - 1) / kTX, (ny + 3) / 4), blk, 0, st, A); break;
-  case 8: hipLaunchKernelGGL(k_fine<8>, dim3((nx + kTX - 1) / kTX, (ny + 7) / 8), blk, 0, st, A); break;
-  default: hipLaunchKernelGGL(k_fine<16>, dim3((nx + kTX - 1) / kTX, (ny + 15) / 16), blk, 0, st, A); break;
+  case 4: DMR_LAUNCH_TILE(k_fine, 4, nt, A, st); break;
+  case 8: DMR_LAUNCH_TILE(k_fine, 8, nt, A, st); break;
+  default: DMR_LAUNCH_TILE(k_fine, 16, nt, A, st); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st) {
+  switch (ty) {
+  case 4: DMR_LAUNCH_TILE(k_fine2, 4, nt, A, st); break;
+  case 8: DMR_LAUNCH_TILE(k_fine2, 8, nt, A, st); break;
+  default: DMR_LAUNCH_TILE(k_fine2, 16, nt, A, st); break;
   }
   return hipGetLastError();
 }
@@ -920,9 +1432,9 @@ hipError_t launch_em_batch(const EMArgs* args, const int2* blk, int nblk, int ty
                            hipStream_t st) {
   if (nblk <= 0) return hipSuccess;
   switch (ty) {
-  case 4: hipLaunchKernelGGL(k_fine_batch<4>, dim3(nblk), dim3(kThreads), 0, st, args, blk); break;
-  case 8: hipLaunchKernelGGL(k_fine_batch<8>, dim3(nblk), dim3(kThreads), 0, st, args, blk); break;
-  default: hipLaunchKernelGGL(k_fine_batch<16>, dim3(nblk), dim3(kThreads), 0, st, args, blk); break;
+  case 4: hipLaunchKernelGGL(k_fine_batch<4>, dim3(nblk), dim3(kFineThreads), 0, st, args, blk); break;
+  case 8: hipLaunchKernelGGL(k_fine_batch<8>, dim3(nblk), dim3(kFineThreads), 0, st, args, blk); break;
+  default: hipLaunchKernelGGL(k_fine_batch<16>, dim3(nblk), dim3(kFineThreads), 0, st, args, blk); break;
   }
   return hipGetLastError();
 }
