@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--only-large", action="store_true",
                     help="profiling aid: run only 4096x2048 base steps and a "
                          "256 MiB device copy (counter calibration), no JSON")
+    ap.add_argument("--only-config1", action="store_true",
+                    help="profiling aid: run only 256 steps of DMR config 1 and a "
+                         "256 MiB device copy (counter calibration), no JSON")
     return ap.parse_args()
 
 
@@ -77,7 +80,7 @@ def traffic_records():
     the kernel source is the one that was profiled; else {}."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "k_em_stream_4096x2048_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles", "hbm_counters_large_and_config1.md")
     src = os.path.join(ROOT, "paper_2105_13276_amd", "csrc", "dmr_kernels.hip")
     if not (os.path.exists(path) and os.path.exists(src)):
         return {}
@@ -91,6 +94,25 @@ def traffic_records():
             f, w, ff, wf = (float(m.group(k)) for k in (2, 3, 4, 5))
             out[m.group(1)] = (f * ff + w * wf) * 1024.0
     return out
+
+
+def only_config1(steps=256):
+    """Profiling aid: DMR config-1 steps (one combined launch per coarse step)
+    and the 256 MiB calibration copy."""
+    import torch
+    from paper_2105_13276_amd import binding as B
+    from paper_2105_13276_amd import workloads as W
+    cfg = W.config1_dmr(periods=4)
+    sim = B.Sim(cfg, *W.seeds(cfg))
+    sim.step(steps)
+    sim.sync()
+    a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print("only-config1: %d steps, patch %s" % (steps, sim.patch()), flush=True)
 
 
 def em_bytes_per_cell():
@@ -183,6 +205,9 @@ def main():
     if args.only_large:
         only_large()
         return
+    if args.only_config1:
+        only_config1()
+        return
     import numpy as np
     import torch
     from paper_2105_13276_amd import binding as B
@@ -223,7 +248,8 @@ def main():
     dom = int(np.argmax(ms))
     per_launch_ms = ms[dom] / max(cnt[dom], 1)
     if dom == 0:
-        alg_bytes = em_bytes_per_cell() * coarse_cells
+        # without patch launches the base launch also ran both patch substeps
+        alg_bytes = em_bytes_per_cell() * (coarse_cells + (2 * fine_cells if cnt[1] == 0 else 0))
     elif dom == 1:
         # one launch per coarse step runs both substeps (two cell-updates per cell)
         subs = 2 if cnt[1] == cnt[0] else 1
@@ -232,11 +258,14 @@ def main():
         alg_bytes = None
     achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9 if alg_bytes else None
     rec = traffic_records()
-    roofline = {"bound": "hbm", "kernel": "k_em_stream (base)" if dom == 0 else
+    roofline = {"bound": "hbm", "kernel": ("k_dmr_step (base step + both patch substeps)"
+                                           if cnt[1] == 0 else "k_em_stream (base)") if dom == 0 else
                 ("k_fine2 (both patch substeps)" if dom == 1 else cls_names[dom]),
                 "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                 "frac": (achieved / 8000.0) if achieved else None,
-                "traffic": rec.get("k_fine2@64x64") if (dom == 1 and fine_cells == 64 * 64) else None,
+                "traffic": (rec.get("k_dmr_step@config1") if (dom == 0 and cnt[1] == 0)
+                            else rec.get("k_fine2@64x64") if dom == 1 else None)
+                           if fine_cells == 64 * 64 else None,
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_us": per_launch_ms * 1e3,
                 "note": "config-1 state (7.9 MB) is cache resident and its kernels are "
                         "latency-bound (per-launch HIP events add ~2 us to the ~9 us "

@@ -178,6 +178,8 @@ struct dmr_sim {
   // both patch substeps in one launch (dmr_step only; the adjoint's record and
   // replay and the batched form run them one launch each, bit-identically)
   bool fuse_fine = true;
+  // base-level step and both patch substeps in one launch (dmr_step only)
+  bool combine = true;
   int nt1 = 1024;  // threads per patch tile
   uint8_t* d_flag = nullptr;
   int32_t *d_scan = nullptr, *d_list = nullptr;
@@ -555,17 +557,44 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
   EMArgs A;
   make_base_em(s, c, s->ncur, &A);
   incident_values(s, s->step, &A.ey_src, &A.hz_src);
-  ev_begin(s, 0);
-  hipError_t e = launch_em_stream(A, s->seg0, s->depth0, s->st);
-  ev_end(s);
-  if (e != hipSuccess) return hipfail(s, e, "base EM launch");
+  hipError_t e = hipSuccess;
+  const bool combined = s->has_patch && s->combine && s->fuse_fine && !cx;
+  if (combined) {  // base step and both patch substeps, one launch
+    Level &C = s->L0, &F = s->L1;
+    A.skip_on = 1;
+    A.sL = s->ext[0]; A.sB = s->ext[1]; A.sR = s->ext[2]; A.sT = s->ext[3];
+    EMArgs G;
+    make_fine_em(s, p.r, c, s->ncur, s->ty1, &G);  // restriction targets
+    em_args_level(&G, F, 0, 1, F.n[s->ncur], F.acc);
+    G.frac = 1.f / (float)p.r;  // time fraction of substep 1
+    G.chz0 = C.hz[c]; G.cjx0 = C.jx[c]; G.cjy0 = C.jy[c]; G.cn0 = C.n[s->ncur];
+    G.cS = C.S; G.cc1 = C.c1; G.ckn = C.kn; G.cis = p.tfsf_i;
+    G.cey_src = A.ey_src; G.chz_src = A.hz_src;
+    G.cnx = p.nx; G.cny = p.ny;
+    ev_begin(s, 0);
+    e = launch_dmr_step(A, G, s->seg0, s->depth0, s->ty1, s->st);
+    ev_end(s);
+    if (e != hipSuccess) return hipfail(s, e, "combined step launch");
+    std::swap(F.hz[0], F.hz[1]);
+    std::swap(F.ex[0], F.ex[1]);
+    std::swap(F.ey[0], F.ey[1]);
+    std::swap(F.jx[0], F.jx[1]);
+    std::swap(F.jy[0], F.jy[1]);
+  } else {
+    ev_begin(s, 0);
+    e = launch_em_stream(A, s->seg0, s->depth0, s->st);
+    ev_end(s);
+    if (e != hipSuccess) return hipfail(s, e, "base EM launch");
+  }
   if (st) {
     CopyJobs J{};
     job(&J, s->L0.ex[1 - c], cx->ss.cexp, s->L0.plane);
     job(&J, s->L0.ey[1 - c], cx->ss.ceyp, s->L0.plane);
     if (int rc = run_copies(s, J)) return rc;
   }
-  if (s->has_patch && s->fuse_fine && !cx) {  // both substeps, one launch
+  if (combined) {
+    // done above
+  } else if (s->has_patch && s->fuse_fine && !cx) {  // both substeps, one launch
     Level& F = s->L1;
     EMArgs G;
     make_fine_em(s, p.r, c, s->ncur, s->ty1, &G);  // restriction targets
@@ -757,6 +786,10 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   s->stage = (float*)(s->ws + lay.off_stage);
   s->seg0 = stream_rows(p->nx, p->ny);
   if (const char* f = getenv("DMR_FUSE")) s->fuse_fine = atoi(f) != 0;
+  // one launch per coarse step pays off where launch latency dominates; on
+  // bandwidth-bound grids the base kernel's own launch shape is faster
+  s->combine = (long)p->nx * p->ny <= (1L << 21);
+  if (const char* f = getenv("DMR_COMBINE")) s->combine = atoi(f) != 0;
   if (const char* f = getenv("DMR_FNT")) s->nt1 = atoi(f) >= 1024 ? 1024 : 256;
   s->depth0 = stream_depth(s->seg0);
   hipError_t e = hipMemsetAsync(s->ws, 0, lay.total, s->st);
@@ -1815,6 +1848,7 @@ int dmr_batch_create(const dmr_params* p, int count, const double* const* seed_b
       return rc;
     }
     s->fuse_fine = false;  // the batch's tables name fixed patch buffers
+    s->combine = false;
     b->sims.push_back(s);
   }
   b->d_em = (EMArgs*)(b->ws + L.off_em);

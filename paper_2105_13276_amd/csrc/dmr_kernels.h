@@ -39,6 +39,14 @@ struct EMArgs {
   float *chz, *cex, *cey, *cjx, *cjy;
   // batched launches: tiles per row of tiles, and the streaming segments
   int nbx, seg, nseg;
+  // base level in the combined step: coarse entities [sL,sR) x [sB,sT)
+  // strictly inside the patch are not stored (the patch tiles write them)
+  int skip_on, sL, sB, sR, sT;
+  // patch tiles of the combined step: coarse state entering the step, for
+  // the coarse E after it on the patch boundary lines (computed locally)
+  const float *chz0, *cjx0, *cjy0, *cn0;
+  float cS, cc1, ckn, cey_src, chz_src;
+  int cis, cnx, cny;
 };
 
 struct ContArgs {
@@ -93,6 +101,10 @@ hipError_t launch_em(const EMArgs& A, bool fine, int ty, int nt, hipStream_t st)
 // both patch substeps of a coarse step in one launch: reads buffer 0 (hz0..),
 // writes buffer 1 (hz1..), A.frac = time fraction of substep 1, restriction on
 hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st);
+// base-level step (C, with the patch's coarse entities skipped) and both patch
+// substeps (F, coarse boundary E computed in the tiles) in one launch
+hipError_t launch_dmr_step(const EMArgs& C, const EMArgs& F, int seg, int depth, int ty,
+                           hipStream_t st);
 // base level, column-streaming kernel; seg = rows per segment (>= 2)
 hipError_t launch_em_stream(const EMArgs& A, int seg, int depth, hipStream_t st);
 int stream_segments(int NY, int seg);

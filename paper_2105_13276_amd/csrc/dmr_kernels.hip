@@ -21,6 +21,20 @@
 
 namespace dmr {
 
+// Base-level per-entity arithmetic, shared by the streaming kernel and the
+// patch tiles of the combined step (which recompute coarse E on the patch
+// boundary lines), so both round identically.
+__device__ inline float base_kap(float kn, float n0, float n1) { return kn * (0.5f * (n0 + n1)); }
+__device__ inline float base_hz(float hz, float S, float ey1, float ey, float exu, float ex) {
+  return hz - S * ((ey1 - ey) - (exu - ex));
+}
+__device__ inline float base_ex(float e, float kap, float S, float h, float hp, float c1, float j) {
+  return ((1.f - kap) * e + S * (h - hp) - c1 * j) * __builtin_amdgcn_rcpf(1.f + kap);
+}
+__device__ inline float base_ey(float e, float kap, float curl, float c1, float j) {
+  return ((1.f - kap) * e + curl - c1 * j) * __builtin_amdgcn_rcpf(1.f + kap);
+}
+
 // ---------------------------------------------------------------------------
 // Per-entity arithmetic of the patch substep, shared by the one-substep and
 // the two-substep kernels so that both round identically.
@@ -410,12 +424,13 @@ __global__ __launch_bounds__(NT) void k_fine(EMArgs A) {
 // Eq. (5b) source of thread tid for one substep's new-E region (origin orig
 // relative to the tile corner, NW_ x NH_): group g (x-edges of row B / T,
 // y-edges of column L / R, -1 none), position c, the two coarse edges o, o2
-// with weights w0, w1; ok = the edge exists and lies in the region.
+// (o at coarse column / row cidx along the line) with weights w0, w1;
+// ok = the edge exists and lies in the region.
 __device__ __forceinline__ void bnd_src(int tid, int orig, int NW_, int NH_, int i0, int j0,
                                         int L, int R, int B, int T, int cpitch, int& g,
                                         int& c, size_t& o, size_t& o2, float& w0, float& w1,
-                                        bool& ok) {
-  g = -1; c = 0; o = 0; o2 = 0; w0 = 0.f; w1 = 0.f; ok = false;
+                                        bool& ok, int& cidx) {
+  g = -1; c = 0; o = 0; o2 = 0; w0 = 0.f; w1 = 0.f; ok = false; cidx = 0;
   if (tid < NW_) { g = 0; c = tid; }
   else if (tid < 2 * NW_) { g = 1; c = tid - NW_; }
   else if (tid < 2 * NW_ + NH_) { g = 2; c = tid - 2 * NW_; }
@@ -429,6 +444,7 @@ __device__ __forceinline__ void bnd_src(int tid, int orig, int NW_, int NH_, int
       o = (size_t)(j >> 1) * cpitch + ic;
       o2 = o + 1;
       ok = true;
+      cidx = ic;
     }
   } else if (g >= 2) {
     const int j = j0 + orig + c, i = g == 2 ? L : R;
@@ -439,6 +455,7 @@ __device__ __forceinline__ void bnd_src(int tid, int orig, int NW_, int NH_, int
       o = (size_t)jc * cpitch + (i >> 1);
       o2 = o + cpitch;
       ok = true;
+      cidx = jc;
     }
   }
 }
@@ -454,7 +471,7 @@ __device__ __forceinline__ void bnd_src(int tid, int orig, int NW_, int NH_, int
 // (i0, j0):  raw E0 -7, L(E0) -6, filtered E0 and H1 -5, E1/J1 and n -4;
 // then as in fine_tile: L(E1) -3, filtered E1 and H2 -2, E2/J2 -1.
 // ---------------------------------------------------------------------------
-template <int TY, int NT>
+template <int TY, int NT, bool LOCAL>
 __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
   constexpr int R1W = kTX + 13, R1H = TY + 13;
   constexpr int Q1W = kTX + 11, Q1H = TY + 11;
@@ -537,20 +554,61 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
   // Eq. (5b) sources of both substeps: boundary x-edges of rows B, T and
   // y-edges of columns L, R inside each substep's new-E region (origin
   // -4 of width N1W x N1H for substep 1, -1 of N2W x N2H for substep 2)
-  int g1, c1_, g2, c2;
+  int g1, c1_, g2, c2, k1, k2;
   size_t o1a, o1b, o2a, o2b;
   float w1a, w1b, w2a, w2b;
   bool ok1, ok2;
-  bnd_src(tid, -4, N1W, N1H, i0, j0, L, R, B, T, A.cpitch, g1, c1_, o1a, o1b, w1a, w1b, ok1);
-  bnd_src(tid, -1, N2W, N2H, i0, j0, L, R, B, T, A.cpitch, g2, c2, o2a, o2b, w2a, w2b, ok2);
+  bnd_src(tid, -4, N1W, N1H, i0, j0, L, R, B, T, A.cpitch, g1, c1_, o1a, o1b, w1a, w1b, ok1, k1);
+  bnd_src(tid, -1, N2W, N2H, i0, j0, L, R, B, T, A.cpitch, g2, c2, o2a, o2b, w2a, w2b, ok2, k2);
   // addresses selected as integers (a select of two argument pointers can
   // otherwise be lowered through private memory)
   const float* b1o = (const float*)(g1 >= 2 ? (uintptr_t)A.cey0 : (uintptr_t)A.cex0);
-  const float* b1n = (const float*)(g1 >= 2 ? (uintptr_t)A.cey1 : (uintptr_t)A.cex1);
   const float* b2o = (const float*)(g2 >= 2 ? (uintptr_t)A.cey0 : (uintptr_t)A.cex0);
-  const float* b2n = (const float*)(g2 >= 2 ? (uintptr_t)A.cey1 : (uintptr_t)A.cex1);
-  const float b1v0 = b1o[o1a], b1v1 = b1o[o1b], b1v2 = b1n[o1a], b1v3 = b1n[o1b];
-  const float b2v0 = b2o[o2a], b2v1 = b2o[o2b], b2v2 = b2n[o2a], b2v3 = b2n[o2b];
+  const float b1v0 = b1o[o1a], b1v1 = b1o[o1b];
+  const float b2v0 = b2o[o2a], b2v1 = b2o[o2b];
+  float b1v2 = 0.f, b1v3 = 0.f, b2v2 = 0.f, b2v3 = 0.f;
+  if constexpr (!LOCAL) {
+    const float* b1n = (const float*)(g1 >= 2 ? (uintptr_t)A.cey1 : (uintptr_t)A.cex1);
+    const float* b2n = (const float*)(g2 >= 2 ? (uintptr_t)A.cey1 : (uintptr_t)A.cex1);
+    b1v2 = b1n[o1a]; b1v3 = b1n[o1b];
+    b2v2 = b2n[o2a]; b2v3 = b2n[o2b];
+  }
+  // combined step: the coarse E after the coarse step on the patch boundary
+  // lines is computed here from the coarse state entering it (the base-level
+  // waves of the same launch compute the same values).  x-lines: coarse rows
+  // B/2 and T/2 at columns [cx0, cx0 + CW); y-lines: coarse columns L/2 and
+  // R/2 at rows [cy0, cy0 + CH).
+  constexpr int CW = kTX / 2 + 6, CH = TY / 2 + 6;
+  __shared__ float sC[5][CW > CH ? CW : CH];
+  const int cx0 = ((i0 - 4) >> 1) - 1, cy0 = ((j0 - 4) >> 1) - 1;
+  int cg = -1, cc = 0;
+  float q[12];
+  if constexpr (LOCAL) {
+    if (tid < CW) { cg = 0; cc = tid; }
+    else if (tid < 2 * CW) { cg = 1; cc = tid - CW; }
+    else if (tid < 2 * CW + CH) { cg = 2; cc = tid - 2 * CW; }
+    else if (tid < 2 * CW + 2 * CH) { cg = 3; cc = tid - 2 * CW - CH; }
+    const int cp = A.cpitch, NXc = A.cnx, NYc = A.cny;
+    auto cidx = [=](int a, int b) {  // clamped coarse address
+      const int aa = a < 0 ? 0 : (a > NXc ? NXc : a), bb = b < 0 ? 0 : (b > NYc ? NYc : b);
+      return (size_t)bb * cp + aa;
+    };
+    if (cg <= 1) {  // x-edge (ic, J) of a boundary row (threads without a role: cg = -1)
+      const int ic = cx0 + cc, J = cg == 1 ? (T >> 1) : (B >> 1);
+      q[0] = A.cex0[cidx(ic, J - 1)]; q[1] = A.cex0[cidx(ic, J)]; q[2] = A.cex0[cidx(ic, J + 1)];
+      q[3] = A.cey0[cidx(ic, J - 1)]; q[4] = A.cey0[cidx(ic + 1, J - 1)];
+      q[5] = A.cey0[cidx(ic, J)]; q[6] = A.cey0[cidx(ic + 1, J)];
+      q[7] = A.chz0[cidx(ic, J - 1)]; q[8] = A.chz0[cidx(ic, J)];
+      q[9] = A.cjx0[cidx(ic, J)]; q[10] = A.cn0[cidx(ic, J)]; q[11] = A.cn0[cidx(ic + 1, J)];
+    } else {        // y-edge (I, jc) of a boundary column
+      const int jc = cy0 + cc, I = cg == 3 ? (R >> 1) : (L >> 1);
+      q[0] = A.cey0[cidx(I - 1, jc)]; q[1] = A.cey0[cidx(I, jc)]; q[2] = A.cey0[cidx(I + 1, jc)];
+      q[3] = A.cex0[cidx(I - 1, jc)]; q[4] = A.cex0[cidx(I - 1, jc + 1)];
+      q[5] = A.cex0[cidx(I, jc)]; q[6] = A.cex0[cidx(I, jc + 1)];
+      q[7] = A.chz0[cidx(I - 1, jc)]; q[8] = A.chz0[cidx(I, jc)];
+      q[9] = A.cjy0[cidx(I, jc)]; q[10] = A.cn0[cidx(I, jc)]; q[11] = A.cn0[cidx(I, jc + 1)];
+    }
+  }
 
   // -- substep 1: raw E0, n, boundary values ----------------------------------
 #pragma unroll
@@ -571,11 +629,42 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
       sN[cj][ci] = nd_ok(i0 - 4 + ci, j0 - 4 + cj) ? pn[q] : 0.f;
     }
   }
-  {  // every thread writes (row 4 is a dummy), so the loads above stay put
+  if constexpr (LOCAL) {  // coarse E after the coarse step (base_* as the base level)
+    float v;
+    const float S = A.cS, c1 = A.cc1;
+    if (cg <= 1) {
+      const int ic = cx0 + cc;
+      float hp = base_hz(q[7], S, q[4], q[3], q[1], q[0]);
+      if (ic == A.cis - 1) hp += S * A.cey_src;
+      float h = base_hz(q[8], S, q[6], q[5], q[2], q[1]);
+      if (ic == A.cis - 1) h += S * A.cey_src;
+      const float kap = base_kap(A.ckn, q[10], q[11]);
+      v = base_ex(q[1], kap, S, h, hp, c1, q[9]);
+    } else {
+      const int I = cg == 3 ? (R >> 1) : (L >> 1);
+      float h = base_hz(q[8], S, q[2], q[1], q[6], q[5]);
+      if (I == A.cis - 1) h += S * A.cey_src;
+      float hl = base_hz(q[7], S, q[1], q[0], q[4], q[3]);
+      if (I - 1 == A.cis - 1) hl += S * A.cey_src;
+      float curl = -S * (h - hl);
+      if (I == A.cis) curl += S * A.chz_src;
+      const float kap = base_kap(A.ckn, q[10], q[11]);
+      v = base_ey(q[1], kap, curl, c1, q[9]);
+    }
+    sC[cg < 0 ? 4 : cg][cg < 0 ? 0 : cc] = v;
+  } else {  // every thread writes (row 4 is a dummy), so the loads above stay put
     sB1[g1 < 0 ? 4 : g1][g1 < 0 ? 0 : c1_] = ok1 ? cfb(w1a, w1b, b1v0, b1v1, b1v2, b1v3, frac1) : 0.f;
     sB2[g2 < 0 ? 4 : g2][g2 < 0 ? 0 : c2] = ok2 ? cfb(w2a, w2b, b2v0, b2v1, b2v2, b2v3, frac2) : 0.f;
   }
   __syncthreads();
+  if constexpr (LOCAL) {  // Eq. (5b) values from the old coarse E and sC
+    const int x1 = g1 >= 2 ? cy0 : cx0, x2 = g2 >= 2 ? cy0 : cx0;
+    const int r1 = g1 < 0 ? 4 : g1, r2 = g2 < 0 ? 4 : g2;
+    const float n1a = ok1 ? sC[r1][k1 - x1] : 0.f, n1b = ok1 ? sC[r1][k1 + 1 - x1] : 0.f;
+    const float n2a = ok2 ? sC[r2][k2 - x2] : 0.f, n2b = ok2 ? sC[r2][k2 + 1 - x2] : 0.f;
+    sB1[r1][g1 < 0 ? 0 : c1_] = ok1 ? cfb(w1a, w1b, b1v0, b1v1, n1a, n1b, frac1) : 0.f;
+    sB2[r2][g2 < 0 ? 0 : c2] = ok2 ? cfb(w2a, w2b, b2v0, b2v1, n2a, n2b, frac2) : 0.f;
+  }
 
   // filter of E0: L over origin -6, filtered over origin -5
   auto laplace = [&](const float (*rx)[R1W], const float (*ry)[R1W], int rorg, int qorg, int QW,
@@ -873,8 +962,9 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
 
 template <int TY, int NT>
 __global__ __launch_bounds__(NT) void k_fine2(EMArgs A) {
-  fine2_tile<TY, NT>(A, blockIdx.x, blockIdx.y);
+  fine2_tile<TY, NT, false>(A, blockIdx.x, blockIdx.y);
 }
+
 
 // batched form: one launch over the tiles of many independent instances;
 // blk[b] = (instance, tile index within it)
@@ -1223,11 +1313,11 @@ __device__ inline RowData mask_row(const EMArgs& A, const RowData& q, int i, int
 }
 
 template <int DEPTH>
-__device__ __forceinline__ void em_stream_body(const EMArgs& A, int bx, int k, int seg,
+__device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, int seg,
                                                int nseg, float ey_src, float hz_src) {
   const int NX = A.R, NY = A.T;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int c0 = (bx * (kThreads / 64) + wv) * 62;
+  const int lane = threadIdx.x & 63;
+  const int c0 = cw * 62;  // first own column of this wave
   const int i = c0 - 2 + lane;
   const bool own = lane >= 2 && i <= NX;
   const int j0 = k * seg;
@@ -1237,6 +1327,10 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int bx, int k, i
   const bool exv = i >= 0 && i < NX;
   const bool eyc = i >= 0 && i <= NX;
   const float S = A.S, c1 = A.c1, a = A.a, kn = A.kn, cm = A.cmur;
+  // combined step: the coarse entities strictly inside the patch are written
+  // by the patch tiles' fine -> coarse transfer in the same launch
+  const bool skc = A.skip_on && i >= A.sL && i < A.sR;  // cells, x-edges
+  const bool sky = A.skip_on && i > A.sL && i < A.sR;   // y-edges
   const bool mur_x = A.bc_x == kBcMur, mur_y = A.bc_y == kBcMur;
 
   const int js = j0 > 0 ? j0 - 1 : 0;
@@ -1258,19 +1352,19 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int bx, int k, i
     // Faraday, Eq. (2)
     float hzn = 0.f;
     if (exv && j < NY) {
-      hzn = cur.hz - S * ((cur.ey1 - cur.ey) - (nxt.ex - cur.ex));
+      hzn = base_hz(cur.hz, S, cur.ey1, cur.ey, nxt.ex, cur.ex);
       if (i == A.is - 1) hzn += S * ey_src;
-      if (store && own) A.hz1[o] = hzn;
+      if (store && own && !(skc && j >= A.sB && j < A.sT)) A.hz1[o] = hzn;
     }
     const float hzl = __shfl_up(hzn, 1, 64);  // Hz(i-1, j)
 
     // Ampere + Drude, Eqs. (1), (3): x-edges
     float exn = 0.f;
-    const float kapx = kn * (0.5f * (cur.n + cur.n1));
+    const float kapx = base_kap(kn, cur.n, cur.n1);
     if (exv) {
       if (j > 0 && j < NY) {
-        exn = ((1.f - kapx) * cur.ex + S * (hzn - hzn_p) - c1 * cur.jx) * __builtin_amdgcn_rcpf(1.f + kapx);
-        if (store && own) {
+        exn = base_ex(cur.ex, kapx, S, hzn, hzn_p, c1, cur.jx);
+        if (store && own && !(skc && j > A.sB && j < A.sT)) {
           A.ex1[o] = exn;
           A.jx1[o] = a * cur.jx + 2.f * kapx * (cur.ex + exn);
         }
@@ -1288,11 +1382,11 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int bx, int k, i
     }
     // y-edges
     float eyn = 0.f;
-    const float kapy = kn * (0.5f * (cur.n + nxt.n));
+    const float kapy = base_kap(kn, cur.n, nxt.n);
     if (eyc && j < NY && i > 0 && i < NX) {
       float curl = -S * (hzn - hzl);
       if (i == A.is) curl += S * hz_src;
-      eyn = ((1.f - kapy) * cur.ey + curl - c1 * cur.jy) * __builtin_amdgcn_rcpf(1.f + kapy);
+      eyn = base_ey(cur.ey, kapy, curl, c1, cur.jy);
     }
     if (j < NY && (wave_has_left || wave_has_right)) {
       const float nr = __shfl_down(eyn, 1, 64), orr = __shfl_down(cur.ey, 1, 64);
@@ -1300,7 +1394,7 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int bx, int k, i
       if (i == 0) eyn = mur_x ? orr + cm * (nr - cur.ey) : 0.f;
       if (i == NX) eyn = mur_x ? ol + cm * (nl - cur.ey) : 0.f;
     }
-    if (eyc && j < NY && store && own) {
+    if (eyc && j < NY && store && own && !(sky && j >= A.sB && j < A.sT)) {
       A.ey1[o] = eyn;
       A.jy1[o] = a * cur.jy + 2.f * kapy * (cur.ey + eyn);
     }
@@ -1374,7 +1468,8 @@ __device__ inline int xcd_band(int L, int N) {
 template <int DEPTH>
 __global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int nseg, int nbx) {
   const int b = xcd_band(blockIdx.x, nbx * nseg);
-  em_stream_body<DEPTH>(A, b % nbx, b / nbx, seg, nseg, A.ey_src, A.hz_src);
+  em_stream_body<DEPTH>(A, (b % nbx) * (kThreads / 64) + (threadIdx.x >> 6), b / nbx, seg, nseg,
+                        A.ey_src, A.hz_src);
 }
 
 // batched form; the incident values of step k of the current interval come
@@ -1387,7 +1482,30 @@ __global__ __launch_bounds__(kThreads) void k_em_stream_batch(const EMArgs* __re
   const int2 bi = blk[blockIdx.x];
   const EMArgs& A = args[bi.x];
   const float2 sv = src[(size_t)bi.x * kSrcSteps + k];
-  em_stream_body<DEPTH>(A, bi.y % A.nbx, bi.y / A.nbx, A.seg, A.nseg, sv.x, sv.y);
+  em_stream_body<DEPTH>(A, (bi.y % A.nbx) * (kThreads / 64) + (threadIdx.x >> 6), bi.y / A.nbx,
+                        A.seg, A.nseg, sv.x, sv.y);
+}
+
+// ---------------------------------------------------------------------------
+// Combined step: the base-level EM step and both patch substeps of a coarse
+// step in one launch.  Blocks [0, ncb) are base-level waves (16 per block,
+// column-wave w % waves_x of segment w / waves_x, blocks banded over the
+// XCDs); the rest are 64 x TY patch tiles, which compute the coarse E after
+// the step on their boundary lines themselves.  The base waves do not store
+// the coarse entities the tiles' fine -> coarse transfer writes.
+// ---------------------------------------------------------------------------
+template <int DEPTH, int TY>
+__global__ __launch_bounds__(kFineThreads) void k_dmr_step(EMArgs C, EMArgs F, int seg, int nseg,
+                                                           int waves_x, int ncb, int nbx_f) {
+  const int b = blockIdx.x;
+  if (b < ncb) {
+    const int w = xcd_band(b, ncb) * (kFineThreads / 64) + (threadIdx.x >> 6);
+    const int k = w / waves_x;
+    if (k < nseg) em_stream_body<DEPTH>(C, w % waves_x, k, seg, nseg, C.ey_src, C.hz_src);
+    return;
+  }
+  const int t = b - ncb;
+  fine2_tile<TY, kFineThreads, true>(F, t % nbx_f, t / nbx_f);
 }
 
 // ---- host-side launchers ----------------------------------------------------
@@ -1415,6 +1533,25 @@ hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st) {
   case 8: DMR_LAUNCH_TILE(k_fine2, 8, nt, A, st); break;
   default: DMR_LAUNCH_TILE(k_fine2, 16, nt, A, st); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_dmr_step(const EMArgs& C, const EMArgs& F, int seg, int depth, int ty,
+                           hipStream_t st) {
+  const int waves_x = (C.R + 1 + 61) / 62;
+  const int nseg = stream_segments(C.T, seg);
+  const int wpb = kFineThreads / 64;
+  const int ncb = (waves_x * nseg + wpb - 1) / wpb;
+  const int nbx_f = (F.R - F.L + 1 + kTX - 1) / kTX;
+  const int nby_f = (F.T - F.B + 1 + ty - 1) / ty;
+  const dim3 g(ncb + nbx_f * nby_f), blk(kFineThreads);
+#define DMR_STEP(D, T_) hipLaunchKernelGGL((k_dmr_step<D, T_>), g, blk, 0, st, C, F, seg, nseg, waves_x, ncb, nbx_f)
+  if (depth >= 4) {
+    if (ty == 4) DMR_STEP(4, 4); else if (ty == 8) DMR_STEP(4, 8); else DMR_STEP(4, 16);
+  } else {
+    if (ty == 4) DMR_STEP(2, 4); else if (ty == 8) DMR_STEP(2, 8); else DMR_STEP(2, 16);
+  }
+#undef DMR_STEP
   return hipGetLastError();
 }
 
