@@ -33,120 +33,139 @@ __device__ inline size_t at(int i, int j, int p) { return (size_t)j * p + i; }
 // node has two edges along that axis, 1 where it has one
 __device__ inline float wwin(int q, int lo, int hi) { return (q > lo && q < hi) ? 0.5f : 1.f; }
 
-// ---- fine-patch E filter, forward expressions ------------------------------
-// Laplacian of an edge component at (i, j) with neighbours outside the
-// component's patch grid replaced by the centre value
-template <class OK>
-__device__ inline float lap_at(const float* e, int p, int i, int j, OK ok) {
-  const float c = e[at(i, j, p)];
-  return (ok(i - 1, j) ? e[at(i - 1, j, p)] : c) + (ok(i + 1, j) ? e[at(i + 1, j, p)] : c) +
-         (ok(i, j - 1) ? e[at(i, j - 1, p)] : c) + (ok(i, j + 1) ? e[at(i, j + 1, p)] : c) -
-         4.f * c;
+// ---- gather helpers ----------------------------------------------------------
+// Every thread first loads all the values it needs from clamped (always
+// valid) addresses, then computes; entries that do not exist are discarded
+// by selects.  (Loads under conditions would each wait for memory.)
+struct Reg {
+  int L, B, R, T, p;
+  __device__ size_t o(int a, int b) const {
+    a = a < L ? L : (a > R ? R : a);
+    b = b < B ? B : (b > T ? T : b);
+    return (size_t)b * p + a;
+  }
+  __device__ float ld(const float* q, int a, int b) const { return q[o(a, b)]; }
+  __device__ bool ex(int a, int b) const { return a >= L && a < R && b >= B && b <= T; }
+  __device__ bool ey(int a, int b) const { return a >= L && a <= R && b >= B && b < T; }
+  __device__ bool hz(int a, int b) const { return a >= L && a < R && b >= B && b < T; }
+};
+
+__device__ inline float lap5a(float c, float l, float r, float d, float u) {
+  return l + r + d + u - 4.f * c;
+}
+
+// 13-point diamond around (i, j): slot of offset (a, b), |a| + |b| <= 2
+__device__ constexpr int dmd(int a, int b) {
+  return (a == 0 && b == 0) ? 0 : (a == -1 && b == 0) ? 1 : (a == 1 && b == 0) ? 2
+       : (a == 0 && b == -1) ? 3 : (a == 0 && b == 1) ? 4 : (a == -2 && b == 0) ? 5
+       : (a == 2 && b == 0) ? 6 : (a == 0 && b == -2) ? 7 : (a == 0 && b == 2) ? 8
+       : (a == -1 && b == -1) ? 9 : (a == 1 && b == -1) ? 10 : (a == -1 && b == 1) ? 11 : 12;
 }
 
 template <class OK>
-__device__ inline float lap2_at(const float* e, int p, int i, int j, OK ok) {
-  const float c = lap_at(e, p, i, j, ok);
-  return (ok(i - 1, j) ? lap_at(e, p, i - 1, j, ok) : c) +
-         (ok(i + 1, j) ? lap_at(e, p, i + 1, j, ok) : c) +
-         (ok(i, j - 1) ? lap_at(e, p, i, j - 1, ok) : c) +
-         (ok(i, j + 1) ? lap_at(e, p, i, j + 1, ok) : c) - 4.f * c;
+__device__ inline void load13(const Reg& g, const float* q, int i, int j, float v[13]) {
+#pragma unroll
+  for (int b = -2; b <= 2; b++)
+#pragma unroll
+    for (int a = -2; a <= 2; a++)
+      if ((a < 0 ? -a : a) + (b < 0 ? -b : b) <= 2) v[dmd(a, b)] = g.ld(q, i + a, j + b);
 }
 
-// Laplacian of the masked field m(i,j) = filtered(i,j) ? t(i,j) : 0
-template <class OK, class MASK>
-__device__ inline float lapm_at(const float* t, int p, int i, int j, OK ok, MASK msk) {
-  auto v = [&](int a, int b) { return msk(a, b) ? t[at(a, b, p)] : 0.f; };
-  const float c = v(i, j);
-  return (ok(i - 1, j) ? v(i - 1, j) : c) + (ok(i + 1, j) ? v(i + 1, j) : c) +
-         (ok(i, j - 1) ? v(i, j - 1) : c) + (ok(i, j + 1) ? v(i, j + 1) : c) - 4.f * c;
-}
-
-template <class OK, class MASK>
-__device__ inline float lap2m_at(const float* t, int p, int i, int j, OK ok, MASK msk) {
-  const float c = lapm_at(t, p, i, j, ok, msk);
-  return (ok(i - 1, j) ? lapm_at(t, p, i - 1, j, ok, msk) : c) +
-         (ok(i + 1, j) ? lapm_at(t, p, i + 1, j, ok, msk) : c) +
-         (ok(i, j - 1) ? lapm_at(t, p, i, j - 1, ok, msk) : c) +
-         (ok(i, j + 1) ? lapm_at(t, p, i, j + 1, ok, msk) : c) - 4.f * c;
+// L(L(v)) at (i, j) from the diamond, neighbours outside the component's
+// grid replaced by the centre value (the forward filter's rule)
+template <class OK>
+__device__ inline float ll13(const float v[13], int i, int j, OK ok) {
+  auto lapP = [&](int a, int b) {
+    const float c = v[dmd(a, b)];
+    return lap5a(c, ok(i + a - 1, j + b) ? v[dmd(a - 1, b)] : c,
+                 ok(i + a + 1, j + b) ? v[dmd(a + 1, b)] : c,
+                 ok(i + a, j + b - 1) ? v[dmd(a, b - 1)] : c,
+                 ok(i + a, j + b + 1) ? v[dmd(a, b + 1)] : c);
+  };
+  const float c = lapP(0, 0);
+  return lap5a(c, ok(i - 1, j) ? lapP(-1, 0) : c, ok(i + 1, j) ? lapP(1, 0) : c,
+               ok(i, j - 1) ? lapP(0, -1) : c, ok(i, j + 1) ? lapP(0, 1) : c);
 }
 
 // ---------------------------------------------------------------------------
 // EM adjoint, pass 1 (edges): G / g, lam k per edge.  gx/gy hold g on
 // interior edges and, on boundary edges, G (Mur: feeds the interior
 // neighbour and the old values; patch: lam of the coarse-driven value).
+// FINE: the patch (E filter, no outer boundary); else the base level.
 // ---------------------------------------------------------------------------
+template <bool FINE>
 __global__ __launch_bounds__(kThreads) void k_adj_em_a(AdjEMArgs A) {
   const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
   const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
   if (i > A.R || j > A.T) return;
-  const int L = A.L, R = A.R, B = A.B, T = A.T, p = A.pitch;
-  auto ex_ok = [&](int a, int b) { return a >= L && a < R && b >= B && b <= T; };
-  auto ey_ok = [&](int a, int b) { return a >= L && a <= R && b >= B && b < T; };
-  const bool filt = A.fine && A.gamma > 0.f;
-
-  // total lam of a new x-edge value through the window (and its own lam)
-  auto ax = [&](int a, int b) {
-    const size_t o = at(a, b, p);
-    const float e = A.exo[o];
-    return A.lex[o] + 2.f * e * (wwin(a, L, R) * A.lacc[o] + wwin(a + 1, L, R) * A.lacc[o + 1]);
-  };
-  auto ay = [&](int a, int b) {
-    const size_t o = at(a, b, p);
-    const float e = A.eyo[o];
-    return A.ley[o] + 2.f * e * (wwin(b, B, T) * A.lacc[o] + wwin(b + 1, B, T) * A.lacc[o + p]);
-  };
-  auto kapx = [&](int a, int b) {
-    const size_t o = at(a, b, p);
-    return A.kn * (0.5f * (A.n[o] + A.n[o + 1]));
-  };
-  auto kapy = [&](int a, int b) {
-    const size_t o = at(a, b, p);
-    return A.kn * (0.5f * (A.n[o] + A.n[o + p]));
-  };
-
+  const Reg g{A.L, A.B, A.R, A.T, A.pitch};
+  const int L = A.L, R = A.R, B = A.B, T = A.T;
+  auto ex_ok = [=](int a, int b) { return g.ex(a, b); };
+  auto ey_ok = [=](int a, int b) { return g.ey(a, b); };
+  // Mur partners (own edge where there is none: a cache hit, never used)
+  const int jb = (j == B + 1) ? B : (j == T - 1 ? T : j);
+  const int ib = (i == L + 1) ? L : (i == R - 1 ? R : i);
+  // -- loads --
+  const float xle = g.ld(A.lex, i, j), xen = g.ld(A.exo, i, j), xeo = g.ld(A.exi, i, j);
+  const float xa0 = g.ld(A.lacc, i, j), xa1 = g.ld(A.lacc, i + 1, j);
+  const float n00 = g.ld(A.n, i, j), n10 = g.ld(A.n, i + 1, j), n01 = g.ld(A.n, i, j + 1);
+  const float xlj = g.ld(A.ljx, i, j);
+  const float yle = g.ld(A.ley, i, j), yen = g.ld(A.eyo, i, j), yeo = g.ld(A.eyi, i, j);
+  const float ya1 = g.ld(A.lacc, i, j + 1), ylj = g.ld(A.ljy, i, j);
+  float mx[7] = {0, 0, 0, 0, 0, 0, 0}, my[7] = {0, 0, 0, 0, 0, 0, 0};
+  float dx[13], dy[13];
+  if constexpr (!FINE) {
+    mx[0] = g.ld(A.lex, i, jb); mx[1] = g.ld(A.exo, i, jb); mx[2] = g.ld(A.lacc, i, jb);
+    mx[3] = g.ld(A.lacc, i + 1, jb); mx[4] = g.ld(A.n, i, jb); mx[5] = g.ld(A.n, i + 1, jb);
+    mx[6] = g.ld(A.ljx, i, jb);
+    my[0] = g.ld(A.ley, ib, j); my[1] = g.ld(A.eyo, ib, j); my[2] = g.ld(A.lacc, ib, j);
+    my[3] = g.ld(A.lacc, ib, j + 1); my[4] = g.ld(A.n, ib, j); my[5] = g.ld(A.n, ib, j + 1);
+    my[6] = g.ld(A.ljy, ib, j);
+  } else {
+    load13<decltype(ex_ok)>(g, A.exi, i, j, dx);
+    load13<decltype(ey_ok)>(g, A.eyi, i, j, dy);
+  }
+  // -- compute --
+  auto kapf = [&](float a, float b) { return A.kn * (0.5f * (a + b)); };
   if (ex_ok(i, j)) {
-    const size_t o = at(i, j, p);
-    const float kap = kapx(i, j);
-    const float lj = A.ljx[o];
-    const float en = A.exo[o];
-    float eo = A.exi[o];
+    const size_t o = g.o(i, j);
+    const float kap = kapf(n00, n10);
     const bool bnd = (j == B || j == T);
-    if (filt && !bnd) eo -= A.gamma * lap2_at(A.exi, p, i, j, ex_ok);
-    float tot = ax(i, j);
+    float eo = xeo;
+    if (FINE && A.gamma > 0.f && !bnd) eo -= A.gamma * ll13(dx, i, j, ex_ok);
+    // own lam plus the window: acc at both end nodes (1/2 where a node has two x-edges)
+    float tot = xle + 2.f * xen * (wwin(i, L, R) * xa0 + wwin(i + 1, L, R) * xa1);
     if (!bnd) {
-      if (!A.fine && A.bc_y == kBcMur && (j == B + 1 || j == T - 1)) {
-        const int b = (j == B + 1) ? B : T;
-        tot += A.cmur * (ax(i, b) + 2.f * kapx(i, b) * A.ljx[at(i, b, p)]);
+      if (!FINE && A.bc_y == kBcMur && (j == B + 1 || j == T - 1)) {
+        const float ab = mx[0] + 2.f * mx[1] * (wwin(i, L, R) * mx[2] + wwin(i + 1, L, R) * mx[3]);
+        tot += A.cmur * (ab + 2.f * kapf(mx[4], mx[5]) * mx[6]);
       }
-      const float g = (tot + 2.f * kap * lj) / (1.f + kap);
-      A.gx[o] = g;
-      A.kx[o] = (eo + en) * (2.f * lj - g);
+      const float gg = (tot + 2.f * kap * xlj) / (1.f + kap);
+      A.gx[o] = gg;
+      A.kx[o] = (eo + xen) * (2.f * xlj - gg);
     } else {
-      A.gx[o] = tot + 2.f * kap * lj;
-      A.kx[o] = 2.f * (eo + en) * lj;
+      A.gx[o] = tot + 2.f * kap * xlj;
+      A.kx[o] = 2.f * (eo + xen) * xlj;
     }
   }
   if (ey_ok(i, j)) {
-    const size_t o = at(i, j, p);
-    const float kap = kapy(i, j);
-    const float lj = A.ljy[o];
-    const float en = A.eyo[o];
-    float eo = A.eyi[o];
+    const size_t o = g.o(i, j);
+    const float kap = kapf(n00, n01);
     const bool bnd = (i == L || i == R);
-    if (filt && !bnd) eo -= A.gamma * lap2_at(A.eyi, p, i, j, ey_ok);
-    float tot = ay(i, j);
+    float eo = yeo;
+    if (FINE && A.gamma > 0.f && !bnd) eo -= A.gamma * ll13(dy, i, j, ey_ok);
+    float tot = yle + 2.f * yen * (wwin(j, B, T) * xa0 + wwin(j + 1, B, T) * ya1);
     if (!bnd) {
-      if (!A.fine && A.bc_x == kBcMur && (i == L + 1 || i == R - 1)) {
-        const int a = (i == L + 1) ? L : R;
-        tot += A.cmur * (ay(a, j) + 2.f * kapy(a, j) * A.ljy[at(a, j, p)]);
+      if (!FINE && A.bc_x == kBcMur && (i == L + 1 || i == R - 1)) {
+        const float ab = my[0] + 2.f * my[1] * (wwin(j, B, T) * my[2] + wwin(j + 1, B, T) * my[3]);
+        tot += A.cmur * (ab + 2.f * kapf(my[4], my[5]) * my[6]);
       }
-      const float g = (tot + 2.f * kap * lj) / (1.f + kap);
-      A.gy[o] = g;
-      A.ky[o] = (eo + en) * (2.f * lj - g);
+      const float gg = (tot + 2.f * kap * ylj) / (1.f + kap);
+      A.gy[o] = gg;
+      A.ky[o] = (eo + yen) * (2.f * ylj - gg);
     } else {
-      A.gy[o] = tot + 2.f * kap * lj;
-      A.ky[o] = 2.f * (eo + en) * lj;
+      A.gy[o] = tot + 2.f * kap * ylj;
+      A.ky[o] = 2.f * (eo + yen) * ylj;
     }
   }
 }
@@ -155,96 +174,100 @@ __global__ __launch_bounds__(kThreads) void k_adj_em_a(AdjEMArgs A) {
 // EM adjoint, pass 2 (cells, edges, nodes): lam H entering the step, lam E
 // and lam J entering it, lam n, and the source-column sensitivities.
 // ---------------------------------------------------------------------------
+template <bool FINE>
 __global__ __launch_bounds__(kThreads) void k_adj_em_bc(AdjEMArgs A) {
   const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
   const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
   if (i > A.R || j > A.T) return;
-  const int L = A.L, R = A.R, B = A.B, T = A.T, p = A.pitch;
-  auto hz_ok = [&](int a, int b) { return a >= L && a < R && b >= B && b < T; };
-  auto ex_ok = [&](int a, int b) { return a >= L && a < R && b >= B && b <= T; };
-  auto ey_ok = [&](int a, int b) { return a >= L && a <= R && b >= B && b < T; };
+  const Reg g{A.L, A.B, A.R, A.T, A.pitch};
+  const int L = A.L, R = A.R, B = A.B, T = A.T;
   const float S = A.S;
-  // g of interior edges (boundary E' does not depend on H')
-  auto gxi = [&](int a, int b) { return (b == B || b == T) ? 0.f : A.gx[at(a, b, p)]; };
-  auto gyi = [&](int a, int b) { return (a == L || a == R) ? 0.f : A.gy[at(a, b, p)]; };
-  // lam of H' at a cell: its own plus the curl terms of the four edges
-  auto hcell = [&](int a, int b) {
-    return A.lhz_in[at(a, b, p)] + S * (gxi(a, b) - gxi(a, b + 1)) +
-           S * (gyi(a + 1, b) - gyi(a, b));
-  };
-  const size_t o = at(i, j, p);
-  const bool filt = A.fine && A.gamma > 0.f;
-
-  if (hz_ok(i, j)) {
-    const float h = hcell(i, j);
-    if (A.src_e && i == A.is - 1) A.src_e[j] = S * h;
-    float v = h;
-    if (A.hz_extra) {
-      v += A.hz_extra[o];
-      A.hz_extra[o] = 0.f;
-    }
-    A.lhz_out[o] = v;
+  const bool filt = FINE && A.gamma > 0.f;
+  // -- loads --
+  const float h00 = g.ld(A.lhz_in, i, j), h0m = g.ld(A.lhz_in, i, j - 1), hm0 = g.ld(A.lhz_in, i - 1, j);
+  const float gx00 = g.ld(A.gx, i, j), gx01 = g.ld(A.gx, i, j + 1), gx0m = g.ld(A.gx, i, j - 1);
+  const float gxm0 = g.ld(A.gx, i - 1, j), gxm1 = g.ld(A.gx, i - 1, j + 1);
+  const float gy10 = g.ld(A.gy, i + 1, j), gy00 = g.ld(A.gy, i, j), gy1m = g.ld(A.gy, i + 1, j - 1);
+  const float gy0m = g.ld(A.gy, i, j - 1), gym0 = g.ld(A.gy, i - 1, j);
+  const float n00 = g.ld(A.n, i, j), n10 = g.ld(A.n, i + 1, j), n01 = g.ld(A.n, i, j + 1);
+  const float ljx = g.ld(A.ljx, i, j), ljy = g.ld(A.ljy, i, j);
+  const float kxm = g.ld(A.kx, i - 1, j), kx0 = g.ld(A.kx, i, j);
+  const float kym = g.ld(A.ky, i, j - 1), ky0 = g.ld(A.ky, i, j), ln0 = g.ld(A.ln, i, j);
+  float gxB = 0.f, gxT = 0.f, gyL = 0.f, gyR = 0.f;
+  if constexpr (!FINE) {
+    gxB = g.ld(A.gx, i, B); gxT = g.ld(A.gx, i, T); gyL = g.ld(A.gy, L, j); gyR = g.ld(A.gy, R, j);
   }
-  if (ex_ok(i, j)) {
-    const float kap = A.kn * (0.5f * (A.n[o] + A.n[o + 1]));
-    const float lj = A.ljx[o];
-    float le = (hz_ok(i, j - 1) ? S * hcell(i, j - 1) : 0.f) - (hz_ok(i, j) ? S * hcell(i, j) : 0.f);
+  // optional additions (pointers fixed per launch)
+  const float hxv = A.hz_extra ? g.ld(A.hz_extra, i, j) : 0.f;
+  const float pxv = A.pex ? g.ld(A.pex, i, j) : 0.f;
+  const float pyv = A.pey ? g.ld(A.pey, i, j) : 0.f;
+  // -- compute --
+  // g of interior edges (boundary E' does not depend on H')
+  auto xi = [&](float v, int b) { return (b == B || b == T) ? 0.f : v; };
+  auto yi = [&](float v, int a) { return (a == L || a == R) ? 0.f : v; };
+  // lam of H' at a cell: its own plus the curl terms of the four edges
+  const float hc00 = h00 + S * (xi(gx00, j) - xi(gx01, j + 1)) + S * (yi(gy10, i + 1) - yi(gy00, i));
+  const float hc0m = h0m + S * (xi(gx0m, j - 1) - xi(gx00, j)) + S * (yi(gy1m, i + 1) - yi(gy0m, i));
+  const float hcm0 = hm0 + S * (xi(gxm0, j) - xi(gxm1, j + 1)) + S * (yi(gy00, i) - yi(gym0, i - 1));
+  const size_t o = g.o(i, j);
+
+  if (g.hz(i, j)) {
+    if (A.src_e && i == A.is - 1) A.src_e[j] = S * hc00;
+    A.lhz_out[o] = hc00 + hxv;
+    if (A.hz_extra) A.hz_extra[o] = 0.f;
+  }
+  if (g.ex(i, j)) {
+    const float kap = A.kn * (0.5f * (n00 + n10));
+    float le = (g.hz(i, j - 1) ? S * hc0m : 0.f) - (g.hz(i, j) ? S * hc00 : 0.f);
     const bool bnd = (j == B || j == T);
     float ljn;
     if (!bnd) {
-      const float g = A.gx[o];
-      le += (1.f - kap) * g + 2.f * kap * lj;
-      ljn = A.a * lj - A.c1 * g;
-      if (!A.fine && A.bc_y == kBcMur) {
-        if (j == B + 1) le += A.gx[at(i, B, p)];
-        if (j == T - 1) le += A.gx[at(i, T, p)];
+      le += (1.f - kap) * gx00 + 2.f * kap * ljx;
+      ljn = A.a * ljx - A.c1 * gx00;
+      if (!FINE && A.bc_y == kBcMur) {
+        if (j == B + 1) le += gxB;
+        if (j == T - 1) le += gxT;
       }
     } else {
-      le += 2.f * kap * lj;
-      if (!A.fine && A.bc_y == kBcMur) le -= A.cmur * A.gx[o];
-      ljn = A.a * lj;
+      le += 2.f * kap * ljx;
+      if (!FINE && A.bc_y == kBcMur) le -= A.cmur * gx00;
+      ljn = A.a * ljx;
     }
-    if (A.pex) {
-      le += A.pex[o];
-      A.pex[o] = 0.f;
-    }
+    le += pxv;
+    if (A.pex) A.pex[o] = 0.f;
     if (filt) A.tex[o] = le; else A.lex[o] = le;
     A.ljx[o] = ljn;
   }
-  if (ey_ok(i, j)) {
-    const float kap = A.kn * (0.5f * (A.n[o] + A.n[o + p]));
-    const float lj = A.ljy[o];
-    float le = (hz_ok(i, j) ? S * hcell(i, j) : 0.f) - (hz_ok(i - 1, j) ? S * hcell(i - 1, j) : 0.f);
+  if (g.ey(i, j)) {
+    const float kap = A.kn * (0.5f * (n00 + n01));
+    float le = (g.hz(i, j) ? S * hc00 : 0.f) - (g.hz(i - 1, j) ? S * hcm0 : 0.f);
     const bool bnd = (i == L || i == R);
     float ljn;
     if (!bnd) {
-      const float g = A.gy[o];
-      if (A.src_h && i == A.is) A.src_h[j] = S * g;
-      le += (1.f - kap) * g + 2.f * kap * lj;
-      ljn = A.a * lj - A.c1 * g;
-      if (!A.fine && A.bc_x == kBcMur) {
-        if (i == L + 1) le += A.gy[at(L, j, p)];
-        if (i == R - 1) le += A.gy[at(R, j, p)];
+      if (A.src_h && i == A.is) A.src_h[j] = S * gy00;
+      le += (1.f - kap) * gy00 + 2.f * kap * ljy;
+      ljn = A.a * ljy - A.c1 * gy00;
+      if (!FINE && A.bc_x == kBcMur) {
+        if (i == L + 1) le += gyL;
+        if (i == R - 1) le += gyR;
       }
     } else {
-      le += 2.f * kap * lj;
-      if (!A.fine && A.bc_x == kBcMur) le -= A.cmur * A.gy[o];
-      ljn = A.a * lj;
+      le += 2.f * kap * ljy;
+      if (!FINE && A.bc_x == kBcMur) le -= A.cmur * gy00;
+      ljn = A.a * ljy;
     }
-    if (A.pey) {
-      le += A.pey[o];
-      A.pey[o] = 0.f;
-    }
+    le += pyv;
+    if (A.pey) A.pey[o] = 0.f;
     if (filt) A.tey[o] = le; else A.ley[o] = le;
     A.ljy[o] = ljn;
   }
   // node: k of the (up to four) edges that average this node's density
   float s = 0.f;
-  if (ex_ok(i - 1, j)) s += A.kx[o - 1];
-  if (ex_ok(i, j)) s += A.kx[o];
-  if (ey_ok(i, j - 1)) s += A.ky[o - p];
-  if (ey_ok(i, j)) s += A.ky[o];
-  A.ln[o] += 0.5f * A.kn * s;
+  if (g.ex(i - 1, j)) s += kxm;
+  if (g.ex(i, j)) s += kx0;
+  if (g.ey(i, j - 1)) s += kym;
+  if (g.ey(i, j)) s += ky0;
+  A.ln[o] = ln0 + 0.5f * A.kn * s;
 }
 
 // ---------------------------------------------------------------------------
@@ -255,14 +278,27 @@ __global__ __launch_bounds__(kThreads) void k_adj_filter(AdjEMArgs A) {
   const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
   const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
   if (i > A.R || j > A.T) return;
-  const int L = A.L, R = A.R, B = A.B, T = A.T, p = A.pitch;
-  auto ex_ok = [&](int a, int b) { return a >= L && a < R && b >= B && b <= T; };
-  auto ey_ok = [&](int a, int b) { return a >= L && a <= R && b >= B && b < T; };
-  auto fx = [&](int a, int b) { return b != B && b != T; };
-  auto fy = [&](int a, int b) { return a != L && a != R; };
-  const size_t o = at(i, j, p);
-  if (ex_ok(i, j)) A.lex[o] = A.tex[o] - A.gamma * lap2m_at(A.tex, p, i, j, ex_ok, fx);
-  if (ey_ok(i, j)) A.ley[o] = A.tey[o] - A.gamma * lap2m_at(A.tey, p, i, j, ey_ok, fy);
+  const Reg g{A.L, A.B, A.R, A.T, A.pitch};
+  const int L = A.L, R = A.R, B = A.B, T = A.T;
+  auto ex_ok = [=](int a, int b) { return g.ex(a, b); };
+  auto ey_ok = [=](int a, int b) { return g.ey(a, b); };
+  float tx[13], ty[13];
+  load13<decltype(ex_ok)>(g, A.tex, i, j, tx);
+  load13<decltype(ey_ok)>(g, A.tey, i, j, ty);
+  // masked: only filtered edges (not the patch boundary ones) carry lam
+#pragma unroll
+  for (int b = -2; b <= 2; b++)
+#pragma unroll
+    for (int a = -2; a <= 2; a++)
+      if ((a < 0 ? -a : a) + (b < 0 ? -b : b) <= 2) {
+        const int k = dmd(a, b);
+        const int jj = j + b, ii = i + a;
+        if (jj == B || jj == T) tx[k] = 0.f;
+        if (ii == L || ii == R) ty[k] = 0.f;
+      }
+  const size_t o = g.o(i, j);
+  if (g.ex(i, j)) A.lex[o] = A.tex[o] - A.gamma * ll13(tx, i, j, ex_ok);
+  if (g.ey(i, j)) A.ley[o] = A.tey[o] - A.gamma * ll13(ty, i, j, ey_ok);
 }
 
 // ---------------------------------------------------------------------------
@@ -692,9 +728,14 @@ dim3 node_grid(int L, int B, int R, int T) {
 
 hipError_t launch_adj_em(const AdjEMArgs& A, hipStream_t st) {
   const dim3 g = node_grid(A.L, A.B, A.R, A.T);
-  k_adj_em_a<<<g, kThreads, 0, st>>>(A);
-  k_adj_em_bc<<<g, kThreads, 0, st>>>(A);
-  if (A.fine && A.gamma > 0.f) k_adj_filter<<<g, kThreads, 0, st>>>(A);
+  if (A.fine) {
+    k_adj_em_a<true><<<g, kThreads, 0, st>>>(A);
+    k_adj_em_bc<true><<<g, kThreads, 0, st>>>(A);
+    if (A.gamma > 0.f) k_adj_filter<<<g, kThreads, 0, st>>>(A);
+  } else {
+    k_adj_em_a<false><<<g, kThreads, 0, st>>>(A);
+    k_adj_em_bc<false><<<g, kThreads, 0, st>>>(A);
+  }
   return hipGetLastError();
 }
 

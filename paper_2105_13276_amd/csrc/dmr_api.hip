@@ -133,6 +133,8 @@ struct StepMeta {
 };
 struct StepCtx {
   bool store = false;  // copy the step's forward values into ss
+  bool last = false;   // last step of its segment (E after substep 2 is stored;
+                       // otherwise it is the next step's stored E entering)
   StepStore ss{};
   bool forced = false;  // replay: apply force_ext instead of the growth test
   bool force_grow = false;
@@ -191,6 +193,8 @@ struct dmr_sim {
   bool had0 = false, keep_n0 = false;
   int ext0[4] = {0, 0, 0, 0};
   AdjTape tape;
+  hipStream_t rep_st = nullptr;  // the adjoint's replay stream (default priority)
+  hipEvent_t ev_rep[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr}, ev_sync = nullptr;
   // timing
   bool timing = false;
   struct Ev { int cls; hipEvent_t a, b; };
@@ -586,7 +590,7 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
     ev_end(s);
     if (e != hipSuccess) return hipfail(s, e, "base EM launch");
   }
-  if (st) {
+  if (st && !s->has_patch) {  // with a patch: stored after substep 1
     CopyJobs J{};
     job(&J, s->L0.ex[1 - c], cx->ss.cexp, s->L0.plane);
     job(&J, s->L0.ey[1 - c], cx->ss.ceyp, s->L0.plane);
@@ -618,10 +622,14 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
       e = launch_em(G, true, s->ty1, s->nt1, s->st);
       ev_end(s);
       if (e != hipSuccess) return hipfail(s, e, "fine EM launch");
-      if (st) {
+      if (st && (m == 1 || cx->last)) {
         CopyJobs J{};
         job_rows(&J, s, s->L1.ex[m & 1], m == 1 ? cx->ss.fex1 : cx->ss.fex2);
         job_rows(&J, s, s->L1.ey[m & 1], m == 1 ? cx->ss.fey1 : cx->ss.fey2);
+        if (m == 1) {  // the coarse E after the coarse step (the transfer comes in substep 2)
+          job(&J, s->L0.ex[1 - c], cx->ss.cexp, s->L0.plane);
+          job(&J, s->L0.ey[1 - c], cx->ss.ceyp, s->L0.plane);
+        }
         if (int rc = run_copies(s, J)) return rc;
       }
     }
@@ -838,6 +846,15 @@ int dmr_create(const dmr_params* p, const double* seed_base,
 void dmr_destroy(dmr_sim* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->st);
+  if (s->rep_st) {
+    (void)hipStreamSynchronize(s->rep_st);
+    (void)hipStreamDestroy(s->rep_st);
+    for (int b = 0; b < 2; b++) {
+      (void)hipEventDestroy(s->ev_rep[b]);
+      (void)hipEventDestroy(s->ev_adj[b]);
+    }
+    (void)hipEventDestroy(s->ev_sync);
+  }
   for (auto& e : s->evs) {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
@@ -1039,7 +1056,7 @@ TapeLayout tape_layout(const dmr_params* p, int64_t steps, int every) {
   T.ck_size = align256((L.plane0 * kCkC + L.plane1 * kCkF) * f);
   T.ck = off; off += T.ck_size * (size_t)(T.nck + 1);
   T.st_size = align256((L.plane0 * kStC + L.plane1 * kStF) * f);
-  T.store = off; off += T.st_size * (size_t)every;
+  T.store = off; off += T.st_size * (size_t)every * 2;  // two banks: replay / reverse overlap
   T.src_size = align256((size_t)2 * p->ny * f);
   T.src = off; off += T.src_size * (size_t)every;
   T.u = off; off += align256((size_t)2 * steps * sizeof(double));
@@ -1074,8 +1091,8 @@ AdjLevel adj_carve(char* base, size_t plane) {
   return a;
 }
 
-StepStore store_slot(const dmr_sim* s, const TapeLayout& T, int k) {
-  float* b = (float*)(s->tape.base + T.store + T.st_size * (size_t)k);
+StepStore store_slot(const dmr_sim* s, const TapeLayout& T, int k, int bank) {
+  float* b = (float*)(s->tape.base + T.store + T.st_size * ((size_t)bank * s->tape.every + k));
   const size_t p0 = s->L0.plane, p1 = s->L1.plane;
   StepStore ss;
   ss.cexi = b; ss.ceyi = b + p0; ss.cexp = b + 2 * p0; ss.ceyp = b + 3 * p0;
@@ -1199,7 +1216,7 @@ AdjGrowArgs adj_grow_args(const dmr_sim* s, AdjLevel& ac, AdjLevel& af, bool had
 
 // adjoint of base step k (meta: what the replay did; ss: its stored values)
 int adj_step(dmr_sim* s, const TapeLayout& T, AdjLevel& ac, AdjLevel& af, int kk,
-             const StepMeta& m, const StepStore& ss, size_t* npart) {
+             const StepMeta& m, const StepStore& ss, const StepStore* nxt, size_t* npart) {
   const dmr_params& p = s->p;
   const Level &C = s->L0, &F = s->L1;
   const int r = p.r;
@@ -1254,8 +1271,10 @@ int adj_step(dmr_sim* s, const TapeLayout& T, AdjLevel& ac, AdjLevel& af, int kk
       AdjEMArgs A = adj_em_args(s, F, af, true, freg);
       A.exi = sub == 2 ? ss.fex1 : ss.fex0;
       A.eyi = sub == 2 ? ss.fey1 : ss.fey0;
-      A.exo = sub == 2 ? ss.fex2 : ss.fex1;
-      A.eyo = sub == 2 ? ss.fey2 : ss.fey1;
+      // E after substep 2 = the next step's stored E entering (the last
+      // step of a segment stores it itself)
+      A.exo = sub == 2 ? (nxt ? nxt->fex0 : ss.fex2) : ss.fex1;
+      A.eyo = sub == 2 ? (nxt ? nxt->fey0 : ss.fey2) : ss.fey1;
       A.n = ss.fn;
       A.hz_extra = sub == 2 ? af.hx : nullptr;
       e = launch_adj_em(A, s->st);
@@ -1368,28 +1387,55 @@ int dmr_backward(dmr_sim* s, const void* d_tape, const float* d_w_coarse,
                              hipMemcpyHostToDevice, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
   }
+  // Reverse sweep, segments from the last: segment s is replayed on a
+  // private stream into store bank s % 2 while the reverse kernels of
+  // segment s + 1 run on the caller's stream from the other bank.
+  hipStream_t user = s->st;
+  if (!s->rep_st) {
+    HIPCHK(s, hipStreamCreateWithFlags(&s->rep_st, hipStreamNonBlocking));
+    for (int b = 0; b < 2; b++) {
+      HIPCHK(s, hipEventCreateWithFlags(&s->ev_rep[b], hipEventDisableTiming));
+      HIPCHK(s, hipEventCreateWithFlags(&s->ev_adj[b], hipEventDisableTiming));
+    }
+    HIPCHK(s, hipEventCreateWithFlags(&s->ev_sync, hipEventDisableTiming));
+  }
+  hipStream_t rep = s->rep_st;
+  HIPCHK(s, hipEventRecord(s->ev_sync, user));
+  HIPCHK(s, hipStreamWaitEvent(rep, s->ev_sync, 0));
   std::vector<StepMeta> meta((size_t)tp.every);
   for (int seg = tp.nck - 1; seg >= 0; seg--) {
+    const int bank = seg & 1;
     const int64_t k0 = (int64_t)seg * tp.every;
     const int64_t k1 = std::min(tp.steps, k0 + tp.every);
-    if (int rc = ck_restore(s, T, seg, tp.ck[seg])) return rc;
-    for (int64_t k = k0; k < k1; k++) {
+    // replay into this bank once the reverse sweep that read it is done
+    if (seg + 2 <= tp.nck - 1) HIPCHK(s, hipStreamWaitEvent(rep, s->ev_adj[bank], 0));
+    s->st = rep;
+    int rc = ck_restore(s, T, seg, tp.ck[seg]);
+    for (int64_t k = k0; k < k1 && !rc; k++) {
       StepCtx cx;
       cx.store = true;
-      cx.ss = store_slot(s, T, (int)(k - k0));
+      cx.last = k == k1 - 1;
+      cx.ss = store_slot(s, T, (int)(k - k0), bank);
       cx.forced = true;
       for (const Growth& g : tp.grow)
         if (g.after == k + 1) {
           cx.force_grow = true;
           for (int q = 0; q < 4; q++) cx.force_ext[q] = g.ext[q];
         }
-      if (int rc = base_step(s, &cx)) return rc;
+      rc = base_step(s, &cx);
       meta[(size_t)(k - k0)] = cx.meta;
     }
+    s->st = user;
+    if (rc) return rc;
+    HIPCHK(s, hipEventRecord(s->ev_rep[bank], rep));
+    HIPCHK(s, hipStreamWaitEvent(user, s->ev_rep[bank], 0));
     size_t npart = 0;
     for (int64_t k = k1 - 1; k >= k0; k--) {
       const int kk = (int)(k - k0);
-      if (int rc = adj_step(s, T, ac, af, kk, meta[kk], store_slot(s, T, kk), &npart)) return rc;
+      const StepStore ss = store_slot(s, T, kk, bank);
+      const StepStore nx = store_slot(s, T, kk + 1, bank);
+      if (int rc2 = adj_step(s, T, ac, af, kk, meta[kk], ss, k == k1 - 1 ? nullptr : &nx, &npart))
+        return rc2;
     }
     e = launch_adj_reduce((const float*)(tp.base + T.src), (int)(k1 - k0),
                           (int)(T.src_size / sizeof(float)), p.ny,
@@ -1397,7 +1443,11 @@ int dmr_backward(dmr_sim* s, const void* d_tape, const float* d_w_coarse,
                           (const double*)(tp.base + T.part), (int)npart,
                           (double*)(tp.base + T.gsum), s->st);
     if (e != hipSuccess) return hipfail(s, e, "adjoint reduction launch");
+    HIPCHK(s, hipEventRecord(s->ev_adj[bank], user));
   }
+  // the replay stream's work (the live state) precedes the final restore
+  HIPCHK(s, hipEventRecord(s->ev_sync, rep));
+  HIPCHK(s, hipStreamWaitEvent(user, s->ev_sync, 0));
   // t = 0: the patch seeded from the coarse density (Eq. (5a))
   if (ref && s->had0) {
     const AdjGrowArgs G = adj_grow_args(s, ac, af, false, s->ext0, s->ext0, !s->keep_n0);
