@@ -88,17 +88,27 @@ __device__ inline float ll13(const float v[13], int i, int j, OK ok) {
 }
 
 // ---------------------------------------------------------------------------
-// EM adjoint, pass 1 (edges): G / g, lam k per edge.  gx/gy hold g on
-// interior edges and, on boundary edges, G (Mur: feeds the interior
-// neighbour and the old values; patch: lam of the coarse-driven value).
-// FINE: the patch (E filter, no outer boundary); else the base level.
+// EM adjoint of one (sub)step of a level, one launch per (sub)step.  A block
+// owns a kAdjTX x kAdjTY tile of node positions (i, j) (cell (i, j), x-edge
+// (i, j), y-edge (i, j), node (i, j)) and runs three phases through LDS:
+//   1. per edge over the tile grown by H1: G, g = G/(1+k) and lam k
+//      (boundary edges keep G: Mur feeds the interior neighbour and the old
+//      values; on the patch it is the lam of the coarse-driven value);
+//   2. per position over the tile grown by H2: lam of H' at the cells, lam E
+//      and lam J entering, lam n at the nodes, source-column sums;
+//   3. (patch) the E filter transposed: E~ = E - gamma P L(L(E)) with P the
+//      filtered edges and L symmetric, so lam E = lam E~ - gamma L(L(P lam E~)).
+// Halo values are recomputed, never exchanged; lam E and lam J are read
+// from one buffer and written to another, so no block reads what another
+// block writes in the same launch.
 // ---------------------------------------------------------------------------
+constexpr int kAdjTX = 32, kAdjTY = 16, kAdjNT = 512;
+
+// phase 1 at position (i, j): g and lam k of x-edge (i, j) and y-edge (i, j)
+// (zero where the edge does not exist)
 template <bool FINE>
-__global__ __launch_bounds__(kThreads) void k_adj_em_a(AdjEMArgs A) {
-  const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
-  const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
-  if (i > A.R || j > A.T) return;
-  const Reg g{A.L, A.B, A.R, A.T, A.pitch};
+__device__ inline void adj_p1(const AdjEMArgs& A, const Reg& g, int i, int j, float& gx,
+                              float& kx, float& gy, float& ky) {
   const int L = A.L, R = A.R, B = A.B, T = A.T;
   auto ex_ok = [=](int a, int b) { return g.ex(a, b); };
   auto ey_ok = [=](int a, int b) { return g.ey(a, b); };
@@ -127,8 +137,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_em_a(AdjEMArgs A) {
   }
   // -- compute --
   auto kapf = [&](float a, float b) { return A.kn * (0.5f * (a + b)); };
+  gx = 0.f; kx = 0.f; gy = 0.f; ky = 0.f;
   if (ex_ok(i, j)) {
-    const size_t o = g.o(i, j);
     const float kap = kapf(n00, n10);
     const bool bnd = (j == B || j == T);
     float eo = xeo;
@@ -140,16 +150,14 @@ __global__ __launch_bounds__(kThreads) void k_adj_em_a(AdjEMArgs A) {
         const float ab = mx[0] + 2.f * mx[1] * (wwin(i, L, R) * mx[2] + wwin(i + 1, L, R) * mx[3]);
         tot += A.cmur * (ab + 2.f * kapf(mx[4], mx[5]) * mx[6]);
       }
-      const float gg = (tot + 2.f * kap * xlj) / (1.f + kap);
-      A.gx[o] = gg;
-      A.kx[o] = (eo + xen) * (2.f * xlj - gg);
+      gx = (tot + 2.f * kap * xlj) / (1.f + kap);
+      kx = (eo + xen) * (2.f * xlj - gx);
     } else {
-      A.gx[o] = tot + 2.f * kap * xlj;
-      A.kx[o] = 2.f * (eo + xen) * xlj;
+      gx = tot + 2.f * kap * xlj;
+      kx = 2.f * (eo + xen) * xlj;
     }
   }
   if (ey_ok(i, j)) {
-    const size_t o = g.o(i, j);
     const float kap = kapf(n00, n01);
     const bool bnd = (i == L || i == R);
     float eo = yeo;
@@ -160,145 +168,169 @@ __global__ __launch_bounds__(kThreads) void k_adj_em_a(AdjEMArgs A) {
         const float ab = my[0] + 2.f * my[1] * (wwin(j, B, T) * my[2] + wwin(j + 1, B, T) * my[3]);
         tot += A.cmur * (ab + 2.f * kapf(my[4], my[5]) * my[6]);
       }
-      const float gg = (tot + 2.f * kap * ylj) / (1.f + kap);
-      A.gy[o] = gg;
-      A.ky[o] = (eo + yen) * (2.f * ylj - gg);
+      gy = (tot + 2.f * kap * ylj) / (1.f + kap);
+      ky = (eo + yen) * (2.f * ylj - gy);
     } else {
-      A.gy[o] = tot + 2.f * kap * ylj;
-      A.ky[o] = 2.f * (eo + yen) * ylj;
+      gy = tot + 2.f * kap * ylj;
+      ky = 2.f * (eo + yen) * ylj;
     }
   }
 }
 
-// ---------------------------------------------------------------------------
-// EM adjoint, pass 2 (cells, edges, nodes): lam H entering the step, lam E
-// and lam J entering it, lam n, and the source-column sensitivities.
-// ---------------------------------------------------------------------------
 template <bool FINE>
-__global__ __launch_bounds__(kThreads) void k_adj_em_bc(AdjEMArgs A) {
-  const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
-  const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
-  if (i > A.R || j > A.T) return;
+__global__ __launch_bounds__(kAdjNT) void k_adj_em(AdjEMArgs A) {
+  constexpr int H1 = FINE ? 3 : 1, H2 = FINE ? 2 : 0;
+  constexpr int W1 = kAdjTX + 2 * H1, N1 = kAdjTY + 2 * H1;
+  constexpr int W2 = kAdjTX + 2 * H2, N2 = kAdjTY + 2 * H2;
+  __shared__ float sgx[N1][W1], sgy[N1][W1], skx[N1][W1], sky[N1][W1];
+  __shared__ float stx[FINE ? N2 : 1][FINE ? W2 : 1], sty[FINE ? N2 : 1][FINE ? W2 : 1];
   const Reg g{A.L, A.B, A.R, A.T, A.pitch};
   const int L = A.L, R = A.R, B = A.B, T = A.T;
+  const int i0 = L + blockIdx.x * kAdjTX, j0 = B + blockIdx.y * kAdjTY;
+  const int tid = threadIdx.x;
   const float S = A.S;
   const bool filt = FINE && A.gamma > 0.f;
-  // -- loads --
-  const float h00 = g.ld(A.lhz_in, i, j), h0m = g.ld(A.lhz_in, i, j - 1), hm0 = g.ld(A.lhz_in, i - 1, j);
-  const float gx00 = g.ld(A.gx, i, j), gx01 = g.ld(A.gx, i, j + 1), gx0m = g.ld(A.gx, i, j - 1);
-  const float gxm0 = g.ld(A.gx, i - 1, j), gxm1 = g.ld(A.gx, i - 1, j + 1);
-  const float gy10 = g.ld(A.gy, i + 1, j), gy00 = g.ld(A.gy, i, j), gy1m = g.ld(A.gy, i + 1, j - 1);
-  const float gy0m = g.ld(A.gy, i, j - 1), gym0 = g.ld(A.gy, i - 1, j);
-  const float n00 = g.ld(A.n, i, j), n10 = g.ld(A.n, i + 1, j), n01 = g.ld(A.n, i, j + 1);
-  const float ljx = g.ld(A.ljx, i, j), ljy = g.ld(A.ljy, i, j);
-  const float kxm = g.ld(A.kx, i - 1, j), kx0 = g.ld(A.kx, i, j);
-  const float kym = g.ld(A.ky, i, j - 1), ky0 = g.ld(A.ky, i, j), ln0 = g.ld(A.ln, i, j);
-  float gxB = 0.f, gxT = 0.f, gyL = 0.f, gyR = 0.f;
-  if constexpr (!FINE) {
-    gxB = g.ld(A.gx, i, B); gxT = g.ld(A.gx, i, T); gyL = g.ld(A.gy, L, j); gyR = g.ld(A.gy, R, j);
-  }
-  // optional additions (pointers fixed per launch)
-  const float hxv = A.hz_extra ? g.ld(A.hz_extra, i, j) : 0.f;
-  const float pxv = A.pex ? g.ld(A.pex, i, j) : 0.f;
-  const float pyv = A.pey ? g.ld(A.pey, i, j) : 0.f;
-  // -- compute --
-  // g of interior edges (boundary E' does not depend on H')
-  auto xi = [&](float v, int b) { return (b == B || b == T) ? 0.f : v; };
-  auto yi = [&](float v, int a) { return (a == L || a == R) ? 0.f : v; };
-  // lam of H' at a cell: its own plus the curl terms of the four edges
-  const float hc00 = h00 + S * (xi(gx00, j) - xi(gx01, j + 1)) + S * (yi(gy10, i + 1) - yi(gy00, i));
-  const float hc0m = h0m + S * (xi(gx0m, j - 1) - xi(gx00, j)) + S * (yi(gy1m, i + 1) - yi(gy0m, i));
-  const float hcm0 = hm0 + S * (xi(gxm0, j) - xi(gxm1, j + 1)) + S * (yi(gy00, i) - yi(gym0, i - 1));
-  const size_t o = g.o(i, j);
 
-  if (g.hz(i, j)) {
-    if (A.src_e && i == A.is - 1) A.src_e[j] = S * hc00;
-    A.lhz_out[o] = hc00 + hxv;
-    if (A.hz_extra) A.hz_extra[o] = 0.f;
+  // -- phase 1 ----------------------------------------------------------------
+  for (int k = tid; k < N1 * W1; k += kAdjNT) {
+    const int ci = k % W1, cj = k / W1;
+    float gx, kx, gy, ky;
+    adj_p1<FINE>(A, g, i0 - H1 + ci, j0 - H1 + cj, gx, kx, gy, ky);
+    sgx[cj][ci] = gx; skx[cj][ci] = kx;
+    sgy[cj][ci] = gy; sky[cj][ci] = ky;
   }
-  if (g.ex(i, j)) {
-    const float kap = A.kn * (0.5f * (n00 + n10));
-    float le = (g.hz(i, j - 1) ? S * hc0m : 0.f) - (g.hz(i, j) ? S * hc00 : 0.f);
-    const bool bnd = (j == B || j == T);
-    float ljn;
-    if (!bnd) {
-      le += (1.f - kap) * gx00 + 2.f * kap * ljx;
-      ljn = A.a * ljx - A.c1 * gx00;
-      if (!FINE && A.bc_y == kBcMur) {
-        if (j == B + 1) le += gxB;
-        if (j == T - 1) le += gxT;
-      }
-    } else {
-      le += 2.f * kap * ljx;
-      if (!FINE && A.bc_y == kBcMur) le -= A.cmur * gx00;
-      ljn = A.a * ljx;
-    }
-    le += pxv;
-    if (A.pex) A.pex[o] = 0.f;
-    if (filt) A.tex[o] = le; else A.lex[o] = le;
-    A.ljx[o] = ljn;
-  }
-  if (g.ey(i, j)) {
-    const float kap = A.kn * (0.5f * (n00 + n01));
-    float le = (g.hz(i, j) ? S * hc00 : 0.f) - (g.hz(i - 1, j) ? S * hcm0 : 0.f);
-    const bool bnd = (i == L || i == R);
-    float ljn;
-    if (!bnd) {
-      if (A.src_h && i == A.is) A.src_h[j] = S * gy00;
-      le += (1.f - kap) * gy00 + 2.f * kap * ljy;
-      ljn = A.a * ljy - A.c1 * gy00;
-      if (!FINE && A.bc_x == kBcMur) {
-        if (i == L + 1) le += gyL;
-        if (i == R - 1) le += gyR;
-      }
-    } else {
-      le += 2.f * kap * ljy;
-      if (!FINE && A.bc_x == kBcMur) le -= A.cmur * gy00;
-      ljn = A.a * ljy;
-    }
-    le += pyv;
-    if (A.pey) A.pey[o] = 0.f;
-    if (filt) A.tey[o] = le; else A.ley[o] = le;
-    A.ljy[o] = ljn;
-  }
-  // node: k of the (up to four) edges that average this node's density
-  float s = 0.f;
-  if (g.ex(i - 1, j)) s += kxm;
-  if (g.ex(i, j)) s += kx0;
-  if (g.ey(i, j - 1)) s += kym;
-  if (g.ey(i, j)) s += ky0;
-  A.ln[o] = ln0 + 0.5f * A.kn * s;
-}
+  __syncthreads();
+  auto GX = [&](int a, int b) { return sgx[b - j0 + H1][a - i0 + H1]; };
+  auto GY = [&](int a, int b) { return sgy[b - j0 + H1][a - i0 + H1]; };
+  auto KX = [&](int a, int b) { return skx[b - j0 + H1][a - i0 + H1]; };
+  auto KY = [&](int a, int b) { return sky[b - j0 + H1][a - i0 + H1]; };
 
-// ---------------------------------------------------------------------------
-// Fine patch: adjoint of the E filter E~ = E - gamma P L(L(E)) (P: the
-// filtered edges), with L symmetric:  lam E = lam E~ - gamma L(L(P lam E~)).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_adj_filter(AdjEMArgs A) {
-  const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
-  const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
-  if (i > A.R || j > A.T) return;
-  const Reg g{A.L, A.B, A.R, A.T, A.pitch};
-  const int L = A.L, R = A.R, B = A.B, T = A.T;
-  auto ex_ok = [=](int a, int b) { return g.ex(a, b); };
-  auto ey_ok = [=](int a, int b) { return g.ey(a, b); };
-  float tx[13], ty[13];
-  load13<decltype(ex_ok)>(g, A.tex, i, j, tx);
-  load13<decltype(ey_ok)>(g, A.tey, i, j, ty);
-  // masked: only filtered edges (not the patch boundary ones) carry lam
-#pragma unroll
-  for (int b = -2; b <= 2; b++)
-#pragma unroll
-    for (int a = -2; a <= 2; a++)
-      if ((a < 0 ? -a : a) + (b < 0 ? -b : b) <= 2) {
-        const int k = dmd(a, b);
-        const int jj = j + b, ii = i + a;
-        if (jj == B || jj == T) tx[k] = 0.f;
-        if (ii == L || ii == R) ty[k] = 0.f;
+  // -- phase 2 ----------------------------------------------------------------
+  for (int k = tid; k < N2 * W2; k += kAdjNT) {
+    const int ci = k % W2, cj = k / W2;
+    const int i = i0 - H2 + ci, j = j0 - H2 + cj;
+    const bool own = ci >= H2 && ci < H2 + kAdjTX && cj >= H2 && cj < H2 + kAdjTY &&
+                     i <= R && j <= T;
+    // loads (clamped)
+    const float h00 = g.ld(A.lhz_in, i, j), h0m = g.ld(A.lhz_in, i, j - 1),
+                hm0 = g.ld(A.lhz_in, i - 1, j);
+    const float n00 = g.ld(A.n, i, j), n10 = g.ld(A.n, i + 1, j), n01 = g.ld(A.n, i, j + 1);
+    const float ljx = g.ld(A.ljx, i, j), ljy = g.ld(A.ljy, i, j), ln0 = g.ld(A.ln, i, j);
+    const float hxv = A.hz_extra ? g.ld(A.hz_extra, i, j) : 0.f;
+    const float pxv = A.pex ? g.ld(A.pex, i, j) : 0.f;
+    const float pyv = A.pey ? g.ld(A.pey, i, j) : 0.f;
+    // g of interior edges (boundary E' does not depend on H')
+    auto xi = [&](int a, int b) { return (b == B || b == T) ? 0.f : GX(a, b); };
+    auto yi = [&](int a, int b) { return (a == L || a == R) ? 0.f : GY(a, b); };
+    // lam of H' at a cell: its own plus the curl terms of the four edges
+    const float hc00 = h00 + S * (xi(i, j) - xi(i, j + 1)) + S * (yi(i + 1, j) - yi(i, j));
+    const float hc0m = h0m + S * (xi(i, j - 1) - xi(i, j)) + S * (yi(i + 1, j - 1) - yi(i, j - 1));
+    const float hcm0 = hm0 + S * (xi(i - 1, j) - xi(i - 1, j + 1)) + S * (yi(i, j) - yi(i - 1, j));
+    const size_t o = g.o(i, j);
+    float tex = 0.f, tey = 0.f;
+    if (g.hz(i, j) && own) {
+      if (A.src_e && i == A.is - 1) A.src_e[j] = S * hc00;
+      A.lhz_out[o] = hc00 + hxv;
+      if (A.hz_extra) A.hz_extra[o] = 0.f;
+    }
+    if (g.ex(i, j)) {
+      const float gxv = GX(i, j);
+      const float kap = A.kn * (0.5f * (n00 + n10));
+      float le = (g.hz(i, j - 1) ? S * hc0m : 0.f) - (g.hz(i, j) ? S * hc00 : 0.f);
+      const bool bnd = (j == B || j == T);
+      float ljn;
+      if (!bnd) {
+        le += (1.f - kap) * gxv + 2.f * kap * ljx;
+        ljn = A.a * ljx - A.c1 * gxv;
+        if (!FINE && A.bc_y == kBcMur) {
+          if (j == B + 1) le += GX(i, B);
+          if (j == T - 1) le += GX(i, T);
+        }
+      } else {
+        le += 2.f * kap * ljx;
+        if (!FINE && A.bc_y == kBcMur) le -= A.cmur * gxv;
+        ljn = A.a * ljx;
       }
-  const size_t o = g.o(i, j);
-  if (g.ex(i, j)) A.lex[o] = A.tex[o] - A.gamma * ll13(tx, i, j, ex_ok);
-  if (g.ey(i, j)) A.ley[o] = A.tey[o] - A.gamma * ll13(ty, i, j, ey_ok);
+      le += pxv;
+      tex = le;
+      if (own) {
+        if (A.pex) A.pex[o] = 0.f;
+        if (!filt) A.lex_o[o] = le;
+        A.ljx_o[o] = ljn;
+        A.gx[o] = gxv;
+      }
+    }
+    if (g.ey(i, j)) {
+      const float gyv = GY(i, j);
+      const float kap = A.kn * (0.5f * (n00 + n01));
+      float le = (g.hz(i, j) ? S * hc00 : 0.f) - (g.hz(i - 1, j) ? S * hcm0 : 0.f);
+      const bool bnd = (i == L || i == R);
+      float ljn;
+      if (!bnd) {
+        if (own && A.src_h && i == A.is) A.src_h[j] = S * gyv;
+        le += (1.f - kap) * gyv + 2.f * kap * ljy;
+        ljn = A.a * ljy - A.c1 * gyv;
+        if (!FINE && A.bc_x == kBcMur) {
+          if (i == L + 1) le += GY(L, j);
+          if (i == R - 1) le += GY(R, j);
+        }
+      } else {
+        le += 2.f * kap * ljy;
+        if (!FINE && A.bc_x == kBcMur) le -= A.cmur * gyv;
+        ljn = A.a * ljy;
+      }
+      le += pyv;
+      tey = le;
+      if (own) {
+        if (A.pey) A.pey[o] = 0.f;
+        if (!filt) A.ley_o[o] = le;
+        A.ljy_o[o] = ljn;
+        A.gy[o] = gyv;
+      }
+    }
+    if (own) {
+      // node: k of the (up to four) edges that average this node's density
+      float sk = 0.f;
+      if (g.ex(i - 1, j)) sk += KX(i - 1, j);
+      if (g.ex(i, j)) sk += KX(i, j);
+      if (g.ey(i, j - 1)) sk += KY(i, j - 1);
+      if (g.ey(i, j)) sk += KY(i, j);
+      A.ln[o] = ln0 + 0.5f * A.kn * sk;
+    }
+    if constexpr (FINE) {
+      stx[cj][ci] = tex;
+      sty[cj][ci] = tey;
+    }
+  }
+
+  // -- phase 3 (patch): E filter transposed -------------------------------------
+  if constexpr (FINE) {
+    if (!filt) return;
+    __syncthreads();
+    auto ex_ok = [=](int a, int b) { return g.ex(a, b); };
+    auto ey_ok = [=](int a, int b) { return g.ey(a, b); };
+    for (int k = tid; k < kAdjTX * kAdjTY; k += kAdjNT) {
+      const int i = i0 + k % kAdjTX, j = j0 + k / kAdjTX;
+      if (i > R || j > T) continue;
+      // P lam E~ on the diamond: only filtered edges (not the boundary ones)
+      float tx[13], ty[13];
+#pragma unroll
+      for (int b = -2; b <= 2; b++)
+#pragma unroll
+        for (int a = -2; a <= 2; a++)
+          if ((a < 0 ? -a : a) + (b < 0 ? -b : b) <= 2) {
+            const int q = dmd(a, b);
+            const float vx = stx[j - j0 + H2 + b][i - i0 + H2 + a];
+            const float vy = sty[j - j0 + H2 + b][i - i0 + H2 + a];
+            tx[q] = (j + b == B || j + b == T) ? 0.f : vx;
+            ty[q] = (i + a == L || i + a == R) ? 0.f : vy;
+          }
+      const size_t o = g.o(i, j);
+      const float tex = stx[j - j0 + H2][i - i0 + H2], tey = sty[j - j0 + H2][i - i0 + H2];
+      if (g.ex(i, j)) A.lex_o[o] = tex - A.gamma * ll13(tx, i, j, ex_ok);
+      if (g.ey(i, j)) A.ley_o[o] = tey - A.gamma * ll13(ty, i, j, ey_ok);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -727,15 +759,9 @@ dim3 node_grid(int L, int B, int R, int T) {
 }  // namespace
 
 hipError_t launch_adj_em(const AdjEMArgs& A, hipStream_t st) {
-  const dim3 g = node_grid(A.L, A.B, A.R, A.T);
-  if (A.fine) {
-    k_adj_em_a<true><<<g, kThreads, 0, st>>>(A);
-    k_adj_em_bc<true><<<g, kThreads, 0, st>>>(A);
-    if (A.gamma > 0.f) k_adj_filter<<<g, kThreads, 0, st>>>(A);
-  } else {
-    k_adj_em_a<false><<<g, kThreads, 0, st>>>(A);
-    k_adj_em_bc<false><<<g, kThreads, 0, st>>>(A);
-  }
+  const dim3 g((A.R - A.L + kAdjTX) / kAdjTX, (A.T - A.B + kAdjTY) / kAdjTY);
+  if (A.fine) k_adj_em<true><<<g, kAdjNT, 0, st>>>(A);
+  else k_adj_em<false><<<g, kAdjNT, 0, st>>>(A);
   return hipGetLastError();
 }
 

@@ -1073,9 +1073,16 @@ struct AdjLevel {
   float* hz[2] = {nullptr, nullptr};
   float *ex = nullptr, *ey = nullptr, *jx = nullptr, *jy = nullptr, *n = nullptr,
         *acc = nullptr, *ring = nullptr;
-  float *gx = nullptr, *gy = nullptr, *kx = nullptr, *ky = nullptr, *tex = nullptr,
-        *tey = nullptr, *ell = nullptr, *hx = nullptr, *pex = nullptr, *pey = nullptr;
+  // second buffers of lam E, J: an EM adjoint launch reads one and writes
+  // the other (flip() swaps them, with the two lam Hz buffers)
+  float *ex2 = nullptr, *ey2 = nullptr, *jx2 = nullptr, *jy2 = nullptr;
+  float *gx = nullptr, *gy = nullptr, *ell = nullptr, *hx = nullptr, *pex = nullptr,
+        *pey = nullptr;
   int cur = 0;
+  void flip() {
+    cur = 1 - cur;
+    std::swap(ex, ex2); std::swap(ey, ey2); std::swap(jx, jx2); std::swap(jy, jy2);
+  }
 };
 
 AdjLevel adj_carve(char* base, size_t plane) {
@@ -1085,8 +1092,8 @@ AdjLevel adj_carve(char* base, size_t plane) {
   a.hz[0] = take(1); a.hz[1] = take(1);
   a.ex = take(1); a.ey = take(1); a.jx = take(1); a.jy = take(1);
   a.n = take(1); a.acc = take(1); a.ring = take(kRing);
-  a.gx = take(1); a.gy = take(1); a.kx = take(1); a.ky = take(1);
-  a.tex = take(1); a.tey = take(1); a.ell = take(1); a.hx = take(1);
+  a.gx = take(1); a.gy = take(1); a.ex2 = take(1); a.ey2 = take(1);
+  a.jx2 = take(1); a.jy2 = take(1); a.ell = take(1); a.hx = take(1);
   a.pex = take(1); a.pey = take(1);
   return a;
 }
@@ -1166,7 +1173,8 @@ AdjEMArgs adj_em_args(const dmr_sim* s, const Level& Lv, AdjLevel& a, bool fine,
   A.is = fine ? -1 : p.tfsf_i;
   A.lhz_in = a.hz[a.cur]; A.lhz_out = a.hz[1 - a.cur];
   A.lex = a.ex; A.ley = a.ey; A.ljx = a.jx; A.ljy = a.jy; A.lacc = a.acc;
-  A.gx = a.gx; A.gy = a.gy; A.kx = a.kx; A.ky = a.ky; A.tex = a.tex; A.tey = a.tey;
+  A.lex_o = a.ex2; A.ley_o = a.ey2; A.ljx_o = a.jx2; A.ljy_o = a.jy2;
+  A.gx = a.gx; A.gy = a.gy;
   A.ln = a.n;
   return A;
 }
@@ -1279,7 +1287,7 @@ int adj_step(dmr_sim* s, const TapeLayout& T, AdjLevel& ac, AdjLevel& af, int kk
       A.hz_extra = sub == 2 ? af.hx : nullptr;
       e = launch_adj_em(A, s->st);
       if (e != hipSuccess) return hipfail(s, e, "adjoint fine EM launch");
-      af.cur = 1 - af.cur;
+      af.flip();
       AdjCfbArgs Q{freg[0], freg[1], freg[2], freg[3], m.ext[0], m.ext[1], m.ext[2], m.ext[3],
                    F.pitch, C.pitch, (float)sub / (float)r, af.gx, af.gy,
                    ac.ex, ac.ey, ac.pex, ac.pey};
@@ -1297,7 +1305,7 @@ int adj_step(dmr_sim* s, const TapeLayout& T, AdjLevel& ac, AdjLevel& af, int kk
   }
   e = launch_adj_em(A, s->st);
   if (e != hipSuccess) return hipfail(s, e, "adjoint base EM launch");
-  ac.cur = 1 - ac.cur;
+  ac.flip();
   return DMR_OK;
 }
 

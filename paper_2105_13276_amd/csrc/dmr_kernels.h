@@ -139,12 +139,12 @@ struct AdjEMArgs {
   const float* n;
   const float* lhz_in;     // lam of Hz leaving the step
   float* lhz_out;          // lam of Hz entering it
-  float *lex, *ley, *ljx, *ljy;  // lam of E, J: leaving in, entering out
+  const float *lex, *ley, *ljx, *ljy;  // lam of E, J leaving the step
+  float *lex_o, *ley_o, *ljx_o, *ljy_o;  // lam of E, J entering it (other buffers)
   const float* lacc;
   float* hz_extra;         // added to lam Hz entering, then cleared (nullable)
   float *pex, *pey;        // added to lam E entering, then cleared (nullable)
-  float *gx, *gy, *kx, *ky;  // per-edge temporaries
-  float *tex, *tey;        // fine with filter: lam of the filtered E
+  float *gx, *gy;          // out: g per edge (G on boundary edges)
   float* ln;               // lam n (accumulated)
   float *src_e, *src_h;    // base: per-row source sensitivities (nullable)
 };
