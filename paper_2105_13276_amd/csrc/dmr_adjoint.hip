@@ -102,28 +102,104 @@ __device__ inline float ll13(const float v[13], int i, int j, OK ok) {
 // from one buffer and written to another, so no block reads what another
 // block writes in the same launch.
 // ---------------------------------------------------------------------------
-constexpr int kAdjTX = 32, kAdjTY = 16, kAdjNT = 512;
+constexpr int kAdjTX = 32, kAdjTY = 16;
+
+// lam inputs of a (sub)step with the transfers folded in.  Patch, last
+// substep: + the coarse lam of the entity the fine one was averaged into
+// (Hz: 1/4 of the cell mean x 1/2 of the two half levels; E: 1/2 of the edge
+// mean; J~: the sum).  Base level: zero strictly inside the patch.
+template <bool FINE>
+struct LamIn {
+  const AdjEMArgs& A;
+  const Reg& g;
+  __device__ size_t co(int i, int j) const {  // coarse entity of fine (i, j)
+    const int a = i < g.L ? g.L : (i > g.R ? g.R : i), b = j < g.B ? g.B : (j > g.T ? g.T : j);
+    return (size_t)(b >> 1) * A.cpitch + (a >> 1);
+  }
+  __device__ float hz(int i, int j) const {
+    const float v = g.ld(A.lhz_in, i, j);
+    if constexpr (FINE) {
+      if (A.rhz) return v + 0.125f * A.rhz[co(i, j)];
+      return v;
+    } else {
+      const bool in = A.has_patch && i >= A.I0 && i < A.I1 && j >= A.J0 && j < A.J1;
+      return in ? 0.f : v;
+    }
+  }
+  // x-edges (X) or y-edges (!X): lam E (ex) and lam J (jx)
+  template <bool X>
+  __device__ void ej(int i, int j, float& le, float& lj) const {
+    le = g.ld(X ? A.lex : A.ley, i, j);
+    lj = g.ld(X ? A.ljx : A.ljy, i, j);
+    if constexpr (FINE) {
+      if (A.rex) {
+        const size_t c = co(i, j);
+        const float ve = X ? A.rex[c] : A.rey[c], vj = X ? A.rjx[c] : A.rjy[c];
+        const int q = X ? j : i, q0 = X ? A.J0 : A.I0, q1 = X ? A.J1 : A.I1;
+        const bool in = (q & 1) == 0 && (q >> 1) > q0 && (q >> 1) < q1;
+        if (in) { le += 0.5f * ve; lj += vj; }
+      }
+    } else {
+      const bool in = A.has_patch &&
+                      (X ? (i >= A.I0 && i < A.I1 && j > A.J0 && j < A.J1)
+                         : (i > A.I0 && i < A.I1 && j >= A.J0 && j < A.J1));
+      if (in) { le = 0.f; lj = 0.f; }
+    }
+  }
+};
+
+// Eq. (5b) transposed at a coarse edge of the patch boundary lines: the sum
+// of the fine boundary g of one substep weighted 1/4, 3/4, 3/4, 1/4 in space
+// (zero off the lines)
+template <bool X>
+__device__ inline float cfb_sum(const AdjEMArgs& A, const float* gf, int i, int j) {
+  const int c = X ? i : j, line = X ? j : i;
+  const int l0 = X ? A.J0 : A.I0, l1 = X ? A.J1 : A.I1, c0 = X ? A.I0 : A.J0, c1 = X ? A.I1 : A.J1;
+  const int lo = X ? A.fL : A.fB, hi = X ? A.fR : A.fT;
+  const int f = 2 * (line < l0 ? l0 : (line > l1 ? l1 : line));
+  const float w[4] = {0.25f, 0.75f, 0.75f, 0.25f};
+  float v[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    int fc = 2 * c - 1 + q;
+    fc = fc < lo ? lo : (fc > hi ? hi : fc);
+    v[q] = X ? gf[(size_t)f * A.fpitch + fc] : gf[(size_t)fc * A.fpitch + f];
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const int fc = 2 * c - 1 + q;
+    s += (fc >= lo && fc < hi) ? w[q] * v[q] : 0.f;
+  }
+  const bool on = (line == l0 || line == l1) && c >= c0 - 1 && c <= c1;
+  return on ? s : 0.f;
+}
 
 // phase 1 at position (i, j): g and lam k of x-edge (i, j) and y-edge (i, j)
-// (zero where the edge does not exist)
+// (zero where the edge does not exist); base level with a patch: px, py =
+// the lam of the coarse E entering the step from Eq. (5b)
 template <bool FINE>
 __device__ inline void adj_p1(const AdjEMArgs& A, const Reg& g, int i, int j, float& gx,
-                              float& kx, float& gy, float& ky) {
+                              float& kx, float& gy, float& ky, float& px, float& py) {
   const int L = A.L, R = A.R, B = A.B, T = A.T;
+  const LamIn<FINE> in{A, g};
   auto ex_ok = [=](int a, int b) { return g.ex(a, b); };
   auto ey_ok = [=](int a, int b) { return g.ey(a, b); };
   // Mur partners (own edge where there is none: a cache hit, never used)
   const int jb = (j == B + 1) ? B : (j == T - 1 ? T : j);
   const int ib = (i == L + 1) ? L : (i == R - 1 ? R : i);
   // -- loads --
-  const float xle = g.ld(A.lex, i, j), xen = g.ld(A.exo, i, j), xeo = g.ld(A.exi, i, j);
+  float xle, xlj, yle, ylj;
+  in.template ej<true>(i, j, xle, xlj);
+  in.template ej<false>(i, j, yle, ylj);
+  const float xen = g.ld(A.exo, i, j), xeo = g.ld(A.exi, i, j);
   const float xa0 = g.ld(A.lacc, i, j), xa1 = g.ld(A.lacc, i + 1, j);
   const float n00 = g.ld(A.n, i, j), n10 = g.ld(A.n, i + 1, j), n01 = g.ld(A.n, i, j + 1);
-  const float xlj = g.ld(A.ljx, i, j);
-  const float yle = g.ld(A.ley, i, j), yen = g.ld(A.eyo, i, j), yeo = g.ld(A.eyi, i, j);
-  const float ya1 = g.ld(A.lacc, i, j + 1), ylj = g.ld(A.ljy, i, j);
+  const float yen = g.ld(A.eyo, i, j), yeo = g.ld(A.eyi, i, j);
+  const float ya1 = g.ld(A.lacc, i, j + 1);
   float mx[7] = {0, 0, 0, 0, 0, 0, 0}, my[7] = {0, 0, 0, 0, 0, 0, 0};
   float dx[13], dy[13];
+  float s1x = 0.f, s2x = 0.f, s1y = 0.f, s2y = 0.f;
   if constexpr (!FINE) {
     mx[0] = g.ld(A.lex, i, jb); mx[1] = g.ld(A.exo, i, jb); mx[2] = g.ld(A.lacc, i, jb);
     mx[3] = g.ld(A.lacc, i + 1, jb); mx[4] = g.ld(A.n, i, jb); mx[5] = g.ld(A.n, i + 1, jb);
@@ -131,11 +207,24 @@ __device__ inline void adj_p1(const AdjEMArgs& A, const Reg& g, int i, int j, fl
     my[0] = g.ld(A.ley, ib, j); my[1] = g.ld(A.eyo, ib, j); my[2] = g.ld(A.lacc, ib, j);
     my[3] = g.ld(A.lacc, ib, j + 1); my[4] = g.ld(A.n, ib, j); my[5] = g.ld(A.n, ib, j + 1);
     my[6] = g.ld(A.ljy, ib, j);
+    if (A.has_patch) {
+      s1x = cfb_sum<true>(A, A.g1x, i, j); s2x = cfb_sum<true>(A, A.g2x, i, j);
+      s1y = cfb_sum<false>(A, A.g1y, i, j); s2y = cfb_sum<false>(A, A.g2y, i, j);
+    }
   } else {
     load13<decltype(ex_ok)>(g, A.exi, i, j, dx);
     load13<decltype(ey_ok)>(g, A.eyi, i, j, dy);
   }
   // -- compute --
+  // Eq. (5b) in time: substep m takes frac m/2 of E^{n+1}, 1 - m/2 of E^n
+  if constexpr (!FINE) {
+    xle = (xle + 1.f * s2x) + 0.5f * s1x;
+    yle = (yle + 1.f * s2y) + 0.5f * s1y;
+    px = (0.f + 0.f * s2x) + 0.5f * s1x;
+    py = (0.f + 0.f * s2y) + 0.5f * s1y;
+  } else {
+    px = 0.f; py = 0.f;
+  }
   auto kapf = [&](float a, float b) { return A.kn * (0.5f * (a + b)); };
   gx = 0.f; kx = 0.f; gy = 0.f; ky = 0.f;
   if (ex_ok(i, j)) {
@@ -177,14 +266,16 @@ __device__ inline void adj_p1(const AdjEMArgs& A, const Reg& g, int i, int j, fl
   }
 }
 
-template <bool FINE>
-__global__ __launch_bounds__(kAdjNT) void k_adj_em(AdjEMArgs A) {
+template <bool FINE, int NT>
+__global__ __launch_bounds__(NT) void k_adj_em(AdjEMArgs A) {
   constexpr int H1 = FINE ? 3 : 1, H2 = FINE ? 2 : 0;
   constexpr int W1 = kAdjTX + 2 * H1, N1 = kAdjTY + 2 * H1;
   constexpr int W2 = kAdjTX + 2 * H2, N2 = kAdjTY + 2 * H2;
   __shared__ float sgx[N1][W1], sgy[N1][W1], skx[N1][W1], sky[N1][W1];
+  __shared__ float spx[FINE ? 1 : N1][FINE ? 1 : W1], spy[FINE ? 1 : N1][FINE ? 1 : W1];
   __shared__ float stx[FINE ? N2 : 1][FINE ? W2 : 1], sty[FINE ? N2 : 1][FINE ? W2 : 1];
   const Reg g{A.L, A.B, A.R, A.T, A.pitch};
+  const LamIn<FINE> in{A, g};
   const int L = A.L, R = A.R, B = A.B, T = A.T;
   const int i0 = L + blockIdx.x * kAdjTX, j0 = B + blockIdx.y * kAdjTY;
   const int tid = threadIdx.x;
@@ -192,12 +283,13 @@ __global__ __launch_bounds__(kAdjNT) void k_adj_em(AdjEMArgs A) {
   const bool filt = FINE && A.gamma > 0.f;
 
   // -- phase 1 ----------------------------------------------------------------
-  for (int k = tid; k < N1 * W1; k += kAdjNT) {
+  for (int k = tid; k < N1 * W1; k += NT) {
     const int ci = k % W1, cj = k / W1;
-    float gx, kx, gy, ky;
-    adj_p1<FINE>(A, g, i0 - H1 + ci, j0 - H1 + cj, gx, kx, gy, ky);
+    float gx, kx, gy, ky, px, py;
+    adj_p1<FINE>(A, g, i0 - H1 + ci, j0 - H1 + cj, gx, kx, gy, ky, px, py);
     sgx[cj][ci] = gx; skx[cj][ci] = kx;
     sgy[cj][ci] = gy; sky[cj][ci] = ky;
+    if constexpr (!FINE) { spx[cj][ci] = px; spy[cj][ci] = py; }
   }
   __syncthreads();
   auto GX = [&](int a, int b) { return sgx[b - j0 + H1][a - i0 + H1]; };
@@ -206,19 +298,29 @@ __global__ __launch_bounds__(kAdjNT) void k_adj_em(AdjEMArgs A) {
   auto KY = [&](int a, int b) { return sky[b - j0 + H1][a - i0 + H1]; };
 
   // -- phase 2 ----------------------------------------------------------------
-  for (int k = tid; k < N2 * W2; k += kAdjNT) {
+  for (int k = tid; k < N2 * W2; k += NT) {
     const int ci = k % W2, cj = k / W2;
     const int i = i0 - H2 + ci, j = j0 - H2 + cj;
     const bool own = ci >= H2 && ci < H2 + kAdjTX && cj >= H2 && cj < H2 + kAdjTY &&
                      i <= R && j <= T;
     // loads (clamped)
-    const float h00 = g.ld(A.lhz_in, i, j), h0m = g.ld(A.lhz_in, i, j - 1),
-                hm0 = g.ld(A.lhz_in, i - 1, j);
+    const float h00 = in.hz(i, j), h0m = in.hz(i, j - 1), hm0 = in.hz(i - 1, j);
+    float lex_, ljx, ley_, ljy;
+    in.template ej<true>(i, j, lex_, ljx);
+    in.template ej<false>(i, j, ley_, ljy);
     const float n00 = g.ld(A.n, i, j), n10 = g.ld(A.n, i + 1, j), n01 = g.ld(A.n, i, j + 1);
-    const float ljx = g.ld(A.ljx, i, j), ljy = g.ld(A.ljy, i, j), ln0 = g.ld(A.ln, i, j);
-    const float hxv = A.hz_extra ? g.ld(A.hz_extra, i, j) : 0.f;
-    const float pxv = A.pex ? g.ld(A.pex, i, j) : 0.f;
-    const float pyv = A.pey ? g.ld(A.pey, i, j) : 0.f;
+    const float ln0 = g.ld(A.ln, i, j);
+    float hxv = 0.f;
+    if constexpr (FINE) {
+      if (A.rhz) hxv = 0.125f * A.rhz[in.co(i, j)];
+    } else {
+      if (A.hz_extra) hxv = g.ld(A.hz_extra, i, j);
+    }
+    float pxv = 0.f, pyv = 0.f;
+    if constexpr (!FINE) {
+      pxv = spx[j - j0 + H1][i - i0 + H1];
+      pyv = spy[j - j0 + H1][i - i0 + H1];
+    }
     // g of interior edges (boundary E' does not depend on H')
     auto xi = [&](int a, int b) { return (b == B || b == T) ? 0.f : GX(a, b); };
     auto yi = [&](int a, int b) { return (a == L || a == R) ? 0.f : GY(a, b); };
@@ -231,7 +333,7 @@ __global__ __launch_bounds__(kAdjNT) void k_adj_em(AdjEMArgs A) {
     if (g.hz(i, j) && own) {
       if (A.src_e && i == A.is - 1) A.src_e[j] = S * hc00;
       A.lhz_out[o] = hc00 + hxv;
-      if (A.hz_extra) A.hz_extra[o] = 0.f;
+      if (!FINE && A.hz_extra) A.hz_extra[o] = 0.f;
     }
     if (g.ex(i, j)) {
       const float gxv = GX(i, j);
@@ -254,10 +356,9 @@ __global__ __launch_bounds__(kAdjNT) void k_adj_em(AdjEMArgs A) {
       le += pxv;
       tex = le;
       if (own) {
-        if (A.pex) A.pex[o] = 0.f;
         if (!filt) A.lex_o[o] = le;
         A.ljx_o[o] = ljn;
-        A.gx[o] = gxv;
+        if (FINE) A.gx[o] = gxv;
       }
     }
     if (g.ey(i, j)) {
@@ -282,12 +383,12 @@ __global__ __launch_bounds__(kAdjNT) void k_adj_em(AdjEMArgs A) {
       le += pyv;
       tey = le;
       if (own) {
-        if (A.pey) A.pey[o] = 0.f;
         if (!filt) A.ley_o[o] = le;
         A.ljy_o[o] = ljn;
-        A.gy[o] = gyv;
+        if (FINE) A.gy[o] = gyv;
       }
     }
+    (void)lex_; (void)ley_;
     if (own) {
       // node: k of the (up to four) edges that average this node's density
       float sk = 0.f;
@@ -309,7 +410,7 @@ __global__ __launch_bounds__(kAdjNT) void k_adj_em(AdjEMArgs A) {
     __syncthreads();
     auto ex_ok = [=](int a, int b) { return g.ex(a, b); };
     auto ey_ok = [=](int a, int b) { return g.ey(a, b); };
-    for (int k = tid; k < kAdjTX * kAdjTY; k += kAdjNT) {
+    for (int k = tid; k < kAdjTX * kAdjTY; k += NT) {
       const int i = i0 + k % kAdjTX, j = j0 + k / kAdjTX;
       if (i > R || j > T) continue;
       // P lam E~ on the diamond: only filtered edges (not the boundary ones)
@@ -417,84 +518,6 @@ __global__ __launch_bounds__(kThreads) void k_adj_grow_clear(AdjGrowArgs A, floa
     if (A.with_n) ln[o] = 0.f;
     lacc[o] = 0.f;
     for (int s = 0; s < kRing; s++) lring[(size_t)s * A.plane + o] = 0.f;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Eq. (5b) transposed: coarse edges on the patch boundary lines gather the
-// lam of the fine boundary values that interpolated them (space weights
-// 1/4, 3/4; time weights 1-frac on E^n, frac on E^{n+1}).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_adj_cfb(AdjCfbArgs A) {
-  const int nx = A.I1 - A.I0 + 2, ny = A.J1 - A.J0 + 2;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 2 * nx + 2 * ny) return;
-  float s = 0.f;
-  size_t co;
-  bool xline;
-  if (t < 2 * nx) {  // Ex on coarse rows J0, J1
-    xline = true;
-    const int J = (t < nx) ? A.J0 : A.J1;
-    const int c = A.I0 - 1 + (t % nx);
-    const int jf = 2 * J;
-    const int fi[4] = {2 * c - 1, 2 * c, 2 * c + 1, 2 * c + 2};
-    const float fw[4] = {0.25f, 0.75f, 0.75f, 0.25f};
-    for (int q = 0; q < 4; q++)
-      if (fi[q] >= A.L && fi[q] < A.R) s += fw[q] * A.gx[at(fi[q], jf, A.pitch)];
-    co = at(c, J, A.cpitch);
-  } else {           // Ey on coarse columns I0, I1
-    xline = false;
-    const int u = t - 2 * nx;
-    const int I = (u < ny) ? A.I0 : A.I1;
-    const int c = A.J0 - 1 + (u % ny);
-    const int iff = 2 * I;
-    const int fj[4] = {2 * c - 1, 2 * c, 2 * c + 1, 2 * c + 2};
-    const float fw[4] = {0.25f, 0.75f, 0.75f, 0.25f};
-    for (int q = 0; q < 4; q++)
-      if (fj[q] >= A.B && fj[q] < A.T) s += fw[q] * A.gy[at(iff, fj[q], A.pitch)];
-    co = at(I, c, A.cpitch);
-  }
-  float* ln = xline ? A.lcex : A.lcey;
-  float* lo = xline ? A.pcex : A.pcey;
-  ln[co] += A.frac * s;
-  lo[co] += (1.f - A.frac) * s;
-}
-
-// ---------------------------------------------------------------------------
-// Fine -> coarse transfer transposed, one thread per coarse node position
-// of the patch: the coarse entities strictly inside hand their lam to the
-// fine entities they were averaged from and drop it (they were overwritten).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_adj_restrict(AdjRestrictArgs A) {
-  const int a = A.I0 + blockIdx.x * kAT + (threadIdx.x % kAT);
-  const int b = A.J0 + blockIdx.y * kAR + (threadIdx.x / kAT);
-  if (a > A.I1 || b > A.J1) return;
-  const size_t co = at(a, b, A.cpitch);
-  const int p = A.pitch;
-  const int i = 2 * a, j = 2 * b;
-  if (a < A.I1 && b < A.J1) {
-    const float v = 0.125f * A.lchz[co];
-    for (int db = 0; db < 2; db++)
-      for (int da = 0; da < 2; da++) {
-        const size_t o = at(i + da, j + db, p);
-        A.lfhz[o] += v;
-        A.hz_extra[o] = v;
-      }
-    A.lchz[co] = 0.f;
-  }
-  if (a < A.I1 && b > A.J0 && b < A.J1) {
-    const float v = 0.5f * A.lcex[co], w = A.lcjx[co];
-    const size_t o = at(i, j, p);
-    A.lfex[o] += v; A.lfex[o + 1] += v;
-    A.lfjx[o] += w; A.lfjx[o + 1] += w;
-    A.lcex[co] = 0.f; A.lcjx[co] = 0.f;
-  }
-  if (a > A.I0 && a < A.I1 && b < A.J1) {
-    const float v = 0.5f * A.lcey[co], w = A.lcjy[co];
-    const size_t o = at(i, j, p);
-    A.lfey[o] += v; A.lfey[o + p] += v;
-    A.lfjy[o] += w; A.lfjy[o + p] += w;
-    A.lcey[co] = 0.f; A.lcjy[co] = 0.f;
   }
 }
 
@@ -760,8 +783,8 @@ dim3 node_grid(int L, int B, int R, int T) {
 
 hipError_t launch_adj_em(const AdjEMArgs& A, hipStream_t st) {
   const dim3 g((A.R - A.L + kAdjTX) / kAdjTX, (A.T - A.B + kAdjTY) / kAdjTY);
-  if (A.fine) k_adj_em<true><<<g, kAdjNT, 0, st>>>(A);
-  else k_adj_em<false><<<g, kAdjNT, 0, st>>>(A);
+  if (A.fine) k_adj_em<true, 1024><<<g, 1024, 0, st>>>(A);
+  else k_adj_em<false, 512><<<g, 512, 0, st>>>(A);
   return hipGetLastError();
 }
 
@@ -775,17 +798,6 @@ hipError_t launch_adj_grow_clear(const AdjGrowArgs& A, float* lhz, float* lex, f
                                  float* lring, hipStream_t st) {
   k_adj_grow_clear<<<node_grid(A.L, A.B, A.R, A.T), kThreads, 0, st>>>(A, lhz, lex, ley, ljx,
                                                                          ljy, ln, lacc, lring);
-  return hipGetLastError();
-}
-
-hipError_t launch_adj_cfb(const AdjCfbArgs& A, hipStream_t st) {
-  const int n = 2 * (A.I1 - A.I0 + 2) + 2 * (A.J1 - A.J0 + 2);
-  k_adj_cfb<<<(n + kThreads - 1) / kThreads, kThreads, 0, st>>>(A);
-  return hipGetLastError();
-}
-
-hipError_t launch_adj_restrict(const AdjRestrictArgs& A, hipStream_t st) {
-  k_adj_restrict<<<node_grid(A.I0, A.J0, A.I1, A.J1), kThreads, 0, st>>>(A);
   return hipGetLastError();
 }
 

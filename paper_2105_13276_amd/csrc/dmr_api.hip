@@ -1076,8 +1076,9 @@ struct AdjLevel {
   // second buffers of lam E, J: an EM adjoint launch reads one and writes
   // the other (flip() swaps them, with the two lam Hz buffers)
   float *ex2 = nullptr, *ey2 = nullptr, *jx2 = nullptr, *jy2 = nullptr;
-  float *gx = nullptr, *gy = nullptr, *ell = nullptr, *hx = nullptr, *pex = nullptr,
-        *pey = nullptr;
+  // patch: g of substeps 1 (gx, gy) and 2 (g2x, g2y) for Eq. (5b) transposed
+  float *gx = nullptr, *gy = nullptr, *g2x = nullptr, *g2y = nullptr;
+  float *ell = nullptr, *hx = nullptr;
   int cur = 0;
   void flip() {
     cur = 1 - cur;
@@ -1094,7 +1095,7 @@ AdjLevel adj_carve(char* base, size_t plane) {
   a.n = take(1); a.acc = take(1); a.ring = take(kRing);
   a.gx = take(1); a.gy = take(1); a.ex2 = take(1); a.ey2 = take(1);
   a.jx2 = take(1); a.jy2 = take(1); a.ell = take(1); a.hx = take(1);
-  a.pex = take(1); a.pey = take(1);
+  a.g2x = take(1); a.g2y = take(1);
   return a;
 }
 
@@ -1269,12 +1270,7 @@ int adj_step(dmr_sim* s, const TapeLayout& T, AdjLevel& ac, AdjLevel& af, int kk
     }
     if (e != hipSuccess) return hipfail(s, e, "adjoint continuity launch");
   }
-  if (m.has) {  // fine -> coarse transfer, substeps 2 and 1, Eq. (5b)
-    AdjRestrictArgs X{m.ext[0], m.ext[1], m.ext[2], m.ext[3], F.pitch, C.pitch,
-                      ac.hz[ac.cur], ac.ex, ac.ey, ac.jx, ac.jy,
-                      af.hz[af.cur], af.ex, af.ey, af.jx, af.jy, af.hx};
-    e = launch_adj_restrict(X, s->st);
-    if (e != hipSuccess) return hipfail(s, e, "adjoint transfer launch");
+  if (m.has) {  // substeps 2 and 1 (the fine -> coarse transfer folded into 2)
     for (int sub = r; sub >= 1; sub--) {
       AdjEMArgs A = adj_em_args(s, F, af, true, freg);
       A.exi = sub == 2 ? ss.fex1 : ss.fex0;
@@ -1284,20 +1280,28 @@ int adj_step(dmr_sim* s, const TapeLayout& T, AdjLevel& ac, AdjLevel& af, int kk
       A.exo = sub == 2 ? (nxt ? nxt->fex0 : ss.fex2) : ss.fex1;
       A.eyo = sub == 2 ? (nxt ? nxt->fey0 : ss.fey2) : ss.fey1;
       A.n = ss.fn;
-      A.hz_extra = sub == 2 ? af.hx : nullptr;
+      A.gx = sub == 2 ? af.g2x : af.gx;
+      A.gy = sub == 2 ? af.g2y : af.gy;
+      A.I0 = m.ext[0]; A.J0 = m.ext[1]; A.I1 = m.ext[2]; A.J1 = m.ext[3];
+      A.cpitch = C.pitch;
+      if (sub == 2) {
+        A.rhz = ac.hz[ac.cur]; A.rex = ac.ex; A.rey = ac.ey; A.rjx = ac.jx; A.rjy = ac.jy;
+      }
       e = launch_adj_em(A, s->st);
       if (e != hipSuccess) return hipfail(s, e, "adjoint fine EM launch");
       af.flip();
-      AdjCfbArgs Q{freg[0], freg[1], freg[2], freg[3], m.ext[0], m.ext[1], m.ext[2], m.ext[3],
-                   F.pitch, C.pitch, (float)sub / (float)r, af.gx, af.gy,
-                   ac.ex, ac.ey, ac.pex, ac.pey};
-      e = launch_adj_cfb(Q, s->st);
-      if (e != hipSuccess) return hipfail(s, e, "adjoint boundary launch");
     }
   }
   AdjEMArgs A = adj_em_args(s, C, ac, false, creg);
   A.exi = ss.cexi; A.eyi = ss.ceyi; A.exo = ss.cexp; A.eyo = ss.ceyp; A.n = ss.cn;
-  A.hz_extra = ac.hx; A.pex = ac.pex; A.pey = ac.pey;
+  A.hz_extra = ac.hx;
+  if (m.has) {  // Eq. (5b) transposed and the patch interior, folded in
+    A.has_patch = 1;
+    A.I0 = m.ext[0]; A.J0 = m.ext[1]; A.I1 = m.ext[2]; A.J1 = m.ext[3];
+    A.fL = freg[0]; A.fB = freg[1]; A.fR = freg[2]; A.fT = freg[3];
+    A.fpitch = F.pitch;
+    A.g1x = af.gx; A.g1y = af.gy; A.g2x = af.g2x; A.g2y = af.g2y;
+  }
   if (p.tfsf_i > 0) {
     float* src = (float*)(s->tape.base + T.src + T.src_size * (size_t)kk);
     A.src_e = src;

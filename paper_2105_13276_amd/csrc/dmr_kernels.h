@@ -142,11 +142,21 @@ struct AdjEMArgs {
   const float *lex, *ley, *ljx, *ljy;  // lam of E, J leaving the step
   float *lex_o, *ley_o, *ljx_o, *ljy_o;  // lam of E, J entering it (other buffers)
   const float* lacc;
-  float* hz_extra;         // added to lam Hz entering, then cleared (nullable)
-  float *pex, *pey;        // added to lam E entering, then cleared (nullable)
-  float *gx, *gy;          // out: g per edge (G on boundary edges)
+  float* hz_extra;         // base: added to lam Hz entering, then cleared (nullable)
+  float *gx, *gy;          // patch, out: g per edge (G on boundary edges)
   float* ln;               // lam n (accumulated)
   float *src_e, *src_h;    // base: per-row source sensitivities (nullable)
+  // patch, last substep: the fine -> coarse transfer transposed, folded into
+  // the loads (the coarse lam of the entities strictly inside the coarse
+  // patch I0..I1 x J0..J1 goes to the fine entities averaged into them)
+  int I0, J0, I1, J1, cpitch;
+  const float *rhz, *rex, *rey, *rjx, *rjy;  // coarse lam (null: no transfer)
+  // base level with a patch (has_patch): the lam inputs of the entities
+  // strictly inside it read as zero (their lam went to the patch), and the
+  // Eq. (5b) boundary values transposed are gathered from the patch g of
+  // the two substeps on the fine cells fL..fR x fB..fT
+  int has_patch, fL, fB, fR, fT, fpitch;
+  const float *g1x, *g1y, *g2x, *g2y;
 };
 
 struct AdjGrowArgs {
@@ -159,22 +169,6 @@ struct AdjGrowArgs {
   int with_n;
   const float *lhz, *lex, *ley, *ljx, *ljy, *ln, *lacc, *lring;   // fine lam
   float *chz, *chz_prev, *cex, *cey, *cjx, *cjy, *cn, *cacc, *cring;  // coarse lam
-};
-
-struct AdjCfbArgs {
-  int L, B, R, T;        // fine patch (fine cells)
-  int I0, J0, I1, J1;    // coarse patch
-  int pitch, cpitch;
-  float frac;
-  const float *gx, *gy;  // fine: lam of the boundary E values
-  float *lcex, *lcey;    // coarse lam E after the coarse step
-  float *pcex, *pcey;    // coarse lam E before it (pending)
-};
-
-struct AdjRestrictArgs {
-  int I0, J0, I1, J1, pitch, cpitch;
-  float *lchz, *lcex, *lcey, *lcjx, *lcjy;
-  float *lfhz, *lfex, *lfey, *lfjx, *lfjy, *hz_extra;
 };
 
 struct AdjContArgs {
@@ -218,8 +212,6 @@ hipError_t launch_adj_grow_clear(const AdjGrowArgs& A, float* lhz, float* lex, f
 // rows x cols block between two pitched arrays
 hipError_t launch_copy2d(const float* src, int spitch, int si0, int sj0, float* dst,
                          int dpitch, int di0, int dj0, int cols, int rows, hipStream_t st);
-hipError_t launch_adj_cfb(const AdjCfbArgs& A, hipStream_t st);
-hipError_t launch_adj_restrict(const AdjRestrictArgs& A, hipStream_t st);
 hipError_t launch_adj_inj(const AdjInjArgs& A, hipStream_t st);
 // continuity adjoint; returns the number of partial pairs written
 hipError_t launch_adj_cont(const AdjContArgs& A, int* nparts, hipStream_t st);
