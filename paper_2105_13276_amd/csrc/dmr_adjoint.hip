@@ -102,69 +102,66 @@ __device__ inline float ll13(const float v[13], int i, int j, OK ok) {
 // from one buffer and written to another, so no block reads what another
 // block writes in the same launch.
 // ---------------------------------------------------------------------------
-constexpr int kAdjTX = 32, kAdjTY = 16;
-
-// lam inputs of a (sub)step with the transfers folded in.  Patch, last
-// substep: + the coarse lam of the entity the fine one was averaged into
-// (Hz: 1/4 of the cell mean x 1/2 of the two half levels; E: 1/2 of the edge
-// mean; J~: the sum).  Base level: zero strictly inside the patch.
-template <bool FINE>
-struct LamIn {
-  const AdjEMArgs& A;
-  const Reg& g;
-  __device__ size_t co(int i, int j) const {  // coarse entity of fine (i, j)
-    const int a = i < g.L ? g.L : (i > g.R ? g.R : i), b = j < g.B ? g.B : (j > g.T ? g.T : j);
-    return (size_t)(b >> 1) * A.cpitch + (a >> 1);
-  }
-  __device__ float hz(int i, int j) const {
-    const float v = g.ld(A.lhz_in, i, j);
-    if constexpr (FINE) {
-      if (A.rhz) return v + 0.125f * A.rhz[co(i, j)];
-      return v;
-    } else {
-      const bool in = A.has_patch && i >= A.I0 && i < A.I1 && j >= A.J0 && j < A.J1;
-      return in ? 0.f : v;
-    }
-  }
-  // x-edges (X) or y-edges (!X): lam E (ex) and lam J (jx)
-  template <bool X>
-  __device__ void ej(int i, int j, float& le, float& lj) const {
-    le = g.ld(X ? A.lex : A.ley, i, j);
-    lj = g.ld(X ? A.ljx : A.ljy, i, j);
-    if constexpr (FINE) {
-      if (A.rex) {
-        const size_t c = co(i, j);
-        const float ve = X ? A.rex[c] : A.rey[c], vj = X ? A.rjx[c] : A.rjy[c];
-        const int q = X ? j : i, q0 = X ? A.J0 : A.I0, q1 = X ? A.J1 : A.I1;
-        const bool in = (q & 1) == 0 && (q >> 1) > q0 && (q >> 1) < q1;
-        if (in) { le += 0.5f * ve; lj += vj; }
-      }
-    } else {
-      const bool in = A.has_patch &&
-                      (X ? (i >= A.I0 && i < A.I1 && j > A.J0 && j < A.J1)
-                         : (i > A.I0 && i < A.I1 && j >= A.J0 && j < A.J1));
-      if (in) { le = 0.f; lj = 0.f; }
-    }
-  }
+// Tiles: patch 32 x 16 positions (phase-1 region 38 x 22, phase-2 36 x 20),
+// base level 32 x 28 (34 x 30, phase 2 = the tile); 1024 threads, so every
+// phase is one position per thread and all of a thread's loads for both
+// phases are issued before any arithmetic.
+template <bool FINE> struct AdjTile {
+  static constexpr int TX = 32, TY = FINE ? 16 : 28, NT = 1024;
+  static constexpr int H1 = FINE ? 3 : 1, H2 = FINE ? 2 : 0;
+  static constexpr int W1 = TX + 2 * H1, N1 = TY + 2 * H1;
+  static constexpr int W2 = TX + 2 * H2, N2 = TY + 2 * H2;
+  static_assert(W1 * N1 <= NT && W2 * N2 <= NT, "one position per thread");
 };
 
-// Eq. (5b) transposed at a coarse edge of the patch boundary lines: the sum
-// of the fine boundary g of one substep weighted 1/4, 3/4, 3/4, 1/4 in space
-// (zero off the lines)
+// coarse entity of fine position (i, j) of the patch region g
+__device__ inline size_t coarse_of(const AdjEMArgs& A, const Reg& g, int i, int j) {
+  const int a = i < g.L ? g.L : (i > g.R ? g.R : i), b = j < g.B ? g.B : (j > g.T ? g.T : j);
+  return (size_t)(b >> 1) * A.cpitch + (a >> 1);
+}
+
+// Folded fine -> coarse transfer (patch, last substep): a fine entity gets
+// the coarse lam of the entity it was averaged into: Hz 1/4 of the cell mean
+// x 1/2 of the two half levels, E 1/2 of the edge mean, J~ the sum.
+// x-edges (X) on even rows strictly inside, y-edges on even columns.
 template <bool X>
-__device__ inline float cfb_sum(const AdjEMArgs& A, const float* gf, int i, int j) {
+__device__ inline bool fold_edge(const AdjEMArgs& A, int i, int j) {
+  const int q = X ? j : i, q0 = X ? A.J0 : A.I0, q1 = X ? A.J1 : A.I1;
+  return (q & 1) == 0 && (q >> 1) > q0 && (q >> 1) < q1;
+}
+// base level: coarse entities strictly inside the patch (their lam went to it)
+__device__ inline bool inside_hz(const AdjEMArgs& A, int i, int j) {
+  return A.has_patch && i >= A.I0 && i < A.I1 && j >= A.J0 && j < A.J1;
+}
+__device__ inline bool inside_ex(const AdjEMArgs& A, int i, int j) {
+  return A.has_patch && i >= A.I0 && i < A.I1 && j > A.J0 && j < A.J1;
+}
+__device__ inline bool inside_ey(const AdjEMArgs& A, int i, int j) {
+  return A.has_patch && i > A.I0 && i < A.I1 && j >= A.J0 && j < A.J1;
+}
+
+// Eq. (5b) transposed at coarse edge (i, j) of a patch boundary line: fine
+// boundary g of one substep weighted 1/4, 3/4, 3/4, 1/4 in space.  Split in
+// the four (clamped) loads and the sum, zero off the lines.
+template <bool X>
+__device__ inline void cfb_load(const AdjEMArgs& A, const float* gf, int i, int j, float v[4]) {
   const int c = X ? i : j, line = X ? j : i;
-  const int l0 = X ? A.J0 : A.I0, l1 = X ? A.J1 : A.I1, c0 = X ? A.I0 : A.J0, c1 = X ? A.I1 : A.J1;
+  const int l0 = X ? A.J0 : A.I0, l1 = X ? A.J1 : A.I1;
   const int lo = X ? A.fL : A.fB, hi = X ? A.fR : A.fT;
   const int f = 2 * (line < l0 ? l0 : (line > l1 ? l1 : line));
-  const float w[4] = {0.25f, 0.75f, 0.75f, 0.25f};
-  float v[4];
 #pragma unroll
   for (int q = 0; q < 4; q++) {
     int fc = 2 * c - 1 + q;
     fc = fc < lo ? lo : (fc > hi ? hi : fc);
     v[q] = X ? gf[(size_t)f * A.fpitch + fc] : gf[(size_t)fc * A.fpitch + f];
   }
+}
+template <bool X>
+__device__ inline float cfb_sum(const AdjEMArgs& A, const float v[4], int i, int j) {
+  const int c = X ? i : j, line = X ? j : i;
+  const int l0 = X ? A.J0 : A.I0, l1 = X ? A.J1 : A.I1, c0 = X ? A.I0 : A.J0, c1 = X ? A.I1 : A.J1;
+  const int lo = X ? A.fL : A.fB, hi = X ? A.fR : A.fT;
+  const float w[4] = {0.25f, 0.75f, 0.75f, 0.25f};
   float s = 0.f;
 #pragma unroll
   for (int q = 0; q < 4; q++) {
@@ -175,121 +172,190 @@ __device__ inline float cfb_sum(const AdjEMArgs& A, const float* gf, int i, int 
   return on ? s : 0.f;
 }
 
-// phase 1 at position (i, j): g and lam k of x-edge (i, j) and y-edge (i, j)
-// (zero where the edge does not exist); base level with a patch: px, py =
-// the lam of the coarse E entering the step from Eq. (5b)
+// values phase 1 needs at position (i, j)
+struct P1In {
+  float xle, xlj, yle, ylj;            // lam E, J leaving
+  float rxe, rye, rxj, ryj;            // patch, last substep: coarse lam (fold)
+  float xen, xeo, yen, yeo;            // E leaving / entering
+  float a00, a10, a01;                 // lam acc at the end nodes
+  float n00, n10, n01;                 // density at the end nodes
+  float mx[7], my[7];                  // base: the Mur partner edges
+  float dx[13], dy[13];                // patch: E entering on the filter's diamond
+  float c1x[4], c2x[4], c1y[4], c2y[4];  // base: patch g for Eq. (5b) transposed
+};
+
 template <bool FINE>
-__device__ inline void adj_p1(const AdjEMArgs& A, const Reg& g, int i, int j, float& gx,
-                              float& kx, float& gy, float& ky, float& px, float& py) {
+__device__ inline void p1_load(const AdjEMArgs& A, const Reg& g, int i, int j, P1In& v) {
   const int L = A.L, R = A.R, B = A.B, T = A.T;
-  const LamIn<FINE> in{A, g};
-  auto ex_ok = [=](int a, int b) { return g.ex(a, b); };
-  auto ey_ok = [=](int a, int b) { return g.ey(a, b); };
-  // Mur partners (own edge where there is none: a cache hit, never used)
-  const int jb = (j == B + 1) ? B : (j == T - 1 ? T : j);
-  const int ib = (i == L + 1) ? L : (i == R - 1 ? R : i);
-  // -- loads --
-  float xle, xlj, yle, ylj;
-  in.template ej<true>(i, j, xle, xlj);
-  in.template ej<false>(i, j, yle, ylj);
-  const float xen = g.ld(A.exo, i, j), xeo = g.ld(A.exi, i, j);
-  const float xa0 = g.ld(A.lacc, i, j), xa1 = g.ld(A.lacc, i + 1, j);
-  const float n00 = g.ld(A.n, i, j), n10 = g.ld(A.n, i + 1, j), n01 = g.ld(A.n, i, j + 1);
-  const float yen = g.ld(A.eyo, i, j), yeo = g.ld(A.eyi, i, j);
-  const float ya1 = g.ld(A.lacc, i, j + 1);
-  float mx[7] = {0, 0, 0, 0, 0, 0, 0}, my[7] = {0, 0, 0, 0, 0, 0, 0};
-  float dx[13], dy[13];
-  float s1x = 0.f, s2x = 0.f, s1y = 0.f, s2y = 0.f;
-  if constexpr (!FINE) {
-    mx[0] = g.ld(A.lex, i, jb); mx[1] = g.ld(A.exo, i, jb); mx[2] = g.ld(A.lacc, i, jb);
-    mx[3] = g.ld(A.lacc, i + 1, jb); mx[4] = g.ld(A.n, i, jb); mx[5] = g.ld(A.n, i + 1, jb);
-    mx[6] = g.ld(A.ljx, i, jb);
-    my[0] = g.ld(A.ley, ib, j); my[1] = g.ld(A.eyo, ib, j); my[2] = g.ld(A.lacc, ib, j);
-    my[3] = g.ld(A.lacc, ib, j + 1); my[4] = g.ld(A.n, ib, j); my[5] = g.ld(A.n, ib, j + 1);
-    my[6] = g.ld(A.ljy, ib, j);
+  v.xle = g.ld(A.lex, i, j); v.xlj = g.ld(A.ljx, i, j);
+  v.yle = g.ld(A.ley, i, j); v.ylj = g.ld(A.ljy, i, j);
+  v.xen = g.ld(A.exo, i, j); v.xeo = g.ld(A.exi, i, j);
+  v.yen = g.ld(A.eyo, i, j); v.yeo = g.ld(A.eyi, i, j);
+  v.a00 = g.ld(A.lacc, i, j); v.a10 = g.ld(A.lacc, i + 1, j); v.a01 = g.ld(A.lacc, i, j + 1);
+  v.n00 = g.ld(A.n, i, j); v.n10 = g.ld(A.n, i + 1, j); v.n01 = g.ld(A.n, i, j + 1);
+  if constexpr (FINE) {
+    auto ex_ok = [=](int a, int b) { return g.ex(a, b); };
+    auto ey_ok = [=](int a, int b) { return g.ey(a, b); };
+    load13<decltype(ex_ok)>(g, A.exi, i, j, v.dx);
+    load13<decltype(ey_ok)>(g, A.eyi, i, j, v.dy);
+    v.rxe = v.rye = v.rxj = v.ryj = 0.f;
+    if (A.rex) {
+      const size_t c = coarse_of(A, g, i, j);
+      v.rxe = A.rex[c]; v.rye = A.rey[c]; v.rxj = A.rjx[c]; v.ryj = A.rjy[c];
+    }
+  } else {
+    // Mur partners (own edge where there is none: a cache hit, never used)
+    const int jb = (j == B + 1) ? B : (j == T - 1 ? T : j);
+    const int ib = (i == L + 1) ? L : (i == R - 1 ? R : i);
+    v.mx[0] = g.ld(A.lex, i, jb); v.mx[1] = g.ld(A.exo, i, jb); v.mx[2] = g.ld(A.lacc, i, jb);
+    v.mx[3] = g.ld(A.lacc, i + 1, jb); v.mx[4] = g.ld(A.n, i, jb); v.mx[5] = g.ld(A.n, i + 1, jb);
+    v.mx[6] = g.ld(A.ljx, i, jb);
+    v.my[0] = g.ld(A.ley, ib, j); v.my[1] = g.ld(A.eyo, ib, j); v.my[2] = g.ld(A.lacc, ib, j);
+    v.my[3] = g.ld(A.lacc, ib, j + 1); v.my[4] = g.ld(A.n, ib, j); v.my[5] = g.ld(A.n, ib, j + 1);
+    v.my[6] = g.ld(A.ljy, ib, j);
     if (A.has_patch) {
-      s1x = cfb_sum<true>(A, A.g1x, i, j); s2x = cfb_sum<true>(A, A.g2x, i, j);
-      s1y = cfb_sum<false>(A, A.g1y, i, j); s2y = cfb_sum<false>(A, A.g2y, i, j);
-    }
-  } else {
-    load13<decltype(ex_ok)>(g, A.exi, i, j, dx);
-    load13<decltype(ey_ok)>(g, A.eyi, i, j, dy);
-  }
-  // -- compute --
-  // Eq. (5b) in time: substep m takes frac m/2 of E^{n+1}, 1 - m/2 of E^n
-  if constexpr (!FINE) {
-    xle = (xle + 1.f * s2x) + 0.5f * s1x;
-    yle = (yle + 1.f * s2y) + 0.5f * s1y;
-    px = (0.f + 0.f * s2x) + 0.5f * s1x;
-    py = (0.f + 0.f * s2y) + 0.5f * s1y;
-  } else {
-    px = 0.f; py = 0.f;
-  }
-  auto kapf = [&](float a, float b) { return A.kn * (0.5f * (a + b)); };
-  gx = 0.f; kx = 0.f; gy = 0.f; ky = 0.f;
-  if (ex_ok(i, j)) {
-    const float kap = kapf(n00, n10);
-    const bool bnd = (j == B || j == T);
-    float eo = xeo;
-    if (FINE && A.gamma > 0.f && !bnd) eo -= A.gamma * ll13(dx, i, j, ex_ok);
-    // own lam plus the window: acc at both end nodes (1/2 where a node has two x-edges)
-    float tot = xle + 2.f * xen * (wwin(i, L, R) * xa0 + wwin(i + 1, L, R) * xa1);
-    if (!bnd) {
-      if (!FINE && A.bc_y == kBcMur && (j == B + 1 || j == T - 1)) {
-        const float ab = mx[0] + 2.f * mx[1] * (wwin(i, L, R) * mx[2] + wwin(i + 1, L, R) * mx[3]);
-        tot += A.cmur * (ab + 2.f * kapf(mx[4], mx[5]) * mx[6]);
-      }
-      gx = (tot + 2.f * kap * xlj) / (1.f + kap);
-      kx = (eo + xen) * (2.f * xlj - gx);
-    } else {
-      gx = tot + 2.f * kap * xlj;
-      kx = 2.f * (eo + xen) * xlj;
-    }
-  }
-  if (ey_ok(i, j)) {
-    const float kap = kapf(n00, n01);
-    const bool bnd = (i == L || i == R);
-    float eo = yeo;
-    if (FINE && A.gamma > 0.f && !bnd) eo -= A.gamma * ll13(dy, i, j, ey_ok);
-    float tot = yle + 2.f * yen * (wwin(j, B, T) * xa0 + wwin(j + 1, B, T) * ya1);
-    if (!bnd) {
-      if (!FINE && A.bc_x == kBcMur && (i == L + 1 || i == R - 1)) {
-        const float ab = my[0] + 2.f * my[1] * (wwin(j, B, T) * my[2] + wwin(j + 1, B, T) * my[3]);
-        tot += A.cmur * (ab + 2.f * kapf(my[4], my[5]) * my[6]);
-      }
-      gy = (tot + 2.f * kap * ylj) / (1.f + kap);
-      ky = (eo + yen) * (2.f * ylj - gy);
-    } else {
-      gy = tot + 2.f * kap * ylj;
-      ky = 2.f * (eo + yen) * ylj;
+      cfb_load<true>(A, A.g1x, i, j, v.c1x); cfb_load<true>(A, A.g2x, i, j, v.c2x);
+      cfb_load<false>(A, A.g1y, i, j, v.c1y); cfb_load<false>(A, A.g2y, i, j, v.c2y);
     }
   }
 }
 
-template <bool FINE, int NT>
-__global__ __launch_bounds__(NT) void k_adj_em(AdjEMArgs A) {
-  constexpr int H1 = FINE ? 3 : 1, H2 = FINE ? 2 : 0;
-  constexpr int W1 = kAdjTX + 2 * H1, N1 = kAdjTY + 2 * H1;
-  constexpr int W2 = kAdjTX + 2 * H2, N2 = kAdjTY + 2 * H2;
+// phase 1 at position (i, j): g and lam k of x-edge (i, j) and y-edge (i, j)
+// (zero where the edge does not exist); base level: px, py = the lam of the
+// coarse E entering the step from Eq. (5b)
+template <bool FINE>
+__device__ inline void p1_compute(const AdjEMArgs& A, const Reg& g, int i, int j, P1In& v,
+                                  float& gx, float& kx, float& gy, float& ky, float& px,
+                                  float& py) {
+  const int L = A.L, R = A.R, B = A.B, T = A.T;
+  auto ex_ok = [=](int a, int b) { return g.ex(a, b); };
+  auto ey_ok = [=](int a, int b) { return g.ey(a, b); };
+  float xle = v.xle, xlj = v.xlj, yle = v.yle, ylj = v.ylj;
+  px = 0.f; py = 0.f;
+  if constexpr (FINE) {
+    if (A.rex) {
+      if (fold_edge<true>(A, i, j)) { xle += 0.5f * v.rxe; xlj += v.rxj; }
+      if (fold_edge<false>(A, i, j)) { yle += 0.5f * v.rye; ylj += v.ryj; }
+    }
+  } else {
+    if (inside_ex(A, i, j)) { xle = 0.f; xlj = 0.f; }
+    if (inside_ey(A, i, j)) { yle = 0.f; ylj = 0.f; }
+    if (A.has_patch) {
+      // Eq. (5b) in time: substep m takes m/2 of E^{n+1} and 1 - m/2 of E^n
+      const float s1x = cfb_sum<true>(A, v.c1x, i, j), s2x = cfb_sum<true>(A, v.c2x, i, j);
+      const float s1y = cfb_sum<false>(A, v.c1y, i, j), s2y = cfb_sum<false>(A, v.c2y, i, j);
+      xle = (xle + 1.f * s2x) + 0.5f * s1x;
+      yle = (yle + 1.f * s2y) + 0.5f * s1y;
+      px = (0.f + 0.f * s2x) + 0.5f * s1x;
+      py = (0.f + 0.f * s2y) + 0.5f * s1y;
+    }
+  }
+  auto kapf = [&](float a, float b) { return A.kn * (0.5f * (a + b)); };
+  gx = 0.f; kx = 0.f; gy = 0.f; ky = 0.f;
+  if (ex_ok(i, j)) {
+    const float kap = kapf(v.n00, v.n10);
+    const bool bnd = (j == B || j == T);
+    float eo = v.xeo;
+    if (FINE && A.gamma > 0.f && !bnd) eo -= A.gamma * ll13(v.dx, i, j, ex_ok);
+    // own lam plus the window: acc at both end nodes (1/2 where a node has two x-edges)
+    float tot = xle + 2.f * v.xen * (wwin(i, L, R) * v.a00 + wwin(i + 1, L, R) * v.a10);
+    if (!bnd) {
+      if (!FINE && A.bc_y == kBcMur && (j == B + 1 || j == T - 1)) {
+        const float* m = v.mx;
+        const float ab = m[0] + 2.f * m[1] * (wwin(i, L, R) * m[2] + wwin(i + 1, L, R) * m[3]);
+        tot += A.cmur * (ab + 2.f * kapf(m[4], m[5]) * m[6]);
+      }
+      gx = (tot + 2.f * kap * xlj) / (1.f + kap);
+      kx = (eo + v.xen) * (2.f * xlj - gx);
+    } else {
+      gx = tot + 2.f * kap * xlj;
+      kx = 2.f * (eo + v.xen) * xlj;
+    }
+  }
+  if (ey_ok(i, j)) {
+    const float kap = kapf(v.n00, v.n01);
+    const bool bnd = (i == L || i == R);
+    float eo = v.yeo;
+    if (FINE && A.gamma > 0.f && !bnd) eo -= A.gamma * ll13(v.dy, i, j, ey_ok);
+    float tot = yle + 2.f * v.yen * (wwin(j, B, T) * v.a00 + wwin(j + 1, B, T) * v.a01);
+    if (!bnd) {
+      if (!FINE && A.bc_x == kBcMur && (i == L + 1 || i == R - 1)) {
+        const float* m = v.my;
+        const float ab = m[0] + 2.f * m[1] * (wwin(j, B, T) * m[2] + wwin(j + 1, B, T) * m[3]);
+        tot += A.cmur * (ab + 2.f * kapf(m[4], m[5]) * m[6]);
+      }
+      gy = (tot + 2.f * kap * ylj) / (1.f + kap);
+      ky = (eo + v.yen) * (2.f * ylj - gy);
+    } else {
+      gy = tot + 2.f * kap * ylj;
+      ky = 2.f * (eo + v.yen) * ylj;
+    }
+  }
+}
+
+// values phase 2 needs at position (i, j)
+struct P2In {
+  float h00, h0m, hm0;     // lam Hz leaving at cells (i,j), (i,j-1), (i-1,j)
+  float r00, r0m, rm0;     // patch, last substep: coarse lam Hz of those cells (fold)
+  float ljx, ljy, rjx, rjy;
+  float n00, n10, n01, ln0, hxv;
+};
+
+template <bool FINE>
+__device__ inline void p2_load(const AdjEMArgs& A, const Reg& g, int i, int j, P2In& v) {
+  v.h00 = g.ld(A.lhz_in, i, j); v.h0m = g.ld(A.lhz_in, i, j - 1); v.hm0 = g.ld(A.lhz_in, i - 1, j);
+  v.ljx = g.ld(A.ljx, i, j); v.ljy = g.ld(A.ljy, i, j);
+  v.n00 = g.ld(A.n, i, j); v.n10 = g.ld(A.n, i + 1, j); v.n01 = g.ld(A.n, i, j + 1);
+  v.ln0 = g.ld(A.ln, i, j);
+  v.r00 = v.r0m = v.rm0 = v.rjx = v.rjy = v.hxv = 0.f;
+  if constexpr (FINE) {
+    if (A.rhz) {
+      v.r00 = A.rhz[coarse_of(A, g, i, j)];
+      v.r0m = A.rhz[coarse_of(A, g, i, j - 1)];
+      v.rm0 = A.rhz[coarse_of(A, g, i - 1, j)];
+      const size_t c = coarse_of(A, g, i, j);
+      v.rjx = A.rjx[c]; v.rjy = A.rjy[c];
+    }
+  } else {
+    if (A.hz_extra) v.hxv = g.ld(A.hz_extra, i, j);
+  }
+}
+
+template <bool FINE>
+__global__ __launch_bounds__(AdjTile<FINE>::NT) void k_adj_em(AdjEMArgs A) {
+  using Tl = AdjTile<FINE>;
+  constexpr int TX = Tl::TX, TY = Tl::TY, H1 = Tl::H1, H2 = Tl::H2;
+  constexpr int W1 = Tl::W1, N1 = Tl::N1, W2 = Tl::W2, N2 = Tl::N2;
   __shared__ float sgx[N1][W1], sgy[N1][W1], skx[N1][W1], sky[N1][W1];
   __shared__ float spx[FINE ? 1 : N1][FINE ? 1 : W1], spy[FINE ? 1 : N1][FINE ? 1 : W1];
   __shared__ float stx[FINE ? N2 : 1][FINE ? W2 : 1], sty[FINE ? N2 : 1][FINE ? W2 : 1];
   const Reg g{A.L, A.B, A.R, A.T, A.pitch};
-  const LamIn<FINE> in{A, g};
   const int L = A.L, R = A.R, B = A.B, T = A.T;
-  const int i0 = L + blockIdx.x * kAdjTX, j0 = B + blockIdx.y * kAdjTY;
+  const int i0 = L + blockIdx.x * TX, j0 = B + blockIdx.y * TY;
   const int tid = threadIdx.x;
   const float S = A.S;
   const bool filt = FINE && A.gamma > 0.f;
 
-  // -- phase 1 ----------------------------------------------------------------
-  for (int k = tid; k < N1 * W1; k += NT) {
-    const int ci = k % W1, cj = k / W1;
+  // this thread's positions: phase 1 (tile grown by H1), phase 2 (by H2)
+  const bool a1 = tid < N1 * W1, a2 = tid < N2 * W2;
+  const int c1i = a1 ? tid % W1 : 0, c1j = a1 ? tid / W1 : 0;
+  const int c2i = a2 ? tid % W2 : 0, c2j = a2 ? tid / W2 : 0;
+  const int i1 = i0 - H1 + c1i, j1 = j0 - H1 + c1j;
+  const int i = i0 - H2 + c2i, j = j0 - H2 + c2j;
+
+  // -- every load of both phases ------------------------------------------------
+  P1In v1;
+  p1_load<FINE>(A, g, i1, j1, v1);
+  P2In v2;
+  p2_load<FINE>(A, g, i, j, v2);
+
+  // -- phase 1 --------------------------------------------------------------------
+  if (a1) {
     float gx, kx, gy, ky, px, py;
-    adj_p1<FINE>(A, g, i0 - H1 + ci, j0 - H1 + cj, gx, kx, gy, ky, px, py);
-    sgx[cj][ci] = gx; skx[cj][ci] = kx;
-    sgy[cj][ci] = gy; sky[cj][ci] = ky;
-    if constexpr (!FINE) { spx[cj][ci] = px; spy[cj][ci] = py; }
+    p1_compute<FINE>(A, g, i1, j1, v1, gx, kx, gy, ky, px, py);
+    sgx[c1j][c1i] = gx; skx[c1j][c1i] = kx;
+    sgy[c1j][c1i] = gy; sky[c1j][c1i] = ky;
+    if constexpr (!FINE) { spx[c1j][c1i] = px; spy[c1j][c1i] = py; }
   }
   __syncthreads();
   auto GX = [&](int a, int b) { return sgx[b - j0 + H1][a - i0 + H1]; };
@@ -297,27 +363,26 @@ __global__ __launch_bounds__(NT) void k_adj_em(AdjEMArgs A) {
   auto KX = [&](int a, int b) { return skx[b - j0 + H1][a - i0 + H1]; };
   auto KY = [&](int a, int b) { return sky[b - j0 + H1][a - i0 + H1]; };
 
-  // -- phase 2 ----------------------------------------------------------------
-  for (int k = tid; k < N2 * W2; k += NT) {
-    const int ci = k % W2, cj = k / W2;
-    const int i = i0 - H2 + ci, j = j0 - H2 + cj;
-    const bool own = ci >= H2 && ci < H2 + kAdjTX && cj >= H2 && cj < H2 + kAdjTY &&
-                     i <= R && j <= T;
-    // loads (clamped)
-    const float h00 = in.hz(i, j), h0m = in.hz(i, j - 1), hm0 = in.hz(i - 1, j);
-    float lex_, ljx, ley_, ljy;
-    in.template ej<true>(i, j, lex_, ljx);
-    in.template ej<false>(i, j, ley_, ljy);
-    const float n00 = g.ld(A.n, i, j), n10 = g.ld(A.n, i + 1, j), n01 = g.ld(A.n, i, j + 1);
-    const float ln0 = g.ld(A.ln, i, j);
-    float hxv = 0.f;
-    if constexpr (FINE) {
-      if (A.rhz) hxv = 0.125f * A.rhz[in.co(i, j)];
-    } else {
-      if (A.hz_extra) hxv = g.ld(A.hz_extra, i, j);
-    }
+  // -- phase 2 --------------------------------------------------------------------
+  if (a2) {
+    const bool own = c2i >= H2 && c2i < H2 + TX && c2j >= H2 && c2j < H2 + TY && i <= R && j <= T;
+    float h00 = v2.h00, h0m = v2.h0m, hm0 = v2.hm0, ljx = v2.ljx, ljy = v2.ljy, hxv = v2.hxv;
     float pxv = 0.f, pyv = 0.f;
-    if constexpr (!FINE) {
+    if constexpr (FINE) {
+      if (A.rhz) {
+        h00 = h00 + 0.125f * v2.r00;
+        h0m = h0m + 0.125f * v2.r0m;
+        hm0 = hm0 + 0.125f * v2.rm0;
+        hxv = 0.125f * v2.r00;
+        if (fold_edge<true>(A, i, j)) ljx += v2.rjx;
+        if (fold_edge<false>(A, i, j)) ljy += v2.rjy;
+      }
+    } else {
+      if (inside_hz(A, i, j)) h00 = 0.f;
+      if (inside_hz(A, i, j - 1)) h0m = 0.f;
+      if (inside_hz(A, i - 1, j)) hm0 = 0.f;
+      if (inside_ex(A, i, j)) ljx = 0.f;
+      if (inside_ey(A, i, j)) ljy = 0.f;
       pxv = spx[j - j0 + H1][i - i0 + H1];
       pyv = spy[j - j0 + H1][i - i0 + H1];
     }
@@ -337,7 +402,7 @@ __global__ __launch_bounds__(NT) void k_adj_em(AdjEMArgs A) {
     }
     if (g.ex(i, j)) {
       const float gxv = GX(i, j);
-      const float kap = A.kn * (0.5f * (n00 + n10));
+      const float kap = A.kn * (0.5f * (v2.n00 + v2.n10));
       float le = (g.hz(i, j - 1) ? S * hc0m : 0.f) - (g.hz(i, j) ? S * hc00 : 0.f);
       const bool bnd = (j == B || j == T);
       float ljn;
@@ -363,7 +428,7 @@ __global__ __launch_bounds__(NT) void k_adj_em(AdjEMArgs A) {
     }
     if (g.ey(i, j)) {
       const float gyv = GY(i, j);
-      const float kap = A.kn * (0.5f * (n00 + n01));
+      const float kap = A.kn * (0.5f * (v2.n00 + v2.n01));
       float le = (g.hz(i, j) ? S * hc00 : 0.f) - (g.hz(i - 1, j) ? S * hcm0 : 0.f);
       const bool bnd = (i == L || i == R);
       float ljn;
@@ -388,7 +453,6 @@ __global__ __launch_bounds__(NT) void k_adj_em(AdjEMArgs A) {
         if (FINE) A.gy[o] = gyv;
       }
     }
-    (void)lex_; (void)ley_;
     if (own) {
       // node: k of the (up to four) edges that average this node's density
       float sk = 0.f;
@@ -396,41 +460,40 @@ __global__ __launch_bounds__(NT) void k_adj_em(AdjEMArgs A) {
       if (g.ex(i, j)) sk += KX(i, j);
       if (g.ey(i, j - 1)) sk += KY(i, j - 1);
       if (g.ey(i, j)) sk += KY(i, j);
-      A.ln[o] = ln0 + 0.5f * A.kn * sk;
+      A.ln[o] = v2.ln0 + 0.5f * A.kn * sk;
     }
     if constexpr (FINE) {
-      stx[cj][ci] = tex;
-      sty[cj][ci] = tey;
+      stx[c2j][c2i] = tex;
+      sty[c2j][c2i] = tey;
     }
   }
 
-  // -- phase 3 (patch): E filter transposed -------------------------------------
+  // -- phase 3 (patch): E filter transposed ---------------------------------------
   if constexpr (FINE) {
     if (!filt) return;
     __syncthreads();
     auto ex_ok = [=](int a, int b) { return g.ex(a, b); };
     auto ey_ok = [=](int a, int b) { return g.ey(a, b); };
-    for (int k = tid; k < kAdjTX * kAdjTY; k += NT) {
-      const int i = i0 + k % kAdjTX, j = j0 + k / kAdjTX;
-      if (i > R || j > T) continue;
-      // P lam E~ on the diamond: only filtered edges (not the boundary ones)
-      float tx[13], ty[13];
+    if (tid >= TX * TY) return;
+    const int ii = i0 + tid % TX, jj = j0 + tid / TX;
+    if (ii > R || jj > T) return;
+    // P lam E~ on the diamond: only filtered edges (not the boundary ones)
+    float tx[13], ty[13];
 #pragma unroll
-      for (int b = -2; b <= 2; b++)
+    for (int b = -2; b <= 2; b++)
 #pragma unroll
-        for (int a = -2; a <= 2; a++)
-          if ((a < 0 ? -a : a) + (b < 0 ? -b : b) <= 2) {
-            const int q = dmd(a, b);
-            const float vx = stx[j - j0 + H2 + b][i - i0 + H2 + a];
-            const float vy = sty[j - j0 + H2 + b][i - i0 + H2 + a];
-            tx[q] = (j + b == B || j + b == T) ? 0.f : vx;
-            ty[q] = (i + a == L || i + a == R) ? 0.f : vy;
-          }
-      const size_t o = g.o(i, j);
-      const float tex = stx[j - j0 + H2][i - i0 + H2], tey = sty[j - j0 + H2][i - i0 + H2];
-      if (g.ex(i, j)) A.lex_o[o] = tex - A.gamma * ll13(tx, i, j, ex_ok);
-      if (g.ey(i, j)) A.ley_o[o] = tey - A.gamma * ll13(ty, i, j, ey_ok);
-    }
+      for (int a = -2; a <= 2; a++)
+        if ((a < 0 ? -a : a) + (b < 0 ? -b : b) <= 2) {
+          const int q = dmd(a, b);
+          const float vx = stx[jj - j0 + H2 + b][ii - i0 + H2 + a];
+          const float vy = sty[jj - j0 + H2 + b][ii - i0 + H2 + a];
+          tx[q] = (jj + b == B || jj + b == T) ? 0.f : vx;
+          ty[q] = (ii + a == L || ii + a == R) ? 0.f : vy;
+        }
+    const size_t o = g.o(ii, jj);
+    const float tex = stx[jj - j0 + H2][ii - i0 + H2], tey = sty[jj - j0 + H2][ii - i0 + H2];
+    if (g.ex(ii, jj)) A.lex_o[o] = tex - A.gamma * ll13(tx, ii, jj, ex_ok);
+    if (g.ey(ii, jj)) A.ley_o[o] = tey - A.gamma * ll13(ty, ii, jj, ey_ok);
   }
 }
 
@@ -782,9 +845,15 @@ dim3 node_grid(int L, int B, int R, int T) {
 }  // namespace
 
 hipError_t launch_adj_em(const AdjEMArgs& A, hipStream_t st) {
-  const dim3 g((A.R - A.L + kAdjTX) / kAdjTX, (A.T - A.B + kAdjTY) / kAdjTY);
-  if (A.fine) k_adj_em<true, 1024><<<g, 1024, 0, st>>>(A);
-  else k_adj_em<false, 512><<<g, 512, 0, st>>>(A);
+  if (A.fine) {
+    using Tl = AdjTile<true>;
+    const dim3 g((A.R - A.L + Tl::TX) / Tl::TX, (A.T - A.B + Tl::TY) / Tl::TY);
+    k_adj_em<true><<<g, Tl::NT, 0, st>>>(A);
+  } else {
+    using Tl = AdjTile<false>;
+    const dim3 g((A.R - A.L + Tl::TX) / Tl::TX, (A.T - A.B + Tl::TY) / Tl::TY);
+    k_adj_em<false><<<g, Tl::NT, 0, st>>>(A);
+  }
   return hipGetLastError();
 }
 

@@ -562,7 +562,9 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
   make_base_em(s, c, s->ncur, &A);
   incident_values(s, s->step, &A.ey_src, &A.hz_src);
   hipError_t e = hipSuccess;
-  const bool combined = s->has_patch && s->combine && s->fuse_fine && !cx;
+  // the fused forms are bit-identical to the separate launches; a replay
+  // that stores per-step values takes the separate ones
+  const bool combined = s->has_patch && s->combine && s->fuse_fine && !st;
   if (combined) {  // base step and both patch substeps, one launch
     Level &C = s->L0, &F = s->L1;
     A.skip_on = 1;
@@ -598,7 +600,7 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
   }
   if (combined) {
     // done above
-  } else if (s->has_patch && s->fuse_fine && !cx) {  // both substeps, one launch
+  } else if (s->has_patch && s->fuse_fine && !st) {  // both substeps, one launch
     Level& F = s->L1;
     EMArgs G;
     make_fine_em(s, p.r, c, s->ncur, s->ty1, &G);  // restriction targets
