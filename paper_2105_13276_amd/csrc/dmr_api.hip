@@ -544,7 +544,10 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
     cx->meta.has = s->has_patch;
     for (int q = 0; q < 4; q++) cx->meta.ext[q] = s->ext[q];
   }
-  if (st) {
+  // replay: the fused kernels store the step's values themselves; the
+  // one-substep form takes copies
+  const bool kst = st && (!s->has_patch || s->fuse_fine);
+  if (st && !kst) {
     CopyJobs J{};
     const size_t n0 = s->L0.plane;
     job(&J, s->L0.ex[c], cx->ss.cexi, n0);
@@ -562,9 +565,20 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
   make_base_em(s, c, s->ncur, &A);
   incident_values(s, s->step, &A.ey_src, &A.hz_src);
   hipError_t e = hipSuccess;
-  // the fused forms are bit-identical to the separate launches; a replay
-  // that stores per-step values takes the separate ones
-  const bool combined = s->has_patch && s->combine && s->fuse_fine && !st;
+  if (kst) {
+    A.stix = cx->ss.cexi; A.stiy = cx->ss.ceyi;
+    A.stox = cx->ss.cexp; A.stoy = cx->ss.ceyp; A.stn = cx->ss.cn;
+  }
+  auto fine_stores = [&](EMArgs* G) {
+    if (!kst) return;
+    G->st0x = cx->ss.fex0; G->st0y = cx->ss.fey0;
+    G->st1x = cx->ss.fex1; G->st1y = cx->ss.fey1;
+    G->st2x = cx->last ? cx->ss.fex2 : nullptr;
+    G->st2y = cx->last ? cx->ss.fey2 : nullptr;
+    G->stn = cx->ss.fn;
+  };
+  // the fused forms are bit-identical to the separate launches
+  const bool combined = s->has_patch && s->combine && s->fuse_fine;
   if (combined) {  // base step and both patch substeps, one launch
     Level &C = s->L0, &F = s->L1;
     A.skip_on = 1;
@@ -577,6 +591,7 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
     G.cS = C.S; G.cc1 = C.c1; G.ckn = C.kn; G.cis = p.tfsf_i;
     G.cey_src = A.ey_src; G.chz_src = A.hz_src;
     G.cnx = p.nx; G.cny = p.ny;
+    fine_stores(&G);
     ev_begin(s, 0);
     e = launch_dmr_step(A, G, s->seg0, s->depth0, s->ty1, s->st);
     ev_end(s);
@@ -592,7 +607,7 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
     ev_end(s);
     if (e != hipSuccess) return hipfail(s, e, "base EM launch");
   }
-  if (st && !s->has_patch) {  // with a patch: stored after substep 1
+  if (st && !kst && !s->has_patch) {  // with a patch: stored after substep 1
     CopyJobs J{};
     job(&J, s->L0.ex[1 - c], cx->ss.cexp, s->L0.plane);
     job(&J, s->L0.ey[1 - c], cx->ss.ceyp, s->L0.plane);
@@ -600,12 +615,13 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
   }
   if (combined) {
     // done above
-  } else if (s->has_patch && s->fuse_fine && !st) {  // both substeps, one launch
+  } else if (s->has_patch && s->fuse_fine) {  // both substeps, one launch
     Level& F = s->L1;
     EMArgs G;
     make_fine_em(s, p.r, c, s->ncur, s->ty1, &G);  // restriction targets
     em_args_level(&G, F, 0, 1, F.n[s->ncur], F.acc);
     G.frac = 1.f / (float)p.r;  // time fraction of substep 1
+    fine_stores(&G);
     ev_begin(s, 1);
     e = launch_fine2(G, s->ty1, s->nt1, s->st);
     ev_end(s);

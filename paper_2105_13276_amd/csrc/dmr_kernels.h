@@ -47,6 +47,13 @@ struct EMArgs {
   const float *chz0, *cjx0, *cjy0, *cn0;
   float cS, cc1, ckn, cey_src, chz_src;
   int cis, cnx, cny;
+  // replay for the adjoint (null: off): the step's values it needs, written
+  // at the entity's own position.  Base level: E entering (sti), E after the
+  // step before the fine -> coarse transfer (sto), n.  Patch (both
+  // substeps): E entering substep 1 (st0), after substep 1 (st1), after
+  // substep 2 (st2, nullable), n.
+  float *stix, *stiy, *stox, *stoy, *stn;
+  float *st0x, *st0y, *st1x, *st1y, *st2x, *st2y;
 };
 
 struct ContArgs {

@@ -471,7 +471,7 @@ __device__ __forceinline__ void bnd_src(int tid, int orig, int NW_, int NH_, int
 // (i0, j0):  raw E0 -7, L(E0) -6, filtered E0 and H1 -5, E1/J1 and n -4;
 // then as in fine_tile: L(E1) -3, filtered E1 and H2 -2, E2/J2 -1.
 // ---------------------------------------------------------------------------
-template <int TY, int NT, bool LOCAL>
+template <int TY, int NT, bool LOCAL, bool ST = false>
 __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
   constexpr int R1W = kTX + 13, R1H = TY + 13;
   constexpr int Q1W = kTX + 11, Q1H = TY + 11;
@@ -958,11 +958,32 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
       A.cjy[co] = j2Y[r][tx] + j2Y[r + 1][tx];
     }
   }
+
+  // replay for the adjoint: E entering (raw E0 at origin -7), after
+  // substep 1 (origin -4), after substep 2 (origin -1), n (origin -4)
+  if constexpr (ST) {
+    for (int r = ty; r < TY; r += RP) {
+      const int i = i0 + tx, j = j0 + r;
+      if (!nd_ok(i, j)) continue;
+      const size_t o = (size_t)j * pitch + i;
+      A.stn[o] = sN[r + 4][tx + 4];
+      if (ex_ok(i, j)) {
+        A.st0x[o] = rX[r + 7][tx + 7];
+        A.st1x[o] = e1X[r + 4][tx + 4];
+        if (A.st2x) A.st2x[o] = e2X[r + 1][tx + 1];
+      }
+      if (ey_ok(i, j)) {
+        A.st0y[o] = rY[r + 7][tx + 7];
+        A.st1y[o] = e1Y[r + 4][tx + 4];
+        if (A.st2y) A.st2y[o] = e2Y[r + 1][tx + 1];
+      }
+    }
+  }
 }
 
-template <int TY, int NT>
+template <int TY, int NT, bool ST = false>
 __global__ __launch_bounds__(NT) void k_fine2(EMArgs A) {
-  fine2_tile<TY, NT, false>(A, blockIdx.x, blockIdx.y);
+  fine2_tile<TY, NT, false, ST>(A, blockIdx.x, blockIdx.y);
 }
 
 
@@ -1312,7 +1333,7 @@ __device__ inline RowData mask_row(const EMArgs& A, const RowData& q, int i, int
   return r;
 }
 
-template <int DEPTH>
+template <int DEPTH, bool ST = false>
 __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, int seg,
                                                int nseg, float ey_src, float hz_src) {
   const int NX = A.R, NY = A.T;
@@ -1348,6 +1369,11 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, i
     const RowData nxt = mask_row(A, rn, i, j + 1);
     const bool store = j >= j0 && j < j1;
     const size_t o = (size_t)j * A.pitch + i;
+    if (ST && store && own) {  // replay: the values entering the step
+      if (exv) A.stix[o] = cur.ex;
+      if (eyc && j < NY) A.stiy[o] = cur.ey;
+      if (eyc) A.stn[o] = cur.n;
+    }
 
     // Faraday, Eq. (2)
     float hzn = 0.f;
@@ -1364,12 +1390,14 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, i
     if (exv) {
       if (j > 0 && j < NY) {
         exn = base_ex(cur.ex, kapx, S, hzn, hzn_p, c1, cur.jx);
+        if (ST && store && own) A.stox[o] = exn;
         if (store && own && !(skc && j > A.sB && j < A.sT)) {
           A.ex1[o] = exn;
           A.jx1[o] = a * cur.jx + 2.f * kapx * (cur.ex + exn);
         }
       } else if (j == NY) {
         exn = mur_y ? exo_p + cm * (exn_p - cur.ex) : 0.f;
+        if (ST && store && own) A.stox[o] = exn;
         if (store && own) {
           A.ex1[o] = exn;
           A.jx1[o] = a * cur.jx + 2.f * kapx * (cur.ex + exn);
@@ -1394,6 +1422,7 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, i
       if (i == 0) eyn = mur_x ? orr + cm * (nr - cur.ey) : 0.f;
       if (i == NX) eyn = mur_x ? ol + cm * (nl - cur.ey) : 0.f;
     }
+    if (ST && eyc && j < NY && store && own) A.stoy[o] = eyn;
     if (eyc && j < NY && store && own && !(sky && j >= A.sB && j < A.sT)) {
       A.ey1[o] = eyn;
       A.jy1[o] = a * cur.jy + 2.f * kapy * (cur.ey + eyn);
@@ -1405,6 +1434,7 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, i
       if (exv) {
         ex0 = mur_y ? cur.ex + cm * (exn - ex0_old) : 0.f;
         if (own) {
+          if (ST) A.stox[i] = ex0;
           A.ex1[i] = ex0;
           A.jx1[i] = a * jx0_old + 2.f * kap0 * (ex0_old + ex0);
         }
@@ -1465,10 +1495,10 @@ __device__ inline int xcd_band(int L, int N) {
   return x * q + min(x, r) + k;
 }
 
-template <int DEPTH>
+template <int DEPTH, bool ST = false>
 __global__ __launch_bounds__(kThreads) void k_em_stream(EMArgs A, int seg, int nseg, int nbx) {
   const int b = xcd_band(blockIdx.x, nbx * nseg);
-  em_stream_body<DEPTH>(A, (b % nbx) * (kThreads / 64) + (threadIdx.x >> 6), b / nbx, seg, nseg,
+  em_stream_body<DEPTH, ST>(A, (b % nbx) * (kThreads / 64) + (threadIdx.x >> 6), b / nbx, seg, nseg,
                         A.ey_src, A.hz_src);
 }
 
@@ -1494,18 +1524,18 @@ __global__ __launch_bounds__(kThreads) void k_em_stream_batch(const EMArgs* __re
 // the step on their boundary lines themselves.  The base waves do not store
 // the coarse entities the tiles' fine -> coarse transfer writes.
 // ---------------------------------------------------------------------------
-template <int DEPTH, int TY>
+template <int DEPTH, int TY, bool ST = false>
 __global__ __launch_bounds__(kFineThreads) void k_dmr_step(EMArgs C, EMArgs F, int seg, int nseg,
                                                            int waves_x, int ncb, int nbx_f) {
   const int b = blockIdx.x;
   if (b < ncb) {
     const int w = xcd_band(b, ncb) * (kFineThreads / 64) + (threadIdx.x >> 6);
     const int k = w / waves_x;
-    if (k < nseg) em_stream_body<DEPTH>(C, w % waves_x, k, seg, nseg, C.ey_src, C.hz_src);
+    if (k < nseg) em_stream_body<DEPTH, ST>(C, w % waves_x, k, seg, nseg, C.ey_src, C.hz_src);
     return;
   }
   const int t = b - ncb;
-  fine2_tile<TY, kFineThreads, true>(F, t % nbx_f, t / nbx_f);
+  fine2_tile<TY, kFineThreads, true, ST>(F, t % nbx_f, t / nbx_f);
 }
 
 // ---- host-side launchers ----------------------------------------------------
@@ -1515,6 +1545,12 @@ __global__ __launch_bounds__(kFineThreads) void k_dmr_step(EMArgs C, EMArgs F, i
     const dim3 g_((A.R - A.L + 1 + kTX - 1) / kTX, (A.T - A.B + 1 + (TY_)-1) / (TY_));  \
     if ((nt) >= 1024) hipLaunchKernelGGL((KERNEL<TY_, 1024>), g_, dim3(1024), 0, st, A); \
     else hipLaunchKernelGGL((KERNEL<TY_, 256>), g_, dim3(256), 0, st, A);                \
+  } while (0)
+// the replay form (stores for the adjoint), 1024 threads
+#define DMR_LAUNCH_TILE_ST(KERNEL, TY_, A, st)                                           \
+  do {                                                                                  \
+    const dim3 g_((A.R - A.L + 1 + kTX - 1) / kTX, (A.T - A.B + 1 + (TY_)-1) / (TY_));  \
+    hipLaunchKernelGGL((KERNEL<TY_, 1024, true>), g_, dim3(1024), 0, st, A);             \
   } while (0)
 
 hipError_t launch_em(const EMArgs& A, bool fine, int ty, int nt, hipStream_t st) {
@@ -1528,6 +1564,14 @@ hipError_t launch_em(const EMArgs& A, bool fine, int ty, int nt, hipStream_t st)
 }
 
 hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st) {
+  if (A.stn) {
+    switch (ty) {
+    case 4: DMR_LAUNCH_TILE_ST(k_fine2, 4, A, st); break;
+    case 8: DMR_LAUNCH_TILE_ST(k_fine2, 8, A, st); break;
+    default: DMR_LAUNCH_TILE_ST(k_fine2, 16, A, st); break;
+    }
+    return hipGetLastError();
+  }
   switch (ty) {
   case 4: DMR_LAUNCH_TILE(k_fine2, 4, nt, A, st); break;
   case 8: DMR_LAUNCH_TILE(k_fine2, 8, nt, A, st); break;
@@ -1546,12 +1590,20 @@ hipError_t launch_dmr_step(const EMArgs& C, const EMArgs& F, int seg, int depth,
   const int nby_f = (F.T - F.B + 1 + ty - 1) / ty;
   const dim3 g(ncb + nbx_f * nby_f), blk(kFineThreads);
 #define DMR_STEP(D, T_) hipLaunchKernelGGL((k_dmr_step<D, T_>), g, blk, 0, st, C, F, seg, nseg, waves_x, ncb, nbx_f)
-  if (depth >= 4) {
+#define DMR_STEP_ST(D, T_) hipLaunchKernelGGL((k_dmr_step<D, T_, true>), g, blk, 0, st, C, F, seg, nseg, waves_x, ncb, nbx_f)
+  if (C.stix) {  // replay: stores for the adjoint
+    if (depth >= 4) {
+      if (ty == 4) DMR_STEP_ST(4, 4); else if (ty == 8) DMR_STEP_ST(4, 8); else DMR_STEP_ST(4, 16);
+    } else {
+      if (ty == 4) DMR_STEP_ST(2, 4); else if (ty == 8) DMR_STEP_ST(2, 8); else DMR_STEP_ST(2, 16);
+    }
+  } else if (depth >= 4) {
     if (ty == 4) DMR_STEP(4, 4); else if (ty == 8) DMR_STEP(4, 8); else DMR_STEP(4, 16);
   } else {
     if (ty == 4) DMR_STEP(2, 4); else if (ty == 8) DMR_STEP(2, 8); else DMR_STEP(2, 16);
   }
 #undef DMR_STEP
+#undef DMR_STEP_ST
   return hipGetLastError();
 }
 
@@ -1595,8 +1647,14 @@ hipError_t launch_em_stream(const EMArgs& A, int seg, int depth, hipStream_t st)
   const int nseg = stream_segments(A.T, seg);
   const int nbx = (waves + kThreads / 64 - 1) / (kThreads / 64);
   dim3 g(nbx * nseg);
-  if (depth >= 4) hipLaunchKernelGGL(k_em_stream<4>, g, dim3(kThreads), 0, st, A, seg, nseg, nbx);
-  else hipLaunchKernelGGL(k_em_stream<2>, g, dim3(kThreads), 0, st, A, seg, nseg, nbx);
+  if (A.stix) {  // replay: stores for the adjoint
+    if (depth >= 4) hipLaunchKernelGGL((k_em_stream<4, true>), g, dim3(kThreads), 0, st, A, seg, nseg, nbx);
+    else hipLaunchKernelGGL((k_em_stream<2, true>), g, dim3(kThreads), 0, st, A, seg, nseg, nbx);
+  } else if (depth >= 4) {
+    hipLaunchKernelGGL(k_em_stream<4>, g, dim3(kThreads), 0, st, A, seg, nseg, nbx);
+  } else {
+    hipLaunchKernelGGL(k_em_stream<2>, g, dim3(kThreads), 0, st, A, seg, nseg, nbx);
+  }
   return hipGetLastError();
 }
 
