@@ -184,8 +184,11 @@ struct P1In {
   float c1x[4], c2x[4], c1y[4], c2y[4];  // base: patch g for Eq. (5b) transposed
 };
 
+// mur / cfb: the block's phase-1 region reaches a Mur partner row or
+// column / a patch boundary line (uniform per block)
 template <bool FINE>
-__device__ inline void p1_load(const AdjEMArgs& A, const Reg& g, int i, int j, P1In& v) {
+__device__ inline void p1_load(const AdjEMArgs& A, const Reg& g, int i, int j, P1In& v,
+                               bool mur, bool cfb) {
   const int L = A.L, R = A.R, B = A.B, T = A.T;
   v.xle = g.ld(A.lex, i, j); v.xlj = g.ld(A.ljx, i, j);
   v.yle = g.ld(A.ley, i, j); v.ylj = g.ld(A.ljy, i, j);
@@ -204,16 +207,23 @@ __device__ inline void p1_load(const AdjEMArgs& A, const Reg& g, int i, int j, P
       v.rxe = A.rex[c]; v.rye = A.rey[c]; v.rxj = A.rjx[c]; v.ryj = A.rjy[c];
     }
   } else {
-    // Mur partners (own edge where there is none: a cache hit, never used)
-    const int jb = (j == B + 1) ? B : (j == T - 1 ? T : j);
-    const int ib = (i == L + 1) ? L : (i == R - 1 ? R : i);
-    v.mx[0] = g.ld(A.lex, i, jb); v.mx[1] = g.ld(A.exo, i, jb); v.mx[2] = g.ld(A.lacc, i, jb);
-    v.mx[3] = g.ld(A.lacc, i + 1, jb); v.mx[4] = g.ld(A.n, i, jb); v.mx[5] = g.ld(A.n, i + 1, jb);
-    v.mx[6] = g.ld(A.ljx, i, jb);
-    v.my[0] = g.ld(A.ley, ib, j); v.my[1] = g.ld(A.eyo, ib, j); v.my[2] = g.ld(A.lacc, ib, j);
-    v.my[3] = g.ld(A.lacc, ib, j + 1); v.my[4] = g.ld(A.n, ib, j); v.my[5] = g.ld(A.n, ib, j + 1);
-    v.my[6] = g.ld(A.ljy, ib, j);
-    if (A.has_patch) {
+    if (mur) {
+      // Mur partners (own edge where there is none: a cache hit, never used)
+      const int jb = (j == B + 1) ? B : (j == T - 1 ? T : j);
+      const int ib = (i == L + 1) ? L : (i == R - 1 ? R : i);
+      v.mx[0] = g.ld(A.lex, i, jb); v.mx[1] = g.ld(A.exo, i, jb); v.mx[2] = g.ld(A.lacc, i, jb);
+      v.mx[3] = g.ld(A.lacc, i + 1, jb); v.mx[4] = g.ld(A.n, i, jb); v.mx[5] = g.ld(A.n, i + 1, jb);
+      v.mx[6] = g.ld(A.ljx, i, jb);
+      v.my[0] = g.ld(A.ley, ib, j); v.my[1] = g.ld(A.eyo, ib, j); v.my[2] = g.ld(A.lacc, ib, j);
+      v.my[3] = g.ld(A.lacc, ib, j + 1); v.my[4] = g.ld(A.n, ib, j); v.my[5] = g.ld(A.n, ib, j + 1);
+      v.my[6] = g.ld(A.ljy, ib, j);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 7; q++) { v.mx[q] = 0.f; v.my[q] = 0.f; }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) { v.c1x[q] = v.c2x[q] = v.c1y[q] = v.c2y[q] = 0.f; }
+    if (cfb) {
       cfb_load<true>(A, A.g1x, i, j, v.c1x); cfb_load<true>(A, A.g2x, i, j, v.c2x);
       cfb_load<false>(A, A.g1y, i, j, v.c1y); cfb_load<false>(A, A.g2y, i, j, v.c2y);
     }
@@ -344,8 +354,18 @@ __global__ __launch_bounds__(AdjTile<FINE>::NT) void k_adj_em(AdjEMArgs A) {
   const int i = i0 - H2 + c2i, j = j0 - H2 + c2j;
 
   // -- every load of both phases ------------------------------------------------
+  // (block-uniform: Mur partner rows / columns, patch boundary lines)
+  const int rl = i0 - H1, rr = i0 + TX + H1 - 1, rb = j0 - H1, rt = j0 + TY + H1 - 1;
+  auto span = [](int lo, int hi, int a, int b) { return hi >= a && lo <= b; };
+  const bool mur = !FINE && (span(rb, rt, B + 1, B + 1) || span(rb, rt, T - 1, T - 1) ||
+                             span(rl, rr, L + 1, L + 1) || span(rl, rr, R - 1, R - 1));
+  const bool cfb = !FINE && A.has_patch &&
+                   (((span(rb, rt, A.J0, A.J0) || span(rb, rt, A.J1, A.J1)) &&
+                     span(rl, rr, A.I0 - 1, A.I1)) ||
+                    ((span(rl, rr, A.I0, A.I0) || span(rl, rr, A.I1, A.I1)) &&
+                     span(rb, rt, A.J0 - 1, A.J1)));
   P1In v1;
-  p1_load<FINE>(A, g, i1, j1, v1);
+  p1_load<FINE>(A, g, i1, j1, v1, mur, cfb);
   P2In v2;
   p2_load<FINE>(A, g, i, j, v2);
 
