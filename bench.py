@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 4096x2048 bandwidth-bound kernel measurement")
-    ap.add_argument("--cpu-steps", type=int, default=1024,
+    ap.add_argument("--cpu-steps", type=int, default=6400,
                     help="coarse steps of the oracle sample")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched 64-instance comparison")
@@ -328,6 +328,30 @@ def main():
             "dmr_s": wl_d, "uniform_fine_s": wl_u, "speedup": wl_u / wl_d,
             "dmr_mcell_updates_per_s": kl_d / wl_d / 1e6,
             "uniform_mcell_updates_per_s": kl_u / wl_u / 1e6}
+
+    # ---- the multi-seed large case: 8 seeds in the right third -------------
+    if not args.no_large:
+        log("config 2 (8 seeds, 4096x2048) DMR vs uniform-fine, one interval")
+        cfg_2 = W.config2(periods=4)
+        centres, peaks = W.config2_seed_layout(cfg_2)
+        sd_2 = W.seeds(cfg_2, centres, peaks)
+        s2d, w2d, k2d = run_case(B, cfg_2, sd_2, 1, INTERVAL, 0, False)
+        ext2 = s2d.patch()
+        s2d.close()
+        cfg_2u = W.config2_uniform(periods=4)
+        sd_2u = W.seeds(cfg_2u, centres, peaks)
+        s2u, w2u, k2u = run_case(B, cfg_2u, sd_2u, 1, 2 * INTERVAL, 0, False)
+        s2u.close()
+        area = (ext2[2] - ext2[0]) * (ext2[3] - ext2[1]) / float(cfg_2["nx"] * cfg_2["ny"])
+        out["config2_dmr_vs_uniform"] = {
+            "workload": "coarse 4096x2048 @ lambda/32 + r=2 patch (bounding box of 8 "
+                        "seeds in the right third, E_rms/E_bd = 1.5) vs uniform-fine "
+                        "8192x4096 @ lambda/64, 4 periods (256 coarse steps) from t = 0",
+            "patch": list(ext2), "patch_area_fraction": area,
+            "dmr_s": w2d, "uniform_fine_s": w2u, "speedup": w2u / w2d,
+            "speedup_bound_single_rectangle": 1.0 / (1.0 / 8.0 + area),
+            "dmr_mcell_updates_per_s": k2d / w2d / 1e6,
+            "uniform_mcell_updates_per_s": k2u / w2u / 1e6}
 
     # ---- batched form: 64 independent DMR runs (config-3 draw) -----------
     if not args.no_batch:

@@ -95,6 +95,11 @@ def config2(periods=2000):
     return make(4096, 2048, 32, "dynamic", periods, erms_over_ebd=1.5)
 
 
+def config2_uniform(periods=2000):
+    """The uniform-fine counterpart of config 2: 8192x4096 at lambda/64."""
+    return make(8192, 4096, 64, "uniform", periods, erms_over_ebd=1.5)
+
+
 # --- seeds ------------------------------------------------------------------
 def node_coords(nx, ny, dx):
     x = np.arange(nx + 1, dtype=np.float64) * dx
