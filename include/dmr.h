@@ -162,6 +162,28 @@ int dmr_write_field(dmr_sim *s, int field, int level, const float *src,
 /* Simulated time (s) and base steps taken. */
 int dmr_time(dmr_sim *s, double *t, int64_t *step);
 
+/* Checkpoint and restart of the explicit time stepping (Sec. II.B, III.C: the
+ * state at a base step is the fields of both levels, the density, the window
+ * and the patch extents).  A saved state is a 256-byte header (format tag,
+ * a hash of the parameters, step, window block count, patch) followed by the
+ * live planes: base level Hz at n+1/2 and n-1/2, Ex, Ey, Jx, Jy, n, acc, the
+ * 8 window slots; patch Hz, Ex, Ey, Jx, Jy, n, acc, 8 slots over the patch
+ * rows of the full-domain fine grid.
+ *   dmr_state_bytes  bytes of a saved state of this handle (fixed by its
+ *                    parameters).
+ *   dmr_save         writes the state of the handle after all queued work
+ *                    (synchronizes) to dst: host memory (dst_on_device = 0)
+ *                    or device memory, 256-byte aligned; caller-owned.
+ *   dmr_load         replaces the handle's state with one saved from a handle
+ *                    created with the same parameters (EINVAL otherwise, and
+ *                    for a buffer that is not a saved state); the next
+ *                    dmr_step continues from the saved step.  A recorded
+ *                    adjoint tape of the handle is invalidated.
+ * ENOMEM if bytes is below dmr_state_bytes. */
+int dmr_state_bytes(const dmr_sim *s, size_t *bytes);
+int dmr_save(dmr_sim *s, void *dst, size_t bytes, int dst_on_device);
+int dmr_load(dmr_sim *s, const void *src, size_t bytes, int src_on_device);
+
 /* Wait for queued work; returns DMR_EUNSTABLE if a continuity step saw a
  * non-finite density or window value, DMR_EHIP on a HIP error. */
 int dmr_sync(dmr_sim *s);

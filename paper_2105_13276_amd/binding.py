@@ -29,7 +29,7 @@ SYMBOLS = ["dmr_workspace_bytes", "dmr_create", "dmr_destroy", "dmr_step",
            "dmr_batch_instance", "dmr_batch_sync", "dmr_batch_config",
            "dmr_batch_set_config", "dmr_batch_destroy", "dmr_batch_last_error",
            "dmr_adjoint_tape_bytes", "dmr_forward_record", "dmr_backward",
-           "dmr_weighted_sum"]
+           "dmr_weighted_sum", "dmr_state_bytes", "dmr_save", "dmr_load"]
 
 
 class DmrParams(C.Structure):
@@ -104,6 +104,9 @@ def lib():
         L.dmr_forward_record.argtypes = [V, C.c_int64, C.c_int, V, C.c_size_t]
         L.dmr_backward.argtypes = [V, V, V, V, V, V, P(C.c_double)]
         L.dmr_weighted_sum.argtypes = [V, C.c_int, V, P(C.c_double)]
+        L.dmr_state_bytes.argtypes = [V, P(C.c_size_t)]
+        L.dmr_save.argtypes = [V, V, C.c_size_t, C.c_int]
+        L.dmr_load.argtypes = [V, V, C.c_size_t, C.c_int]
         _lib = L
     return _lib
 
@@ -141,6 +144,13 @@ def workspace_bytes(cfg: dict) -> int:
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _buffer(buf):
+    """(on device, pointer, bytes) of a numpy array or a torch tensor."""
+    if isinstance(buf, np.ndarray):
+        return 0, buf.ctypes.data_as(C.c_void_p), buf.nbytes
+    return (1 if buf.is_cuda else 0), C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()
 
 
 class _Handle:
@@ -193,6 +203,26 @@ class _Handle:
         st = C.c_int64()
         self._check(lib().dmr_time(self._h, C.byref(t), C.byref(st)), "dmr_time")
         return t.value, st.value
+
+    def state_bytes(self) -> int:
+        n = C.c_size_t()
+        self._check(lib().dmr_state_bytes(self._h, C.byref(n)), "dmr_state_bytes")
+        return n.value
+
+    def save(self, buf=None):
+        """Checkpoint of the state: into `buf` (a host numpy uint8 array or a
+        256-byte aligned CUDA uint8 tensor of state_bytes()) or a new host
+        array, which is returned."""
+        if buf is None:
+            buf = np.empty(self.state_bytes(), np.uint8)
+        dev, ptr, n = _buffer(buf)
+        self._check(lib().dmr_save(self._h, ptr, n, dev), "dmr_save")
+        return buf
+
+    def load(self, buf):
+        """Restore a state saved from a handle with the same parameters."""
+        dev, ptr, n = _buffer(buf)
+        self._check(lib().dmr_load(self._h, ptr, n, dev), "dmr_load")
 
 
 class BatchInstance(_Handle):

@@ -1331,6 +1331,59 @@ int adj_step(dmr_sim* s, const TapeLayout& T, AdjLevel& ac, AdjLevel& af, int kk
   return DMR_OK;
 }
 
+// ---- state save / load (checkpoint and restart) -----------------------------
+// Layout: a 256-byte header, then the planes of one checkpoint (16 base-level
+// planes: Hz at n+1/2 and n-1/2, Ex, Ey, Jx, Jy, n, acc, 8 window slots; 15
+// patch planes: Hz, Ex, Ey, Jx, Jy, n, acc, 8 slots, of which only the
+// patch's rows are written).
+struct StateHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  uint64_t params_hash, total_bytes;
+  int64_t step, blocks;
+  int32_t has_patch, ext[4], ty1;
+};
+static_assert(sizeof(StateHeader) <= 256, "header fits its slot");
+constexpr size_t kStateHeader = 256;
+
+uint64_t params_hash(const dmr_params& p) {
+  const unsigned char* b = (const unsigned char*)&p;
+  uint64_t h = 1469598103934665603ull;  // FNV-1a
+  for (size_t k = 0; k < sizeof(dmr_params); k++) h = (h ^ b[k]) * 1099511628211ull;
+  return h;
+}
+
+size_t state_bytes(const dmr_sim* s) {
+  return kStateHeader + tape_layout(&s->p, 1, 1).ck_size;
+}
+
+// host-side copy of the live planes to / from a host buffer b (floats after
+// the header), the patch planes over the patch's rows only
+int state_host_copy(dmr_sim* s, float* b, bool save) {
+  float *lc[9], *lf[15];
+  ck_planes(s, lc, lf);
+  const size_t p0 = s->L0.plane, p1 = s->L1.plane;
+  auto cp = [&](float* live, float* host, size_t n) {
+    return save ? hipMemcpyAsync(host, live, n * 4, hipMemcpyDeviceToHost, s->st)
+                : hipMemcpyAsync(live, host, n * 4, hipMemcpyHostToDevice, s->st);
+  };
+  for (int q = 0; q < 9; q++) {
+    const hipError_t e = cp(lc[q], b + q * p0, q == 8 ? kRing * p0 : p0);
+    if (e != hipSuccess) return hipfail(s, e, "state copy");
+  }
+  if (s->has_patch) {
+    const size_t off = (size_t)(s->p.r * s->ext[1]) * s->L1.pitch;
+    const size_t n = (size_t)(s->p.r * (s->ext[3] - s->ext[1]) + 1) * s->L1.pitch;
+    float* fb = b + kCkC * p0;
+    for (int q = 0; q < kCkF; q++) {
+      const hipError_t e = cp(lf[q] + off, fb + q * p1 + off, n);
+      if (e != hipSuccess) return hipfail(s, e, "state copy");
+    }
+  }
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  return DMR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1505,6 +1558,68 @@ int dmr_backward(dmr_sim* s, const void* d_tape, const float* d_w_coarse,
   HIPCHK(s, hipStreamSynchronize(s->st));
   if (grad) for (int q = 0; q < 3; q++) grad[q] = g3[q];
   return DMR_OK;
+}
+
+int dmr_state_bytes(const dmr_sim* s, size_t* bytes) {
+  if (!s || !bytes) return DMR_EINVAL;
+  *bytes = state_bytes(s);
+  return DMR_OK;
+}
+
+int dmr_save(dmr_sim* s, void* dst, size_t bytes, int dst_on_device) {
+  if (!s || !dst) return DMR_EINVAL;
+  const size_t need = state_bytes(s);
+  if (bytes < need) return fail(s, DMR_ENOMEM, "state needs %zu bytes", need);
+  if (dst_on_device && ((uintptr_t)dst & 255))
+    return fail(s, DMR_EINVAL, "device state buffer must be 256-byte aligned");
+  StateHeader h{};
+  memcpy(h.magic, "DMRSTATE", 8);
+  h.version = 1; h.header_bytes = (uint32_t)kStateHeader;
+  h.params_hash = params_hash(s->p); h.total_bytes = need;
+  h.step = s->step; h.blocks = s->blocks; h.has_patch = s->has_patch ? 1 : 0;
+  for (int q = 0; q < 4; q++) h.ext[q] = s->ext[q];
+  h.ty1 = s->ty1;
+  float* body = (float*)((char*)dst + kStateHeader);
+  if (dst_on_device) {
+    if (int rc = ck_copy(s, body, true)) return rc;
+    HIPCHK(s, hipMemcpyAsync(dst, &h, sizeof(h), hipMemcpyHostToDevice, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+  } else {
+    if (int rc = state_host_copy(s, body, true)) return rc;
+    memcpy(dst, &h, sizeof(h));
+  }
+  return DMR_OK;
+}
+
+int dmr_load(dmr_sim* s, const void* src, size_t bytes, int src_on_device) {
+  if (!s || !src) return DMR_EINVAL;
+  const size_t need = state_bytes(s);
+  if (bytes < need) return fail(s, DMR_ENOMEM, "state needs %zu bytes", need);
+  if (src_on_device && ((uintptr_t)src & 255))
+    return fail(s, DMR_EINVAL, "device state buffer must be 256-byte aligned");
+  StateHeader h{};
+  if (src_on_device) {
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    HIPCHK(s, hipMemcpy(&h, src, sizeof(h), hipMemcpyDeviceToHost));
+  } else {
+    memcpy(&h, src, sizeof(h));
+  }
+  if (memcmp(h.magic, "DMRSTATE", 8) != 0 || h.version != 1 || h.header_bytes != kStateHeader)
+    return fail(s, DMR_EINVAL, "not a saved state");
+  if (h.params_hash != params_hash(s->p) || h.total_bytes != need)
+    return fail(s, DMR_EINVAL, "saved state belongs to other parameters");
+  if (h.has_patch && !refined(&s->p)) return fail(s, DMR_EINVAL, "saved state has a patch");
+  s->step = h.step; s->blocks = h.blocks; s->has_patch = h.has_patch != 0;
+  for (int q = 0; q < 4; q++) s->ext[q] = h.ext[q];
+  s->ty1 = h.ty1;
+  s->tape.valid = false;  // a recorded run no longer describes this state
+  float* body = (float*)((char*)src + kStateHeader);
+  if (src_on_device) {
+    if (int rc = ck_copy(s, body, false)) return rc;
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return DMR_OK;
+  }
+  return state_host_copy(s, body, false);
 }
 
 int dmr_weighted_sum(dmr_sim* s, int level, const float* d_w, double* out) {
