@@ -58,6 +58,7 @@ extern "C" {
 
 enum { DMR_BC_MUR = 0, DMR_BC_PEC = 1 };
 enum { DMR_UNIFORM = 0, DMR_STATIC = 1, DMR_DYNAMIC = 2 };
+enum { DMR_RULE_BLOCKS = 0, DMR_RULE_LINES = 1 };
 enum { DMR_D_BLEND = 0, DMR_D_CONST = 1 };
 enum {
   DMR_HZ = 0, DMR_EX = 1, DMR_EY = 2, DMR_JX = 3, DMR_JY = 4,
@@ -100,6 +101,21 @@ typedef struct dmr_params {
                                 fine substep (1e-4 suppresses the slow growth
                                 of sub-coarse modes at the interface; 0: off;
                                 at most 1/64) */
+  /* growth rule of DMR_DYNAMIC (Sec. III.D):
+   *   DMR_RULE_BLOCKS  flag nodes (n_thr_over_nc, grad_thr, n_floor_over_nc),
+   *                    OR over block x block cells, prefix-sum compaction,
+   *                    bounding box of the old patch and the flagged blocks;
+   *   DMR_RULE_LINES   the threshold lines: the initial patch is m_lx x m_ly
+   *                    base cells centred on the seed's peak node; at each
+   *                    test, a side of the patch whose boundary line carries a
+   *                    node with n > n_line moves out by m_ex (left / right
+   *                    sides) or m_ey (bottom / top).
+   * Both keep the patch one block clear of the outer boundary and right of
+   * the source line by one block, and only grow it. */
+  int32_t regrid_rule;
+  int32_t m_lx, m_ly, m_ex, m_ey;  /* base cells (DMR_RULE_LINES) */
+  int32_t pad2_;
+  double n_line;             /* threshold density on the lines, m^-3 */
 } dmr_params;
 
 typedef struct dmr_sim dmr_sim;

@@ -787,9 +787,66 @@ static int build_patch(orc_sim *s, const int ne[4], const double *seed_fine) {
   return s->hz_sub1 ? 0 : -2;
 }
 
+/* The threshold lines of Sec. III.D.  The lines coincide with the sides of
+ * the patch (the coarse-fine boundary).  A side whose line carries a base
+ * node with n above the threshold density moves outward: by m_ex for the
+ * two sides crossing x (left, right), by m_ey for the two crossing y (bottom,
+ * top).  Before any patch exists, the first one is m_lx x m_ly cells centred
+ * on the peak of the density (its first maximum, rows from the bottom).  The
+ * same margins as the block rule apply; the patch only grows.  The density is
+ * compared in binary32, as the flags of the block rule. */
+static void line_rule(orc_sim *s, int ne[4]) {
+  const orc_params *p = &s->p;
+  const level_t *L = &s->L0;
+  const int B = p->block;
+  int xmin = 1;
+  if (p->tfsf_i > 0) {
+    int m = (p->tfsf_i + 2 * B - 1) / B;
+    if (m > xmin) xmin = m;
+  }
+  if (!s->has_patch) {
+    int pi = 0, pj = 0;
+    double best = NODE(L, n, 0, 0);
+    for (int j = 0; j <= L->ny; j++)
+      for (int i = 0; i <= L->nx; i++)
+        if (NODE(L, n, i, j) > best) {
+          best = NODE(L, n, i, j);
+          pi = i;
+          pj = j;
+        }
+    ne[0] = pi - p->m_lx / 2;
+    ne[1] = pj - p->m_ly / 2;
+    ne[2] = ne[0] + p->m_lx;
+    ne[3] = ne[1] + p->m_ly;
+  } else {
+    const float thr = (float)p->n_line;
+    int left = 0, right = 0, bottom = 0, top = 0;
+    for (int j = s->ext[1]; j <= s->ext[3]; j++) {
+      if ((float)NODE(L, n, s->ext[0], j) > thr) left = 1;
+      if ((float)NODE(L, n, s->ext[2], j) > thr) right = 1;
+    }
+    for (int i = s->ext[0]; i <= s->ext[2]; i++) {
+      if ((float)NODE(L, n, i, s->ext[1]) > thr) bottom = 1;
+      if ((float)NODE(L, n, i, s->ext[3]) > thr) top = 1;
+    }
+    ne[0] = s->ext[0] - (left ? p->m_ex : 0);
+    ne[2] = s->ext[2] + (right ? p->m_ex : 0);
+    ne[1] = s->ext[1] - (bottom ? p->m_ey : 0);
+    ne[3] = s->ext[3] + (top ? p->m_ey : 0);
+  }
+  if (ne[0] < xmin * B) ne[0] = xmin * B;
+  if (ne[1] < B) ne[1] = B;
+  if (ne[2] > L->nx - B) ne[2] = L->nx - B;
+  if (ne[3] > L->ny - B) ne[3] = L->ny - B;
+  if (ne[0] >= ne[2] || ne[1] >= ne[3]) ne[0] = ne[1] = ne[2] = ne[3] = 0;
+}
+
 static int do_regrid(orc_sim *s, const double *seed_fine) {
   int ne[4];
-  regrid_test(s, ne);
+  if (s->p.regrid_rule == ORC_RULE_LINES)
+    line_rule(s, ne);
+  else
+    regrid_test(s, ne);
   if (ne[2] <= ne[0]) return 0; /* nothing to refine */
   if (s->has_patch && !memcmp(ne, s->ext, sizeof(ne))) return 0;
   return build_patch(s, ne, seed_fine);
@@ -852,6 +909,9 @@ int orc_create(const orc_params *p, const double *seed_base,
       return -1;
     if (p->bc_x == ORC_BC_PERIODIC || p->bc_y == ORC_BC_PERIODIC) return -1;
     if (p->mode == ORC_DYNAMIC && p->regrid_every % (spp / NRING)) return -1;
+    if (p->regrid_rule == ORC_RULE_LINES &&
+        (p->m_lx < 1 || p->m_ly < 1 || p->m_ex < 1 || p->m_ey < 1 || !(p->n_line > 0.0)))
+      return -1;
   }
   if (p->tfsf_i > 0 && (p->tfsf_i >= p->nx || p->bc_x == ORC_BC_PERIODIC))
     return -1;

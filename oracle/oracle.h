@@ -18,7 +18,8 @@
  *   - one r = 2 fine patch with time subcycling, Eq. (5b) boundary transfer,
  *     restriction back to the coarse mesh, and the self-aware expansion of
  *     Sec. III.D (threshold + gradient-length flags on 16x16 blocks, prefix
- *     sum compaction, bounding-box growth, Eq. (5a) prolongation).
+ *     sum compaction, bounding-box growth; or the threshold lines on the
+ *     patch sides with steps m_ex, m_ey; Eq. (5a) prolongation).
  * All floating-point state is double.  The regrid flag decision is taken in
  * binary32 (the precision of the GPU kernels) so that both sides decide on
  * identical inputs identically.
@@ -44,6 +45,7 @@ extern "C" {
 enum { ORC_BC_MUR = 0, ORC_BC_PEC = 1, ORC_BC_PERIODIC = 2 };
 enum { ORC_UNIFORM = 0, ORC_STATIC = 1, ORC_DYNAMIC = 2 };
 enum { ORC_D_BLEND = 0, ORC_D_CONST = 1 };
+enum { ORC_RULE_BLOCKS = 0, ORC_RULE_LINES = 1 };
 enum {
   ORC_HZ = 0, ORC_EX = 1, ORC_EY = 2, ORC_JX = 3, ORC_JY = 4,
   ORC_N = 5, ORC_ACC = 6, ORC_ERMS2 = 7, ORC_RING = 8
@@ -74,6 +76,13 @@ typedef struct orc_params {
   int32_t static_ext[4];   /* I0, J0, I1, J1 in base cells (ORC_STATIC) */
   int32_t d_mode;          /* ORC_D_* */
   int32_t continuity_on;   /* 0 freezes n (and skips the window) */
+  /* growth rule of ORC_DYNAMIC: ORC_RULE_BLOCKS (flags, 16x16 blocks,
+   * bounding box) or ORC_RULE_LINES (threshold lines on the patch sides,
+   * Sec. III.D): initial m_lx x m_ly cells centred on the seed peak; a side
+   * whose line has a node with n > n_line moves out by m_ex (x) / m_ey (y) */
+  int32_t regrid_rule;
+  int32_t m_lx, m_ly, m_ex, m_ey;
+  double n_line;           /* m^-3 */
 } orc_params;
 
 typedef struct orc_sim orc_sim;

@@ -41,6 +41,8 @@ class OrcParams(C.Structure):
         ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("mode", C.c_int32),
         ("static_ext", C.c_int32 * 4), ("d_mode", C.c_int32),
         ("continuity_on", C.c_int32),
+        ("regrid_rule", C.c_int32), ("m_lx", C.c_int32), ("m_ly", C.c_int32),
+        ("m_ex", C.c_int32), ("m_ey", C.c_int32), ("n_line", C.c_double),
     ]
 
 
@@ -100,6 +102,8 @@ def make_params(cfg: dict) -> OrcParams:
             setattr(p, name, MODE[cfg["mode"]])
         elif name == "d_mode":
             setattr(p, name, DMODE[cfg["d_mode"]])
+        elif name == "regrid_rule":
+            p.regrid_rule = {"blocks": 0, "lines": 1}[cfg.get("regrid_rule", "blocks")]
         elif name == "static_ext":
             for k, v in enumerate(cfg.get("static_ext", (0, 0, 0, 0))):
                 p.static_ext[k] = int(v)

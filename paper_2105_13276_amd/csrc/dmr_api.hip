@@ -7,6 +7,7 @@
 #include <array>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -110,6 +111,10 @@ int check_params(const dmr_params* p, std::string* why) {
     if (p->mode == DMR_DYNAMIC &&
         (p->regrid_every <= 0 || p->regrid_every % (spp / kRing)))
       return bad("regrid_every must be a positive multiple of steps per window block");
+    if (p->regrid_rule < 0 || p->regrid_rule > 1) return bad("bad regrid_rule");
+    if (p->mode == DMR_DYNAMIC && p->regrid_rule == DMR_RULE_LINES &&
+        (p->m_lx < 1 || p->m_ly < 1 || p->m_ex < 1 || p->m_ey < 1 || !(p->n_line > 0.0)))
+      return bad("the threshold-line rule needs m_lx, m_ly, m_ex, m_ey >= 1, n_line > 0");
     if (p->mode == DMR_STATIC) {
       const int* e = p->static_ext;
       if (e[0] < 1 || e[1] < 1 || e[2] > p->nx - 1 || e[3] > p->ny - 1 ||
@@ -192,6 +197,7 @@ struct dmr_sim {
   // patch built at t = 0, and whether its density came from a fine seed
   bool had0 = false, keep_n0 = false;
   int ext0[4] = {0, 0, 0, 0};
+  int peak[2] = {0, 0};  // base node of the seed's first maximum (row by row)
   AdjTape tape;
   hipStream_t rep_st = nullptr;  // the adjoint's replay stream (default priority)
   hipEvent_t ev_rep[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr}, ev_sync = nullptr;
@@ -384,8 +390,48 @@ int prolong(dmr_sim* s, const int ne[4], bool keep_n) {
   return DMR_OK;
 }
 
+// Growth by the threshold lines of Sec. III.D: the patch sides are the lines;
+// a side whose line carries a node with n > n_line moves out by m_ex (x) or
+// m_ey (y).  The first patch is m_lx x m_ly cells centred on the seed peak.
+int regrid_lines(dmr_sim* s, bool keep_n) {
+  const dmr_params& p = s->p;
+  const int Bk = p.block;
+  int xmin = 1;
+  if (p.tfsf_i > 0) xmin = std::max(xmin, (p.tfsf_i + 2 * Bk - 1) / Bk);
+  int ne[4];
+  if (!s->has_patch) {
+    ne[0] = s->peak[0] - p.m_lx / 2;
+    ne[1] = s->peak[1] - p.m_ly / 2;
+    ne[2] = ne[0] + p.m_lx;
+    ne[3] = ne[1] + p.m_ly;
+  } else {
+    int* f = (int*)s->stage;
+    ev_begin(s, 3);
+    hipError_t e = launch_line_flags(s->L0.n[s->ncur], s->L0.pitch, s->ext[0], s->ext[1],
+                                     s->ext[2], s->ext[3], (float)p.n_line, f, s->st);
+    ev_end(s);
+    if (e != hipSuccess) return hipfail(s, e, "threshold-line launch");
+    int h[4];
+    HIPCHK(s, hipMemcpyAsync(h, f, sizeof(h), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    for (int q = 0; q < 4; q++) ne[q] = s->ext[q];
+    if (h[0]) ne[0] -= p.m_ex;
+    if (h[1]) ne[2] += p.m_ex;
+    if (h[2]) ne[1] -= p.m_ey;
+    if (h[3]) ne[3] += p.m_ey;
+  }
+  ne[0] = std::max(ne[0], xmin * Bk);
+  ne[1] = std::max(ne[1], Bk);
+  ne[2] = std::min(ne[2], p.nx - Bk);
+  ne[3] = std::min(ne[3], p.ny - Bk);
+  if (ne[0] >= ne[2] || ne[1] >= ne[3]) return DMR_OK;  // no room for a patch
+  if (s->has_patch && !memcmp(ne, s->ext, sizeof(ne))) return DMR_OK;
+  return prolong(s, ne, keep_n);
+}
+
 int regrid(dmr_sim* s, bool keep_n) {
   const dmr_params& p = s->p;
+  if (p.regrid_rule == DMR_RULE_LINES) return regrid_lines(s, keep_n);
   const int Bk = p.block, NBx = p.nx / Bk, NBy = p.ny / Bk;
   int* D = s->h_desc;
   for (int k = 0; k < 4; k++) D[k] = s->has_patch ? s->ext[k] / Bk : 0;
@@ -832,6 +878,15 @@ int dmr_create(const dmr_params* p, const double* seed_base,
     if (r1 != hipSuccess) return r1;
     return hipStreamSynchronize(s->st);
   };
+  if (seed_base) {  // the seed's peak (the threshold-line rule centres the first patch on it)
+    double best = seed_base[0];
+    for (int j = 0; j <= p->ny; j++)
+      for (int i = 0; i <= p->nx; i++)
+        if (seed_base[(size_t)j * (p->nx + 1) + i] > best) {
+          best = seed_base[(size_t)j * (p->nx + 1) + i];
+          s->peak[0] = i; s->peak[1] = j;
+        }
+  }
   if (seed_base && (e = upload(seed_base, s->L0)) != hipSuccess) {
     rc = hipfail(s, e, "seed upload");
     delete s;
@@ -1347,9 +1402,15 @@ static_assert(sizeof(StateHeader) <= 256, "header fits its slot");
 constexpr size_t kStateHeader = 256;
 
 uint64_t params_hash(const dmr_params& p) {
+  // FNV-1a over the named fields (padding and the pad_ fields left out)
   const unsigned char* b = (const unsigned char*)&p;
-  uint64_t h = 1469598103934665603ull;  // FNV-1a
-  for (size_t k = 0; k < sizeof(dmr_params); k++) h = (h ^ b[k]) * 1099511628211ull;
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](size_t lo, size_t hi) {
+    for (size_t k = lo; k < hi; k++) h = (h ^ b[k]) * 1099511628211ull;
+  };
+  mix(0, offsetof(dmr_params, pad_));
+  mix(offsetof(dmr_params, freq_hz), offsetof(dmr_params, pad2_));
+  mix(offsetof(dmr_params, n_line), sizeof(dmr_params));
   return h;
 }
 

@@ -1658,6 +1658,42 @@ hipError_t launch_em_stream(const EMArgs& A, int seg, int depth, hipStream_t st)
   return hipGetLastError();
 }
 
+// Sec. III.D threshold lines: one block walks the perimeter nodes of the
+// patch; each side's flag is the OR over its line.
+__global__ __launch_bounds__(1024) void k_line_flags(const float* __restrict__ n, int pitch,
+                                                     int I0, int J0, int I1, int J1, float thr,
+                                                     int* flags) {
+  const int h = J1 - J0 + 1, w = I1 - I0 + 1;
+  int fl = 0, fr = 0, fb = 0, ft = 0;
+  for (int k = threadIdx.x; k < 2 * h + 2 * w; k += blockDim.x) {
+    int i, j;
+    if (k < h) { i = I0; j = J0 + k; }
+    else if (k < 2 * h) { i = I1; j = J0 + k - h; }
+    else if (k < 2 * h + w) { i = I0 + k - 2 * h; j = J0; }
+    else { i = I0 + k - 2 * h - w; j = J1; }
+    const bool hit = n[(size_t)j * pitch + i] > thr;
+    if (k < h) fl |= hit;
+    else if (k < 2 * h) fr |= hit;
+    else if (k < 2 * h + w) fb |= hit;
+    else ft |= hit;
+  }
+  fl = __syncthreads_or(fl);
+  fr = __syncthreads_or(fr);
+  fb = __syncthreads_or(fb);
+  ft = __syncthreads_or(ft);
+  if (threadIdx.x < 4) {
+    const int v = threadIdx.x == 0 ? fl : threadIdx.x == 1 ? fr : threadIdx.x == 2 ? fb : ft;
+    flags[threadIdx.x] = v ? 1 : 0;
+  }
+}
+
+hipError_t launch_line_flags(const float* n, int pitch, int I0, int J0, int I1, int J1,
+                             float thr, int* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_line_flags, dim3(1), dim3(1024), 0, st, n, pitch, I0, J0, I1, J1, thr,
+                     flags);
+  return hipGetLastError();
+}
+
 hipError_t launch_cont(const ContArgs& A, bool fine, hipStream_t st) {
   const int nx = A.R - A.L + 1, ny = A.T - A.B + 1;
   dim3 g((nx + kTX - 1) / kTX, (ny + kThreads / kTX - 1) / (kThreads / kTX));

@@ -47,6 +47,14 @@ PHYSICS = dict(
     d_mode="blend",
     continuity_on=True,
     static_ext=(0, 0, 0, 0),
+    # growth rule of the dynamic mode: "blocks" (flag / block / prefix-sum /
+    # bounding box) or "lines" (the threshold lines of Sec. III.D: initial
+    # patch m_lx x m_ly base cells on the seed peak, sides move out by m_ex
+    # in x and m_ey in y, m_ex > m_ey, where a line carries n > n_line; the
+    # paper's optimal threshold density is 1e16-1e17 m^-3)
+    regrid_rule="blocks",
+    m_lx=32, m_ly=32, m_ex=16, m_ey=8,
+    n_line=1e16,
 )
 
 
