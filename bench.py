@@ -295,6 +295,21 @@ def main():
         "roofline": roofline,
     }
 
+    # ---- the same DMR run grown by the paper's threshold lines ---------------
+    log("DMR config 1 with the threshold-line growth rule")
+    cfg_t = dict(cfg_d, regrid_rule="lines")
+    sim_t2, wall_t, work_t = run_case(B, cfg_t, seeds_d, K, INTERVAL, Wm, False)
+    ext_t = sim_t2.patch()
+    sim_t2.close()
+    out["threshold_lines"] = {
+        "workload": "DMR config 1 grown by the threshold lines (Sec. III.D): first patch "
+                    "%dx%d on the seed peak, steps m_ex=%d, m_ey=%d, n_line=%.0e m^-3"
+                    % (cfg_t["m_lx"], cfg_t["m_ly"], cfg_t["m_ex"], cfg_t["m_ey"],
+                       cfg_t["n_line"]),
+        "time_to_t_final_s": wall_t, "patch_final": list(ext_t),
+        "mcell_updates_per_s": work_t / wall_t / 1e6,
+        "speedup_vs_uniform_fine": wall_u / wall_t}
+
     # ---- bandwidth-bound shape: 4096x2048 coarse (added large row) --------
     if not args.no_large:
         log("4096x2048 kernel and DMR vs uniform-fine")

@@ -59,6 +59,7 @@ extern "C" {
 enum { DMR_BC_MUR = 0, DMR_BC_PEC = 1 };
 enum { DMR_UNIFORM = 0, DMR_STATIC = 1, DMR_DYNAMIC = 2 };
 enum { DMR_RULE_BLOCKS = 0, DMR_RULE_LINES = 1 };
+enum { DMR_SOURCE_POWER = 0, DMR_SOURCE_TOWNSEND = 1 };
 enum { DMR_D_BLEND = 0, DMR_D_CONST = 1 };
 enum {
   DMR_HZ = 0, DMR_EX = 1, DMR_EY = 2, DMR_JX = 3, DMR_JY = 4,
@@ -116,6 +117,19 @@ typedef struct dmr_params {
   int32_t m_lx, m_ly, m_ex, m_ey;  /* base cells (DMR_RULE_LINES) */
   int32_t pad2_;
   double n_line;             /* threshold density on the lines, m^-3 */
+  /* source of Eq. (4): n (nu_i - nu_a) - r_ei n^2 with
+   *   DMR_SOURCE_POWER     nu_i - nu_a = nu_m A [(E_eff/p)^beta - (E_cr/p)^beta]
+   *   DMR_SOURCE_TOWNSEND  nu_i - nu_a = gamma v_d - nu_att, Townsend
+   *                        gamma = A_town p exp(-B_town p / E_eff) (A_town in
+   *                        1/(cm Torr), B_town in V/(cm Torr), E_eff/p in
+   *                        V/(cm Torr)), drift v_d = e E_eff / (m nu_m),
+   *                        attachment nu_att (1/s)
+   * and recombination r_ei = beta_rec 1e-13 (300 K / T_e)^(1/2) m^3/s
+   * (T_e = te_ev in kelvin; beta_rec in [0, 2], 0: none).  The adjoint
+   * supports the power law without recombination. */
+  int32_t source_model;
+  int32_t pad3_;
+  double A_town, B_town, nu_att, beta_rec;
 } dmr_params;
 
 typedef struct dmr_sim dmr_sim;

@@ -17,6 +17,7 @@
 /* CODATA 2018 SI constants (the paper prints none). */
 static const double Q_E = 1.602176634e-19;
 static const double M_E = 9.1093837015e-31;
+static const double K_B = 1.380649e-23; /* J/K */
 static const double EPS_0 = 8.8541878128e-12;
 static const double C_0 = 299792458.0;
 static const double PI_ = 3.14159265358979323846;
@@ -463,10 +464,28 @@ double orc_nu_net(const orc_params *p, double erms2) {
   double omega = 2.0 * PI_ * p->freq_hz;
   double nu_m = 5.3e9 * p->p_torr;
   double eeff2 = erms2 / (1.0 + (omega * omega) / (nu_m * nu_m));
+  if (p->source_model == ORC_SOURCE_TOWNSEND) {
+    /* Eq. (4) with nu_i - nu_a = gamma v_d: Townsend's first coefficient
+     * gamma = A p exp(-B p / E_eff) (per cm, E in V/cm), the drift velocity
+     * of the collisional electron fluid v_d = mu_e E_eff, mu_e = e/(m nu_m);
+     * attachment as a separate constant rate */
+    double eeff = sqrt(eeff2);                 /* V/m */
+    if (eeff <= 0.0) return -p->nu_att;
+    double e_cm = eeff / 100.0;                /* V/cm */
+    double gamma_cm = p->A_town * p->p_torr * exp(-p->B_town * p->p_torr / e_cm);
+    double v_d = Q_E / (M_E * nu_m) * eeff;    /* m/s */
+    return 100.0 * gamma_cm * v_d - p->nu_att;
+  }
   /* (E_eff / p)^beta with E_eff/p in V/(cm Torr), via the square */
   double x = eeff2 / (1.0e4 * p->p_torr * p->p_torr);
   return nu_m * p->A_ion *
          (pow(x, 0.5 * p->beta_ion) - pow(p->ecr_over_p, p->beta_ion));
+}
+
+double orc_r_ei(const orc_params *p) {
+  if (!(p->beta_rec > 0.0)) return 0.0;
+  double te_kelvin = p->te_ev * Q_E / K_B;
+  return p->beta_rec * 1e-13 * sqrt(300.0 / te_kelvin);
 }
 
 double orc_d_eff(const orc_params *p, double n) {
@@ -503,6 +522,7 @@ static void continuity_core(const orc_params *p, int nx, int ny, double dx,
                             int perx, int pery, const double *nold,
                             const double *e2, double *nout) {
 #define AT(arr, i, j) arr[(size_t)(i) * (ny + 1) + (j)]
+  const double r_ei = orc_r_ei(p);
   memcpy(nout, nold, (size_t)(nx + 1) * (ny + 1) * sizeof(double));
   for (int i = ilo; i <= ihi; i++)
     for (int j = jlo; j <= jhi; j++) {
@@ -525,7 +545,7 @@ static void continuity_core(const orc_params *p, int nx, int ny, double dx,
         flux += 0.5 * (di + orc_d_eff(p, nn)) * (nn - ni);
       }
       double nu = orc_nu_net(p, AT(e2, i, j));
-      double nnew = ni + dtn * (flux / (dx * dx) + nu * ni);
+      double nnew = ni + dtn * (flux / (dx * dx) + nu * ni - r_ei * ni * ni);
       AT(nout, i, j) = nnew > 0.0 ? nnew : 0.0;
     }
   if (perx)
@@ -914,6 +934,9 @@ int orc_create(const orc_params *p, const double *seed_base,
       return -1;
   }
   if (p->tfsf_i > 0 && (p->tfsf_i >= p->nx || p->bc_x == ORC_BC_PERIODIC))
+    return -1;
+  if (p->source_model < 0 || p->source_model > 1 || !(p->beta_rec >= 0.0) ||
+      p->beta_rec > 2.0)
     return -1;
   orc_sim *s = calloc(1, sizeof(*s));
   if (!s) return -2;

@@ -46,6 +46,7 @@ enum { ORC_BC_MUR = 0, ORC_BC_PEC = 1, ORC_BC_PERIODIC = 2 };
 enum { ORC_UNIFORM = 0, ORC_STATIC = 1, ORC_DYNAMIC = 2 };
 enum { ORC_D_BLEND = 0, ORC_D_CONST = 1 };
 enum { ORC_RULE_BLOCKS = 0, ORC_RULE_LINES = 1 };
+enum { ORC_SOURCE_POWER = 0, ORC_SOURCE_TOWNSEND = 1 };
 enum {
   ORC_HZ = 0, ORC_EX = 1, ORC_EY = 2, ORC_JX = 3, ORC_JY = 4,
   ORC_N = 5, ORC_ACC = 6, ORC_ERMS2 = 7, ORC_RING = 8
@@ -83,6 +84,13 @@ typedef struct orc_params {
   int32_t regrid_rule;
   int32_t m_lx, m_ly, m_ex, m_ey;
   double n_line;           /* m^-3 */
+  /* source of Eq. (4): ORC_SOURCE_POWER (the net power law above) or
+   * ORC_SOURCE_TOWNSEND: nu_i - nu_a = gamma v_d - nu_att with the Townsend
+   * coefficient gamma = A_town p exp(-B_town p / E_eff) (A_town 1/(cm Torr),
+   * B_town V/(cm Torr)) and the drift velocity v_d = e E_eff / (m nu_m);
+   * recombination r_ei = beta_rec 1e-13 (300/T_e[K])^(1/2) m^3/s */
+  int32_t source_model;
+  double A_town, B_town, nu_att, beta_rec;
 } orc_params;
 
 typedef struct orc_sim orc_sim;
@@ -108,6 +116,8 @@ int orc_time(const orc_sim *s, double *t, int64_t *step);
 int orc_derived(const orc_params *p, double *out, int n_out);
 /* net ionisation rate for a given E_rms^2 (V^2/m^2) */
 double orc_nu_net(const orc_params *p, double erms2);
+/* recombination coefficient r_ei, m^3/s */
+double orc_r_ei(const orc_params *p);
 double orc_d_eff(const orc_params *p, double n);
 /* one continuity step on given node arrays (layout as the fields above),
  * zero-flux or periodic outer faces */

@@ -43,6 +43,8 @@ class OrcParams(C.Structure):
         ("continuity_on", C.c_int32),
         ("regrid_rule", C.c_int32), ("m_lx", C.c_int32), ("m_ly", C.c_int32),
         ("m_ex", C.c_int32), ("m_ey", C.c_int32), ("n_line", C.c_double),
+        ("source_model", C.c_int32), ("A_town", C.c_double), ("B_town", C.c_double),
+        ("nu_att", C.c_double), ("beta_rec", C.c_double),
     ]
 
 
@@ -84,6 +86,8 @@ def lib():
         L.orc_derived.argtypes = [P(OrcParams), P(C.c_double), C.c_int]
         L.orc_nu_net.argtypes = [P(OrcParams), C.c_double]
         L.orc_nu_net.restype = C.c_double
+        L.orc_r_ei.argtypes = [P(OrcParams)]
+        L.orc_r_ei.restype = C.c_double
         L.orc_d_eff.argtypes = [P(OrcParams), C.c_double]
         L.orc_d_eff.restype = C.c_double
         L.orc_continuity_apply.argtypes = [
@@ -102,6 +106,8 @@ def make_params(cfg: dict) -> OrcParams:
             setattr(p, name, MODE[cfg["mode"]])
         elif name == "d_mode":
             setattr(p, name, DMODE[cfg["d_mode"]])
+        elif name == "source_model":
+            p.source_model = {"power": 0, "townsend": 1}[cfg.get("source_model", "power")]
         elif name == "regrid_rule":
             p.regrid_rule = {"blocks": 0, "lines": 1}[cfg.get("regrid_rule", "blocks")]
         elif name == "static_ext":
@@ -119,6 +125,12 @@ def derived(cfg: dict) -> dict:
     out = (C.c_double * len(DERIVED))()
     lib().orc_derived(C.byref(p), out, len(DERIVED))
     return dict(zip(DERIVED, list(out)))
+
+
+def r_ei(cfg: dict) -> float:
+    """Recombination coefficient of Eq. (4), m^3/s."""
+    p = make_params(cfg)
+    return lib().orc_r_ei(C.byref(p))
 
 
 def nu_net(cfg: dict, erms2: float) -> float:

@@ -18,6 +18,7 @@ BC = {"mur": 0, "pec": 1}
 MODE = {"uniform": 0, "static": 1, "dynamic": 2}
 DMODE = {"blend": 0, "const": 1}
 RULE = {"blocks": 0, "lines": 1}
+SOURCE = {"power": 0, "townsend": 1}
 FIELD = {"hz": 0, "ex": 1, "ey": 2, "jx": 3, "jy": 4, "n": 5, "acc": 6,
          "erms2": 7, "ring": 8}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSTABLE"}
@@ -52,7 +53,9 @@ class DmrParams(C.Structure):
         ("courant", C.c_double), ("fine_filter", C.c_double),
         ("regrid_rule", C.c_int32), ("m_lx", C.c_int32), ("m_ly", C.c_int32),
         ("m_ex", C.c_int32), ("m_ey", C.c_int32), ("pad2_", C.c_int32),
-        ("n_line", C.c_double),
+        ("n_line", C.c_double), ("source_model", C.c_int32), ("pad3_", C.c_int32),
+        ("A_town", C.c_double), ("B_town", C.c_double), ("nu_att", C.c_double),
+        ("beta_rec", C.c_double),
     ]
 
 
@@ -119,7 +122,7 @@ def make_params(cfg: dict) -> DmrParams:
     p = DmrParams()
     p.struct_size = C.sizeof(DmrParams)
     for name, _ in DmrParams._fields_:
-        if name in ("struct_size", "pad_", "pad2_"):
+        if name in ("struct_size", "pad_", "pad2_", "pad3_"):
             continue
         if name in ("bc_x", "bc_y"):
             setattr(p, name, BC[cfg[name]])
@@ -129,6 +132,8 @@ def make_params(cfg: dict) -> DmrParams:
             p.d_mode = DMODE[cfg["d_mode"]]
         elif name == "regrid_rule":
             p.regrid_rule = RULE[cfg["regrid_rule"]]
+        elif name == "source_model":
+            p.source_model = SOURCE[cfg["source_model"]]
         elif name == "static_ext":
             for k, v in enumerate(cfg.get("static_ext", (0, 0, 0, 0))):
                 p.static_ext[k] = int(v)

@@ -25,6 +25,7 @@ namespace {
 // CODATA 2018
 constexpr double kQe = 1.602176634e-19;
 constexpr double kMe = 9.1093837015e-31;
+constexpr double kKb = 1.380649e-23;  // J/K
 constexpr double kEps0 = 8.8541878128e-12;
 constexpr double kC0 = 299792458.0;
 constexpr double kPi = 3.14159265358979323846;
@@ -102,6 +103,11 @@ int check_params(const dmr_params* p, std::string* why) {
   if (p->mode < 0 || p->mode > 2) return bad("bad mode");
   if (p->d_mode < 0 || p->d_mode > 1) return bad("bad d_mode");
   if (p->tfsf_i < 0 || p->tfsf_i >= p->nx) return bad("tfsf_i out of range");
+  if (p->source_model < 0 || p->source_model > 1) return bad("bad source_model");
+  if (p->source_model == DMR_SOURCE_TOWNSEND &&
+      (!(p->A_town >= 0.0) || !(p->B_town > 0.0) || !(p->nu_att >= 0.0)))
+    return bad("Townsend source needs A_town >= 0, B_town > 0, nu_att >= 0");
+  if (!(p->beta_rec >= 0.0) || p->beta_rec > 2.0) return bad("beta_rec must be in [0, 2]");
   if (refined(p)) {
     if (p->r != 2) return bad("only r = 2 is supported");
     if (p->block < 2 || p->nx % p->block || p->ny % p->block)
@@ -523,6 +529,13 @@ void make_fine_em(const dmr_sim* s, int m, int c, int nc, int ty, EMArgs* G) {
   (void)ty;
 }
 
+// recombination coefficient of Eq. (4), m^3/s: beta 1e-13 (300 K / T_e)^(1/2)
+double rei_of(const dmr_params& p) {
+  if (!(p.beta_rec > 0.0)) return 0.0;
+  const double te_k = p.te_ev * kQe / kKb;
+  return p.beta_rec * 1e-13 * std::sqrt(300.0 / te_k);
+}
+
 void make_base_cont(const dmr_sim* s, int nc, ContArgs* K) {
   const Level& C = s->L0;
   const dmr_params& p = s->p;
@@ -537,6 +550,15 @@ void make_base_cont(const dmr_sim* s, int nc, ContArgs* K) {
   K->half_beta = (float)(0.5 * p.beta_ion);
   K->att = (float)std::pow(p.ecr_over_p, p.beta_ion);
   K->nuA = (float)(s->nu_m * p.A_ion);
+  if (p.source_model == DMR_SOURCE_TOWNSEND) {
+    // gamma v_d = [100 A_town p exp(-B_town / y)] [mu_e 100 p y], y = E_eff/(100 p)
+    const double mu_e = kQe / (kMe * s->nu_m);
+    K->town = 1;
+    K->tK = (float)(1.0e4 * p.A_town * p.p_torr * p.p_torr * mu_e);
+    K->tB = (float)p.B_town;
+    K->tatt = (float)p.nu_att;
+  }
+  K->rei = (float)rei_of(p);
   K->inv_namb = (float)(1.0 / s->n_amb);
   K->De = (float)s->De; K->Da = (float)s->Da;
   K->d_const_mode = p.d_mode == DMR_D_CONST;
@@ -1410,7 +1432,8 @@ uint64_t params_hash(const dmr_params& p) {
   };
   mix(0, offsetof(dmr_params, pad_));
   mix(offsetof(dmr_params, freq_hz), offsetof(dmr_params, pad2_));
-  mix(offsetof(dmr_params, n_line), sizeof(dmr_params));
+  mix(offsetof(dmr_params, n_line), offsetof(dmr_params, pad3_));
+  mix(offsetof(dmr_params, A_town), sizeof(dmr_params));
   return h;
 }
 
@@ -1462,6 +1485,8 @@ int dmr_forward_record(dmr_sim* s, int64_t steps, int ckpt_every, void* d_tape, 
   if (!s) return DMR_EINVAL;
   if (steps < 1 || ckpt_every < 1) return fail(s, DMR_EINVAL, "steps and ckpt_every must be >= 1");
   if (s->step != 0) return fail(s, DMR_EINVAL, "recording starts at t = 0 (fresh handle)");
+  if (s->p.source_model != DMR_SOURCE_POWER || s->p.beta_rec > 0.0)
+    return fail(s, DMR_EINVAL, "the adjoint supports the power-law source without recombination");
   if (!d_tape || ((uintptr_t)d_tape & 255)) return fail(s, DMR_EINVAL, "tape must be 256-byte aligned");
   const TapeLayout T = tape_layout(&s->p, steps, ckpt_every);
   if (bytes < T.total) return fail(s, DMR_ENOMEM, "tape needs %zu bytes", T.total);

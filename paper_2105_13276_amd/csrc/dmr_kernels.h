@@ -70,6 +70,10 @@ struct ContArgs {
   float inv_dx2;
   float eeff_p2;   // (1/(1 + w^2/nu^2)) / (100 p)^2
   float half_beta, att, nuA;
+  // Townsend source (town): nu = tK y exp(-tB / y) - tatt, y = E_eff/(100 p);
+  // recombination r_ei (0: none)
+  int town;
+  float tK, tB, tatt, rei;
   float inv_namb, De, Da;
   int d_const_mode;
   float d_const;

@@ -1001,8 +1001,9 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_batch(const EMArgs* __res
 // Window block close and continuity step (Eq. (4)), one thread per node of
 // the region [L..R] x [B..T].  ring[slot] <- acc / steps_per_period,
 // acc <- 0; with `update`, E_rms^2 = sum of the 8 ring slots,
-// nu = nu_m A [(E_eff^2/(100p)^2)^(beta/2) - (E_cr/p)^beta],
-// n+ = n + dt_n [dx^-2 sum_faces (D_i+D_nb)/2 (n_nb - n) + nu n]  (>= 0).
+// nu = nu_m A [(E_eff^2/(100p)^2)^(beta/2) - (E_cr/p)^beta] (or the
+// Townsend form gamma v_d - nu_att),
+// n+ = n + dt_n [dx^-2 sum_faces (D_i+D_nb)/2 (n_nb - n) + (nu - r_ei n) n]  (>= 0).
 // Fine level: interior nodes are updated; boundary nodes take the new coarse
 // density (copy / mean along the boundary line); the coarse nodes strictly
 // inside the patch take the new fine density (injection).
@@ -1045,8 +1046,19 @@ __device__ __forceinline__ void cont_body(const ContArgs& A, int bx, int by, int
     if (i < A.R) { const float v = A.n0[o + 1]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
     if (j > A.B) { const float v = A.n0[o - pitch]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
     if (j < A.T) { const float v = A.n0[o + pitch]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
-    const float nu = A.nuA * (powf(e2 * A.eeff_p2, A.half_beta) - A.att);
-    nn = ni + A.dtn * (flux * A.inv_dx2 + nu * ni);
+    if (!A.town && A.rei == 0.f) {
+      const float nu = A.nuA * (powf(e2 * A.eeff_p2, A.half_beta) - A.att);
+      nn = ni + A.dtn * (flux * A.inv_dx2 + nu * ni);
+    } else {  // Townsend ionisation and / or recombination
+      float nu;
+      if (A.town) {
+        const float y = sqrtf(e2 * A.eeff_p2);  // E_eff / (100 p), V/(cm Torr)
+        nu = (y > 0.f ? A.tK * y * expf(-A.tB / y) : 0.f) - A.tatt;
+      } else {
+        nu = A.nuA * (powf(e2 * A.eeff_p2, A.half_beta) - A.att);
+      }
+      nn = ni + A.dtn * (flux * A.inv_dx2 + (nu - A.rei * ni) * ni);
+    }
     nn = nn > 0.f ? nn : 0.f;
     if (FINE && (((i - A.L) | (j - A.B)) & 1) == 0) {
       const int a = i >> 1, b = j >> 1;  // strictly inside: interior even node

@@ -55,6 +55,15 @@ PHYSICS = dict(
     regrid_rule="blocks",
     m_lx=32, m_ly=32, m_ex=16, m_ey=8,
     n_line=1e16,
+    # source of Eq. (4): "power" (the calibrated net power law) or "townsend"
+    # (gamma = A p exp(-B p / E_eff), v_d = mu_e E_eff, separate attachment);
+    # air A = 15 /(cm Torr), B = 365 V/(cm Torr) (the textbook fit for
+    # E/p ~ 100-800); attachment = the power law's attachment part
+    # nu_m A_ion (E_cr/p)^beta; recombination beta_rec in [0, 2] (0: none)
+    source_model="power",
+    A_town=15.0, B_town=365.0,
+    nu_att=5.3e9 * 700.0 * 9.02e-14 * (2.5e6 / 760.0 / 100.0) ** 5.3,
+    beta_rec=0.0,
 )
 
 
