@@ -42,7 +42,9 @@ struct orc_sim {
   int ext[4]; /* I0, J0, I1, J1 base cells */
   int64_t step;
   int64_t blocks; /* window blocks closed so far */
-  double *ex_old, *ey_old, *hz_prev, *hz_sub1;
+  /* hz_lo, hz_hi: fine Hz after substeps r/2 and r/2 + 1, the two half
+   * levels that bracket coarse n+1/2 (for r = 2, hz_hi is the final Hz) */
+  double *ex_old, *ey_old, *hz_prev, *hz_lo, *hz_hi;
   int NBx, NBy;
   uint8_t *bflag;
   int32_t *bscan, *blist, bcount;
@@ -307,10 +309,11 @@ static void em_step_base(orc_sim *s) {
 /* ---- coarse -> fine transfer on the coarse/fine boundary, Eq. (5b) ------ */
 /* linear in time between the old and new coarse values (frac), linear in
  * space along the boundary line; coarse Ey lies at j+1/2, coarse Ex at i+1/2.
- * A fine y-edge at global fine row Q sits at coarse y-index Q/2 - 1/4. */
+ * A fine y-edge at global fine row Q sits at coarse y-index (Q+1/2)/r - 1/2
+ * (r = 2: Q/2 - 1/4; the offsets 1/(2r) of Fig. 5(c)). */
 static double cfb_ey(const orc_sim *s, int I, int Q, double frac) {
   const level_t *C = &s->L0;
-  double v = 0.5 * Q - 0.25;
+  double v = (Q + 0.5) / s->p.r - 0.5;
   int j = (int)floor(v);
   double xp = v - j;
   double o = (1.0 - xp) * s->ey_old[(size_t)I * C->ny + j] +
@@ -321,7 +324,7 @@ static double cfb_ey(const orc_sim *s, int I, int Q, double frac) {
 
 static double cfb_ex(const orc_sim *s, int P, int J, double frac) {
   const level_t *C = &s->L0;
-  double u = 0.5 * P - 0.25;
+  double u = (P + 0.5) / s->p.r - 0.5;
   int i = (int)floor(u);
   double xp = u - i;
   double o = (1.0 - xp) * s->ex_old[(size_t)i * (C->ny + 1) + J] +
@@ -386,7 +389,9 @@ static void em_step_fine(orc_sim *s, int m) {
     for (int j = 0; j < fh; j++)
       HZ(F, i, j) -= F->ch * ((EY(F, i + 1, j) - EY(F, i, j)) -
                               (EX(F, i, j + 1) - EX(F, i, j)));
-  if (m == 1) memcpy(s->hz_sub1, F->hz, n_hz(F) * sizeof(double));
+  if (m == s->p.r / 2) memcpy(s->hz_lo, F->hz, n_hz(F) * sizeof(double));
+  if (m == s->p.r / 2 + 1 && m < s->p.r)
+    memcpy(s->hz_hi, F->hz, n_hz(F) * sizeof(double));
 
   for (int i = 0; i < fw; i++)
     for (int j = 1; j < fh; j++) {
@@ -433,29 +438,41 @@ static void em_step_fine(orc_sim *s, int m) {
  * two fine H levels of the interval) ---------------------------------- */
 static void restrict_patch(orc_sim *s) {
   level_t *C = &s->L0, *F = &s->L1;
+  const int r = s->p.r;
   const int I0 = s->ext[0], J0 = s->ext[1], I1 = s->ext[2], J1 = s->ext[3];
   const int fh = F->ny;
+  const double *hi = r == 2 ? F->hz : s->hz_hi;
   for (int i = I0; i < I1; i++)
     for (int j = J0; j < J1; j++) {
-      int p = 2 * (i - I0), q = 2 * (j - J0);
+      int p = r * (i - I0), q = r * (j - J0);
       double sum = 0.0;
-      for (int a = 0; a < 2; a++)
-        for (int b = 0; b < 2; b++)
-          sum += 0.5 * (s->hz_sub1[(size_t)(p + a) * fh + q + b] +
-                        HZ(F, p + a, q + b));
-      HZ(C, i, j) = 0.25 * sum;
+      for (int a = 0; a < r; a++)
+        for (int b = 0; b < r; b++)
+          sum += 0.5 * (s->hz_lo[(size_t)(p + a) * fh + q + b] +
+                        hi[(size_t)(p + a) * fh + q + b]);
+      HZ(C, i, j) = sum / (r * r);
     }
   for (int i = I0; i < I1; i++)
     for (int j = J0 + 1; j < J1; j++) {
-      int p = 2 * (i - I0), q = 2 * (j - J0);
-      EX(C, i, j) = 0.5 * (EX(F, p, q) + EX(F, p + 1, q));
-      JX(C, i, j) = 0.5 * (JX(F, p, q) + JX(F, p + 1, q));
+      int p = r * (i - I0), q = r * (j - J0);
+      double se = 0.0, sj = 0.0;
+      for (int a = 0; a < r; a++) {
+        se += EX(F, p + a, q);
+        sj += JX(F, p + a, q);
+      }
+      EX(C, i, j) = se / r;
+      JX(C, i, j) = sj / r;
     }
   for (int i = I0 + 1; i < I1; i++)
     for (int j = J0; j < J1; j++) {
-      int p = 2 * (i - I0), q = 2 * (j - J0);
-      EY(C, i, j) = 0.5 * (EY(F, p, q) + EY(F, p, q + 1));
-      JY(C, i, j) = 0.5 * (JY(F, p, q) + JY(F, p, q + 1));
+      int p = r * (i - I0), q = r * (j - J0);
+      double se = 0.0, sj = 0.0;
+      for (int b = 0; b < r; b++) {
+        se += EY(F, p, q + b);
+        sj += JY(F, p, q + b);
+      }
+      EY(C, i, j) = se / r;
+      JY(C, i, j) = sj / r;
     }
 }
 
@@ -621,16 +638,17 @@ static double bilin(const double *arr, int nj, double u, double v) {
  * the coarse nodes strictly inside the patch (Sec. III.C transfers) */
 static void transfer_density(orc_sim *s) {
   level_t *C = &s->L0, *F = &s->L1;
-  const int P0 = 2 * s->ext[0], Q0 = 2 * s->ext[1];
+  const int r = s->p.r;
+  const int P0 = r * s->ext[0], Q0 = r * s->ext[1];
   const int fw = F->nx, fh = F->ny;
   for (int i = 0; i <= fw; i++)
     for (int j = 0; j <= fh; j++) {
       if (i != 0 && i != fw && j != 0 && j != fh) continue;
-      NODE(F, n, i, j) = bilin(C->n, C->ny + 1, 0.5 * (P0 + i), 0.5 * (Q0 + j));
+      NODE(F, n, i, j) = bilin(C->n, C->ny + 1, (double)(P0 + i) / r, (double)(Q0 + j) / r);
     }
   for (int i = s->ext[0] + 1; i < s->ext[2]; i++)
     for (int j = s->ext[1] + 1; j < s->ext[3]; j++)
-      NODE(C, n, i, j) = NODE(F, n, 2 * (i - s->ext[0]), 2 * (j - s->ext[1]));
+      NODE(C, n, i, j) = NODE(F, n, r * (i - s->ext[0]), r * (j - s->ext[1]));
 }
 
 /* ---- self-aware expansion, Sec. III.A/B/D ------------------------------ */
@@ -743,7 +761,10 @@ static int build_patch(orc_sim *s, const int ne[4], const double *seed_fine) {
   const level_t *O = s->has_patch ? &s->L1 : NULL;
   const int oP0 = O ? r * s->ext[0] : 0, oQ0 = O ? r * s->ext[1] : 0;
   const int oP1 = O ? r * s->ext[2] : 0, oQ1 = O ? r * s->ext[3] : 0;
-  const double fr = 1.25; /* frac for Hz */
+  /* fine Hz after a coarse step sits at coarse n + 1 - 1/(2r): Eq. (5a)
+   * in time with frac 3/2 - 1/(2r) between Hz^{n-1/2} and Hz^{n+1/2}
+   * (5/4 for r = 2) */
+  const double fr = 1.5 - 0.5 / r;
   const int fgx = r * s->p.nx + 1;
 
   for (int i = 0; i < F.nx; i++)
@@ -752,7 +773,7 @@ static int build_patch(orc_sim *s, const int ne[4], const double *seed_fine) {
       if (O && P >= oP0 && P < oP1 && Q >= oQ0 && Q < oQ1) {
         HZ(&F, i, j) = HZ(O, P - oP0, Q - oQ0);
       } else {
-        double u = 0.5 * P - 0.25, v = 0.5 * Q - 0.25;
+        double u = (P + 0.5) / r - 0.5, v = (Q + 0.5) / r - 0.5;
         HZ(&F, i, j) = (1.0 - fr) * bilin(s->hz_prev, C->ny, u, v) +
                        fr * bilin(C->hz, C->ny, u, v);
       }
@@ -764,7 +785,7 @@ static int build_patch(orc_sim *s, const int ne[4], const double *seed_fine) {
         EX(&F, i, j) = EX(O, P - oP0, Q - oQ0);
         JX(&F, i, j) = JX(O, P - oP0, Q - oQ0);
       } else {
-        double u = 0.5 * P - 0.25, v = 0.5 * Q;
+        double u = (P + 0.5) / r - 0.5, v = (double)Q / r;
         EX(&F, i, j) = bilin(C->ex, C->ny + 1, u, v);
         JX(&F, i, j) = bilin(C->jx, C->ny + 1, u, v);
       }
@@ -776,7 +797,7 @@ static int build_patch(orc_sim *s, const int ne[4], const double *seed_fine) {
         EY(&F, i, j) = EY(O, P - oP0, Q - oQ0);
         JY(&F, i, j) = JY(O, P - oP0, Q - oQ0);
       } else {
-        double u = 0.5 * P, v = 0.5 * Q - 0.25;
+        double u = (double)P / r, v = (Q + 0.5) / r - 0.5;
         EY(&F, i, j) = bilin(C->ey, C->ny, u, v);
         JY(&F, i, j) = bilin(C->jy, C->ny, u, v);
       }
@@ -790,7 +811,7 @@ static int build_patch(orc_sim *s, const int ne[4], const double *seed_fine) {
         NODE(&F, acc, i, j) = NODE(O, acc, a, b);
         for (int k = 0; k < NRING; k++) RING(&F, k, i, j) = RING(O, k, a, b);
       } else {
-        double u = 0.5 * P, v = 0.5 * Q;
+        double u = (double)P / r, v = (double)Q / r;
         NODE(&F, n, i, j) = seed_fine ? seed_fine[(size_t)Q * fgx + P]
                                       : bilin(C->n, C->ny + 1, u, v);
         NODE(&F, acc, i, j) = bilin(C->acc, C->ny + 1, u, v);
@@ -799,12 +820,14 @@ static int build_patch(orc_sim *s, const int ne[4], const double *seed_fine) {
       }
     }
   if (s->has_patch) level_free(&s->L1);
-  free(s->hz_sub1);
+  free(s->hz_lo);
+  free(s->hz_hi);
   s->L1 = F;
-  s->hz_sub1 = calloc(n_hz(&F), sizeof(double));
+  s->hz_lo = calloc(n_hz(&F), sizeof(double));
+  s->hz_hi = calloc(n_hz(&F), sizeof(double));
   memcpy(s->ext, ne, sizeof(s->ext));
   s->has_patch = 1;
-  return s->hz_sub1 ? 0 : -2;
+  return s->hz_lo && s->hz_hi ? 0 : -2;
 }
 
 /* The threshold lines of Sec. III.D.  The lines coincide with the sides of
@@ -925,7 +948,8 @@ int orc_create(const orc_params *p, const double *seed_base,
   int spp = (int)floor(sppd + 0.5);
   if (fabs(sppd - spp) > 1e-9 || spp % NRING) return -1;
   if (p->mode != ORC_UNIFORM) {
-    if (p->r != 2 || p->block < 1 || p->nx % p->block || p->ny % p->block)
+    if ((p->r != 2 && p->r != 4) || p->block < 1 || p->nx % p->block ||
+        p->ny % p->block)
       return -1;
     if (p->bc_x == ORC_BC_PERIODIC || p->bc_y == ORC_BC_PERIODIC) return -1;
     if (p->mode == ORC_DYNAMIC && p->regrid_every % (spp / NRING)) return -1;
@@ -997,7 +1021,8 @@ void orc_destroy(orc_sim *s) {
   free(s->ex_old);
   free(s->ey_old);
   free(s->hz_prev);
-  free(s->hz_sub1);
+  free(s->hz_lo);
+  free(s->hz_hi);
   free(s->bflag);
   free(s->bscan);
   free(s->blist);

@@ -120,3 +120,51 @@ def test_interface_grows_without_fine_filter(oracle_mod):
     # the reason for the filter: sub-coarse modes trapped in the patch grow
     n = _perturbation_growth(oracle_mod, 0.0)
     assert n[-1] > 5.0 * n[0]
+
+
+# ---- refinement factor 4 (Sec. IV.C validates r = 2 and 4) -------------------
+def test_r4_vacuum_patch_reflection_and_stability(oracle_mod):
+    """Coarse lambda/16 with an r = 4 patch at lambda/64: the incident wave
+    crosses the patch without visible reflection, and stays bounded."""
+    cfg = W.make(64, 32, 16, "static", 1, r=4, block=8, static_ext=(24, 8, 48, 24),
+                 continuity_on=False)
+    E0 = oracle_mod.derived(cfg)["E0"]
+    s = oracle_mod.Sim(cfg, np.zeros((cfg["ny"] + 1, cfg["nx"] + 1)))
+    spp = cfg["steps_per_period"]
+    peaks = []
+    for per in range(1, 61):
+        s.step(spp)
+        if per >= 10 and per % 5 == 0:
+            ey = s.get("ey")
+            assert np.abs(ey[:, :cfg["tfsf_i"]]).max() < 0.01 * E0
+            peaks.append(np.abs(s.get("ey", 1)).max() / E0)
+    peaks = np.array(peaks)
+    assert peaks.max() < 1.01 and np.ptp(peaks) < 1e-3
+
+
+def test_r4_dmr_matches_uniform_fine_with_growth(oracle_mod):
+    """Coarse lambda/16 + r = 4 patch against the uniform lambda/64 mesh: the
+    density and E_rms^2 on the patch agree within 2% (Sec. IV.B reports
+    1-2%) after the patch has grown."""
+    dxc = LAM / 16
+    cfgd = W.make(48, 24, 16, "dynamic", 1, r=4, block=8, erms_over_ebd=2.5)
+    cfgu = W.make(192, 96, 64, "uniform", 1, erms_over_ebd=2.5)
+    cen, pk = [(29.75 * dxc, 12 * dxc)], [1e17]
+    sb, sf = W.seeds(cfgd, cen, pk)
+    su = W.seeds(cfgu, cen, pk)[0]
+    d = oracle_mod.Sim(cfgd, sb, sf)
+    u = oracle_mod.Sim(cfgu, su)
+    p0 = d.patch()
+    spp = cfgd["steps_per_period"]
+    d.step(60 * spp)
+    u.step(240 * spp)
+    p1 = d.patch()
+    assert p1 != p0
+    P0, Q0, P1, Q1 = (4 * v for v in p1)
+    nf, nu = d.get("n", 1), u.get("n")[Q0:Q1 + 1, P0:P1 + 1]
+    ef, eu = d.get("erms2", 1), u.get("erms2")[Q0:Q1 + 1, P0:P1 + 1]
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert nu.max() > 5e17
+    assert rel(nf, nu) < 0.02 and rel(ef, eu) < 0.02
+    nc = d.get("n", 0)[p1[1] + 1:p1[3], p1[0] + 1:p1[2]]
+    assert np.array_equal(nc, nf[4:-1:4, 4:-1:4])

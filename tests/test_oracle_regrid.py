@@ -144,11 +144,12 @@ def test_growth_is_monotone_union(oracle_mod):
     assert s.patch() == (24, 16, 72, 40)
 
 
-def test_prolongation_exact_and_copy(oracle_mod):
+@pytest.mark.parametrize("rf", [2, 4])
+def test_prolongation_exact_and_copy(oracle_mod, rf):
     """New fine data: bilinear (Eq. (5a)) from coarse, which reproduces linear
-    fields exactly; Hz at frac = 5/4 (coarse Hz^{n-1/2} is zero at t = 0);
-    old fine data is copied unchanged."""
-    cfg = _cfg()
+    fields exactly; Hz at frac = 3/2 - 1/(2r) (5/4 for r = 2; coarse
+    Hz^{n-1/2} is zero at t = 0); old fine data is copied unchanged."""
+    cfg = _cfg(r=rf)
     d = oracle_mod.derived(cfg)
     dx = d["dx"]
     big = 10 * cfg["n_thr_over_nc"] * d["n_c"]
@@ -174,7 +175,7 @@ def test_prolongation_exact_and_copy(oracle_mod):
     s.regrid()
     new = s.patch()
     assert new != old
-    P0, Q0, oP0, oQ0, oP1, oQ1 = 2 * new[0], 2 * new[1], 2 * old[0], 2 * old[1], 2 * old[2], 2 * old[3]
+    P0, Q0, oP0, oQ0, oP1, oQ1 = (rf * v for v in (new[0], new[1], old[0], old[1], old[2], old[3]))
     for f, (ox, oy) in pos.items():
         got = s.get(f, 1)
         r, c = got.shape
@@ -182,7 +183,7 @@ def test_prolongation_exact_and_copy(oracle_mod):
         hx = 1 if ox == 0.5 else 0   # half-offset entities end one short
         hy = 1 if oy == 0.5 else 0
         inold = (P >= oP0) & (P <= oP1 - hx) & (Q >= oQ0) & (Q <= oQ1 - hy)
-        want = lin((P + ox) * dx / 2, (Q + oy) * dx / 2) * (1.25 if f == "hz" else 1.0)
+        want = lin((P + ox) * dx / rf, (Q + oy) * dx / rf) * ((1.5 - 0.5 / rf) if f == "hz" else 1.0)
         assert np.allclose(got[~inold], want[~inold], rtol=1e-12, atol=1e-12), f
         a, b = P[inold] - oP0, Q[inold] - oQ0
         assert (got[inold] == marks[f][b, a]).all(), f
@@ -191,6 +192,6 @@ def test_prolongation_exact_and_copy(oracle_mod):
     r, c = nf.shape
     P, Q = np.meshgrid(P0 + np.arange(c), Q0 + np.arange(r))
     interp = RegularGridInterpolator((np.arange(cfg["ny"] + 1), np.arange(cfg["nx"] + 1)), n2)
-    want = interp(np.stack([Q.ravel() / 2, P.ravel() / 2], -1)).reshape(r, c)
+    want = interp(np.stack([Q.ravel() / rf, P.ravel() / rf], -1)).reshape(r, c)
     inold = (P >= oP0) & (P <= oP1) & (Q >= oQ0) & (Q <= oQ1)
     assert np.allclose(nf[~inold], want[~inold], rtol=1e-12)
