@@ -310,6 +310,20 @@ def main():
         "mcell_updates_per_s": work_t / wall_t / 1e6,
         "speedup_vs_uniform_fine": wall_u / wall_t}
 
+    # ---- refinement factor 4: coarse lambda/16 + lambda/64 patch -----------
+    log("DMR r = 4: coarse 256x128 at lambda/16, same uniform-fine reference")
+    cfg_4 = W.make(256, 128, 16, "dynamic", periods, r=4, block=8)
+    seeds_4 = W.seeds(cfg_4)
+    sim_4, wall_4, work_4 = run_case(B, cfg_4, seeds_4, K, cfg_4["regrid_every"], Wm, False)
+    ext_4 = sim_4.patch()
+    sim_4.close()
+    out["refinement_r4"] = {
+        "workload": "config-1 physics, coarse 256x128 @ lambda/16 + r=4 patch @ lambda/64 "
+                    "(block 8), %d periods, vs the uniform-fine 1024x512 run above" % periods,
+        "time_to_t_final_s": wall_4, "patch_final": list(ext_4),
+        "mcell_updates_per_s": work_4 / wall_4 / 1e6,
+        "speedup_vs_uniform_fine": wall_u / wall_4}
+
     # ---- bandwidth-bound shape: 4096x2048 coarse (added large row) --------
     if not args.no_large:
         log("4096x2048 kernel and DMR vs uniform-fine")

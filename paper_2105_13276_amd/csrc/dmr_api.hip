@@ -36,6 +36,7 @@ struct Level {
   size_t plane = 0;
   float *hz[2] = {}, *ex[2] = {}, *ey[2] = {}, *jx[2] = {}, *jy[2] = {};
   float *n[2] = {}, *acc = nullptr, *ring = nullptr;
+  float* hz_mid = nullptr;  // patch with r = 4: Hz after substep r/2
   double dx = 0, dt = 0;
   int spp = 0, spb = 0;
   float S = 0, c1 = 0, a = 0, kn = 0, cmur = 0;
@@ -68,7 +69,7 @@ Layout layout_of(const dmr_params* p) {
   size_t stage = L.plane0;
   if (refined(p)) {
     L.plane1 = plane_floats(p->r * p->nx, p->r * p->ny, &L.pitch1);
-    off += align256(L.plane1 * kPlanes * sizeof(float));
+    off += align256(L.plane1 * (kPlanes + (p->r > 2 ? 1 : 0)) * sizeof(float));
     stage = L.plane1;
     L.NB = (p->nx / p->block) * (p->ny / p->block);
   }
@@ -109,7 +110,7 @@ int check_params(const dmr_params* p, std::string* why) {
     return bad("Townsend source needs A_town >= 0, B_town > 0, nu_att >= 0");
   if (!(p->beta_rec >= 0.0) || p->beta_rec > 2.0) return bad("beta_rec must be in [0, 2]");
   if (refined(p)) {
-    if (p->r != 2) return bad("only r = 2 is supported");
+    if (p->r != 2 && p->r != 4) return bad("r must be 2 or 4");
     if (p->block < 2 || p->nx % p->block || p->ny % p->block)
       return bad("block must divide nx and ny");
     if (p->nx / p->block < 3 || p->ny / p->block < 3)
@@ -287,6 +288,7 @@ void carve(dmr_sim* s, Level* L, size_t off, size_t plane, int pitch, int NX,
   }
   L->acc = q; q += plane;
   L->ring = q;
+  L->hz_mid = q + (size_t)kRing * plane;  // allocated for the r = 4 patch only
 }
 
 // incident Ey at (x, t): E0 g(t - x/c) sin(w t - k~ x), sin^2 ramp g
@@ -378,6 +380,7 @@ int prolong(dmr_sim* s, const int ne[4], bool keep_n) {
   A.pitch = F.pitch; A.cpitch = C.pitch;
   A.plane = F.plane; A.cplane = C.plane;
   A.keep_n = keep_n ? 1 : 0;
+  A.rf = r;
   const int c = s->ccur;
   A.chz = C.hz[c]; A.chz_prev = C.hz[1 - c];
   A.cex = C.ex[c]; A.cey = C.ey[c]; A.cjx = C.jx[c]; A.cjy = C.jy[c];
@@ -520,6 +523,9 @@ void make_fine_em(const dmr_sim* s, int m, int c, int nc, int ty, EMArgs* G) {
   G->cpitch = C.pitch;
   G->frac = (float)m / (float)r;
   G->gamma = (float)p.fine_filter;
+  G->rf = r;
+  if (r > 2 && m == r / 2) G->hz_save = F.hz_mid;
+  if (r > 2 && m == r) G->hz_lo = F.hz_mid;
   if (m == r) {
     G->restrict_on = 1;
     G->chz = C.hz[1 - c]; G->cex = C.ex[1 - c]; G->cey = C.ey[1 - c];
@@ -579,6 +585,7 @@ void make_fine_cont(const dmr_sim* s, int nc, ContArgs* G) {
   G->dtn = (float)(F.spb * F.dt);
   G->inv_dx2 = (float)(1.0 / (F.dx * F.dx));
   G->cn1 = C.n[1 - nc]; G->cpitch = C.pitch;
+  G->rf = p.r;
   G->nbx = (G->R - G->L + 1 + kTX - 1) / kTX;
 }
 
@@ -884,6 +891,7 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   // bandwidth-bound grids the base kernel's own launch shape is faster
   s->combine = (long)p->nx * p->ny <= (1L << 21);
   if (const char* f = getenv("DMR_COMBINE")) s->combine = atoi(f) != 0;
+  if (p->r != 2) s->fuse_fine = s->combine = false;  // the fused forms are r = 2
   if (const char* f = getenv("DMR_FNT")) s->nt1 = atoi(f) >= 1024 ? 1024 : 256;
   s->depth0 = stream_depth(s->seg0);
   hipError_t e = hipMemsetAsync(s->ws, 0, lay.total, s->st);
@@ -1487,6 +1495,7 @@ int dmr_forward_record(dmr_sim* s, int64_t steps, int ckpt_every, void* d_tape, 
   if (s->step != 0) return fail(s, DMR_EINVAL, "recording starts at t = 0 (fresh handle)");
   if (s->p.source_model != DMR_SOURCE_POWER || s->p.beta_rec > 0.0)
     return fail(s, DMR_EINVAL, "the adjoint supports the power-law source without recombination");
+  if (refined(&s->p) && s->p.r != 2) return fail(s, DMR_EINVAL, "the adjoint supports r = 2");
   if (!d_tape || ((uintptr_t)d_tape & 255)) return fail(s, DMR_EINVAL, "tape must be 256-byte aligned");
   const TapeLayout T = tape_layout(&s->p, steps, ckpt_every);
   if (bytes < T.total) return fail(s, DMR_ENOMEM, "tape needs %zu bytes", T.total);
@@ -1778,6 +1787,7 @@ int batch_layout(const dmr_params* p, int count, BatchLayout* L, std::string* wh
   for (int k = 0; k < count; k++) {
     int rc = check_params(&p[k], why);
     if (rc) return rc;
+    if (refined(&p[k]) && p[k].r != 2) { *why = "the batched form supports r = 2"; return DMR_EINVAL; }
     const double spp0 = p[0].cells_per_lambda / p[0].courant;
     const double sppk = p[k].cells_per_lambda / p[k].courant;
     if (std::fabs(spp0 - sppk) > 1e-9 || p[k].mode != p[0].mode ||

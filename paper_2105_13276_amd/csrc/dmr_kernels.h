@@ -47,6 +47,12 @@ struct EMArgs {
   const float *chz0, *cjx0, *cjy0, *cn0;
   float cS, cc1, ckn, cey_src, chz_src;
   int cis, cnx, cny;
+  // refinement factor of the patch (0 or 2: r = 2; 4).  r = 4: substep r/2
+  // saves its new Hz (hz_save), the last substep reads it back (hz_lo): the
+  // two half levels around coarse n+1/2 are after substeps r/2 and r/2 + 1
+  int rf;
+  float* hz_save;
+  const float* hz_lo;
   // replay for the adjoint (null: off): the step's values it needs, written
   // at the entity's own position.  Base level: E entering (sti), E after the
   // step before the fine -> coarse transfer (sto), n.  Patch (both
@@ -80,6 +86,7 @@ struct ContArgs {
   int* err;        // 64 flags, set on non-finite values
   float* cn1;      // fine level: coarse density after its update
   int cpitch;
+  int rf;          // fine level: refinement factor (0 or 2: r = 2; 4)
   int nbx;         // batched launches: blocks per row of blocks
 };
 
@@ -103,6 +110,7 @@ struct ProlongArgs {
   int pitch, cpitch;
   size_t plane, cplane;
   int keep_n;
+  int rf;              // refinement factor (0 or 2: r = 2; 4)
   const float *chz, *chz_prev, *cex, *cey, *cjx, *cjy, *cn, *cacc, *cring;
   float *hz, *ex, *ey, *jx, *jy, *n, *acc, *ring;
 };

@@ -181,13 +181,27 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   size_t bco = 0, bco2 = 0;
   float bw0 = 0.f, bw1 = 0.f;
   bool bvalid = false;
+  // fine edge q of the line at coarse position (q + 1/2)/r - 1/2 between
+  // coarse edges c and c + 1 (offsets 1/(2r), Fig. 5(c))
+  auto cfb_w = [&](int q, int& c) {
+    if (A.rf == 4) {
+      const int m = q & 3;
+      c = (q >> 2) - (m < 2 ? 1 : 0);
+      bw0 = m == 0 ? 0.375f : m == 1 ? 0.125f : m == 2 ? 0.875f : 0.625f;
+      bw1 = 1.f - bw0;
+    } else if ((q & 1) == 0) {
+      c = (q >> 1) - 1; bw0 = 0.25f; bw1 = 0.75f;
+    } else {
+      c = q >> 1; bw0 = 0.75f; bw1 = 0.25f;
+    }
+  };
+  const int rsh = A.rf == 4 ? 2 : 1;  // fine -> coarse index on a line
   if (bg == 0 || bg == 1) {
     const int i = i0 - 1 + bc, j = bg == 0 ? B : T;
     if (ex_ok(i, j) && j >= j0 - 1 && j < j0 + TY) {
-      const int J = j >> 1;
+      const int J = j >> rsh;
       int ic;
-      if ((i & 1) == 0) { ic = (i >> 1) - 1; bw0 = 0.25f; bw1 = 0.75f; }
-      else              { ic = i >> 1;       bw0 = 0.75f; bw1 = 0.25f; }
+      cfb_w(i, ic);
       bco = (size_t)J * A.cpitch + ic;
       bco2 = bco + 1;
       bvalid = true;
@@ -195,10 +209,9 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   } else if (bg >= 2) {
     const int j = j0 - 1 + bc, i = bg == 2 ? L : R;
     if (ey_ok(i, j) && i >= i0 - 1 && i < i0 + kTX) {
-      const int I = i >> 1;
+      const int I = i >> rsh;
       int jc;
-      if ((j & 1) == 0) { jc = (j >> 1) - 1; bw0 = 0.25f; bw1 = 0.75f; }
-      else              { jc = j >> 1;       bw0 = 0.75f; bw1 = 0.25f; }
+      cfb_w(j, jc);
       bco = (size_t)jc * A.cpitch + I;
       bco2 = bco + A.cpitch;
       bvalid = true;
@@ -309,7 +322,10 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
         const float dex = sExo[cj + 1][ci] - sExo[cj][ci];
         ho = phz[q];
         h = faraday(ho, A.S, dey, dex);
-        if (ci >= 2 && cj >= 2) A.hz1[o] = h;
+        if (ci >= 2 && cj >= 2) {
+          A.hz1[o] = h;
+          if (A.hz_save) A.hz_save[o] = h;
+        }
       }
       sH[cj][ci] = h;
       sHo[cj][ci] = ho;
@@ -388,7 +404,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   }
 
   // -- fine -> coarse transfer after the last substep ------------------------
-  if (A.restrict_on) {
+  if (A.restrict_on && A.rf != 4) {
     for (int r = ty; r < TY; r += RP) {
       const int i = i0 + tx, j = j0 + r;
       if (((i - L) | (j - B)) & 1) continue;
@@ -411,6 +427,37 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
       if (ey_ok(i, j) && i > L && i < R) {
         A.cey[co] = 0.5f * (sEyn[cj][ci] + sEyn[cj + 1][ci]);
         A.cjy[co] = sJy[r][tx] + sJy[r + 1][tx];
+      }
+    }
+  } else if (A.restrict_on) {
+    // r = 4: 4 x 4 cells and the half levels after substeps 2 (hz_lo, global)
+    // and 3 (the Hz entering this last substep); 4 edges, J~ summed
+    for (int r = ty; r < TY; r += RP) {
+      const int i = i0 + tx, j = j0 + r;
+      if (((i - L) | (j - B)) & 3) continue;
+      const int a = i >> 2, b = j >> 2;
+      const size_t co = (size_t)b * A.cpitch + a;
+      const int ci = tx + 1, cj = r + 1;
+      if (hz_ok(i, j)) {
+        float s = 0.f;
+        for (int da = 0; da < 4; da++)
+          for (int db = 0; db < 4; db++) {
+            const float lo = A.hz_lo[(size_t)(j + db) * pitch + i + da];
+            s += 0.5f * (lo + sHo[r + 2 + db][tx + 2 + da]);
+          }
+        A.chz[co] = 0.0625f * s;
+      }
+      if (ex_ok(i, j) && j > B && j < T) {
+        float se = 0.f, sj = 0.f;
+        for (int da = 0; da < 4; da++) { se += sExn[cj][ci + da]; sj += sJx[r][tx + da]; }
+        A.cex[co] = 0.25f * se;
+        A.cjx[co] = sj;
+      }
+      if (ey_ok(i, j) && i > L && i < R) {
+        float se = 0.f, sj = 0.f;
+        for (int db = 0; db < 4; db++) { se += sEyn[cj + db][ci]; sj += sJy[r + db][tx]; }
+        A.cey[co] = 0.25f * se;
+        A.cjy[co] = sj;
       }
     }
   }
@@ -1033,7 +1080,15 @@ __device__ __forceinline__ void cont_body(const ContArgs& A, int bx, int by, int
   for (int s = 0; s < kRing; s++)
     e2 += (s == slot) ? sv : A.ring[(size_t)s * A.plane + o];
   float nn;
-  if (FINE && (i == A.L || i == A.R || j == A.B || j == A.T)) {
+  if (FINE && A.rf == 4 && (i == A.L || i == A.R || j == A.B || j == A.T)) {
+    // linear along the boundary line between the two coarse nodes
+    const int a = i >> 2, b = j >> 2, cp = A.cpitch;
+    const float ti = (i & 3) * 0.25f, tj = (j & 3) * 0.25f;
+    const float c00 = A.cn1[(size_t)b * cp + a];
+    if ((i & 3) != 0) nn = (1.f - ti) * c00 + ti * A.cn1[(size_t)b * cp + a + 1];
+    else if ((j & 3) != 0) nn = (1.f - tj) * c00 + tj * A.cn1[(size_t)(b + 1) * cp + a];
+    else nn = c00;
+  } else if (FINE && (i == A.L || i == A.R || j == A.B || j == A.T)) {
     const int a = i >> 1, b = j >> 1, cp = A.cpitch;
     if (((i | j) & 1) == 0) nn = A.cn1[(size_t)b * cp + a];
     else if (i & 1) nn = 0.5f * (A.cn1[(size_t)b * cp + a] + A.cn1[(size_t)b * cp + a + 1]);
@@ -1060,8 +1115,9 @@ __device__ __forceinline__ void cont_body(const ContArgs& A, int bx, int by, int
       nn = ni + A.dtn * (flux * A.inv_dx2 + (nu - A.rei * ni) * ni);
     }
     nn = nn > 0.f ? nn : 0.f;
-    if (FINE && (((i - A.L) | (j - A.B)) & 1) == 0) {
-      const int a = i >> 1, b = j >> 1;  // strictly inside: interior even node
+    const int rm = A.rf == 4 ? 3 : 1, rs = A.rf == 4 ? 2 : 1;
+    if (FINE && (((i - A.L) | (j - A.B)) & rm) == 0) {
+      const int a = i >> rs, b = j >> rs;  // strictly inside: coincident node
       A.cn1[(size_t)b * A.cpitch + a] = nn;
     }
   }
@@ -1214,9 +1270,11 @@ __global__ __launch_bounds__(1024) void k_scan_bbox(ScanArgs A) {
 // coarse units: fine index P -> 2P (on a coarse line) or 2P - 1 (a quarter
 // below the next coarse half-point).
 // ---------------------------------------------------------------------------
-__device__ inline float bilin4(const float* a, int pitch, int U4, int V4) {
-  const int i = U4 >> 2, j = V4 >> 2;
-  const float fu = (U4 & 3) * 0.25f, fv = (V4 & 3) * 0.25f;
+// Eq. (5a) at (U, V) / D in coarse index units (D = 2r: offsets 1/(2r))
+__device__ inline float bilin4(const float* a, int pitch, int U4, int V4, int D = 4) {
+  const int i = U4 / D, j = V4 / D;
+  const float inv = D == 4 ? 0.25f : 0.125f;
+  const float fu = (U4 % D) * inv, fv = (V4 % D) * inv;
   float v = 0.f;
   for (int di = 0; di < 2; di++) {
     const float wu = di ? fu : 1.f - fu;
@@ -1240,24 +1298,32 @@ __global__ __launch_bounds__(kThreads) void k_prolong(ProlongArgs A) {
   auto in_old = [&](int hx, int hy) {  // hx/hy: entity ends one short
     return old && i >= A.oL && i <= A.oR - hx && j >= A.oB && j <= A.oT - hy;
   };
+  // positions in units of 1/(2r) coarse cells: a fine node i sits at 2i; a
+  // fine half-offset entity at (i + 1/2)/r - 1/2 coarse half-offset
+  // entities, i.e. at 2i + 1 - r
+  const int D = A.rf == 4 ? 8 : 4, h = A.rf == 4 ? 3 : 1;
+  // fine Hz after a coarse step sits at coarse n + 1 - 1/(2r): frac 3/2 - 1/(2r)
+  const float fr = A.rf == 4 ? 1.375f : 1.25f;
+  const float jsc = A.rf == 4 ? 0.25f : 0.5f;  // J~ scales with dt
   if (i < A.R && j < A.T && !in_old(1, 1)) {
-    const float hp = bilin4(A.chz_prev, cp, 2 * i - 1, 2 * j - 1);
-    const float hn = bilin4(A.chz, cp, 2 * i - 1, 2 * j - 1);
-    A.hz[o] = (1.f - 1.25f) * hp + 1.25f * hn;
+    const float hp = bilin4(A.chz_prev, cp, 2 * i - h, 2 * j - h, D);
+    const float hn = bilin4(A.chz, cp, 2 * i - h, 2 * j - h, D);
+    A.hz[o] = (1.f - fr) * hp + fr * hn;
   }
   if (i < A.R && !in_old(1, 0)) {
-    A.ex[o] = bilin4(A.cex, cp, 2 * i - 1, 2 * j);
-    A.jx[o] = 0.5f * bilin4(A.cjx, cp, 2 * i - 1, 2 * j);  // J~ scales with dt
+    A.ex[o] = bilin4(A.cex, cp, 2 * i - h, 2 * j, D);
+    A.jx[o] = jsc * bilin4(A.cjx, cp, 2 * i - h, 2 * j, D);
   }
   if (j < A.T && !in_old(0, 1)) {
-    A.ey[o] = bilin4(A.cey, cp, 2 * i, 2 * j - 1);
-    A.jy[o] = 0.5f * bilin4(A.cjy, cp, 2 * i, 2 * j - 1);
+    A.ey[o] = bilin4(A.cey, cp, 2 * i, 2 * j - h, D);
+    A.jy[o] = jsc * bilin4(A.cjy, cp, 2 * i, 2 * j - h, D);
   }
   if (!in_old(0, 0)) {
-    if (!A.keep_n) A.n[o] = bilin4(A.cn, cp, 2 * i, 2 * j);
-    A.acc[o] = bilin4(A.cacc, cp, 2 * i, 2 * j);
+    if (!A.keep_n) A.n[o] = bilin4(A.cn, cp, 2 * i, 2 * j, D);
+    A.acc[o] = bilin4(A.cacc, cp, 2 * i, 2 * j, D);
     for (int s = 0; s < kRing; s++)
-      A.ring[(size_t)s * A.plane + o] = bilin4(A.cring + (size_t)s * A.cplane, cp, 2 * i, 2 * j);
+      A.ring[(size_t)s * A.plane + o] =
+          bilin4(A.cring + (size_t)s * A.cplane, cp, 2 * i, 2 * j, D);
   }
 }
 
