@@ -194,6 +194,7 @@ struct dmr_sim {
   bool fuse_fine = true;
   // base-level step and both patch substeps in one launch (dmr_step only)
   bool combine = true;
+  long fuse_max = 1L << 20;  // fine cells up to which the two-substep launch is used
   int nt1 = 1024;  // threads per patch tile
   uint8_t* d_flag = nullptr;
   int32_t *d_scan = nullptr, *d_list = nullptr;
@@ -619,9 +620,15 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
     cx->meta.has = s->has_patch;
     for (int q = 0; q < 4; q++) cx->meta.ext[q] = s->ext[q];
   }
+  // the two-substep tile keeps a 7-cell halo in LDS (one block per CU): it
+  // wins where the patch is small and the step latency-bound; large patches
+  // stream better as two one-substep launches
+  const bool fuse = s->has_patch && s->fuse_fine &&
+                    (long)p.r * p.r * (s->ext[2] - s->ext[0]) * (s->ext[3] - s->ext[1]) <=
+                        s->fuse_max;
   // replay: the fused kernels store the step's values themselves; the
   // one-substep form takes copies
-  const bool kst = st && (!s->has_patch || s->fuse_fine);
+  const bool kst = st && (!s->has_patch || fuse);
   if (st && !kst) {
     CopyJobs J{};
     const size_t n0 = s->L0.plane;
@@ -653,7 +660,7 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
     G->stn = cx->ss.fn;
   };
   // the fused forms are bit-identical to the separate launches
-  const bool combined = s->has_patch && s->combine && s->fuse_fine;
+  const bool combined = fuse && s->combine;
   if (combined) {  // base step and both patch substeps, one launch
     Level &C = s->L0, &F = s->L1;
     A.skip_on = 1;
@@ -690,7 +697,7 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
   }
   if (combined) {
     // done above
-  } else if (s->has_patch && s->fuse_fine) {  // both substeps, one launch
+  } else if (fuse) {  // both substeps, one launch
     Level& F = s->L1;
     EMArgs G;
     make_fine_em(s, p.r, c, s->ncur, s->ty1, &G);  // restriction targets
@@ -892,6 +899,7 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   s->combine = (long)p->nx * p->ny <= (1L << 21);
   if (const char* f = getenv("DMR_COMBINE")) s->combine = atoi(f) != 0;
   if (p->r != 2) s->fuse_fine = s->combine = false;  // the fused forms are r = 2
+  if (const char* f = getenv("DMR_FUSE_MAX")) s->fuse_max = atol(f);
   if (const char* f = getenv("DMR_FNT")) s->nt1 = atoi(f) >= 1024 ? 1024 : 256;
   s->depth0 = stream_depth(s->seg0);
   hipError_t e = hipMemsetAsync(s->ws, 0, lay.total, s->st);
