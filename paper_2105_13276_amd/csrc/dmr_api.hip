@@ -623,9 +623,10 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
   // the two-substep tile keeps a 7-cell halo in LDS (one block per CU): it
   // wins where the patch is small and the step latency-bound; large patches
   // stream better as two one-substep launches
-  const bool fuse = s->has_patch && s->fuse_fine &&
-                    (long)p.r * p.r * (s->ext[2] - s->ext[0]) * (s->ext[3] - s->ext[1]) <=
-                        s->fuse_max;
+  const long fine_cells =
+      s->has_patch ? (long)p.r * p.r * (s->ext[2] - s->ext[0]) * (s->ext[3] - s->ext[1]) : 0;
+  const bool big = fine_cells > s->fuse_max;
+  const bool fuse = s->has_patch && s->fuse_fine && !big;
   // replay: the fused kernels store the step's values themselves; the
   // one-substep form takes copies
   const bool kst = st && (!s->has_patch || fuse);
