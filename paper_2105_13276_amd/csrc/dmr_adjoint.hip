@@ -156,6 +156,39 @@ __device__ inline void cfb_load(const AdjEMArgs& A, const float* gf, int i, int 
     v[q] = X ? gf[(size_t)f * A.fpitch + fc] : gf[(size_t)fc * A.fpitch + f];
   }
 }
+// G of patch substep 1 at the fine boundary edges of coarse edge (i, j):
+// lam E + the window terms + 2 k lam J, the patch kernel's expression for a
+// boundary edge (substep 1 has no fine -> coarse fold)
+template <bool X>
+__device__ inline void cfb_g1(const AdjEMArgs& A, int i, int j, float v[4]) {
+  const int c = X ? i : j, line = X ? j : i;
+  const int l0 = X ? A.J0 : A.I0, l1 = X ? A.J1 : A.I1;
+  const int lo = X ? A.fL : A.fB, hi = X ? A.fR : A.fT;
+  const int f = 2 * (line < l0 ? l0 : (line > l1 ? l1 : line));
+  const int p = A.fpitch;
+  float le[4], en[4], a0[4], a1[4], n0[4], n1[4], lj[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    int fc = 2 * c - 1 + q;
+    fc = fc < lo ? lo : (fc > hi ? hi : fc);
+    const int fc1 = fc + 1 > hi ? hi : fc + 1;
+    const size_t o = X ? (size_t)f * p + fc : (size_t)fc * p + f;
+    const size_t o1 = X ? (size_t)f * p + fc1 : (size_t)fc1 * p + f;
+    le[q] = X ? A.s1ex[o] : A.s1ey[o];
+    lj[q] = X ? A.s1jx[o] : A.s1jy[o];
+    en[q] = X ? A.s1exo[o] : A.s1eyo[o];
+    a0[q] = A.s1acc[o]; a1[q] = A.s1acc[o1];
+    n0[q] = A.s1n[o]; n1[q] = A.s1n[o1];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const int fc = 2 * c - 1 + q;
+    const float kap = A.s1kn * (0.5f * (n0[q] + n1[q]));
+    const float tot = le[q] + 2.f * en[q] * (wwin(fc, lo, hi) * a0[q] + wwin(fc + 1, lo, hi) * a1[q]);
+    v[q] = tot + 2.f * kap * lj[q];
+  }
+}
+
 template <bool X>
 __device__ inline float cfb_sum(const AdjEMArgs& A, const float v[4], int i, int j) {
   const int c = X ? i : j, line = X ? j : i;
@@ -224,8 +257,8 @@ __device__ inline void p1_load(const AdjEMArgs& A, const Reg& g, int i, int j, P
 #pragma unroll
     for (int q = 0; q < 4; q++) { v.c1x[q] = v.c2x[q] = v.c1y[q] = v.c2y[q] = 0.f; }
     if (cfb) {
-      cfb_load<true>(A, A.g1x, i, j, v.c1x); cfb_load<true>(A, A.g2x, i, j, v.c2x);
-      cfb_load<false>(A, A.g1y, i, j, v.c1y); cfb_load<false>(A, A.g2y, i, j, v.c2y);
+      cfb_g1<true>(A, i, j, v.c1x); cfb_load<true>(A, A.g2x, i, j, v.c2x);
+      cfb_g1<false>(A, i, j, v.c1y); cfb_load<false>(A, A.g2y, i, j, v.c2y);
     }
   }
 }
@@ -332,7 +365,7 @@ __device__ inline void p2_load(const AdjEMArgs& A, const Reg& g, int i, int j, P
 }
 
 template <bool FINE>
-__global__ __launch_bounds__(AdjTile<FINE>::NT) void k_adj_em(AdjEMArgs A) {
+__device__ __forceinline__ void adj_em_tile(const AdjEMArgs& A, int bx, int by) {
   using Tl = AdjTile<FINE>;
   constexpr int TX = Tl::TX, TY = Tl::TY, H1 = Tl::H1, H2 = Tl::H2;
   constexpr int W1 = Tl::W1, N1 = Tl::N1, W2 = Tl::W2, N2 = Tl::N2;
@@ -341,7 +374,7 @@ __global__ __launch_bounds__(AdjTile<FINE>::NT) void k_adj_em(AdjEMArgs A) {
   __shared__ float stx[FINE ? N2 : 1][FINE ? W2 : 1], sty[FINE ? N2 : 1][FINE ? W2 : 1];
   const Reg g{A.L, A.B, A.R, A.T, A.pitch};
   const int L = A.L, R = A.R, B = A.B, T = A.T;
-  const int i0 = L + blockIdx.x * TX, j0 = B + blockIdx.y * TY;
+  const int i0 = L + bx * TX, j0 = B + by * TY;
   const int tid = threadIdx.x;
   const float S = A.S;
   const bool filt = FINE && A.gamma > 0.f;
@@ -863,6 +896,31 @@ dim3 node_grid(int L, int B, int R, int T) {
 }
 
 }  // namespace
+
+template <bool FINE>
+__global__ __launch_bounds__(AdjTile<FINE>::NT) void k_adj_em(AdjEMArgs A) {
+  adj_em_tile<FINE>(A, blockIdx.x, blockIdx.y);
+}
+
+// patch substep 1 (blocks [0, nbf)) and the base level (the rest) of a base
+// step: independent (the base level forms substep 1's boundary G itself)
+__global__ __launch_bounds__(1024) void k_adj_em_pair(AdjEMArgs F, AdjEMArgs C, int nbf,
+                                                      int nbfx, int nbcx) {
+  static_assert(AdjTile<true>::NT == 1024 && AdjTile<false>::NT == 1024, "one block shape");
+  const int b = blockIdx.x;
+  if (b < nbf) adj_em_tile<true>(F, b % nbfx, b / nbfx);
+  else adj_em_tile<false>(C, (b - nbf) % nbcx, (b - nbf) / nbcx);
+}
+
+hipError_t launch_adj_em_pair(const AdjEMArgs& F, const AdjEMArgs& C, hipStream_t st) {
+  using TF = AdjTile<true>;
+  using TC = AdjTile<false>;
+  const int nbfx = (F.R - F.L + TF::TX) / TF::TX, nbfy = (F.T - F.B + TF::TY) / TF::TY;
+  const int nbcx = (C.R - C.L + TC::TX) / TC::TX, nbcy = (C.T - C.B + TC::TY) / TC::TY;
+  const int nbf = nbfx * nbfy;
+  k_adj_em_pair<<<nbf + nbcx * nbcy, 1024, 0, st>>>(F, C, nbf, nbfx, nbcx);
+  return hipGetLastError();
+}
 
 hipError_t launch_adj_em(const AdjEMArgs& A, hipStream_t st) {
   if (A.fine) {

@@ -1382,27 +1382,29 @@ int adj_step(dmr_sim* s, const TapeLayout& T, AdjLevel& ac, AdjLevel& af, int kk
     }
     if (e != hipSuccess) return hipfail(s, e, "adjoint continuity launch");
   }
-  if (m.has) {  // substeps 2 and 1 (the fine -> coarse transfer folded into 2)
-    for (int sub = r; sub >= 1; sub--) {
-      AdjEMArgs A = adj_em_args(s, F, af, true, freg);
-      A.exi = sub == 2 ? ss.fex1 : ss.fex0;
-      A.eyi = sub == 2 ? ss.fey1 : ss.fey0;
-      // E after substep 2 = the next step's stored E entering (the last
-      // step of a segment stores it itself)
-      A.exo = sub == 2 ? (nxt ? nxt->fex0 : ss.fex2) : ss.fex1;
-      A.eyo = sub == 2 ? (nxt ? nxt->fey0 : ss.fey2) : ss.fey1;
-      A.n = ss.fn;
-      A.gx = sub == 2 ? af.g2x : af.gx;
-      A.gy = sub == 2 ? af.g2y : af.gy;
-      A.I0 = m.ext[0]; A.J0 = m.ext[1]; A.I1 = m.ext[2]; A.J1 = m.ext[3];
-      A.cpitch = C.pitch;
-      if (sub == 2) {
-        A.rhz = ac.hz[ac.cur]; A.rex = ac.ex; A.rey = ac.ey; A.rjx = ac.jx; A.rjy = ac.jy;
-      }
-      e = launch_adj_em(A, s->st);
-      if (e != hipSuccess) return hipfail(s, e, "adjoint fine EM launch");
-      af.flip();
+  // patch substep m's adjoint arguments
+  auto fine_args = [&](int sub) {
+    AdjEMArgs A = adj_em_args(s, F, af, true, freg);
+    A.exi = sub == 2 ? ss.fex1 : ss.fex0;
+    A.eyi = sub == 2 ? ss.fey1 : ss.fey0;
+    // E after substep 2 = the next step's stored E entering (the last
+    // step of a segment stores it itself)
+    A.exo = sub == 2 ? (nxt ? nxt->fex0 : ss.fex2) : ss.fex1;
+    A.eyo = sub == 2 ? (nxt ? nxt->fey0 : ss.fey2) : ss.fey1;
+    A.n = ss.fn;
+    A.gx = sub == 2 ? af.g2x : af.gx;
+    A.gy = sub == 2 ? af.g2y : af.gy;
+    A.I0 = m.ext[0]; A.J0 = m.ext[1]; A.I1 = m.ext[2]; A.J1 = m.ext[3];
+    A.cpitch = C.pitch;
+    if (sub == 2) {  // the fine -> coarse transfer folded into substep 2
+      A.rhz = ac.hz[ac.cur]; A.rex = ac.ex; A.rey = ac.ey; A.rjx = ac.jx; A.rjy = ac.jy;
     }
+    return A;
+  };
+  if (m.has) {  // substep 2
+    e = launch_adj_em(fine_args(2), s->st);
+    if (e != hipSuccess) return hipfail(s, e, "adjoint fine EM launch");
+    af.flip();
   }
   AdjEMArgs A = adj_em_args(s, C, ac, false, creg);
   A.exi = ss.cexi; A.eyi = ss.ceyi; A.exo = ss.cexp; A.eyo = ss.ceyp; A.n = ss.cn;
@@ -1412,15 +1414,25 @@ int adj_step(dmr_sim* s, const TapeLayout& T, AdjLevel& ac, AdjLevel& af, int kk
     A.I0 = m.ext[0]; A.J0 = m.ext[1]; A.I1 = m.ext[2]; A.J1 = m.ext[3];
     A.fL = freg[0]; A.fB = freg[1]; A.fR = freg[2]; A.fT = freg[3];
     A.fpitch = F.pitch;
-    A.g1x = af.gx; A.g1y = af.gy; A.g2x = af.g2x; A.g2y = af.g2y;
+    A.g2x = af.g2x; A.g2y = af.g2y;
+    // substep 1's boundary G from its inputs (lam leaving it: after the flip)
+    A.s1ex = af.ex; A.s1ey = af.ey; A.s1jx = af.jx; A.s1jy = af.jy;
+    A.s1exo = ss.fex1; A.s1eyo = ss.fey1; A.s1acc = af.acc; A.s1n = ss.fn;
+    A.s1kn = F.kn;
   }
   if (p.tfsf_i > 0) {
     float* src = (float*)(s->tape.base + T.src + T.src_size * (size_t)kk);
     A.src_e = src;
     A.src_h = src + p.ny;
   }
-  e = launch_adj_em(A, s->st);
-  if (e != hipSuccess) return hipfail(s, e, "adjoint base EM launch");
+  if (m.has) {  // substep 1 and the base level: one launch
+    e = launch_adj_em_pair(fine_args(1), A, s->st);
+    if (e != hipSuccess) return hipfail(s, e, "adjoint EM launch");
+    af.flip();
+  } else {
+    e = launch_adj_em(A, s->st);
+    if (e != hipSuccess) return hipfail(s, e, "adjoint base EM launch");
+  }
   ac.flip();
   return DMR_OK;
 }

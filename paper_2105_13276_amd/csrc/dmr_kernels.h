@@ -179,7 +179,12 @@ struct AdjEMArgs {
   // Eq. (5b) boundary values transposed are gathered from the patch g of
   // the two substeps on the fine cells fL..fR x fB..fT
   int has_patch, fL, fB, fR, fT, fpitch;
-  const float *g1x, *g1y, *g2x, *g2y;
+  const float *g2x, *g2y;  // patch g of substep 2 (its boundary G)
+  // substep 1's boundary G is computed here from its inputs (it does not
+  // depend on substep 1's H'), so substep 1 can run in the same launch:
+  // lam E, lam J leaving substep 1, E after it, lam acc, n, and the patch kn
+  const float *s1ex, *s1ey, *s1jx, *s1jy, *s1exo, *s1eyo, *s1acc, *s1n;
+  float s1kn;
 };
 
 struct AdjGrowArgs {
@@ -228,6 +233,8 @@ struct CopyJobs {
 };
 
 hipError_t launch_adj_em(const AdjEMArgs& A, hipStream_t st);
+// patch substep 1 (F) and the base level (C) of one base step in one launch
+hipError_t launch_adj_em_pair(const AdjEMArgs& F, const AdjEMArgs& C, hipStream_t st);
 hipError_t launch_adj_grow(const AdjGrowArgs& A, hipStream_t st);
 hipError_t launch_adj_grow_clear(const AdjGrowArgs& A, float* lhz, float* lex, float* ley,
                                  float* ljx, float* ljy, float* ln, float* lacc,
