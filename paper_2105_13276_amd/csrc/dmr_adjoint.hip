@@ -668,11 +668,18 @@ __global__ __launch_bounds__(kThreads) void k_adj_inj(AdjInjArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// Window close and continuity step (Eq. (4)) transposed.
-// Pass 1 (per node): clamp mask, ell = mask * lam n', the E_rms^2 lam into
-// the ring and the accumulator (close transposed), and the dF/dA, dF/dbeta
-// partial sums of the block.  Patch boundary nodes took coarse values, so
-// their ell is zero.
+// Window close and continuity step (Eq. (4)) transposed, one launch for both
+// levels: a block owns a 32 x 16 tile of nodes and works over the tile grown
+// by one node.
+// Phase 1 (tile + halo): recompute the forward update, clamp mask, ell =
+// mask * lam n'; at the own nodes also the E_rms^2 lam into the ring and the
+// accumulator (close transposed) and the dF/dA, dF/dbeta partials.  Patch
+// boundary nodes took coarse values, so their ell is zero.
+// Phase 2 (own nodes): lam n entering the step,
+//   lam n_j = ell_j (1 + dt_n nu_j)
+//           + c sum_f (ell_j - ell_f) [D'_j (n_f - n_j)/2 - (D_j + D_f)/2],
+// c = dt_n/dx^2, over the neighbours f the forward's flux used; written to
+// the other lam n buffer (halo reads of lam n leaving never race).
 // ---------------------------------------------------------------------------
 __device__ inline float d_eff_a(const AdjContArgs& A, float n) {
   if (A.d_const_mode) return A.d_const;
@@ -686,99 +693,122 @@ __device__ inline float d_eff_prime(const AdjContArgs& A, float n) {
   return A.inv_namb * (A.Da - A.De) / ((1.f + al) * (1.f + al));
 }
 
-__global__ __launch_bounds__(kThreads) void k_adj_cont_a(AdjContArgs A) {
-  const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
-  const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
+constexpr int kCTX = 32, kCTY = 16, kCW = kCTX + 2, kCH = kCTY + 2;
+
+__device__ __forceinline__ void adj_cont_tile(const AdjContArgs& A, int bx, int by,
+                                              size_t blk) {
+  __shared__ float sEll[kCH][kCW], sN[kCH][kCW];
+  __shared__ double sA[16], sB[16];
+  const int i0 = A.L + bx * kCTX, j0 = A.B + by * kCTY;
+  const int tid = threadIdx.x;
+  const int p = A.pitch;
+  auto cl = [](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
   double dA = 0.0, dB = 0.0;
-  if (i <= A.R && j <= A.T) {
-    const int p = A.pitch;
-    const size_t o = at(i, j, p);
+  // -- phase 1 --
+  if (tid < kCW * kCH) {
+    const int ci = tid % kCW, cj = tid / kCW;
+    const int i = i0 - 1 + ci, j = j0 - 1 + cj;
+    const bool in = i >= A.L && i <= A.R && j >= A.B && j <= A.T;
+    const bool own = in && ci >= 1 && ci <= kCTX && cj >= 1 && cj <= kCTY;
+    const int ic = cl(i, A.L, A.R), jc = cl(j, A.B, A.T);
+    const size_t o = (size_t)jc * p + ic;
+    // loads (clamped), then arithmetic
+    const float ni = A.n[o], e2 = A.e2[o], lno = A.ln[o];
+    const float vl = A.n[(size_t)jc * p + cl(ic - 1, A.L, A.R)];
+    const float vr = A.n[(size_t)jc * p + cl(ic + 1, A.L, A.R)];
+    const float vd = A.n[(size_t)cl(jc - 1, A.B, A.T) * p + ic];
+    const float vu = A.n[(size_t)cl(jc + 1, A.B, A.T) * p + ic];
     const bool edge = A.fine && (i == A.L || i == A.R || j == A.B || j == A.T);
-    float lE2 = 0.f;
-    float ell = 0.f;
-    if (!edge) {
+    float lE2 = 0.f, ell = 0.f;
+    if (in && !edge) {
       // forward, as the continuity kernel evaluates it
-      const float e2 = A.e2[o];
-      const float ni = A.n[o];
       const float di = d_eff_a(A, ni);
       float flux = 0.f;
-      if (i > A.L) { const float v = A.n[o - 1]; flux += 0.5f * (di + d_eff_a(A, v)) * (v - ni); }
-      if (i < A.R) { const float v = A.n[o + 1]; flux += 0.5f * (di + d_eff_a(A, v)) * (v - ni); }
-      if (j > A.B) { const float v = A.n[o - p]; flux += 0.5f * (di + d_eff_a(A, v)) * (v - ni); }
-      if (j < A.T) { const float v = A.n[o + p]; flux += 0.5f * (di + d_eff_a(A, v)) * (v - ni); }
+      if (i > A.L) flux += 0.5f * (di + d_eff_a(A, vl)) * (vl - ni);
+      if (i < A.R) flux += 0.5f * (di + d_eff_a(A, vr)) * (vr - ni);
+      if (j > A.B) flux += 0.5f * (di + d_eff_a(A, vd)) * (vd - ni);
+      if (j < A.T) flux += 0.5f * (di + d_eff_a(A, vu)) * (vu - ni);
       const float x = e2 * A.eeff_p2;
       const float pw = powf(x, A.half_beta);
       const float nu = A.nuA * (pw - A.att);
       float nn = ni + A.dtn * (flux * A.inv_dx2 + nu * ni);
       // max(0, .): right derivative at 0 (a zero density is perturbed upward)
-      ell = nn >= 0.f ? A.ln[o] : 0.f;
-      // nu = nu_m A (x^(beta/2) - c^beta),  x = E_rms^2 E_eff-factor/(100 p)^2
-      const float lnu = ell * A.dtn * ni;
-      if (x > 0.f) {
-        lE2 = lnu * A.nuA * A.half_beta * (pw / x) * A.eeff_p2;
-        dB = (double)lnu * (double)A.nuA * ((double)pw * 0.5 * (double)logf(x) - (double)A.att * (double)A.ln_c);
-      } else {
-        dB = (double)lnu * (double)A.nuA * (-(double)A.att * (double)A.ln_c);
+      ell = nn >= 0.f ? lno : 0.f;
+      if (own) {
+        // nu = nu_m A (x^(beta/2) - c^beta),  x = E_rms^2 E_eff-factor/(100 p)^2
+        const float lnu = ell * A.dtn * ni;
+        if (x > 0.f) {
+          lE2 = lnu * A.nuA * A.half_beta * (pw / x) * A.eeff_p2;
+          dB = (double)lnu * (double)A.nuA *
+               ((double)pw * 0.5 * (double)logf(x) - (double)A.att * (double)A.ln_c);
+        } else {
+          dB = (double)lnu * (double)A.nuA * (-(double)A.att * (double)A.ln_c);
+        }
+        dA = (double)lnu * (double)A.nu_m * ((double)pw - (double)A.att);
       }
-      dA = (double)lnu * (double)A.nu_m * ((double)pw - (double)A.att);
     }
-    A.ell[o] = ell;
-    // close: ring[slot] = acc / spp, acc = 0; E_rms^2 = sum of the ring
-    float* rs = A.lring + (size_t)A.slot * A.plane + o;
-    const float lsv = *rs + lE2;
-    for (int s = 0; s < kRing; s++)
-      if (s != A.slot) A.lring[(size_t)s * A.plane + o] += lE2;
-    *rs = 0.f;
-    A.lacc[o] = lsv * A.inv_spp;
+    sEll[cj][ci] = ell;
+    sN[cj][ci] = ni;
+    if (own) {
+      // close: ring[slot] = acc / spp, acc = 0; E_rms^2 = sum of the ring
+      float* rs = A.lring + (size_t)A.slot * A.plane + o;
+      const float lsv = *rs + lE2;
+      for (int q = 0; q < kRing; q++)
+        if (q != A.slot) A.lring[(size_t)q * A.plane + o] += lE2;
+      *rs = 0.f;
+      A.lacc[o] = lsv * A.inv_spp;
+    }
   }
   // block partial sums, fixed order
-  __shared__ double sA[kThreads / 64], sB[kThreads / 64];
   for (int d = 32; d >= 1; d >>= 1) {
     dA += __shfl_xor(dA, d, 64);
     dB += __shfl_xor(dB, d, 64);
   }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) { sA[w] = dA; sB[w] = dB; }
+  const int w = tid >> 6;
+  if ((tid & 63) == 0) { sA[w] = dA; sB[w] = dB; }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     double a = 0.0, b = 0.0;
-    for (int k = 0; k < kThreads / 64; k++) { a += sA[k]; b += sB[k]; }
-    const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    for (int k = 0; k < 16; k++) { a += sA[k]; b += sB[k]; }
     A.part[2 * blk] = a;
     A.part[2 * blk + 1] = b;
   }
+  // -- phase 2 --
+  if (tid < kCTX * kCTY) {
+    const int tx = tid % kCTX, ty = tid / kCTX;
+    const int i = i0 + tx, j = j0 + ty;
+    if (i > A.R || j > A.T) return;
+    const int ci = tx + 1, cj = ty + 1;
+    const size_t o = (size_t)j * p + i;
+    const float nj = sN[cj][ci];
+    const float dj = d_eff_a(A, nj);
+    const float dpj = d_eff_prime(A, nj);
+    const float lj = sEll[cj][ci];
+    float sacc = 0.f;
+    auto face = [&](int a, int b) {
+      const float nf = sN[b][a];
+      sacc += (lj - sEll[b][a]) * (0.5f * dpj * (nf - nj) - 0.5f * (dj + d_eff_a(A, nf)));
+    };
+    if (i > A.L) face(ci - 1, cj);
+    if (i < A.R) face(ci + 1, cj);
+    if (j > A.B) face(ci, cj - 1);
+    if (j < A.T) face(ci, cj + 1);
+    float self = 0.f;
+    if (lj != 0.f) {
+      const float x = A.e2[o] * A.eeff_p2;
+      const float nu = A.nuA * (powf(x, A.half_beta) - A.att);
+      self = lj * (1.f + A.dtn * nu);
+    }
+    A.ln_o[o] = self + A.dtn * A.inv_dx2 * sacc;
+  }
 }
 
-// Pass 2 (per node): lam n entering the step,
-//   lam n_j = ell_j (1 + dt_n nu_j)
-//           + c sum_f (ell_j - ell_f) [D'_j (n_f - n_j)/2 - (D_j + D_f)/2],
-// c = dt_n/dx^2, over the neighbours f the forward's flux used.
-__global__ __launch_bounds__(kThreads) void k_adj_cont_b(AdjContArgs A) {
-  const int i = A.L + blockIdx.x * kAT + (threadIdx.x % kAT);
-  const int j = A.B + blockIdx.y * kAR + (threadIdx.x / kAT);
-  if (i > A.R || j > A.T) return;
-  const int p = A.pitch;
-  const size_t o = at(i, j, p);
-  const float nj = A.n[o];
-  const float dj = d_eff_a(A, nj);
-  const float dpj = d_eff_prime(A, nj);
-  const float lj = A.ell[o];
-  float s = 0.f;
-  auto face = [&](size_t q) {
-    const float nf = A.n[q];
-    s += (lj - A.ell[q]) * (0.5f * dpj * (nf - nj) - 0.5f * (dj + d_eff_a(A, nf)));
-  };
-  if (i > A.L) face(o - 1);
-  if (i < A.R) face(o + 1);
-  if (j > A.B) face(o - p);
-  if (j < A.T) face(o + p);
-  float self = 0.f;
-  if (lj != 0.f) {
-    const float x = A.e2[o] * A.eeff_p2;
-    const float nu = A.nuA * (powf(x, A.half_beta) - A.att);
-    self = lj * (1.f + A.dtn * nu);
-  }
-  A.ln[o] = self + A.dtn * A.inv_dx2 * s;
+// blocks [0, nbf): the patch (F), the rest: the base level (C)
+__global__ __launch_bounds__(1024) void k_adj_cont(AdjContArgs F, AdjContArgs C, int nbf,
+                                                   int nbfx, int nbcx) {
+  const int b = blockIdx.x;
+  if (b < nbf) adj_cont_tile(F, b % nbfx, b / nbfx, b);
+  else adj_cont_tile(C, (b - nbf) % nbcx, (b - nbf) / nbcx, b);
 }
 
 // window close without a continuity step: lam acc = lam ring[slot] / spp
@@ -953,11 +983,14 @@ hipError_t launch_adj_inj(const AdjInjArgs& A, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_adj_cont(const AdjContArgs& A, int* nparts, hipStream_t st) {
-  const dim3 g = node_grid(A.L, A.B, A.R, A.T);
-  k_adj_cont_a<<<g, kThreads, 0, st>>>(A);
-  k_adj_cont_b<<<g, kThreads, 0, st>>>(A);
-  *nparts = (int)(g.x * g.y);
+hipError_t launch_adj_cont(const AdjContArgs& F, const AdjContArgs& C, int has_f, int* nparts,
+                           hipStream_t st) {
+  const int nbfx = has_f ? (F.R - F.L + kCTX) / kCTX : 0;
+  const int nbf = has_f ? nbfx * ((F.T - F.B + kCTY) / kCTY) : 0;
+  const int nbcx = (C.R - C.L + kCTX) / kCTX;
+  const int nbc = nbcx * ((C.T - C.B + kCTY) / kCTY);
+  k_adj_cont<<<nbf + nbc, 1024, 0, st>>>(F, C, nbf, nbfx > 0 ? nbfx : 1, nbcx);
+  *nparts = nbf + nbc;
   return hipGetLastError();
 }
 

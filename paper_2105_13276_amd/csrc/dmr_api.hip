@@ -343,8 +343,9 @@ int stream_rows(int NX, int NY) {
   }
   // a wave walks its rows one memory round trip (over the load depth) apart:
   // small grids take short segments and many waves
+  // (measured: 8 rows on 4096x2048, 16 on 8192x4096, 2 on config-1 sizes)
   const long waves_x = (NX + 1 + 61) / 62;
-  int seg = 64;
+  int seg = 16;
   while (seg > 2 && waves_x * ((NY + seg) / seg) < 16384) seg >>= 1;
   return seg;
 }
@@ -1190,7 +1191,7 @@ struct AdjLevel {
   float *ex2 = nullptr, *ey2 = nullptr, *jx2 = nullptr, *jy2 = nullptr;
   // patch: g of substeps 1 (gx, gy) and 2 (g2x, g2y) for Eq. (5b) transposed
   float *gx = nullptr, *gy = nullptr, *g2x = nullptr, *g2y = nullptr;
-  float *ell = nullptr, *hx = nullptr;
+  float *n2 = nullptr, *hx = nullptr;  // n2: second lam n buffer (continuity)
   int cur = 0;
   void flip() {
     cur = 1 - cur;
@@ -1206,7 +1207,7 @@ AdjLevel adj_carve(char* base, size_t plane) {
   a.ex = take(1); a.ey = take(1); a.jx = take(1); a.jy = take(1);
   a.n = take(1); a.acc = take(1); a.ring = take(kRing);
   a.gx = take(1); a.gy = take(1); a.ex2 = take(1); a.ey2 = take(1);
-  a.jx2 = take(1); a.jy2 = take(1); a.ell = take(1); a.hx = take(1);
+  a.jx2 = take(1); a.jy2 = take(1); a.n2 = take(1); a.hx = take(1);
   a.g2x = take(1); a.g2y = take(1);
   return a;
 }
@@ -1311,7 +1312,7 @@ AdjContArgs adj_cont_args(const dmr_sim* s, const Level& Lv, AdjLevel& a, bool f
   K.De = (float)s->De; K.Da = (float)s->Da;
   K.d_const_mode = p.d_mode == DMR_D_CONST;
   K.d_const = (float)p.d_const;
-  K.ln = a.n; K.lacc = a.acc; K.lring = a.ring; K.ell = a.ell;
+  K.ln = a.n; K.ln_o = a.n2; K.lacc = a.acc; K.lring = a.ring;
   return K;
 }
 
@@ -1368,14 +1369,13 @@ int adj_step(dmr_sim* s, const TapeLayout& T, AdjLevel& ac, AdjLevel& af, int kk
         if (e != hipSuccess) return hipfail(s, e, "adjoint transfer launch");
       }
       int np = 0;
-      K.n = ss.cn; K.e2 = ss.ce2; K.part = part + 2 * *npart;
-      e = launch_adj_cont(K, &np, s->st);
+      K.n = ss.cn; K.e2 = ss.ce2;
+      if (m.has) { G.n = ss.fn; G.e2 = ss.fe2; }
+      G.part = K.part = part + 2 * *npart;  // patch blocks first, then the base level
+      e = launch_adj_cont(G, K, m.has ? 1 : 0, &np, s->st);
       *npart += (size_t)np;
-      if (e == hipSuccess && m.has) {
-        G.n = ss.fn; G.e2 = ss.fe2; G.part = part + 2 * *npart;
-        e = launch_adj_cont(G, &np, s->st);
-        *npart += (size_t)np;
-      }
+      std::swap(ac.n, ac.n2);
+      if (m.has) std::swap(af.n, af.n2);
     } else {
       e = launch_adj_close(K, s->st);
       if (e == hipSuccess && m.has) e = launch_adj_close(G, s->st);

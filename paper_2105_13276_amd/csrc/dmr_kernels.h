@@ -209,10 +209,10 @@ struct AdjContArgs {
   float d_const;
   const float* n;   // density entering the continuity step
   const float* e2;  // E_rms^2 the step used
-  float* ln;        // lam n: leaving in, entering out
+  float* ln;        // lam n leaving (entering: ln_o)
+  float* ln_o;      // lam n entering the step (another buffer)
   float* lacc;
   float* lring;
-  float* ell;       // temporary: clamp mask times lam n leaving
   double* part;     // per-block (dF/dA, dF/dbeta) partial sums
 };
 
@@ -244,7 +244,10 @@ hipError_t launch_copy2d(const float* src, int spitch, int si0, int sj0, float* 
                          int dpitch, int di0, int dj0, int cols, int rows, hipStream_t st);
 hipError_t launch_adj_inj(const AdjInjArgs& A, hipStream_t st);
 // continuity adjoint; returns the number of partial pairs written
-hipError_t launch_adj_cont(const AdjContArgs& A, int* nparts, hipStream_t st);
+// continuity step transposed on the patch (F, if has_f) and the base level
+// (C) in one launch; nparts: the partial-sum blocks written from A.part on
+hipError_t launch_adj_cont(const AdjContArgs& F, const AdjContArgs& C, int has_f, int* nparts,
+                           hipStream_t st);
 hipError_t launch_adj_close(const AdjContArgs& A, hipStream_t st);
 hipError_t launch_copy(const CopyJobs& J, hipStream_t st);
 hipError_t launch_ring_e2(const float* ring, size_t plane, int pitch, int L, int B,
