@@ -17,8 +17,6 @@
 // E, J, Hz are ping-ponged (read buffer 0, write buffer 1) so a tile can
 // recompute its halo without racing its neighbours; the window accumulator
 // is updated in place by the tile owning the node.
-#include <algorithm>
-
 #include "dmr_kernels.h"
 
 namespace dmr {
@@ -520,57 +518,55 @@ __device__ __forceinline__ void bnd_src(int tid, int orig, int NW_, int NH_, int
 // (i0, j0):  raw E0 -7, L(E0) -6, filtered E0 and H1 -5, E1/J1 and n -4;
 // then as in fine_tile: L(E1) -3, filtered E1 and H2 -2, E2/J2 -1.
 // ---------------------------------------------------------------------------
-// Sizes of the two-substep tile (64 x TY nodes, NT threads): regions of
-// substep 1 (raw E0 at origin -7 ... n at -4) and substep 2, and the loads
-// per thread.
-template <int TY, int NT>
-struct F2Dims {
-  static constexpr int R1W = kTX + 13, R1H = TY + 13;
-  static constexpr int H1W = kTX + 8, H1H = TY + 8;
-  static constexpr int N1W = kTX + 7, N1H = TY + 7;
-  static constexpr int D1W = kTX + 8, D1H = TY + 8;
-  static constexpr int N2W = kTX + 1, N2H = TY + 1;
-  static constexpr int NR = (R1H * R1W + NT - 1) / NT;
-  static constexpr int NH0 = (H1H * H1W + NT - 1) / NT;
-  static constexpr int NJ0 = (N1H * N1W + NT - 1) / NT;
-  static constexpr int ND = (D1H * D1W + NT - 1) / NT;
-  static constexpr int RP = NT / kTX;
-  static constexpr int NA = (TY + RP - 1) / RP;
-  static constexpr int CW = kTX / 2 + 6, CH = TY / 2 + 6;
-};
+template <int TY, int NT, bool LOCAL, bool ST = false>
+__device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
+  constexpr int R1W = kTX + 13, R1H = TY + 13;
+  constexpr int Q1W = kTX + 11, Q1H = TY + 11;
+  constexpr int F1W = kTX + 9, F1H = TY + 9;
+  constexpr int H1W = kTX + 8, H1H = TY + 8;
+  constexpr int N1W = kTX + 7, N1H = TY + 7;
+  constexpr int D1W = kTX + 8, D1H = TY + 8;
+  constexpr int Q2W = kTX + 5, Q2H = TY + 5;
+  constexpr int F2W = kTX + 3, F2H = TY + 3;
+  constexpr int H2W = kTX + 2, H2H = TY + 2;
+  constexpr int N2W = kTX + 1, N2H = TY + 1;
+  constexpr int NR = (R1H * R1W + NT - 1) / NT;
+  constexpr int NH0 = (H1H * H1W + NT - 1) / NT;
+  constexpr int NJ0 = (N1H * N1W + NT - 1) / NT;
+  constexpr int ND = (D1H * D1W + NT - 1) / NT;
+  constexpr int RP = NT / kTX;  // tile rows per pass of the block
+  constexpr int NA = (TY + RP - 1) / RP;
+  __shared__ float rX[R1H][R1W], rY[R1H][R1W];  // raw E0
+  __shared__ float qX[Q1H][Q1W], qY[Q1H][Q1W];  // L(E0), then L(E1)
+  __shared__ float fX[F1H][F1W], fY[F1H][F1W];  // filtered E0, then filtered E1
+  __shared__ float sH1[H1H][H1W];
+  __shared__ float e1X[N1H][N1W], e1Y[N1H][N1W];
+  __shared__ float j1X[N2H][N2W], j1Y[N2H][N2W];
+  __shared__ float sN[D1H][D1W];
+  __shared__ float sH2[H2H][H2W];
+  __shared__ float e2X[N2H][N2W], e2Y[N2H][N2W];
+  __shared__ float j2X[TY][kTX], j2Y[TY][kTX];
+  __shared__ float sB1[5][N1W], sB2[5][N2W];  // Eq. (5b) values of substeps 1 and 2
 
-// Everything one thread reads from global memory for one tile (issued in one
-// batch before any of it is used)
-template <int TY, int NT, bool LOCAL>
-struct F2Regs {
-  using D = F2Dims<TY, NT>;
-  float pex[D::NR], pey[D::NR], phz[D::NH0], pjx[D::NJ0], pjy[D::NJ0], pn[D::ND], pacc[D::NA];
-  float b1v0, b1v1, b1v2, b1v3, b2v0, b2v1, b2v2, b2v3;
-  float q[LOCAL ? 12 : 1];  // combined step: coarse values around the boundary lines
-};
-
-template <int TY, int NT, bool LOCAL>
-__device__ __forceinline__ void fine2_load(const EMArgs& A, int bx, int by,
-                                           F2Regs<TY, NT, LOCAL>& rg) {
-  using Dm = F2Dims<TY, NT>;
-  constexpr int R1W = Dm::R1W, R1H = Dm::R1H, H1W = Dm::H1W, H1H = Dm::H1H;
-  constexpr int N1W = Dm::N1W, N1H = Dm::N1H, D1W = Dm::D1W, D1H = Dm::D1H;
-  constexpr int N2W = Dm::N2W, N2H = Dm::N2H;
-  constexpr int NR = Dm::NR, NH0 = Dm::NH0, NJ0 = Dm::NJ0, ND = Dm::ND, RP = Dm::RP, NA = Dm::NA;
-  constexpr int CW = Dm::CW, CH = Dm::CH;
   const int i0 = A.L + bx * kTX;
   const int j0 = A.B + by * TY;
   const int tid = threadIdx.x;
   const int L = A.L, R = A.R, B = A.B, T = A.T;
   const int pitch = A.pitch;
+  const bool filt = A.gamma > 0.f;
+  const float frac1 = A.frac, frac2 = 1.f;
+  auto hz_ok = [=](int i, int j) { return i >= L && i < R && j >= B && j < T; };
+  auto ex_ok = [=](int i, int j) { return i >= L && i < R && j >= B && j <= T; };
+  auto ey_ok = [=](int i, int j) { return i >= L && i <= R && j >= B && j < T; };
+  auto nd_ok = [=](int i, int j) { return i >= L && i <= R && j >= B && j <= T; };
   auto cl = [=](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
   auto o_hz = [=](int i, int j) { return (size_t)cl(j, B, T - 1) * pitch + cl(i, L, R - 1); };
   auto o_ex = [=](int i, int j) { return (size_t)cl(j, B, T) * pitch + cl(i, L, R - 1); };
   auto o_ey = [=](int i, int j) { return (size_t)cl(j, B, T - 1) * pitch + cl(i, L, R); };
   auto o_nd = [=](int i, int j) { return (size_t)cl(j, B, T) * pitch + cl(i, L, R); };
-  auto& pex = rg.pex; auto& pey = rg.pey; auto& phz = rg.phz; auto& pjx = rg.pjx;
-  auto& pjy = rg.pjy; auto& pn = rg.pn; auto& pacc = rg.pacc; auto& q = rg.q;
+
   // -- one batch of global loads ------------------------------------------------
+  float pex[NR], pey[NR];
 #pragma unroll
   for (int q = 0; q < NR; q++) {
     const int k = min(tid + q * NT, R1H * R1W - 1);
@@ -578,11 +574,13 @@ __device__ __forceinline__ void fine2_load(const EMArgs& A, int bx, int by,
     pex[q] = A.ex0[o_ex(i, j)];
     pey[q] = A.ey0[o_ey(i, j)];
   }
+  float phz[NH0];
 #pragma unroll
   for (int q = 0; q < NH0; q++) {
     const int k = min(tid + q * NT, H1H * H1W - 1);
     phz[q] = A.hz0[o_hz(i0 - 5 + k % H1W, j0 - 5 + k / H1W)];
   }
+  float pjx[NJ0], pjy[NJ0];
 #pragma unroll
   for (int q = 0; q < NJ0; q++) {
     const int k = min(tid + q * NT, N1H * N1W - 1);
@@ -590,12 +588,14 @@ __device__ __forceinline__ void fine2_load(const EMArgs& A, int bx, int by,
     pjx[q] = A.jx0[o_ex(i, j)];
     pjy[q] = A.jy0[o_ey(i, j)];
   }
+  float pn[ND];
 #pragma unroll
   for (int q = 0; q < ND; q++) {
     const int k = min(tid + q * NT, D1H * D1W - 1);
     pn[q] = A.n[o_nd(i0 - 4 + k % D1W, j0 - 4 + k / D1W)];
   }
   const int tx = tid % kTX, ty = tid / kTX;
+  float pacc[NA];
 #pragma unroll
   for (int q = 0; q < NA; q++) pacc[q] = A.acc[o_nd(i0 + tx, j0 + ty + q * RP)];
   // Eq. (5b) sources of both substeps: boundary x-edges of rows B, T and
@@ -611,22 +611,25 @@ __device__ __forceinline__ void fine2_load(const EMArgs& A, int bx, int by,
   // otherwise be lowered through private memory)
   const float* b1o = (const float*)(g1 >= 2 ? (uintptr_t)A.cey0 : (uintptr_t)A.cex0);
   const float* b2o = (const float*)(g2 >= 2 ? (uintptr_t)A.cey0 : (uintptr_t)A.cex0);
-  rg.b1v0 = b1o[o1a]; rg.b1v1 = b1o[o1b];
-  rg.b2v0 = b2o[o2a]; rg.b2v1 = b2o[o2b];
-  rg.b1v2 = rg.b1v3 = rg.b2v2 = rg.b2v3 = 0.f;
+  const float b1v0 = b1o[o1a], b1v1 = b1o[o1b];
+  const float b2v0 = b2o[o2a], b2v1 = b2o[o2b];
+  float b1v2 = 0.f, b1v3 = 0.f, b2v2 = 0.f, b2v3 = 0.f;
   if constexpr (!LOCAL) {
     const float* b1n = (const float*)(g1 >= 2 ? (uintptr_t)A.cey1 : (uintptr_t)A.cex1);
     const float* b2n = (const float*)(g2 >= 2 ? (uintptr_t)A.cey1 : (uintptr_t)A.cex1);
-    rg.b1v2 = b1n[o1a]; rg.b1v3 = b1n[o1b];
-    rg.b2v2 = b2n[o2a]; rg.b2v3 = b2n[o2b];
+    b1v2 = b1n[o1a]; b1v3 = b1n[o1b];
+    b2v2 = b2n[o2a]; b2v3 = b2n[o2b];
   }
   // combined step: the coarse E after the coarse step on the patch boundary
   // lines is computed here from the coarse state entering it (the base-level
   // waves of the same launch compute the same values).  x-lines: coarse rows
   // B/2 and T/2 at columns [cx0, cx0 + CW); y-lines: coarse columns L/2 and
   // R/2 at rows [cy0, cy0 + CH).
+  constexpr int CW = kTX / 2 + 6, CH = TY / 2 + 6;
+  __shared__ float sC[5][CW > CH ? CW : CH];
   const int cx0 = ((i0 - 4) >> 1) - 1, cy0 = ((j0 - 4) >> 1) - 1;
   int cg = -1, cc = 0;
+  float q[12];
   if constexpr (LOCAL) {
     if (tid < CW) { cg = 0; cc = tid; }
     else if (tid < 2 * CW) { cg = 1; cc = tid - CW; }
@@ -654,95 +657,6 @@ __device__ __forceinline__ void fine2_load(const EMArgs& A, int bx, int by,
     }
   }
 
-}
-
-// rg: the tile's values from fine2_load
-template <int TY, int NT, bool LOCAL, bool ST = false>
-__device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by,
-                                           F2Regs<TY, NT, LOCAL>& rg) {
-  constexpr int R1W = kTX + 13, R1H = TY + 13;
-  constexpr int Q1W = kTX + 11, Q1H = TY + 11;
-  constexpr int F1W = kTX + 9, F1H = TY + 9;
-  constexpr int H1W = kTX + 8, H1H = TY + 8;
-  constexpr int N1W = kTX + 7, N1H = TY + 7;
-  constexpr int D1W = kTX + 8, D1H = TY + 8;
-  constexpr int Q2W = kTX + 5, Q2H = TY + 5;
-  constexpr int F2W = kTX + 3, F2H = TY + 3;
-  constexpr int H2W = kTX + 2, H2H = TY + 2;
-  constexpr int N2W = kTX + 1, N2H = TY + 1;
-  constexpr int NR = (R1H * R1W + NT - 1) / NT;
-  constexpr int NH0 = (H1H * H1W + NT - 1) / NT;
-  constexpr int NJ0 = (N1H * N1W + NT - 1) / NT;
-  constexpr int ND = (D1H * D1W + NT - 1) / NT;
-  constexpr int RP = NT / kTX;  // tile rows per pass of the block
-  constexpr int NA = (TY + RP - 1) / RP;
-  // LDS: arrays whose lifetimes do not overlap share space, so that two
-  // 16-row tiles fit a CU.  Pool A holds the raw E0 (read up to the filtered
-  // E0), then J1 (Ampere 1 -> Ampere 2) and J2 (Ampere 2 -> the transfer);
-  // pool B holds L(E0) and L(E1) (read up to the filtered E1), then H2 and E2.
-  constexpr int SA = 2 * R1H * R1W, SB = 2 * Q1H * Q1W;
-  static_assert(2 * N2H * N2W + 2 * TY * kTX <= SA, "J1 and J2 fit pool A");
-  static_assert(H2H * H2W + 2 * N2H * N2W <= SB, "H2 and E2 fit pool B");
-  __shared__ float poolA[SA], poolB[SB];
-  float (*rX)[R1W] = reinterpret_cast<float (*)[R1W]>(poolA);  // raw E0
-  float (*rY)[R1W] = reinterpret_cast<float (*)[R1W]>(poolA + R1H * R1W);
-  float (*j1X)[N2W] = reinterpret_cast<float (*)[N2W]>(poolA);
-  float (*j1Y)[N2W] = reinterpret_cast<float (*)[N2W]>(poolA + N2H * N2W);
-  float (*j2X)[kTX] = reinterpret_cast<float (*)[kTX]>(poolA + 2 * N2H * N2W);
-  float (*j2Y)[kTX] = reinterpret_cast<float (*)[kTX]>(poolA + 2 * N2H * N2W + TY * kTX);
-  float (*qX)[Q1W] = reinterpret_cast<float (*)[Q1W]>(poolB);  // L(E0), then L(E1)
-  float (*qY)[Q1W] = reinterpret_cast<float (*)[Q1W]>(poolB + Q1H * Q1W);
-  float (*sH2)[H2W] = reinterpret_cast<float (*)[H2W]>(poolB);
-  float (*e2X)[N2W] = reinterpret_cast<float (*)[N2W]>(poolB + H2H * H2W);
-  float (*e2Y)[N2W] = reinterpret_cast<float (*)[N2W]>(poolB + H2H * H2W + N2H * N2W);
-  __shared__ float fX[F1H][F1W], fY[F1H][F1W];  // filtered E0, then filtered E1
-  __shared__ float sH1[H1H][H1W];
-  __shared__ float e1X[N1H][N1W], e1Y[N1H][N1W];
-  __shared__ float sN[D1H][D1W];
-  __shared__ float sB1[5][N1W], sB2[5][N2W];  // Eq. (5b) values of substeps 1 and 2
-
-  const int i0 = A.L + bx * kTX;
-  const int j0 = A.B + by * TY;
-  const int tid = threadIdx.x;
-  const int L = A.L, R = A.R, B = A.B, T = A.T;
-  const int pitch = A.pitch;
-  const bool filt = A.gamma > 0.f;
-  const float frac1 = A.frac, frac2 = 1.f;
-  auto hz_ok = [=](int i, int j) { return i >= L && i < R && j >= B && j < T; };
-  auto ex_ok = [=](int i, int j) { return i >= L && i < R && j >= B && j <= T; };
-  auto ey_ok = [=](int i, int j) { return i >= L && i <= R && j >= B && j < T; };
-  auto nd_ok = [=](int i, int j) { return i >= L && i <= R && j >= B && j <= T; };
-  auto cl = [=](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
-  auto o_hz = [=](int i, int j) { return (size_t)cl(j, B, T - 1) * pitch + cl(i, L, R - 1); };
-  auto o_ex = [=](int i, int j) { return (size_t)cl(j, B, T) * pitch + cl(i, L, R - 1); };
-  auto o_ey = [=](int i, int j) { return (size_t)cl(j, B, T - 1) * pitch + cl(i, L, R); };
-  auto o_nd = [=](int i, int j) { return (size_t)cl(j, B, T) * pitch + cl(i, L, R); };
-
-  // -- the tile's loaded values (fine2_load) ---------------------------------------
-  auto& pex = rg.pex; auto& pey = rg.pey; auto& phz = rg.phz; auto& pjx = rg.pjx;
-  auto& pjy = rg.pjy; auto& pn = rg.pn; auto& pacc = rg.pacc; auto& q = rg.q;
-  const float b1v0 = rg.b1v0, b1v1 = rg.b1v1, b1v2 = rg.b1v2, b1v3 = rg.b1v3;
-  const float b2v0 = rg.b2v0, b2v1 = rg.b2v1, b2v2 = rg.b2v2, b2v3 = rg.b2v3;
-  const int tx = tid % kTX, ty = tid / kTX;
-  // Eq. (5b) sources of both substeps (as in fine2_load)
-  int g1, c1_, g2, c2, k1, k2;
-  size_t o1a, o1b, o2a, o2b;
-  float w1a, w1b, w2a, w2b;
-  bool ok1, ok2;
-  bnd_src(tid, -4, N1W, N1H, i0, j0, L, R, B, T, A.cpitch, g1, c1_, o1a, o1b, w1a, w1b, ok1, k1);
-  bnd_src(tid, -1, N2W, N2H, i0, j0, L, R, B, T, A.cpitch, g2, c2, o2a, o2b, w2a, w2b, ok2, k2);
-  (void)o1a; (void)o1b; (void)o2a; (void)o2b;
-  constexpr int CW = kTX / 2 + 6, CH = TY / 2 + 6;
-  __shared__ float sC[5][CW > CH ? CW : CH];
-  const int cx0 = ((i0 - 4) >> 1) - 1, cy0 = ((j0 - 4) >> 1) - 1;
-  int cg = -1, cc = 0;
-  if constexpr (LOCAL) {
-    if (tid < CW) { cg = 0; cc = tid; }
-    else if (tid < 2 * CW) { cg = 1; cc = tid - CW; }
-    else if (tid < 2 * CW + CH) { cg = 2; cc = tid - 2 * CW; }
-    else if (tid < 2 * CW + 2 * CH) { cg = 3; cc = tid - 2 * CW - CH; }
-  }
-
   // -- substep 1: raw E0, n, boundary values ----------------------------------
 #pragma unroll
   for (int q = 0; q < NR; q++) {
@@ -752,13 +666,6 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by,
       const int i = i0 - 7 + ci, j = j0 - 7 + cj;
       rX[cj][ci] = ex_ok(i, j) ? pex[q] : 0.f;
       rY[cj][ci] = ey_ok(i, j) ? pey[q] : 0.f;
-      if constexpr (ST) {  // replay: E entering, at the tile's own positions
-        if (ci >= 7 && ci < 7 + kTX && cj >= 7 && cj < 7 + TY && nd_ok(i, j)) {
-          const size_t o = (size_t)j * pitch + i;
-          if (ex_ok(i, j)) A.st0x[o] = pex[q];
-          if (ey_ok(i, j)) A.st0y[o] = pey[q];
-        }
-      }
     }
   }
 #pragma unroll
@@ -1099,7 +1006,7 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by,
     }
   }
 
-  // replay for the adjoint (E entering went out in the first phase): E after
+  // replay for the adjoint: E entering (raw E0 at origin -7), after
   // substep 1 (origin -4), after substep 2 (origin -1), n (origin -4)
   if constexpr (ST) {
     for (int r = ty; r < TY; r += RP) {
@@ -1108,10 +1015,12 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by,
       const size_t o = (size_t)j * pitch + i;
       A.stn[o] = sN[r + 4][tx + 4];
       if (ex_ok(i, j)) {
+        A.st0x[o] = rX[r + 7][tx + 7];
         A.st1x[o] = e1X[r + 4][tx + 4];
         if (A.st2x) A.st2x[o] = e2X[r + 1][tx + 1];
       }
       if (ey_ok(i, j)) {
+        A.st0y[o] = rY[r + 7][tx + 7];
         A.st1y[o] = e1Y[r + 4][tx + 4];
         if (A.st2y) A.st2y[o] = e2Y[r + 1][tx + 1];
       }
@@ -1121,10 +1030,9 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by,
 
 template <int TY, int NT, bool ST = false>
 __global__ __launch_bounds__(NT) void k_fine2(EMArgs A) {
-  F2Regs<TY, NT, false> rg;
-  fine2_load<TY, NT, false>(A, blockIdx.x, blockIdx.y, rg);
-  fine2_tile<TY, NT, false, ST>(A, blockIdx.x, blockIdx.y, rg);
+  fine2_tile<TY, NT, false, ST>(A, blockIdx.x, blockIdx.y);
 }
+
 
 // batched form: one launch over the tiles of many independent instances;
 // blk[b] = (instance, tile index within it)
@@ -1705,9 +1613,7 @@ __global__ __launch_bounds__(kFineThreads) void k_dmr_step(EMArgs C, EMArgs F, i
     return;
   }
   const int t = b - ncb;
-  F2Regs<TY, kFineThreads, true> rg;
-  fine2_load<TY, kFineThreads, true>(F, t % nbx_f, t / nbx_f, rg);
-  fine2_tile<TY, kFineThreads, true, ST>(F, t % nbx_f, t / nbx_f, rg);
+  fine2_tile<TY, kFineThreads, true, ST>(F, t % nbx_f, t / nbx_f);
 }
 
 // ---- host-side launchers ----------------------------------------------------
