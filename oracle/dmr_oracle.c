@@ -48,6 +48,9 @@ struct orc_sim {
   int NBx, NBy;
   uint8_t *bflag;
   int32_t *bscan, *blist, bcount;
+  /* ORC_RULE_UNION: active blocks [NBy][NBx]; the fine level L1 then spans
+   * the whole domain at r times the resolution */
+  uint8_t *act;
 };
 
 /* ---- indexing ---------------------------------------------------------- */
@@ -532,18 +535,20 @@ static double erms2_at(const level_t *L, int i, int j) {
 
 /* forward Euler, flux form with face D = mean of the two node values,
  * zero flux through the outer faces (or periodic wrap).  Arrays are node
- * arrays [nx+1][ny+1] (j fastest); nodes in [ilo,ihi]x[jlo,jhi] are
- * updated, the rest copied. */
+ * arrays [nx+1][ny+1] (j fastest); nodes in [ilo,ihi]x[jlo,jhi] (and, when
+ * mask is given, with a non-zero mask entry) are updated, the rest copied. */
 static void continuity_core(const orc_params *p, int nx, int ny, double dx,
                             double dtn, int ilo, int ihi, int jlo, int jhi,
                             int perx, int pery, const double *nold,
-                            const double *e2, double *nout) {
+                            const double *e2, double *nout,
+                            const uint8_t *mask) {
 #define AT(arr, i, j) arr[(size_t)(i) * (ny + 1) + (j)]
   const double r_ei = orc_r_ei(p);
   memcpy(nout, nold, (size_t)(nx + 1) * (ny + 1) * sizeof(double));
   for (int i = ilo; i <= ihi; i++)
     for (int j = jlo; j <= jhi; j++) {
       if ((perx && i == nx) || (pery && j == ny)) continue;
+      if (mask && !AT(mask, i, j)) continue;
       double ni = AT(nold, i, j);
       double di = orc_d_eff(p, ni);
       double flux = 0.0;
@@ -573,9 +578,9 @@ static void continuity_core(const orc_params *p, int nx, int ny, double dx,
 }
 
 /* interior_only leaves the patch boundary nodes (they carry coarse values)
- * untouched */
+ * untouched; mask (node array) restricts the update further */
 static void continuity(orc_sim *s, level_t *L, int interior_only, int perx,
-                       int pery) {
+                       int pery, const uint8_t *mask) {
   const int nx = L->nx, ny = L->ny;
   const double dtn = L->spb * L->dt;
   double *nold = malloc(n_nd(L) * sizeof(double));
@@ -585,10 +590,10 @@ static void continuity(orc_sim *s, level_t *L, int interior_only, int perx,
     for (int j = 0; j <= ny; j++) e2[(size_t)i * (ny + 1) + j] = erms2_at(L, i, j);
   if (interior_only)
     continuity_core(&s->p, nx, ny, L->dx, dtn, 1, nx - 1, 1, ny - 1, 0, 0,
-                    nold, e2, L->n);
+                    nold, e2, L->n, mask);
   else
     continuity_core(&s->p, nx, ny, L->dx, dtn, 0, nx, 0, ny, perx, pery, nold,
-                    e2, L->n);
+                    e2, L->n, mask);
   free(nold);
   free(e2);
 }
@@ -608,7 +613,7 @@ int orc_continuity_apply(const orc_params *p, int nx, int ny, double dx,
       a[(size_t)i * (ny + 1) + j] = n_in[(size_t)j * (nx + 1) + i];
       e[(size_t)i * (ny + 1) + j] = erms2[(size_t)j * (nx + 1) + i];
     }
-  continuity_core(p, nx, ny, dx, dtn, 0, nx, 0, ny, perx, pery, a, e, o);
+  continuity_core(p, nx, ny, dx, dtn, 0, nx, 0, ny, perx, pery, a, e, o, NULL);
   for (int j = 0; j <= ny; j++)
     for (int i = 0; i <= nx; i++)
       n_out[(size_t)j * (nx + 1) + i] = o[(size_t)i * (ny + 1) + j];
@@ -683,9 +688,8 @@ static int node_flag(const orc_sim *s, int i, int j, float thr, float flo,
   return lhs > rhs;
 }
 
-/* flags -> block flags -> exclusive prefix sum -> compacted block list ->
- * bounding box of old patch and flagged blocks, clipped to the margins */
-static void regrid_test(orc_sim *s, int newext[4]) {
+/* flags -> block flags -> exclusive prefix sum -> compacted block list */
+static void flag_blocks(orc_sim *s) {
   const level_t *L = &s->L0;
   const int B = s->p.block, NBx = s->NBx, NBy = s->NBy;
   const float thr = (float)(s->p.n_thr_over_nc * s->n_c);
@@ -705,6 +709,24 @@ static void regrid_test(orc_sim *s, int newext[4]) {
     run += s->bflag[b];
   }
   s->bcount = run;
+}
+
+/* first block column a patch may use: one block clear of the outer boundary
+ * and of the source line */
+static int block_xmin(const orc_sim *s) {
+  const int B = s->p.block;
+  int xmin = 1;
+  if (s->p.tfsf_i > 0) {
+    int m = (s->p.tfsf_i + 2 * B - 1) / B;
+    if (m > xmin) xmin = m;
+  }
+  return xmin;
+}
+
+/* bounding box of old patch and flagged blocks, clipped to the margins */
+static void regrid_test(orc_sim *s, int newext[4]) {
+  const int B = s->p.block, NBx = s->NBx, NBy = s->NBy;
+  flag_blocks(s);
   int bx0 = NBx, by0 = NBy, bx1 = 0, by1 = 0;
   for (int k = 0; k < s->bcount; k++) {
     int bx = s->blist[k] % NBx, by = s->blist[k] / NBx;
@@ -722,11 +744,7 @@ static void regrid_test(orc_sim *s, int newext[4]) {
     if (o3 > by1) by1 = o3;
   }
   /* keep one block clear of the outer boundary and of the source line */
-  int xmin = 1;
-  if (s->p.tfsf_i > 0) {
-    int m = (s->p.tfsf_i + 2 * B - 1) / B;
-    if (m > xmin) xmin = m;
-  }
+  const int xmin = block_xmin(s);
   if (bx0 < xmin) bx0 = xmin;
   if (by0 < 1) by0 = 1;
   if (bx1 > NBx - 1) bx1 = NBx - 1;
@@ -884,8 +902,345 @@ static void line_rule(orc_sim *s, int ne[4]) {
   if (ne[0] >= ne[2] || ne[1] >= ne[3]) ne[0] = ne[1] = ne[2] = ne[3] = 0;
 }
 
+/* ---- the fine level as a union of blocks (ORC_RULE_UNION) --------------
+ * The growth test of Sec. III.A/B flags blocks; here the fine level is the
+ * union of the flagged blocks themselves instead of their bounding box, so
+ * that several separate regions are refined without the space between them.
+ * The fine arrays span the whole domain at r times the resolution.  A fine
+ * cell belongs to the fine level when its block is active.  An edge belongs
+ * to it when a cell beside it does: interior when both cells do, a
+ * coarse/fine boundary edge (driven by Eq. (5b)) when exactly one does.  A
+ * node belongs to it when a cell around it does, interior when all four do.
+ * Every rule of the rectangular patch above is the special case of a
+ * rectangle of blocks. */
+static int cact_m(const orc_sim *s, const uint8_t *map, int P, int Q) {
+  const int fb = s->p.r * s->p.block;
+  if (P < 0 || Q < 0 || P >= s->p.r * s->p.nx || Q >= s->p.r * s->p.ny) return 0;
+  return map[(size_t)(Q / fb) * s->NBx + P / fb];
+}
+static int cact(const orc_sim *s, int P, int Q) { return cact_m(s, s->act, P, Q); }
+static int ex_has_m(const orc_sim *s, const uint8_t *m, int P, int Q) {
+  return cact_m(s, m, P, Q) || cact_m(s, m, P, Q - 1);
+}
+static int ey_has_m(const orc_sim *s, const uint8_t *m, int P, int Q) {
+  return cact_m(s, m, P, Q) || cact_m(s, m, P - 1, Q);
+}
+static int nd_has_m(const orc_sim *s, const uint8_t *m, int P, int Q) {
+  return cact_m(s, m, P - 1, Q - 1) || cact_m(s, m, P, Q - 1) ||
+         cact_m(s, m, P - 1, Q) || cact_m(s, m, P, Q);
+}
+static int ex_has(const orc_sim *s, int P, int Q) { return ex_has_m(s, s->act, P, Q); }
+static int ey_has(const orc_sim *s, int P, int Q) { return ey_has_m(s, s->act, P, Q); }
+static int nd_has(const orc_sim *s, int P, int Q) { return nd_has_m(s, s->act, P, Q); }
+static int ex_inner(const orc_sim *s, int P, int Q) { return cact(s, P, Q) && cact(s, P, Q - 1); }
+static int ey_inner(const orc_sim *s, int P, int Q) { return cact(s, P, Q) && cact(s, P - 1, Q); }
+static int nd_inner(const orc_sim *s, int P, int Q) {
+  return cact(s, P - 1, Q - 1) && cact(s, P, Q - 1) && cact(s, P - 1, Q) && cact(s, P, Q);
+}
+/* coarse cell (I, J) active */
+static int coarse_act(const orc_sim *s, int I, int J) {
+  const int B = s->p.block;
+  if (I < 0 || J < 0 || I >= s->p.nx || J >= s->p.ny) return 0;
+  return s->act[(size_t)(J / B) * s->NBx + I / B];
+}
+
+/* 5-point Laplacian on the fine level's own edges of one kind (0: Ex grid
+ * [fw][fh+1], 1: Ey grid [fw+1][fh]); a neighbour outside the level counts
+ * as the centre value, as for the rectangle */
+static void lap_union(const orc_sim *s, const double *a, double *out, int ni,
+                      int nj, int kind) {
+#define HAS(i, j) (kind ? ey_has(s, i, j) : ex_has(s, i, j))
+  for (int i = 0; i < ni; i++)
+    for (int j = 0; j < nj; j++) {
+      if (!HAS(i, j)) {
+        out[(size_t)i * nj + j] = 0.0;
+        continue;
+      }
+      double c = a[(size_t)i * nj + j];
+      double l = HAS(i - 1, j) ? a[(size_t)(i - 1) * nj + j] : c;
+      double r = HAS(i + 1, j) ? a[(size_t)(i + 1) * nj + j] : c;
+      double d = HAS(i, j - 1) ? a[(size_t)i * nj + j - 1] : c;
+      double u = HAS(i, j + 1) ? a[(size_t)i * nj + j + 1] : c;
+      out[(size_t)i * nj + j] = l + r + d + u - 4.0 * c;
+    }
+#undef HAS
+}
+
+static void fine_filter_union(orc_sim *s) {
+  level_t *F = &s->L1;
+  const double g = s->p.fine_filter;
+  if (g <= 0.0) return;
+  const int fw = F->nx, fh = F->ny;
+  size_t nx_ = n_ex(F), ny_ = n_ey(F);
+  size_t nmax = nx_ > ny_ ? nx_ : ny_;
+  double *t1 = malloc(nmax * sizeof(double)), *t2 = malloc(nmax * sizeof(double));
+  lap_union(s, F->ex, t1, fw, fh + 1, 0);
+  lap_union(s, t1, t2, fw, fh + 1, 0);
+  for (int i = 0; i < fw; i++)
+    for (int j = 1; j < fh; j++)
+      if (ex_inner(s, i, j)) EX(F, i, j) -= g * t2[(size_t)i * (fh + 1) + j];
+  lap_union(s, F->ey, t1, fw + 1, fh, 1);
+  lap_union(s, t1, t2, fw + 1, fh, 1);
+  for (int i = 1; i < fw; i++)
+    for (int j = 0; j < fh; j++)
+      if (ey_inner(s, i, j)) EY(F, i, j) -= g * t2[(size_t)i * fh + j];
+  free(t1);
+  free(t2);
+}
+
+/* node E^2 from the fine level's own edges (as node_e2) */
+static double node_e2_union(const orc_sim *s, int i, int j) {
+  const level_t *L = &s->L1;
+  double sx = 0.0, sy = 0.0;
+  int cx = 0, cy = 0;
+  if (ex_has(s, i - 1, j)) {
+    sx += EX(L, i - 1, j) * EX(L, i - 1, j);
+    cx++;
+  }
+  if (ex_has(s, i, j)) {
+    sx += EX(L, i, j) * EX(L, i, j);
+    cx++;
+  }
+  if (ey_has(s, i, j - 1)) {
+    sy += EY(L, i, j - 1) * EY(L, i, j - 1);
+    cy++;
+  }
+  if (ey_has(s, i, j)) {
+    sy += EY(L, i, j) * EY(L, i, j);
+    cy++;
+  }
+  return (cx ? sx / cx : 0.0) + (cy ? sy / cy : 0.0);
+}
+
+/* one fine substep m (1..r) on the union of blocks, Sec. III.C */
+static void em_step_fine_union(orc_sim *s, int m) {
+  level_t *F = &s->L1;
+  const int fw = F->nx, fh = F->ny, r = s->p.r;
+  const double frac = (double)m / r;
+
+  fine_filter_union(s);
+
+  for (int i = 0; i < fw; i++)
+    for (int j = 0; j < fh; j++)
+      if (cact(s, i, j))
+        HZ(F, i, j) -= F->ch * ((EY(F, i + 1, j) - EY(F, i, j)) -
+                                (EX(F, i, j + 1) - EX(F, i, j)));
+  if (m == r / 2) memcpy(s->hz_lo, F->hz, n_hz(F) * sizeof(double));
+  if (m == r / 2 + 1 && m < r) memcpy(s->hz_hi, F->hz, n_hz(F) * sizeof(double));
+
+  for (int i = 0; i < fw; i++)
+    for (int j = 1; j < fh; j++) {
+      if (!ex_inner(s, i, j)) continue;
+      double curl = (HZ(F, i, j) - HZ(F, i, j - 1)) / F->dx;
+      double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i + 1, j));
+      ej_edge(F, &EX(F, i, j), &JX(F, i, j), curl, ne);
+    }
+  for (int i = 1; i < fw; i++)
+    for (int j = 0; j < fh; j++) {
+      if (!ey_inner(s, i, j)) continue;
+      double curl = -(HZ(F, i, j) - HZ(F, i - 1, j)) / F->dx;
+      double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i, j + 1));
+      ej_edge(F, &EY(F, i, j), &JY(F, i, j), curl, ne);
+    }
+  /* boundary edges lie on block lines, so on coarse lines: Eq. (5b) */
+  for (int i = 0; i <= fw; i++)
+    for (int j = 0; j < fh; j++) {
+      if (!ey_has(s, i, j) || ey_inner(s, i, j)) continue;
+      double eo = EY(F, i, j);
+      double en = cfb_ey(s, i / r, j, frac);
+      double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i, j + 1));
+      j_only(F, &JY(F, i, j), eo, en, ne);
+      EY(F, i, j) = en;
+    }
+  for (int i = 0; i < fw; i++)
+    for (int j = 0; j <= fh; j++) {
+      if (!ex_has(s, i, j) || ex_inner(s, i, j)) continue;
+      double eo = EX(F, i, j);
+      double en = cfb_ex(s, i, j / r, frac);
+      double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i + 1, j));
+      j_only(F, &JX(F, i, j), eo, en, ne);
+      EX(F, i, j) = en;
+    }
+  for (int i = 0; i <= fw; i++)
+    for (int j = 0; j <= fh; j++)
+      if (nd_has(s, i, j)) NODE(F, acc, i, j) += node_e2_union(s, i, j);
+}
+
+/* fine -> coarse transfer over the coarse entities whose cells are all
+ * active (as restrict_patch) */
+static void restrict_union(orc_sim *s) {
+  level_t *C = &s->L0, *F = &s->L1;
+  const int r = s->p.r, fh = F->ny;
+  const double *hi = r == 2 ? F->hz : s->hz_hi;
+  for (int i = 0; i < C->nx; i++)
+    for (int j = 0; j < C->ny; j++) {
+      if (!coarse_act(s, i, j)) continue;
+      int p = r * i, q = r * j;
+      double sum = 0.0;
+      for (int a = 0; a < r; a++)
+        for (int b = 0; b < r; b++)
+          sum += 0.5 * (s->hz_lo[(size_t)(p + a) * fh + q + b] +
+                        hi[(size_t)(p + a) * fh + q + b]);
+      HZ(C, i, j) = sum / (r * r);
+    }
+  for (int i = 0; i < C->nx; i++)
+    for (int j = 1; j < C->ny; j++) {
+      if (!coarse_act(s, i, j) || !coarse_act(s, i, j - 1)) continue;
+      int p = r * i, q = r * j;
+      double se = 0.0, sj = 0.0;
+      for (int a = 0; a < r; a++) {
+        se += EX(F, p + a, q);
+        sj += JX(F, p + a, q);
+      }
+      EX(C, i, j) = se / r;
+      JX(C, i, j) = sj / r;
+    }
+  for (int i = 1; i < C->nx; i++)
+    for (int j = 0; j < C->ny; j++) {
+      if (!coarse_act(s, i, j) || !coarse_act(s, i - 1, j)) continue;
+      int p = r * i, q = r * j;
+      double se = 0.0, sj = 0.0;
+      for (int b = 0; b < r; b++) {
+        se += EY(F, p, q + b);
+        sj += JY(F, p, q + b);
+      }
+      EY(C, i, j) = se / r;
+      JY(C, i, j) = sj / r;
+    }
+}
+
+/* continuity on the interior fine nodes; boundary nodes take the coarse
+ * density; coarse nodes with all four cells active take the fine density */
+static void sync_union(orc_sim *s) {
+  level_t *C = &s->L0, *F = &s->L1;
+  const int r = s->p.r, fw = F->nx, fh = F->ny;
+  uint8_t *mask = malloc(n_nd(F));
+  for (int i = 0; i <= fw; i++)
+    for (int j = 0; j <= fh; j++)
+      mask[(size_t)i * (fh + 1) + j] = (uint8_t)nd_inner(s, i, j);
+  continuity(s, F, 1, 0, 0, mask);
+  free(mask);
+  for (int i = 0; i <= fw; i++)
+    for (int j = 0; j <= fh; j++)
+      if (nd_has(s, i, j) && !nd_inner(s, i, j))
+        NODE(F, n, i, j) = bilin(C->n, C->ny + 1, (double)i / r, (double)j / r);
+  for (int i = 1; i < C->nx; i++)
+    for (int j = 1; j < C->ny; j++)
+      if (coarse_act(s, i - 1, j - 1) && coarse_act(s, i, j - 1) &&
+          coarse_act(s, i - 1, j) && coarse_act(s, i, j))
+        NODE(C, n, i, j) = NODE(F, n, r * i, r * j);
+}
+
+/* Add blocks to the fine level (growth only, Sec. III.D).  Entities new to
+ * the level take Eq. (5a) values from the coarse mesh exactly as in
+ * build_patch; the ones it already had keep theirs.  add: [NBy][NBx];
+ * blocks outside the margins are an error. */
+static int grow_union(orc_sim *s, const uint8_t *add, const double *seed_fine) {
+  const level_t *C = &s->L0;
+  level_t *F = &s->L1;
+  const int r = s->p.r, NBx = s->NBx, NBy = s->NBy, xmin = block_xmin(s);
+  size_t nb = (size_t)NBx * NBy;
+  uint8_t *old = malloc(nb);
+  if (!old) return -2;
+  memcpy(old, s->act, nb);
+  int changed = 0;
+  for (int by = 0; by < NBy; by++)
+    for (int bx = 0; bx < NBx; bx++)
+      if (add[by * NBx + bx] && (bx < xmin || by < 1 || bx > NBx - 2 || by > NBy - 2)) {
+        free(old);
+        return -1;
+      }
+  for (size_t b = 0; b < nb; b++)
+    if (add[b] && !s->act[b]) {
+      s->act[b] = 1;
+      changed = 1;
+    }
+  if (!changed) {
+    free(old);
+    return 0;
+  }
+  const double fr = 1.5 - 0.5 / r;
+  const int fw = F->nx, fh = F->ny, fgx = fw + 1;
+  for (int i = 0; i < fw; i++)
+    for (int j = 0; j < fh; j++) {
+      if (!cact(s, i, j) || cact_m(s, old, i, j)) continue;
+      double u = (i + 0.5) / r - 0.5, v = (j + 0.5) / r - 0.5;
+      HZ(F, i, j) = (1.0 - fr) * bilin(s->hz_prev, C->ny, u, v) +
+                    fr * bilin(C->hz, C->ny, u, v);
+    }
+  for (int i = 0; i < fw; i++)
+    for (int j = 0; j <= fh; j++) {
+      if (!ex_has(s, i, j) || ex_has_m(s, old, i, j)) continue;
+      double u = (i + 0.5) / r - 0.5, v = (double)j / r;
+      EX(F, i, j) = bilin(C->ex, C->ny + 1, u, v);
+      JX(F, i, j) = bilin(C->jx, C->ny + 1, u, v);
+    }
+  for (int i = 0; i <= fw; i++)
+    for (int j = 0; j < fh; j++) {
+      if (!ey_has(s, i, j) || ey_has_m(s, old, i, j)) continue;
+      double u = (double)i / r, v = (j + 0.5) / r - 0.5;
+      EY(F, i, j) = bilin(C->ey, C->ny, u, v);
+      JY(F, i, j) = bilin(C->jy, C->ny, u, v);
+    }
+  for (int i = 0; i <= fw; i++)
+    for (int j = 0; j <= fh; j++) {
+      if (!nd_has(s, i, j) || nd_has_m(s, old, i, j)) continue;
+      double u = (double)i / r, v = (double)j / r;
+      NODE(F, n, i, j) = seed_fine ? seed_fine[(size_t)j * fgx + i]
+                                   : bilin(C->n, C->ny + 1, u, v);
+      NODE(F, acc, i, j) = bilin(C->acc, C->ny + 1, u, v);
+      for (int k = 0; k < NRING; k++)
+        RING(F, k, i, j) = bilin(C->ring + (size_t)k * n_nd(C), C->ny + 1, u, v);
+    }
+  free(old);
+  /* extents reported for the union: its bounding box */
+  int bx0 = NBx, by0 = NBy, bx1 = 0, by1 = 0;
+  for (int by = 0; by < NBy; by++)
+    for (int bx = 0; bx < NBx; bx++)
+      if (s->act[by * NBx + bx]) {
+        if (bx < bx0) bx0 = bx;
+        if (by < by0) by0 = by;
+        if (bx + 1 > bx1) bx1 = bx + 1;
+        if (by + 1 > by1) by1 = by + 1;
+      }
+  const int B = s->p.block;
+  s->ext[0] = bx0 * B;
+  s->ext[1] = by0 * B;
+  s->ext[2] = bx1 * B;
+  s->ext[3] = by1 * B;
+  s->has_patch = 1;
+  return 0;
+}
+
+/* growth test of the union: the flagged blocks inside the margins join */
+static int regrid_union(orc_sim *s, const double *seed_fine) {
+  const int NBx = s->NBx, NBy = s->NBy, xmin = block_xmin(s);
+  flag_blocks(s);
+  uint8_t *add = calloc((size_t)NBx * NBy, 1);
+  if (!add) return -2;
+  for (int by = 1; by < NBy - 1; by++)
+    for (int bx = xmin; bx < NBx - 1; bx++) add[by * NBx + bx] = s->bflag[by * NBx + bx];
+  int rc = grow_union(s, add, seed_fine);
+  free(add);
+  return rc;
+}
+
+int orc_add_blocks(orc_sim *s, const uint8_t *mask) {
+  if (!s || !mask || s->p.regrid_rule != ORC_RULE_UNION || s->p.mode == ORC_UNIFORM)
+    return -1;
+  return grow_union(s, mask, NULL);
+}
+
+int orc_get_blocks(const orc_sim *s, uint8_t *dst) {
+  if (!s || !dst || s->p.regrid_rule != ORC_RULE_UNION || s->p.mode == ORC_UNIFORM)
+    return -1;
+  memcpy(dst, s->act, (size_t)s->NBx * s->NBy);
+  return 0;
+}
+
 static int do_regrid(orc_sim *s, const double *seed_fine) {
   int ne[4];
+  if (s->p.regrid_rule == ORC_RULE_UNION) return regrid_union(s, seed_fine);
   if (s->p.regrid_rule == ORC_RULE_LINES)
     line_rule(s, ne);
   else
@@ -909,16 +1264,21 @@ static void sync_point(orc_sim *s) {
   if (s->has_patch) close_block(&s->L1, slot);
   s->blocks++;
   if (s->blocks < NRING) return; /* the first period only fills the window */
-  continuity(s, &s->L0, 0, perx, pery);
-  if (s->has_patch) {
-    continuity(s, &s->L1, 1, 0, 0);
+  continuity(s, &s->L0, 0, perx, pery, NULL);
+  if (s->has_patch && s->act) {
+    sync_union(s);
+  } else if (s->has_patch) {
+    continuity(s, &s->L1, 1, 0, 0, NULL);
     transfer_density(s);
   }
 }
 
 static int base_step(orc_sim *s) {
   em_step_base(s);
-  if (s->has_patch) {
+  if (s->has_patch && s->act) {
+    for (int m = 1; m <= s->p.r; m++) em_step_fine_union(s, m);
+    restrict_union(s);
+  } else if (s->has_patch) {
     for (int m = 1; m <= s->p.r; m++) em_step_fine(s, m);
     restrict_patch(s);
   }
@@ -953,6 +1313,7 @@ int orc_create(const orc_params *p, const double *seed_base,
       return -1;
     if (p->bc_x == ORC_BC_PERIODIC || p->bc_y == ORC_BC_PERIODIC) return -1;
     if (p->mode == ORC_DYNAMIC && p->regrid_every % (spp / NRING)) return -1;
+    if (p->regrid_rule < 0 || p->regrid_rule > 2) return -1;
     if (p->regrid_rule == ORC_RULE_LINES &&
         (p->m_lx < 1 || p->m_ly < 1 || p->m_ex < 1 || p->m_ey < 1 || !(p->n_line > 0.0)))
       return -1;
@@ -993,7 +1354,30 @@ int orc_create(const orc_params *p, const double *seed_base,
       orc_destroy(s);
       return -2;
     }
-    if (p->mode == ORC_STATIC) {
+    if (p->regrid_rule == ORC_RULE_UNION) {
+      s->act = calloc((size_t)s->NBx * s->NBy, 1);
+      rc = level_init(&s->L1, p->r * p->nx, p->r * p->ny, dx / p->r, dt / p->r,
+                      spp * p->r, s->nu_m, p->courant);
+      s->hz_lo = calloc(n_hz(&s->L1), sizeof(double));
+      s->hz_hi = calloc(n_hz(&s->L1), sizeof(double));
+      if (rc || !s->act || !s->hz_lo || !s->hz_hi) {
+        orc_destroy(s);
+        return -2;
+      }
+    }
+    if (p->mode == ORC_STATIC && p->regrid_rule == ORC_RULE_UNION) {
+      /* the blocks covering static_ext (which must be whole blocks) */
+      const int *e = p->static_ext, B = p->block;
+      uint8_t *add = calloc((size_t)s->NBx * s->NBy, 1);
+      rc = add ? 0 : -2;
+      if (!rc && (e[0] % B || e[1] % B || e[2] % B || e[3] % B || e[0] >= e[2] ||
+                  e[1] >= e[3]))
+        rc = -1;
+      for (int by = e[1] / B; !rc && by < e[3] / B; by++)
+        for (int bx = e[0] / B; bx < e[2] / B; bx++) add[by * s->NBx + bx] = 1;
+      if (!rc) rc = grow_union(s, add, seed_fine);
+      free(add);
+    } else if (p->mode == ORC_STATIC) {
       const int *e = p->static_ext;
       if (e[0] < 1 || e[1] < 1 || e[2] > p->nx - 1 || e[3] > p->ny - 1 ||
           e[0] >= e[2] || e[1] >= e[3] ||
@@ -1017,7 +1401,7 @@ int orc_create(const orc_params *p, const double *seed_base,
 void orc_destroy(orc_sim *s) {
   if (!s) return;
   level_free(&s->L0);
-  if (s->has_patch) level_free(&s->L1);
+  if (s->has_patch || s->act) level_free(&s->L1);
   free(s->ex_old);
   free(s->ey_old);
   free(s->hz_prev);
@@ -1026,26 +1410,47 @@ void orc_destroy(orc_sim *s) {
   free(s->bflag);
   free(s->bscan);
   free(s->blist);
+  free(s->act);
   free(s);
 }
 
 /* ---- field access ------------------------------------------------------- */
-static const level_t *level_of(const orc_sim *s, int level) {
-  if (level == 0) return &s->L0;
-  if (level == 1 && s->has_patch) return &s->L1;
-  return NULL;
+/* a level and the region of it that the field calls see: the whole base
+ * level; the patch; for the union of blocks, the bounding box of the active
+ * blocks on the full-domain fine arrays (entries outside the union are 0) */
+typedef struct {
+  const level_t *L;
+  int i0, j0, nx, ny;
+} view_t;
+
+static int view_of(const orc_sim *s, int level, view_t *v) {
+  if (level == 0) {
+    *v = (view_t){&s->L0, 0, 0, s->L0.nx, s->L0.ny};
+    return 0;
+  }
+  if (level == 1 && s->has_patch) {
+    if (s->act) {
+      const int r = s->p.r;
+      *v = (view_t){&s->L1, r * s->ext[0], r * s->ext[1], r * (s->ext[2] - s->ext[0]),
+                    r * (s->ext[3] - s->ext[1])};
+    } else {
+      *v = (view_t){&s->L1, 0, 0, s->L1.nx, s->L1.ny};
+    }
+    return 0;
+  }
+  return -1;
 }
 
 int orc_field_dims(const orc_sim *s, int field, int level, int32_t dims[2]) {
-  const level_t *L = level_of(s, level);
-  if (!L) return -1;
+  view_t v;
+  if (view_of(s, level, &v)) return -1;
   switch (field) {
-  case ORC_HZ: dims[0] = L->ny; dims[1] = L->nx; break;
-  case ORC_EX: case ORC_JX: dims[0] = L->ny + 1; dims[1] = L->nx; break;
-  case ORC_EY: case ORC_JY: dims[0] = L->ny; dims[1] = L->nx + 1; break;
+  case ORC_HZ: dims[0] = v.ny; dims[1] = v.nx; break;
+  case ORC_EX: case ORC_JX: dims[0] = v.ny + 1; dims[1] = v.nx; break;
+  case ORC_EY: case ORC_JY: dims[0] = v.ny; dims[1] = v.nx + 1; break;
   case ORC_N: case ORC_ACC: case ORC_ERMS2:
-    dims[0] = L->ny + 1; dims[1] = L->nx + 1; break;
-  case ORC_RING: dims[0] = NRING * (L->ny + 1); dims[1] = L->nx + 1; break;
+    dims[0] = v.ny + 1; dims[1] = v.nx + 1; break;
+  case ORC_RING: dims[0] = NRING * (v.ny + 1); dims[1] = v.nx + 1; break;
   default: return -1;
   }
   return 0;
@@ -1067,31 +1472,33 @@ static double *field_ptr(const level_t *L, int field, int i, int j, int k) {
 }
 
 int orc_get_field(const orc_sim *s, int field, int level, double *dst) {
-  const level_t *L = level_of(s, level);
+  view_t v;
   int32_t d[2];
-  if (!L || orc_field_dims(s, field, level, d)) return -1;
+  if (view_of(s, level, &v) || orc_field_dims(s, field, level, d)) return -1;
   int planes = field == ORC_RING ? NRING : 1;
   int rows = d[0] / planes, cols = d[1];
   for (int k = 0; k < planes; k++)
     for (int j = 0; j < rows; j++)
       for (int i = 0; i < cols; i++) {
-        double v = field == ORC_ERMS2 ? erms2_at(L, i, j)
-                                      : *field_ptr(L, field, i, j, k);
-        dst[((size_t)k * rows + j) * cols + i] = v;
+        int a = v.i0 + i, b = v.j0 + j;
+        double val = field == ORC_ERMS2 ? erms2_at(v.L, a, b)
+                                        : *field_ptr(v.L, field, a, b, k);
+        dst[((size_t)k * rows + j) * cols + i] = val;
       }
   return 0;
 }
 
 int orc_set_field(orc_sim *s, int field, int level, const double *src) {
-  const level_t *L = level_of(s, level);
+  view_t v;
   int32_t d[2];
-  if (!L || field == ORC_ERMS2 || orc_field_dims(s, field, level, d)) return -1;
+  if (view_of(s, level, &v) || field == ORC_ERMS2 || orc_field_dims(s, field, level, d))
+    return -1;
   int planes = field == ORC_RING ? NRING : 1;
   int rows = d[0] / planes, cols = d[1];
   for (int k = 0; k < planes; k++)
     for (int j = 0; j < rows; j++)
       for (int i = 0; i < cols; i++)
-        *field_ptr(L, field, i, j, k) = src[((size_t)k * rows + j) * cols + i];
+        *field_ptr(v.L, field, v.i0 + i, v.j0 + j, k) = src[((size_t)k * rows + j) * cols + i];
   return 0;
 }
 

@@ -15,11 +15,13 @@
  *     semi-implicit exponential-trapezoid E-J coupling
  *   - a one-period sliding E_rms window and the continuity step, Eq. (4),
  *     with effective-field ionisation and an effective-diffusion blend
- *   - one r = 2 fine patch with time subcycling, Eq. (5b) boundary transfer,
- *     restriction back to the coarse mesh, and the self-aware expansion of
- *     Sec. III.D (threshold + gradient-length flags on 16x16 blocks, prefix
- *     sum compaction, bounding-box growth; or the threshold lines on the
- *     patch sides with steps m_ex, m_ey; Eq. (5a) prolongation).
+ *   - one r = 2 (or 4) fine patch with time subcycling, Eq. (5b) boundary
+ *     transfer, restriction back to the coarse mesh, and the self-aware
+ *     expansion of Sec. III.D (threshold + gradient-length flags on 16x16
+ *     blocks, prefix sum compaction, bounding-box growth; or the threshold
+ *     lines on the patch sides with steps m_ex, m_ey; Eq. (5a)
+ *     prolongation); or, as a variant, a fine level that is the union of the
+ *     flagged blocks themselves.
  * All floating-point state is double.  The regrid flag decision is taken in
  * binary32 (the precision of the GPU kernels) so that both sides decide on
  * identical inputs identically.
@@ -30,7 +32,9 @@
  *   EX  [ny+1][nx  ]   x-edges      (i+1/2, j)      (JX likewise)
  *   EY  [ny  ][nx+1]   y-edges      (i, j+1/2)      (JY likewise)
  *   N, ACC, ERMS2 [ny+1][nx+1] nodes (i, j); RING = 8 node planes.
- * For level 1 (the fine patch) nx, ny are the patch size in fine cells.
+ * For level 1 (the fine patch) nx, ny are the patch size in fine cells; for
+ * the union of blocks, the size of its bounding box (entries outside the
+ * union read 0).
  * Units are SI.  Functions return 0 on success and a negative code on error.
  */
 #ifndef DMR_ORACLE_H
@@ -45,7 +49,7 @@ extern "C" {
 enum { ORC_BC_MUR = 0, ORC_BC_PEC = 1, ORC_BC_PERIODIC = 2 };
 enum { ORC_UNIFORM = 0, ORC_STATIC = 1, ORC_DYNAMIC = 2 };
 enum { ORC_D_BLEND = 0, ORC_D_CONST = 1 };
-enum { ORC_RULE_BLOCKS = 0, ORC_RULE_LINES = 1 };
+enum { ORC_RULE_BLOCKS = 0, ORC_RULE_LINES = 1, ORC_RULE_UNION = 2 };
 enum { ORC_SOURCE_POWER = 0, ORC_SOURCE_TOWNSEND = 1 };
 enum {
   ORC_HZ = 0, ORC_EX = 1, ORC_EY = 2, ORC_JX = 3, ORC_JY = 4,
@@ -80,7 +84,9 @@ typedef struct orc_params {
   /* growth rule of ORC_DYNAMIC: ORC_RULE_BLOCKS (flags, 16x16 blocks,
    * bounding box) or ORC_RULE_LINES (threshold lines on the patch sides,
    * Sec. III.D): initial m_lx x m_ly cells centred on the seed peak; a side
-   * whose line has a node with n > n_line moves out by m_ex (x) / m_ey (y) */
+   * whose line has a node with n > n_line moves out by m_ex (x) / m_ey (y);
+   * or ORC_RULE_UNION: the fine level is the union of the flagged blocks
+   * themselves (with ORC_STATIC: the blocks of static_ext, whole blocks) */
   int32_t regrid_rule;
   int32_t m_lx, m_ly, m_ex, m_ey;
   double n_line;           /* m^-3 */
@@ -112,6 +118,10 @@ int orc_set_field(orc_sim *s, int field, int level, const double *src);
 int orc_get_regrid(const orc_sim *s, uint8_t *flags, int32_t *scan,
                    int32_t *list, int32_t *count);
 int orc_time(const orc_sim *s, double *t, int64_t *step);
+/* ORC_RULE_UNION: add blocks (mask [NBy][NBx], growth only; a block outside
+ * the margins is an error) / read the active blocks */
+int orc_add_blocks(orc_sim *s, const uint8_t *mask);
+int orc_get_blocks(const orc_sim *s, uint8_t *dst);
 /* derived scalars, for pins: see orc_derived in the source */
 int orc_derived(const orc_params *p, double *out, int n_out);
 /* net ionisation rate for a given E_rms^2 (V^2/m^2) */

@@ -83,6 +83,8 @@ def lib():
         L.orc_get_regrid.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, P(C.c_int32)]
         L.orc_time.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int64)]
+        L.orc_add_blocks.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_get_blocks.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_derived.argtypes = [P(OrcParams), P(C.c_double), C.c_int]
         L.orc_nu_net.argtypes = [P(OrcParams), C.c_double]
         L.orc_nu_net.restype = C.c_double
@@ -109,7 +111,7 @@ def make_params(cfg: dict) -> OrcParams:
         elif name == "source_model":
             p.source_model = {"power": 0, "townsend": 1}[cfg.get("source_model", "power")]
         elif name == "regrid_rule":
-            p.regrid_rule = {"blocks": 0, "lines": 1}[cfg.get("regrid_rule", "blocks")]
+            p.regrid_rule = {"blocks": 0, "lines": 1, "union": 2}[cfg.get("regrid_rule", "blocks")]
         elif name == "static_ext":
             for k, v in enumerate(cfg.get("static_ext", (0, 0, 0, 0))):
                 p.static_ext[k] = int(v)
@@ -232,6 +234,21 @@ class Sim:
         lib().orc_get_regrid(self._h, _ptr(flags), _ptr(scan), _ptr(lst),
                              C.byref(cnt))
         return flags, scan, lst[:cnt.value].copy(), cnt.value
+
+    def blocks(self) -> np.ndarray:
+        """Active blocks [NBy][NBx] of the union-of-blocks fine level."""
+        nbx = self.cfg["nx"] // self.cfg["block"]
+        nby = self.cfg["ny"] // self.cfg["block"]
+        out = np.zeros((nby, nbx), np.uint8)
+        if lib().orc_get_blocks(self._h, _ptr(out)):
+            raise RuntimeError("orc_get_blocks failed")
+        return out
+
+    def add_blocks(self, mask):
+        m = np.ascontiguousarray(mask, np.uint8)
+        rc = lib().orc_add_blocks(self._h, _ptr(m))
+        if rc:
+            raise RuntimeError("orc_add_blocks failed: %d" % rc)
 
     def time(self):
         t = C.c_double()
