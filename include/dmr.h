@@ -18,7 +18,8 @@
  *     fine -> coarse transfer after the second substep, density transfers at
  *     each continuity step, and the self-aware growth test of Sec. III.A-D
  *     (threshold and gradient-length flags on square blocks, prefix-sum
- *     compaction, bounding-box growth, Eq. (5a) prolongation).
+ *     compaction, bounding-box growth, Eq. (5a) prolongation); or a fine
+ *     level made of the flagged blocks themselves (DMR_RULE_UNION).
  *
  * Conventions for every call:
  *   - Return value: DMR_OK (0) or a negative DMR_E* code; the text of the
@@ -58,7 +59,7 @@ extern "C" {
 
 enum { DMR_BC_MUR = 0, DMR_BC_PEC = 1 };
 enum { DMR_UNIFORM = 0, DMR_STATIC = 1, DMR_DYNAMIC = 2 };
-enum { DMR_RULE_BLOCKS = 0, DMR_RULE_LINES = 1 };
+enum { DMR_RULE_BLOCKS = 0, DMR_RULE_LINES = 1, DMR_RULE_UNION = 2 };
 enum { DMR_SOURCE_POWER = 0, DMR_SOURCE_TOWNSEND = 1 };
 enum { DMR_D_BLEND = 0, DMR_D_CONST = 1 };
 enum {
@@ -111,9 +112,17 @@ typedef struct dmr_params {
    *                    base cells centred on the seed's peak node; at each
    *                    test, a side of the patch whose boundary line carries a
    *                    node with n > n_line moves out by m_ex (left / right
-   *                    sides) or m_ey (bottom / top).
-   * Both keep the patch one block clear of the outer boundary and right of
-   * the source line by one block, and only grow it. */
+   *                    sides) or m_ey (bottom / top);
+   *   DMR_RULE_UNION   the flags of DMR_RULE_BLOCKS, but the fine level is
+   *                    the union of the flagged blocks themselves instead of
+   *                    their bounding box (several separate regions; Sec.
+   *                    III.A/B flags, Sec. III.C transfers on every
+   *                    coarse/fine boundary edge).  r = 2, block a power of
+   *                    two >= 8; with DMR_STATIC the fine level starts as the
+   *                    blocks of static_ext (whole blocks).  Not supported by
+   *                    the adjoint, save/load and the batched form.
+   * All keep the fine level one block clear of the outer boundary and right
+   * of the source line by one block, and only grow it. */
   int32_t regrid_rule;
   int32_t m_lx, m_ly, m_ex, m_ey;  /* base cells (DMR_RULE_LINES) */
   int32_t pad2_;
@@ -167,8 +176,21 @@ int dmr_step(dmr_sim *s, int64_t n);
 int dmr_regrid(dmr_sim *s);
 
 /* Patch extents in base cells {I0, J0, I1, J1}; all zero when there is no
- * patch.  Synchronises the stream. */
+ * patch.  For DMR_RULE_UNION: the bounding box of the active blocks, which
+ * is also the region level-1 fields are read and written over (entries
+ * outside the union are not part of the level and read 0).  Synchronises
+ * the stream. */
 int dmr_get_patch(dmr_sim *s, int32_t ext[4]);
+
+/* DMR_RULE_UNION only (EINVAL otherwise).  dmr_get_blocks: the active blocks
+ * of the fine level, [NBy][NBx] uint8 (1 = refined), NBx = nx/block;
+ * synchronises the stream.  dmr_add_blocks: add the blocks set in mask
+ * [NBy][NBx] to the fine level (growth only, Sec. III.D); entities new to the
+ * level take Eq. (5a) values from the base level as in a growth; EINVAL if a
+ * block lies within one block of the outer boundary or left of the source
+ * line's margin.  Synchronises the stream. */
+int dmr_get_blocks(dmr_sim *s, uint8_t *dst);
+int dmr_add_blocks(dmr_sim *s, const uint8_t *mask);
 
 /* Result of the last growth test: block flags [NBy][NBx] (uint8), their
  * exclusive prefix sum, the compacted list of flagged block ids (row-major

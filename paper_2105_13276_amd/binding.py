@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libdmr.so")
 BC = {"mur": 0, "pec": 1}
 MODE = {"uniform": 0, "static": 1, "dynamic": 2}
 DMODE = {"blend": 0, "const": 1}
-RULE = {"blocks": 0, "lines": 1}
+RULE = {"blocks": 0, "lines": 1, "union": 2}
 SOURCE = {"power": 0, "townsend": 1}
 FIELD = {"hz": 0, "ex": 1, "ey": 2, "jx": 3, "jy": 4, "n": 5, "acc": 6,
          "erms2": 7, "ring": 8}
@@ -31,7 +31,8 @@ SYMBOLS = ["dmr_workspace_bytes", "dmr_create", "dmr_destroy", "dmr_step",
            "dmr_batch_instance", "dmr_batch_sync", "dmr_batch_config",
            "dmr_batch_set_config", "dmr_batch_destroy", "dmr_batch_last_error",
            "dmr_adjoint_tape_bytes", "dmr_forward_record", "dmr_backward",
-           "dmr_weighted_sum", "dmr_state_bytes", "dmr_save", "dmr_load"]
+           "dmr_weighted_sum", "dmr_state_bytes", "dmr_save", "dmr_load",
+           "dmr_get_blocks", "dmr_add_blocks"]
 
 
 class DmrParams(C.Structure):
@@ -114,6 +115,8 @@ def lib():
         L.dmr_state_bytes.argtypes = [V, P(C.c_size_t)]
         L.dmr_save.argtypes = [V, V, C.c_size_t, C.c_int]
         L.dmr_load.argtypes = [V, V, C.c_size_t, C.c_int]
+        L.dmr_get_blocks.argtypes = [V, V]
+        L.dmr_add_blocks.argtypes = [V, V]
         _lib = L
     return _lib
 
@@ -183,6 +186,19 @@ class _Handle:
         e = (C.c_int32 * 4)()
         self._check(lib().dmr_get_patch(self._h, e), "dmr_get_patch")
         return tuple(e)
+
+    def blocks(self) -> np.ndarray:
+        """Active blocks [NBy][NBx] of a union-of-blocks fine level."""
+        out = np.zeros((self.cfg["ny"] // self.cfg["block"],
+                        self.cfg["nx"] // self.cfg["block"]), np.uint8)
+        self._check(lib().dmr_get_blocks(self._h, _ptr(out)), "dmr_get_blocks")
+        return out
+
+    def add_blocks(self, mask):
+        m = np.ascontiguousarray(mask, np.uint8)
+        if m.shape != (self.cfg["ny"] // self.cfg["block"], self.cfg["nx"] // self.cfg["block"]):
+            raise ValueError("mask shape %s" % (m.shape,))
+        self._check(lib().dmr_add_blocks(self._h, _ptr(m)), "dmr_add_blocks")
 
     def regrid_info(self):
         nbx = self.cfg["nx"] // self.cfg["block"]

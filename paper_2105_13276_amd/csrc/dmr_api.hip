@@ -55,6 +55,10 @@ struct Layout {
   size_t off_l1 = 0, off_flag = 0, off_scan = 0, off_list = 0, off_desc = 0,
          off_err = 0, off_stage = 0, total = 0;
   int NB = 0;
+  // union-of-blocks fine level: two block maps, two tile lists (64 x 4 tiles
+  // at most over the fine domain)
+  size_t off_act = 0, off_tiles = 0;
+  size_t max_tiles = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
@@ -80,6 +84,11 @@ Layout layout_of(const dmr_params* p) {
   L.off_desc = off;  off += 256;
   L.off_err = off;   off += 256;
   L.off_stage = off; off += align256(stage * sizeof(float));
+  if (refined(p) && p->regrid_rule == DMR_RULE_UNION) {
+    L.max_tiles = (size_t)((p->r * p->nx + 1 + kTX - 1) / kTX) * ((p->r * p->ny + 1 + 3) / 4);
+    L.off_act = off;   off += 2 * align256(nb);
+    L.off_tiles = off; off += 2 * align256(L.max_tiles * sizeof(int2));
+  }
   L.total = off;
   return L;
 }
@@ -118,7 +127,16 @@ int check_params(const dmr_params* p, std::string* why) {
     if (p->mode == DMR_DYNAMIC &&
         (p->regrid_every <= 0 || p->regrid_every % (spp / kRing)))
       return bad("regrid_every must be a positive multiple of steps per window block");
-    if (p->regrid_rule < 0 || p->regrid_rule > 1) return bad("bad regrid_rule");
+    if (p->regrid_rule < 0 || p->regrid_rule > 2) return bad("bad regrid_rule");
+    if (p->regrid_rule == DMR_RULE_UNION) {
+      if (p->r != 2) return bad("the union-of-blocks fine level needs r = 2");
+      if (p->block < 8 || (p->block & (p->block - 1)))
+        return bad("the union-of-blocks fine level needs a power-of-two block >= 8");
+      const int* e = p->static_ext;
+      if (p->mode == DMR_STATIC &&
+          (e[0] % p->block || e[1] % p->block || e[2] % p->block || e[3] % p->block))
+        return bad("static_ext of the union-of-blocks fine level must be whole blocks");
+    }
     if (p->mode == DMR_DYNAMIC && p->regrid_rule == DMR_RULE_LINES &&
         (p->m_lx < 1 || p->m_ly < 1 || p->m_ex < 1 || p->m_ey < 1 || !(p->n_line > 0.0)))
       return bad("the threshold-line rule needs m_lx, m_ly, m_ex, m_ey >= 1, n_line > 0");
@@ -206,6 +224,16 @@ struct dmr_sim {
   bool had0 = false, keep_n0 = false;
   int ext0[4] = {0, 0, 0, 0};
   int peak[2] = {0, 0};  // base node of the seed's first maximum (row by row)
+  // union-of-blocks fine level: block maps on the device (current d_act[acur],
+  // the other one free for the next growth) and on the host, the tiles of
+  // the level (d_tiles) and of the last growth (d_ptiles), 64 x tyu
+  bool uni = false;
+  uint8_t* d_act[2] = {nullptr, nullptr};
+  int acur = 0;
+  std::vector<uint8_t> h_act, h_act_new, h_flag;
+  int2 *d_tiles = nullptr, *d_ptiles = nullptr;
+  std::vector<int2> h_tiles, h_ptiles;
+  int ntiles = 0, tyu = 16;
   AdjTape tape;
   hipStream_t rep_st = nullptr;  // the adjoint's replay stream (default priority)
   hipEvent_t ev_rep[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr}, ev_sync = nullptr;
@@ -440,8 +468,155 @@ int regrid_lines(dmr_sim* s, bool keep_n) {
   return prolong(s, ne, keep_n);
 }
 
+// ---- the fine level as a union of blocks ----------------------------------
+// The blocks the growth test flags (Sec. III.A/B) are refined as they are,
+// instead of their bounding box: the level is every cell of an active block
+// (r = 2, blocks of 2^fbs fine cells a side), with the edges and nodes
+// touching them.  Tiles (64 x tyu fine nodes) run where a cell of their
+// one-cell dilation is active; growth prolongs only what is new.
+
+// first block column a fine region may use: one block clear of the outer
+// boundary and of the source line
+int block_xmin(const dmr_params& p) {
+  int xmin = 1;
+  if (p.tfsf_i > 0) xmin = std::max(xmin, (p.tfsf_i + 2 * p.block - 1) / p.block);
+  return xmin;
+}
+
+int log2i(int v) {
+  int k = 0;
+  while ((1 << k) < v) k++;
+  return k;
+}
+
+// tiles whose dilated cells [i0-1, i0+63] x [j0-1, j0+ty-1] meet a block
+// with pick(block) set
+template <class Pick>
+void union_tiles(const dmr_sim* s, int ty, Pick pick, std::vector<int2>* out) {
+  const dmr_params& p = s->p;
+  const int fnx = p.r * p.nx, fny = p.r * p.ny, FB = p.r * p.block;
+  const int NBx = p.nx / p.block, NBy = p.ny / p.block;
+  const int ntx = (fnx + 1 + kTX - 1) / kTX, nty = (fny + 1 + ty - 1) / ty;
+  out->clear();
+  for (int ty_ = 0; ty_ < nty; ty_++) {
+    const int jl = std::max(ty_ * ty - 1, 0), jh = std::min(ty_ * ty + ty - 1, fny - 1);
+    if (jl > jh) continue;
+    for (int tx = 0; tx < ntx; tx++) {
+      const int il = std::max(tx * kTX - 1, 0), ih = std::min(tx * kTX + kTX - 1, fnx - 1);
+      if (il > ih) continue;
+      bool hit = false;
+      for (int bj = jl / FB; bj <= std::min(jh / FB, NBy - 1) && !hit; bj++)
+        for (int bi = il / FB; bi <= std::min(ih / FB, NBx - 1) && !hit; bi++)
+          hit = pick(bj * NBx + bi);
+      if (hit) out->push_back(make_int2(tx, ty_));
+    }
+  }
+}
+
+void union_level_args(const dmr_sim* s, int* fbs, int* nbkx, int* nbky) {
+  *fbs = log2i(s->p.r * s->p.block);
+  *nbkx = s->p.nx / s->p.block;
+  *nbky = s->p.ny / s->p.block;
+}
+
+// Add the blocks of add ([NBy][NBx]) to the level.  strict: a block outside
+// the margins is an error (else it is left out).
+int grow_union(dmr_sim* s, const uint8_t* add, bool keep_n, bool strict) {
+  const dmr_params& p = s->p;
+  const int NBx = p.nx / p.block, NBy = p.ny / p.block, xmin = block_xmin(p);
+  auto inside = [&](int b) {
+    const int bx = b % NBx, by = b / NBx;
+    return bx >= xmin && by >= 1 && bx <= NBx - 2 && by <= NBy - 2;
+  };
+  s->h_act_new = s->h_act;
+  bool changed = false;
+  for (int b = 0; b < NBx * NBy; b++) {
+    if (!add[b]) continue;
+    if (!inside(b)) {
+      if (strict) return fail(s, DMR_EINVAL, "block %d outside the margins", b);
+      continue;
+    }
+    if (!s->h_act_new[b]) { s->h_act_new[b] = 1; changed = true; }
+  }
+  if (!changed) return DMR_OK;
+  const std::vector<uint8_t>& nw = s->h_act_new;
+  const std::vector<uint8_t>& od = s->h_act;
+  union_tiles(s, s->tyu, [&](int b) { return nw[b] && !od[b]; }, &s->h_ptiles);
+  union_tiles(s, s->tyu, [&](int b) { return nw[b] != 0; }, &s->h_tiles);
+  uint8_t* act_new = s->d_act[1 - s->acur];
+  HIPCHK(s, hipMemcpyAsync(act_new, nw.data(), nw.size(), hipMemcpyHostToDevice, s->st));
+  HIPCHK(s, hipMemcpyAsync(s->d_ptiles, s->h_ptiles.data(), s->h_ptiles.size() * sizeof(int2),
+                           hipMemcpyHostToDevice, s->st));
+  HIPCHK(s, hipMemcpyAsync(s->d_tiles, s->h_tiles.data(), s->h_tiles.size() * sizeof(int2),
+                           hipMemcpyHostToDevice, s->st));
+  Level &C = s->L0, &F = s->L1;
+  ProlongArgs A{};
+  A.L = 0; A.B = 0; A.R = F.NX; A.T = F.NY;
+  A.pitch = F.pitch; A.cpitch = C.pitch;
+  A.plane = F.plane; A.cplane = C.plane;
+  A.keep_n = keep_n ? 1 : 0;
+  A.rf = p.r;
+  const int c = s->ccur;
+  A.chz = C.hz[c]; A.chz_prev = C.hz[1 - c];
+  A.cex = C.ex[c]; A.cey = C.ey[c]; A.cjx = C.jx[c]; A.cjy = C.jy[c];
+  A.cn = C.n[s->ncur]; A.cacc = C.acc; A.cring = C.ring;
+  A.hz = F.hz[0]; A.ex = F.ex[0]; A.ey = F.ey[0]; A.jx = F.jx[0]; A.jy = F.jy[0];
+  A.n = F.n[s->ncur]; A.acc = F.acc; A.ring = F.ring;
+  A.act = act_new; A.act_old = s->d_act[s->acur];
+  A.seed = keep_n ? s->stage : nullptr;  // the fine seed, uploaded there at creation
+  union_level_args(s, &A.fbs, &A.nbkx, &A.nbky);
+  ev_begin(s, 3);
+  hipError_t e = launch_prolong_union(A, s->d_ptiles, (int)s->h_ptiles.size(), s->tyu, s->st);
+  ev_end(s);
+  if (e != hipSuccess) return hipfail(s, e, "prolongation launch");
+  s->acur = 1 - s->acur;
+  s->h_act.swap(s->h_act_new);
+  s->ntiles = (int)s->h_tiles.size();
+  int bx0 = NBx, by0 = NBy, bx1 = 0, by1 = 0;
+  for (int b = 0; b < NBx * NBy; b++)
+    if (s->h_act[b]) {
+      bx0 = std::min(bx0, b % NBx); by0 = std::min(by0, b / NBx);
+      bx1 = std::max(bx1, b % NBx + 1); by1 = std::max(by1, b / NBx + 1);
+    }
+  s->ext[0] = bx0 * p.block; s->ext[1] = by0 * p.block;
+  s->ext[2] = bx1 * p.block; s->ext[3] = by1 * p.block;
+  s->has_patch = true;
+  return DMR_OK;
+}
+
+// the growth test of the union: the flagged blocks inside the margins join
+int regrid_union(dmr_sim* s, bool keep_n) {
+  const dmr_params& p = s->p;
+  const int Bk = p.block, NBx = p.nx / Bk, NBy = p.ny / Bk;
+  int* D = s->h_desc;
+  for (int k = 0; k < 16; k++) D[k] = 0;
+  D[10] = block_xmin(p); D[11] = 1; D[12] = NBx - 1; D[13] = NBy - 1;
+  HIPCHK(s, hipMemcpyAsync(s->d_desc, D, 16 * sizeof(int), hipMemcpyHostToDevice, s->st));
+  FlagArgs F{};
+  F.n = s->L0.n[s->ncur];
+  F.pitch = s->L0.pitch; F.NX = p.nx; F.NY = p.ny; F.Bk = Bk;
+  F.NBx = NBx; F.NBy = NBy;
+  F.thr = (float)(p.n_thr_over_nc * s->n_c);
+  F.flo = (float)(p.n_floor_over_nc * s->n_c);
+  F.g2 = (float)(p.grad_thr * p.grad_thr);
+  F.bflag = s->d_flag;
+  ScanArgs S{};
+  S.bflag = s->d_flag; S.NB = NBx * NBy; S.NBx = NBx; S.NBy = NBy;
+  S.scan = s->d_scan; S.list = s->d_list; S.desc = s->d_desc;
+  ev_begin(s, 3);
+  hipError_t e = launch_regrid_test(F, S, s->st);
+  ev_end(s);
+  if (e != hipSuccess) return hipfail(s, e, "regrid launch");
+  s->h_flag.assign((size_t)NBx * NBy, 0);
+  HIPCHK(s, hipMemcpyAsync(s->h_flag.data(), s->d_flag, s->h_flag.size(),
+                           hipMemcpyDeviceToHost, s->st));
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  return grow_union(s, s->h_flag.data(), keep_n, false);
+}
+
 int regrid(dmr_sim* s, bool keep_n) {
   const dmr_params& p = s->p;
+  if (p.regrid_rule == DMR_RULE_UNION) return regrid_union(s, keep_n);
   if (p.regrid_rule == DMR_RULE_LINES) return regrid_lines(s, keep_n);
   const int Bk = p.block, NBx = p.nx / Bk, NBy = p.ny / Bk;
   int* D = s->h_desc;
@@ -534,6 +709,12 @@ void make_fine_em(const dmr_sim* s, int m, int c, int nc, int ty, EMArgs* G) {
     G->cjx = C.jx[1 - c]; G->cjy = C.jy[1 - c];
   }
   G->nbx = (G->R - G->L + 1 + kTX - 1) / kTX;
+  if (s->uni) {  // the whole fine domain; membership from the block map
+    G->L = 0; G->B = 0; G->R = F.NX; G->T = F.NY;
+    G->act = s->d_act[s->acur];
+    union_level_args(s, &G->fbs, &G->nbkx, &G->nbky);
+    G->cnx = p.nx; G->cny = p.ny;
+  }
   (void)ty;
 }
 
@@ -589,6 +770,11 @@ void make_fine_cont(const dmr_sim* s, int nc, ContArgs* G) {
   G->cn1 = C.n[1 - nc]; G->cpitch = C.pitch;
   G->rf = p.r;
   G->nbx = (G->R - G->L + 1 + kTX - 1) / kTX;
+  if (s->uni) {
+    G->L = 0; G->B = 0; G->R = F.NX; G->T = F.NY;
+    G->act = s->d_act[s->acur];
+    union_level_args(s, &G->fbs, &G->nbkx, &G->nbky);
+  }
 }
 
 // copy jobs of one stored plane: whole coarse planes, patch rows of fine ones
@@ -627,7 +813,7 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
   const long fine_cells =
       s->has_patch ? (long)p.r * p.r * (s->ext[2] - s->ext[0]) * (s->ext[3] - s->ext[1]) : 0;
   const bool big = fine_cells > s->fuse_max;
-  const bool fuse = s->has_patch && s->fuse_fine && !big;
+  const bool fuse = s->has_patch && s->fuse_fine && !big && !s->uni;
   // replay: the fused kernels store the step's values themselves; the
   // one-substep form takes copies
   const bool kst = st && (!s->has_patch || fuse);
@@ -721,7 +907,16 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
       EMArgs G;
       make_fine_em(s, m, c, s->ncur, s->ty1, &G);
       ev_begin(s, 1);
-      e = launch_em(G, true, s->ty1, s->nt1, s->st);
+      if (s->uni) {
+        // the transfer runs after the substep (see launch_restrict_union)
+        const bool last = G.restrict_on != 0;
+        G.restrict_on = 0;
+        e = launch_em_union(G, s->d_tiles, s->ntiles, s->tyu, s->nt1, s->st);
+        if (e == hipSuccess && last)
+          e = launch_restrict_union(G, G.hz0, s->d_tiles, s->ntiles, s->tyu, s->st);
+      } else {
+        e = launch_em(G, true, s->ty1, s->nt1, s->st);
+      }
       ev_end(s);
       if (e != hipSuccess) return hipfail(s, e, "fine EM launch");
       if (st && (m == 1 || cx->last)) {
@@ -759,7 +954,8 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
       make_fine_cont(s, s->ncur, &G);
       G.slot = slot; G.update = update;
       ev_begin(s, 2);
-      e = launch_cont(G, true, s->st);
+      if (s->uni) e = launch_cont_union(G, s->d_tiles, s->ntiles, s->tyu, s->st);
+      else e = launch_cont(G, true, s->st);
       ev_end(s);
       if (e != hipSuccess) return hipfail(s, e, "fine continuity launch");
     }
@@ -894,6 +1090,19 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   s->d_desc = (int*)(s->ws + lay.off_desc);
   s->d_err = (int*)(s->ws + lay.off_err);
   s->stage = (float*)(s->ws + lay.off_stage);
+  if (refined(p) && p->regrid_rule == DMR_RULE_UNION) {
+    s->uni = true;
+    const size_t nb = (size_t)lay.NB;
+    s->d_act[0] = (uint8_t*)(s->ws + lay.off_act);
+    s->d_act[1] = s->d_act[0] + align256(nb);
+    s->d_tiles = (int2*)(s->ws + lay.off_tiles);
+    s->d_ptiles = s->d_tiles + align256(lay.max_tiles * sizeof(int2)) / sizeof(int2);
+    s->h_act.assign(nb, 0);
+    if (const char* f = getenv("DMR_UTY")) {
+      const int v = atoi(f);
+      if (v == 4 || v == 8 || v == 16) s->tyu = v;
+    }
+  }
   s->seg0 = stream_rows(p->nx, p->ny);
   if (const char* f = getenv("DMR_FUSE")) s->fuse_fine = atoi(f) != 0;
   // one launch per coarse step pays off where launch latency dominates; on
@@ -908,12 +1117,12 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   if (e != hipSuccess) { rc = hipfail(s, e, "workspace clear"); delete s; return rc; }
   // seeds: float32 on the pitched node grid
   std::vector<float> h;
-  auto upload = [&](const double* src, const Level& L) -> hipError_t {
+  auto upload = [&](const double* src, const Level& L, float* dst) -> hipError_t {
     h.assign(L.plane, 0.f);
     for (int j = 0; j <= L.NY; j++)
       for (int i = 0; i <= L.NX; i++)
         h[(size_t)j * L.pitch + i] = (float)src[(size_t)j * (L.NX + 1) + i];
-    hipError_t r1 = hipMemcpyAsync(L.n[0], h.data(), L.plane * sizeof(float),
+    hipError_t r1 = hipMemcpyAsync(dst, h.data(), L.plane * sizeof(float),
                                    hipMemcpyHostToDevice, s->st);
     if (r1 != hipSuccess) return r1;
     return hipStreamSynchronize(s->st);
@@ -927,19 +1136,31 @@ int dmr_create(const dmr_params* p, const double* seed_base,
           s->peak[0] = i; s->peak[1] = j;
         }
   }
-  if (seed_base && (e = upload(seed_base, s->L0)) != hipSuccess) {
+  if (seed_base && (e = upload(seed_base, s->L0, s->L0.n[0])) != hipSuccess) {
     rc = hipfail(s, e, "seed upload");
     delete s;
     return rc;
   }
   const bool keep_n = refined(p) && seed_fine;
-  if (keep_n && (e = upload(seed_fine, s->L1)) != hipSuccess) {
+  // the union of blocks takes the fine seed on its own nodes only (through
+  // the prolongation, from the staging plane); the patch keeps it in place
+  if (keep_n && (e = upload(seed_fine, s->L1, s->uni ? s->stage : s->L1.n[0])) != hipSuccess) {
     rc = hipfail(s, e, "fine seed upload");
     delete s;
     return rc;
   }
-  if (p->mode == DMR_STATIC) rc = prolong(s, p->static_ext, keep_n);
-  else if (p->mode == DMR_DYNAMIC) rc = regrid(s, keep_n);
+  if (p->mode == DMR_STATIC && s->uni) {  // the blocks of static_ext
+    const int Bk = p->block, NBx = p->nx / Bk;
+    std::vector<uint8_t> add((size_t)lay.NB, 0);
+    for (int by = p->static_ext[1] / Bk; by < p->static_ext[3] / Bk; by++)
+      for (int bx = p->static_ext[0] / Bk; bx < p->static_ext[2] / Bk; bx++)
+        add[(size_t)by * NBx + bx] = 1;
+    rc = grow_union(s, add.data(), keep_n, true);
+  } else if (p->mode == DMR_STATIC) {
+    rc = prolong(s, p->static_ext, keep_n);
+  } else if (p->mode == DMR_DYNAMIC) {
+    rc = regrid(s, keep_n);
+  }
   s->had0 = s->has_patch;
   s->keep_n0 = keep_n;
   for (int k = 0; k < 4; k++) s->ext0[k] = s->ext[k];
@@ -996,6 +1217,23 @@ int dmr_get_patch(dmr_sim* s, int32_t ext[4]) {
   if (!s || !ext) return DMR_EINVAL;
   HIPCHK(s, hipStreamSynchronize(s->st));
   for (int k = 0; k < 4; k++) ext[k] = s->has_patch ? s->ext[k] : 0;
+  return DMR_OK;
+}
+
+int dmr_get_blocks(dmr_sim* s, uint8_t* dst) {
+  if (!s || !dst) return DMR_EINVAL;
+  if (!s->uni) return fail(s, DMR_EINVAL, "not a union-of-blocks fine level");
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  memcpy(dst, s->h_act.data(), s->h_act.size());
+  return DMR_OK;
+}
+
+int dmr_add_blocks(dmr_sim* s, const uint8_t* mask) {
+  if (!s || !mask) return DMR_EINVAL;
+  if (!s->uni) return fail(s, DMR_EINVAL, "not a union-of-blocks fine level");
+  const int rc = grow_union(s, mask, false, true);
+  if (rc) return rc;
+  HIPCHK(s, hipStreamSynchronize(s->st));
   return DMR_OK;
 }
 
@@ -1517,6 +1755,7 @@ int dmr_forward_record(dmr_sim* s, int64_t steps, int ckpt_every, void* d_tape, 
   if (s->p.source_model != DMR_SOURCE_POWER || s->p.beta_rec > 0.0)
     return fail(s, DMR_EINVAL, "the adjoint supports the power-law source without recombination");
   if (refined(&s->p) && s->p.r != 2) return fail(s, DMR_EINVAL, "the adjoint supports r = 2");
+  if (s->uni) return fail(s, DMR_EINVAL, "the adjoint supports the rectangular patch");
   if (!d_tape || ((uintptr_t)d_tape & 255)) return fail(s, DMR_EINVAL, "tape must be 256-byte aligned");
   const TapeLayout T = tape_layout(&s->p, steps, ckpt_every);
   if (bytes < T.total) return fail(s, DMR_ENOMEM, "tape needs %zu bytes", T.total);
@@ -1684,6 +1923,7 @@ int dmr_state_bytes(const dmr_sim* s, size_t* bytes) {
 
 int dmr_save(dmr_sim* s, void* dst, size_t bytes, int dst_on_device) {
   if (!s || !dst) return DMR_EINVAL;
+  if (s->uni) return fail(s, DMR_EINVAL, "save/load support the rectangular patch");
   const size_t need = state_bytes(s);
   if (bytes < need) return fail(s, DMR_ENOMEM, "state needs %zu bytes", need);
   if (dst_on_device && ((uintptr_t)dst & 255))
@@ -1709,6 +1949,7 @@ int dmr_save(dmr_sim* s, void* dst, size_t bytes, int dst_on_device) {
 
 int dmr_load(dmr_sim* s, const void* src, size_t bytes, int src_on_device) {
   if (!s || !src) return DMR_EINVAL;
+  if (s->uni) return fail(s, DMR_EINVAL, "save/load support the rectangular patch");
   const size_t need = state_bytes(s);
   if (bytes < need) return fail(s, DMR_ENOMEM, "state needs %zu bytes", need);
   if (src_on_device && ((uintptr_t)src & 255))
@@ -1809,6 +2050,10 @@ int batch_layout(const dmr_params* p, int count, BatchLayout* L, std::string* wh
     int rc = check_params(&p[k], why);
     if (rc) return rc;
     if (refined(&p[k]) && p[k].r != 2) { *why = "the batched form supports r = 2"; return DMR_EINVAL; }
+    if (refined(&p[k]) && p[k].regrid_rule == DMR_RULE_UNION) {
+      *why = "the batched form supports the rectangular patch";
+      return DMR_EINVAL;
+    }
     const double spp0 = p[0].cells_per_lambda / p[0].courant;
     const double sppk = p[k].cells_per_lambda / p[k].courant;
     if (std::fabs(spp0 - sppk) > 1e-9 || p[k].mode != p[0].mode ||

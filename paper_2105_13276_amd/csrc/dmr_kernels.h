@@ -60,6 +60,11 @@ struct EMArgs {
   // substep 2 (st2, nullable), n.
   float *stix, *stiy, *stox, *stoy, *stn;
   float *st0x, *st0y, *st1x, *st1y, *st2x, *st2y;
+  // fine level as a union of blocks (act non-null): active blocks
+  // [nbky][nbkx] of 2^fbs x 2^fbs fine cells; L = B = 0, R x T the fine
+  // domain; the tiles come from a list
+  const uint8_t* act;
+  int fbs, nbkx, nbky;
 };
 
 struct ContArgs {
@@ -88,6 +93,9 @@ struct ContArgs {
   int cpitch;
   int rf;          // fine level: refinement factor (0 or 2: r = 2; 4)
   int nbx;         // batched launches: blocks per row of blocks
+  // fine level as a union of blocks (as in EMArgs)
+  const uint8_t* act;
+  int fbs, nbkx, nbky;
 };
 
 struct FlagArgs {
@@ -113,10 +121,30 @@ struct ProlongArgs {
   int rf;              // refinement factor (0 or 2: r = 2; 4)
   const float *chz, *chz_prev, *cex, *cey, *cjx, *cjy, *cn, *cacc, *cring;
   float *hz, *ex, *ey, *jx, *jy, *n, *acc, *ring;
+  // fine level as a union of blocks: active blocks after (act) and before
+  // (act_old) the growth, as in EMArgs
+  const uint8_t *act, *act_old;
+  int fbs, nbkx, nbky;
+  const float* seed;  // union with keep_n: the fine density of new nodes (pitched)
 };
 
 // patch substep kernel, 64 x ty tiles of nt threads (256 or 1024)
 hipError_t launch_em(const EMArgs& A, bool fine, int ty, int nt, hipStream_t st);
+// the same substep on the union of blocks: the 64 x ty tiles (tile column,
+// tile row) listed in tiles[ntiles]
+hipError_t launch_em_union(const EMArgs& A, const int2* tiles, int ntiles, int ty, int nt,
+                           hipStream_t st);
+// fine -> coarse transfer of the union of blocks after the last substep
+// (A.restrict_on off in that substep): A holds the final fine state in
+// hz1.. and the coarse targets; hz_half the Hz entering the last substep
+hipError_t launch_restrict_union(const EMArgs& A, const float* hz_half, const int2* tiles,
+                                 int ntiles, int ty, hipStream_t st);
+// continuity on the fine union of blocks over the same tile list (64 x ty)
+hipError_t launch_cont_union(const ContArgs& A, const int2* tiles, int ntiles, int ty,
+                             hipStream_t st);
+// prolongation into the blocks new to the union, over the listed 64 x ty tiles
+hipError_t launch_prolong_union(const ProlongArgs& A, const int2* tiles, int ntiles, int ty,
+                                hipStream_t st);
 // both patch substeps of a coarse step in one launch: reads buffer 0 (hz0..),
 // writes buffer 1 (hz1..), A.frac = time fraction of substep 1, restriction on
 hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st);

@@ -84,7 +84,7 @@ __device__ inline float win_e2(float sx, int cx, float sy, int cy) {
 // (registers), so the block waits for memory once; the phases after that
 // run from LDS and registers.
 // ---------------------------------------------------------------------------
-template <int TY, int NT>
+template <int TY, int NT, bool UN = false>
 __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   constexpr int EW = kTX + 3, EH = TY + 3;  // old E (filtered)
   constexpr int HW = kTX + 2, HH = TY + 2;  // new Hz
@@ -106,7 +106,13 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   __shared__ float sExn[NH][NW], sEyn[NH][NW];
   __shared__ float sN[DH][DW];
   __shared__ float sJx[TY][kTX], sJy[TY][kTX];
-  __shared__ float sB[5][NW > NH ? NW : NH];  // Eq. (5b) values: Ex rows B, T; Ey columns L, R
+  // Eq. (5b) values: Ex rows B, T; Ey columns L, R.  Union of blocks: Ey on
+  // up to 4 block columns (rows 0-3), Ex on up to 2 block rows (4-5)
+  constexpr int NBL = UN ? 6 : 4;
+  __shared__ float sB[NBL + 1][NW > NH ? NW : NH];
+  // union of blocks: activity of the cells [i0-5, i0+kTX+3) x [j0-5, j0+TY+3)
+  constexpr int CW = kTX + 8, CH = TY + 8;
+  __shared__ uint8_t sC[UN ? CH : 1][UN ? CW : 1];
 
   const int i0 = A.L + bx * kTX;
   const int j0 = A.B + by * TY;
@@ -114,10 +120,35 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   const int L = A.L, R = A.R, B = A.B, T = A.T;
   const int pitch = A.pitch;
   const bool filt = A.gamma > 0.f;
-  auto hz_ok = [&](int i, int j) { return i >= L && i < R && j >= B && j < T; };
-  auto ex_ok = [&](int i, int j) { return i >= L && i < R && j >= B && j <= T; };
-  auto ey_ok = [&](int i, int j) { return i >= L && i <= R && j >= B && j < T; };
-  auto nd_ok = [&](int i, int j) { return i >= L && i <= R && j >= B && j <= T; };
+  // which entities belong to the fine level: the patch rectangle, or (union
+  // of blocks) a cell in an active block, an edge beside such a cell, a node
+  // at one.  ex_in / ey_in (for an edge that belongs): both cells beside it
+  // do (else it lies on the coarse/fine boundary).
+  auto cact = [&](int i, int j) -> bool { return sC[UN ? j - j0 + 5 : 0][UN ? i - i0 + 5 : 0]; };
+  auto hz_ok = [&](int i, int j) -> bool {
+    if constexpr (UN) return cact(i, j);
+    else return i >= L && i < R && j >= B && j < T;
+  };
+  auto ex_ok = [&](int i, int j) -> bool {
+    if constexpr (UN) return cact(i, j) || cact(i, j - 1);
+    else return i >= L && i < R && j >= B && j <= T;
+  };
+  auto ey_ok = [&](int i, int j) -> bool {
+    if constexpr (UN) return cact(i, j) || cact(i - 1, j);
+    else return i >= L && i <= R && j >= B && j < T;
+  };
+  auto nd_ok = [&](int i, int j) -> bool {
+    if constexpr (UN) return cact(i, j) || cact(i - 1, j) || cact(i, j - 1) || cact(i - 1, j - 1);
+    else return i >= L && i <= R && j >= B && j <= T;
+  };
+  auto ex_in = [&](int i, int j) -> bool {
+    if constexpr (UN) return cact(i, j) && cact(i, j - 1);
+    else return j != B && j != T;
+  };
+  auto ey_in = [&](int i, int j) -> bool {
+    if constexpr (UN) return cact(i, j) && cact(i - 1, j);
+    else return i != L && i != R;
+  };
   // clamped (always valid) addresses of each entity kind
   auto cl = [&](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
   auto o_hz = [&](int i, int j) { return (size_t)cl(j, B, T - 1) * pitch + cl(i, L, R - 1); };
@@ -174,10 +205,15 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   // nearest coarse edges (weights w0, w1) and in time between the old and
   // new coarse E.  Loads are unconditional (address 0 where unused).
   int bg = -1, bc = 0;
-  if (tid < NW) { bg = 0; bc = tid; }
-  else if (tid < 2 * NW) { bg = 1; bc = tid - NW; }
-  else if (tid < 2 * NW + NH) { bg = 2; bc = tid - 2 * NW; }
-  else if (tid < 2 * NW + 2 * NH) { bg = 3; bc = tid - 2 * NW - NH; }
+  if constexpr (UN) {
+    if (tid < 4 * NH) { bg = tid / NH; bc = tid % NH; }
+    else if (tid < 4 * NH + 2 * NW) { bg = 4 + (tid - 4 * NH) / NW; bc = (tid - 4 * NH) % NW; }
+  } else {
+    if (tid < NW) { bg = 0; bc = tid; }
+    else if (tid < 2 * NW) { bg = 1; bc = tid - NW; }
+    else if (tid < 2 * NW + NH) { bg = 2; bc = tid - 2 * NW; }
+    else if (tid < 2 * NW + 2 * NH) { bg = 3; bc = tid - 2 * NW - NH; }
+  }
   size_t bco = 0, bco2 = 0;
   float bw0 = 0.f, bw1 = 0.f;
   bool bvalid = false;
@@ -196,7 +232,48 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
     }
   };
   const int rsh = A.rf == 4 ? 2 : 1;  // fine -> coarse index on a line
-  if (bg == 0 || bg == 1) {
+  // union of blocks: the block lines crossing the new-E region [i0-1,
+  // i0+kTX) x [j0-1, j0+TY), the first at or after i0-1 (j0-1); every
+  // position on them gets its Eq. (5b) value, loads clamped into the coarse
+  // grid (used only where the edge is on the coarse/fine boundary)
+  const int FB = UN ? 1 << A.fbs : 1;
+  const int lc0 = UN ? ((i0 - 1 + FB) >> A.fbs << A.fbs) - (((i0 - 1) & (FB - 1)) == 0 ? FB : 0) : 0;
+  const int lr0 = UN ? ((j0 - 1 + FB) >> A.fbs << A.fbs) - (((j0 - 1) & (FB - 1)) == 0 ? FB : 0) : 0;
+  uint8_t pc[UN ? (CH * CW + NT - 1) / NT : 1];
+  if constexpr (UN) {
+#pragma unroll
+    for (int q = 0; q < (CH * CW + NT - 1) / NT; q++) {
+      const int k = min(tid + q * NT, CH * CW - 1);
+      const int i = i0 - 5 + k % CW, j = j0 - 5 + k / CW;
+      const int bi = i >> A.fbs, bj = j >> A.fbs;  // arithmetic shift: -1 outside
+      const bool in = i >= 0 && j >= 0 && bi < A.nbkx && bj < A.nbky;
+      pc[q] = A.act[in ? (size_t)bj * A.nbkx + bi : 0];
+      if (!in) pc[q] = 0;
+    }
+    if (bg >= 0 && bg < 4) {  // Ey on a block column
+      const int i = lc0 + bg * FB, j = j0 - 1 + bc;
+      if (i < i0 + kTX) {
+        const int I = min(max(i >> rsh, 0), A.cnx);
+        int jc;
+        cfb_w(j, jc);
+        jc = min(max(jc, 0), A.cny - 2);
+        bco = (size_t)jc * A.cpitch + I;
+        bco2 = bco + A.cpitch;
+        bvalid = true;
+      }
+    } else if (bg >= 4) {  // Ex on a block row
+      const int j = lr0 + (bg - 4) * FB, i = i0 - 1 + bc;
+      if (j < j0 + TY) {
+        const int J = min(max(j >> rsh, 0), A.cny);
+        int ic;
+        cfb_w(i, ic);
+        ic = min(max(ic, 0), A.cnx - 2);
+        bco = (size_t)J * A.cpitch + ic;
+        bco2 = bco + 1;
+        bvalid = true;
+      }
+    }
+  } else if (bg == 0 || bg == 1) {
     const int i = i0 - 1 + bc, j = bg == 0 ? B : T;
     if (ex_ok(i, j) && j >= j0 - 1 && j < j0 + TY) {
       const int J = j >> rsh;
@@ -217,9 +294,19 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
       bvalid = true;
     }
   }
-  const float* bp0 = (const float*)(bg >= 2 ? (uintptr_t)A.cey0 : (uintptr_t)A.cex0);
-  const float* bp1 = (const float*)(bg >= 2 ? (uintptr_t)A.cey1 : (uintptr_t)A.cex1);
+  const bool bey = UN ? (bg >= 0 && bg < 4) : bg >= 2;  // Ey (else Ex) line
+  const float* bp0 = (const float*)(bey ? (uintptr_t)A.cey0 : (uintptr_t)A.cex0);
+  const float* bp1 = (const float*)(bey ? (uintptr_t)A.cey1 : (uintptr_t)A.cex1);
   const float bo0 = bp0[bco], bo1 = bp0[bco2], bn0 = bp1[bco], bn1 = bp1[bco2];
+
+  if constexpr (UN) {
+#pragma unroll
+    for (int q = 0; q < (CH * CW + NT - 1) / NT; q++) {
+      const int k = tid + q * NT;
+      if (k < CH * CW) sC[k / CW][k % CW] = pc[q];
+    }
+    __syncthreads();
+  }
 
   // -- old E: raw, Laplacian, filtered ----------------------------------------
   // Weak fourth-order hyper-diffusion of the patch's interior E before the
@@ -264,7 +351,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
       float ex = 0.f, ey = 0.f;
       if (ex_ok(i, j)) {
         ex = rEx[cj + 2][ci + 2];
-        if (j != B && j != T) {
+        if (ex_in(i, j)) {
           const float c = qEx[b][a];
           const float l2 = lap5(c, ex_ok(i - 1, j) ? qEx[b][a - 1] : c, ex_ok(i + 1, j) ? qEx[b][a + 1] : c,
                                 ex_ok(i, j - 1) ? qEx[b - 1][a] : c, ex_ok(i, j + 1) ? qEx[b + 1][a] : c);
@@ -273,7 +360,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
       }
       if (ey_ok(i, j)) {
         ey = rEy[cj + 2][ci + 2];
-        if (i != L && i != R) {
+        if (ey_in(i, j)) {
           const float c = qEy[b][a];
           const float l2 = lap5(c, ey_ok(i - 1, j) ? qEy[b][a - 1] : c, ey_ok(i + 1, j) ? qEy[b][a + 1] : c,
                                 ey_ok(i, j - 1) ? qEy[b - 1][a] : c, ey_ok(i, j + 1) ? qEy[b + 1][a] : c);
@@ -303,8 +390,8 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
       sN[cj][ci] = nd_ok(i0 - 1 + ci, j0 - 1 + cj) ? pn[q] : 0.f;
     }
   }
-  {  // every thread writes (row 4 is a dummy), so the loads above stay put
-    sB[bg < 0 ? 4 : bg][bg < 0 ? 0 : bc] = bvalid ? cfb(bw0, bw1, bo0, bo1, bn0, bn1, A.frac) : 0.f;
+  {  // every thread writes (row NBL is a dummy), so the loads above stay put
+    sB[bg < 0 ? NBL : bg][bg < 0 ? 0 : bc] = bvalid ? cfb(bw0, bw1, bo0, bo1, bn0, bn1, A.frac) : 0.f;
   }
   __syncthreads();
 
@@ -348,9 +435,11 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
         const float ne = 0.5f * (sN[cj][ci] + sN[cj][ci + 1]);
         const float kap = A.kn * ne;
         const float jo = pjx[q];
-        if (j != B && j != T) {
+        if (ex_in(i, j)) {
           const float dh = sH[cj + 1][ci + 1] - sH[cj][ci + 1];
           exn = ampere(e, kap, A.S * dh, A.c1, jo);
+        } else if constexpr (UN) {
+          exn = sB[4 + ((j - lr0) >> A.fbs)][ci];
         } else {
           exn = sB[j == B ? 0 : 1][ci];
         }
@@ -366,9 +455,11 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
         const float ne = 0.5f * (sN[cj][ci] + sN[cj + 1][ci]);
         const float kap = A.kn * ne;
         const float jo = pjy[q];
-        if (i != L && i != R) {
+        if (ey_in(i, j)) {
           const float dh = sH[cj + 1][ci + 1] - sH[cj + 1][ci];
           eyn = ampere(e, kap, -A.S * dh, A.c1, jo);
+        } else if constexpr (UN) {
+          eyn = sB[(i - lc0) >> A.fbs][cj];
         } else {
           eyn = sB[i == L ? 2 : 3][cj];
         }
@@ -394,10 +485,13 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
     const int ci = tx + 1, cj = r + 1;
     float sx = 0.f, sy = 0.f;
     int cx = 0, cy = 0;
-    if (i > L) { const float v = sExn[cj][ci - 1]; sx += v * v; cx++; }
-    if (i < R) { const float v = sExn[cj][ci]; sx += v * v; cx++; }
-    if (j > B) { const float v = sEyn[cj - 1][ci]; sy += v * v; cy++; }
-    if (j < T) { const float v = sEyn[cj][ci]; sy += v * v; cy++; }
+    // the node's own edges (rectangle: i > L is Ex(i-1, j) belonging, ...)
+    const bool xl = UN ? ex_ok(i - 1, j) : i > L, xr = UN ? ex_ok(i, j) : i < R;
+    const bool yd = UN ? ey_ok(i, j - 1) : j > B, yu = UN ? ey_ok(i, j) : j < T;
+    if (xl) { const float v = sExn[cj][ci - 1]; sx += v * v; cx++; }
+    if (xr) { const float v = sExn[cj][ci]; sx += v * v; cx++; }
+    if (yd) { const float v = sEyn[cj - 1][ci]; sy += v * v; cy++; }
+    if (yu) { const float v = sEyn[cj][ci]; sy += v * v; cy++; }
     const float e2 = win_e2(sx, cx, sy, cy);
     const size_t o = (size_t)j * pitch + i;
     A.acc[o] = pacc[q] + e2;
@@ -420,11 +514,11 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
           }
         A.chz[co] = 0.25f * s;
       }
-      if (ex_ok(i, j) && j > B && j < T) {
+      if (ex_ok(i, j) && ex_in(i, j)) {
         A.cex[co] = 0.5f * (sExn[cj][ci] + sExn[cj][ci + 1]);
         A.cjx[co] = sJx[r][tx] + sJx[r][tx + 1];  // J~ scales with dt
       }
-      if (ey_ok(i, j) && i > L && i < R) {
+      if (ey_ok(i, j) && ey_in(i, j)) {
         A.cey[co] = 0.5f * (sEyn[cj][ci] + sEyn[cj + 1][ci]);
         A.cjy[co] = sJy[r][tx] + sJy[r + 1][tx];
       }
@@ -466,6 +560,57 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
 template <int TY, int NT>
 __global__ __launch_bounds__(NT) void k_fine(EMArgs A) {
   fine_tile<TY, NT>(A, blockIdx.x, blockIdx.y);
+}
+
+// Fine -> coarse transfer of a union-of-blocks level after its last substep
+// (r = 2), the arithmetic of fine_tile's transfer in its own launch: on a
+// non-convex level the Eq. (5b) values of the last substep read coarse edges
+// beside the boundary that the transfer overwrites, so they must all be read
+// first.  A: the final fine state (hz1, ex1, ...) and the coarse targets;
+// hz_half: the fine Hz entering the last substep.
+template <int TY>
+__global__ __launch_bounds__(kThreads) void k_restrict_union(EMArgs A, const float* __restrict__ hz_half,
+                                                             const int2* __restrict__ tiles) {
+  const int2 t = tiles[blockIdx.x];
+  const int i = t.x * kTX + (int)(threadIdx.x % kTX);
+  const int pitch = A.pitch;
+  auto act = [&](int a, int b) {
+    if (a < 0 || b < 0) return false;
+    const int bi = a >> A.fbs, bj = b >> A.fbs;
+    return bi < A.nbkx && bj < A.nbky && A.act[(size_t)bj * A.nbkx + bi] != 0;
+  };
+  for (int rr = threadIdx.x / kTX; rr < TY; rr += kThreads / kTX) {
+    const int j = t.y * TY + rr;
+    if (((i | j) & 1) || i >= A.R || j >= A.T) continue;
+    const size_t o = (size_t)j * pitch + i;
+    const size_t co = (size_t)(j >> 1) * A.cpitch + (i >> 1);
+    const bool c11 = act(i, j);
+    if (c11) {
+      float s = 0.f;
+      for (int da = 0; da < 2; da++)
+        for (int db = 0; db < 2; db++) {
+          const size_t q = o + (size_t)db * pitch + da;
+          const float hold = hz_half[q];
+          s += 0.5f * (hold + A.hz1[q]);
+        }
+      A.chz[co] = 0.25f * s;
+    }
+    if (c11 && act(i, j - 1)) {
+      A.cex[co] = 0.5f * (A.ex1[o] + A.ex1[o + 1]);
+      A.cjx[co] = A.jx1[o] + A.jx1[o + 1];
+    }
+    if (c11 && act(i - 1, j)) {
+      A.cey[co] = 0.5f * (A.ey1[o] + A.ey1[o + pitch]);
+      A.cjy[co] = A.jy1[o] + A.jy1[o + pitch];
+    }
+  }
+}
+
+// the fine level as a union of blocks: one listed tile per block
+template <int TY, int NT>
+__global__ __launch_bounds__(NT) void k_fine_union(EMArgs A, const int2* __restrict__ tiles) {
+  const int2 t = tiles[blockIdx.x];
+  fine_tile<TY, NT, true>(A, t.x, t.y);
 }
 
 // Eq. (5b) source of thread tid for one substep's new-E region (origin orig
@@ -1061,6 +1206,35 @@ __device__ inline float d_eff(const ContArgs &A, float n) {
   return (al * A.Da + A.De) / (1.f + al);
 }
 
+// the new density of one updated node from its old value, the neighbours
+// that exist (zero-flux faces elsewhere) and E_rms^2
+__device__ __forceinline__ float cont_update(const ContArgs& A, size_t o, float e2, bool l,
+                                             bool r, bool d, bool u) {
+  const int pitch = A.pitch;
+  const float ni = A.n0[o];
+  const float di = d_eff(A, ni);
+  float flux = 0.f;
+  if (l) { const float v = A.n0[o - 1]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
+  if (r) { const float v = A.n0[o + 1]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
+  if (d) { const float v = A.n0[o - pitch]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
+  if (u) { const float v = A.n0[o + pitch]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
+  float nn;
+  if (!A.town && A.rei == 0.f) {
+    const float nu = A.nuA * (powf(e2 * A.eeff_p2, A.half_beta) - A.att);
+    nn = ni + A.dtn * (flux * A.inv_dx2 + nu * ni);
+  } else {  // Townsend ionisation and / or recombination
+    float nu;
+    if (A.town) {
+      const float y = sqrtf(e2 * A.eeff_p2);  // E_eff / (100 p), V/(cm Torr)
+      nu = (y > 0.f ? A.tK * y * expf(-A.tB / y) : 0.f) - A.tatt;
+    } else {
+      nu = A.nuA * (powf(e2 * A.eeff_p2, A.half_beta) - A.att);
+    }
+    nn = ni + A.dtn * (flux * A.inv_dx2 + (nu - A.rei * ni) * ni);
+  }
+  return nn > 0.f ? nn : 0.f;
+}
+
 template <bool FINE>
 __device__ __forceinline__ void cont_body(const ContArgs& A, int bx, int by, int slot,
                                           int update) {
@@ -1094,27 +1268,7 @@ __device__ __forceinline__ void cont_body(const ContArgs& A, int bx, int by, int
     else if (i & 1) nn = 0.5f * (A.cn1[(size_t)b * cp + a] + A.cn1[(size_t)b * cp + a + 1]);
     else nn = 0.5f * (A.cn1[(size_t)b * cp + a] + A.cn1[(size_t)(b + 1) * cp + a]);
   } else {
-    const float ni = A.n0[o];
-    const float di = d_eff(A, ni);
-    float flux = 0.f;
-    if (i > A.L) { const float v = A.n0[o - 1]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
-    if (i < A.R) { const float v = A.n0[o + 1]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
-    if (j > A.B) { const float v = A.n0[o - pitch]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
-    if (j < A.T) { const float v = A.n0[o + pitch]; flux += 0.5f * (di + d_eff(A, v)) * (v - ni); }
-    if (!A.town && A.rei == 0.f) {
-      const float nu = A.nuA * (powf(e2 * A.eeff_p2, A.half_beta) - A.att);
-      nn = ni + A.dtn * (flux * A.inv_dx2 + nu * ni);
-    } else {  // Townsend ionisation and / or recombination
-      float nu;
-      if (A.town) {
-        const float y = sqrtf(e2 * A.eeff_p2);  // E_eff / (100 p), V/(cm Torr)
-        nu = (y > 0.f ? A.tK * y * expf(-A.tB / y) : 0.f) - A.tatt;
-      } else {
-        nu = A.nuA * (powf(e2 * A.eeff_p2, A.half_beta) - A.att);
-      }
-      nn = ni + A.dtn * (flux * A.inv_dx2 + (nu - A.rei * ni) * ni);
-    }
-    nn = nn > 0.f ? nn : 0.f;
+    nn = cont_update(A, o, e2, i > A.L, i < A.R, j > A.B, j < A.T);
     const int rm = A.rf == 4 ? 3 : 1, rs = A.rf == 4 ? 2 : 1;
     if (FINE && (((i - A.L) | (j - A.B)) & rm) == 0) {
       const int a = i >> rs, b = j >> rs;  // strictly inside: coincident node
@@ -1137,6 +1291,58 @@ __global__ __launch_bounds__(kThreads) void k_cont_batch(const ContArgs* __restr
   const int2 bi = blk[blockIdx.x];
   const ContArgs& A = args[bi.x];
   cont_body<FINE>(A, bi.y % A.nbx, bi.y / A.nbx, slot, update);
+}
+
+// cell (i, j) of a fine level made of the active blocks of act
+__device__ inline bool cell_active(const uint8_t* act, int fbs, int nbkx, int nbky, int i,
+                                   int j) {
+  if (i < 0 || j < 0) return false;
+  const int bi = i >> fbs, bj = j >> fbs;
+  return bi < nbkx && bj < nbky && act[(size_t)bj * nbkx + bi] != 0;
+}
+
+// Continuity on the fine level made of a union of blocks, over the listed
+// 64 x TY node tiles: as for the patch, nodes with all four cells active are
+// updated, the other nodes of the level (on the coarse/fine boundary) take
+// the new coarse density, and coarse nodes whose four cells are active take
+// the fine density at the coincident node (injection).  r = 2.
+template <int TY>
+__global__ __launch_bounds__(kThreads) void k_cont_union(ContArgs A,
+                                                         const int2* __restrict__ tiles) {
+  const int2 t = tiles[blockIdx.x];
+  const int i = t.x * kTX + (int)(threadIdx.x % kTX);
+  for (int rr = threadIdx.x / kTX; rr < TY; rr += kThreads / kTX) {
+    const int j = t.y * TY + rr;
+    if (i > A.R || j > A.T) continue;
+    const bool c00 = cell_active(A.act, A.fbs, A.nbkx, A.nbky, i - 1, j - 1);
+    const bool c10 = cell_active(A.act, A.fbs, A.nbkx, A.nbky, i, j - 1);
+    const bool c01 = cell_active(A.act, A.fbs, A.nbkx, A.nbky, i - 1, j);
+    const bool c11 = cell_active(A.act, A.fbs, A.nbkx, A.nbky, i, j);
+    if (!(c00 || c10 || c01 || c11)) continue;
+    const size_t o = (size_t)j * A.pitch + i;
+    const float sv = A.acc[o] * A.inv_spp;
+    A.ring[(size_t)A.slot * A.plane + o] = sv;
+    A.acc[o] = 0.f;
+    if (!A.update) {
+      if (!isfinite(sv)) A.err[threadIdx.x & 63] = 1;
+      continue;
+    }
+    float e2 = 0.f;
+    for (int s = 0; s < kRing; s++)
+      e2 += (s == A.slot) ? sv : A.ring[(size_t)s * A.plane + o];
+    float nn;
+    if (!(c00 && c10 && c01 && c11)) {
+      const int a = i >> 1, b = j >> 1, cp = A.cpitch;
+      if (((i | j) & 1) == 0) nn = A.cn1[(size_t)b * cp + a];
+      else if (i & 1) nn = 0.5f * (A.cn1[(size_t)b * cp + a] + A.cn1[(size_t)b * cp + a + 1]);
+      else nn = 0.5f * (A.cn1[(size_t)b * cp + a] + A.cn1[(size_t)(b + 1) * cp + a]);
+    } else {
+      nn = cont_update(A, o, e2, true, true, true, true);
+      if (((i | j) & 1) == 0) A.cn1[(size_t)(j >> 1) * A.cpitch + (i >> 1)] = nn;
+    }
+    A.n1[o] = nn;
+    if (!isfinite(nn) || !isfinite(e2)) A.err[threadIdx.x & 63] = 1;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1324,6 +1530,45 @@ __global__ __launch_bounds__(kThreads) void k_prolong(ProlongArgs A) {
     for (int s = 0; s < kRing; s++)
       A.ring[(size_t)s * A.plane + o] =
           bilin4(A.cring + (size_t)s * A.cplane, cp, 2 * i, 2 * j, D);
+  }
+}
+
+// Prolongation into the blocks new to a union-of-blocks fine level (r = 2),
+// over the listed 64 x TY tiles: every entity that belongs to the level now
+// (act) and did not before (act_old) takes the Eq. (5a) values of k_prolong.
+template <int TY>
+__global__ __launch_bounds__(kThreads) void k_prolong_union(ProlongArgs A,
+                                                            const int2* __restrict__ tiles) {
+  const int2 t = tiles[blockIdx.x];
+  const int i = t.x * kTX + (int)(threadIdx.x % kTX);
+  const int cp = A.cpitch;
+  auto now = [&](int a, int b) { return cell_active(A.act, A.fbs, A.nbkx, A.nbky, a, b); };
+  auto was = [&](int a, int b) { return cell_active(A.act_old, A.fbs, A.nbkx, A.nbky, a, b); };
+  for (int rr = threadIdx.x / kTX; rr < TY; rr += kThreads / kTX) {
+    const int j = t.y * TY + rr;
+    if (i > A.R || j > A.T) continue;
+    const size_t o = (size_t)j * A.pitch + i;
+    const bool n11 = now(i, j), n01 = now(i - 1, j), n10 = now(i, j - 1), n00 = now(i - 1, j - 1);
+    const bool w11 = was(i, j), w01 = was(i - 1, j), w10 = was(i, j - 1), w00 = was(i - 1, j - 1);
+    if (n11 && !w11) {
+      const float hp = bilin4(A.chz_prev, cp, 2 * i - 1, 2 * j - 1);
+      const float hn = bilin4(A.chz, cp, 2 * i - 1, 2 * j - 1);
+      A.hz[o] = (1.f - 1.25f) * hp + 1.25f * hn;
+    }
+    if ((n11 || n10) && !(w11 || w10)) {
+      A.ex[o] = bilin4(A.cex, cp, 2 * i - 1, 2 * j);
+      A.jx[o] = 0.5f * bilin4(A.cjx, cp, 2 * i - 1, 2 * j);
+    }
+    if ((n11 || n01) && !(w11 || w01)) {
+      A.ey[o] = bilin4(A.cey, cp, 2 * i, 2 * j - 1);
+      A.jy[o] = 0.5f * bilin4(A.cjy, cp, 2 * i, 2 * j - 1);
+    }
+    if ((n11 || n01 || n10 || n00) && !(w11 || w01 || w10 || w00)) {
+      A.n[o] = A.keep_n ? A.seed[o] : bilin4(A.cn, cp, 2 * i, 2 * j);
+      A.acc[o] = bilin4(A.cacc, cp, 2 * i, 2 * j);
+      for (int s = 0; s < kRing; s++)
+        A.ring[(size_t)s * A.plane + o] = bilin4(A.cring + (size_t)s * A.cplane, cp, 2 * i, 2 * j);
+    }
   }
 }
 
@@ -1637,6 +1882,55 @@ hipError_t launch_em(const EMArgs& A, bool fine, int ty, int nt, hipStream_t st)
   case 4: DMR_LAUNCH_TILE(k_fine, 4, nt, A, st); break;
   case 8: DMR_LAUNCH_TILE(k_fine, 8, nt, A, st); break;
   default: DMR_LAUNCH_TILE(k_fine, 16, nt, A, st); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_em_union(const EMArgs& A, const int2* tiles, int ntiles, int ty, int nt,
+                           hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  const dim3 g(ntiles);
+#define DMR_UNION_TILE(TY_)                                                                   \
+  if (nt >= 1024) hipLaunchKernelGGL((k_fine_union<TY_, 1024>), g, dim3(1024), 0, st, A, tiles); \
+  else hipLaunchKernelGGL((k_fine_union<TY_, 256>), g, dim3(256), 0, st, A, tiles)
+  switch (ty) {
+  case 4: DMR_UNION_TILE(4); break;
+  case 8: DMR_UNION_TILE(8); break;
+  default: DMR_UNION_TILE(16); break;
+  }
+#undef DMR_UNION_TILE
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_union(const EMArgs& A, const float* hz_half, const int2* tiles,
+                                 int ntiles, int ty, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  switch (ty) {
+  case 4: hipLaunchKernelGGL(k_restrict_union<4>, dim3(ntiles), dim3(kThreads), 0, st, A, hz_half, tiles); break;
+  case 8: hipLaunchKernelGGL(k_restrict_union<8>, dim3(ntiles), dim3(kThreads), 0, st, A, hz_half, tiles); break;
+  default: hipLaunchKernelGGL(k_restrict_union<16>, dim3(ntiles), dim3(kThreads), 0, st, A, hz_half, tiles); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cont_union(const ContArgs& A, const int2* tiles, int ntiles, int ty,
+                             hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  switch (ty) {
+  case 4: hipLaunchKernelGGL(k_cont_union<4>, dim3(ntiles), dim3(kThreads), 0, st, A, tiles); break;
+  case 8: hipLaunchKernelGGL(k_cont_union<8>, dim3(ntiles), dim3(kThreads), 0, st, A, tiles); break;
+  default: hipLaunchKernelGGL(k_cont_union<16>, dim3(ntiles), dim3(kThreads), 0, st, A, tiles); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong_union(const ProlongArgs& A, const int2* tiles, int ntiles, int ty,
+                                hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  switch (ty) {
+  case 4: hipLaunchKernelGGL(k_prolong_union<4>, dim3(ntiles), dim3(kThreads), 0, st, A, tiles); break;
+  case 8: hipLaunchKernelGGL(k_prolong_union<8>, dim3(ntiles), dim3(kThreads), 0, st, A, tiles); break;
+  default: hipLaunchKernelGGL(k_prolong_union<16>, dim3(ntiles), dim3(kThreads), 0, st, A, tiles); break;
   }
   return hipGetLastError();
 }
