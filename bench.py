@@ -51,7 +51,24 @@ def parse():
     ap.add_argument("--only-config1", action="store_true",
                     help="profiling aid: run only 256 steps of DMR config 1 and a "
                          "256 MiB device copy (counter calibration), no JSON")
+    ap.add_argument("--only-config2-union", action="store_true",
+                    help="profiling aid: run only 256 coarse steps of config 2 with the "
+                         "union-of-blocks fine level, no JSON")
     return ap.parse_args()
+
+
+def only_config2_union(steps=256):
+    """Profiling aid: config 2 (8 seeds, 4096x2048) with the fine level made
+    of the flagged blocks, one regrid interval from t = 0."""
+    from paper_2105_13276_amd import binding as B
+    from paper_2105_13276_amd import workloads as W
+    cfg = dict(W.config2(periods=4), regrid_rule="union")
+    centres, peaks = W.config2_seed_layout(cfg)
+    sim = B.Sim(cfg, *W.seeds(cfg, centres, peaks))
+    sim.step(steps)
+    sim.sync()
+    print("only-config2-union: %d steps, %d active blocks" % (steps, sim.blocks().sum()),
+          flush=True)
 
 
 def only_large(steps=48):
@@ -140,9 +157,12 @@ def run_case(B, cfg, seeds, chunks, chunk, warmup, timing):
     work = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    union = cfg["mode"] != "uniform" and cfg.get("regrid_rule") == "union"
     for _ in range(chunks):
         e = sim.patch() if cfg["mode"] != "uniform" else (0, 0, 0, 0)
         fine_cells = r * r * (e[2] - e[0]) * (e[3] - e[1])
+        if union:  # the active blocks, not their bounding box
+            fine_cells = r * r * int(sim.blocks().sum()) * cfg["block"] ** 2
         work += chunk * (base_cells + r * fine_cells)  # r fine steps per base step
         sim.step(chunk)
     torch.cuda.synchronize()
@@ -207,6 +227,9 @@ def main():
         return
     if args.only_config1:
         only_config1()
+        return
+    if args.only_config2_union:
+        only_config2_union()
         return
     import numpy as np
     import torch
@@ -372,6 +395,19 @@ def main():
         s2u, w2u, k2u = run_case(B, cfg_2u, sd_2u, 1, 2 * INTERVAL, 0, False)
         s2u.close()
         area = (ext2[2] - ext2[0]) * (ext2[3] - ext2[1]) / float(cfg_2["nx"] * cfg_2["ny"])
+        # the same run with the fine level made of the flagged blocks themselves
+        cfg_2n = dict(cfg_2, regrid_rule="union")
+        s2n, w2n, k2n = run_case(B, cfg_2n, sd_2, 1, INTERVAL, 0, False)
+        blk2 = s2n.blocks()
+        s2n.close()
+        area_n = float(blk2.sum()) / blk2.size
+        out["config2_union_vs_uniform"] = {
+            "workload": "config 2 as below with the fine level = the union of the flagged "
+                        "16x16 blocks (not their bounding box), 4 periods from t = 0",
+            "active_blocks": int(blk2.sum()), "fine_area_fraction": area_n,
+            "dmr_s": w2n, "uniform_fine_s": w2u, "speedup": w2u / w2n,
+            "speedup_bound": 1.0 / (1.0 / 8.0 + area_n),
+            "dmr_mcell_updates_per_s": k2n / w2n / 1e6}
         out["config2_dmr_vs_uniform"] = {
             "workload": "coarse 4096x2048 @ lambda/32 + r=2 patch (bounding box of 8 "
                         "seeds in the right third, E_rms/E_bd = 1.5) vs uniform-fine "

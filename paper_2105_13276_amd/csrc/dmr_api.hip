@@ -57,7 +57,7 @@ struct Layout {
   int NB = 0;
   // union-of-blocks fine level: two block maps, two tile lists (64 x 4 tiles
   // at most over the fine domain)
-  size_t off_act = 0, off_tiles = 0;
+  size_t off_act = 0, off_tiles = 0, off_cfb = 0;
   size_t max_tiles = 0;
 };
 
@@ -88,6 +88,7 @@ Layout layout_of(const dmr_params* p) {
     L.max_tiles = (size_t)((p->r * p->nx + 1 + kTX - 1) / kTX) * ((p->r * p->ny + 1 + 3) / 4);
     L.off_act = off;   off += 2 * align256(nb);
     L.off_tiles = off; off += 2 * align256(L.max_tiles * sizeof(int2));
+    L.off_cfb = off;   off += align256(L.max_tiles * kCfbStride * sizeof(float));
   }
   L.total = off;
   return L;
@@ -232,8 +233,10 @@ struct dmr_sim {
   int acur = 0;
   std::vector<uint8_t> h_act, h_act_new, h_flag;
   int2 *d_tiles = nullptr, *d_ptiles = nullptr;
+  float* d_cfb = nullptr;  // Eq. (5b) values from substep 1 to substep 2, per tile
   std::vector<int2> h_tiles, h_ptiles;
-  int ntiles = 0, tyu = 16;
+  int ntiles = 0, tyu = 4;
+  bool tyu_env = false;  // tile rows fixed by DMR_UTY
   AdjTape tape;
   hipStream_t rep_st = nullptr;  // the adjoint's replay stream (default priority)
   hipEvent_t ev_rep[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr}, ev_sync = nullptr;
@@ -539,6 +542,15 @@ int grow_union(dmr_sim* s, const uint8_t* add, bool keep_n, bool strict) {
     if (!s->h_act_new[b]) { s->h_act_new[b] = 1; changed = true; }
   }
   if (!changed) return DMR_OK;
+  // tile rows: short tiles (more of them, shorter per-tile chains) while the
+  // level is small (measured on config 2: 33.1 ms with 4 rows against 36.0
+  // ms with 16 for 256 coarse steps), the tile_rows rule once it is large
+  if (!s->tyu_env) {
+    long act = 0;
+    for (uint8_t v : s->h_act_new) act += v;
+    const long cells = act * (long)(p.r * p.block) * (p.r * p.block);
+    s->tyu = cells / (kTX * 16) >= 2048 ? 16 : cells / (kTX * 8) >= 1024 ? 8 : 4;
+  }
   const std::vector<uint8_t>& nw = s->h_act_new;
   const std::vector<uint8_t>& od = s->h_act;
   union_tiles(s, s->tyu, [&](int b) { return nw[b] && !od[b]; }, &s->h_ptiles);
@@ -908,12 +920,9 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
       make_fine_em(s, m, c, s->ncur, s->ty1, &G);
       ev_begin(s, 1);
       if (s->uni) {
-        // the transfer runs after the substep (see launch_restrict_union)
-        const bool last = G.restrict_on != 0;
-        G.restrict_on = 0;
+        if (m == 1) G.cfb_next = s->d_cfb;
+        if (m == p.r) G.cfb_prev = s->d_cfb;
         e = launch_em_union(G, s->d_tiles, s->ntiles, s->tyu, s->nt1, s->st);
-        if (e == hipSuccess && last)
-          e = launch_restrict_union(G, G.hz0, s->d_tiles, s->ntiles, s->tyu, s->st);
       } else {
         e = launch_em(G, true, s->ty1, s->nt1, s->st);
       }
@@ -1097,10 +1106,11 @@ int dmr_create(const dmr_params* p, const double* seed_base,
     s->d_act[1] = s->d_act[0] + align256(nb);
     s->d_tiles = (int2*)(s->ws + lay.off_tiles);
     s->d_ptiles = s->d_tiles + align256(lay.max_tiles * sizeof(int2)) / sizeof(int2);
+    s->d_cfb = (float*)(s->ws + lay.off_cfb);
     s->h_act.assign(nb, 0);
     if (const char* f = getenv("DMR_UTY")) {
       const int v = atoi(f);
-      if (v == 4 || v == 8 || v == 16) s->tyu = v;
+      if (v == 4 || v == 8 || v == 16) { s->tyu = v; s->tyu_env = true; }
     }
   }
   s->seg0 = stream_rows(p->nx, p->ny);

@@ -10,6 +10,9 @@ constexpr int kTX = 64;        // tile width in nodes: one wavefront per row
 constexpr int kThreads = 256;  // threads per tile
 constexpr int kFineThreads = 1024;  // threads per patch tile (phases run from LDS)
 constexpr int kRing = 8;       // window blocks per period
+// union-of-blocks level: Eq. (5b) values one tile hands from substep 1 to the
+// last substep (4 block columns x (16+1) rows + 2 block rows x (kTX+1))
+constexpr int kCfbStride = 4 * 17 + 2 * (kTX + 1);
 constexpr int kBcMur = 0;
 constexpr int kSrcSteps = 256;  // incident-value table length of the batched form
 
@@ -65,6 +68,11 @@ struct EMArgs {
   // domain; the tiles come from a list
   const uint8_t* act;
   int fbs, nbkx, nbky;
+  // union, r = 2: substep 1 writes the Eq. (5b) values of the last substep
+  // (frac = 1) per listed tile (cfb_next), which reads them back (cfb_prev)
+  // instead of the coarse E its own fine -> coarse transfer rewrites
+  float* cfb_next;
+  const float* cfb_prev;
 };
 
 struct ContArgs {
@@ -134,11 +142,6 @@ hipError_t launch_em(const EMArgs& A, bool fine, int ty, int nt, hipStream_t st)
 // tile row) listed in tiles[ntiles]
 hipError_t launch_em_union(const EMArgs& A, const int2* tiles, int ntiles, int ty, int nt,
                            hipStream_t st);
-// fine -> coarse transfer of the union of blocks after the last substep
-// (A.restrict_on off in that substep): A holds the final fine state in
-// hz1.. and the coarse targets; hz_half the Hz entering the last substep
-hipError_t launch_restrict_union(const EMArgs& A, const float* hz_half, const int2* tiles,
-                                 int ntiles, int ty, hipStream_t st);
 // continuity on the fine union of blocks over the same tile list (64 x ty)
 hipError_t launch_cont_union(const ContArgs& A, const int2* tiles, int ntiles, int ty,
                              hipStream_t st);

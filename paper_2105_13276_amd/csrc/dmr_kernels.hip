@@ -297,7 +297,16 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   const bool bey = UN ? (bg >= 0 && bg < 4) : bg >= 2;  // Ey (else Ex) line
   const float* bp0 = (const float*)(bey ? (uintptr_t)A.cey0 : (uintptr_t)A.cex0);
   const float* bp1 = (const float*)(bey ? (uintptr_t)A.cey1 : (uintptr_t)A.cex1);
+  // union, last substep: the Eq. (5b) values come from substep 1 (cfb_prev),
+  // because the in-tile fine -> coarse transfer of this launch overwrites
+  // coarse edges next to the boundary at concave corners
+  const bool from_prev = UN && A.cfb_prev != nullptr;
+  if (from_prev) bco = bco2 = 0;
   const float bo0 = bp0[bco], bo1 = bp0[bco2], bn0 = bp1[bco], bn1 = bp1[bco2];
+  float bpre = 0.f;
+  if constexpr (UN) {
+    if (from_prev && bg >= 0) bpre = A.cfb_prev[(size_t)blockIdx.x * kCfbStride + tid];
+  }
 
   if constexpr (UN) {
 #pragma unroll
@@ -391,7 +400,13 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
     }
   }
   {  // every thread writes (row NBL is a dummy), so the loads above stay put
-    sB[bg < 0 ? NBL : bg][bg < 0 ? 0 : bc] = bvalid ? cfb(bw0, bw1, bo0, bo1, bn0, bn1, A.frac) : 0.f;
+    sB[bg < 0 ? NBL : bg][bg < 0 ? 0 : bc] =
+        from_prev ? bpre : (bvalid ? cfb(bw0, bw1, bo0, bo1, bn0, bn1, A.frac) : 0.f);
+    if constexpr (UN) {  // substep 1 hands the last substep its values (frac = 1)
+      if (A.cfb_next && bg >= 0)
+        A.cfb_next[(size_t)blockIdx.x * kCfbStride + tid] =
+            bvalid ? cfb(bw0, bw1, bo0, bo1, bn0, bn1, 1.f) : 0.f;
+    }
   }
   __syncthreads();
 
@@ -560,50 +575,6 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
 template <int TY, int NT>
 __global__ __launch_bounds__(NT) void k_fine(EMArgs A) {
   fine_tile<TY, NT>(A, blockIdx.x, blockIdx.y);
-}
-
-// Fine -> coarse transfer of a union-of-blocks level after its last substep
-// (r = 2), the arithmetic of fine_tile's transfer in its own launch: on a
-// non-convex level the Eq. (5b) values of the last substep read coarse edges
-// beside the boundary that the transfer overwrites, so they must all be read
-// first.  A: the final fine state (hz1, ex1, ...) and the coarse targets;
-// hz_half: the fine Hz entering the last substep.
-template <int TY>
-__global__ __launch_bounds__(kThreads) void k_restrict_union(EMArgs A, const float* __restrict__ hz_half,
-                                                             const int2* __restrict__ tiles) {
-  const int2 t = tiles[blockIdx.x];
-  const int i = t.x * kTX + (int)(threadIdx.x % kTX);
-  const int pitch = A.pitch;
-  auto act = [&](int a, int b) {
-    if (a < 0 || b < 0) return false;
-    const int bi = a >> A.fbs, bj = b >> A.fbs;
-    return bi < A.nbkx && bj < A.nbky && A.act[(size_t)bj * A.nbkx + bi] != 0;
-  };
-  for (int rr = threadIdx.x / kTX; rr < TY; rr += kThreads / kTX) {
-    const int j = t.y * TY + rr;
-    if (((i | j) & 1) || i >= A.R || j >= A.T) continue;
-    const size_t o = (size_t)j * pitch + i;
-    const size_t co = (size_t)(j >> 1) * A.cpitch + (i >> 1);
-    const bool c11 = act(i, j);
-    if (c11) {
-      float s = 0.f;
-      for (int da = 0; da < 2; da++)
-        for (int db = 0; db < 2; db++) {
-          const size_t q = o + (size_t)db * pitch + da;
-          const float hold = hz_half[q];
-          s += 0.5f * (hold + A.hz1[q]);
-        }
-      A.chz[co] = 0.25f * s;
-    }
-    if (c11 && act(i, j - 1)) {
-      A.cex[co] = 0.5f * (A.ex1[o] + A.ex1[o + 1]);
-      A.cjx[co] = A.jx1[o] + A.jx1[o + 1];
-    }
-    if (c11 && act(i - 1, j)) {
-      A.cey[co] = 0.5f * (A.ey1[o] + A.ey1[o + pitch]);
-      A.cjy[co] = A.jy1[o] + A.jy1[o + pitch];
-    }
-  }
 }
 
 // the fine level as a union of blocks: one listed tile per block
@@ -1899,17 +1870,6 @@ hipError_t launch_em_union(const EMArgs& A, const int2* tiles, int ntiles, int t
   default: DMR_UNION_TILE(16); break;
   }
 #undef DMR_UNION_TILE
-  return hipGetLastError();
-}
-
-hipError_t launch_restrict_union(const EMArgs& A, const float* hz_half, const int2* tiles,
-                                 int ntiles, int ty, hipStream_t st) {
-  if (ntiles <= 0) return hipSuccess;
-  switch (ty) {
-  case 4: hipLaunchKernelGGL(k_restrict_union<4>, dim3(ntiles), dim3(kThreads), 0, st, A, hz_half, tiles); break;
-  case 8: hipLaunchKernelGGL(k_restrict_union<8>, dim3(ntiles), dim3(kThreads), 0, st, A, hz_half, tiles); break;
-  default: hipLaunchKernelGGL(k_restrict_union<16>, dim3(ntiles), dim3(kThreads), 0, st, A, hz_half, tiles); break;
-  }
   return hipGetLastError();
 }
 
