@@ -88,3 +88,28 @@ def test_adjoint_tape_sizing():
     assert n.value != big
     assert B.lib().dmr_adjoint_tape_bytes(C.byref(p), 0, 45, C.byref(n)) == -1
     assert B.lib().dmr_adjoint_tape_bytes(C.byref(p), 2000, 0, C.byref(n)) == -1
+
+
+@pytest.mark.parametrize("over", [
+    dict(r=4, block=8),                 # the union-of-blocks level is r = 2
+    dict(block=12),                     # divides 384 x 192, not a power of two
+    dict(block=4),                      # below 8
+    dict(mode="static", static_ext=(40, 64, 96, 128)),  # not whole blocks
+])
+def test_invalid_union_rejected(over):
+    cfg = dict(W.make(384, 192, 32, "dynamic", 1, regrid_rule="union"))
+    B.workspace_bytes(cfg)              # valid as it stands
+    cfg.update(over)
+    with pytest.raises(B.DmrError):
+        B.workspace_bytes(cfg)
+
+
+def test_union_workspace_holds_maps_and_tiles():
+    """The union-of-blocks level needs two block maps, two tile lists (64x4
+    tiles over the fine domain) and the per-tile Eq. (5b) hand-off on top of
+    the rectangle's workspace."""
+    cfg = W.make(512, 256, 32, "dynamic", 1)
+    rect = B.workspace_bytes(cfg)
+    uni = B.workspace_bytes(dict(cfg, regrid_rule="union"))
+    tiles = ((1024 + 1 + 63) // 64) * ((512 + 1 + 3) // 4)
+    assert uni - rect >= 2 * (32 * 16) + 2 * 8 * tiles + 4 * 198 * tiles

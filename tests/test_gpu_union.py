@@ -138,3 +138,17 @@ def test_union_errors():
     with pytest.raises(B.DmrError):
         r.blocks()
     r.close()
+
+
+def test_union_with_townsend_and_recombination():
+    """The full Eq. (4) source on the union level (same continuity update)."""
+    cfg, m = _static_l(periods=16)
+    cfg.update(erms_over_ebd=2.0, source_model="townsend", beta_rec=1.0)
+    sb, sf = W.seeds(cfg, [(56.5 * DX, 32 * DX)], [1e20])
+    g, o = both(cfg, sb, sf)
+    g.add_blocks(m)
+    o.add_blocks(m)
+    g.step(cfg["steps"])
+    o.step(cfg["steps"])
+    assert_parity(g, o, O.derived(cfg)["n_c"], tag="union townsend")
+    g.close()
