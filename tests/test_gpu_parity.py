@@ -1,6 +1,6 @@
 """GPU (float32, HIP) against the FP64 oracle on the same seeded inputs.
 
-Tolerance (stated in the benchmark spec): relative L2 <= 1e-4 per
+Tolerance: relative L2 <= 1e-4 per
 field group (E = (Ex, Ey), Hz, J = (Jx, Jy), E_rms^2) per level, <= 1e-3 on
 log(max(n, 1e-12 n_c)); integer regrid results (block flags, prefix sum,
 compacted list, patch extents) equal.
