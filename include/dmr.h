@@ -120,7 +120,7 @@ typedef struct dmr_params {
    *                    coarse/fine boundary edge).  r = 2, block a power of
    *                    two >= 8; with DMR_STATIC the fine level starts as the
    *                    blocks of static_ext (whole blocks).  Not supported by
-   *                    the adjoint, save/load and the batched form.
+   *                    the adjoint and the batched form.
    * All keep the fine level one block clear of the outer boundary and right
    * of the source line by one block, and only grow it. */
   int32_t regrid_rule;
@@ -221,7 +221,8 @@ int dmr_time(dmr_sim *s, double *t, int64_t *step);
  * a hash of the parameters, step, window block count, patch) followed by the
  * live planes: base level Hz at n+1/2 and n-1/2, Ex, Ey, Jx, Jy, n, acc, the
  * 8 window slots; patch Hz, Ex, Ey, Jx, Jy, n, acc, 8 slots over the patch
- * rows of the full-domain fine grid.
+ * rows of the full-domain fine grid; for DMR_RULE_UNION, then the block map
+ * (one byte per block, padded to 256 bytes).
  *   dmr_state_bytes  bytes of a saved state of this handle (fixed by its
  *                    parameters).
  *   dmr_save         writes the state of the handle after all queued work

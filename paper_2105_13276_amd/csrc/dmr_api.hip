@@ -522,6 +522,50 @@ void union_level_args(const dmr_sim* s, int* fbs, int* nbkx, int* nbky) {
   *nbky = s->p.ny / s->p.block;
 }
 
+// tile rows: short tiles (more of them, shorter per-tile chains) while the
+// level is small (measured on config 2: 33.1 ms with 4 rows against 36.0 ms
+// with 16 for 256 coarse steps), the tile_rows rule once it is large
+void pick_union_rows(dmr_sim* s, const std::vector<uint8_t>& map) {
+  if (s->tyu_env) return;
+  long act = 0;
+  for (uint8_t v : map) act += v;
+  const long fb = (long)s->p.r * s->p.block;
+  const long cells = act * fb * fb;
+  s->tyu = cells / (kTX * 16) >= 2048 ? 16 : cells / (kTX * 8) >= 1024 ? 8 : 4;
+}
+
+// extents (bounding box of the active blocks) and presence of the level
+void union_extents(dmr_sim* s) {
+  const dmr_params& p = s->p;
+  const int NBx = p.nx / p.block, NBy = p.ny / p.block;
+  int bx0 = NBx, by0 = NBy, bx1 = 0, by1 = 0;
+  for (int b = 0; b < NBx * NBy; b++)
+    if (s->h_act[b]) {
+      bx0 = std::min(bx0, b % NBx); by0 = std::min(by0, b / NBx);
+      bx1 = std::max(bx1, b % NBx + 1); by1 = std::max(by1, b / NBx + 1);
+    }
+  s->has_patch = bx1 > bx0;
+  if (!s->has_patch) bx0 = by0 = bx1 = by1 = 0;
+  s->ext[0] = bx0 * p.block; s->ext[1] = by0 * p.block;
+  s->ext[2] = bx1 * p.block; s->ext[3] = by1 * p.block;
+}
+
+// make h_act the level as it stands (restart): map and tile list to the
+// device, extents; no prolongation (the state carries the fine data)
+int union_install(dmr_sim* s) {
+  pick_union_rows(s, s->h_act);
+  union_tiles(s, s->tyu, [&](int b) { return s->h_act[b] != 0; }, &s->h_tiles);
+  HIPCHK(s, hipMemcpyAsync(s->d_act[s->acur], s->h_act.data(), s->h_act.size(),
+                           hipMemcpyHostToDevice, s->st));
+  if (!s->h_tiles.empty())
+    HIPCHK(s, hipMemcpyAsync(s->d_tiles, s->h_tiles.data(), s->h_tiles.size() * sizeof(int2),
+                             hipMemcpyHostToDevice, s->st));
+  s->ntiles = (int)s->h_tiles.size();
+  union_extents(s);
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  return DMR_OK;
+}
+
 // Add the blocks of add ([NBy][NBx]) to the level.  strict: a block outside
 // the margins is an error (else it is left out).
 int grow_union(dmr_sim* s, const uint8_t* add, bool keep_n, bool strict) {
@@ -542,15 +586,7 @@ int grow_union(dmr_sim* s, const uint8_t* add, bool keep_n, bool strict) {
     if (!s->h_act_new[b]) { s->h_act_new[b] = 1; changed = true; }
   }
   if (!changed) return DMR_OK;
-  // tile rows: short tiles (more of them, shorter per-tile chains) while the
-  // level is small (measured on config 2: 33.1 ms with 4 rows against 36.0
-  // ms with 16 for 256 coarse steps), the tile_rows rule once it is large
-  if (!s->tyu_env) {
-    long act = 0;
-    for (uint8_t v : s->h_act_new) act += v;
-    const long cells = act * (long)(p.r * p.block) * (p.r * p.block);
-    s->tyu = cells / (kTX * 16) >= 2048 ? 16 : cells / (kTX * 8) >= 1024 ? 8 : 4;
-  }
+  pick_union_rows(s, s->h_act_new);
   const std::vector<uint8_t>& nw = s->h_act_new;
   const std::vector<uint8_t>& od = s->h_act;
   union_tiles(s, s->tyu, [&](int b) { return nw[b] && !od[b]; }, &s->h_ptiles);
@@ -584,15 +620,7 @@ int grow_union(dmr_sim* s, const uint8_t* add, bool keep_n, bool strict) {
   s->acur = 1 - s->acur;
   s->h_act.swap(s->h_act_new);
   s->ntiles = (int)s->h_tiles.size();
-  int bx0 = NBx, by0 = NBy, bx1 = 0, by1 = 0;
-  for (int b = 0; b < NBx * NBy; b++)
-    if (s->h_act[b]) {
-      bx0 = std::min(bx0, b % NBx); by0 = std::min(by0, b / NBx);
-      bx1 = std::max(bx1, b % NBx + 1); by1 = std::max(by1, b / NBx + 1);
-    }
-  s->ext[0] = bx0 * p.block; s->ext[1] = by0 * p.block;
-  s->ext[2] = bx1 * p.block; s->ext[3] = by1 * p.block;
-  s->has_patch = true;
+  union_extents(s);
   return DMR_OK;
 }
 
@@ -1714,9 +1742,11 @@ uint64_t params_hash(const dmr_params& p) {
   return h;
 }
 
+// the union-of-blocks level appends its block map (one byte per block)
 size_t state_bytes(const dmr_sim* s) {
-  return kStateHeader + tape_layout(&s->p, 1, 1).ck_size;
+  return kStateHeader + tape_layout(&s->p, 1, 1).ck_size + (s->uni ? align256(s->h_act.size()) : 0);
 }
+size_t state_map_offset(const dmr_sim* s) { return kStateHeader + tape_layout(&s->p, 1, 1).ck_size; }
 
 // host-side copy of the live planes to / from a host buffer b (floats after
 // the header), the patch planes over the patch's rows only
@@ -1933,7 +1963,6 @@ int dmr_state_bytes(const dmr_sim* s, size_t* bytes) {
 
 int dmr_save(dmr_sim* s, void* dst, size_t bytes, int dst_on_device) {
   if (!s || !dst) return DMR_EINVAL;
-  if (s->uni) return fail(s, DMR_EINVAL, "save/load support the rectangular patch");
   const size_t need = state_bytes(s);
   if (bytes < need) return fail(s, DMR_ENOMEM, "state needs %zu bytes", need);
   if (dst_on_device && ((uintptr_t)dst & 255))
@@ -1946,20 +1975,23 @@ int dmr_save(dmr_sim* s, void* dst, size_t bytes, int dst_on_device) {
   for (int q = 0; q < 4; q++) h.ext[q] = s->ext[q];
   h.ty1 = s->ty1;
   float* body = (float*)((char*)dst + kStateHeader);
+  char* map = (char*)dst + state_map_offset(s);
   if (dst_on_device) {
     if (int rc = ck_copy(s, body, true)) return rc;
     HIPCHK(s, hipMemcpyAsync(dst, &h, sizeof(h), hipMemcpyHostToDevice, s->st));
+    if (s->uni)
+      HIPCHK(s, hipMemcpyAsync(map, s->h_act.data(), s->h_act.size(), hipMemcpyHostToDevice, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
   } else {
     if (int rc = state_host_copy(s, body, true)) return rc;
     memcpy(dst, &h, sizeof(h));
+    if (s->uni) memcpy(map, s->h_act.data(), s->h_act.size());
   }
   return DMR_OK;
 }
 
 int dmr_load(dmr_sim* s, const void* src, size_t bytes, int src_on_device) {
   if (!s || !src) return DMR_EINVAL;
-  if (s->uni) return fail(s, DMR_EINVAL, "save/load support the rectangular patch");
   const size_t need = state_bytes(s);
   if (bytes < need) return fail(s, DMR_ENOMEM, "state needs %zu bytes", need);
   if (src_on_device && ((uintptr_t)src & 255))
@@ -1981,12 +2013,17 @@ int dmr_load(dmr_sim* s, const void* src, size_t bytes, int src_on_device) {
   s->ty1 = h.ty1;
   s->tape.valid = false;  // a recorded run no longer describes this state
   float* body = (float*)((char*)src + kStateHeader);
+  const char* map = (const char*)src + state_map_offset(s);
   if (src_on_device) {
     if (int rc = ck_copy(s, body, false)) return rc;
+    if (s->uni)
+      HIPCHK(s, hipMemcpyAsync(s->h_act.data(), map, s->h_act.size(), hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
-    return DMR_OK;
+  } else {
+    if (int rc = state_host_copy(s, body, false)) return rc;
+    if (s->uni) memcpy(s->h_act.data(), map, s->h_act.size());
   }
-  return state_host_copy(s, body, false);
+  return s->uni ? union_install(s) : DMR_OK;
 }
 
 int dmr_weighted_sum(dmr_sim* s, int level, const float* d_w, double* out) {

@@ -92,3 +92,27 @@ def test_load_rejects_other_parameters_and_short_buffers():
     assert g.time()[1] == t[1] + 8
     g.close()
     h.close()
+
+
+def test_union_restart_equals_uninterrupted_run():
+    """The union-of-blocks level: the state carries the block map; a restart
+    before a growth rebuilds the tile list and continues bit for bit."""
+    cfg = W.make(128, 64, 32, "dynamic", 14, block=8, erms_over_ebd=3.0, regrid_rule="union")
+    cfg["regrid_every"] = 2 * cfg["steps_per_period"]
+    dx = LAM / 32
+    sb, sf = W.seeds(cfg, [(46.5 * dx, 21 * dx), (92.5 * dx, 45.5 * dx)], [3e17, 2e17])
+    g = B.Sim(cfg, sb, sf)
+    g.step(300)
+    b0 = g.blocks().copy()
+    buf = g.save()
+    g.step(500)
+    ref = _snapshot(g)
+    assert g.blocks().sum() > b0.sum(), "the continued run should grow the level"
+    h = B.Sim(cfg, np.zeros_like(sb), None)   # its own (empty) level is replaced
+    h.load(buf)
+    assert np.array_equal(h.blocks(), b0)
+    h.step(500)
+    _same(ref, _snapshot(h))
+    assert np.array_equal(h.blocks(), g.blocks())
+    g.close()
+    h.close()
