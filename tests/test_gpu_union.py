@@ -152,3 +152,42 @@ def test_union_with_townsend_and_recombination():
     o.step(cfg["steps"])
     assert_parity(g, o, O.derived(cfg)["n_c"], tag="union townsend")
     g.close()
+
+
+def test_full_size_rectangle_of_blocks_is_the_patch():
+    """Config 2 at full size (coarse 4096x2048, 8-seed layout) with the fine
+    level fixed to the seeds' bounding box: the union kernels (large level:
+    16-row tiles) give the rectangular patch's run bit for bit over 80
+    coarse steps (two continuity updates)."""
+    cfg = W.config2(periods=1)
+    centres, peaks = W.config2_seed_layout(cfg)
+    sb, sf = W.seeds(cfg, centres, peaks)
+    ext = (2896, 352, 3664, 1888)
+    cr = dict(cfg, mode="static", static_ext=ext)
+    cu = dict(cr, regrid_rule="union")
+    a = B.Sim(cr, sb, sf)
+    a.step(80)
+    ref = {(f, lv): a.get(f, lv) for lv in (0, 1) for f in FIELDS}
+    a.close()
+    b = B.Sim(cu, sb, sf)
+    assert b.patch() == ext and b.blocks().sum() == 48 * 96
+    b.step(80)
+    for (f, lv), x in ref.items():
+        assert np.array_equal(x, b.get(f, lv)), (f, lv)
+    b.close()
+
+
+def test_full_size_blocks_match_oracle():
+    """Config 2 at full size: the union's active blocks at t = 0 equal the
+    oracle's (integer decisions on the same float32 density)."""
+    cfg = dict(W.config2(periods=1), regrid_rule="union")
+    centres, peaks = W.config2_seed_layout(cfg)
+    sb, sf = W.seeds(cfg, centres, peaks)
+    g = B.Sim(cfg, sb, sf)
+    gb = g.blocks()
+    g.close()
+    o = O.Sim(cfg, sb, sf)
+    ob = o.blocks()
+    print("config 2 union: %d active blocks" % gb.sum(), flush=True)
+    assert gb.sum() > 8 and np.array_equal(gb, ob)
+    o.close()
