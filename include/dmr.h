@@ -120,7 +120,7 @@ typedef struct dmr_params {
    *                    coarse/fine boundary edge).  r = 2, block a power of
    *                    two >= 8; with DMR_STATIC the fine level starts as the
    *                    blocks of static_ext (whole blocks).  Not supported by
-   *                    the adjoint and the batched form.
+   *                    the adjoint; in a batch, every instance or none.
    * All keep the fine level one block clear of the outer boundary and right
    * of the source line by one block, and only grow it. */
   int32_t regrid_rule;

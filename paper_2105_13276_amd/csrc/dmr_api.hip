@@ -236,6 +236,7 @@ struct dmr_sim {
   float* d_cfb = nullptr;  // Eq. (5b) values from substep 1 to substep 2, per tile
   std::vector<int2> h_tiles, h_ptiles;
   int ntiles = 0, tyu = 4;
+  int64_t ugen = 0;  // growths of the level (the batch rebuilds its tables on a change)
   bool tyu_env = false;  // tile rows fixed by DMR_UTY
   AdjTape tape;
   hipStream_t rep_st = nullptr;  // the adjoint's replay stream (default priority)
@@ -620,6 +621,7 @@ int grow_union(dmr_sim* s, const uint8_t* add, bool keep_n, bool strict) {
   s->acur = 1 - s->acur;
   s->h_act.swap(s->h_act_new);
   s->ntiles = (int)s->h_tiles.size();
+  s->ugen++;
   union_extents(s);
   return DMR_OK;
 }
@@ -754,6 +756,10 @@ void make_fine_em(const dmr_sim* s, int m, int c, int nc, int ty, EMArgs* G) {
     G->act = s->d_act[s->acur];
     union_level_args(s, &G->fbs, &G->nbkx, &G->nbky);
     G->cnx = p.nx; G->cny = p.ny;
+    G->utiles = s->d_tiles;
+    // Eq. (5b) values handed from substep 1 to the last substep
+    if (m == 1) G->cfb_next = s->d_cfb;
+    if (m == r) G->cfb_prev = s->d_cfb;
   }
   (void)ty;
 }
@@ -814,6 +820,7 @@ void make_fine_cont(const dmr_sim* s, int nc, ContArgs* G) {
     G->L = 0; G->B = 0; G->R = F.NX; G->T = F.NY;
     G->act = s->d_act[s->acur];
     union_level_args(s, &G->fbs, &G->nbkx, &G->nbky);
+    G->utiles = s->d_tiles;
   }
 }
 
@@ -948,8 +955,6 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
       make_fine_em(s, m, c, s->ncur, s->ty1, &G);
       ev_begin(s, 1);
       if (s->uni) {
-        if (m == 1) G.cfb_next = s->d_cfb;
-        if (m == p.r) G.cfb_prev = s->d_cfb;
         e = launch_em_union(G, s->d_tiles, s->ntiles, s->tyu, s->nt1, s->st);
       } else {
         e = launch_em(G, true, s->ty1, s->nt1, s->st);
@@ -2097,8 +2102,8 @@ int batch_layout(const dmr_params* p, int count, BatchLayout* L, std::string* wh
     int rc = check_params(&p[k], why);
     if (rc) return rc;
     if (refined(&p[k]) && p[k].r != 2) { *why = "the batched form supports r = 2"; return DMR_EINVAL; }
-    if (refined(&p[k]) && p[k].regrid_rule == DMR_RULE_UNION) {
-      *why = "the batched form supports the rectangular patch";
+    if (refined(&p[k]) && (p[k].regrid_rule == DMR_RULE_UNION) != (p[0].regrid_rule == DMR_RULE_UNION)) {
+      *why = "instances must all or none use the union-of-blocks fine level";
       return DMR_EINVAL;
     }
     const double spp0 = p[0].cells_per_lambda / p[0].courant;
@@ -2155,6 +2160,11 @@ int batch_tables(dmr_batch* b) {
     s->seg0 = b->seg;
     s->depth0 = b->depth;
     s->ty1 = b->ty;
+    if (s->uni && (s->tyu != b->ty || !s->tyu_env)) {  // the batch's tile rows
+      s->tyu = b->ty;
+      s->tyu_env = true;
+      if (int rc = union_install(s)) return bfail(b, rc, s->err.c_str());
+    }
     for (int v = 0; v < 4; v++) {
       make_base_em(s, v & 1, v >> 1, &b->h_em[v * n + k]);
       if (s->has_patch)
@@ -2170,7 +2180,12 @@ int batch_tables(dmr_batch* b) {
     const ContArgs& K = b->h_cont[k];
     const int cny = (K.T - K.B + 1 + 3) / 4;
     for (int t = 0; t < K.nbx * cny; t++) b->h_blk_cont.push_back(make_int2(k, t));
-    if (s->has_patch) {
+    if (s->has_patch && s->uni) {  // the instance's tile list
+      for (int t = 0; t < s->ntiles; t++) {
+        b->h_blk_fine.push_back(make_int2(k, t));
+        b->h_blk_fcont.push_back(make_int2(k, t));
+      }
+    } else if (s->has_patch) {
       const EMArgs& G = b->h_fem[k];
       const int fny = (G.T - G.B + 1 + b->ty - 1) / b->ty;
       for (int t = 0; t < G.nbx * fny; t++) b->h_blk_fine.push_back(make_int2(k, t));
@@ -2246,9 +2261,11 @@ int batch_launch_step(dmr_batch* b, hipEvent_t* tb, hipEvent_t* tf) {
   if (tb) (void)hipEventRecord(tb[1], b->st);
   if (e != hipSuccess) return bfail(b, DMR_EHIP, "batched base EM launch");
   if (tf) (void)hipEventRecord(tf[0], b->st);
+  const bool uni = s0->uni;
   for (int m = 1; m <= 2 && b->nblk_fine; m++) {
-    e = launch_em_batch(b->d_fem + ((m - 1) * 4 + v) * n, b->d_blk_fine, b->nblk_fine,
-                        b->ty, b->st);
+    const EMArgs* fa = b->d_fem + ((m - 1) * 4 + v) * n;
+    e = uni ? launch_em_union_batch(fa, b->d_blk_fine, b->nblk_fine, b->ty, b->st)
+            : launch_em_batch(fa, b->d_blk_fine, b->nblk_fine, b->ty, b->st);
     if (e != hipSuccess) return bfail(b, DMR_EHIP, "batched fine EM launch");
   }
   if (tf) (void)hipEventRecord(tf[1], b->st);
@@ -2257,7 +2274,10 @@ int batch_launch_step(dmr_batch* b, hipEvent_t* tb, hipEvent_t* tf) {
   if (slot >= 0) {
     e = launch_cont_batch(b->d_cont + nc * n, b->d_blk_cont, b->nblk_cont, false, slot,
                           update, b->st);
-    if (e == hipSuccess)
+    if (e == hipSuccess && uni)
+      e = launch_cont_union_batch(b->d_fcont + nc * n, b->d_blk_fcont, b->nblk_fcont, b->ty,
+                                  slot, update, b->st);
+    else if (e == hipSuccess)
       e = launch_cont_batch(b->d_fcont + nc * n, b->d_blk_fcont, b->nblk_fcont, true, slot,
                             update, b->st);
     if (e != hipSuccess) return bfail(b, DMR_EHIP, "batched continuity launch");
@@ -2270,9 +2290,10 @@ int batch_regrid(dmr_batch* b) {
   for (dmr_sim* s : b->sims) {
     int old[4] = {s->ext[0], s->ext[1], s->ext[2], s->ext[3]};
     const bool had = s->has_patch;
+    const int64_t gen = s->ugen;
     const int rc = regrid(s, false);
     if (rc) return bfail(b, rc, s->err.c_str());
-    if (s->has_patch != had || memcmp(old, s->ext, sizeof(old))) changed = true;
+    if (s->has_patch != had || memcmp(old, s->ext, sizeof(old)) || s->ugen != gen) changed = true;
   }
   return changed ? batch_tables(b) : DMR_OK;
 }

@@ -73,6 +73,7 @@ struct EMArgs {
   // instead of the coarse E its own fine -> coarse transfer rewrites
   float* cfb_next;
   const float* cfb_prev;
+  const int2* utiles;  // batched union levels: the instance's tile list
 };
 
 struct ContArgs {
@@ -104,6 +105,7 @@ struct ContArgs {
   // fine level as a union of blocks (as in EMArgs)
   const uint8_t* act;
   int fbs, nbkx, nbky;
+  const int2* utiles;  // batched union levels: the instance's tile list
 };
 
 struct FlagArgs {
@@ -145,6 +147,12 @@ hipError_t launch_em_union(const EMArgs& A, const int2* tiles, int ntiles, int t
 // continuity on the fine union of blocks over the same tile list (64 x ty)
 hipError_t launch_cont_union(const ContArgs& A, const int2* tiles, int ntiles, int ty,
                              hipStream_t st);
+// batched union levels (every instance a union): blk[b] = (instance, index in
+// the instance's tile list utiles), 64 x ty tiles for every instance
+hipError_t launch_em_union_batch(const EMArgs* args, const int2* blk, int nblk, int ty,
+                                 hipStream_t st);
+hipError_t launch_cont_union_batch(const ContArgs* args, const int2* blk, int nblk, int ty,
+                                   int slot, int update, hipStream_t st);
 // prolongation into the blocks new to the union, over the listed 64 x ty tiles
 hipError_t launch_prolong_union(const ProlongArgs& A, const int2* tiles, int ntiles, int ty,
                                 hipStream_t st);

@@ -84,8 +84,10 @@ __device__ inline float win_e2(float sx, int cx, float sy, int cy) {
 // (registers), so the block waits for memory once; the phases after that
 // run from LDS and registers.
 // ---------------------------------------------------------------------------
+// tix: the tile's index in the union's tile list (its slot of the Eq. (5b)
+// hand-off between the substeps); unused for the rectangle
 template <int TY, int NT, bool UN = false>
-__device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
+__device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int tix = 0) {
   constexpr int EW = kTX + 3, EH = TY + 3;  // old E (filtered)
   constexpr int HW = kTX + 2, HH = TY + 2;  // new Hz
   constexpr int NW = kTX + 1, NH = TY + 1;  // new E
@@ -305,7 +307,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
   const float bo0 = bp0[bco], bo1 = bp0[bco2], bn0 = bp1[bco], bn1 = bp1[bco2];
   float bpre = 0.f;
   if constexpr (UN) {
-    if (from_prev && bg >= 0) bpre = A.cfb_prev[(size_t)blockIdx.x * kCfbStride + tid];
+    if (from_prev && bg >= 0) bpre = A.cfb_prev[(size_t)tix * kCfbStride + tid];
   }
 
   if constexpr (UN) {
@@ -404,7 +406,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by) {
         from_prev ? bpre : (bvalid ? cfb(bw0, bw1, bo0, bo1, bn0, bn1, A.frac) : 0.f);
     if constexpr (UN) {  // substep 1 hands the last substep its values (frac = 1)
       if (A.cfb_next && bg >= 0)
-        A.cfb_next[(size_t)blockIdx.x * kCfbStride + tid] =
+        A.cfb_next[(size_t)tix * kCfbStride + tid] =
             bvalid ? cfb(bw0, bw1, bo0, bo1, bn0, bn1, 1.f) : 0.f;
     }
   }
@@ -581,7 +583,17 @@ __global__ __launch_bounds__(NT) void k_fine(EMArgs A) {
 template <int TY, int NT>
 __global__ __launch_bounds__(NT) void k_fine_union(EMArgs A, const int2* __restrict__ tiles) {
   const int2 t = tiles[blockIdx.x];
-  fine_tile<TY, NT, true>(A, t.x, t.y);
+  fine_tile<TY, NT, true>(A, t.x, t.y, blockIdx.x);
+}
+
+// batched union levels: blk[b] = (instance, index in the instance's tile list)
+template <int TY>
+__global__ __launch_bounds__(kFineThreads) void k_fine_union_batch(const EMArgs* __restrict__ args,
+                                                                   const int2* __restrict__ blk) {
+  const int2 bi = blk[blockIdx.x];
+  const EMArgs& A = args[bi.x];
+  const int2 t = A.utiles[bi.y];
+  fine_tile<TY, kFineThreads, true>(A, t.x, t.y, bi.y);
 }
 
 // Eq. (5b) source of thread tid for one substep's new-E region (origin orig
@@ -1278,9 +1290,7 @@ __device__ inline bool cell_active(const uint8_t* act, int fbs, int nbkx, int nb
 // the new coarse density, and coarse nodes whose four cells are active take
 // the fine density at the coincident node (injection).  r = 2.
 template <int TY>
-__global__ __launch_bounds__(kThreads) void k_cont_union(ContArgs A,
-                                                         const int2* __restrict__ tiles) {
-  const int2 t = tiles[blockIdx.x];
+__device__ __forceinline__ void cont_union_tile(const ContArgs& A, int2 t, int slot, int update) {
   const int i = t.x * kTX + (int)(threadIdx.x % kTX);
   for (int rr = threadIdx.x / kTX; rr < TY; rr += kThreads / kTX) {
     const int j = t.y * TY + rr;
@@ -1292,15 +1302,15 @@ __global__ __launch_bounds__(kThreads) void k_cont_union(ContArgs A,
     if (!(c00 || c10 || c01 || c11)) continue;
     const size_t o = (size_t)j * A.pitch + i;
     const float sv = A.acc[o] * A.inv_spp;
-    A.ring[(size_t)A.slot * A.plane + o] = sv;
+    A.ring[(size_t)slot * A.plane + o] = sv;
     A.acc[o] = 0.f;
-    if (!A.update) {
+    if (!update) {
       if (!isfinite(sv)) A.err[threadIdx.x & 63] = 1;
       continue;
     }
     float e2 = 0.f;
     for (int s = 0; s < kRing; s++)
-      e2 += (s == A.slot) ? sv : A.ring[(size_t)s * A.plane + o];
+      e2 += (s == slot) ? sv : A.ring[(size_t)s * A.plane + o];
     float nn;
     if (!(c00 && c10 && c01 && c11)) {
       const int a = i >> 1, b = j >> 1, cp = A.cpitch;
@@ -1314,6 +1324,21 @@ __global__ __launch_bounds__(kThreads) void k_cont_union(ContArgs A,
     A.n1[o] = nn;
     if (!isfinite(nn) || !isfinite(e2)) A.err[threadIdx.x & 63] = 1;
   }
+}
+
+template <int TY>
+__global__ __launch_bounds__(kThreads) void k_cont_union(ContArgs A,
+                                                         const int2* __restrict__ tiles) {
+  cont_union_tile<TY>(A, tiles[blockIdx.x], A.slot, A.update);
+}
+
+template <int TY>
+__global__ __launch_bounds__(kThreads) void k_cont_union_batch(const ContArgs* __restrict__ args,
+                                                               const int2* __restrict__ blk,
+                                                               int slot, int update) {
+  const int2 bi = blk[blockIdx.x];
+  const ContArgs& A = args[bi.x];
+  cont_union_tile<TY>(A, A.utiles[bi.y], slot, update);
 }
 
 // ---------------------------------------------------------------------------
@@ -1880,6 +1905,28 @@ hipError_t launch_cont_union(const ContArgs& A, const int2* tiles, int ntiles, i
   case 4: hipLaunchKernelGGL(k_cont_union<4>, dim3(ntiles), dim3(kThreads), 0, st, A, tiles); break;
   case 8: hipLaunchKernelGGL(k_cont_union<8>, dim3(ntiles), dim3(kThreads), 0, st, A, tiles); break;
   default: hipLaunchKernelGGL(k_cont_union<16>, dim3(ntiles), dim3(kThreads), 0, st, A, tiles); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_em_union_batch(const EMArgs* args, const int2* blk, int nblk, int ty,
+                                 hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  switch (ty) {
+  case 4: hipLaunchKernelGGL(k_fine_union_batch<4>, dim3(nblk), dim3(kFineThreads), 0, st, args, blk); break;
+  case 8: hipLaunchKernelGGL(k_fine_union_batch<8>, dim3(nblk), dim3(kFineThreads), 0, st, args, blk); break;
+  default: hipLaunchKernelGGL(k_fine_union_batch<16>, dim3(nblk), dim3(kFineThreads), 0, st, args, blk); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cont_union_batch(const ContArgs* args, const int2* blk, int nblk, int ty,
+                                   int slot, int update, hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  switch (ty) {
+  case 4: hipLaunchKernelGGL(k_cont_union_batch<4>, dim3(nblk), dim3(kThreads), 0, st, args, blk, slot, update); break;
+  case 8: hipLaunchKernelGGL(k_cont_union_batch<8>, dim3(nblk), dim3(kThreads), 0, st, args, blk, slot, update); break;
+  default: hipLaunchKernelGGL(k_cont_union_batch<16>, dim3(nblk), dim3(kThreads), 0, st, args, blk, slot, update); break;
   }
   return hipGetLastError();
 }

@@ -75,3 +75,53 @@ def test_batch_instance_vs_oracle():
     o.step(cfgs[k]["steps"])
     assert bt.instances[k].patch() == o.patch()
     assert_parity(bt.instances[k], o, O.derived(cfgs[k])["n_c"], tag="batch[1]")
+
+
+def _mixed_union(count=4, periods=12):
+    """Union-of-blocks instances of three sizes, two seeds each, growing."""
+    cfgs, seeds = W.config3(count, periods)
+    out_c, out_s = [], []
+    for k, c in enumerate(cfgs):
+        side = [128, 192, 256][k % 3]
+        c2 = W.make(side, side // 2, 32, "dynamic", periods, erms_over_ebd=3.0,
+                    p_torr=c["p_torr"], freq_hz=c["freq_hz"], L_amb=c["L_amb"],
+                    block=8, regrid_rule="union")
+        c2["regrid_every"] = 2 * c2["steps_per_period"]
+        dx = 299792458.0 / c2["freq_hz"] / 32
+        cen = [(0.45 * side * dx, 0.15 * side * dx), (0.75 * side * dx, 0.35 * side * dx)]
+        out_c.append(c2)
+        out_s.append(W.seeds(c2, cen, [3e17, 2e17]))
+    return out_c, out_s
+
+
+def test_union_batch_equals_plain_runs():
+    cfgs, seeds = _mixed_union()
+    steps = cfgs[0]["steps"]
+    bt = B.Batch(cfgs, seeds)
+    b0 = [bt.instances[k].blocks().sum() for k in range(len(cfgs))]
+    bt.step(steps)
+    bt.sync()
+    print("union batch config", bt.config(), "blocks", b0, "->",
+          [bt.instances[k].blocks().sum() for k in range(len(cfgs))], flush=True)
+    grew = 0
+    for k, (c, s) in enumerate(zip(cfgs, seeds)):
+        g = B.Sim(c, *s)
+        g.step(steps)
+        inst = bt.instances[k]
+        assert np.array_equal(inst.blocks(), g.blocks())
+        grew += int(inst.blocks().sum() > b0[k])
+        _same(inst, g)
+    assert grew >= 1
+
+
+def test_union_batch_launch_shape_invariance():
+    cfgs, seeds = _mixed_union(count=3, periods=8)
+    steps = cfgs[0]["steps"]
+    ref = B.Batch(cfgs, seeds)
+    ref.set_config(16, 2, 4, 0)
+    ref.step(steps)
+    bt = B.Batch(cfgs, seeds)
+    bt.set_config(32, 2, 16, 1)
+    bt.step(steps)
+    for k in range(len(cfgs)):
+        _same(bt.instances[k], ref.instances[k])
