@@ -138,6 +138,14 @@ def em_bytes_per_cell():
     return 13 * 4
 
 
+def hbm_share(mcell_per_s):
+    """Algorithmic HBM rate of a whole-step throughput: 55 B per cell-update
+    (52 B EM step + 3 B continuity amortised over 16 fine steps), against the
+    8 TB/s peak."""
+    gbs = mcell_per_s * 1e6 * (em_bytes_per_cell() + 3) / 1e9
+    return {"alg_GB_per_s": gbs, "frac_of_8TBps": gbs / 8000.0}
+
+
 def run_case(B, cfg, seeds, chunks, chunk, warmup, timing):
     """Fresh simulation at t = 0, `chunks` x `chunk` base steps timed.
     Returns the handle, the wall time and the cell-updates performed (the
@@ -212,6 +220,8 @@ def adjoint_leg(B, W, torch, steps=2000, every=45):
             "gradient_over_forward": (t_rec + t_bwd) / t_plain,
             "forward_mcell_updates_per_s": work / t_plain / 1e6,
             "gradient_mcell_updates_per_s": work / (t_rec + t_bwd) / 1e6,
+            "forward_hbm": hbm_share(work / t_plain / 1e6),
+            "gradient_hbm_forward_equivalent": hbm_share(work / (t_rec + t_bwd) / 1e6),
             "tape_GB": tape_gb,
             "dF_dE0": res["E0"], "dF_dA": res["A"], "dF_dbeta": res["beta"]}
 
@@ -407,7 +417,8 @@ def main():
             "active_blocks": int(blk2.sum()), "fine_area_fraction": area_n,
             "dmr_s": w2n, "uniform_fine_s": w2u, "speedup": w2u / w2n,
             "speedup_bound": 1.0 / (1.0 / 8.0 + area_n),
-            "dmr_mcell_updates_per_s": k2n / w2n / 1e6}
+            "dmr_mcell_updates_per_s": k2n / w2n / 1e6,
+            "dmr_hbm": hbm_share(k2n / w2n / 1e6)}
         out["config2_dmr_vs_uniform"] = {
             "workload": "coarse 4096x2048 @ lambda/32 + r=2 patch (bounding box of 8 "
                         "seeds in the right third, E_rms/E_bd = 1.5) vs uniform-fine "
@@ -457,6 +468,7 @@ def main():
             "batched_s": wall_b, "sequential_plain_s": wall_s,
             "speedup": wall_s / wall_b,
             "mcell_updates_per_s": work_b / wall_b / 1e6,
+            "hbm": hbm_share(work_b / wall_b / 1e6),
             "launch_shape": {"seg": shape[0], "depth": shape[1], "fine_ty": shape[2],
                              "graph": shape[3]}}
 
