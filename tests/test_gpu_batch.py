@@ -125,3 +125,23 @@ def test_union_batch_launch_shape_invariance():
     bt.step(steps)
     for k in range(len(cfgs)):
         _same(bt.instances[k], ref.instances[k])
+
+
+def test_batch_config3_full_size_prefix():
+    """The benchmark's batch at full size (64 instances drawn as config 3:
+    sides 256/512/1024, 35/110/170 GHz, 100-760 Torr, tuned launch shape,
+    graph replay) over its first 4 periods (one growth test): every instance
+    equals its own plain run bit for bit."""
+    cfgs, seeds = W.config3(64, periods=4)
+    steps = cfgs[0]["steps"]
+    bt = B.Batch(cfgs, seeds)
+    bt.step(steps)
+    bt.sync()
+    print("config 3 batch: launch shape", bt.config(), flush=True)
+    for k, (c, s) in enumerate(zip(cfgs, seeds)):
+        g = B.Sim(c, *s)
+        g.step(steps)
+        inst = bt.instances[k]
+        assert inst.patch() == g.patch(), k
+        _same(inst, g)
+        g.close()
