@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
+from paper_2105_13276_amd import binding as B
 from paper_2105_13276_amd import workloads as W
 
 from gpu_helpers import assert_parity, both
@@ -123,3 +124,36 @@ def test_config2_full_size_prefix():
     o.step(cfg["steps"])
     g.sync()
     assert_parity(g, o, _nc(cfg), tag="config2-prefix")
+
+
+def test_fused_forms_bitwise():
+    """The one-launch step (base step + both patch substeps), the two-substep
+    patch launch and two one-substep launches give the same bits (each
+    entity is computed with the same operations in all three)."""
+    import os
+    cfg = W.make(128, 64, 32, "dynamic", 10, erms_over_ebd=3.0)
+    cfg["regrid_every"] = 2 * cfg["steps_per_period"]
+    sb, sf = W.seeds(cfg, [(80 * LAM / 32, 32 * LAM / 32)], [3e17])
+    runs = {}
+    for name, env in (("combined", {}), ("fused", {"DMR_COMBINE": "0"}),
+                      ("separate", {"DMR_COMBINE": "0", "DMR_FUSE": "0"})):
+        old = {k: os.environ.get(k) for k in ("DMR_COMBINE", "DMR_FUSE")}
+        os.environ.update(env)
+        try:
+            g = B.Sim(cfg, sb, sf)
+        finally:
+            for k, v in old.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+        g.step(cfg["steps"])
+        runs[name] = {(f, lv): g.get(f, lv) for lv in (0, 1)
+                      for f in ("hz", "ex", "ey", "jx", "jy", "n", "acc", "ring")}
+        runs[name]["patch"] = g.patch()
+        g.close()
+    for name in ("fused", "separate"):
+        assert runs[name]["patch"] == runs["combined"]["patch"]
+        for k, v in runs["combined"].items():
+            if k != "patch":
+                assert np.array_equal(v, runs[name][k]), (name, k)
