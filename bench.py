@@ -146,10 +146,11 @@ def hbm_share(mcell_per_s):
     return {"alg_GB_per_s": gbs, "frac_of_8TBps": gbs / 8000.0}
 
 
-def run_case(B, cfg, seeds, chunks, chunk, warmup, timing):
+def run_case(B, cfg, seeds, chunks, chunk, warmup, timing, hist=None):
     """Fresh simulation at t = 0, `chunks` x `chunk` base steps timed.
     Returns the handle, the wall time and the cell-updates performed (the
-    patch changes only at the regrid that ends a chunk)."""
+    patch changes only at the regrid that ends a chunk).  hist (a list), if
+    given, receives the refined fraction R of the domain for each chunk."""
     import torch
     sb, sf = seeds
     if warmup:  # a throw-away instance runs the same kernels first
@@ -171,6 +172,8 @@ def run_case(B, cfg, seeds, chunks, chunk, warmup, timing):
         fine_cells = r * r * (e[2] - e[0]) * (e[3] - e[1])
         if union:  # the active blocks, not their bounding box
             fine_cells = r * r * int(sim.blocks().sum()) * cfg["block"] ** 2
+        if hist is not None:
+            hist.append(fine_cells / float(r * r * base_cells))
         work += chunk * (base_cells + r * fine_cells)  # r fine steps per base step
         sim.step(chunk)
     torch.cuda.synchronize()
@@ -255,7 +258,8 @@ def main():
     cfg_d = W.config1_dmr(periods=periods)
     seeds_d = W.seeds(cfg_d)
     n_coarse = K * INTERVAL
-    sim_d, wall_d, work_d = run_case(B, cfg_d, seeds_d, K, INTERVAL, Wm, False)
+    r_hist = []
+    sim_d, wall_d, work_d = run_case(B, cfg_d, seeds_d, K, INTERVAL, Wm, False, r_hist)
     ext = sim_d.patch()
     fine_cells = 4 * (ext[2] - ext[0]) * (ext[3] - ext[1])
     coarse_cells = cfg_d["nx"] * cfg_d["ny"]
@@ -318,6 +322,7 @@ def main():
                    "global_batch": 1, "seq_len": None, "parallelism": "none"},
         "time_to_t_final_s": wall_d,
         "patch_final": list(ext),
+        "refined_fraction_per_interval": [round(v, 6) for v in r_hist],
         "uniform_fine_equiv_mcell_updates_per_s": work_u / wall_d / 1e6,
         "uniform_fine": {"time_to_t_final_s": wall_u,
                          "mcell_updates_per_s": work_u / wall_u / 1e6,
