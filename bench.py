@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--only-config1", action="store_true",
                     help="profiling aid: run only 256 steps of DMR config 1 and a "
                          "256 MiB device copy (counter calibration), no JSON")
+    ap.add_argument("--config2-intervals", type=int, default=10,
+                    help="regrid intervals (4 periods each) of the config-2 legs")
     ap.add_argument("--only-config2-union", action="store_true",
                     help="profiling aid: run only 256 coarse steps of config 2 with the "
                          "union-of-blocks fine level, no JSON")
@@ -398,39 +400,45 @@ def main():
 
     # ---- the multi-seed large case: 8 seeds in the right third -------------
     if not args.no_large:
-        log("config 2 (8 seeds, 4096x2048) DMR vs uniform-fine, one interval")
-        cfg_2 = W.config2(periods=4)
+        c2k = max(1, args.config2_intervals)
+        log("config 2 (8 seeds, 4096x2048) DMR vs uniform-fine, %d intervals" % c2k)
+        cfg_2 = W.config2(periods=4 * c2k)
         centres, peaks = W.config2_seed_layout(cfg_2)
         sd_2 = W.seeds(cfg_2, centres, peaks)
-        s2d, w2d, k2d = run_case(B, cfg_2, sd_2, 1, INTERVAL, 0, False)
+        h2d = []
+        s2d, w2d, k2d = run_case(B, cfg_2, sd_2, c2k, INTERVAL, 0, False, h2d)
         ext2 = s2d.patch()
         s2d.close()
-        cfg_2u = W.config2_uniform(periods=4)
+        cfg_2u = W.config2_uniform(periods=4 * c2k)
         sd_2u = W.seeds(cfg_2u, centres, peaks)
-        s2u, w2u, k2u = run_case(B, cfg_2u, sd_2u, 1, 2 * INTERVAL, 0, False)
+        s2u, w2u, k2u = run_case(B, cfg_2u, sd_2u, c2k, 2 * INTERVAL, 0, False)
         s2u.close()
         area = (ext2[2] - ext2[0]) * (ext2[3] - ext2[1]) / float(cfg_2["nx"] * cfg_2["ny"])
         # the same run with the fine level made of the flagged blocks themselves
         cfg_2n = dict(cfg_2, regrid_rule="union")
-        s2n, w2n, k2n = run_case(B, cfg_2n, sd_2, 1, INTERVAL, 0, False)
+        h2n = []
+        s2n, w2n, k2n = run_case(B, cfg_2n, sd_2, c2k, INTERVAL, 0, False, h2n)
         blk2 = s2n.blocks()
         s2n.close()
         area_n = float(blk2.sum()) / blk2.size
         out["config2_union_vs_uniform"] = {
             "workload": "config 2 as below with the fine level = the union of the flagged "
-                        "16x16 blocks (not their bounding box), 4 periods from t = 0",
-            "active_blocks": int(blk2.sum()), "fine_area_fraction": area_n,
+                        "16x16 blocks (not their bounding box), %d periods from t = 0" % (4 * c2k),
+            "active_blocks_final": int(blk2.sum()), "fine_area_fraction_final": area_n,
+            "refined_fraction_per_interval": [round(v, 6) for v in h2n],
             "dmr_s": w2n, "uniform_fine_s": w2u, "speedup": w2u / w2n,
-            "speedup_bound": 1.0 / (1.0 / 8.0 + area_n),
+            "speedup_bound": 1.0 / (1.0 / 8.0 + float(np.mean(h2n))),
             "dmr_mcell_updates_per_s": k2n / w2n / 1e6,
             "dmr_hbm": hbm_share(k2n / w2n / 1e6)}
         out["config2_dmr_vs_uniform"] = {
             "workload": "coarse 4096x2048 @ lambda/32 + r=2 patch (bounding box of 8 "
                         "seeds in the right third, E_rms/E_bd = 1.5) vs uniform-fine "
-                        "8192x4096 @ lambda/64, 4 periods (256 coarse steps) from t = 0",
-            "patch": list(ext2), "patch_area_fraction": area,
+                        "8192x4096 @ lambda/64, %d periods (%d coarse steps) from t = 0"
+                        % (4 * c2k, c2k * INTERVAL),
+            "patch_final": list(ext2), "patch_area_fraction_final": area,
+            "refined_fraction_per_interval": [round(v, 6) for v in h2d],
             "dmr_s": w2d, "uniform_fine_s": w2u, "speedup": w2u / w2d,
-            "speedup_bound_single_rectangle": 1.0 / (1.0 / 8.0 + area),
+            "speedup_bound_single_rectangle": 1.0 / (1.0 / 8.0 + float(np.mean(h2d))),
             "dmr_mcell_updates_per_s": k2d / w2d / 1e6,
             "uniform_mcell_updates_per_s": k2u / w2u / 1e6}
 
