@@ -53,6 +53,8 @@ def parse():
                          "256 MiB device copy (counter calibration), no JSON")
     ap.add_argument("--config2-intervals", type=int, default=10,
                     help="regrid intervals (4 periods each) of the config-2 legs")
+    ap.add_argument("--no-config2-tfinal", action="store_true",
+                    help="skip the config-2 union run to t_final (2000 periods, ~17 s)")
     ap.add_argument("--only-config2-union", action="store_true",
                     help="profiling aid: run only 256 coarse steps of config 2 with the "
                          "union-of-blocks fine level, no JSON")
@@ -430,6 +432,27 @@ def main():
             "speedup_bound": 1.0 / (1.0 / 8.0 + float(np.mean(h2n))),
             "dmr_mcell_updates_per_s": k2n / w2n / 1e6,
             "dmr_hbm": hbm_share(k2n / w2n / 1e6)}
+        if not args.no_config2_tfinal:
+            # the union run to t_final; uniform-fine does the same work every
+            # step, so its time to t_final is the 40-period time scaled
+            log("config 2 union to t_final (2000 periods)")
+            cfg_2f = dict(W.config2(periods=2000), regrid_rule="union")
+            hf = []
+            s2f, w2f, k2f = run_case(B, cfg_2f, sd_2, cfg_2f["steps"] // INTERVAL, INTERVAL, 0,
+                                     False, hf)
+            blkf = s2f.blocks()
+            nmax = float(s2f.get("n", 0).max())
+            s2f.close()
+            uni_tf = w2u * cfg_2f["steps"] / float(c2k * INTERVAL)
+            out["config2_union_t_final"] = {
+                "workload": "config 2 with the union-of-blocks fine level, 2000 periods "
+                            "(128000 coarse steps) from t = 0",
+                "time_to_t_final_s": w2f, "uniform_fine_s_scaled": uni_tf,
+                "uniform_fine_scaled_from": "%d-period uniform-fine run (same work every step)"
+                                            % (4 * c2k),
+                "speedup": uni_tf / w2f, "active_blocks_final": int(blkf.sum()),
+                "refined_fraction_max": float(max(hf)), "n_max_final": nmax,
+                "mcell_updates_per_s": k2f / w2f / 1e6}
         out["config2_dmr_vs_uniform"] = {
             "workload": "coarse 4096x2048 @ lambda/32 + r=2 patch (bounding box of 8 "
                         "seeds in the right third, E_rms/E_bd = 1.5) vs uniform-fine "

@@ -101,9 +101,9 @@ typedef struct dmr_params {
   double courant;            /* S = c dt/dx, same on both levels, <= 1/sqrt 2 */
   double fine_filter;        /* gamma of the weak 4th-order hyper-diffusion of
                                 the patch's interior E, applied before each
-                                fine substep (1e-4 suppresses the slow growth
-                                of sub-coarse modes at the interface; 0: off;
-                                at most 1/64) */
+                                fine substep (1e-3 suppresses the slow growth
+                                of sub-coarse modes at the interface for the
+                                patch shapes tried; 0: off; at most 1/64) */
   /* growth rule of DMR_DYNAMIC (Sec. III.D):
    *   DMR_RULE_BLOCKS  flag nodes (n_thr_over_nc, grad_thr, n_floor_over_nc),
    *                    OR over block x block cells, prefix-sum compaction,

@@ -342,8 +342,10 @@ static double cfb_ex(const orc_sim *s, int P, int J, double frac) {
  * normal difference).  Boundary (coarse-driven) edges are not changed.
  * The paper does not describe how its interface is stabilised; without this
  * term modes finer than the coarse grid can resolve grow slowly inside the
- * patch (doubling every few tens of periods).  gamma = 1e-4 leaves a
- * wavelength of 64 fine cells damped by ~1e-8 per substep. */
+ * patch (doubling every few tens of periods).  gamma = 1e-3 keeps every
+ * patch shape tried stable (1e-4 is not enough for patches 16 coarse cells
+ * across: the growth returns after some hundred periods) and damps a
+ * wavelength of 64 fine cells by ~1e-7 per substep. */
 static void lap_grid(const double *a, double *out, int ni, int nj) {
   for (int i = 0; i < ni; i++)
     for (int j = 0; j < nj; j++) {

@@ -38,7 +38,7 @@ PHYSICS = dict(
     grad_thr=0.2,
     n_floor_over_nc=1e-6,
     courant=0.5,
-    fine_filter=1e-4,
+    fine_filter=1e-3,
     r=2,
     block=16,
     ramp_periods=2,

@@ -168,3 +168,40 @@ def test_r4_dmr_matches_uniform_fine_with_growth(oracle_mod):
     assert rel(nf, nu) < 0.02 and rel(ef, eu) < 0.02
     nc = d.get("n", 0)[p1[1] + 1:p1[3], p1[0] + 1:p1[2]]
     assert np.array_equal(nc, nf[4:-1:4, 4:-1:4])
+
+
+def _narrow_growth(oracle_mod, gamma, periods=600):
+    """Perturbation norm (as _perturbation_growth) in a patch 16 coarse cells
+    tall, every 50 periods."""
+    cfg = W.make(96, 48, 32, "static", 1, static_ext=(40, 16, 72, 32),
+                 continuity_on=False, fine_filter=gamma)
+    z = np.zeros((49, 97))
+    a, b = oracle_mod.Sim(cfg, z), oracle_mod.Sim(cfg, z)
+    spp = cfg["steps_per_period"]
+    a.step(10 * spp)
+    b.step(10 * spp)
+    rng = np.random.default_rng(0)
+    for lv in (0, 1):
+        for f in ("hz", "ex", "ey"):
+            v = b.get(f, lv)
+            sc = 1e6 / 376.73 if f == "hz" else 1e6
+            b.set(f, lv, v + 1e-7 * sc * rng.standard_normal(v.shape))
+    norms = []
+    for _ in range(periods // 50):
+        a.step(50 * spp)
+        b.step(50 * spp)
+        norms.append(np.sqrt(sum((((b.get(f, 1) - a.get(f, 1)) * (376.73 if f == "hz" else 1.0)) ** 2).sum()
+                                 for f in ("hz", "ex", "ey"))))
+    return np.array(norms)
+
+
+@pytest.mark.slow
+def test_narrow_patch_needs_the_filter_strength(oracle_mod):
+    """A 32x16-cell patch: the default filter (1e-3) keeps a perturbation
+    bounded over 600 periods; 1e-4, enough for a 32x32 patch, lets it grow
+    (the long-run growth seen on such patches)."""
+    ok = _narrow_growth(oracle_mod, W.PHYSICS["fine_filter"])
+    weak = _narrow_growth(oracle_mod, 1e-4)
+    print("narrow patch: default %s, 1e-4 %s" % (ok[[0, -1]], weak[[0, -1]]))
+    assert ok[-1] < 1.2 * ok[0]
+    assert weak[-1] > 2.0 * weak[0]
