@@ -18,16 +18,27 @@ def _emax(s):
                np.abs(s.get("ey", 0)).max())
 
 
-@pytest.mark.parametrize("shape", ["32x16", "16x32", "64x16", "L"])
+@pytest.mark.parametrize("shape", ["32x16", "16x32", "64x16", "L", "r4_16x8", "u8_corner"])
 def test_narrow_patch_long_run_bounded(shape):
-    ext = {"32x16": (128, 32, 160, 48), "16x32": (144, 32, 160, 64),
-           "64x16": (128, 32, 192, 48), "L": (128, 32, 176, 48)}[shape]
-    over = dict(regrid_rule="union", block=16) if shape == "L" else {}
-    cfg = W.make(256, 128, 32, "static", 3000, static_ext=ext, continuity_on=False, **over)
-    s = B.Sim(cfg, np.zeros((129, 257)), None)
-    if shape == "L":
-        m = np.zeros((8, 16), np.uint8)
-        m[3, 8] = 1
+    """(At 1e-4 the r = 4 16x8-cell patch and the 8-cell-block corner blow up
+    within 500-750 periods.)"""
+    if shape == "r4_16x8":   # lambda/16 coarse, r = 4
+        cfg = W.make(128, 64, 16, "static", 3000, r=4, block=8, static_ext=(64, 24, 80, 32),
+                     continuity_on=False)
+    else:
+        ext = {"32x16": (128, 32, 160, 48), "16x32": (144, 32, 160, 64),
+               "64x16": (128, 32, 192, 48), "L": (128, 32, 176, 48),
+               "u8_corner": (128, 40, 136, 48)}[shape]
+        over = {"L": dict(regrid_rule="union", block=16),
+                "u8_corner": dict(regrid_rule="union", block=8)}.get(shape, {})
+        cfg = W.make(256, 128, 32, "static", 3000, static_ext=ext, continuity_on=False, **over)
+    s = B.Sim(cfg, np.zeros((cfg["ny"] + 1, cfg["nx"] + 1)), None)
+    if shape in ("L", "u8_corner"):
+        m = np.zeros((cfg["ny"] // cfg["block"], cfg["nx"] // cfg["block"]), np.uint8)
+        if shape == "L":
+            m[3, 8] = 1
+        else:
+            m[6, 17] = 1   # touches the first block at a corner only
         s.add_blocks(m)
     spp = cfg["steps_per_period"]
     s.step(250 * spp)
