@@ -932,6 +932,20 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
   }
   if (combined) {
     // done above
+  } else if (fuse && p.r == 4) {  // substeps (1, 2) then (3, 4), one launch each
+    Level& F = s->L1;
+    for (int h = 0; h < 2; h++) {
+      EMArgs G;
+      make_fine_em(s, 2 * h + 2, c, s->ncur, s->ty1, &G);  // the second pair restricts
+      em_args_level(&G, F, h, 1 - h, F.n[s->ncur], F.acc);
+      G.frac = (float)(2 * h + 1) / (float)p.r;  // time fraction of the pair's first
+      G.hz_save = nullptr;
+      G.hz_lo = nullptr;
+      ev_begin(s, 1);
+      e = launch_fine2(G, s->ty1, s->nt1, s->st);
+      ev_end(s);
+      if (e != hipSuccess) return hipfail(s, e, "fine EM launch");
+    }
   } else if (fuse) {  // both substeps, one launch
     Level& F = s->L1;
     EMArgs G;
@@ -1152,7 +1166,8 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   // bandwidth-bound grids the base kernel's own launch shape is faster
   s->combine = (long)p->nx * p->ny <= (1L << 21);
   if (const char* f = getenv("DMR_COMBINE")) s->combine = atoi(f) != 0;
-  if (p->r != 2) s->fuse_fine = s->combine = false;  // the fused forms are r = 2
+  // the one-launch step is r = 2; r = 4 runs its substeps as two pairs
+  if (p->r != 2) s->combine = false;
   if (const char* f = getenv("DMR_FUSE_MAX")) s->fuse_max = atol(f);
   if (const char* f = getenv("DMR_FNT")) s->nt1 = atoi(f) >= 1024 ? 1024 : 256;
   s->depth0 = stream_depth(s->seg0);

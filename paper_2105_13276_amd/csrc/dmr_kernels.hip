@@ -600,11 +600,26 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_union_batch(const EMArgs*
 // relative to the tile corner, NW_ x NH_): group g (x-edges of row B / T,
 // y-edges of column L / R, -1 none), position c, the two coarse edges o, o2
 // (o at coarse column / row cidx along the line) with weights w0, w1;
-// ok = the edge exists and lies in the region.
+// ok = the edge exists and lies in the region.  r4: refinement factor 4
+// (offsets 1/8: weights 3/8, 1/8, 7/8, 5/8 on the lower coarse edge).
 __device__ __forceinline__ void bnd_src(int tid, int orig, int NW_, int NH_, int i0, int j0,
                                         int L, int R, int B, int T, int cpitch, int& g,
                                         int& c, size_t& o, size_t& o2, float& w0, float& w1,
-                                        bool& ok, int& cidx) {
+                                        bool& ok, int& cidx, bool r4 = false) {
+  // fine edge q of a line: lower coarse edge and its weight
+  auto wq = [&](int q, int& cq) {
+    if (r4) {
+      const int m = q & 3;
+      cq = (q >> 2) - (m < 2 ? 1 : 0);
+      w0 = m == 0 ? 0.375f : m == 1 ? 0.125f : m == 2 ? 0.875f : 0.625f;
+      w1 = 1.f - w0;
+    } else if ((q & 1) == 0) {
+      cq = (q >> 1) - 1; w0 = 0.25f; w1 = 0.75f;
+    } else {
+      cq = q >> 1; w0 = 0.75f; w1 = 0.25f;
+    }
+  };
+  const int rsh = r4 ? 2 : 1;
   g = -1; c = 0; o = 0; o2 = 0; w0 = 0.f; w1 = 0.f; ok = false; cidx = 0;
   if (tid < NW_) { g = 0; c = tid; }
   else if (tid < 2 * NW_) { g = 1; c = tid - NW_; }
@@ -614,9 +629,8 @@ __device__ __forceinline__ void bnd_src(int tid, int orig, int NW_, int NH_, int
     const int i = i0 + orig + c, j = g == 0 ? B : T;
     if (i >= L && i < R && j >= j0 + orig && j < j0 + orig + NH_) {
       int ic;
-      if ((i & 1) == 0) { ic = (i >> 1) - 1; w0 = 0.25f; w1 = 0.75f; }
-      else              { ic = i >> 1;       w0 = 0.75f; w1 = 0.25f; }
-      o = (size_t)(j >> 1) * cpitch + ic;
+      wq(i, ic);
+      o = (size_t)(j >> rsh) * cpitch + ic;
       o2 = o + 1;
       ok = true;
       cidx = ic;
@@ -625,9 +639,8 @@ __device__ __forceinline__ void bnd_src(int tid, int orig, int NW_, int NH_, int
     const int j = j0 + orig + c, i = g == 2 ? L : R;
     if (j >= B && j < T && i >= i0 + orig && i < i0 + orig + NW_) {
       int jc;
-      if ((j & 1) == 0) { jc = (j >> 1) - 1; w0 = 0.25f; w1 = 0.75f; }
-      else              { jc = j >> 1;       w0 = 0.75f; w1 = 0.25f; }
-      o = (size_t)jc * cpitch + (i >> 1);
+      wq(j, jc);
+      o = (size_t)jc * cpitch + (i >> rsh);
       o2 = o + cpitch;
       ok = true;
       cidx = jc;
@@ -645,8 +658,12 @@ __device__ __forceinline__ void bnd_src(int tid, int orig, int NW_, int NH_, int
 // results are identical.  Region origins are relative to the tile corner
 // (i0, j0):  raw E0 -7, L(E0) -6, filtered E0 and H1 -5, E1/J1 and n -4;
 // then as in fine_tile: L(E1) -3, filtered E1 and H2 -2, E2/J2 -1.
+// R4: refinement factor 4, the launch runs substeps (1, 2) or (3, 4) of a
+// coarse step (A.frac = time fraction of the first); the fine -> coarse
+// transfer (A.restrict_on, second pair) uses the Hz after substep 2, which
+// is this launch's input, and after substep 3 (H1).
 // ---------------------------------------------------------------------------
-template <int TY, int NT, bool LOCAL, bool ST = false>
+template <int TY, int NT, bool LOCAL, bool ST = false, bool R4 = false>
 __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
   constexpr int R1W = kTX + 13, R1H = TY + 13;
   constexpr int Q1W = kTX + 11, Q1H = TY + 11;
@@ -682,7 +699,7 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
   const int L = A.L, R = A.R, B = A.B, T = A.T;
   const int pitch = A.pitch;
   const bool filt = A.gamma > 0.f;
-  const float frac1 = A.frac, frac2 = 1.f;
+  const float frac1 = A.frac, frac2 = R4 ? A.frac + 0.25f : 1.f;
   auto hz_ok = [=](int i, int j) { return i >= L && i < R && j >= B && j < T; };
   auto ex_ok = [=](int i, int j) { return i >= L && i < R && j >= B && j <= T; };
   auto ey_ok = [=](int i, int j) { return i >= L && i <= R && j >= B && j < T; };
@@ -733,8 +750,8 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
   size_t o1a, o1b, o2a, o2b;
   float w1a, w1b, w2a, w2b;
   bool ok1, ok2;
-  bnd_src(tid, -4, N1W, N1H, i0, j0, L, R, B, T, A.cpitch, g1, c1_, o1a, o1b, w1a, w1b, ok1, k1);
-  bnd_src(tid, -1, N2W, N2H, i0, j0, L, R, B, T, A.cpitch, g2, c2, o2a, o2b, w2a, w2b, ok2, k2);
+  bnd_src(tid, -4, N1W, N1H, i0, j0, L, R, B, T, A.cpitch, g1, c1_, o1a, o1b, w1a, w1b, ok1, k1, R4);
+  bnd_src(tid, -1, N2W, N2H, i0, j0, L, R, B, T, A.cpitch, g2, c2, o2a, o2b, w2a, w2b, ok2, k2, R4);
   // addresses selected as integers (a select of two argument pointers can
   // otherwise be lowered through private memory)
   const float* b1o = (const float*)(g1 >= 2 ? (uintptr_t)A.cey0 : (uintptr_t)A.cex0);
@@ -1109,28 +1126,63 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
   }
 
   // fine -> coarse transfer (H1 at origin -5, H2 at origin -2)
-  for (int r = ty; r < TY; r += RP) {
-    const int i = i0 + tx, j = j0 + r;
-    if (((i - L) | (j - B)) & 1) continue;
-    const int a = i >> 1, b = j >> 1;
-    const size_t co = (size_t)b * A.cpitch + a;
-    const int ci = tx + 1, cj = r + 1;
-    if (hz_ok(i, j)) {
-      float s = 0.f;
-      for (int da = 0; da < 2; da++)
-        for (int db = 0; db < 2; db++) {
-          const float hold = sH1[r + 5 + db][tx + 5 + da];
-          s += 0.5f * (hold + sH2[r + 2 + db][tx + 2 + da]);
+  if constexpr (R4) {
+    // 4 x 4 cells at the half levels after substeps 2 (the input Hz) and 3
+    // (H1); 4 edges, J~ summed
+    if (A.restrict_on) {
+      for (int r = ty; r < TY; r += RP) {
+        const int i = i0 + tx, j = j0 + r;
+        if (((i - L) | (j - B)) & 3) continue;
+        const int a = i >> 2, b = j >> 2;
+        const size_t co = (size_t)b * A.cpitch + a;
+        const int ci = tx + 1, cj = r + 1;
+        if (hz_ok(i, j)) {
+          float s = 0.f;
+          for (int da = 0; da < 4; da++)
+            for (int db = 0; db < 4; db++) {
+              const float lo = A.hz0[(size_t)(j + db) * pitch + i + da];
+              s += 0.5f * (lo + sH1[r + 5 + db][tx + 5 + da]);
+            }
+          A.chz[co] = 0.0625f * s;
         }
-      A.chz[co] = 0.25f * s;
+        if (ex_ok(i, j) && j > B && j < T) {
+          float se = 0.f, sj = 0.f;
+          for (int da = 0; da < 4; da++) { se += e2X[cj][ci + da]; sj += j2X[r][tx + da]; }
+          A.cex[co] = 0.25f * se;
+          A.cjx[co] = sj;
+        }
+        if (ey_ok(i, j) && i > L && i < R) {
+          float se = 0.f, sj = 0.f;
+          for (int db = 0; db < 4; db++) { se += e2Y[cj + db][ci]; sj += j2Y[r + db][tx]; }
+          A.cey[co] = 0.25f * se;
+          A.cjy[co] = sj;
+        }
+      }
     }
-    if (ex_ok(i, j) && j > B && j < T) {
-      A.cex[co] = 0.5f * (e2X[cj][ci] + e2X[cj][ci + 1]);
-      A.cjx[co] = j2X[r][tx] + j2X[r][tx + 1];  // J~ scales with dt
-    }
-    if (ey_ok(i, j) && i > L && i < R) {
-      A.cey[co] = 0.5f * (e2Y[cj][ci] + e2Y[cj + 1][ci]);
-      A.cjy[co] = j2Y[r][tx] + j2Y[r + 1][tx];
+  } else {
+    for (int r = ty; r < TY; r += RP) {
+      const int i = i0 + tx, j = j0 + r;
+      if (((i - L) | (j - B)) & 1) continue;
+      const int a = i >> 1, b = j >> 1;
+      const size_t co = (size_t)b * A.cpitch + a;
+      const int ci = tx + 1, cj = r + 1;
+      if (hz_ok(i, j)) {
+        float s = 0.f;
+        for (int da = 0; da < 2; da++)
+          for (int db = 0; db < 2; db++) {
+            const float hold = sH1[r + 5 + db][tx + 5 + da];
+            s += 0.5f * (hold + sH2[r + 2 + db][tx + 2 + da]);
+          }
+        A.chz[co] = 0.25f * s;
+      }
+      if (ex_ok(i, j) && j > B && j < T) {
+        A.cex[co] = 0.5f * (e2X[cj][ci] + e2X[cj][ci + 1]);
+        A.cjx[co] = j2X[r][tx] + j2X[r][tx + 1];  // J~ scales with dt
+      }
+      if (ey_ok(i, j) && i > L && i < R) {
+        A.cey[co] = 0.5f * (e2Y[cj][ci] + e2Y[cj + 1][ci]);
+        A.cjy[co] = j2Y[r][tx] + j2Y[r + 1][tx];
+      }
     }
   }
 
@@ -1156,9 +1208,9 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
   }
 }
 
-template <int TY, int NT, bool ST = false>
+template <int TY, int NT, bool ST = false, bool R4 = false>
 __global__ __launch_bounds__(NT) void k_fine2(EMArgs A) {
-  fine2_tile<TY, NT, false, ST>(A, blockIdx.x, blockIdx.y);
+  fine2_tile<TY, NT, false, ST, R4>(A, blockIdx.x, blockIdx.y);
 }
 
 
@@ -1943,6 +1995,15 @@ hipError_t launch_prolong_union(const ProlongArgs& A, const int2* tiles, int nti
 }
 
 hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st) {
+  if (A.rf == 4) {  // a pair of the four substeps, 1024 threads
+    const dim3 g((A.R - A.L + 1 + kTX - 1) / kTX, (A.T - A.B + 1 + ty - 1) / ty);
+    switch (ty) {
+    case 4: hipLaunchKernelGGL((k_fine2<4, 1024, false, true>), g, dim3(1024), 0, st, A); break;
+    case 8: hipLaunchKernelGGL((k_fine2<8, 1024, false, true>), g, dim3(1024), 0, st, A); break;
+    default: hipLaunchKernelGGL((k_fine2<16, 1024, false, true>), g, dim3(1024), 0, st, A); break;
+    }
+    return hipGetLastError();
+  }
   if (A.stn) {
     switch (ty) {
     case 4: DMR_LAUNCH_TILE_ST(k_fine2, 4, A, st); break;

@@ -126,17 +126,25 @@ def test_config2_full_size_prefix():
     assert_parity(g, o, _nc(cfg), tag="config2-prefix")
 
 
-def test_fused_forms_bitwise():
+@pytest.mark.parametrize("r", [2, 4])
+def test_fused_forms_bitwise(r):
     """The one-launch step (base step + both patch substeps), the two-substep
     patch launch and two one-substep launches give the same bits (each
-    entity is computed with the same operations in all three)."""
+    entity is computed with the same operations in all three); for r = 4 the
+    substeps run as two two-substep launches or four one-substep launches."""
     import os
-    cfg = W.make(128, 64, 32, "dynamic", 10, erms_over_ebd=3.0)
+    if r == 2:
+        cfg = W.make(128, 64, 32, "dynamic", 10, erms_over_ebd=3.0)
+        sb, sf = W.seeds(cfg, [(80 * LAM / 32, 32 * LAM / 32)], [3e17])
+        forms = (("combined", {}), ("fused", {"DMR_COMBINE": "0"}),
+                 ("separate", {"DMR_COMBINE": "0", "DMR_FUSE": "0"}))
+    else:
+        cfg = W.make(64, 32, 16, "dynamic", 10, r=4, block=8, erms_over_ebd=3.0)
+        sb, sf = W.seeds(cfg, [(40 * LAM / 16, 16 * LAM / 16)], [3e17])
+        forms = (("combined", {}), ("separate", {"DMR_FUSE": "0"}))
     cfg["regrid_every"] = 2 * cfg["steps_per_period"]
-    sb, sf = W.seeds(cfg, [(80 * LAM / 32, 32 * LAM / 32)], [3e17])
     runs = {}
-    for name, env in (("combined", {}), ("fused", {"DMR_COMBINE": "0"}),
-                      ("separate", {"DMR_COMBINE": "0", "DMR_FUSE": "0"})):
+    for name, env in forms:
         old = {k: os.environ.get(k) for k in ("DMR_COMBINE", "DMR_FUSE")}
         os.environ.update(env)
         try:
@@ -147,12 +155,14 @@ def test_fused_forms_bitwise():
                     os.environ.pop(k, None)
                 else:
                     os.environ[k] = v
+        p0 = g.patch()
         g.step(cfg["steps"])
         runs[name] = {(f, lv): g.get(f, lv) for lv in (0, 1)
                       for f in ("hz", "ex", "ey", "jx", "jy", "n", "acc", "ring")}
-        runs[name]["patch"] = g.patch()
+        runs[name]["patch"] = (p0, g.patch())
         g.close()
-    for name in ("fused", "separate"):
+    print("r = %d patch %s" % (r, runs["combined"]["patch"]), flush=True)
+    for name, _ in forms[1:]:
         assert runs[name]["patch"] == runs["combined"]["patch"]
         for k, v in runs["combined"].items():
             if k != "patch":
