@@ -144,6 +144,21 @@ typedef struct dmr_params {
 
 typedef struct dmr_sim dmr_sim;
 
+/* Host only, no device call: the scalars the library derives from *p before
+ * a run, as dmr_create computes them, in this order: omega = 2 pi f; lambda
+ * = c/f; the base level's dx = lambda/cells_per_lambda and dt = S dx/c;
+ * nu_m = 5.3e9 p (Sec. II.A); the critical density n_c = m_e eps0 omega^2 /
+ * e^2; the effective-field factor 1/(1 + (omega/nu_m)^2) (Eq. (3)); the rms
+ * breakdown field E_bd and the incident amplitude E0 = sqrt 2 (E_rms/E_bd)
+ * E_bd; D_e and D_a and the ambipolar density scale of Eq. (4); the base
+ * level's Drude decay a = exp(-nu_m dt) and drive b = e^2 (1 - a)/(m_e nu_m)
+ * (Eq. (2), both as the kernels receive them in float32); the numerical
+ * wavenumber of the incident wave (Sec. II.B); the ionisation model's
+ * nu_m A (E_cr/p)^beta (float32 product, as the kernels use it); and the base
+ * steps per period.  out receives the first min(n_out, 17) of these.
+ * EINVAL on bad params or out == NULL. */
+int dmr_derived(const dmr_params *p, double *out, int n_out);
+
 /* Bytes of device workspace the problem needs, sized for a patch covering
  * the whole domain so that growth never reallocates.  EINVAL on bad params. */
 int dmr_workspace_bytes(const dmr_params *p, size_t *bytes);

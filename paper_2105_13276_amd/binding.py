@@ -32,7 +32,12 @@ SYMBOLS = ["dmr_workspace_bytes", "dmr_create", "dmr_destroy", "dmr_step",
            "dmr_batch_set_config", "dmr_batch_destroy", "dmr_batch_last_error",
            "dmr_adjoint_tape_bytes", "dmr_forward_record", "dmr_backward",
            "dmr_weighted_sum", "dmr_state_bytes", "dmr_save", "dmr_load",
-           "dmr_get_blocks", "dmr_add_blocks"]
+           "dmr_get_blocks", "dmr_add_blocks", "dmr_derived"]
+
+# the scalars dmr_derived returns, in its order
+DERIVED = ["omega", "lambda", "dx", "dt", "nu_m", "n_c", "eeff_fac", "E_bd",
+           "E0", "D_e", "D_a", "n_amb", "a", "b", "ktilde", "nu_att",
+           "steps_per_period"]
 
 
 class DmrParams(C.Structure):
@@ -81,6 +86,7 @@ def lib():
         L = C.CDLL(LIB)
         P, V = C.POINTER, C.c_void_p
         L.dmr_workspace_bytes.argtypes = [P(DmrParams), P(C.c_size_t)]
+        L.dmr_derived.argtypes = [P(DmrParams), P(C.c_double), C.c_int]
         L.dmr_create.argtypes = [P(DmrParams), V, V, V, C.c_size_t, V, P(V)]
         L.dmr_destroy.argtypes = [V]
         L.dmr_destroy.restype = None
@@ -145,6 +151,16 @@ def make_params(cfg: dict) -> DmrParams:
         else:
             setattr(p, name, cfg[name])
     return p
+
+
+def derived(cfg: dict) -> dict:
+    """The library's derived scalars for cfg (host only, no device call)."""
+    p = make_params(cfg)
+    out = (C.c_double * len(DERIVED))()
+    rc = lib().dmr_derived(C.byref(p), out, len(DERIVED))
+    if rc:
+        raise DmrError("dmr_derived: %s" % ERRORS.get(rc, rc))
+    return dict(zip(DERIVED, list(out)))
 
 
 def workspace_bytes(cfg: dict) -> int:

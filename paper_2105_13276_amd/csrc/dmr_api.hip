@@ -303,6 +303,19 @@ void level_coeffs(dmr_sim* s, Level* L, double dx, double dt, int spp) {
   L->cmur = (float)((S - 1.0) / (S + 1.0));
 }
 
+// the base level's step sizes and coefficients and the incident wavenumber;
+// no device memory is touched
+void setup_scalars(dmr_sim* s) {
+  const dmr_params& p = s->p;
+  derive(s);
+  const double dx0 = s->lambda / p.cells_per_lambda;
+  const double dt0 = p.courant * dx0 / kC0;
+  const int spp0 = (int)std::lround(p.cells_per_lambda / p.courant);
+  // numerical wavenumber of the 1-D Yee wave
+  s->ktil = 2.0 / dx0 * std::asin(std::sin(0.5 * s->omega * dt0) / p.courant);
+  level_coeffs(s, &s->L0, dx0, dt0, spp0);
+}
+
 void carve(dmr_sim* s, Level* L, size_t off, size_t plane, int pitch, int NX,
            int NY) {
   float* base = (float*)(s->ws + off);
@@ -1100,6 +1113,31 @@ float* array_of(dmr_sim* s, int field, int level, double* scale) {
 
 extern "C" {
 
+int dmr_derived(const dmr_params* p, double* out, int n_out) {
+  std::string why;
+  const int rc = check_params(p, &why);
+  if (rc) {
+    fprintf(stderr, "dmr_derived: %s\n", why.c_str());
+    return rc;
+  }
+  if (!out || n_out < 0) return DMR_EINVAL;
+  dmr_sim* s = new (std::nothrow) dmr_sim();
+  if (!s) return DMR_ENOMEM;
+  s->p = *p;
+  setup_scalars(s);
+  ContArgs K;
+  make_base_cont(s, 0, &K);
+  const Level& L = s->L0;
+  const double v[17] = {
+      s->omega, s->lambda, L.dx, L.dt, s->nu_m, s->n_c, s->eeff,
+      s->e0 / (std::sqrt(2.0) * p->erms_over_ebd), s->e0, s->De, s->Da, s->n_amb,
+      (double)L.a, (double)L.kn * 4.0 * kEps0 / L.dt, s->ktil,
+      (double)K.nuA * (double)K.att, (double)L.spp};
+  for (int k = 0; k < n_out && k < 17; k++) out[k] = v[k];
+  delete s;
+  return DMR_OK;
+}
+
 int dmr_workspace_bytes(const dmr_params* p, size_t* bytes) {
   std::string why;
   const int rc = check_params(p, &why);
@@ -1128,14 +1166,10 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   s->st = (hipStream_t)stream;
   s->lay = lay;
   s->ws = (char*)d_workspace;
-  derive(s);
-  const double dx0 = s->lambda / p->cells_per_lambda;
-  const double dt0 = p->courant * dx0 / kC0;
-  const int spp0 = (int)std::lround(p->cells_per_lambda / p->courant);
-  // numerical wavenumber of the 1-D Yee wave
-  s->ktil = 2.0 / dx0 * std::asin(std::sin(0.5 * s->omega * dt0) / p->courant);
+  setup_scalars(s);
+  const double dx0 = s->L0.dx, dt0 = s->L0.dt;
+  const int spp0 = s->L0.spp;
   carve(s, &s->L0, 0, lay.plane0, lay.pitch0, p->nx, p->ny);
-  level_coeffs(s, &s->L0, dx0, dt0, spp0);
   if (refined(p)) {
     carve(s, &s->L1, lay.off_l1, lay.plane1, lay.pitch1, p->r * p->nx, p->r * p->ny);
     level_coeffs(s, &s->L1, dx0 / p->r, dt0 / p->r, spp0 * p->r);

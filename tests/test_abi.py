@@ -113,3 +113,28 @@ def test_union_workspace_holds_maps_and_tiles():
     uni = B.workspace_bytes(dict(cfg, regrid_rule="union"))
     tiles = ((1024 + 1 + 63) // 64) * ((512 + 1 + 3) // 4)
     assert uni - rect >= 2 * (32 * 16) + 2 * 8 * tiles + 4 * 198 * tiles
+
+
+@pytest.mark.parametrize("over", [
+    dict(),
+    dict(p_torr=200.0, freq_hz=60e9, erms_over_ebd=2.5, te_ev=1.5),
+    dict(source_model="townsend", beta_rec=1.0),
+    dict(cells_per_lambda=16, courant=0.5),
+])
+def test_library_derives_the_oracles_constants(oracle_mod, over):
+    """The library's own host-side derivation of the run's scalars (collision
+    rate, critical density, breakdown field, diffusivities, Drude decay and
+    drive, incident wavenumber) against the oracle's, with no device call:
+    FP64 values to rounding, those the kernels take in float32 to float32."""
+    cfg = dict(W.config1_dmr())
+    cfg.update(over)
+    g, o = B.derived(cfg), oracle_mod.derived(cfg)
+    assert list(g) == list(o)
+    f32 = {"a", "b", "nu_att"}
+    for k in g:
+        tol = 2e-7 if k in f32 else 1e-13
+        assert abs(g[k] - o[k]) <= tol * abs(o[k]), (k, g[k], o[k])
+    p = B.make_params(cfg)
+    p.courant = 0.75
+    out = (C.c_double * 17)()
+    assert B.lib().dmr_derived(C.byref(p), out, 17) == -1
