@@ -99,6 +99,9 @@ int check_params(const dmr_params* p, std::string* why) {
   if (!p) return bad("params is NULL");
   if (p->struct_size != sizeof(dmr_params)) return bad("struct_size mismatch");
   if (p->nx < 4 || p->ny < 4) return bad("nx, ny must be >= 4");
+  // patch tiles address rows with 24-bit products of the byte pitch
+  if ((long)p->nx * (p->r > 1 ? p->r : 1) >= (1L << 21))
+    return bad("a level must be narrower than 2^21 cells");
   if (p->cells_per_lambda < 4) return bad("cells_per_lambda must be >= 4");
   if (!(p->courant > 0.0) || p->courant > 1.0 / std::sqrt(2.0) + 1e-12)
     return bad("Courant number must be in (0, 1/sqrt(2)] (2-D Yee stability)");
@@ -215,6 +218,7 @@ struct dmr_sim {
   bool combine = true;
   long fuse_max = 1L << 20;  // fine cells up to which the two-substep launch is used
   int nt1 = 1024;  // threads per patch tile
+  int tw1 = 0;     // patch tile width of the combined step (0: by patch size)
   uint8_t* d_flag = nullptr;
   int32_t *d_scan = nullptr, *d_list = nullptr;
   int* d_desc = nullptr;
@@ -923,7 +927,7 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
     G.cnx = p.nx; G.cny = p.ny;
     fine_stores(&G);
     ev_begin(s, 0);
-    e = launch_dmr_step(A, G, s->seg0, s->depth0, s->ty1, s->st);
+    e = launch_dmr_step(A, G, s->seg0, s->depth0, s->ty1, s->tw1, s->st);
     ev_end(s);
     if (e != hipSuccess) return hipfail(s, e, "combined step launch");
     std::swap(F.hz[0], F.hz[1]);
@@ -1204,6 +1208,7 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   if (p->r != 2) s->combine = false;
   if (const char* f = getenv("DMR_FUSE_MAX")) s->fuse_max = atol(f);
   if (const char* f = getenv("DMR_FNT")) s->nt1 = atoi(f) >= 1024 ? 1024 : 256;
+  if (const char* f = getenv("DMR_TW")) { const int v = atoi(f); s->tw1 = (v == 16 || v == 32 || v == 64) ? v : 0; }
   s->depth0 = stream_depth(s->seg0);
   hipError_t e = hipMemsetAsync(s->ws, 0, lay.total, s->st);
   if (e != hipSuccess) { rc = hipfail(s, e, "workspace clear"); delete s; return rc; }
@@ -2119,6 +2124,7 @@ struct dmr_batch {
   int2 *d_blk_base = nullptr, *d_blk_fine = nullptr, *d_blk_cont = nullptr,
        *d_blk_fcont = nullptr;
   int nblk_base = 0, nblk_fine = 0, nblk_cont = 0, nblk_fcont = 0;
+  size_t cap_base = 0, cap_fine = 0, cap_cont = 0, cap_fcont = 0;  // table entries
   float2* d_src = nullptr;
   float2* h_src = nullptr;
   int64_t src_base = -1;
@@ -2168,7 +2174,8 @@ int batch_layout(const dmr_params* p, int count, BatchLayout* L, std::string* wh
     L->size.push_back(b);
     off += align256(b);
     const int nx = p[k].nx, ny = p[k].ny, r = refined(&p[k]) ? p[k].r : 1;
-    L->cap_base += (size_t)stream_blocks_x(nx) * stream_segments(ny, 4);
+    // the shortest segment a batch may use (2 rows) gives the most blocks
+    L->cap_base += (size_t)stream_blocks_x(nx) * stream_segments(ny, 2);
     L->cap_cont += (size_t)((nx + 1 + kTX - 1) / kTX) * ((ny + 1 + 3) / 4);
     if (refined(&p[k])) {
       const size_t t = (size_t)((r * nx + 1 + kTX - 1) / kTX) * ((r * ny + 1 + 3) / 4);
@@ -2243,6 +2250,9 @@ int batch_tables(dmr_batch* b) {
       for (int t = 0; t < H.nbx * hny; t++) b->h_blk_fcont.push_back(make_int2(k, t));
     }
   }
+  if (b->h_blk_base.size() > b->cap_base || b->h_blk_fine.size() > b->cap_fine ||
+      b->h_blk_cont.size() > b->cap_cont || b->h_blk_fcont.size() > b->cap_fcont)
+    return bfail(b, DMR_EINVAL, "batch block table exceeds its workspace capacity");
   b->nblk_base = (int)b->h_blk_base.size();
   b->nblk_fine = (int)b->h_blk_fine.size();
   b->nblk_cont = (int)b->h_blk_cont.size();
@@ -2533,6 +2543,8 @@ int dmr_batch_create(const dmr_params* p, int count, const double* const* seed_b
   b->d_blk_fine = (int2*)(b->ws + L.off_blk_fine);
   b->d_blk_cont = (int2*)(b->ws + L.off_blk_cont);
   b->d_blk_fcont = (int2*)(b->ws + L.off_blk_fcont);
+  b->cap_base = std::max<size_t>(L.cap_base, 1); b->cap_fine = std::max<size_t>(L.cap_fine, 1);
+  b->cap_cont = std::max<size_t>(L.cap_cont, 1); b->cap_fcont = std::max<size_t>(L.cap_fcont, 1);
   b->d_src = (float2*)(b->ws + L.off_src);
   rc = batch_tables(b);
   if (rc) {

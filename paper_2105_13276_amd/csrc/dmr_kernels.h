@@ -162,7 +162,7 @@ hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st);
 // base-level step (C, with the patch's coarse entities skipped) and both patch
 // substeps (F, coarse boundary E computed in the tiles) in one launch
 hipError_t launch_dmr_step(const EMArgs& C, const EMArgs& F, int seg, int depth, int ty,
-                           hipStream_t st);
+                           int tw, hipStream_t st);
 // base level, column-streaming kernel; seg = rows per segment (>= 2)
 hipError_t launch_em_stream(const EMArgs& A, int seg, int depth, hipStream_t st);
 // threshold lines of the patch sides (left I0, right I1, bottom J0, top J1):

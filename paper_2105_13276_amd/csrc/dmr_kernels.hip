@@ -86,6 +86,35 @@ __device__ inline float win_e2(float sx, int cx, float sy, int cy) {
 // ---------------------------------------------------------------------------
 // tix: the tile's index in the union's tile list (its slot of the Eq. (5b)
 // hand-off between the substeps); unused for the rectangle
+// A patch tile's fine arrays from a per-tile corner (ib, jb): entity (i, j)
+// at byte offset 4 ((j - jb) pitch + i - ib) of each base.  The offsets stay
+// far below 2^32 (a few dozen rows), so loads and stores take a 32-bit
+// offset from a uniform base (no per-lane 64-bit address arithmetic);
+// pitch * 4 < 2^24 is required by the parameter checks.
+struct TileBase {
+  const float *hz0, *ex0, *ey0, *jx0, *jy0, *n;
+  float *hz1, *ex1, *ey1, *jx1, *jy1, *acc;
+  int ib, jb;
+  unsigned p4;
+  __device__ __forceinline__ TileBase(const EMArgs& A, int ib_, int jb_) : ib(ib_), jb(jb_) {
+    const size_t t = (size_t)jb_ * A.pitch + ib_;
+    hz0 = A.hz0 + t; ex0 = A.ex0 + t; ey0 = A.ey0 + t;
+    jx0 = A.jx0 + t; jy0 = A.jy0 + t; n = A.n + t;
+    hz1 = A.hz1 + t; ex1 = A.ex1 + t; ey1 = A.ey1 + t;
+    jx1 = A.jx1 + t; jy1 = A.jy1 + t; acc = A.acc + t;
+    p4 = (unsigned)A.pitch * 4u;
+  }
+  __device__ __forceinline__ unsigned off(int i, int j) const {
+    return (unsigned)__umul24((unsigned)(j - jb), p4) + ((unsigned)(i - ib) << 2);
+  }
+};
+__device__ __forceinline__ float ldo(const float* p, unsigned b) {
+  return *(const float*)((const char*)p + b);
+}
+__device__ __forceinline__ void sto(float* p, unsigned b, float v) {
+  *(float*)((char*)p + b) = v;
+}
+
 template <int TY, int NT, bool UN = false>
 __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int tix = 0) {
   constexpr int EW = kTX + 3, EH = TY + 3;  // old E (filtered)
@@ -152,11 +181,15 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int t
     else return i != L && i != R;
   };
   // clamped (always valid) addresses of each entity kind
-  auto cl = [&](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
-  auto o_hz = [&](int i, int j) { return (size_t)cl(j, B, T - 1) * pitch + cl(i, L, R - 1); };
-  auto o_ex = [&](int i, int j) { return (size_t)cl(j, B, T) * pitch + cl(i, L, R - 1); };
-  auto o_ey = [&](int i, int j) { return (size_t)cl(j, B, T - 1) * pitch + cl(i, L, R); };
-  auto o_nd = [&](int i, int j) { return (size_t)cl(j, B, T) * pitch + cl(i, L, R); };
+  // (tile-relative byte offsets from the corner (ib, jb), as in fine2_tile)
+  const int ib = max(i0 - 8, L), jb = max(j0 - 8, B);
+  const TileBase tb(A, ib, jb);
+  auto cl = [&](int v, int lo, int hi) { return min(max(v, lo), hi); };
+  auto ob = [&](int i, int j) { return tb.off(i, j); };
+  auto o_hz = [&](int i, int j) { return ob(cl(i, L, R - 1), cl(j, B, T - 1)); };
+  auto o_ex = [&](int i, int j) { return ob(cl(i, L, R - 1), cl(j, B, T)); };
+  auto o_ey = [&](int i, int j) { return ob(cl(i, L, R), cl(j, B, T - 1)); };
+  auto o_nd = [&](int i, int j) { return ob(cl(i, L, R), cl(j, B, T)); };
 
   // -- one batch of global loads ------------------------------------------------
   constexpr int NP = NR > NO ? NR : NO;
@@ -166,42 +199,42 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int t
     for (int q = 0; q < NR; q++) {
       const int k = min(tid + q * NT, RH * RW - 1);
       const int i = i0 - 4 + k % RW, j = j0 - 4 + k / RW;
-      pex[q] = A.ex0[o_ex(i, j)];
-      pey[q] = A.ey0[o_ey(i, j)];
+      pex[q] = ldo(tb.ex0, o_ex(i, j));
+      pey[q] = ldo(tb.ey0, o_ey(i, j));
     }
   } else {
 #pragma unroll
     for (int q = 0; q < NO; q++) {
       const int k = min(tid + q * NT, EH * EW - 1);
       const int i = i0 - 2 + k % EW, j = j0 - 2 + k / EW;
-      pex[q] = A.ex0[o_ex(i, j)];
-      pey[q] = A.ey0[o_ey(i, j)];
+      pex[q] = ldo(tb.ex0, o_ex(i, j));
+      pey[q] = ldo(tb.ey0, o_ey(i, j));
     }
   }
   float pn[ND];
 #pragma unroll
   for (int q = 0; q < ND; q++) {
     const int k = min(tid + q * NT, DH * DW - 1);
-    pn[q] = A.n[o_nd(i0 - 1 + k % DW, j0 - 1 + k / DW)];
+    pn[q] = ldo(tb.n, o_nd(i0 - 1 + k % DW, j0 - 1 + k / DW));
   }
   float phz[NHZ];
 #pragma unroll
   for (int q = 0; q < NHZ; q++) {
     const int k = min(tid + q * NT, HH * HW - 1);
-    phz[q] = A.hz0[o_hz(i0 - 2 + k % HW, j0 - 2 + k / HW)];
+    phz[q] = ldo(tb.hz0, o_hz(i0 - 2 + k % HW, j0 - 2 + k / HW));
   }
   float pjx[NE], pjy[NE];
 #pragma unroll
   for (int q = 0; q < NE; q++) {
     const int k = min(tid + q * NT, NH * NW - 1);
     const int i = i0 - 1 + k % NW, j = j0 - 1 + k / NW;
-    pjx[q] = A.jx0[o_ex(i, j)];
-    pjy[q] = A.jy0[o_ey(i, j)];
+    pjx[q] = ldo(tb.jx0, o_ex(i, j));
+    pjy[q] = ldo(tb.jy0, o_ey(i, j));
   }
   const int tx = tid % kTX, ty = tid / kTX;
   float pacc[NA];
 #pragma unroll
-  for (int q = 0; q < NA; q++) pacc[q] = A.acc[o_nd(i0 + tx, j0 + ty + q * RP)];
+  for (int q = 0; q < NA; q++) pacc[q] = ldo(tb.acc, o_nd(i0 + tx, j0 + ty + q * RP));
   // Eq. (5b) boundary values: x-edges of rows B and T, y-edges of columns L
   // and R inside this tile's new-E region, linear in space between the two
   // nearest coarse edges (weights w0, w1) and in time between the old and
@@ -421,14 +454,14 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int t
       const int i = i0 - 2 + ci, j = j0 - 2 + cj;
       float h = 0.f, ho = 0.f;
       if (hz_ok(i, j)) {
-        const size_t o = (size_t)j * pitch + i;
+        const unsigned o = ob(i, j);
         const float dey = sEyo[cj][ci + 1] - sEyo[cj][ci];
         const float dex = sExo[cj + 1][ci] - sExo[cj][ci];
         ho = phz[q];
         h = faraday(ho, A.S, dey, dex);
         if (ci >= 2 && cj >= 2) {
-          A.hz1[o] = h;
-          if (A.hz_save) A.hz_save[o] = h;
+          sto(tb.hz1, o, h);
+          if (A.hz_save) A.hz_save[(size_t)j * pitch + i] = h;
         }
       }
       sH[cj][ci] = h;
@@ -445,7 +478,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int t
       const int ci = k % NW, cj = k / NW;
       const int i = i0 - 1 + ci, j = j0 - 1 + cj;
       const bool own = ci >= 1 && cj >= 1;
-      const size_t o = (size_t)j * pitch + i;
+      const unsigned o = ob(i, j);
       float exn = 0.f, eyn = 0.f;
       if (ex_ok(i, j)) {
         const float e = sExo[cj + 1][ci + 1];
@@ -462,8 +495,8 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int t
         }
         if (own) {
           const float jn = drude(A.a, jo, kap, e, exn);
-          A.ex1[o] = exn;
-          A.jx1[o] = jn;
+          sto(tb.ex1, o, exn);
+          sto(tb.jx1, o, jn);
           sJx[cj - 1][ci - 1] = jn;
         }
       }
@@ -482,8 +515,8 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int t
         }
         if (own) {
           const float jn = drude(A.a, jo, kap, e, eyn);
-          A.ey1[o] = eyn;
-          A.jy1[o] = jn;
+          sto(tb.ey1, o, eyn);
+          sto(tb.jy1, o, jn);
           sJy[cj - 1][ci - 1] = jn;
         }
       }
@@ -510,8 +543,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int t
     if (yd) { const float v = sEyn[cj - 1][ci]; sy += v * v; cy++; }
     if (yu) { const float v = sEyn[cj][ci]; sy += v * v; cy++; }
     const float e2 = win_e2(sx, cx, sy, cy);
-    const size_t o = (size_t)j * pitch + i;
-    A.acc[o] = pacc[q] + e2;
+    sto(tb.acc, ob(i, j), pacc[q] + e2);
   }
 
   // -- fine -> coarse transfer after the last substep ------------------------
@@ -663,23 +695,23 @@ __device__ __forceinline__ void bnd_src(int tid, int orig, int NW_, int NH_, int
 // transfer (A.restrict_on, second pair) uses the Hz after substep 2, which
 // is this launch's input, and after substep 3 (H1).
 // ---------------------------------------------------------------------------
-template <int TY, int NT, bool LOCAL, bool ST = false, bool R4 = false>
+template <int TY, int NT, bool LOCAL, bool ST = false, bool R4 = false, int TW = kTX>
 __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
-  constexpr int R1W = kTX + 13, R1H = TY + 13;
-  constexpr int Q1W = kTX + 11, Q1H = TY + 11;
-  constexpr int F1W = kTX + 9, F1H = TY + 9;
-  constexpr int H1W = kTX + 8, H1H = TY + 8;
-  constexpr int N1W = kTX + 7, N1H = TY + 7;
-  constexpr int D1W = kTX + 8, D1H = TY + 8;
-  constexpr int Q2W = kTX + 5, Q2H = TY + 5;
-  constexpr int F2W = kTX + 3, F2H = TY + 3;
-  constexpr int H2W = kTX + 2, H2H = TY + 2;
-  constexpr int N2W = kTX + 1, N2H = TY + 1;
+  constexpr int R1W = TW + 13, R1H = TY + 13;
+  constexpr int Q1W = TW + 11, Q1H = TY + 11;
+  constexpr int F1W = TW + 9, F1H = TY + 9;
+  constexpr int H1W = TW + 8, H1H = TY + 8;
+  constexpr int N1W = TW + 7, N1H = TY + 7;
+  constexpr int D1W = TW + 8, D1H = TY + 8;
+  constexpr int Q2W = TW + 5, Q2H = TY + 5;
+  constexpr int F2W = TW + 3, F2H = TY + 3;
+  constexpr int H2W = TW + 2, H2H = TY + 2;
+  constexpr int N2W = TW + 1, N2H = TY + 1;
   constexpr int NR = (R1H * R1W + NT - 1) / NT;
   constexpr int NH0 = (H1H * H1W + NT - 1) / NT;
   constexpr int NJ0 = (N1H * N1W + NT - 1) / NT;
   constexpr int ND = (D1H * D1W + NT - 1) / NT;
-  constexpr int RP = NT / kTX;  // tile rows per pass of the block
+  constexpr int RP = NT / TW;  // tile rows per pass of the block
   constexpr int NA = (TY + RP - 1) / RP;
   __shared__ float rX[R1H][R1W], rY[R1H][R1W];  // raw E0
   __shared__ float qX[Q1H][Q1W], qY[Q1H][Q1W];  // L(E0), then L(E1)
@@ -690,10 +722,10 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
   __shared__ float sN[D1H][D1W];
   __shared__ float sH2[H2H][H2W];
   __shared__ float e2X[N2H][N2W], e2Y[N2H][N2W];
-  __shared__ float j2X[TY][kTX], j2Y[TY][kTX];
+  __shared__ float j2X[TY][TW], j2Y[TY][TW];
   __shared__ float sB1[5][N1W], sB2[5][N2W];  // Eq. (5b) values of substeps 1 and 2
 
-  const int i0 = A.L + bx * kTX;
+  const int i0 = A.L + bx * TW;
   const int j0 = A.B + by * TY;
   const int tid = threadIdx.x;
   const int L = A.L, R = A.R, B = A.B, T = A.T;
@@ -704,11 +736,17 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
   auto ex_ok = [=](int i, int j) { return i >= L && i < R && j >= B && j <= T; };
   auto ey_ok = [=](int i, int j) { return i >= L && i <= R && j >= B && j < T; };
   auto nd_ok = [=](int i, int j) { return i >= L && i <= R && j >= B && j <= T; };
-  auto cl = [=](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
-  auto o_hz = [=](int i, int j) { return (size_t)cl(j, B, T - 1) * pitch + cl(i, L, R - 1); };
-  auto o_ex = [=](int i, int j) { return (size_t)cl(j, B, T) * pitch + cl(i, L, R - 1); };
-  auto o_ey = [=](int i, int j) { return (size_t)cl(j, B, T - 1) * pitch + cl(i, L, R); };
-  auto o_nd = [=](int i, int j) { return (size_t)cl(j, B, T) * pitch + cl(i, L, R); };
+  // tile-relative byte offsets: every fine entity the tile reads or writes
+  // lies in [ib, ib + TW + 16) x [jb, jb + TY + 16) (clamped loads
+  // included), so a 32-bit offset from per-tile bases addresses it
+  const int ib = max(i0 - 8, L), jb = max(j0 - 8, B);
+  const TileBase tb(A, ib, jb);
+  auto cl = [=](int v, int lo, int hi) { return min(max(v, lo), hi); };
+  auto ob = [=](int i, int j) { return tb.off(i, j); };
+  auto o_hz = [=](int i, int j) { return ob(cl(i, L, R - 1), cl(j, B, T - 1)); };
+  auto o_ex = [=](int i, int j) { return ob(cl(i, L, R - 1), cl(j, B, T)); };
+  auto o_ey = [=](int i, int j) { return ob(cl(i, L, R), cl(j, B, T - 1)); };
+  auto o_nd = [=](int i, int j) { return ob(cl(i, L, R), cl(j, B, T)); };
 
   // -- one batch of global loads ------------------------------------------------
   float pex[NR], pey[NR];
@@ -716,33 +754,33 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
   for (int q = 0; q < NR; q++) {
     const int k = min(tid + q * NT, R1H * R1W - 1);
     const int i = i0 - 7 + k % R1W, j = j0 - 7 + k / R1W;
-    pex[q] = A.ex0[o_ex(i, j)];
-    pey[q] = A.ey0[o_ey(i, j)];
+    pex[q] = ldo(tb.ex0, o_ex(i, j));
+    pey[q] = ldo(tb.ey0, o_ey(i, j));
   }
   float phz[NH0];
 #pragma unroll
   for (int q = 0; q < NH0; q++) {
     const int k = min(tid + q * NT, H1H * H1W - 1);
-    phz[q] = A.hz0[o_hz(i0 - 5 + k % H1W, j0 - 5 + k / H1W)];
+    phz[q] = ldo(tb.hz0, o_hz(i0 - 5 + k % H1W, j0 - 5 + k / H1W));
   }
   float pjx[NJ0], pjy[NJ0];
 #pragma unroll
   for (int q = 0; q < NJ0; q++) {
     const int k = min(tid + q * NT, N1H * N1W - 1);
     const int i = i0 - 4 + k % N1W, j = j0 - 4 + k / N1W;
-    pjx[q] = A.jx0[o_ex(i, j)];
-    pjy[q] = A.jy0[o_ey(i, j)];
+    pjx[q] = ldo(tb.jx0, o_ex(i, j));
+    pjy[q] = ldo(tb.jy0, o_ey(i, j));
   }
   float pn[ND];
 #pragma unroll
   for (int q = 0; q < ND; q++) {
     const int k = min(tid + q * NT, D1H * D1W - 1);
-    pn[q] = A.n[o_nd(i0 - 4 + k % D1W, j0 - 4 + k / D1W)];
+    pn[q] = ldo(tb.n, o_nd(i0 - 4 + k % D1W, j0 - 4 + k / D1W));
   }
-  const int tx = tid % kTX, ty = tid / kTX;
+  const int tx = tid % TW, ty = tid / TW;
   float pacc[NA];
 #pragma unroll
-  for (int q = 0; q < NA; q++) pacc[q] = A.acc[o_nd(i0 + tx, j0 + ty + q * RP)];
+  for (int q = 0; q < NA; q++) pacc[q] = ldo(tb.acc, o_nd(i0 + tx, j0 + ty + q * RP));
   // Eq. (5b) sources of both substeps: boundary x-edges of rows B, T and
   // y-edges of columns L, R inside each substep's new-E region (origin
   // -4 of width N1W x N1H for substep 1, -1 of N2W x N2H for substep 2)
@@ -770,7 +808,7 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
   // waves of the same launch compute the same values).  x-lines: coarse rows
   // B/2 and T/2 at columns [cx0, cx0 + CW); y-lines: coarse columns L/2 and
   // R/2 at rows [cy0, cy0 + CH).
-  constexpr int CW = kTX / 2 + 6, CH = TY / 2 + 6;
+  constexpr int CW = TW / 2 + 6, CH = TY / 2 + 6;
   __shared__ float sC[5][CW > CH ? CW : CH];
   const int cx0 = ((i0 - 4) >> 1) - 1, cy0 = ((j0 - 4) >> 1) - 1;
   int cg = -1, cc = 0;
@@ -1055,7 +1093,7 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
       const float dey = fY[cj][ci + 1] - fY[cj][ci];
       const float dex = fX[cj + 1][ci] - fX[cj][ci];
       h = faraday(sH1[cj + 3][ci + 3], A.S, dey, dex);
-      if (ci >= 2 && cj >= 2) A.hz1[(size_t)j * pitch + i] = h;
+      if (ci >= 2 && cj >= 2) sto(tb.hz1, ob(i, j), h);
     }
     sH2[cj][ci] = h;
   }
@@ -1066,7 +1104,7 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
     const int ci = k % N2W, cj = k / N2W;
     const int i = i0 - 1 + ci, j = j0 - 1 + cj;
     const bool own = ci >= 1 && cj >= 1;
-    const size_t o = (size_t)j * pitch + i;
+    const unsigned o = ob(i, j);
     float exn = 0.f, eyn = 0.f;
     if (ex_ok(i, j)) {
       const float e = fX[cj + 1][ci + 1];
@@ -1081,8 +1119,8 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
       }
       if (own) {
         const float jn = drude(A.a, jo, kap, e, exn);
-        A.ex1[o] = exn;
-        A.jx1[o] = jn;
+        sto(tb.ex1, o, exn);
+        sto(tb.jx1, o, jn);
         j2X[cj - 1][ci - 1] = jn;
       }
     }
@@ -1099,8 +1137,8 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
       }
       if (own) {
         const float jn = drude(A.a, jo, kap, e, eyn);
-        A.ey1[o] = eyn;
-        A.jy1[o] = jn;
+        sto(tb.ey1, o, eyn);
+        sto(tb.jy1, o, jn);
         j2Y[cj - 1][ci - 1] = jn;
       }
     }
@@ -1122,7 +1160,7 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
     if (i < R) { const float v = e2X[cj][ci]; sx += v * v; cx++; }
     if (j > B) { const float v = e2Y[cj - 1][ci]; sy += v * v; cy++; }
     if (j < T) { const float v = e2Y[cj][ci]; sy += v * v; cy++; }
-    A.acc[(size_t)j * pitch + i] = acc1[q] + win_e2(sx, cx, sy, cy);
+    sto(tb.acc, ob(i, j), acc1[q] + win_e2(sx, cx, sy, cy));
   }
 
   // fine -> coarse transfer (H1 at origin -5, H2 at origin -2)
@@ -1208,9 +1246,9 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
   }
 }
 
-template <int TY, int NT, bool ST = false, bool R4 = false>
+template <int TY, int NT, bool ST = false, bool R4 = false, int TW = kTX>
 __global__ __launch_bounds__(NT) void k_fine2(EMArgs A) {
-  fine2_tile<TY, NT, false, ST, R4>(A, blockIdx.x, blockIdx.y);
+  fine2_tile<TY, NT, false, ST, R4, TW>(A, blockIdx.x, blockIdx.y);
 }
 
 
@@ -1895,7 +1933,7 @@ __global__ __launch_bounds__(kThreads) void k_em_stream_batch(const EMArgs* __re
 // the step on their boundary lines themselves.  The base waves do not store
 // the coarse entities the tiles' fine -> coarse transfer writes.
 // ---------------------------------------------------------------------------
-template <int DEPTH, int TY, bool ST = false>
+template <int DEPTH, int TY, bool ST = false, int TW = kTX>
 __global__ __launch_bounds__(kFineThreads) void k_dmr_step(EMArgs C, EMArgs F, int seg, int nseg,
                                                            int waves_x, int ncb, int nbx_f) {
   const int b = blockIdx.x;
@@ -1906,7 +1944,7 @@ __global__ __launch_bounds__(kFineThreads) void k_dmr_step(EMArgs C, EMArgs F, i
     return;
   }
   const int t = b - ncb;
-  fine2_tile<TY, kFineThreads, true, ST>(F, t % nbx_f, t / nbx_f);
+  fine2_tile<TY, kFineThreads, true, ST, false, TW>(F, t % nbx_f, t / nbx_f);
 }
 
 // ---- host-side launchers ----------------------------------------------------
@@ -1994,11 +2032,29 @@ hipError_t launch_prolong_union(const ProlongArgs& A, const int2* tiles, int nti
   return hipGetLastError();
 }
 
+// Width of the 4-row patch tiles: a tile's latency is set by its substep-1
+// region (the tile plus a 7-cell halo), so small patches take the narrowest
+// width whose tiles, with `others` blocks beside them, still fit one block
+// per compute unit.  The width does not change any result.
+int patch_tile_width(const EMArgs& F, int others) {
+  const int nby = (F.T - F.B + 1 + 3) / 4;
+  for (int tw = 16; tw < kTX; tw *= 2)
+    if ((long)((F.R - F.L + 1 + tw - 1) / tw) * nby + others <= 256) return tw;
+  return kTX;
+}
+
 hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st) {
   if (A.rf == 4) {  // a pair of the four substeps, 1024 threads
+    if (ty == 4) {
+      const int tw = patch_tile_width(A, 0);
+      const dim3 g((A.R - A.L + 1 + tw - 1) / tw, (A.T - A.B + 1 + 3) / 4);
+      if (tw == 16) hipLaunchKernelGGL((k_fine2<4, 1024, false, true, 16>), g, dim3(1024), 0, st, A);
+      else if (tw == 32) hipLaunchKernelGGL((k_fine2<4, 1024, false, true, 32>), g, dim3(1024), 0, st, A);
+      else hipLaunchKernelGGL((k_fine2<4, 1024, false, true>), g, dim3(1024), 0, st, A);
+      return hipGetLastError();
+    }
     const dim3 g((A.R - A.L + 1 + kTX - 1) / kTX, (A.T - A.B + 1 + ty - 1) / ty);
     switch (ty) {
-    case 4: hipLaunchKernelGGL((k_fine2<4, 1024, false, true>), g, dim3(1024), 0, st, A); break;
     case 8: hipLaunchKernelGGL((k_fine2<8, 1024, false, true>), g, dim3(1024), 0, st, A); break;
     default: hipLaunchKernelGGL((k_fine2<16, 1024, false, true>), g, dim3(1024), 0, st, A); break;
     }
@@ -2012,6 +2068,14 @@ hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st) {
     }
     return hipGetLastError();
   }
+  if (ty == 4 && nt >= 1024) {
+    const int tw = patch_tile_width(A, 0);
+    const dim3 g((A.R - A.L + 1 + tw - 1) / tw, (A.T - A.B + 1 + 3) / 4);
+    if (tw == 16) hipLaunchKernelGGL((k_fine2<4, 1024, false, false, 16>), g, dim3(1024), 0, st, A);
+    else if (tw == 32) hipLaunchKernelGGL((k_fine2<4, 1024, false, false, 32>), g, dim3(1024), 0, st, A);
+    else hipLaunchKernelGGL((k_fine2<4, 1024>), g, dim3(1024), 0, st, A);
+    return hipGetLastError();
+  }
   switch (ty) {
   case 4: DMR_LAUNCH_TILE(k_fine2, 4, nt, A, st); break;
   case 8: DMR_LAUNCH_TILE(k_fine2, 8, nt, A, st); break;
@@ -2021,26 +2085,32 @@ hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st) {
 }
 
 hipError_t launch_dmr_step(const EMArgs& C, const EMArgs& F, int seg, int depth, int ty,
-                           hipStream_t st) {
+                           int tw, hipStream_t st) {
   const int waves_x = (C.R + 1 + 61) / 62;
   const int nseg = stream_segments(C.T, seg);
   const int wpb = kFineThreads / 64;
   const int ncb = (waves_x * nseg + wpb - 1) / wpb;
-  const int nbx_f = (F.R - F.L + 1 + kTX - 1) / kTX;
+  if (ty != 4) tw = kTX;  // narrow tiles: 4-row tiles only
+  else if (tw <= 0) tw = patch_tile_width(F, ncb);
+  const int nbx_f = (F.R - F.L + 1 + tw - 1) / tw;
   const int nby_f = (F.T - F.B + 1 + ty - 1) / ty;
   const dim3 g(ncb + nbx_f * nby_f), blk(kFineThreads);
-#define DMR_STEP(D, T_) hipLaunchKernelGGL((k_dmr_step<D, T_>), g, blk, 0, st, C, F, seg, nseg, waves_x, ncb, nbx_f)
-#define DMR_STEP_ST(D, T_) hipLaunchKernelGGL((k_dmr_step<D, T_, true>), g, blk, 0, st, C, F, seg, nseg, waves_x, ncb, nbx_f)
+#define DMR_STEP(D, T_, W_) hipLaunchKernelGGL((k_dmr_step<D, T_, false, W_>), g, blk, 0, st, C, F, seg, nseg, waves_x, ncb, nbx_f)
+#define DMR_STEP_ST(D, T_, W_) hipLaunchKernelGGL((k_dmr_step<D, T_, true, W_>), g, blk, 0, st, C, F, seg, nseg, waves_x, ncb, nbx_f)
   if (C.stix) {  // replay: stores for the adjoint
     if (depth >= 4) {
-      if (ty == 4) DMR_STEP_ST(4, 4); else if (ty == 8) DMR_STEP_ST(4, 8); else DMR_STEP_ST(4, 16);
+      if (ty == 4) { if (tw == 16) DMR_STEP_ST(4, 4, 16); else if (tw == 32) DMR_STEP_ST(4, 4, 32); else DMR_STEP_ST(4, 4, kTX); }
+      else if (ty == 8) DMR_STEP_ST(4, 8, kTX); else DMR_STEP_ST(4, 16, kTX);
     } else {
-      if (ty == 4) DMR_STEP_ST(2, 4); else if (ty == 8) DMR_STEP_ST(2, 8); else DMR_STEP_ST(2, 16);
+      if (ty == 4) { if (tw == 16) DMR_STEP_ST(2, 4, 16); else if (tw == 32) DMR_STEP_ST(2, 4, 32); else DMR_STEP_ST(2, 4, kTX); }
+      else if (ty == 8) DMR_STEP_ST(2, 8, kTX); else DMR_STEP_ST(2, 16, kTX);
     }
   } else if (depth >= 4) {
-    if (ty == 4) DMR_STEP(4, 4); else if (ty == 8) DMR_STEP(4, 8); else DMR_STEP(4, 16);
+    if (ty == 4) { if (tw == 16) DMR_STEP(4, 4, 16); else if (tw == 32) DMR_STEP(4, 4, 32); else DMR_STEP(4, 4, kTX); }
+    else if (ty == 8) DMR_STEP(4, 8, kTX); else DMR_STEP(4, 16, kTX);
   } else {
-    if (ty == 4) DMR_STEP(2, 4); else if (ty == 8) DMR_STEP(2, 8); else DMR_STEP(2, 16);
+    if (ty == 4) { if (tw == 16) DMR_STEP(2, 4, 16); else if (tw == 32) DMR_STEP(2, 4, 32); else DMR_STEP(2, 4, kTX); }
+    else if (ty == 8) DMR_STEP(2, 8, kTX); else DMR_STEP(2, 16, kTX);
   }
 #undef DMR_STEP
 #undef DMR_STEP_ST

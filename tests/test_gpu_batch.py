@@ -52,7 +52,8 @@ def test_batch_equals_plain_runs():
         _same(inst, g)
 
 
-@pytest.mark.parametrize("shape", [(4, 4, 4, 0), (32, 2, 16, 1), (8, 4, 8, 1)])
+@pytest.mark.parametrize("shape", [(4, 4, 4, 0), (32, 2, 16, 1), (8, 4, 8, 1), (2, 2, 4, 1),
+                                   (2, 2, 8, 0)])
 def test_batch_launch_shape_invariance(shape):
     cfgs, seeds = _mixed(count=4, periods=8)
     steps = cfgs[0]["steps"]
