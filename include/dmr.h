@@ -136,7 +136,7 @@ typedef struct dmr_params {
    *                        attachment nu_att (1/s)
    * and recombination r_ei = beta_rec 1e-13 (300 K / T_e)^(1/2) m^3/s
    * (T_e = te_ev in kelvin; beta_rec in [0, 2], 0: none).  The adjoint
-   * supports the power law without recombination. */
+   * supports both sources, with or without recombination. */
   int32_t source_model;
   int32_t pad3_;
   double A_town, B_town, nu_att, beta_rec;
@@ -307,7 +307,8 @@ int dmr_forward_record(dmr_sim *s, int64_t steps, int ckpt_every, void *d_tape,
  *                     seed) when dmr_create was given one (else zeros); may
  *                     be NULL
  *   grad        out, host: dF/dE0 (per V/m of peak amplitude), dF/dA,
- *               dF/dbeta
+ *               dF/dbeta (A_ion and beta_ion of the power-law source; zero
+ *               with the Townsend source, where they do not enter)
  * The handle is left at t_final, as after the record.  Synchronises. */
 int dmr_backward(dmr_sim *s, const void *d_tape, const float *d_w_coarse,
                  const float *d_w_fine, float *d_grad_seed, float *d_grad_seed_fine,

@@ -5,7 +5,9 @@ implementation of the same discrete update as dmr_oracle.c (Eqs. (1)-(5),
 Sec. II-III), written with whole-array torch operations in float64 so that
 torch.autograd yields the exact discrete adjoint of the objective
 F = dx_c^2 * sum_w w * n_c(t_final) with respect to the incident amplitude
-E0, the ionisation coefficients A and beta and the coarse seed density.
+E0, the ionisation coefficients A and beta and the coarse seed density
+(power-law source; with the Townsend source of Eq. (4) A and beta do not
+enter and their gradients are zero; recombination is included in both).
 The forward is checked against the C oracle (test_oracle_adjoint.py); the
 gradients against central finite differences of the C oracle.
 
@@ -28,6 +30,7 @@ ME = 9.1093837015e-31
 EPS0 = 8.8541878128e-12
 C0 = 299792458.0
 MU0 = 1.0 / (EPS0 * C0 * C0)
+KB = 1.380649e-23
 
 
 def derived(cfg):
@@ -46,6 +49,9 @@ def derived(cfg):
              Da=cfg["mu_i_760"] * (760.0 / cfg["p_torr"]) * (cfg["te_ev"] + cfg["ti_ev"]),
              n_amb=EPS0 * cfg["te_ev"] / (QE * cfg["L_amb"] ** 2),
              spp=int(round(cfg["cells_per_lambda"] / cfg["courant"])))
+    # recombination coefficient of Eq. (4), m^3/s, with T_e in kelvin
+    brec = cfg.get("beta_rec", 0.0)
+    d["r_ei"] = brec * 1e-13 * math.sqrt(300.0 / (cfg["te_ev"] * QE / KB)) if brec > 0 else 0.0
     return d
 
 
@@ -148,7 +154,17 @@ class Model:
 
     # ---- ionisation and diffusion (Eq. (4), Sec. II.A) ------------------
     def nu(self, e2, A, beta):
+        """Net ionisation rate of Eq. (4) at E_rms^2 = e2: the power law in
+        E_eff/p (coefficients A, beta), or Townsend's gamma v_d minus a
+        constant attachment rate (then A and beta do not enter)."""
         c = self.cfg
+        if c.get("source_model", "power") == "townsend":
+            eeff = torch.sqrt(torch.clamp(e2 * self.d["eeff"], min=1e-300))   # V/m
+            pos = e2 > 0
+            e_cm = eeff / 100.0
+            gamma_cm = c["A_town"] * c["p_torr"] * torch.exp(-c["B_town"] * c["p_torr"] / e_cm)
+            v_d = QE / (ME * self.d["nu_m"]) * eeff
+            return torch.where(pos, 100.0 * gamma_cm * v_d, torch.zeros_like(e2)) - c["nu_att"]
         x = e2 * self.d["eeff"] / (1e4 * c["p_torr"] ** 2)
         xb = torch.where(x > 0, torch.pow(torch.clamp(x, min=1e-300), 0.5 * beta),
                          torch.zeros_like(x))
@@ -169,7 +185,7 @@ class Model:
         flux = torch.zeros_like(n)
         flux = flux + torch.nn.functional.pad(fx, (0, 1)) - torch.nn.functional.pad(fx, (1, 0))
         flux = flux + torch.nn.functional.pad(fy, (0, 0, 0, 1)) - torch.nn.functional.pad(fy, (0, 0, 1, 0))
-        nn = n + dtn * (flux / (L.dx * L.dx) + self.nu(e2, A, beta) * n)
+        nn = n + dtn * (flux / (L.dx * L.dx) + self.nu(e2, A, beta) * n - self.d["r_ei"] * n * n)
         nn = torch.clamp(nn, min=0.0)
         if interior:
             out = n.clone()

@@ -729,12 +729,26 @@ __device__ __forceinline__ void adj_cont_tile(const AdjContArgs& A, int bx, int 
       if (j > A.B) flux += 0.5f * (di + d_eff_a(A, vd)) * (vd - ni);
       if (j < A.T) flux += 0.5f * (di + d_eff_a(A, vu)) * (vu - ni);
       const float x = e2 * A.eeff_p2;
-      const float pw = powf(x, A.half_beta);
-      const float nu = A.nuA * (pw - A.att);
-      float nn = ni + A.dtn * (flux * A.inv_dx2 + nu * ni);
+      // net rate as the continuity kernel evaluates it, and d nu / d E_rms^2
+      float nu, pw = 0.f, dnu = 0.f;
+      if (A.town) {
+        // nu = K y exp(-B / y) - nu_att,  y = sqrt(x) = E_eff / (100 p)
+        const float y = sqrtf(x);
+        const float ey = y > 0.f ? expf(-A.tB / y) : 0.f;
+        nu = (y > 0.f ? A.tK * y * ey : 0.f) - A.tatt;
+        if (y > 0.f) dnu = A.tK * ey * (1.f + A.tB / y) * (0.5f * A.eeff_p2 / y);
+      } else {
+        pw = powf(x, A.half_beta);
+        nu = A.nuA * (pw - A.att);
+      }
+      const float nn = (!A.town && A.rei == 0.f)
+                           ? ni + A.dtn * (flux * A.inv_dx2 + nu * ni)
+                           : ni + A.dtn * (flux * A.inv_dx2 + (nu - A.rei * ni) * ni);
       // max(0, .): right derivative at 0 (a zero density is perturbed upward)
       ell = nn >= 0.f ? lno : 0.f;
-      if (own) {
+      if (own && A.town) {
+        lE2 = ell * A.dtn * ni * dnu;  // A and beta do not enter
+      } else if (own) {
         // nu = nu_m A (x^(beta/2) - c^beta),  x = E_rms^2 E_eff-factor/(100 p)^2
         const float lnu = ell * A.dtn * ni;
         if (x > 0.f) {
@@ -796,8 +810,15 @@ __device__ __forceinline__ void adj_cont_tile(const AdjContArgs& A, int bx, int 
     float self = 0.f;
     if (lj != 0.f) {
       const float x = A.e2[o] * A.eeff_p2;
-      const float nu = A.nuA * (powf(x, A.half_beta) - A.att);
-      self = lj * (1.f + A.dtn * nu);
+      float nu;
+      if (A.town) {
+        const float y = sqrtf(x);
+        nu = (y > 0.f ? A.tK * y * expf(-A.tB / y) : 0.f) - A.tatt;
+      } else {
+        nu = A.nuA * (powf(x, A.half_beta) - A.att);
+      }
+      // d/dn of n + dtn (nu - r n) n
+      self = A.rei == 0.f ? lj * (1.f + A.dtn * nu) : lj * (1.f + A.dtn * (nu - 2.f * A.rei * nj));
     }
     A.ln_o[o] = self + A.dtn * A.inv_dx2 * sacc;
   }

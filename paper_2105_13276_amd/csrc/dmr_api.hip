@@ -1647,6 +1647,14 @@ AdjContArgs adj_cont_args(const dmr_sim* s, const Level& Lv, AdjLevel& a, bool f
   K.De = (float)s->De; K.Da = (float)s->Da;
   K.d_const_mode = p.d_mode == DMR_D_CONST;
   K.d_const = (float)p.d_const;
+  if (p.source_model == DMR_SOURCE_TOWNSEND) {  // the forward's constants
+    const double mu_e = kQe / (kMe * s->nu_m);
+    K.town = 1;
+    K.tK = (float)(1.0e4 * p.A_town * p.p_torr * p.p_torr * mu_e);
+    K.tB = (float)p.B_town;
+    K.tatt = (float)p.nu_att;
+  }
+  K.rei = (float)rei_of(p);
   K.ln = a.n; K.ln_o = a.n2; K.lacc = a.acc; K.lring = a.ring;
   return K;
 }
@@ -1851,8 +1859,6 @@ int dmr_forward_record(dmr_sim* s, int64_t steps, int ckpt_every, void* d_tape, 
   if (!s) return DMR_EINVAL;
   if (steps < 1 || ckpt_every < 1) return fail(s, DMR_EINVAL, "steps and ckpt_every must be >= 1");
   if (s->step != 0) return fail(s, DMR_EINVAL, "recording starts at t = 0 (fresh handle)");
-  if (s->p.source_model != DMR_SOURCE_POWER || s->p.beta_rec > 0.0)
-    return fail(s, DMR_EINVAL, "the adjoint supports the power-law source without recombination");
   if (refined(&s->p) && s->p.r != 2) return fail(s, DMR_EINVAL, "the adjoint supports r = 2");
   if (s->uni) return fail(s, DMR_EINVAL, "the adjoint supports the rectangular patch");
   if (!d_tape || ((uintptr_t)d_tape & 255)) return fail(s, DMR_EINVAL, "tape must be 256-byte aligned");

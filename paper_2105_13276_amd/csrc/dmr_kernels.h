@@ -246,6 +246,9 @@ struct AdjContArgs {
   float inv_namb, De, Da;
   int d_const_mode;
   float d_const;
+  // Townsend source (town) and recombination (rei), as in ContArgs
+  int town;
+  float tK, tB, tatt, rei;
   const float* n;   // density entering the continuity step
   const float* e2;  // E_rms^2 the step used
   float* ln;        // lam n leaving (entering: ln_o)

@@ -1,6 +1,7 @@
 """Cases shared by the reference-adjoint tests (CPU) and the GPU adjoint
-tests: a fixed patch, the uniform mesh and a growing patch, each with a
-wavelength-square objective window centred on the seed."""
+tests: a fixed patch, the uniform mesh, a growing patch and the fixed patch
+with the Townsend source and recombination, each with a wavelength-square
+objective window centred on the seed."""
 import numpy as np
 
 from oracle import oracle as O
@@ -8,7 +9,9 @@ from paper_2105_13276_amd import workloads as W
 
 LAM = 299792458.0 / 110e9
 CENTRE = {"static": (57 * LAM / 32, 24 * LAM / 32), "uniform": (57 * LAM / 32, 24 * LAM / 32),
-          "dynamic": (96 * 0.62 * LAM / 32, 24 * LAM / 32)}
+          "dynamic": (96 * 0.62 * LAM / 32, 24 * LAM / 32),
+          "townsend": (57 * LAM / 32, 24 * LAM / 32)}
+PEAK = {"static": 3e17, "uniform": 3e17, "dynamic": 3e17, "townsend": 1e20}
 
 
 def case(mode="static", periods=10):
@@ -19,9 +22,14 @@ def case(mode="static", periods=10):
         # grows once, after 8 of the 10 periods (regrid every 2 periods)
         cfg = W.make(96, 48, 32, "dynamic", periods, erms_over_ebd=3.0)
         cfg["regrid_every"] = 2 * cfg["steps_per_period"]
+    elif mode == "townsend":
+        # the fixed patch with the Townsend source and recombination of
+        # Eq. (4); a dense seed so that the n^2 loss matters
+        cfg = W.make(96, 48, 32, "static", periods, static_ext=(48, 16, 64, 32),
+                     erms_over_ebd=2.0, source_model="townsend", beta_rec=1.0)
     else:
         cfg = W.make(64, 32, 32, "uniform", periods, erms_over_ebd=2.5)
-    sb, _ = W.seeds(cfg, [CENTRE[mode]], [3e17])
+    sb, _ = W.seeds(cfg, [CENTRE[mode]], [PEAK[mode]])
     return cfg, sb
 
 
@@ -61,5 +69,6 @@ def reference_gradients(cfg, sb, w, ext0, growth, seg=45):
     cs, _ = m.run(seed, e0, A, beta, cfg["steps"], seg=seg)
     F = (torch.tensor(w) * cs["n"]).sum()
     F.backward()
+    g = lambda t: 0.0 if t.grad is None else t.grad.item()   # unused: zero
     return dict(F=F.item(), seed=seed.grad.numpy(), E0=e0.grad.item() / m.d["E0"],
-                A=A.grad.item(), beta=beta.grad.item())
+                A=g(A), beta=g(beta))
