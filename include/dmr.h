@@ -74,8 +74,9 @@ typedef struct dmr_params {
   uint32_t struct_size;
   int32_t nx, ny;            /* base-level cells (domain = nx*dx by ny*dx) */
   int32_t cells_per_lambda;  /* base-level N_lambda (dx = lambda/N) */
-  int32_t r;                 /* refinement factor, 2 or 4 (the fused one-launch
-                                forms, the batch and the adjoint: 2) */
+  int32_t r;                 /* refinement factor, 2 or 4 (the combined one-launch
+                                step, the union level and the adjoint: 2; a
+                                batch: one r for all its refined instances) */
   int32_t block;             /* regrid block edge in base cells (divides nx, ny) */
   int32_t regrid_every;      /* base steps between growth tests */
   int32_t tfsf_i;            /* source node column (base cells), 1..nx-1 */

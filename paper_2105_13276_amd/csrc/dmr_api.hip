@@ -2124,7 +2124,8 @@ struct dmr_batch {
   char* ws = nullptr;
   std::string err;
   EMArgs* d_em = nullptr;      // [4 parities][count]
-  EMArgs* d_fem = nullptr;     // [2 substeps][4 parities][count]
+  EMArgs* d_fem = nullptr;     // [rf substeps][4 parities][count]
+  int rf = 2;                  // fine substeps per coarse step (the refined instances' r)
   ContArgs* d_cont = nullptr;  // [2 density parities][count]
   ContArgs* d_fcont = nullptr; // [2][count]
   int2 *d_blk_base = nullptr, *d_blk_fine = nullptr, *d_blk_cont = nullptr,
@@ -2151,6 +2152,7 @@ constexpr int kTyCand[] = {4, 8, 16};
 
 struct BatchLayout {
   std::vector<size_t> off, size;
+  int rf = 2;  // r of the refined instances (all equal)
   size_t off_em = 0, off_fem = 0, off_cont = 0, off_fcont = 0, off_blk_base = 0,
          off_blk_fine = 0, off_blk_cont = 0, off_blk_fcont = 0, off_src = 0, total = 0;
   size_t cap_base = 0, cap_fine = 0, cap_cont = 0, cap_fcont = 0;
@@ -2159,10 +2161,19 @@ struct BatchLayout {
 int batch_layout(const dmr_params* p, int count, BatchLayout* L, std::string* why) {
   if (!p || count < 1) { *why = "count must be >= 1"; return DMR_EINVAL; }
   size_t off = 0;
+  for (int k = count - 1; k >= 0; k--)
+    if (refined(&p[k])) L->rf = p[k].r;
   for (int k = 0; k < count; k++) {
     int rc = check_params(&p[k], why);
     if (rc) return rc;
-    if (refined(&p[k]) && p[k].r != 2) { *why = "the batched form supports r = 2"; return DMR_EINVAL; }
+    if (refined(&p[k]) && p[k].r != L->rf) {
+      *why = "refined instances of a batch must share r";
+      return DMR_EINVAL;
+    }
+    if (refined(&p[k]) && p[k].r != 2 && p[k].regrid_rule == DMR_RULE_UNION) {
+      *why = "the union-of-blocks level is r = 2";
+      return DMR_EINVAL;
+    }
     if (refined(&p[k]) && (p[k].regrid_rule == DMR_RULE_UNION) != (p[0].regrid_rule == DMR_RULE_UNION)) {
       *why = "instances must all or none use the union-of-blocks fine level";
       return DMR_EINVAL;
@@ -2190,7 +2201,7 @@ int batch_layout(const dmr_params* p, int count, BatchLayout* L, std::string* wh
     }
   }
   L->off_em = off;    off += align256(sizeof(EMArgs) * 4 * count);
-  L->off_fem = off;   off += align256(sizeof(EMArgs) * 8 * count);
+  L->off_fem = off;   off += align256(sizeof(EMArgs) * 4 * L->rf * count);
   L->off_cont = off;  off += align256(sizeof(ContArgs) * 2 * count);
   L->off_fcont = off; off += align256(sizeof(ContArgs) * 2 * count);
   L->off_blk_base = off;  off += align256(sizeof(int2) * std::max<size_t>(L->cap_base, 1));
@@ -2212,7 +2223,7 @@ int bfail(dmr_batch* b, int code, const char* what) {
 int batch_tables(dmr_batch* b) {
   const int n = b->count;
   b->h_em.assign(4 * n, EMArgs{});
-  b->h_fem.assign(8 * n, EMArgs{});
+  b->h_fem.assign(4 * b->rf * n, EMArgs{});
   b->h_cont.assign(2 * n, ContArgs{});
   b->h_fcont.assign(2 * n, ContArgs{});
   b->h_blk_base.clear(); b->h_blk_fine.clear();
@@ -2230,7 +2241,7 @@ int batch_tables(dmr_batch* b) {
     for (int v = 0; v < 4; v++) {
       make_base_em(s, v & 1, v >> 1, &b->h_em[v * n + k]);
       if (s->has_patch)
-        for (int m = 1; m <= 2; m++)
+        for (int m = 1; m <= b->rf; m++)
           make_fine_em(s, m, v & 1, v >> 1, b->ty, &b->h_fem[((m - 1) * 4 + v) * n + k]);
     }
     for (int nc = 0; nc < 2; nc++) {
@@ -2327,7 +2338,7 @@ int batch_launch_step(dmr_batch* b, hipEvent_t* tb, hipEvent_t* tf) {
   if (e != hipSuccess) return bfail(b, DMR_EHIP, "batched base EM launch");
   if (tf) (void)hipEventRecord(tf[0], b->st);
   const bool uni = s0->uni;
-  for (int m = 1; m <= 2 && b->nblk_fine; m++) {
+  for (int m = 1; m <= b->rf && b->nblk_fine; m++) {
     const EMArgs* fa = b->d_fem + ((m - 1) * 4 + v) * n;
     e = uni ? launch_em_union_batch(fa, b->d_blk_fine, b->nblk_fine, b->ty, b->st)
             : launch_em_batch(fa, b->d_blk_fine, b->nblk_fine, b->ty, b->st);
@@ -2543,6 +2554,7 @@ int dmr_batch_create(const dmr_params* p, int count, const double* const* seed_b
   }
   b->d_em = (EMArgs*)(b->ws + L.off_em);
   b->d_fem = (EMArgs*)(b->ws + L.off_fem);
+  b->rf = L.rf;
   b->d_cont = (ContArgs*)(b->ws + L.off_cont);
   b->d_fcont = (ContArgs*)(b->ws + L.off_fcont);
   b->d_blk_base = (int2*)(b->ws + L.off_blk_base);

@@ -146,3 +146,30 @@ def test_batch_config3_full_size_prefix():
         assert inst.patch() == g.patch(), k
         _same(inst, g)
         g.close()
+
+
+def test_r4_batch_equals_plain_runs():
+    """Refinement factor 4 in the batched form: four one-substep fine launches
+    per coarse step (substep 2 keeps its Hz for the fine -> coarse transfer
+    after substep 4), bit for bit the plain runs (which take the substeps
+    as two two-substep launches)."""
+    lam = 299792458.0 / 110e9
+    cfgs, seeds = [], []
+    # the first grows its patch within the run (as in the plain r = 4 growth test)
+    for side, e, x, pk in [(48, 2.5, 29.75, 1e17), (64, 2.5, 31.5, 1e17), (96, 2.0, 47.5, 3e17)]:
+        c = W.make(side, side // 2, 16, "dynamic", 60, r=4, block=8, erms_over_ebd=e)
+        cfgs.append(c)
+        seeds.append(W.seeds(c, [(x * lam / 16, side // 4 * lam / 16)], [pk]))
+    bt = B.Batch(cfgs, seeds)
+    bt.step(cfgs[0]["steps"])
+    grown = 0
+    for k, (c, s) in enumerate(zip(cfgs, seeds)):
+        g = B.Sim(c, *s)
+        p0 = g.patch()
+        g.step(c["steps"])
+        inst = bt.instances[k]
+        assert inst.patch() == g.patch()
+        grown += g.patch() != p0
+        _same(inst, g)
+    print("r = 4 batch: %d of 3 patches grew" % grown, flush=True)
+    assert grown >= 1
