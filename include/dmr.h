@@ -13,9 +13,9 @@
  *   - the one-period E_rms window and the continuity step
  *     dn/dt = div(D_eff grad n) + nu(E_eff) n (Eq. (4), Sec. II.A), every 1/8
  *     of a wave period;
- *   - one r = 2 fine patch over the plasma (Sec. III): two fine substeps per
- *     coarse step, tangential E on the coarse/fine boundary by Eq. (5b),
- *     fine -> coarse transfer after the second substep, density transfers at
+ *   - one fine patch over the plasma (Sec. III), r = 2 or 4: r fine substeps
+ *     per coarse step, tangential E on the coarse/fine boundary by Eq. (5b),
+ *     fine -> coarse transfer after the last substep, density transfers at
  *     each continuity step, and the self-aware growth test of Sec. III.A-D
  *     (threshold and gradient-length flags on square blocks, prefix-sum
  *     compaction, bounding-box growth, Eq. (5a) prolongation); or a fine
