@@ -1,6 +1,6 @@
 """The full Eq. (4) source on the GPU (Townsend ionisation with separate
 attachment, recombination) against the FP64 oracle, on the uniform mesh and
-with a patch; the adjoint refuses this source."""
+with a patch; and the adjoint with the power-law source plus recombination."""
 import numpy as np
 import pytest
 
@@ -46,11 +46,26 @@ def test_townsend_with_patch():
     g.close()
 
 
-@pytest.mark.parametrize("over", [dict(source_model="townsend"), dict(beta_rec=1.0)])
-def test_adjoint_refuses_other_sources(over):
-    cfg = W.make(64, 32, 32, "uniform", 2, **over)
-    sb, _ = W.seeds(cfg)
+def test_adjoint_power_source_with_recombination():
+    """The adjoint with the power-law source and the -r_ei n^2 loss (a dense
+    seed, so that the loss matters) against the FP64 reference adjoint:
+    F, dF/dE0, dF/dA, dF/dbeta within 1e-3, dF/dseed within 1e-3 in
+    relative L2.  (The Townsend source's adjoint is a case of the adjoint
+    tests.)"""
+    from adjoint_cases import CENTRE, reference_gradients, window
+    cfg = W.make(64, 32, 32, "uniform", 10, erms_over_ebd=2.5, beta_rec=1.0)
+    sb, _ = W.seeds(cfg, [CENTRE["uniform"]], [1e20])
+    w = window(cfg, CENTRE["uniform"])
     g = B.Sim(cfg, sb, None)
-    with pytest.raises(B.DmrError, match="EINVAL"):
-        g.record(cfg["steps"], 45)
+    g.record(cfg["steps"], 17)
+    F = g.weighted_sum(w)
+    got = g.backward(w)
     g.close()
+    ref = reference_gradients(cfg, sb, w, None, {})
+    seed = got["seed"].cpu().numpy().astype(np.float64)
+    errs = {k: abs(v - ref[k]) / abs(ref[k]) for k, v in
+            (("F", F), ("E0", got["E0"]), ("A", got["A"]), ("beta", got["beta"]))}
+    errs["seed"] = float(np.linalg.norm(seed - ref["seed"]) / np.linalg.norm(ref["seed"]))
+    print("power + recombination: relative errors vs FP64 %s" % errs, flush=True)
+    for k, v in errs.items():
+        assert v <= 1e-3, (k, v)
