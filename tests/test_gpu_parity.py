@@ -167,3 +167,32 @@ def test_fused_forms_bitwise(r):
         for k, v in runs["combined"].items():
             if k != "patch":
                 assert np.array_equal(v, runs[name][k]), (name, k)
+
+
+def test_patch_tile_widths_bitwise():
+    """The combined step's patch tiles at widths 64, 32 and 16 (the width is
+    picked by patch size; DMR_TW forces one) give the same bits: the width
+    changes which tile computes an entity, not how."""
+    import os
+    cfg = W.make(128, 64, 32, "dynamic", 10, erms_over_ebd=3.0)
+    cfg["regrid_every"] = 2 * cfg["steps_per_period"]
+    sb, sf = W.seeds(cfg, [(80 * LAM / 32, 32 * LAM / 32)], [3e17])
+    runs = {}
+    for tw in ("64", "32", "16"):
+        old = os.environ.get("DMR_TW")
+        os.environ["DMR_TW"] = tw
+        try:
+            g = B.Sim(cfg, sb, sf)
+        finally:
+            if old is None:
+                os.environ.pop("DMR_TW", None)
+            else:
+                os.environ["DMR_TW"] = old
+        g.step(cfg["steps"])
+        runs[tw] = {(f, lv): g.get(f, lv) for lv in (0, 1)
+                    for f in ("hz", "ex", "ey", "jx", "jy", "n", "acc", "ring")}
+        runs[tw]["patch"] = g.patch()
+        g.close()
+    for tw in ("32", "16"):
+        for k, v in runs["64"].items():
+            assert np.array_equal(v, runs[tw][k]) if k != "patch" else v == runs[tw][k], (tw, k)
