@@ -236,7 +236,7 @@ def adjoint_leg(B, W, torch, steps=2000, every=45):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+        print("bench.py: the library runs on one GPU (no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.only_large:
