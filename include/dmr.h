@@ -149,11 +149,11 @@ typedef struct dmr_sim dmr_sim;
  * a run, as dmr_create computes them, in this order: omega = 2 pi f; lambda
  * = c/f; the base level's dx = lambda/cells_per_lambda and dt = S dx/c;
  * nu_m = 5.3e9 p (Sec. II.A); the critical density n_c = m_e eps0 omega^2 /
- * e^2; the effective-field factor 1/(1 + (omega/nu_m)^2) (Eq. (3)); the rms
+ * e^2; the effective-field factor 1/(1 + (omega/nu_m)^2) (Sec. II.A); the rms
  * breakdown field E_bd and the incident amplitude E0 = sqrt 2 (E_rms/E_bd)
  * E_bd; D_e and D_a and the ambipolar density scale of Eq. (4); the base
  * level's Drude decay a = exp(-nu_m dt) and drive b = e^2 (1 - a)/(m_e nu_m)
- * (Eq. (2), both as the kernels receive them in float32); the numerical
+ * (Eq. (3), both as the kernels receive them in float32); the numerical
  * wavenumber of the incident wave (Sec. II.B); the ionisation model's
  * nu_m A (E_cr/p)^beta (float32 product, as the kernels use it); and the base
  * steps per period.  out receives the first min(n_out, 17) of these.
@@ -273,7 +273,7 @@ const char *dmr_last_error(const dmr_sim *s);
  * Gradients of a linear functional of the final density,
  *   F = sum_nodes w_c n_c(t_final) + sum_nodes w_f n_f(t_final)
  * (e.g. the integral of n over a window: w = dx^2 on the window's nodes),
- * with respect to the incident amplitude E0 (Sec. II.C), the ionisation
+ * with respect to the incident amplitude E0 (Sec. II.B), the ionisation
  * coefficients A and beta of nu_i in Eq. (4), and the seed density, through
  * the whole refined update (Eqs. (1)-(5), Sec. III): the exact discrete
  * adjoint of the float32 forward, in float32 with float64 accumulation of

@@ -336,6 +336,70 @@ static double cfb_ex(const orc_sim *s, int P, int J, double frac) {
   return (1.0 - frac) * o + frac * nw;
 }
 
+/* ---- Eq. (5b) on every coarse/fine boundary edge of the fine level ------
+ * The tangential fine E on the boundary comes from the coarse mesh (cfb_ey,
+ * cfb_ex); the boundary current follows Eq. (3) with that field.  Boundary
+ * edges: the patch sides (Ey on its left and right columns, Ex on its bottom
+ * and top rows); for the union of blocks, every level edge with an active
+ * cell on one side only (these lie on block lines, so on coarse lines).
+ * out_ex == NULL drives the edges; otherwise the Eq. (5b) values are only
+ * stored into out_ex / out_ey (level-1 internal layout) and nothing changes. */
+static int ex_has(const orc_sim *s, int P, int Q);
+static int ey_has(const orc_sim *s, int P, int Q);
+static int ex_inner(const orc_sim *s, int P, int Q);
+static int ey_inner(const orc_sim *s, int P, int Q);
+
+static void cfb_edge(level_t *F, double *e, double *j, double en, double ne,
+                     double *out) {
+  if (out) {
+    *out = en;
+    return;
+  }
+  j_only(F, j, *e, en, ne);
+  *e = en;
+}
+
+static void cfb_edges(orc_sim *s, double frac, double *out_ex, double *out_ey) {
+  level_t *F = &s->L1;
+  const int fw = F->nx, fh = F->ny, r = s->p.r;
+  if (s->act) {
+    for (int i = 0; i <= fw; i++)
+      for (int j = 0; j < fh; j++) {
+        if (!ey_has(s, i, j) || ey_inner(s, i, j)) continue;
+        double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i, j + 1));
+        cfb_edge(F, &EY(F, i, j), &JY(F, i, j), cfb_ey(s, i / r, j, frac), ne,
+                 out_ey ? &out_ey[(size_t)i * fh + j] : NULL);
+      }
+    for (int i = 0; i < fw; i++)
+      for (int j = 0; j <= fh; j++) {
+        if (!ex_has(s, i, j) || ex_inner(s, i, j)) continue;
+        double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i + 1, j));
+        cfb_edge(F, &EX(F, i, j), &JX(F, i, j), cfb_ex(s, i, j / r, frac), ne,
+                 out_ex ? &out_ex[(size_t)i * (fh + 1) + j] : NULL);
+      }
+    return;
+  }
+  const int P0 = s->ext[0] * r, Q0 = s->ext[1] * r;
+  for (int j = 0; j < fh; j++) {
+    const int ib[2] = {0, fw}, Ic[2] = {s->ext[0], s->ext[2]};
+    for (int k = 0; k < 2; k++) {
+      int i = ib[k];
+      double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i, j + 1));
+      cfb_edge(F, &EY(F, i, j), &JY(F, i, j), cfb_ey(s, Ic[k], Q0 + j, frac), ne,
+               out_ey ? &out_ey[(size_t)i * fh + j] : NULL);
+    }
+  }
+  for (int i = 0; i < fw; i++) {
+    const int jb[2] = {0, fh}, Jc[2] = {s->ext[1], s->ext[3]};
+    for (int k = 0; k < 2; k++) {
+      int j = jb[k];
+      double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i + 1, j));
+      cfb_edge(F, &EX(F, i, j), &JX(F, i, j), cfb_ex(s, P0 + i, Jc[k], frac), ne,
+               out_ex ? &out_ex[(size_t)i * (fh + 1) + j] : NULL);
+    }
+  }
+}
+
 /* ---- weak fourth-order hyper-diffusion of the fine interior E ----------
  * E <- E - gamma L(L(E)), L the 5-point Laplacian of each component on its
  * own grid, entries outside the patch replaced by the entry itself (zero
@@ -384,8 +448,6 @@ static void fine_filter(orc_sim *s) {
 static void em_step_fine(orc_sim *s, int m) {
   level_t *F = &s->L1;
   const int fw = F->nx, fh = F->ny;
-  const int P0 = s->ext[0] * s->p.r, Q0 = s->ext[1] * s->p.r;
-  const int I0 = s->ext[0], I1 = s->ext[2], J0 = s->ext[1], J1 = s->ext[3];
   const double frac = (double)m / s->p.r;
 
   fine_filter(s);
@@ -410,37 +472,14 @@ static void em_step_fine(orc_sim *s, int m) {
       double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i, j + 1));
       ej_edge(F, &EY(F, i, j), &JY(F, i, j), curl, ne);
     }
-  /* tangential E on the patch boundary from the coarse mesh, Eq. (5b);
-   * the boundary current follows Eq. (3) with that field */
-  for (int j = 0; j < fh; j++) {
-    const int ib[2] = {0, fw}, Ic[2] = {I0, I1};
-    for (int k = 0; k < 2; k++) {
-      int i = ib[k];
-      double eo = EY(F, i, j);
-      double en = cfb_ey(s, Ic[k], Q0 + j, frac);
-      double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i, j + 1));
-      j_only(F, &JY(F, i, j), eo, en, ne);
-      EY(F, i, j) = en;
-    }
-  }
-  for (int i = 0; i < fw; i++) {
-    const int jb[2] = {0, fh}, Jc[2] = {J0, J1};
-    for (int k = 0; k < 2; k++) {
-      int j = jb[k];
-      double eo = EX(F, i, j);
-      double en = cfb_ex(s, P0 + i, Jc[k], frac);
-      double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i + 1, j));
-      j_only(F, &JX(F, i, j), eo, en, ne);
-      EX(F, i, j) = en;
-    }
-  }
+  cfb_edges(s, frac, NULL, NULL);
   accumulate(F, 0, 0);
 }
 
-/* ---- fine -> coarse transfer after the last substep (Sec. III.C: "the
- * fine mesh updated quantities are transferred back"): edge means for E and
- * J, cell and half-level mean for Hz (coarse n+1/2 lies midway between the
- * two fine H levels of the interval) ---------------------------------- */
+/* ---- fine -> coarse transfer after the last substep (Sec. III.C: the
+ * updated fine values go back to the coarse mesh): edge means for E and J,
+ * cell and half-level mean for Hz (coarse n+1/2 lies midway between the two
+ * fine H levels of the interval) ---------------------------------------- */
 static void restrict_patch(orc_sim *s) {
   level_t *C = &s->L0, *F = &s->L1;
   const int r = s->p.r;
@@ -1044,25 +1083,7 @@ static void em_step_fine_union(orc_sim *s, int m) {
       double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i, j + 1));
       ej_edge(F, &EY(F, i, j), &JY(F, i, j), curl, ne);
     }
-  /* boundary edges lie on block lines, so on coarse lines: Eq. (5b) */
-  for (int i = 0; i <= fw; i++)
-    for (int j = 0; j < fh; j++) {
-      if (!ey_has(s, i, j) || ey_inner(s, i, j)) continue;
-      double eo = EY(F, i, j);
-      double en = cfb_ey(s, i / r, j, frac);
-      double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i, j + 1));
-      j_only(F, &JY(F, i, j), eo, en, ne);
-      EY(F, i, j) = en;
-    }
-  for (int i = 0; i < fw; i++)
-    for (int j = 0; j <= fh; j++) {
-      if (!ex_has(s, i, j) || ex_inner(s, i, j)) continue;
-      double eo = EX(F, i, j);
-      double en = cfb_ex(s, i, j / r, frac);
-      double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i + 1, j));
-      j_only(F, &JX(F, i, j), eo, en, ne);
-      EX(F, i, j) = en;
-    }
+  cfb_edges(s, frac, NULL, NULL);
   for (int i = 0; i <= fw; i++)
     for (int j = 0; j <= fh; j++)
       if (nd_has(s, i, j)) NODE(F, acc, i, j) += node_e2_union(s, i, j);
@@ -1111,17 +1132,13 @@ static void restrict_union(orc_sim *s) {
     }
 }
 
-/* continuity on the interior fine nodes; boundary nodes take the coarse
- * density; coarse nodes with all four cells active take the fine density */
-static void sync_union(orc_sim *s) {
+/* density transfers of the union (as transfer_density): the level's
+ * boundary nodes take the coarse density (Eq. (5a) weights: copy at
+ * coincident nodes, mean at mid nodes); coarse nodes with all four cells
+ * active take the fine density */
+static void transfer_density_union(orc_sim *s) {
   level_t *C = &s->L0, *F = &s->L1;
   const int r = s->p.r, fw = F->nx, fh = F->ny;
-  uint8_t *mask = malloc(n_nd(F));
-  for (int i = 0; i <= fw; i++)
-    for (int j = 0; j <= fh; j++)
-      mask[(size_t)i * (fh + 1) + j] = (uint8_t)nd_inner(s, i, j);
-  continuity(s, F, 1, 0, 0, mask);
-  free(mask);
   for (int i = 0; i <= fw; i++)
     for (int j = 0; j <= fh; j++)
       if (nd_has(s, i, j) && !nd_inner(s, i, j))
@@ -1131,6 +1148,19 @@ static void sync_union(orc_sim *s) {
       if (coarse_act(s, i - 1, j - 1) && coarse_act(s, i, j - 1) &&
           coarse_act(s, i - 1, j) && coarse_act(s, i, j))
         NODE(C, n, i, j) = NODE(F, n, r * i, r * j);
+}
+
+/* continuity on the interior fine nodes, then the density transfers */
+static void sync_union(orc_sim *s) {
+  level_t *F = &s->L1;
+  const int fw = F->nx, fh = F->ny;
+  uint8_t *mask = malloc(n_nd(F));
+  for (int i = 0; i <= fw; i++)
+    for (int j = 0; j <= fh; j++)
+      mask[(size_t)i * (fh + 1) + j] = (uint8_t)nd_inner(s, i, j);
+  continuity(s, F, 1, 0, 0, mask);
+  free(mask);
+  transfer_density_union(s);
 }
 
 /* Add blocks to the fine level (growth only, Sec. III.D).  Entities new to
@@ -1523,6 +1553,84 @@ int orc_get_regrid(const orc_sim *s, uint8_t *flags, int32_t *scan,
 int orc_time(const orc_sim *s, double *t, int64_t *step) {
   if (t) *t = (double)s->step * s->L0.dt;
   if (step) *step = s->step;
+  return 0;
+}
+
+/* ---- test hooks: the coarse/fine transfers on the current layout -------
+ * These expose the interface operators of Sec. III.C to the pins (exactness
+ * on fields linear in space and time); the time stepping does not use them.
+ * Arrays are in the public layout of the field calls. */
+
+/* coarse E^n that Eq. (5b) interpolates from (base level, EX and EY) */
+int orc_set_old_e(orc_sim *s, const double *ex, const double *ey) {
+  if (!s || !ex || !ey) return -1;
+  const level_t *C = &s->L0;
+  for (int j = 0; j <= C->ny; j++)
+    for (int i = 0; i < C->nx; i++)
+      s->ex_old[(size_t)i * (C->ny + 1) + j] = ex[(size_t)j * C->nx + i];
+  for (int j = 0; j < C->ny; j++)
+    for (int i = 0; i <= C->nx; i++)
+      s->ey_old[(size_t)i * C->ny + j] = ey[(size_t)j * (C->nx + 1) + i];
+  return 0;
+}
+
+/* Eq. (5b) values at time fraction frac on every boundary edge of the fine
+ * level (level-1 EX / EY layout); every other entry is set to NaN.  The
+ * level's own fields are not changed. */
+int orc_cfb_fill(orc_sim *s, double frac, double *ex, double *ey) {
+  view_t v;
+  if (!s || !ex || !ey || view_of(s, 1, &v)) return -1;
+  const level_t *F = &s->L1;
+  double *tx = malloc(n_ex(F) * sizeof(double)), *ty = malloc(n_ey(F) * sizeof(double));
+  if (!tx || !ty) {
+    free(tx);
+    free(ty);
+    return -2;
+  }
+  for (size_t k = 0; k < n_ex(F); k++) tx[k] = NAN;
+  for (size_t k = 0; k < n_ey(F); k++) ty[k] = NAN;
+  cfb_edges(s, frac, tx, ty);
+  for (int j = 0; j <= v.ny; j++)
+    for (int i = 0; i < v.nx; i++)
+      ex[(size_t)j * v.nx + i] = tx[(size_t)(v.i0 + i) * (F->ny + 1) + v.j0 + j];
+  for (int j = 0; j < v.ny; j++)
+    for (int i = 0; i <= v.nx; i++)
+      ey[(size_t)j * (v.nx + 1) + i] = ty[(size_t)(v.i0 + i) * F->ny + v.j0 + j];
+  free(tx);
+  free(ty);
+  return 0;
+}
+
+/* the two fine Hz half levels the fine -> coarse transfer averages (level-1
+ * HZ layout): lo after substep r/2; hi after substep r/2 + 1, which for
+ * r = 2 is the level's own Hz (written there) */
+int orc_set_hz_halves(orc_sim *s, const double *lo, const double *hi) {
+  view_t v;
+  if (!s || !lo || !hi || view_of(s, 1, &v)) return -1;
+  level_t *F = &s->L1;
+  double *dst_hi = s->p.r == 2 ? F->hz : s->hz_hi;
+  for (int j = 0; j < v.ny; j++)
+    for (int i = 0; i < v.nx; i++) {
+      size_t a = (size_t)(v.i0 + i) * F->ny + v.j0 + j, b = (size_t)j * v.nx + i;
+      s->hz_lo[a] = lo[b];
+      dst_hi[a] = hi[b];
+    }
+  return 0;
+}
+
+/* the fine -> coarse transfer of the end of a base step */
+int orc_restrict(orc_sim *s) {
+  if (!s || !s->has_patch) return -1;
+  if (s->act) restrict_union(s);
+  else restrict_patch(s);
+  return 0;
+}
+
+/* the density transfers of a sync point (without its continuity steps) */
+int orc_transfer_density(orc_sim *s) {
+  if (!s || !s->has_patch) return -1;
+  if (s->act) transfer_density_union(s);
+  else transfer_density(s);
   return 0;
 }
 

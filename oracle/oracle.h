@@ -122,6 +122,19 @@ int orc_time(const orc_sim *s, double *t, int64_t *step);
  * the margins is an error) / read the active blocks */
 int orc_add_blocks(orc_sim *s, const uint8_t *mask);
 int orc_get_blocks(const orc_sim *s, uint8_t *dst);
+/* Test hooks: the coarse/fine transfers of Sec. III.C on the current layout,
+ * for the pins (arrays in the field-call layout; see the source):
+ * orc_set_old_e sets the coarse E^n that Eq. (5b) interpolates from;
+ * orc_cfb_fill writes the Eq. (5b) values at time fraction frac on the fine
+ * level's boundary edges (NaN elsewhere) without changing the level;
+ * orc_set_hz_halves sets the two fine Hz half levels the fine -> coarse
+ * transfer averages; orc_restrict runs that transfer; orc_transfer_density
+ * runs the density transfers of a sync point. */
+int orc_set_old_e(orc_sim *s, const double *ex, const double *ey);
+int orc_cfb_fill(orc_sim *s, double frac, double *ex, double *ey);
+int orc_set_hz_halves(orc_sim *s, const double *lo, const double *hi);
+int orc_restrict(orc_sim *s);
+int orc_transfer_density(orc_sim *s);
 /* derived scalars, for pins: see orc_derived in the source */
 int orc_derived(const orc_params *p, double *out, int n_out);
 /* net ionisation rate for a given E_rms^2 (V^2/m^2) */

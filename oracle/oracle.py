@@ -85,6 +85,11 @@ def lib():
         L.orc_time.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int64)]
         L.orc_add_blocks.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_get_blocks.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_set_old_e.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_cfb_fill.argtypes = [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]
+        L.orc_set_hz_halves.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_restrict.argtypes = [C.c_void_p]
+        L.orc_transfer_density.argtypes = [C.c_void_p]
         L.orc_derived.argtypes = [P(OrcParams), P(C.c_double), C.c_int]
         L.orc_nu_net.argtypes = [P(OrcParams), C.c_double]
         L.orc_nu_net.restype = C.c_double
@@ -255,3 +260,43 @@ class Sim:
         st = C.c_int64()
         lib().orc_time(self._h, C.byref(t), C.byref(st))
         return t.value, st.value
+
+    # -- test hooks: the coarse/fine transfers of Sec. III.C on the current
+    # layout (arrays in the field-call layout) --------------------------------
+    def _arr(self, field, level, a):
+        r, c = self.dims(field, level)
+        a = np.ascontiguousarray(a, np.float64)
+        if a.shape != (r, c):
+            raise ValueError("%s level %d: shape %s, expected %s" % (field, level, a.shape, (r, c)))
+        return a
+
+    def set_old_e(self, ex, ey):
+        """Coarse E^n that Eq. (5b) interpolates from (base-level EX, EY)."""
+        ex, ey = self._arr("ex", 0, ex), self._arr("ey", 0, ey)
+        if lib().orc_set_old_e(self._h, _ptr(ex), _ptr(ey)):
+            raise RuntimeError("orc_set_old_e failed")
+
+    def cfb_fill(self, frac):
+        """Eq. (5b) values at time fraction frac on the fine level's boundary
+        edges, NaN elsewhere: (EX, EY) of level 1."""
+        ex = np.empty(self.dims("ex", 1))
+        ey = np.empty(self.dims("ey", 1))
+        if lib().orc_cfb_fill(self._h, float(frac), _ptr(ex), _ptr(ey)):
+            raise RuntimeError("orc_cfb_fill failed")
+        return ex, ey
+
+    def set_hz_halves(self, lo, hi):
+        """The two fine Hz half levels the fine -> coarse transfer averages."""
+        lo, hi = self._arr("hz", 1, lo), self._arr("hz", 1, hi)
+        if lib().orc_set_hz_halves(self._h, _ptr(lo), _ptr(hi)):
+            raise RuntimeError("orc_set_hz_halves failed")
+
+    def restrict(self):
+        """Run the fine -> coarse transfer of the end of a base step."""
+        if lib().orc_restrict(self._h):
+            raise RuntimeError("orc_restrict failed")
+
+    def transfer_density(self):
+        """Run the density transfers of a sync point (no continuity step)."""
+        if lib().orc_transfer_density(self._h):
+            raise RuntimeError("orc_transfer_density failed")

@@ -9,7 +9,6 @@ dF/dA and dF/dbeta.  Every step of both sweeps runs in libdmr.so.
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
 
 from . import binding as B
@@ -28,8 +27,9 @@ class WindowDensity(torch.autograd.Function):
         F = sim.weighted_sum(weights, 0)
         ctx.sim, ctx.weights = sim, weights
         ctx.seed_dtype, ctx.seed_device = seed.dtype, seed.device
-        # E0 of this run per unit e0_scale
-        ctx.e0_unit = e0_of(cfg)
+        # peak incident amplitude of cfg (V/m) per unit e0_scale, as the
+        # library derives it
+        ctx.e0_unit = B.derived(cfg)["E0"]
         return torch.tensor(F, dtype=torch.float64)
 
     @staticmethod
@@ -41,11 +41,3 @@ class WindowDensity(torch.autograd.Function):
         return (gseed, f64(g["E0"] * ctx.e0_unit), f64(g["A"]), f64(g["beta"]),
                 None, None, None, None, None)
 
-
-def e0_of(cfg) -> float:
-    """Peak incident amplitude (V/m) of cfg: sqrt(2) E_rms with
-    E_rms = ratio * E_cr sqrt(1 + w^2/nu_m^2) (Sec. II.A, II.C)."""
-    w = 2 * np.pi * cfg["freq_hz"]
-    num = 5.3e9 * cfg["p_torr"]
-    ecr = cfg["ecr_over_p"] * 100.0 * cfg["p_torr"]
-    return float(np.sqrt(2.0) * cfg["erms_over_ebd"] * ecr * np.sqrt(1.0 + (w / num) ** 2))

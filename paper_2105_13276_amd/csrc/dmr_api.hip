@@ -1916,7 +1916,7 @@ int dmr_backward(dmr_sim* s, const void* d_tape, const float* d_w_coarse,
   if (e == hipSuccess && ref && d_w_fine)
     e = launch_scatter(d_w_fine, r * p.nx + 1, r * p.ny + 1, 1.f, af.n, F.pitch, 0, 0, s->st);
   if (e != hipSuccess) return hipfail(s, e, "weights launch");
-  // incident values per unit amplitude, E0 g sin(...) / E0 (Sec. II.C)
+  // incident values per unit amplitude, E0 g sin(...) / E0 (Sec. II.B)
   {
     std::vector<double> u((size_t)2 * tp.steps, 0.0);
     if (p.tfsf_i > 0) {
@@ -2057,38 +2057,79 @@ int dmr_save(dmr_sim* s, void* dst, size_t bytes, int dst_on_device) {
 
 int dmr_load(dmr_sim* s, const void* src, size_t bytes, int src_on_device) {
   if (!s || !src) return DMR_EINVAL;
+  const dmr_params& p = s->p;
   const size_t need = state_bytes(s);
   if (bytes < need) return fail(s, DMR_ENOMEM, "state needs %zu bytes", need);
   if (src_on_device && ((uintptr_t)src & 255))
     return fail(s, DMR_EINVAL, "device state buffer must be 256-byte aligned");
   StateHeader h{};
+  const char* map = (const char*)src + state_map_offset(s);
+  std::vector<uint8_t> act;
+  if (s->uni) act.resize(s->h_act.size());
   if (src_on_device) {
     HIPCHK(s, hipStreamSynchronize(s->st));
     HIPCHK(s, hipMemcpy(&h, src, sizeof(h), hipMemcpyDeviceToHost));
+    if (s->uni) HIPCHK(s, hipMemcpy(act.data(), map, act.size(), hipMemcpyDeviceToHost));
   } else {
     memcpy(&h, src, sizeof(h));
+    if (s->uni) memcpy(act.data(), map, act.size());
   }
   if (memcmp(h.magic, "DMRSTATE", 8) != 0 || h.version != 1 || h.header_bytes != kStateHeader)
     return fail(s, DMR_EINVAL, "not a saved state");
-  if (h.params_hash != params_hash(s->p) || h.total_bytes != need)
+  if (h.params_hash != params_hash(p) || h.total_bytes != need)
     return fail(s, DMR_EINVAL, "saved state belongs to other parameters");
-  if (h.has_patch && !refined(&s->p)) return fail(s, DMR_EINVAL, "saved state has a patch");
+  // every field of the header is checked before the handle changes: the
+  // extents decide which fine rows the copy below writes
+  if (h.step < 0 || h.blocks < 0 || (h.has_patch != 0 && h.has_patch != 1) ||
+      (h.ty1 != 4 && h.ty1 != 8 && h.ty1 != 16))
+    return fail(s, DMR_EINVAL, "saved state header out of range");
+  if (h.has_patch && !refined(&p)) return fail(s, DMR_EINVAL, "saved state has a patch");
+  if (h.has_patch) {
+    const int* e = h.ext;
+    const int Bk = p.block;
+    const int xmin = p.mode == DMR_STATIC ? std::max(1, p.tfsf_i + 1) : block_xmin(p) * Bk;
+    if (e[0] < xmin || e[1] < 1 || e[2] > p.nx - 1 || e[3] > p.ny - 1 || e[0] >= e[2] ||
+        e[1] >= e[3])
+      return fail(s, DMR_EINVAL, "saved patch extents outside the allowed region");
+    if (p.mode == DMR_STATIC && !s->uni && memcmp(e, p.static_ext, sizeof(h.ext)) != 0)
+      return fail(s, DMR_EINVAL, "saved patch differs from static_ext");
+    if ((s->uni || p.regrid_rule == DMR_RULE_BLOCKS) && p.mode == DMR_DYNAMIC &&
+        (e[0] % Bk || e[1] % Bk || e[2] % Bk || e[3] % Bk))
+      return fail(s, DMR_EINVAL, "saved patch extents are not on the block grid");
+  }
+  if (s->uni) {
+    // the block map: active blocks inside the margins, bounding box = extents
+    const int NBx = p.nx / p.block, NBy = p.ny / p.block, xmin = block_xmin(p);
+    int bb[4] = {NBx, NBy, 0, 0};
+    for (int b = 0; b < NBx * NBy; b++) {
+      if (act[b] > 1) return fail(s, DMR_EINVAL, "saved block map entry %d not 0/1", b);
+      if (!act[b]) continue;
+      const int bx = b % NBx, by = b / NBx;
+      if (bx < xmin || by < 1 || bx > NBx - 2 || by > NBy - 2)
+        return fail(s, DMR_EINVAL, "saved block %d outside the margins", b);
+      bb[0] = std::min(bb[0], bx); bb[1] = std::min(bb[1], by);
+      bb[2] = std::max(bb[2], bx + 1); bb[3] = std::max(bb[3], by + 1);
+    }
+    const bool any = bb[2] > bb[0];
+    if (any != (h.has_patch != 0) ||
+        (any && (bb[0] * p.block != h.ext[0] || bb[1] * p.block != h.ext[1] ||
+                 bb[2] * p.block != h.ext[2] || bb[3] * p.block != h.ext[3])))
+      return fail(s, DMR_EINVAL, "saved block map does not match the saved extents");
+  }
   s->step = h.step; s->blocks = h.blocks; s->has_patch = h.has_patch != 0;
   for (int q = 0; q < 4; q++) s->ext[q] = h.ext[q];
   s->ty1 = h.ty1;
   s->tape.valid = false;  // a recorded run no longer describes this state
   float* body = (float*)((char*)src + kStateHeader);
-  const char* map = (const char*)src + state_map_offset(s);
   if (src_on_device) {
     if (int rc = ck_copy(s, body, false)) return rc;
-    if (s->uni)
-      HIPCHK(s, hipMemcpyAsync(s->h_act.data(), map, s->h_act.size(), hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
   } else {
     if (int rc = state_host_copy(s, body, false)) return rc;
-    if (s->uni) memcpy(s->h_act.data(), map, s->h_act.size());
   }
-  return s->uni ? union_install(s) : DMR_OK;
+  if (!s->uni) return DMR_OK;
+  memcpy(s->h_act.data(), act.data(), act.size());
+  return union_install(s);
 }
 
 int dmr_weighted_sum(dmr_sim* s, int level, const float* d_w, double* out) {

@@ -9,6 +9,7 @@ are noise-limited (~eps32/h), so they are reported with a loose bound."""
 import numpy as np
 import pytest
 
+from oracle import oracle as O
 from paper_2105_13276_amd import binding as B
 from paper_2105_13276_amd import workloads as W
 
@@ -93,8 +94,7 @@ def test_central_differences_fp32_reported():
         fd = (8 * (f[1] - f[-1]) - (f[2] - f[-2])) / (12 * h * cfg[key])
         ad = got[name]
         if name == "E0":
-            from paper_2105_13276_amd.adjoint import e0_of
-            ad = got["E0"] * e0_of(cfg) / cfg["erms_over_ebd"]
+            ad = got["E0"] * O.derived(cfg)["E0"] / cfg["erms_over_ebd"]
         print("FD %s: adjoint %.6e  FP32 central difference %.6e  rel %.2e"
               % (name, ad, fd, _rel(ad, fd)), flush=True)
         assert _rel(ad, fd) < 5e-2
@@ -114,8 +114,8 @@ def test_autograd_function():
     _, got = _gpu(cfg, sb, w, every=45)
     assert F.item() == pytest.approx(got["F"], rel=1e-12)
     assert np.array_equal(seed.grad.numpy(), got["seed"])
-    from paper_2105_13276_amd.adjoint import e0_of
-    assert s.grad.item() == pytest.approx(got["E0"] * e0_of(cfg), rel=1e-12)
+    # the peak amplitude per unit scale, from the oracle's derivation
+    assert s.grad.item() == pytest.approx(got["E0"] * O.derived(cfg)["E0"], rel=1e-12)
     assert A.grad.item() == pytest.approx(got["A"], rel=1e-12)
     assert beta.grad.item() == pytest.approx(got["beta"], rel=1e-12)
 

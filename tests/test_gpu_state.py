@@ -116,3 +116,58 @@ def test_union_restart_equals_uninterrupted_run():
     assert np.array_equal(h.blocks(), g.blocks())
     g.close()
     h.close()
+
+
+def test_load_checks_the_header_before_changing_the_handle():
+    """A saved state whose header names extents outside the domain, off the
+    block grid, a bad tile height, or (union level) a block map that does not
+    match its extents is refused with EINVAL, and the handle keeps its own
+    state (the extents decide which fine rows a load writes)."""
+    import struct
+    cfg, sb = _case()
+    g = B.Sim(cfg, sb, None)
+    g.step(24)
+    buf = g.save()
+    before = _snapshot(g)
+    # StateHeader: magic[8], version, header_bytes (u32), params_hash,
+    # total_bytes (u64), step, blocks (i64), has_patch, ext[4], ty1 (i32)
+    off_ext = 8 + 4 + 4 + 8 + 8 + 8 + 8 + 4
+    off_ty1 = off_ext + 16
+    bad = []
+    # outside the domain, off the block grid, negative, inverted
+    for ext in ((32, 16, 112, 32), (32, 16, 40, 32), (-16, 16, 32, 32), (48, 16, 32, 32)):
+        b = buf.copy()
+        b[off_ext:off_ext + 16] = np.frombuffer(struct.pack("<4i", *ext), np.uint8)
+        bad.append(b)
+    b = buf.copy()
+    b[off_ty1:off_ty1 + 4] = np.frombuffer(struct.pack("<i", 5), np.uint8)
+    bad.append(b)
+    for b in bad:
+        with pytest.raises(B.DmrError, match="EINVAL"):
+            g.load(b)
+        _same(_snapshot(g), before)
+    g.close()
+
+
+def test_union_load_checks_the_block_map():
+    cfg = W.make(128, 64, 32, "dynamic", 2, block=8, erms_over_ebd=3.0, regrid_rule="union")
+    dx = LAM / 32
+    sb, sf = W.seeds(cfg, [(46.5 * dx, 21 * dx)], [3e17])
+    g = B.Sim(cfg, sb, sf)
+    g.step(16)
+    buf = g.save()
+    before = _snapshot(g)
+    nbx, nby = 128 // 8, 64 // 8
+    map0 = len(buf) - ((nbx * nby + 255) // 256) * 256
+    assert np.array_equal(buf[map0:map0 + nbx * nby].reshape(nby, nbx), g.blocks())
+    for b_id in (0, nbx * nby - 1, 5 * nbx + 9):
+        # a block on the outer margin; a block inside the margins but away
+        # from the saved extents
+        b = buf.copy()
+        if b[map0 + b_id]:
+            continue
+        b[map0 + b_id] = 1
+        with pytest.raises(B.DmrError, match="EINVAL"):
+            g.load(b)
+        _same(_snapshot(g), before)
+    g.close()
