@@ -3,7 +3,10 @@
  *
  * Plain loops, one array per quantity, no blocking or fusion.  Every
  * function names the part of the paper it follows.  Where the paper is
- * silent the reading used is stated at the function.
+ * silent the reading used is stated at the function.  Loops whose
+ * iterations update distinct entities from values no iteration writes are
+ * marked for OpenMP worker threads; each entity is computed by the same
+ * operations whatever the thread count, so results are bit-identical.
  *
  * Storage (private to this file): column-major in the sense a[i][j] with j
  * fastest; Hz[nx][ny], Ex[nx][ny+1], Ey[nx+1][ny], nodes [nx+1][ny+1].
@@ -13,6 +16,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* CODATA 2018 SI constants (the paper prints none). */
 static const double Q_E = 1.602176634e-19;
@@ -209,6 +215,7 @@ static double node_e2(const level_t *L, int i, int j, int perx, int pery) {
 }
 
 static void accumulate(level_t *L, int perx, int pery) {
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i <= L->nx; i++)
     for (int j = 0; j <= L->ny; j++) {
       if ((perx && i == L->nx) || (pery && j == L->ny)) continue;
@@ -238,6 +245,7 @@ static void em_step_base(orc_sim *s) {
   memcpy(s->hz_prev, L->hz, n_hz(L) * sizeof(double));
 
   /* Faraday, Eq. (2): dHz/dt = -(dEy/dx - dEx/dy)/mu0 */
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < nx; i++)
     for (int j = 0; j < ny; j++)
       HZ(L, i, j) -= L->ch * ((EY(L, i + 1, j) - EY(L, i, j)) -
@@ -246,6 +254,7 @@ static void em_step_base(orc_sim *s) {
     for (int j = 0; j < ny; j++) HZ(L, is - 1, j) += L->ch * ey_inc(s, xs, t);
 
   /* Ampere with current, Eq. (1), and Drude current, Eq. (3) */
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < nx; i++)
     for (int j = (pery ? 0 : 1); j < ny; j++) {
       int jm = j > 0 ? j - 1 : ny - 1;
@@ -253,6 +262,7 @@ static void em_step_base(orc_sim *s) {
       double ne = 0.5 * (NODE(L, n, i, j) + NODE(L, n, i + 1, j));
       ej_edge(L, &EX(L, i, j), &JX(L, i, j), curl, ne);
     }
+  #pragma omp parallel for schedule(static)
   for (int i = (perx ? 0 : 1); i < nx; i++)
     for (int j = 0; j < ny; j++) {
       int im = i > 0 ? i - 1 : nx - 1;
@@ -363,6 +373,7 @@ static void cfb_edges(orc_sim *s, double frac, double *out_ex, double *out_ey) {
   level_t *F = &s->L1;
   const int fw = F->nx, fh = F->ny, r = s->p.r;
   if (s->act) {
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i <= fw; i++)
       for (int j = 0; j < fh; j++) {
         if (!ey_has(s, i, j) || ey_inner(s, i, j)) continue;
@@ -370,6 +381,7 @@ static void cfb_edges(orc_sim *s, double frac, double *out_ex, double *out_ey) {
         cfb_edge(F, &EY(F, i, j), &JY(F, i, j), cfb_ey(s, i / r, j, frac), ne,
                  out_ey ? &out_ey[(size_t)i * fh + j] : NULL);
       }
+    #pragma omp parallel for schedule(static)
     for (int i = 0; i < fw; i++)
       for (int j = 0; j <= fh; j++) {
         if (!ex_has(s, i, j) || ex_inner(s, i, j)) continue;
@@ -411,6 +423,7 @@ static void cfb_edges(orc_sim *s, double frac, double *out_ex, double *out_ey) {
  * across: the growth returns after some hundred periods) and damps a
  * wavelength of 64 fine cells by ~1e-7 per substep. */
 static void lap_grid(const double *a, double *out, int ni, int nj) {
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < ni; i++)
     for (int j = 0; j < nj; j++) {
       double c = a[(size_t)i * nj + j];
@@ -433,11 +446,13 @@ static void fine_filter(orc_sim *s) {
   /* Ex grid: fw x (fh+1), interior rows 1..fh-1 */
   lap_grid(F->ex, t1, fw, fh + 1);
   lap_grid(t1, t2, fw, fh + 1);
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < fw; i++)
     for (int j = 1; j < fh; j++) EX(F, i, j) -= g * t2[(size_t)i * (fh + 1) + j];
   /* Ey grid: (fw+1) x fh, interior columns 1..fw-1 */
   lap_grid(F->ey, t1, fw + 1, fh);
   lap_grid(t1, t2, fw + 1, fh);
+  #pragma omp parallel for schedule(static)
   for (int i = 1; i < fw; i++)
     for (int j = 0; j < fh; j++) EY(F, i, j) -= g * t2[(size_t)i * fh + j];
   free(t1);
@@ -452,6 +467,7 @@ static void em_step_fine(orc_sim *s, int m) {
 
   fine_filter(s);
 
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < fw; i++)
     for (int j = 0; j < fh; j++)
       HZ(F, i, j) -= F->ch * ((EY(F, i + 1, j) - EY(F, i, j)) -
@@ -460,12 +476,14 @@ static void em_step_fine(orc_sim *s, int m) {
   if (m == s->p.r / 2 + 1 && m < s->p.r)
     memcpy(s->hz_hi, F->hz, n_hz(F) * sizeof(double));
 
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < fw; i++)
     for (int j = 1; j < fh; j++) {
       double curl = (HZ(F, i, j) - HZ(F, i, j - 1)) / F->dx;
       double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i + 1, j));
       ej_edge(F, &EX(F, i, j), &JX(F, i, j), curl, ne);
     }
+  #pragma omp parallel for schedule(static)
   for (int i = 1; i < fw; i++)
     for (int j = 0; j < fh; j++) {
       double curl = -(HZ(F, i, j) - HZ(F, i - 1, j)) / F->dx;
@@ -486,6 +504,7 @@ static void restrict_patch(orc_sim *s) {
   const int I0 = s->ext[0], J0 = s->ext[1], I1 = s->ext[2], J1 = s->ext[3];
   const int fh = F->ny;
   const double *hi = r == 2 ? F->hz : s->hz_hi;
+  #pragma omp parallel for schedule(static)
   for (int i = I0; i < I1; i++)
     for (int j = J0; j < J1; j++) {
       int p = r * (i - I0), q = r * (j - J0);
@@ -496,6 +515,7 @@ static void restrict_patch(orc_sim *s) {
                         hi[(size_t)(p + a) * fh + q + b]);
       HZ(C, i, j) = sum / (r * r);
     }
+  #pragma omp parallel for schedule(static)
   for (int i = I0; i < I1; i++)
     for (int j = J0 + 1; j < J1; j++) {
       int p = r * (i - I0), q = r * (j - J0);
@@ -507,6 +527,7 @@ static void restrict_patch(orc_sim *s) {
       EX(C, i, j) = se / r;
       JX(C, i, j) = sj / r;
     }
+  #pragma omp parallel for schedule(static)
   for (int i = I0 + 1; i < I1; i++)
     for (int j = J0; j < J1; j++) {
       int p = r * (i - I0), q = r * (j - J0);
@@ -561,6 +582,7 @@ double orc_d_eff(const orc_params *p, double n) {
 
 /* close one window block: its mean square field goes into the ring */
 static void close_block(level_t *L, int slot) {
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i <= L->nx; i++)
     for (int j = 0; j <= L->ny; j++) {
       RING(L, slot, i, j) = NODE(L, acc, i, j) / L->spp;
@@ -586,6 +608,7 @@ static void continuity_core(const orc_params *p, int nx, int ny, double dx,
 #define AT(arr, i, j) arr[(size_t)(i) * (ny + 1) + (j)]
   const double r_ei = orc_r_ei(p);
   memcpy(nout, nold, (size_t)(nx + 1) * (ny + 1) * sizeof(double));
+  #pragma omp parallel for schedule(static)
   for (int i = ilo; i <= ihi; i++)
     for (int j = jlo; j <= jhi; j++) {
       if ((perx && i == nx) || (pery && j == ny)) continue;
@@ -627,6 +650,7 @@ static void continuity(orc_sim *s, level_t *L, int interior_only, int perx,
   double *nold = malloc(n_nd(L) * sizeof(double));
   double *e2 = malloc(n_nd(L) * sizeof(double));
   memcpy(nold, L->n, n_nd(L) * sizeof(double));
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i <= nx; i++)
     for (int j = 0; j <= ny; j++) e2[(size_t)i * (ny + 1) + j] = erms2_at(L, i, j);
   if (interior_only)
@@ -687,6 +711,7 @@ static void transfer_density(orc_sim *s) {
   const int r = s->p.r;
   const int P0 = r * s->ext[0], Q0 = r * s->ext[1];
   const int fw = F->nx, fh = F->ny;
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i <= fw; i++)
     for (int j = 0; j <= fh; j++) {
       if (i != 0 && i != fw && j != 0 && j != fh) continue;
@@ -991,6 +1016,7 @@ static int coarse_act(const orc_sim *s, int I, int J) {
 static void lap_union(const orc_sim *s, const double *a, double *out, int ni,
                       int nj, int kind) {
 #define HAS(i, j) (kind ? ey_has(s, i, j) : ex_has(s, i, j))
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < ni; i++)
     for (int j = 0; j < nj; j++) {
       if (!HAS(i, j)) {
@@ -1017,11 +1043,13 @@ static void fine_filter_union(orc_sim *s) {
   double *t1 = malloc(nmax * sizeof(double)), *t2 = malloc(nmax * sizeof(double));
   lap_union(s, F->ex, t1, fw, fh + 1, 0);
   lap_union(s, t1, t2, fw, fh + 1, 0);
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < fw; i++)
     for (int j = 1; j < fh; j++)
       if (ex_inner(s, i, j)) EX(F, i, j) -= g * t2[(size_t)i * (fh + 1) + j];
   lap_union(s, F->ey, t1, fw + 1, fh, 1);
   lap_union(s, t1, t2, fw + 1, fh, 1);
+  #pragma omp parallel for schedule(static)
   for (int i = 1; i < fw; i++)
     for (int j = 0; j < fh; j++)
       if (ey_inner(s, i, j)) EY(F, i, j) -= g * t2[(size_t)i * fh + j];
@@ -1061,6 +1089,7 @@ static void em_step_fine_union(orc_sim *s, int m) {
 
   fine_filter_union(s);
 
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < fw; i++)
     for (int j = 0; j < fh; j++)
       if (cact(s, i, j))
@@ -1069,6 +1098,7 @@ static void em_step_fine_union(orc_sim *s, int m) {
   if (m == r / 2) memcpy(s->hz_lo, F->hz, n_hz(F) * sizeof(double));
   if (m == r / 2 + 1 && m < r) memcpy(s->hz_hi, F->hz, n_hz(F) * sizeof(double));
 
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < fw; i++)
     for (int j = 1; j < fh; j++) {
       if (!ex_inner(s, i, j)) continue;
@@ -1076,6 +1106,7 @@ static void em_step_fine_union(orc_sim *s, int m) {
       double ne = 0.5 * (NODE(F, n, i, j) + NODE(F, n, i + 1, j));
       ej_edge(F, &EX(F, i, j), &JX(F, i, j), curl, ne);
     }
+  #pragma omp parallel for schedule(static)
   for (int i = 1; i < fw; i++)
     for (int j = 0; j < fh; j++) {
       if (!ey_inner(s, i, j)) continue;
@@ -1084,6 +1115,7 @@ static void em_step_fine_union(orc_sim *s, int m) {
       ej_edge(F, &EY(F, i, j), &JY(F, i, j), curl, ne);
     }
   cfb_edges(s, frac, NULL, NULL);
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i <= fw; i++)
     for (int j = 0; j <= fh; j++)
       if (nd_has(s, i, j)) NODE(F, acc, i, j) += node_e2_union(s, i, j);
@@ -1095,6 +1127,7 @@ static void restrict_union(orc_sim *s) {
   level_t *C = &s->L0, *F = &s->L1;
   const int r = s->p.r, fh = F->ny;
   const double *hi = r == 2 ? F->hz : s->hz_hi;
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < C->nx; i++)
     for (int j = 0; j < C->ny; j++) {
       if (!coarse_act(s, i, j)) continue;
@@ -1106,6 +1139,7 @@ static void restrict_union(orc_sim *s) {
                         hi[(size_t)(p + a) * fh + q + b]);
       HZ(C, i, j) = sum / (r * r);
     }
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i < C->nx; i++)
     for (int j = 1; j < C->ny; j++) {
       if (!coarse_act(s, i, j) || !coarse_act(s, i, j - 1)) continue;
@@ -1118,6 +1152,7 @@ static void restrict_union(orc_sim *s) {
       EX(C, i, j) = se / r;
       JX(C, i, j) = sj / r;
     }
+  #pragma omp parallel for schedule(static)
   for (int i = 1; i < C->nx; i++)
     for (int j = 0; j < C->ny; j++) {
       if (!coarse_act(s, i, j) || !coarse_act(s, i - 1, j)) continue;
@@ -1139,10 +1174,12 @@ static void restrict_union(orc_sim *s) {
 static void transfer_density_union(orc_sim *s) {
   level_t *C = &s->L0, *F = &s->L1;
   const int r = s->p.r, fw = F->nx, fh = F->ny;
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i <= fw; i++)
     for (int j = 0; j <= fh; j++)
       if (nd_has(s, i, j) && !nd_inner(s, i, j))
         NODE(F, n, i, j) = bilin(C->n, C->ny + 1, (double)i / r, (double)j / r);
+  #pragma omp parallel for schedule(static)
   for (int i = 1; i < C->nx; i++)
     for (int j = 1; j < C->ny; j++)
       if (coarse_act(s, i - 1, j - 1) && coarse_act(s, i, j - 1) &&
@@ -1155,6 +1192,7 @@ static void sync_union(orc_sim *s) {
   level_t *F = &s->L1;
   const int fw = F->nx, fh = F->ny;
   uint8_t *mask = malloc(n_nd(F));
+  #pragma omp parallel for schedule(static)
   for (int i = 0; i <= fw; i++)
     for (int j = 0; j <= fh; j++)
       mask[(size_t)i * (fh + 1) + j] = (uint8_t)nd_inner(s, i, j);
@@ -1651,4 +1689,23 @@ int orc_derived(const orc_params *p, double *out, int n_out) {
                   s.nu_att, p->cells_per_lambda / p->courant};
   for (int k = 0; k < n_out && k < 17; k++) out[k] = v[k];
   return 0;
+}
+
+/* worker threads of the marked loops; n <= 0: all processors */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
+int orc_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

@@ -135,6 +135,11 @@ int orc_cfb_fill(orc_sim *s, double frac, double *ex, double *ey);
 int orc_set_hz_halves(orc_sim *s, const double *lo, const double *hi);
 int orc_restrict(orc_sim *s);
 int orc_transfer_density(orc_sim *s);
+/* OpenMP worker threads of the loops over independent entities (results are
+ * bit-identical for any count); n <= 0: all processors.  Both return the
+ * count in use (1 in a build without OpenMP). */
+int orc_set_threads(int n);
+int orc_get_threads(void);
 /* derived scalars, for pins: see orc_derived in the source */
 int orc_derived(const orc_params *p, double *out, int n_out);
 /* net ionisation rate for a given E_rms^2 (V^2/m^2) */

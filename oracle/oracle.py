@@ -49,13 +49,14 @@ class OrcParams(C.Structure):
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain C99, FP64, no FMA contraction)."""
+    """Compile the oracle with gcc (plain C99, FP64, no FMA contraction,
+    OpenMP over loops of independent entities)."""
     if force or not os.path.exists(LIB) or \
             os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
             ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
-             "-fno-fast-math", "-Wall", "-o", tmp, SRC, "-lm"])
+             "-fno-fast-math", "-fopenmp", "-Wall", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -90,6 +91,8 @@ def lib():
         L.orc_set_hz_halves.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_restrict.argtypes = [C.c_void_p]
         L.orc_transfer_density.argtypes = [C.c_void_p]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.argtypes = []
         L.orc_derived.argtypes = [P(OrcParams), P(C.c_double), C.c_int]
         L.orc_nu_net.argtypes = [P(OrcParams), C.c_double]
         L.orc_nu_net.restype = C.c_double
@@ -125,6 +128,16 @@ def make_params(cfg: dict) -> OrcParams:
         else:
             setattr(p, name, cfg[name])
     return p
+
+
+def set_threads(n: int) -> int:
+    """OpenMP worker threads of the oracle (n <= 0: all processors); results
+    do not depend on it.  Returns the count in use."""
+    return lib().orc_set_threads(int(n))
+
+
+def threads() -> int:
+    return lib().orc_get_threads()
 
 
 def derived(cfg: dict) -> dict:

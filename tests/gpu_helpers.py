@@ -1,11 +1,22 @@
 """Shared helpers of the GPU parity tests: run the HIP path and the FP64
-oracle on the same seeded inputs and compare them field by field."""
+oracle on the same seeded inputs and compare them field by field.
+
+Every field is scored on its own (relative L2 against its own norm), and the
+vector groups E = (Ex, Ey), J = (Jx, Jy) as a whole.  A component whose norm
+is a small share of its group's (Ex in a y-polarised plane wave is only the
+scattered field) has float32 rounding of group-sized terms as its noise
+floor relative to its own norm; the bar of each component is tol of its own
+norm plus tol/20 of its group's norm (see `component_limit`).  Cases built
+so that every component is large (the x-edge-rich cavity) assert every
+component at the plain tolerance."""
 import numpy as np
 
 from oracle import oracle as O
 from paper_2105_13276_amd import binding as B
 
 GROUPS = {"E": ("ex", "ey"), "H": ("hz",), "J": ("jx", "jy"), "Erms2": ("erms2",)}
+COMPONENTS = ("ex", "ey", "hz", "jx", "jy", "erms2")
+GROUP_OF = {"ex": "E", "ey": "E", "jx": "J", "jy": "J", "hz": "H", "erms2": "Erms2"}
 
 
 def rel_l2(got, ref):
@@ -18,15 +29,24 @@ def rel_l2(got, ref):
 
 def errors(gpu, orc, level, n_c):
     """Relative L2 error of the float32 GPU state against the FP64 oracle per
-    field group, and of log(max(n, 1e-12 n_c))."""
-    out = {}
+    field group, per component, and of log(max(n, 1e-12 n_c)); plus the
+    share of each component in its group's norm (key 'share')."""
+    out, share = {}, {}
+    got = {f: gpu.get(f, level) for f in COMPONENTS}
+    ref = {f: orc.get(f, level) for f in COMPONENTS}
     for g, names in GROUPS.items():
-        out[g] = rel_l2([gpu.get(f, level) for f in names],
-                        [orc.get(f, level) for f in names])
+        out[g] = rel_l2([got[f] for f in names], [ref[f] for f in names])
+        gn = np.sqrt(sum((ref[f].astype(np.float64) ** 2).sum() for f in names))
+        for f in names:
+            share[f] = float(np.linalg.norm(ref[f]) / gn) if gn > 0 else 0.0
+    for f in COMPONENTS:
+        if f in ("ex", "ey", "jx", "jy"):
+            out[f] = rel_l2([got[f]], [ref[f]])
     floor = 1e-12 * n_c
     ln_g = np.log(np.maximum(gpu.get("n", level).astype(np.float64), floor))
     ln_o = np.log(np.maximum(orc.get("n", level), floor))
     out["log_n"] = rel_l2([ln_g], [ln_o])
+    out["share"] = share
     return out
 
 
@@ -36,15 +56,64 @@ def both(cfg, seed_base, seed_fine=None):
     return g, o
 
 
-def assert_parity(gpu, orc, n_c, levels=(0, 1), tol=1e-4, tol_logn=1e-3, tag=""):
+def component_limit(tol, share, every_component):
+    """Bar of one component's own relative L2 error.  every_component: the
+    plain tolerance.  Otherwise tol + (tol/20)/share: the component's
+    absolute error may be tol of its own norm plus tol/20 of its group's
+    norm (20x below what the group bar allows).  For a component that
+    carries its group this is ~tol; for the scattered-field Ex of a
+    plane-wave case (share 1e-6 .. 1e-3) it bounds the float32 noise of the
+    group-sized terms that make it."""
+    if every_component:
+        return tol
+    return tol + (tol / 20.0) / max(share, 1e-30)
+
+
+def assert_parity(gpu, orc, n_c, levels=(0, 1), tol=1e-4, tol_logn=1e-3, tag="",
+                  every_component=False):
     report = {}
     for lv in levels:
         e = errors(gpu, orc, lv, n_c)
         report[lv] = e
-        print("%s level %d: %s" % (tag, lv, " ".join("%s=%.2e" % kv for kv in e.items())),
-              flush=True)
+        print("%s level %d: %s | share %s" % (
+            tag, lv, " ".join("%s=%.2e" % kv for kv in e.items() if k_is_err(kv[0])),
+            " ".join("%s=%.1e" % kv for kv in e["share"].items())), flush=True)
     for lv, e in report.items():
         for k, v in e.items():
-            lim = tol_logn if k == "log_n" else tol
+            if not k_is_err(k):
+                continue
+            if k == "log_n":
+                lim = tol_logn
+            elif k in GROUPS:
+                lim = tol
+            else:
+                lim = component_limit(tol, e["share"][k], every_component)
             assert v <= lim, "%s level %d %s rel L2 %.3e > %.1e" % (tag, lv, k, v, lim)
     return report
+
+
+def k_is_err(k):
+    return k != "share"
+
+
+def load_plane_packet(sim, cfg, E0, x1, width):
+    """Load a right-going plane-wave packet (Ey, Hz uniform in y) into the
+    base level of `sim` (GPU or oracle): Ey = E0 sin^2(pi u) sin(k (x - x1)),
+    u = (x - x1)/width in base cells, 0 < u < 1, k = 2 pi / lambda; Hz = Ey/eta0
+    half a step earlier (the profile shifted back by c dt / 2).  A test input:
+    it lets a wave reach a patch far from the source line within a few
+    periods."""
+    lam = 299792458.0 / cfg["freq_hz"]
+    eta0 = 376.730313668
+    k = 2.0 * np.pi / lam
+    dx = lam / cfg["cells_per_lambda"]
+    nx, ny = cfg["nx"], cfg["ny"]
+
+    def prof(xc):
+        u = (xc - x1) / width
+        env = np.where((u > 0) & (u < 1), np.sin(np.pi * u) ** 2, 0.0)
+        return E0 * env * np.sin(k * (xc - x1) * dx)
+
+    sim.set("ey", 0, np.broadcast_to(prof(np.arange(nx + 1.0)), (ny, nx + 1)))
+    xh = np.arange(nx) + 0.5 + 0.5 * cfg["courant"]
+    sim.set("hz", 0, np.broadcast_to(prof(xh) / eta0, (ny, nx)))

@@ -1,9 +1,10 @@
 """GPU (float32, HIP) against the FP64 oracle on the same seeded inputs.
 
-Tolerance: relative L2 <= 1e-4 per
-field group (E = (Ex, Ey), Hz, J = (Jx, Jy), E_rms^2) per level, <= 1e-3 on
-log(max(n, 1e-12 n_c)); integer regrid results (block flags, prefix sum,
-compacted list, patch extents) equal.
+Tolerance: relative L2 <= 1e-4 per field group (E = (Ex, Ey), Hz,
+J = (Jx, Jy), E_rms^2) per level and per component (each against its own
+norm, with the scattered-field allowance of `gpu_helpers.component_limit`),
+<= 1e-3 on log(max(n, 1e-12 n_c)); integer regrid results (block flags,
+prefix sum, compacted list, patch extents) equal.
 """
 import numpy as np
 import pytest
@@ -12,7 +13,7 @@ from oracle import oracle as O
 from paper_2105_13276_amd import binding as B
 from paper_2105_13276_amd import workloads as W
 
-from gpu_helpers import assert_parity, both
+from gpu_helpers import assert_parity, both, load_plane_packet
 
 pytestmark = pytest.mark.gpu
 
@@ -105,25 +106,44 @@ def test_config1_uniform_fine_prefix():
     assert_parity(g, o, _nc(cfg), levels=(0,), tag="config1-uniform")
 
 
-def test_config2_full_size_prefix():
+# config 2's 8-seed bounding box (coarse cells); the incident wave would need
+# ~90 periods to reach it, so the full-size tests load a plane-wave packet
+# just left of it (2 wavelengths long, ending 8 cells before the patch)
+CONFIG2_BOX = (2896, 352, 3664, 1888)
+CONFIG2_PACKET = (CONFIG2_BOX[0] - 72, 64)
+
+
+def test_config2_full_size_wave_on_the_patch():
     """Config 2 at full size (coarse 4096x2048, r = 2 patch over the 8-seed
     layout, E_rms/E_bd = 1.5) in the launch shape the large benchmark rows
-    use, over its first 2 periods: the initial regrid, one period of window
-    filling and one of continuity steps on both levels.  (The full 2000
-    periods are out of the FP64 oracle's reach.)"""
-    cfg = W.config2(periods=2)
+    use (4.7 M fine cells: one-substep patch launches), over 4 periods (one
+    period of window filling, three of continuity steps, the growth test at
+    step 256), with a right-going plane-wave packet of the incident amplitude
+    loaded just left of the patch at t = 0 (`load_plane_packet`): it crosses
+    the coarse/fine boundary and travels ~90 fine columns into the patch.
+    The level-1 field must carry it and agree with the oracle like every
+    other case."""
+    cfg = W.config2(periods=4)
     centres, peaks = W.config2_seed_layout(cfg)
     sb, sf = W.seeds(cfg, centres, peaks)
     g, o = both(cfg, sb, sf)
-    print("config 2 prefix: patch %s" % (g.patch(),), flush=True)
-    assert g.patch() == o.patch()
+    print("config 2: patch %s" % (g.patch(),), flush=True)
+    assert g.patch() == o.patch() == CONFIG2_BOX
     fg, sg, lg, cg = g.regrid_info()
     fo, so, lo, co = o.regrid_info()
     assert (fg == fo).all() and (sg == so).all() and cg == co and (lg == lo).all()
+    E0 = O.derived(cfg)["E0"]
+    for s in (g, o):
+        load_plane_packet(s, cfg, E0, *CONFIG2_PACKET)
     g.step(cfg["steps"])
     o.step(cfg["steps"])
     g.sync()
-    assert_parity(g, o, _nc(cfg), tag="config2-prefix")
+    assert g.patch() == o.patch()
+    colmax = np.abs(o.get("ey", 1)).max(axis=0)
+    print("config 2: max |Ey| on the patch %.2f E0, %d fine columns above 0.1 E0"
+          % (colmax.max() / E0, (colmax > 0.1 * E0).sum()), flush=True)
+    assert colmax.max() > 0.5 * E0 and (colmax > 0.1 * E0).sum() >= 64
+    assert_parity(g, o, _nc(cfg), tag="config2-wave")
 
 
 @pytest.mark.parametrize("r", [2, 4])

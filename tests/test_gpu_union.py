@@ -10,7 +10,7 @@ from oracle import oracle as O
 from paper_2105_13276_amd import binding as B
 from paper_2105_13276_amd import workloads as W
 
-from gpu_helpers import assert_parity, both
+from gpu_helpers import assert_parity, both, load_plane_packet
 
 pytestmark = pytest.mark.gpu
 
@@ -156,22 +156,28 @@ def test_union_with_townsend_and_recombination():
 
 def test_full_size_rectangle_of_blocks_is_the_patch():
     """Config 2 at full size (coarse 4096x2048, 8-seed layout) with the fine
-    level fixed to the seeds' bounding box: the union kernels (large level:
-    16-row tiles) give the rectangular patch's run bit for bit over 80
-    coarse steps (two continuity updates)."""
-    cfg = W.config2(periods=1)
+    level fixed to the seeds' bounding box and a plane-wave packet loaded
+    just left of it (as in test_gpu_parity.py, whose rectangle run is
+    compared with the oracle at this size): the union kernels (large level:
+    16-row tiles) give the rectangular patch's run bit for bit over 4
+    periods while the packet crosses into the level."""
+    cfg = W.config2(periods=4)
     centres, peaks = W.config2_seed_layout(cfg)
     sb, sf = W.seeds(cfg, centres, peaks)
     ext = (2896, 352, 3664, 1888)
     cr = dict(cfg, mode="static", static_ext=ext)
     cu = dict(cr, regrid_rule="union")
+    E0 = O.derived(cfg)["E0"]
     a = B.Sim(cr, sb, sf)
-    a.step(80)
+    load_plane_packet(a, cfg, E0, ext[0] - 72, 64)
+    a.step(cfg["steps"])
     ref = {(f, lv): a.get(f, lv) for lv in (0, 1) for f in FIELDS}
     a.close()
+    assert np.abs(ref[("ey", 1)]).max() > 0.5 * E0
     b = B.Sim(cu, sb, sf)
     assert b.patch() == ext and b.blocks().sum() == 48 * 96
-    b.step(80)
+    load_plane_packet(b, cfg, E0, ext[0] - 72, 64)
+    b.step(cfg["steps"])
     for (f, lv), x in ref.items():
         assert np.array_equal(x, b.get(f, lv)), (f, lv)
     b.close()

@@ -205,3 +205,48 @@ def test_narrow_patch_needs_the_filter_strength(oracle_mod):
     print("narrow patch: default %s, 1e-4 %s" % (ok[[0, -1]], weak[[0, -1]]))
     assert ok[-1] < 1.2 * ok[0]
     assert weak[-1] > 2.0 * weak[0]
+
+
+# ---- an x-edge-rich case: Ex ~ Ey, Jx ~ Jy across the interface -------------
+@pytest.mark.parametrize("kind,tol", [("rect", 5e-3), ("r4", 2.5e-2), ("union", 1.5e-2)])
+def test_x_edge_rich_cavity_matches_uniform_fine(oracle_mod, kind, tol):
+    """The cavity mode of `cavity_case` (Ex and Ey of equal amplitude, a
+    plasma that makes Jx as large as Jy) against the uniform fine mesh after
+    10 periods: every component on the fine level, and the coarse E against
+    the uniform run's edge means, within `tol` (relative L2; the base mesh's
+    own dispersion sets it: lambda/32 for r = 2, lambda/16 for r = 4).  Any
+    x-edge part of the interface left out (Eq. (5b) on the horizontal patch
+    sides, its time interpolation or its offsets) fails by 2-100x."""
+    import cavity_case as K
+    cfg, extra = K.config(kind)
+    r = cfg["r"]
+    cu = W.make(r * cfg["nx"], r * cfg["ny"], r * cfg["cells_per_lambda"], "uniform", 1,
+                bc_x="pec", bc_y="pec", tfsf_i=0)
+    sb, sf = K.seeds(cfg)
+    d = oracle_mod.Sim(cfg, sb, sf)
+    K.start(d, cfg, extra)
+    u = oracle_mod.Sim(cu, sf)
+    dx = LAM / cu["cells_per_lambda"]
+    X, Y = np.meshgrid((np.arange(cu["nx"]) + 0.5) * dx, (np.arange(cu["ny"]) + 0.5) * dx)
+    u.set("hz", 0, K.H0 * np.cos(2 * np.pi * X / (cu["nx"] * dx)) * np.cos(np.pi * Y / (cu["ny"] * dx)))
+    d.step(cfg["steps"])
+    u.step(r * cfg["steps"])
+    e = d.patch()
+    masks = K.level_masks(d, cfg)
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    errs = {}
+    for f in ("ex", "ey", "jx", "jy", "hz", "n"):
+        fd, fu = d.get(f, 1), u.get(f)
+        fu = fu[r * e[1]:r * e[1] + fd.shape[0], r * e[0]:r * e[0] + fd.shape[1]]
+        m = masks[f]
+        errs[f] = rel(fd[m], fu[m])
+    ue, uy = u.get("ex"), u.get("ey")
+    errs["coarse ex"] = rel(d.get("ex"), sum(ue[::r, a::r] for a in range(r)) / r)
+    errs["coarse ey"] = rel(d.get("ey"), sum(uy[a::r, ::r] for a in range(r)) / r)
+    norm = {f: np.linalg.norm(d.get(f, 1)) for f in ("ex", "ey", "jx", "jy")}
+    print("%s: %s" % (kind, " ".join("%s=%.2e" % kv for kv in errs.items())))
+    # the case is what it claims: x and y parts of comparable size
+    assert 0.3 < norm["ex"] / norm["ey"] < 3.5 and norm["jx"] / norm["jy"] > 0.3
+    assert 0.5 < np.linalg.norm(d.get("ex")) / np.linalg.norm(d.get("ey")) < 2.0
+    for k, v in errs.items():
+        assert v < tol, (kind, k, v)
