@@ -320,6 +320,19 @@ int dmr_backward(dmr_sim *s, const void *d_tape, const float *d_w_coarse,
  * Synchronises. */
 int dmr_weighted_sum(dmr_sim *s, int level, const float *d_w, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * dmr_weighted_sum with its per-block partial sums (at most 1024) and the
+ * result in a library-owned static device array (8 KB per GPU, held until
+ * the process ends) instead of the handle's workspace; the same bits as
+ * dmr_weighted_sum.  Every call on one GPU shares that array, so calls that
+ * overlap on a GPU (any handle, any stream) race: serialise them.  EINVAL
+ * for a level not present or more partial sums than the array holds (no
+ * level reaches that: the partial count is capped at 1024), EHIP if the
+ * array's address could not be found on the workspace's device.
+ * Synchronises. */
+int dmr_weighted_sum_static(dmr_sim *s, int level, const float *d_w, double *out);
+
 /* ---- batched form -------------------------------------------------------
  * count independent simulations (grid sizes and physical parameters may
  * differ; steps per period, mode, continuity switch and regrid cadence must

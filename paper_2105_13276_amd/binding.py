@@ -32,7 +32,8 @@ SYMBOLS = ["dmr_workspace_bytes", "dmr_create", "dmr_destroy", "dmr_step",
            "dmr_batch_set_config", "dmr_batch_destroy", "dmr_batch_last_error",
            "dmr_adjoint_tape_bytes", "dmr_forward_record", "dmr_backward",
            "dmr_weighted_sum", "dmr_state_bytes", "dmr_save", "dmr_load",
-           "dmr_get_blocks", "dmr_add_blocks", "dmr_derived"]
+           "dmr_get_blocks", "dmr_add_blocks", "dmr_derived",
+           "dmr_weighted_sum_static"]
 
 # the scalars dmr_derived returns, in its order
 DERIVED = ["omega", "lambda", "dx", "dt", "nu_m", "n_c", "eeff_fac", "E_bd",
@@ -118,6 +119,7 @@ def lib():
         L.dmr_forward_record.argtypes = [V, C.c_int64, C.c_int, V, C.c_size_t]
         L.dmr_backward.argtypes = [V, V, V, V, V, V, P(C.c_double)]
         L.dmr_weighted_sum.argtypes = [V, C.c_int, V, P(C.c_double)]
+        L.dmr_weighted_sum_static.argtypes = [V, C.c_int, V, P(C.c_double)]
         L.dmr_state_bytes.argtypes = [V, P(C.c_size_t)]
         L.dmr_save.argtypes = [V, V, C.c_size_t, C.c_int]
         L.dmr_load.argtypes = [V, V, C.c_size_t, C.c_int]
@@ -439,6 +441,15 @@ class Sim(_Handle):
         out = C.c_double()
         self._check(lib().dmr_weighted_sum(self._h, level, C.c_void_p(wd.data_ptr()),
                                            C.byref(out)), "dmr_weighted_sum")
+        return out.value
+
+    def weighted_sum_static(self, w, level: int = 0) -> float:
+        """weighted_sum through dmr_weighted_sum_static (no workspace scratch:
+        a static device array of the library)."""
+        wd = self._dev_f32(w)
+        out = C.c_double()
+        self._check(lib().dmr_weighted_sum_static(self._h, level, C.c_void_p(wd.data_ptr()),
+                                                  C.byref(out)), "dmr_weighted_sum_static")
         return out.value
 
     def backward(self, w_coarse, w_fine=None):

@@ -18,6 +18,41 @@
 #include "dmr.h"
 #include "dmr_kernels.h"
 
+#include <mutex>
+
+// Scratch of the allocation-free entry point dmr_weighted_sum_static: the
+// per-block partial sums of the weighted density sum (at most kStaticParts)
+// and the result.  One copy per GPU, held until the process ends; host code
+// uses the address hipGetSymbolAddress returns for the device, never the
+// array's name.
+constexpr int kStaticParts = 1024;
+static __device__ __align__(256) double scratch[kStaticParts + 1];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+bool g_scratch_tried[kMaxDevices] = {};
+
+// the array's address on device dev, looked up once per device with that
+// device current (nullptr if the lookup failed)
+double* static_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_tried[dev]) {
+    g_scratch_tried[dev] = true;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch[dev] = (double*)ptr;
+    (void)hipGetLastError();
+    if (cur != dev) (void)hipSetDevice(cur);
+  }
+  return g_scratch[dev];
+}
+}  // namespace
+
 using namespace dmr;
 
 namespace {
@@ -199,6 +234,7 @@ struct AdjTape {
 struct dmr_sim {
   dmr_params p{};
   hipStream_t st = nullptr;
+  int dev = -1;  // device holding the workspace
   Layout lay;
   char* ws = nullptr;
   std::string err = "";
@@ -1170,6 +1206,14 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   s->st = (hipStream_t)stream;
   s->lay = lay;
   s->ws = (char*)d_workspace;
+  {
+    // the device that holds the workspace; set up the static scratch array's
+    // address there once (used only by dmr_weighted_sum_static)
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, d_workspace) == hipSuccess) s->dev = a.device;
+    (void)hipGetLastError();
+    if (s->dev >= 0) (void)static_scratch(s->dev);
+  }
   setup_scalars(s);
   const double dx0 = s->L0.dx, dt0 = s->L0.dt;
   const int spp0 = s->L0.spp;
@@ -2147,6 +2191,31 @@ int dmr_weighted_sum(dmr_sim* s, int level, const float* d_w, double* out) {
   HIPCHK(s, hipStreamSynchronize(s->st));
   return DMR_OK;
 }
+
+int dmr_weighted_sum_static(dmr_sim* s, int level, const float* d_w, double* out) {
+  if (!s || !d_w || !out) return DMR_EINVAL;
+  if (level != 0 && !(level == 1 && refined(&s->p)))
+    return fail(s, DMR_EINVAL, "level %d not present", level);
+  const Level& L = level == 0 ? s->L0 : s->L1;
+  double* part = static_scratch(s->dev);
+  if (!part)
+    return fail(s, DMR_EHIP, "no address of the static scratch array on device %d", s->dev);
+  // the same partial count as dmr_weighted_sum (so the same bits); the array
+  // holds kStaticParts partials and the result
+  const size_t n = (size_t)(L.NX + 1) * (L.NY + 1);
+  const size_t nb = std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 1024));
+  if (nb > (size_t)kStaticParts)
+    return fail(s, DMR_EINVAL, "%zu partial sums exceed the static scratch array (%d)", nb,
+                kStaticParts);
+  hipError_t e = launch_wdot(d_w, L.n[s->ncur], L.pitch, 0, 0, L.NX + 1, L.NY + 1, part,
+                             part + kStaticParts, s->st);
+  if (e != hipSuccess) return hipfail(s, e, "weighted sum launch");
+  HIPCHK(s, hipMemcpyAsync(out, part + kStaticParts, sizeof(double), hipMemcpyDeviceToHost,
+                           s->st));
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  return DMR_OK;
+}
+
 
 }  // extern "C"
 
