@@ -13,8 +13,11 @@ synthetic (Gaussian seed of the paper's form) and resident in HBM before the
 timed region starts.
 
 Prints one JSON line.  value = cell-updates actually performed by the DMR
-run (sum over levels of cells x steps) per second; the uniform-fine run, the
-uniform-fine-equivalent rate of the DMR run and the speedup are extra keys.
+run (sum over levels of cells x steps) per second over the --steps timed
+intervals; the uniform-fine run, the uniform-fine-equivalent rate of the DMR
+run and the speedup are extra keys.  time_to_t_final_s is always the whole
+200-period run (median of three fresh runs; uniform-fine likewise), whatever
+--steps is.
 """
 from __future__ import annotations
 
@@ -28,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 INTERVAL = 256  # coarse steps per benchmark step
+T_FINAL_PERIODS = 200  # config 1's t_final
 
 
 def parse():
@@ -43,6 +47,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched 64-instance comparison")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--batch-periods", type=int, default=200,
+                    help="periods of the batched leg (config 3: 200)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint (record + reverse sweep) measurement")
     ap.add_argument("--only-large", action="store_true",
@@ -95,17 +101,21 @@ def only_large(steps=48):
     print("only-large: %d steps of %dx%d, copy of %d MiB" % (steps, cfg["nx"], cfg["ny"], a.numel() * 4 >> 20), flush=True)
 
 
+def _kernel_sha():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2105_13276_amd", "csrc", "dmr_kernels.hip")
+    return hashlib.sha1(open(src, "rb").read()).hexdigest() if os.path.exists(src) else None
+
+
 def traffic_records():
     """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE scaled by the copy
     calibration) from the committed rocprofv3 counter summary -- only while
     the kernel source is the one that was profiled; else {}."""
-    import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "hbm_counters_large_and_config1.md")
-    src = os.path.join(ROOT, "paper_2105_13276_amd", "csrc", "dmr_kernels.hip")
-    if not (os.path.exists(path) and os.path.exists(src)):
+    sha = _kernel_sha()
+    if not (os.path.exists(path) and sha):
         return {}
-    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
     pat = re.compile(r"traffic-record kernel=(\S+) fetch_kib=(\S+) write_kib=(\S+) "
                      r"fetch_factor=(\S+) write_factor=(\S+) source_sha1=(\S+)")
     out = {}
@@ -114,6 +124,23 @@ def traffic_records():
         if m and m.group(6) == sha:
             f, w, ff, wf = (float(m.group(k)) for k in (2, 3, 4, 5))
             out[m.group(1)] = (f * ff + w * wf) * 1024.0
+    return out
+
+
+def trace_records():
+    """Average kernel durations (us) of the committed rocprofv3 kernel-trace
+    summaries, keyed by kernel@workload -- only those taken on the current
+    kernel source."""
+    import glob
+    import re
+    sha = _kernel_sha()
+    pat = re.compile(r"trace-record kernel=(\S+) avg_us=(\S+) source_sha1=(\S+)")
+    out = {}
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            m = pat.search(line)
+            if m and m.group(3) == sha:
+                out[m.group(1)] = float(m.group(2))
     return out
 
 
@@ -284,6 +311,23 @@ def main():
     ms_u, cnt_u = sim_ut.timing()
     sim_ut.close()
 
+    # ---- time to t_final: config 1's 200 periods whatever --steps is, three
+    # runs of each (fresh simulations at t = 0), median ----------------------
+    log("time to t_final (200 periods), 3 runs each")
+    tf_k = T_FINAL_PERIODS * 64 // INTERVAL
+    cfg_dt = W.config1_dmr(periods=T_FINAL_PERIODS)
+    cfg_ut = W.config1_uniform(periods=T_FINAL_PERIODS)
+    seeds_ut = W.seeds(cfg_ut)
+    tf_d, tf_u = [], []
+    for rep in range(3):
+        sd_, wd_, _ = run_case(B, cfg_dt, seeds_d, tf_k, INTERVAL, 0, False)
+        sd_.close()
+        su_, wu_, _ = run_case(B, cfg_ut, seeds_ut, tf_k, 2 * INTERVAL, 0, False)
+        su_.close()
+        tf_d.append(wd_)
+        tf_u.append(wu_)
+    med_d, med_u = float(np.median(tf_d)), float(np.median(tf_u))
+
     # dominant kernel of the DMR workload
     cls_names = ["base_em", "fine_em", "continuity", "regrid"]
     dom = int(np.argmax(ms))
@@ -299,18 +343,22 @@ def main():
         alg_bytes = None
     achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9 if alg_bytes else None
     rec = traffic_records()
+    trc = trace_records()
+    key = ("k_dmr_step@config1" if (dom == 0 and cnt[1] == 0) else
+           "k_fine2@64x64" if dom == 1 else None) if fine_cells == 64 * 64 else None
     roofline = {"bound": "hbm", "kernel": ("k_dmr_step (base step + both patch substeps)"
                                            if cnt[1] == 0 else "k_em_stream (base)") if dom == 0 else
                 ("k_fine2 (both patch substeps)" if dom == 1 else cls_names[dom]),
                 "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                 "frac": (achieved / 8000.0) if achieved else None,
-                "traffic": (rec.get("k_dmr_step@config1") if (dom == 0 and cnt[1] == 0)
-                            else rec.get("k_fine2@64x64") if dom == 1 else None)
-                           if fine_cells == 64 * 64 else None,
+                "traffic": rec.get(key) if key else None,
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_us": per_launch_ms * 1e3,
-                "note": "config-1 state (7.9 MB) is cache resident and its kernels are "
-                        "latency-bound (per-launch HIP events add ~2 us to the ~9 us "
-                        "kernel); HBM-bound figures are in roofline_large"}
+                "avg_launch_us_rocprofv3": trc.get(key) if key else None,
+                "timing": "HIP events on the library's stream, one pair per run of "
+                          "consecutive launches of the class (runs of 8 between "
+                          "continuity steps), timed region = the whole DMR run",
+                "note": "config-1 state (7.9 MB) is cache resident and its step kernel is "
+                        "latency-bound; HBM-bound figures are in roofline_large"}
 
     out = {
         "metric": "Mcell-updates/s & time-to-t_final: DMR vs uniform-fine, same MI355X",
@@ -324,14 +372,19 @@ def main():
                                "%d periods (%d coarse steps), vs uniform-fine 1024x512"
                                % (periods, n_coarse),
                    "global_batch": 1, "seq_len": None, "parallelism": "none"},
-        "time_to_t_final_s": wall_d,
+        "timed_periods": periods,
+        "time_to_t_final_s": med_d,
+        "time_to_t_final_runs_s": tf_d,
+        "t_final_periods": T_FINAL_PERIODS,
         "patch_final": list(ext),
         "refined_fraction_per_interval": [round(v, 6) for v in r_hist],
         "uniform_fine_equiv_mcell_updates_per_s": work_u / wall_d / 1e6,
-        "uniform_fine": {"time_to_t_final_s": wall_u,
+        "uniform_fine": {"time_to_t_final_s": med_u, "time_to_t_final_runs_s": tf_u,
+                         "timed_s": wall_u,
                          "mcell_updates_per_s": work_u / wall_u / 1e6,
                          "kernel_ms": ms_u, "launches": cnt_u},
-        "speedup_vs_uniform_fine": wall_u / wall_d,
+        "speedup_vs_uniform_fine": med_u / med_d,
+        "speedup_vs_uniform_fine_timed": wall_u / wall_d,
         "kernel_ms": dict(zip(cls_names, ms)),
         "kernel_launches": dict(zip(cls_names, cnt)),
         "roofline": roofline,
@@ -465,48 +518,57 @@ def main():
             "dmr_mcell_updates_per_s": k2d / w2d / 1e6,
             "uniform_mcell_updates_per_s": k2u / w2u / 1e6}
 
-    # ---- batched form: 64 independent DMR runs (config-3 draw) -----------
+    # ---- batched form: 64 independent DMR runs (config 3) to t_final -----
     if not args.no_batch:
-        log("batched %d instances" % args.batch_count)
-        cfgs, seeds3 = W.config3(args.batch_count, periods=16)
-        warm, timed = 2 * INTERVAL, 2 * INTERVAL
+        bper = args.batch_periods
+        log("batched %d instances, %d periods" % (args.batch_count, bper))
+        cfgs, seeds3 = W.config3(args.batch_count, periods=bper)
+        steps3 = cfgs[0]["steps"]
+        # a throw-away batch of the same instances tunes the launch shape and
+        # schedule (cached per size key); the timed batch starts at t = 0
+        warm = B.Batch(cfgs, seeds3)
+        warm.step(2 * INTERVAL)
+        warm.sync()
+        warm.close()
         bt = B.Batch(cfgs, seeds3)
-        bt.step(warm)           # launch-shape timing + first graph capture
-        bt.sync()
         torch.cuda.synchronize()
+        work_b = 0
         t0 = time.perf_counter()
-        bt.step(timed)
+        for q in range(0, steps3, INTERVAL):
+            for inst, c in zip(bt.instances, cfgs):
+                e = inst.patch()
+                work_b += INTERVAL * (c["nx"] * c["ny"] + 8 * (e[2] - e[0]) * (e[3] - e[1]))
+            bt.step(min(INTERVAL, steps3 - q))
         bt.sync()
         torch.cuda.synchronize()
         wall_b = time.perf_counter() - t0
         shape = bt.config()
-        work_b = 0
-        for inst, c in zip(bt.instances, cfgs):
-            e = inst.patch()
-            work_b += timed * (c["nx"] * c["ny"] + 8 * (e[2] - e[0]) * (e[3] - e[1]))
         bt.close()
         wall_s = 0.0
         for c, sd in zip(cfgs, seeds3):
             g = B.Sim(c, *sd)
-            g.step(warm)
-            g.sync()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            g.step(timed)
+            g.step(steps3)
             g.sync()
             torch.cuda.synchronize()
             wall_s += time.perf_counter() - t0
             g.close()
         out["batched"] = {
-            "workload": "%d DMR instances (coarse sides 256/512/1024 x half, "
-                        "35/110/170 GHz, 100-760 Torr), %d coarse steps timed after %d"
-                        % (len(cfgs), timed, warm),
+            "workload": "config 3: %d DMR instances (coarse sides 256/512/1024 x half, "
+                        "35/110/170 GHz, 100-760 Torr), %d periods (%d coarse steps) from "
+                        "t = 0, vs %d sequential plain runs of the same"
+                        % (len(cfgs), bper, steps3, len(cfgs)),
             "batched_s": wall_b, "sequential_plain_s": wall_s,
             "speedup": wall_s / wall_b,
             "mcell_updates_per_s": work_b / wall_b / 1e6,
+            "sequential_mcell_updates_per_s": work_b / wall_s / 1e6,
             "hbm": hbm_share(work_b / wall_b / 1e6),
+            "note": "tuning excluded (a throw-away batch of the same instances tunes "
+                    "first); the graph captures of the timed batch are included",
             "launch_shape": {"seg": shape[0], "depth": shape[1], "fine_ty": shape[2],
-                             "graph": shape[3]}}
+                             "graph": shape[3],
+                             "schedule": shape[4] if len(shape) > 4 else "separate"}}
 
     # ---- adjoint form: config-1 setup, 2000 coarse steps, checkpoint 45 ----
     if not args.no_adjoint:
@@ -515,21 +577,48 @@ def main():
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample ---------------
     if not args.no_cpu:
-        log("CPU oracle sample")
+        log("CPU oracle samples")
         from oracle import oracle as O
-        o = O.Sim(cfg_d, *seeds_d)
-        e0 = o.patch()
-        t0 = time.perf_counter()
-        o.step(args.cpu_steps)
-        cw = time.perf_counter() - t0
-        e1 = o.patch()
-        fc = 4 * (e1[2] - e1[0]) * (e1[3] - e1[1])
-        work_c = coarse_cells * args.cpu_steps + fc * 2 * args.cpu_steps
-        out["cpu_baseline"] = {"value": work_c / cw / 1e6, "unit": "Mcell-updates/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": "FP64 oracle, DMR config 1, first %d coarse "
-                                         "steps (%.0f periods), %.1f s, single thread"
-                                         % (args.cpu_steps, args.cpu_steps / 64.0, cw)}
+
+        def oracle_rate(cfg, seeds, steps, threads, refined):
+            used = O.set_threads(threads)
+            try:
+                o = O.Sim(cfg, *seeds)
+                t0 = time.perf_counter()
+                o.step(steps)
+                cw = time.perf_counter() - t0
+                cells = cfg["nx"] * cfg["ny"] * steps
+                if refined:
+                    e1 = o.patch()
+                    cells += 4 * (e1[2] - e1[0]) * (e1[3] - e1[1]) * 2 * steps
+                o.close()
+            finally:
+                O.set_threads(0)
+            return cells / cw / 1e6, cw, used
+
+        all_threads = O.threads()
+        v_all, t_all, n_all = oracle_rate(cfg_d, seeds_d, args.cpu_steps, 0, True)
+        v_one, t_one, _ = oracle_rate(cfg_d, seeds_d, args.cpu_steps // 2, 1, True)
+        fu = args.cpu_steps // 10   # uniform-fine steps of the sample
+        u_all, tu_all, _ = oracle_rate(cfg_u, seeds_u, fu, 0, False)
+        u_one, tu_one, _ = oracle_rate(cfg_u, seeds_u, fu // 2, 1, False)
+        out["cpu_baseline"] = {
+            "value": v_all, "unit": "Mcell-updates/s", "cores": n_all, "kind": "oracle",
+            "sample": "FP64 oracle (OpenMP over independent entities, %d threads), DMR "
+                      "config 1, first %d coarse steps (%.0f periods), %.1f s"
+                      % (n_all, args.cpu_steps, args.cpu_steps / 64.0, t_all),
+            "threads_available": all_threads,
+            "single_thread": {"value": v_one, "cores": 1,
+                              "sample": "DMR config 1, first %d coarse steps, %.1f s"
+                                        % (args.cpu_steps // 2, t_one)},
+            "uniform_fine": {"value": u_all, "cores": n_all, "seconds": tu_all,
+                             "single_thread_value": u_one, "single_thread_seconds": tu_one,
+                             "sample": "FP64 oracle, uniform-fine 1024x512, first %d fine "
+                                       "steps (%d single-thread)" % (fu, fu // 2)},
+            # oracle time per coarse step: uniform-fine (two fine steps) over DMR
+            "dmr_speedup_vs_uniform_fine_cpu": (2.0 * cfg_u["nx"] * cfg_u["ny"] / u_all) /
+                                               ((coarse_cells + 2 * fine_cells) / v_all),
+        }
     print(json.dumps(out), flush=True)
 
 

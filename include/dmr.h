@@ -259,10 +259,14 @@ int dmr_load(dmr_sim *s, const void *src, size_t bytes, int src_on_device);
 int dmr_sync(dmr_sim *s);
 
 /* Per-kernel timing with HIP events on the handle's stream (off by
- * default).  Classes: 0 base-level EM step, 1 fine EM substep,
- * 2 continuity (both levels), 3 growth test and prolongation.
- * dmr_get_timing fills total milliseconds and launch counts per class since
- * the last reset and synchronises the stream. */
+ * default).  Classes: 0 base-level EM step (with the patch substeps when
+ * they run in the same launch), 1 fine EM substep, 2 continuity (both
+ * levels), 3 growth test and prolongation.  One pair of events brackets
+ * each run of consecutive launches of one class within a dmr_step call
+ * (events between back-to-back launches would add their own latency to
+ * each), so the time of a class is that of its launches and of the gaps
+ * between them.  dmr_get_timing fills total milliseconds and launch counts
+ * per class since the last reset and synchronises the stream. */
 int dmr_set_timing(dmr_sim *s, int on);
 int dmr_get_timing(dmr_sim *s, double ms[4], int64_t launches[4]);
 
@@ -339,8 +343,9 @@ int dmr_weighted_sum_static(dmr_sim *s, int level, const float *d_w, double *out
  * agree) advanced in lockstep: each per-step kernel is one launch over the
  * tiles of all instances, the steps of every steady 256-step interval are
  * replayed from one captured HIP graph, and the streaming segment length,
- * load depth and fine tile height are chosen by timing real steps (all
- * choices give bit-identical results; choices are cached per size key).
+ * load depth, fine tile height and subcycle schedule are chosen by timing
+ * real steps (all choices give bit-identical results; choices are cached
+ * per size key).
  * The batch runs on a private stream ordered after / before the caller's
  * stream with events.  Results per instance equal those of dmr_step on a
  * dmr_create'd simulation with the same inputs, bit for bit. */
@@ -365,10 +370,17 @@ int dmr_batch_instance(dmr_batch *b, int k, dmr_sim **out);
 /* Wait; DMR_EUNSTABLE if any instance saw a non-finite value. */
 int dmr_batch_sync(dmr_batch *b);
 
-/* Launch configuration {segment rows, load depth, fine tile rows, graph on};
- * set_config forces one (and disables the timing-based choice). */
-int dmr_batch_config(dmr_batch *b, int32_t cfg[4]);
-int dmr_batch_set_config(dmr_batch *b, const int32_t cfg[4]);
+/* Launch configuration {segment rows, load depth, fine tile rows, graph on,
+ * subcycle schedule}.  Schedules (all give the same bits): 0 a base-level
+ * launch and one launch per fine substep; 1 a base-level launch and one
+ * launch of both substeps (temporally blocked; r = 4: two launches of two
+ * substeps); 2 the base step and both substeps in one launch (r = 2).
+ * Schedules 1 and 2 need rectangular patches (no union levels).  The batch
+ * picks them by timing real steps of the run, per size key; set_config
+ * forces one (and disables the timing-based choice); EINVAL for a schedule
+ * the instances do not allow. */
+int dmr_batch_config(dmr_batch *b, int32_t cfg[5]);
+int dmr_batch_set_config(dmr_batch *b, const int32_t cfg[5]);
 
 void dmr_batch_destroy(dmr_batch *b);
 const char *dmr_batch_last_error(const dmr_batch *b);

@@ -334,13 +334,16 @@ class Batch:
     def sync(self):
         self._check(lib().dmr_batch_sync(self._h), "dmr_batch_sync")
 
-    def config(self):
-        c = (C.c_int32 * 4)()
-        self._check(lib().dmr_batch_config(self._h, c), "dmr_batch_config")
-        return tuple(c)
+    SCHEDULES = ("separate", "fused", "combined")
 
-    def set_config(self, seg, depth, ty, graph):
-        c = (C.c_int32 * 4)(seg, depth, ty, int(graph))
+    def config(self):
+        """(segment rows, load depth, fine tile rows, graph on, schedule)."""
+        c = (C.c_int32 * 5)()
+        self._check(lib().dmr_batch_config(self._h, c), "dmr_batch_config")
+        return tuple(c[:4]) + (self.SCHEDULES[c[4]],)
+
+    def set_config(self, seg, depth, ty, graph, schedule="separate"):
+        c = (C.c_int32 * 5)(seg, depth, ty, int(graph), self.SCHEDULES.index(schedule))
         self._check(lib().dmr_batch_set_config(self._h, c), "dmr_batch_set_config")
 
     def close(self):

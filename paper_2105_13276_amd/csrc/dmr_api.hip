@@ -283,7 +283,11 @@ struct dmr_sim {
   hipEvent_t ev_rep[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr}, ev_sync = nullptr;
   // timing
   bool timing = false;
-  struct Ev { int cls; hipEvent_t a, b; };
+  // a group of consecutive launches of one class, bracketed by one pair of
+  // events (events between back-to-back launches would add their own
+  // latency to every launch)
+  struct Ev { int cls; int n; hipEvent_t a, b; };
+  bool ev_open = false;  // the last group has no end event yet
   std::vector<Ev> evs;
   size_t ev_used = 0;
   double t_ms[4] = {0, 0, 0, 0};
@@ -387,36 +391,57 @@ double ey_inc(const dmr_sim* s, double x, double t) {
   return s->e0 * g * std::sin(s->omega * t - s->ktil * x);
 }
 
+void harvest(dmr_sim* s);
+
+// close the open group of launches (its end event after the last launch)
+void ev_close(dmr_sim* s) {
+  if (!s->ev_open) return;
+  (void)hipEventRecord(s->evs[s->ev_used].b, s->st);
+  s->ev_open = false;
+  s->ev_used++;
+  if (s->ev_used >= 4096) harvest(s);
+}
+
+// a launch of class cls follows: extend the open group if it is of the same
+// class, else start a new group
 void ev_begin(dmr_sim* s, int cls) {
   if (!s->timing) return;
+  if (s->ev_open && s->evs[s->ev_used].cls == cls) {
+    s->evs[s->ev_used].n++;
+    return;
+  }
+  ev_close(s);
   if (s->ev_used == s->evs.size()) {
-    dmr_sim::Ev e{cls, nullptr, nullptr};
+    dmr_sim::Ev e{cls, 0, nullptr, nullptr};
     (void)hipEventCreate(&e.a);
     (void)hipEventCreate(&e.b);
     s->evs.push_back(e);
   }
   s->evs[s->ev_used].cls = cls;
+  s->evs[s->ev_used].n = 1;
   (void)hipEventRecord(s->evs[s->ev_used].a, s->st);
+  s->ev_open = true;
 }
 
 void harvest(dmr_sim* s) {
+  ev_close(s);
   if (!s->ev_used) return;
   (void)hipStreamSynchronize(s->st);
   for (size_t k = 0; k < s->ev_used; k++) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, s->evs[k].a, s->evs[k].b) == hipSuccess) {
       s->t_ms[s->evs[k].cls] += ms;
-      s->t_n[s->evs[k].cls] += 1;
+      s->t_n[s->evs[k].cls] += s->evs[k].n;
     }
   }
   s->ev_used = 0;
 }
 
+// after a launch: groups of the step classes stay open for the next launch
+// of the same class; the growth test (class 3) waits on the host between its
+// launches, so its groups end at once
 void ev_end(dmr_sim* s) {
-  if (!s->timing) return;
-  (void)hipEventRecord(s->evs[s->ev_used].b, s->st);
-  s->ev_used++;
-  if (s->ev_used >= 4096) harvest(s);
+  if (s->timing && s->ev_open && s->evs[s->ev_used].cls == 3) ev_close(s);
 }
 
 // rows per segment of the streaming base kernel: long segments for
@@ -1341,8 +1366,9 @@ int dmr_step(dmr_sim* s, int64_t n) {
   if (!s || n < 0) return fail(s, DMR_EINVAL, "bad step count");
   for (int64_t k = 0; k < n; k++) {
     const int rc = base_step(s);
-    if (rc) return rc;
+    if (rc) { ev_close(s); return rc; }
   }
+  ev_close(s);  // a timing group does not span calls (the caller may queue other work)
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hipfail(s, e, "step");
   return DMR_OK;
@@ -2246,6 +2272,20 @@ struct dmr_batch {
   float2* h_src = nullptr;
   int64_t src_base = -1;
   int seg = 8, depth = 4, ty = 8;
+  // subcycle schedule of the refined instances (all rectangles):
+  // kSchedSeparate: base launch + one launch per fine substep;
+  // kSchedFused: base launch + one two-substep patch launch (r = 4: two);
+  // kSchedCombined: base step and both substeps in one launch (r = 2)
+  int sched = 0;
+  bool can_fuse = false, can_combine = false;
+  EMArgs* d_fem2 = nullptr;   // two-substep patch args [pairs][4 parities][count]
+  EMArgs* d_cem = nullptr;    // combined: base args, patch entities skipped [4][count]
+  EMArgs* d_floc = nullptr;   // combined: patch args, boundary E local [4][count]
+  int2* d_blk_comb = nullptr;
+  int nblk_comb = 0;
+  size_t cap_comb = 0;
+  std::vector<EMArgs> h_fem2, h_cem, h_floc;
+  std::vector<int2> h_blk_comb;
   bool use_graph = true, tuned = false, forced = false;
   hipGraphExec_t gexec = nullptr;
   bool graph_ok = false;
@@ -2259,13 +2299,15 @@ namespace {
 
 constexpr int kSegCand[] = {2, 4, 8, 16, 32, 64};
 constexpr int kTyCand[] = {4, 8, 16};
+enum { kSchedSeparate = 0, kSchedFused = 1, kSchedCombined = 2 };
 
 struct BatchLayout {
   std::vector<size_t> off, size;
   int rf = 2;  // r of the refined instances (all equal)
   size_t off_em = 0, off_fem = 0, off_cont = 0, off_fcont = 0, off_blk_base = 0,
          off_blk_fine = 0, off_blk_cont = 0, off_blk_fcont = 0, off_src = 0, total = 0;
-  size_t cap_base = 0, cap_fine = 0, cap_cont = 0, cap_fcont = 0;
+  size_t off_fem2 = 0, off_cem = 0, off_floc = 0, off_blk_comb = 0;
+  size_t cap_base = 0, cap_fine = 0, cap_cont = 0, cap_fcont = 0, cap_comb = 0;
 };
 
 int batch_layout(const dmr_params* p, int count, BatchLayout* L, std::string* why) {
@@ -2319,6 +2361,13 @@ int batch_layout(const dmr_params* p, int count, BatchLayout* L, std::string* wh
   L->off_blk_cont = off;  off += align256(sizeof(int2) * std::max<size_t>(L->cap_cont, 1));
   L->off_blk_fcont = off; off += align256(sizeof(int2) * std::max<size_t>(L->cap_fcont, 1));
   L->off_src = off;       off += align256(sizeof(float2) * kSrcSteps * count);
+  // the two-substep and combined schedules: their argument tables, and the
+  // combined table (groups of 16 base waves <= 4-wave blocks, plus the tiles)
+  L->off_fem2 = off;      off += align256(sizeof(EMArgs) * 4 * 2 * count);
+  L->off_cem = off;       off += align256(sizeof(EMArgs) * 4 * count);
+  L->off_floc = off;      off += align256(sizeof(EMArgs) * 4 * count);
+  L->cap_comb = L->cap_base + L->cap_fine;
+  L->off_blk_comb = off;  off += align256(sizeof(int2) * std::max<size_t>(L->cap_comb, 1));
   L->total = off;
   return DMR_OK;
 }
@@ -2336,8 +2385,21 @@ int batch_tables(dmr_batch* b) {
   b->h_fem.assign(4 * b->rf * n, EMArgs{});
   b->h_cont.assign(2 * n, ContArgs{});
   b->h_fcont.assign(2 * n, ContArgs{});
+  b->h_fem2.assign(4 * 2 * n, EMArgs{});
+  b->h_cem.assign(4 * n, EMArgs{});
+  b->h_floc.assign(4 * n, EMArgs{});
   b->h_blk_base.clear(); b->h_blk_fine.clear();
-  b->h_blk_cont.clear(); b->h_blk_fcont.clear();
+  b->h_blk_cont.clear(); b->h_blk_fcont.clear(); b->h_blk_comb.clear();
+  // the two-substep and combined schedules need rectangular patches
+  bool any_patch = false, any_union = false;
+  for (const dmr_sim* s : b->sims) {
+    any_patch = any_patch || s->has_patch;
+    any_union = any_union || s->uni;
+  }
+  b->can_fuse = any_patch && !any_union;
+  b->can_combine = b->can_fuse && b->rf == 2;
+  if ((b->sched == kSchedFused && !b->can_fuse) || (b->sched == kSchedCombined && !b->can_combine))
+    b->sched = kSchedSeparate;
   for (int k = 0; k < n; k++) {
     dmr_sim* s = b->sims[k];
     s->seg0 = b->seg;
@@ -2349,10 +2411,41 @@ int batch_tables(dmr_batch* b) {
       if (int rc = union_install(s)) return bfail(b, rc, s->err.c_str());
     }
     for (int v = 0; v < 4; v++) {
-      make_base_em(s, v & 1, v >> 1, &b->h_em[v * n + k]);
+      const int c = v & 1, nc = v >> 1;
+      make_base_em(s, c, nc, &b->h_em[v * n + k]);
       if (s->has_patch)
         for (int m = 1; m <= b->rf; m++)
-          make_fine_em(s, m, v & 1, v >> 1, b->ty, &b->h_fem[((m - 1) * 4 + v) * n + k]);
+          make_fine_em(s, m, c, nc, b->ty, &b->h_fem[((m - 1) * 4 + v) * n + k]);
+      b->h_cem[v * n + k] = b->h_em[v * n + k];
+      if (!s->has_patch || s->uni) continue;
+      // two-substep / combined launches read the patch state from one buffer
+      // and write the other; the buffers swap every step (batch_advance), so
+      // at coarse parity c the state is in buffer c ^ ccur of this build
+      const Level &C = s->L0, &F = s->L1;
+      const int rel = c ^ s->ccur;
+      if (b->rf == 4) {  // substeps (1, 2) then (3, 4): buffer 0 -> 1 -> 0
+        for (int h = 0; h < 2; h++) {
+          EMArgs& G = b->h_fem2[(h * 4 + v) * n + k];
+          make_fine_em(s, 2 * h + 2, c, nc, b->ty, &G);
+          em_args_level(&G, F, h, 1 - h, F.n[nc], F.acc);
+          G.frac = (float)(2 * h + 1) / 4.f;
+          G.hz_save = nullptr;
+          G.hz_lo = nullptr;
+        }
+      } else {
+        EMArgs& G = b->h_fem2[v * n + k];
+        make_fine_em(s, 2, c, nc, b->ty, &G);  // restriction targets
+        em_args_level(&G, F, rel, 1 - rel, F.n[nc], F.acc);
+        G.frac = 0.5f;  // time fraction of substep 1
+        EMArgs& A = b->h_cem[v * n + k];
+        A.skip_on = 1;
+        A.sL = s->ext[0]; A.sB = s->ext[1]; A.sR = s->ext[2]; A.sT = s->ext[3];
+        EMArgs& H = b->h_floc[v * n + k];
+        H = G;
+        H.chz0 = C.hz[c]; H.cjx0 = C.jx[c]; H.cjy0 = C.jy[c]; H.cn0 = C.n[nc];
+        H.cS = C.S; H.cc1 = C.c1; H.ckn = C.kn; H.cis = s->p.tfsf_i;
+        H.cnx = s->p.nx; H.cny = s->p.ny;
+      }
     }
     for (int nc = 0; nc < 2; nc++) {
       make_base_cont(s, nc, &b->h_cont[nc * n + k]);
@@ -2377,9 +2470,20 @@ int batch_tables(dmr_batch* b) {
       for (int t = 0; t < H.nbx * hny; t++) b->h_blk_fcont.push_back(make_int2(k, t));
     }
   }
+  // combined table: every instance's groups of 16 base waves, then the
+  // patch tiles (the same 64 x ty tiles as h_blk_fine, coded -1 - t)
+  for (int k = 0; k < n && b->can_combine; k++) {
+    const EMArgs& A = b->h_em[k];
+    const int groups = (A.nbx * (kThreads / 64) * A.nseg + kFineThreads / 64 - 1) / (kFineThreads / 64);
+    for (int g = 0; g < groups; g++) b->h_blk_comb.push_back(make_int2(k, g));
+  }
+  if (b->can_combine)
+    for (const int2& t : b->h_blk_fine) b->h_blk_comb.push_back(make_int2(t.x, -1 - t.y));
   if (b->h_blk_base.size() > b->cap_base || b->h_blk_fine.size() > b->cap_fine ||
-      b->h_blk_cont.size() > b->cap_cont || b->h_blk_fcont.size() > b->cap_fcont)
+      b->h_blk_cont.size() > b->cap_cont || b->h_blk_fcont.size() > b->cap_fcont ||
+      b->h_blk_comb.size() > b->cap_comb)
     return bfail(b, DMR_EINVAL, "batch block table exceeds its workspace capacity");
+  b->nblk_comb = (int)b->h_blk_comb.size();
   b->nblk_base = (int)b->h_blk_base.size();
   b->nblk_fine = (int)b->h_blk_fine.size();
   b->nblk_cont = (int)b->h_blk_cont.size();
@@ -2395,6 +2499,10 @@ int batch_tables(dmr_batch* b) {
       up(b->d_blk_fine, b->h_blk_fine.data(), b->h_blk_fine.size() * sizeof(int2)) ||
       up(b->d_blk_cont, b->h_blk_cont.data(), b->h_blk_cont.size() * sizeof(int2)) ||
       up(b->d_blk_fcont, b->h_blk_fcont.data(), b->h_blk_fcont.size() * sizeof(int2)) ||
+      up(b->d_fem2, b->h_fem2.data(), b->h_fem2.size() * sizeof(EMArgs)) ||
+      up(b->d_cem, b->h_cem.data(), b->h_cem.size() * sizeof(EMArgs)) ||
+      up(b->d_floc, b->h_floc.data(), b->h_floc.size() * sizeof(EMArgs)) ||
+      up(b->d_blk_comb, b->h_blk_comb.data(), b->h_blk_comb.size() * sizeof(int2)) ||
       hipStreamSynchronize(b->st))
     return bfail(b, DMR_EHIP, "batch table upload failed");
   b->graph_ok = false;
@@ -2422,7 +2530,16 @@ int batch_sources(dmr_batch* b, int64_t base) {
 void batch_advance(dmr_batch* b, int* slot, int* update) {
   *slot = -1;
   *update = 0;
+  const bool swap_fine = b->sched != kSchedSeparate && b->rf == 2;
   for (dmr_sim* s : b->sims) {
+    if (swap_fine && s->has_patch) {  // the new patch state is in buffer 1
+      Level& F = s->L1;
+      std::swap(F.hz[0], F.hz[1]);
+      std::swap(F.ex[0], F.ex[1]);
+      std::swap(F.ey[0], F.ey[1]);
+      std::swap(F.jx[0], F.jx[1]);
+      std::swap(F.jy[0], F.jy[1]);
+    }
     s->ccur = 1 - s->ccur;
     s->step++;
     if (s->p.continuity_on && s->step % s->L0.spb == 0) {
@@ -2441,20 +2558,38 @@ int batch_launch_step(dmr_batch* b, hipEvent_t* tb, hipEvent_t* tf) {
   const int v = s0->ccur + 2 * s0->ncur;
   const int nc = s0->ncur;
   const int k = (int)(s0->step - b->src_base);
-  if (tb) (void)hipEventRecord(tb[0], b->st);
-  hipError_t e = launch_em_stream_batch(b->d_em + v * n, b->d_blk_base, b->nblk_base,
-                                        b->d_src, k, b->depth, b->st);
-  if (tb) (void)hipEventRecord(tb[1], b->st);
-  if (e != hipSuccess) return bfail(b, DMR_EHIP, "batched base EM launch");
-  if (tf) (void)hipEventRecord(tf[0], b->st);
   const bool uni = s0->uni;
-  for (int m = 1; m <= b->rf && b->nblk_fine; m++) {
-    const EMArgs* fa = b->d_fem + ((m - 1) * 4 + v) * n;
-    e = uni ? launch_em_union_batch(fa, b->d_blk_fine, b->nblk_fine, b->ty, b->st)
-            : launch_em_batch(fa, b->d_blk_fine, b->nblk_fine, b->ty, b->st);
-    if (e != hipSuccess) return bfail(b, DMR_EHIP, "batched fine EM launch");
+  if (tb) (void)hipEventRecord(tb[0], b->st);
+  hipError_t e = hipSuccess;
+  if (b->sched == kSchedCombined) {
+    e = launch_dmr_step_batch(b->d_cem + v * n, b->d_floc + v * n, b->d_blk_comb, b->nblk_comb,
+                              b->d_src, k, b->depth, b->ty, b->st);
+    if (tb) (void)hipEventRecord(tb[1], b->st);
+    if (tf) (void)hipEventRecord(tf[0], b->st);
+    if (tf) (void)hipEventRecord(tf[1], b->st);
+    if (e != hipSuccess) return bfail(b, DMR_EHIP, "batched combined step launch");
+  } else {
+    e = launch_em_stream_batch(b->d_em + v * n, b->d_blk_base, b->nblk_base, b->d_src, k,
+                               b->depth, b->st);
+    if (tb) (void)hipEventRecord(tb[1], b->st);
+    if (e != hipSuccess) return bfail(b, DMR_EHIP, "batched base EM launch");
+    if (tf) (void)hipEventRecord(tf[0], b->st);
+    if (b->sched == kSchedFused) {
+      for (int h = 0; h < (b->rf == 4 ? 2 : 1) && b->nblk_fine; h++) {
+        e = launch_fine2_batch(b->d_fem2 + (h * 4 + v) * n, b->d_blk_fine, b->nblk_fine, b->ty,
+                               b->rf == 4, b->st);
+        if (e != hipSuccess) return bfail(b, DMR_EHIP, "batched two-substep launch");
+      }
+    } else {
+      for (int m = 1; m <= b->rf && b->nblk_fine; m++) {
+        const EMArgs* fa = b->d_fem + ((m - 1) * 4 + v) * n;
+        e = uni ? launch_em_union_batch(fa, b->d_blk_fine, b->nblk_fine, b->ty, b->st)
+                : launch_em_batch(fa, b->d_blk_fine, b->nblk_fine, b->ty, b->st);
+        if (e != hipSuccess) return bfail(b, DMR_EHIP, "batched fine EM launch");
+      }
+    }
+    if (tf) (void)hipEventRecord(tf[1], b->st);
   }
-  if (tf) (void)hipEventRecord(tf[1], b->st);
   int slot, update;
   batch_advance(b, &slot, &update);
   if (slot >= 0) {
@@ -2486,8 +2621,8 @@ int batch_regrid(dmr_batch* b) {
 
 // pick the streaming segment/depth and the fine tile height by timing real
 // steps (all candidates give bit-identical results)
-std::vector<std::pair<std::string, std::array<int, 3>>>& tune_cache() {
-  static std::vector<std::pair<std::string, std::array<int, 3>>> c;
+std::vector<std::pair<std::string, std::array<int, 4>>>& tune_cache() {
+  static std::vector<std::pair<std::string, std::array<int, 4>>> c;
   return c;
 }
 
@@ -2508,6 +2643,7 @@ int batch_tune(dmr_batch* b, int64_t* used) {
   for (auto& kv : tune_cache())
     if (kv.first == key) {
       b->seg = kv.second[0]; b->depth = kv.second[1]; b->ty = kv.second[2];
+      b->sched = kv.second[3];
       b->tuned = true;
       return batch_tables(b);
     }
@@ -2521,6 +2657,7 @@ int batch_tune(dmr_batch* b, int64_t* used) {
   const int nseg = sizeof(kSegCand) / sizeof(int), nty = sizeof(kTyCand) / sizeof(int);
   const int ncand = std::max(nseg, nty);
   int rc = DMR_OK;
+  b->sched = kSchedSeparate;
   for (int c = 0; c < ncand && !rc; c++) {
     b->seg = kSegCand[c % nseg];
     b->depth = stream_depth(b->seg);
@@ -2541,14 +2678,49 @@ int batch_tune(dmr_batch* b, int64_t* used) {
     if (c < nseg && tbase < best_b) { best_b = tbase; bseg = b->seg; bdep = b->depth; }
     if (c < nty && tfine < best_f) { best_f = tfine; bty = b->ty; }
   }
+  // the subcycle schedule: with the chosen streaming shape, time whole steps
+  // of each schedule the instances allow (the patch tile height per
+  // schedule) and keep the fastest
+  int bsched = kSchedSeparate;
+  b->seg = bseg; b->depth = bdep;
+  auto step_ms = [&](int sched, int ty, float* ms) {
+    b->sched = sched;
+    b->ty = ty;
+    int r = batch_tables(b);
+    *ms = 0.f;
+    for (int rep = 0; rep < 2 && !r; rep++) {
+      if (b->sims[0]->step - b->src_base >= kSrcSteps) r = batch_sources(b, b->sims[0]->step);
+      if (!r) r = batch_launch_step(b, tb, tf);
+      if (!r) (*used)++;
+      if (!r && hipStreamSynchronize(b->st) != hipSuccess) r = DMR_EHIP;
+      float x = 0.f;
+      (void)hipEventElapsedTime(&x, tb[0], tf[1]);
+      *ms += x;
+    }
+    return r;
+  };
+  float best = 1e30f;
+  if (!rc && (b->can_fuse || b->can_combine)) {
+    float t = 0.f;
+    rc = step_ms(kSchedSeparate, bty, &t);
+    best = t;
+    for (int sched = kSchedFused; sched <= kSchedCombined && !rc; sched++) {
+      if ((sched == kSchedFused && !b->can_fuse) || (sched == kSchedCombined && !b->can_combine))
+        continue;
+      for (int c = 0; c < nty && !rc; c++) {
+        rc = step_ms(sched, kTyCand[c], &t);
+        if (!rc && t < best) { best = t; bsched = sched; bty = kTyCand[c]; }
+      }
+    }
+  }
   for (int q = 0; q < 2; q++) {
     (void)hipEventDestroy(tb[q]);
     (void)hipEventDestroy(tf[q]);
   }
   if (rc) return rc;
-  b->seg = bseg; b->depth = bdep; b->ty = bty;
+  b->seg = bseg; b->depth = bdep; b->ty = bty; b->sched = bsched;
   b->tuned = true;
-  tune_cache().push_back({key, {bseg, bdep, bty}});
+  tune_cache().push_back({key, {bseg, bdep, bty, bsched}});
   return batch_tables(b);
 }
 
@@ -2674,6 +2846,11 @@ int dmr_batch_create(const dmr_params* p, int count, const double* const* seed_b
   b->cap_base = std::max<size_t>(L.cap_base, 1); b->cap_fine = std::max<size_t>(L.cap_fine, 1);
   b->cap_cont = std::max<size_t>(L.cap_cont, 1); b->cap_fcont = std::max<size_t>(L.cap_fcont, 1);
   b->d_src = (float2*)(b->ws + L.off_src);
+  b->d_fem2 = (EMArgs*)(b->ws + L.off_fem2);
+  b->d_cem = (EMArgs*)(b->ws + L.off_cem);
+  b->d_floc = (EMArgs*)(b->ws + L.off_floc);
+  b->d_blk_comb = (int2*)(b->ws + L.off_blk_comb);
+  b->cap_comb = std::max<size_t>(L.cap_comb, 1);
   rc = batch_tables(b);
   if (rc) {
     fprintf(stderr, "dmr_batch_create: %s\n", b->err.c_str());
@@ -2722,19 +2899,26 @@ int dmr_batch_sync(dmr_batch* b) {
   return DMR_OK;
 }
 
-int dmr_batch_config(dmr_batch* b, int32_t cfg[4]) {
+int dmr_batch_config(dmr_batch* b, int32_t cfg[5]) {
   if (!b || !cfg) return DMR_EINVAL;
   cfg[0] = b->seg; cfg[1] = b->depth; cfg[2] = b->ty; cfg[3] = b->use_graph;
+  cfg[4] = b->sched;
   return DMR_OK;
 }
 
-int dmr_batch_set_config(dmr_batch* b, const int32_t cfg[4]) {
+int dmr_batch_set_config(dmr_batch* b, const int32_t cfg[5]) {
   if (!b || !cfg || cfg[0] < 2 || (cfg[1] != 2 && cfg[1] != 4) ||
-      (cfg[2] != 4 && cfg[2] != 8 && cfg[2] != 16))
+      (cfg[2] != 4 && cfg[2] != 8 && cfg[2] != 16) || cfg[4] < kSchedSeparate ||
+      cfg[4] > kSchedCombined)
     return DMR_EINVAL;
   b->seg = cfg[0]; b->depth = cfg[1]; b->ty = cfg[2]; b->use_graph = cfg[3] != 0;
+  b->sched = cfg[4];
   b->forced = true;
-  return batch_tables(b);
+  int rc = batch_tables(b);
+  if (!rc && b->sched != cfg[4])
+    return bfail(b, DMR_EINVAL, "schedule not available for these instances (union levels: "
+                                "separate only; combined: r = 2)");
+  return rc;
 }
 
 const char* dmr_batch_last_error(const dmr_batch* b) {

@@ -175,6 +175,16 @@ hipError_t launch_em_stream_batch(const EMArgs* args, const int2* blk, int nblk,
                                   const float2* src, int k, int depth, hipStream_t st);
 hipError_t launch_em_batch(const EMArgs* args, const int2* blk, int nblk, int ty,
                            hipStream_t st);
+// batched two-substep patch launch over the same (instance, tile) table as
+// launch_em_batch (r4: a pair of the four r = 4 substeps)
+hipError_t launch_fine2_batch(const EMArgs* args, const int2* blk, int nblk, int ty, bool r4,
+                              hipStream_t st);
+// batched combined step: blk[b] = (instance, g >= 0: group of 16 base waves,
+// g < 0: patch tile -1 - g); cargs the base levels (patch entities skipped),
+// fargs the patch tiles (coarse boundary E computed locally)
+hipError_t launch_dmr_step_batch(const EMArgs* cargs, const EMArgs* fargs, const int2* blk,
+                                 int nblk, const float2* src, int k, int depth, int ty,
+                                 hipStream_t st);
 hipError_t launch_cont_batch(const ContArgs* args, const int2* blk, int nblk, bool fine,
                              int slot, int update, hipStream_t st);
 hipError_t launch_cont(const ContArgs& A, bool fine, hipStream_t st);

@@ -696,7 +696,8 @@ __device__ __forceinline__ void bnd_src(int tid, int orig, int NW_, int NH_, int
 // is this launch's input, and after substep 3 (H1).
 // ---------------------------------------------------------------------------
 template <int TY, int NT, bool LOCAL, bool ST = false, bool R4 = false, int TW = kTX>
-__device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
+__device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, float cey_src,
+                                           float chz_src) {
   constexpr int R1W = TW + 13, R1H = TY + 13;
   constexpr int Q1W = TW + 11, Q1H = TY + 11;
   constexpr int F1W = TW + 9, F1H = TY + 9;
@@ -865,19 +866,19 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
     if (cg <= 1) {
       const int ic = cx0 + cc;
       float hp = base_hz(q[7], S, q[4], q[3], q[1], q[0]);
-      if (ic == A.cis - 1) hp += S * A.cey_src;
+      if (ic == A.cis - 1) hp += S * cey_src;
       float h = base_hz(q[8], S, q[6], q[5], q[2], q[1]);
-      if (ic == A.cis - 1) h += S * A.cey_src;
+      if (ic == A.cis - 1) h += S * cey_src;
       const float kap = base_kap(A.ckn, q[10], q[11]);
       v = base_ex(q[1], kap, S, h, hp, c1, q[9]);
     } else {
       const int I = cg == 3 ? (R >> 1) : (L >> 1);
       float h = base_hz(q[8], S, q[2], q[1], q[6], q[5]);
-      if (I == A.cis - 1) h += S * A.cey_src;
+      if (I == A.cis - 1) h += S * cey_src;
       float hl = base_hz(q[7], S, q[1], q[0], q[4], q[3]);
-      if (I - 1 == A.cis - 1) hl += S * A.cey_src;
+      if (I - 1 == A.cis - 1) hl += S * cey_src;
       float curl = -S * (h - hl);
-      if (I == A.cis) curl += S * A.chz_src;
+      if (I == A.cis) curl += S * chz_src;
       const float kap = base_kap(A.ckn, q[10], q[11]);
       v = base_ey(q[1], kap, curl, c1, q[9]);
     }
@@ -1248,7 +1249,7 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by) {
 
 template <int TY, int NT, bool ST = false, bool R4 = false, int TW = kTX>
 __global__ __launch_bounds__(NT) void k_fine2(EMArgs A) {
-  fine2_tile<TY, NT, false, ST, R4, TW>(A, blockIdx.x, blockIdx.y);
+  fine2_tile<TY, NT, false, ST, R4, TW>(A, blockIdx.x, blockIdx.y, 0.f, 0.f);
 }
 
 
@@ -1260,6 +1261,16 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_batch(const EMArgs* __res
   const int2 bi = blk[blockIdx.x];
   const EMArgs& A = args[bi.x];
   fine_tile<TY, kFineThreads>(A, bi.y % A.nbx, bi.y / A.nbx);
+}
+
+// batched two-substep patch launch (both substeps of r = 2, or a pair of the
+// four of r = 4), over the same (instance, 64 x TY tile) table
+template <int TY, bool R4>
+__global__ __launch_bounds__(kFineThreads) void k_fine2_batch(const EMArgs* __restrict__ args,
+                                                              const int2* __restrict__ blk) {
+  const int2 bi = blk[blockIdx.x];
+  const EMArgs& A = args[bi.x];
+  fine2_tile<TY, kFineThreads, false, false, R4, kTX>(A, bi.y % A.nbx, bi.y / A.nbx, 0.f, 0.f);
 }
 
 // ---------------------------------------------------------------------------
@@ -1944,7 +1955,33 @@ __global__ __launch_bounds__(kFineThreads) void k_dmr_step(EMArgs C, EMArgs F, i
     return;
   }
   const int t = b - ncb;
-  fine2_tile<TY, kFineThreads, true, ST, false, TW>(F, t % nbx_f, t / nbx_f);
+  fine2_tile<TY, kFineThreads, true, ST, false, TW>(F, t % nbx_f, t / nbx_f, F.cey_src,
+                                                    F.chz_src);
+}
+
+// Batched combined step: blk[b] = (instance, g), g >= 0 a group of 16 base
+// waves of the instance (column wave w % waves_x of segment w / waves_x),
+// g < 0 its patch tile -1 - g (64 x TY).  The incident values of step k of
+// the interval come from src, as in k_em_stream_batch.
+template <int DEPTH, int TY>
+__global__ __launch_bounds__(kFineThreads) void k_dmr_step_batch(const EMArgs* __restrict__ cargs,
+                                                                 const EMArgs* __restrict__ fargs,
+                                                                 const int2* __restrict__ blk,
+                                                                 const float2* __restrict__ src,
+                                                                 int k) {
+  const int2 bi = blk[blockIdx.x];
+  const float2 sv = src[(size_t)bi.x * kSrcSteps + k];
+  if (bi.y >= 0) {
+    const EMArgs& C = cargs[bi.x];
+    const int waves_x = C.nbx * (kThreads / 64);
+    const int w = bi.y * (kFineThreads / 64) + (threadIdx.x >> 6);
+    const int sg = w / waves_x;
+    if (sg < C.nseg) em_stream_body<DEPTH>(C, w % waves_x, sg, C.seg, C.nseg, sv.x, sv.y);
+    return;
+  }
+  const EMArgs& F = fargs[bi.x];
+  const int t = -1 - bi.y;
+  fine2_tile<TY, kFineThreads, true, false, false, kTX>(F, t % F.nbx, t / F.nbx, sv.x, sv.y);
 }
 
 // ---- host-side launchers ----------------------------------------------------
@@ -2114,6 +2151,37 @@ hipError_t launch_dmr_step(const EMArgs& C, const EMArgs& F, int seg, int depth,
   }
 #undef DMR_STEP
 #undef DMR_STEP_ST
+  return hipGetLastError();
+}
+
+hipError_t launch_fine2_batch(const EMArgs* args, const int2* blk, int nblk, int ty, bool r4,
+                              hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  const dim3 g(nblk), b(kFineThreads);
+  if (r4) {
+    if (ty == 4) hipLaunchKernelGGL((k_fine2_batch<4, true>), g, b, 0, st, args, blk);
+    else if (ty == 8) hipLaunchKernelGGL((k_fine2_batch<8, true>), g, b, 0, st, args, blk);
+    else hipLaunchKernelGGL((k_fine2_batch<16, true>), g, b, 0, st, args, blk);
+  } else {
+    if (ty == 4) hipLaunchKernelGGL((k_fine2_batch<4, false>), g, b, 0, st, args, blk);
+    else if (ty == 8) hipLaunchKernelGGL((k_fine2_batch<8, false>), g, b, 0, st, args, blk);
+    else hipLaunchKernelGGL((k_fine2_batch<16, false>), g, b, 0, st, args, blk);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dmr_step_batch(const EMArgs* cargs, const EMArgs* fargs, const int2* blk,
+                                 int nblk, const float2* src, int k, int depth, int ty,
+                                 hipStream_t st) {
+  if (nblk <= 0) return hipSuccess;
+  const dim3 g(nblk), b(kFineThreads);
+#define DMR_SB(D, T_) hipLaunchKernelGGL((k_dmr_step_batch<D, T_>), g, b, 0, st, cargs, fargs, blk, src, k)
+  if (depth >= 4) {
+    if (ty == 4) DMR_SB(4, 4); else if (ty == 8) DMR_SB(4, 8); else DMR_SB(4, 16);
+  } else {
+    if (ty == 4) DMR_SB(2, 4); else if (ty == 8) DMR_SB(2, 8); else DMR_SB(2, 16);
+  }
+#undef DMR_SB
   return hipGetLastError();
 }
 

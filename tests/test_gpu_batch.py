@@ -1,7 +1,8 @@
 """Batched form: every instance of one batched run equals its own plain run
 bit for bit, whatever launch shape the batch uses (segment rows, load depth,
-fine tile rows, graph replay or not); and one instance checked against the
-FP64 oracle."""
+fine tile rows, graph replay or not, subcycle schedule: one-substep
+launches, a two-substep launch, or the base step and both substeps in one
+launch); and one instance checked against the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -16,16 +17,27 @@ pytestmark = pytest.mark.gpu
 FIELDS = ("hz", "ex", "ey", "jx", "jy", "n", "acc", "ring")
 
 
-def _mixed(count=6, periods=12):
+def _mixed(count=6, periods=12, grow=False):
+    """Config-3-like instances on smaller grids (so the plain runs stay
+    quick).  grow: a strong field and an off-centre seed half a cell from a
+    block edge in every other instance, whose patch then grows during the
+    run (regrid every 2 periods)."""
     cfgs, seeds = W.config3(count, periods)
-    # smaller grids than the benchmark's so the plain runs stay quick
     out_c, out_s = [], []
     for k, c in enumerate(cfgs):
         side = [128, 192, 256][k % 3]
-        c2 = W.make(side, side // 2, 32, "dynamic", periods, erms_over_ebd=c["erms_over_ebd"],
+        strong = grow and k % 2 == 0
+        c2 = W.make(side, side // 2, 32, "dynamic", periods,
+                    erms_over_ebd=4.0 if strong else c["erms_over_ebd"],
                     p_torr=c["p_torr"], freq_hz=c["freq_hz"], L_amb=c["L_amb"])
+        if grow:
+            c2["regrid_every"] = 2 * c2["steps_per_period"]
         out_c.append(c2)
-        out_s.append(W.seeds(c2))
+        if strong:
+            dx = 299792458.0 / c2["freq_hz"] / 32
+            out_s.append(W.seeds(c2, [((side // 2 + 11.5) * dx, side // 4 * dx)], [3e17]))
+        else:
+            out_s.append(W.seeds(c2))
     return out_c, out_s
 
 
@@ -53,18 +65,34 @@ def test_batch_equals_plain_runs():
 
 
 @pytest.mark.parametrize("shape", [(4, 4, 4, 0), (32, 2, 16, 1), (8, 4, 8, 1), (2, 2, 4, 1),
-                                   (2, 2, 8, 0)])
+                                   (2, 2, 8, 0), (8, 4, 8, 1, "fused"), (4, 4, 16, 0, "fused"),
+                                   (2, 2, 4, 1, "combined"), (16, 2, 16, 0, "combined"),
+                                   (8, 4, 8, 1, "combined")])
 def test_batch_launch_shape_invariance(shape):
-    cfgs, seeds = _mixed(count=4, periods=8)
+    """12 periods with regrid every 2 periods: patches grow (tables rebuilt
+    at both step parities of the two-substep schedules' buffer swap)."""
+    cfgs, seeds = _mixed(count=4, periods=12, grow=True)
     steps = cfgs[0]["steps"]
     ref = B.Batch(cfgs, seeds)
     ref.set_config(16, 2, 4, 0)
+    p0 = [ref.instances[k].patch() for k in range(len(cfgs))]
     ref.step(steps)
     bt = B.Batch(cfgs, seeds)
     bt.set_config(*shape)
+    assert bt.config()[4] == (shape[4] if len(shape) > 4 else "separate")
     bt.step(steps)
+    grew = sum(ref.instances[k].patch() != p0[k] for k in range(len(cfgs)))
+    print("shape %s: %d patches grew" % (shape, grew), flush=True)
+    assert grew >= 1
     for k in range(len(cfgs)):
+        assert bt.instances[k].patch() == ref.instances[k].patch()
         _same(bt.instances[k], ref.instances[k])
+    # and the plain runs of the same instances
+    for k, (c, s) in enumerate(zip(cfgs[:2], seeds[:2])):
+        g = B.Sim(c, *s)
+        g.step(steps)
+        _same(bt.instances[k], g)
+        g.close()
 
 
 def test_batch_instance_vs_oracle():
@@ -126,6 +154,10 @@ def test_union_batch_launch_shape_invariance():
     bt.step(steps)
     for k in range(len(cfgs)):
         _same(bt.instances[k], ref.instances[k])
+    # union levels run the one-substep schedule only
+    for sched in ("fused", "combined"):
+        with pytest.raises(B.DmrError, match="EINVAL"):
+            bt.set_config(8, 4, 8, 1, sched)
 
 
 def test_batch_config3_full_size_prefix():
@@ -161,15 +193,22 @@ def test_r4_batch_equals_plain_runs():
         cfgs.append(c)
         seeds.append(W.seeds(c, [(x * lam / 16, side // 4 * lam / 16)], [pk]))
     bt = B.Batch(cfgs, seeds)
+    bf = B.Batch(cfgs, seeds)   # the two two-substep launches per coarse step
+    bf.set_config(8, 4, 4, 1, "fused")
+    with pytest.raises(B.DmrError, match="EINVAL"):   # combined: r = 2 only
+        bf.set_config(8, 4, 4, 1, "combined")
+    bf.set_config(8, 4, 4, 1, "fused")
     bt.step(cfgs[0]["steps"])
+    bf.step(cfgs[0]["steps"])
     grown = 0
     for k, (c, s) in enumerate(zip(cfgs, seeds)):
         g = B.Sim(c, *s)
         p0 = g.patch()
         g.step(c["steps"])
         inst = bt.instances[k]
-        assert inst.patch() == g.patch()
+        assert inst.patch() == g.patch() == bf.instances[k].patch()
         grown += g.patch() != p0
         _same(inst, g)
+        _same(bf.instances[k], g)
     print("r = 4 batch: %d of 3 patches grew" % grown, flush=True)
     assert grown >= 1
