@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <array>
 #include <cmath>
 #include <cstdarg>
@@ -253,6 +254,13 @@ struct dmr_sim {
   // base-level step and both patch substeps in one launch (dmr_step only)
   bool combine = true;
   long fuse_max = 1L << 20;  // fine cells up to which the two-substep launch is used
+  // one-substep launches of large rectangular r = 2 patches: the streaming
+  // form from stream_min fine cells on (DMR_FINE_STREAM=0/1 forces either).
+  // Off by default: on config 2's 4.7 M-cell patch it takes 89.5 us per
+  // substep against 87.8 us for the tile form
+  long stream_min = LONG_MAX;
+  int stream_force = -1;
+  int fseg = 0, fdepth = 0;  // its rows per segment and load depth (0: by size)
   int nt1 = 1024;  // threads per patch tile
   int tw1 = 0;     // patch tile width of the combined step (0: by patch size)
   uint8_t* d_flag = nullptr;
@@ -465,6 +473,25 @@ int stream_rows(int NX, int NY) {
 int stream_depth(int seg) {
   if (const char* e = getenv("DMR_DEPTH")) return atoi(e) >= 4 ? 4 : 2;
   return (seg >= 8 && seg <= 16) ? 4 : 2;
+}
+
+// the streaming form of the one-substep patch launch: large rectangular
+// r = 2 patches outside the adjoint's replay (the replay copies values
+// around the tile kernel)
+bool stream_patch(const dmr_sim* s, long fine_cells) {
+  if (s->uni || s->p.r != 2) return false;
+  if (s->stream_force >= 0) return s->stream_force == 1;
+  return fine_cells >= s->stream_min;
+}
+
+// rows per segment of the streaming patch substep: every segment re-reads
+// five rows of E around its start, so segments are longer than the base
+// kernel's; halve them only while the grid has too few waves to fill the chip
+int fine_stream_rows(int NX, int NY) {
+  const long waves_x = (NX + 1 + 57) / 58;
+  int seg = 32;
+  while (seg > 8 && waves_x * ((NY + seg) / seg) < 8192) seg >>= 1;
+  return seg;
 }
 
 int tile_rows(int NX, int NY) {
@@ -1048,6 +1075,9 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
       ev_begin(s, 1);
       if (s->uni) {
         e = launch_em_union(G, s->d_tiles, s->ntiles, s->tyu, s->nt1, s->st);
+      } else if (stream_patch(s, fine_cells)) {
+        const int sg = s->fseg > 0 ? s->fseg : fine_stream_rows(G.R - G.L, G.T - G.B);
+        e = launch_fine_stream(G, sg, s->fdepth > 0 ? s->fdepth : 2, s->st);
       } else {
         e = launch_em(G, true, s->ty1, s->nt1, s->st);
       }
@@ -1278,6 +1308,9 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   if (const char* f = getenv("DMR_FUSE_MAX")) s->fuse_max = atol(f);
   if (const char* f = getenv("DMR_FNT")) s->nt1 = atoi(f) >= 1024 ? 1024 : 256;
   if (const char* f = getenv("DMR_TW")) { const int v = atoi(f); s->tw1 = (v == 16 || v == 32 || v == 64) ? v : 0; }
+  if (const char* f = getenv("DMR_FINE_STREAM")) s->stream_force = atoi(f) != 0 ? 1 : 0;
+  if (const char* f = getenv("DMR_FINE_SEG")) s->fseg = atoi(f) >= 2 ? atoi(f) : 0;
+  if (const char* f = getenv("DMR_FINE_DEPTH")) s->fdepth = atoi(f) >= 4 ? 4 : 2;
   s->depth0 = stream_depth(s->seg0);
   hipError_t e = hipMemsetAsync(s->ws, 0, lay.total, s->st);
   if (e != hipSuccess) { rc = hipfail(s, e, "workspace clear"); delete s; return rc; }

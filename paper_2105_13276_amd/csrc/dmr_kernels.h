@@ -165,6 +165,9 @@ hipError_t launch_dmr_step(const EMArgs& C, const EMArgs& F, int seg, int depth,
                            int tw, hipStream_t st);
 // base level, column-streaming kernel; seg = rows per segment (>= 2)
 hipError_t launch_em_stream(const EMArgs& A, int seg, int depth, hipStream_t st);
+// one patch substep (rectangle, r = 2) in column-streaming form, for large
+// patches; seg = rows per segment (even), depth = rows of loads in flight
+hipError_t launch_fine_stream(const EMArgs& A, int seg, int depth, hipStream_t st);
 // threshold lines of the patch sides (left I0, right I1, bottom J0, top J1):
 // flags[q] = 1 if a base node on line q has n > thr (one block, 4 ints)
 hipError_t launch_line_flags(const float* n, int pitch, int I0, int J0, int I1, int J1,

@@ -1937,6 +1937,261 @@ __global__ __launch_bounds__(kThreads) void k_em_stream_batch(const EMArgs* __re
 }
 
 // ---------------------------------------------------------------------------
+// One patch substep (rectangle, r = 2) in streaming form, for patches too
+// large for the tile kernels to reach the memory rate: a wave owns 58 node
+// columns (lanes 3..60, three halo lanes on each side for the filter's and
+// Faraday's x-neighbours, taken by wave shuffles) and walks a segment of rows
+// upward.  The filter's vertical window lives in registers: raw E of rows
+// j+1..j+3, its Laplacian of rows j..j+2, the filtered E of rows j, j+1; the
+// other inputs of a row are consumed three rows after their load.  Each
+// entity is computed with the same helpers and operands as by fine_tile, so
+// the results are identical; the fine -> coarse transfer of the last
+// substep is taken row by row (Hz and Ey of node row j when row j+1 is done).
+// ---------------------------------------------------------------------------
+struct FRow {
+  float ex, ey;                  // raw E of row j + 2 of the slot's row j
+  float hz, jx, jy, n, acc;      // row j
+  float bo0, bo1, bn0, bn1;      // coarse Ey of row j's Eq. (5b) value (old / new)
+};
+
+// raw loads from clamped (always valid) addresses: E of fine row je, the
+// other inputs of row jf; the Eq. (5b) inputs are those of the patch side
+// nearer to the column
+__device__ __forceinline__ FRow fine_row(const EMArgs& A, int i, int je, int jf) {
+  const int L = A.L, R = A.R, B = A.B, T = A.T;
+  const int ic = min(max(i, L), R);
+  const size_t oe = (size_t)min(max(je, B), T) * A.pitch + ic;
+  const size_t of = (size_t)min(max(jf, B), T) * A.pitch + ic;
+  FRow r;
+  r.ex = A.ex0[oe]; r.ey = A.ey0[oe];
+  r.hz = A.hz0[of]; r.jx = A.jx0[of]; r.jy = A.jy0[of]; r.n = A.n[of]; r.acc = A.acc[of];
+  // Ey on side column L or R at fine row jb: coarse edges (I, c), (I, c + 1)
+  const int jb = min(max(jf, B), T - 1);
+  const int I = (2 * i <= L + R ? L : R) >> 1;
+  const int c = (jb & 1) ? (jb >> 1) : (jb >> 1) - 1;
+  const size_t b0 = (size_t)c * A.cpitch + I;
+  r.bo0 = A.cey0[b0]; r.bo1 = A.cey0[b0 + A.cpitch];
+  r.bn0 = A.cey1[b0]; r.bn1 = A.cey1[b0 + A.cpitch];
+  return r;
+}
+
+template <int DEPTH>
+__device__ __forceinline__ void fine_stream_body(const EMArgs& A, int cw, int k, int seg,
+                                                 int nseg) {
+  const int L = A.L, R = A.R, B = A.B, T = A.T;
+  const int lane = threadIdx.x & 63;
+  const int i = L + cw * 58 - 3 + lane;
+  const bool own = lane >= 3 && lane <= 60 && i <= R;
+  const int j0 = B + k * seg;
+  const int j1 = (k == nseg - 1) ? T + 1 : j0 + seg;
+  const bool filt = A.gamma > 0.f;
+  const float S = A.S, c1 = A.c1, a = A.a, kn = A.kn, gam = A.gamma, frac = A.frac;
+  const bool cx_ = i >= L && i < R;   // x-edge / cell column
+  const bool cy_ = i >= L && i <= R;  // y-edge / node column
+  auto ex_ok = [&](int ii, int jj) { return ii >= L && ii < R && jj >= B && jj <= T; };
+  auto ey_ok = [&](int ii, int jj) { return ii >= L && ii <= R && jj >= B && jj < T; };
+  auto nd_ok = [&](int jj) { return cy_ && jj >= B && jj <= T; };
+  // Eq. (5b) Ex values of the bottom and top rows (space weights by column)
+  float exB = 0.f, exT = 0.f;
+  {
+    const int ib = min(max(i, L), R - 1);
+    const int ic = (ib & 1) ? (ib >> 1) : (ib >> 1) - 1;
+    const float w0 = (ib & 1) ? 0.75f : 0.25f, w1 = (ib & 1) ? 0.25f : 0.75f;
+    const size_t oB = (size_t)(B >> 1) * A.cpitch + ic, oT = (size_t)(T >> 1) * A.cpitch + ic;
+    exB = cfb(w0, w1, A.cex0[oB], A.cex0[oB + 1], A.cex1[oB], A.cex1[oB + 1], frac);
+    exT = cfb(w0, w1, A.cex0[oT], A.cex0[oT + 1], A.cex1[oT], A.cex1[oT + 1], frac);
+  }
+
+  // raw E masked to the patch (zero elsewhere, as fine_tile's LDS copy)
+  auto mx = [&](float v, int jj) { return ex_ok(i, jj) ? v : 0.f; };
+  auto my = [&](float v, int jj) { return ey_ok(i, jj) ? v : 0.f; };
+  // Laplacian of row jj from raw rows jj-1 (d), jj (c), jj+1 (u)
+  auto lapx = [&](float d, float c, float u, int jj) {
+    const float l = __shfl_up(c, 1, 64), r = __shfl_down(c, 1, 64);
+    if (!ex_ok(i, jj)) return 0.f;
+    return lap5(c, ex_ok(i - 1, jj) ? l : c, ex_ok(i + 1, jj) ? r : c,
+                ex_ok(i, jj - 1) ? d : c, ex_ok(i, jj + 1) ? u : c);
+  };
+  auto lapy = [&](float d, float c, float u, int jj) {
+    const float l = __shfl_up(c, 1, 64), r = __shfl_down(c, 1, 64);
+    if (!ey_ok(i, jj)) return 0.f;
+    return lap5(c, ey_ok(i - 1, jj) ? l : c, ey_ok(i + 1, jj) ? r : c,
+                ey_ok(i, jj - 1) ? d : c, ey_ok(i, jj + 1) ? u : c);
+  };
+  // filtered E of row jj from its raw value and the Laplacian rows jj-1..jj+1
+  auto filx = [&](float raw, float qd, float qc, float qu, int jj) {
+    const float l = __shfl_up(qc, 1, 64), r = __shfl_down(qc, 1, 64);
+    if (!ex_ok(i, jj)) return 0.f;
+    if (!filt || jj == B || jj == T) return raw;
+    const float l2 = lap5(qc, ex_ok(i - 1, jj) ? l : qc, ex_ok(i + 1, jj) ? r : qc,
+                          ex_ok(i, jj - 1) ? qd : qc, ex_ok(i, jj + 1) ? qu : qc);
+    return filter_e(raw, gam, l2);
+  };
+  auto fily = [&](float raw, float qd, float qc, float qu, int jj) {
+    const float l = __shfl_up(qc, 1, 64), r = __shfl_down(qc, 1, 64);
+    if (!ey_ok(i, jj)) return 0.f;
+    if (!filt || i == L || i == R) return raw;
+    const float l2 = lap5(qc, ey_ok(i - 1, jj) ? l : qc, ey_ok(i + 1, jj) ? r : qc,
+                          ey_ok(i, jj - 1) ? qd : qc, ey_ok(i, jj + 1) ? qu : qc);
+    return filter_e(raw, gam, l2);
+  };
+
+  const int js = j0 > B ? j0 - 1 : j0;
+  // warm-up: raw E of rows js-2 .. js+2 (Laplacian rows js-1 .. js+1,
+  // filtered row js) and the other inputs of row js
+  float ax[5], ay[5];
+  FRow D0 = fine_row(A, i, js - 2, js);
+  ax[0] = D0.ex; ay[0] = D0.ey;
+#pragma unroll
+  for (int d = 1; d < 5; d++) {
+    const int jj = min(max(js - 2 + d, B), T);
+    const size_t oe = (size_t)jj * A.pitch + min(max(i, L), R);
+    ax[d] = A.ex0[oe];
+    ay[d] = A.ey0[oe];
+  }
+  float rx1, rx2, ry1, ry2, qx0, qx1, qy0, qy1, fx0, fy0;
+  {
+#pragma unroll
+    for (int d = 0; d < 5; d++) { ax[d] = mx(ax[d], js - 2 + d); ay[d] = my(ay[d], js - 2 + d); }
+    const float qxm = lapx(ax[0], ax[1], ax[2], js - 1), qym = lapy(ay[0], ay[1], ay[2], js - 1);
+    qx0 = lapx(ax[1], ax[2], ax[3], js); qy0 = lapy(ay[1], ay[2], ay[3], js);
+    qx1 = lapx(ax[2], ax[3], ax[4], js + 1); qy1 = lapy(ay[2], ay[3], ay[4], js + 1);
+    fx0 = filx(ax[2], qxm, qx0, qx1, js);
+    fy0 = fily(ay[2], qym, qy0, qy1, js);
+    rx1 = ax[3]; rx2 = ax[4]; ry1 = ay[3]; ry2 = ay[4];
+  }
+  // slot of iteration j: raw E of row j+3, the other inputs of row j+1;
+  // slots of iterations js .. js+DEPTH in flight, buf[0] the next to arrive
+  FRow buf[DEPTH + 1];
+#pragma unroll
+  for (int d = 0; d <= DEPTH; d++)
+    buf[d] = fine_row(A, i, min(js + d + 3, j1 + 2), min(js + d + 1, j1));
+  // the previous row: new / old Hz, new Ey and Jy (Ampere, window, transfer)
+  float hn_p = 0.f, ho_p = 0.f, eyn_p = 0.f, jyn_p = 0.f;
+
+  auto row = [&](int j, const FRow& nw) {
+    const bool store = j >= j0 && j < j1;
+    const size_t o = (size_t)j * A.pitch + i;
+    // Laplacian row j+2, filtered row j+1
+    const float rx3 = mx(nw.ex, j + 3), ry3 = my(nw.ey, j + 3);
+    const float qx2 = lapx(rx1, rx2, rx3, j + 2), qy2 = lapy(ry1, ry2, ry3, j + 2);
+    const float fx1 = filx(rx1, qx0, qx1, qx2, j + 1);
+    const float fy1 = fily(ry1, qy0, qy1, qy2, j + 1);
+    // Faraday, Eq. (2)
+    const float fyr = __shfl_down(fy0, 1, 64);
+    float h = 0.f, ho = 0.f;
+    if (cx_ && j >= B && j < T) {
+      ho = D0.hz;
+      h = faraday(ho, S, fyr - fy0, fx1 - fx0);
+      if (store && own) A.hz1[o] = h;
+    }
+    const float hl = __shfl_up(h, 1, 64);
+    // densities at the edges' end nodes (zero outside the patch)
+    const float n0 = nd_ok(j) ? D0.n : 0.f, n1 = nd_ok(j + 1) ? nw.n : 0.f;
+    const float n0r = __shfl_down(n0, 1, 64);
+    // Ampere + Drude, Eqs. (1), (3); Eq. (5b) on the boundary
+    float exn = 0.f, jxn = 0.f;
+    if (ex_ok(i, j)) {
+      const float e = fx0;
+      const float ne = 0.5f * (n0 + n0r);
+      const float kap = kn * ne;
+      const float jo = D0.jx;
+      if (j != B && j != T) {
+        const float dh = h - hn_p;
+        exn = ampere(e, kap, S * dh, c1, jo);
+      } else {
+        exn = j == B ? exB : exT;
+      }
+      jxn = drude(a, jo, kap, e, exn);
+      if (store && own) { A.ex1[o] = exn; A.jx1[o] = jxn; }
+    }
+    float eyn = 0.f, jyn = 0.f;
+    if (ey_ok(i, j)) {
+      const float e = fy0;
+      const float ne = 0.5f * (n0 + n1);
+      const float kap = kn * ne;
+      const float jo = D0.jy;
+      if (i != L && i != R) {
+        const float dh = h - hl;
+        eyn = ampere(e, kap, -S * dh, c1, jo);
+      } else {
+        const float w0 = (j & 1) ? 0.75f : 0.25f, w1 = (j & 1) ? 0.25f : 0.75f;
+        eyn = cfb(w0, w1, D0.bo0, D0.bo1, D0.bn0, D0.bn1, frac);
+      }
+      jyn = drude(a, jo, kap, e, eyn);
+      if (store && own) { A.ey1[o] = eyn; A.jy1[o] = jyn; }
+    }
+    // window at node (i, j)
+    const float exl = __shfl_up(exn, 1, 64);
+    if (store && own && nd_ok(j)) {
+      float sx = 0.f, sy = 0.f;
+      int cx = 0, cy = 0;
+      if (i > L) { const float v = exl; sx += v * v; cx++; }
+      if (i < R) { const float v = exn; sx += v * v; cx++; }
+      if (j > B) { const float v = eyn_p; sy += v * v; cy++; }
+      if (j < T) { const float v = eyn; sy += v * v; cy++; }
+      const float e2 = win_e2(sx, cx, sy, cy);
+      A.acc[o] = D0.acc + e2;
+    }
+    // fine -> coarse transfer (coarse entities strictly inside the patch)
+    const float exr = __shfl_down(exn, 1, 64), jxr = __shfl_down(jxn, 1, 64);
+    const float hr = __shfl_down(h, 1, 64), hor = __shfl_down(ho, 1, 64);
+    const float hr_p = __shfl_down(hn_p, 1, 64), hor_p = __shfl_down(ho_p, 1, 64);
+    if (A.restrict_on && own && ((i - L) & 1) == 0) {
+      // x-edges of node row j
+      if (store && ((j - B) & 1) == 0 && ex_ok(i, j) && j != B && j != T) {
+        const size_t co = (size_t)(j >> 1) * A.cpitch + (i >> 1);
+        A.cex[co] = 0.5f * (exn + exr);
+        A.cjx[co] = jxn + jxr;  // J~ scales with dt
+      }
+      // cells and y-edges of node row j - 1 (rows j - 1 and j are done)
+      const int jn = j - 1;
+      if (jn >= j0 && jn < j1 && ((jn - B) & 1) == 0) {
+        const size_t co = (size_t)(jn >> 1) * A.cpitch + (i >> 1);
+        if (cx_ && jn >= B && jn < T) {
+          float s = 0.f;
+          s += 0.5f * (ho_p + hn_p);
+          s += 0.5f * (ho + h);
+          s += 0.5f * (hor_p + hr_p);
+          s += 0.5f * (hor + hr);
+          A.chz[co] = 0.25f * s;
+        }
+        if (ey_ok(i, jn) && i != L && i != R) {
+          A.cey[co] = 0.5f * (eyn_p + eyn);
+          A.cjy[co] = jyn_p + jyn;
+        }
+      }
+    }
+    // rotate the row windows
+    rx1 = rx2; rx2 = rx3; ry1 = ry2; ry2 = ry3;
+    qx0 = qx1; qx1 = qx2; qy0 = qy1; qy1 = qy2;
+    fx0 = fx1; fy0 = fy1;
+    D0 = nw;
+    hn_p = h; ho_p = ho; eyn_p = eyn; jyn_p = jyn;
+  };
+  // unrolled by DEPTH+1 so the pipeline slots rotate by index (as in
+  // em_stream_body); rows past the segment are computed from clamped reads
+  // and not stored, so every iteration issues the same memory operations
+  // and the wait for a slot's loads is exact
+  for (int jb = js; jb < j1; jb += DEPTH + 1) {
+#pragma unroll
+    for (int u = 0; u <= DEPTH; u++) {
+      const int j = jb + u;
+      row(j, buf[u]);
+      const int jn = j + DEPTH + 1;  // the iteration this slot serves next
+      buf[u] = fine_row(A, i, min(jn + 3, j1 + 2), min(jn + 1, j1));
+    }
+  }
+}
+
+template <int DEPTH>
+__global__ __launch_bounds__(kThreads) void k_fine_stream(EMArgs A, int seg, int nseg, int nbx) {
+  const int b = xcd_band(blockIdx.x, nbx * nseg);
+  fine_stream_body<DEPTH>(A, (b % nbx) * (kThreads / 64) + (threadIdx.x >> 6), b / nbx, seg,
+                          nseg);
+}
+
+// ---------------------------------------------------------------------------
 // Combined step: the base-level EM step and both patch substeps of a coarse
 // step in one launch.  Blocks [0, ncb) are base-level waves (16 per block,
 // column-wave w % waves_x of segment w / waves_x, blocks banded over the
@@ -2006,6 +2261,18 @@ hipError_t launch_em(const EMArgs& A, bool fine, int ty, int nt, hipStream_t st)
   case 8: DMR_LAUNCH_TILE(k_fine, 8, nt, A, st); break;
   default: DMR_LAUNCH_TILE(k_fine, 16, nt, A, st); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_fine_stream(const EMArgs& A, int seg, int depth, hipStream_t st) {
+  if (A.rf == 4 || A.act || A.hz_save || A.hz_lo || A.stn) return hipErrorInvalidValue;
+  seg = seg < 2 ? 2 : (seg & ~1);  // segments start at even offsets from B
+  const int waves = (A.R - A.L + 1 + 57) / 58;
+  const int nbx = (waves + kThreads / 64 - 1) / (kThreads / 64);
+  const int nseg = (A.T - A.B + 1 + seg - 1) / seg;
+  const dim3 g(nbx * nseg);
+  if (depth >= 4) hipLaunchKernelGGL(k_fine_stream<4>, g, dim3(kThreads), 0, st, A, seg, nseg, nbx);
+  else hipLaunchKernelGGL(k_fine_stream<2>, g, dim3(kThreads), 0, st, A, seg, nseg, nbx);
   return hipGetLastError();
 }
 

@@ -149,15 +149,17 @@ def test_config2_full_size_wave_on_the_patch():
 @pytest.mark.parametrize("r", [2, 4])
 def test_fused_forms_bitwise(r):
     """The one-launch step (base step + both patch substeps), the two-substep
-    patch launch and two one-substep launches give the same bits (each
-    entity is computed with the same operations in all three); for r = 4 the
-    substeps run as two two-substep launches or four one-substep launches."""
+    patch launch, two one-substep tile launches and two one-substep streaming
+    launches give the same bits (each entity is computed with the same
+    operations in all of them); for r = 4 the substeps run as two
+    two-substep launches or four one-substep launches."""
     import os
     if r == 2:
         cfg = W.make(128, 64, 32, "dynamic", 10, erms_over_ebd=3.0)
         sb, sf = W.seeds(cfg, [(80 * LAM / 32, 32 * LAM / 32)], [3e17])
         forms = (("combined", {}), ("fused", {"DMR_COMBINE": "0"}),
-                 ("separate", {"DMR_COMBINE": "0", "DMR_FUSE": "0"}))
+                 ("separate", {"DMR_COMBINE": "0", "DMR_FUSE": "0", "DMR_FINE_STREAM": "0"}),
+                 ("streamed", {"DMR_COMBINE": "0", "DMR_FUSE": "0", "DMR_FINE_STREAM": "1"}))
     else:
         cfg = W.make(64, 32, 16, "dynamic", 10, r=4, block=8, erms_over_ebd=3.0)
         sb, sf = W.seeds(cfg, [(40 * LAM / 16, 16 * LAM / 16)], [3e17])
@@ -165,7 +167,7 @@ def test_fused_forms_bitwise(r):
     cfg["regrid_every"] = 2 * cfg["steps_per_period"]
     runs = {}
     for name, env in forms:
-        old = {k: os.environ.get(k) for k in ("DMR_COMBINE", "DMR_FUSE")}
+        old = {k: os.environ.get(k) for k in ("DMR_COMBINE", "DMR_FUSE", "DMR_FINE_STREAM")}
         os.environ.update(env)
         try:
             g = B.Sim(cfg, sb, sf)
@@ -216,3 +218,44 @@ def test_patch_tile_widths_bitwise():
     for tw in ("32", "16"):
         for k, v in runs["64"].items():
             assert np.array_equal(v, runs[tw][k]) if k != "patch" else v == runs[tw][k], (tw, k)
+
+
+def _env_run(cfg, sb, sf, env, steps):
+    import os
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        g = B.Sim(cfg, sb, sf)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    g.step(steps)
+    out = {(f, lv): g.get(f, lv) for lv in (0, 1)
+           for f in ("hz", "ex", "ey", "jx", "jy", "n", "acc", "ring")}
+    out["patch"] = g.patch()
+    g.close()
+    return out
+
+
+@pytest.mark.parametrize("gamma", [1e-3, 0.0])
+def test_streamed_patch_substep_bitwise_large(gamma):
+    """The streaming form of the one-substep patch launch (used for large
+    patches) against the tile form on a patch of 192 x 96 fine cells
+    (several column waves, several row segments, odd offsets of the wave
+    columns against the tiles), with and without the interface filter, with
+    the incident wave and the density evolving: the same bits."""
+    cfg = W.make(128, 64, 32, "static", 12, static_ext=(16, 8, 112, 56),
+                 erms_over_ebd=3.0, fine_filter=gamma)
+    sb, sf = W.seeds(cfg, [(70 * LAM / 32, 30 * LAM / 32)], [3e18])
+    base = {"DMR_COMBINE": "0", "DMR_FUSE": "0"}
+    a = _env_run(cfg, sb, sf, dict(base, DMR_FINE_STREAM="0"), cfg["steps"])
+    b = _env_run(cfg, sb, sf, dict(base, DMR_FINE_STREAM="1"), cfg["steps"])
+    assert np.abs(a[("ey", 1)]).max() > 0
+    for k, v in a.items():
+        if k == "patch":
+            assert v == b[k]
+        else:
+            assert np.array_equal(v, b[k]), k
