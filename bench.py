@@ -240,7 +240,8 @@ def adjoint_leg(B, W, torch, steps=2000, every=45):
     ext = plain.patch()
     plain.close()
     g = B.Sim(cfg, sb, None)
-    t_rec = timed(lambda: g.record(steps, every))
+    rows = 2 * (ext[3] - ext[1]) + 1   # the plain run's last patch (growth is monotone)
+    t_rec = timed(lambda: g.record(steps, every, rows))
     res = {}
     t_bwd = timed(lambda: res.update(g.backward(w)))
     tape_gb = g.tape.numel() / 1e9
@@ -256,7 +257,8 @@ def adjoint_leg(B, W, torch, steps=2000, every=45):
             "gradient_mcell_updates_per_s": work / (t_rec + t_bwd) / 1e6,
             "forward_hbm": hbm_share(work / t_plain / 1e6),
             "gradient_hbm_forward_equivalent": hbm_share(work / (t_rec + t_bwd) / 1e6),
-            "tape_GB": tape_gb,
+            "tape_GB": tape_gb, "tape_fine_rows": rows,
+            "tape_GB_full_grid": B.adjoint_tape_bytes(cfg, steps, every) / 1e9,
             "dF_dE0": res["E0"], "dF_dA": res["A"], "dF_dbeta": res["beta"]}
 
 

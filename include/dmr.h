@@ -294,9 +294,20 @@ const char *dmr_last_error(const dmr_sim *s);
 int dmr_adjoint_tape_bytes(const dmr_params *p, int64_t steps, int ckpt_every,
                            size_t *bytes);
 
+/* The tape for a run whose patch never spans more than fine_rows fine node
+ * rows (r (J1 - J0) + 1 of the largest, i.e. the last, patch; <= 0: all
+ * rows, as dmr_adjoint_tape_bytes).  The fine planes of the checkpoints and
+ * of the stored steps hold only that many rows (the adjoint state still
+ * spans the fine grid).  dmr_forward_record takes the rows from the size of
+ * the tape it is given and fails with ENOMEM when the patch outgrows them
+ * (the handle has then advanced: record again on a fresh one). */
+int dmr_adjoint_tape_bytes_rows(const dmr_params *p, int64_t steps, int ckpt_every,
+                                int32_t fine_rows, size_t *bytes);
+
 /* Advance a fresh handle (t = 0) by `steps` base steps exactly as dmr_step
  * does, recording checkpoints and the patch history into the tape.
- * EINVAL if the handle has already stepped; ENOMEM if the tape is small. */
+ * EINVAL if the handle has already stepped; ENOMEM if the tape is small
+ * (for the current patch, or for a patch the run grows to). */
 int dmr_forward_record(dmr_sim *s, int64_t steps, int ckpt_every, void *d_tape,
                        size_t bytes);
 

@@ -33,7 +33,7 @@ SYMBOLS = ["dmr_workspace_bytes", "dmr_create", "dmr_destroy", "dmr_step",
            "dmr_adjoint_tape_bytes", "dmr_forward_record", "dmr_backward",
            "dmr_weighted_sum", "dmr_state_bytes", "dmr_save", "dmr_load",
            "dmr_get_blocks", "dmr_add_blocks", "dmr_derived",
-           "dmr_weighted_sum_static"]
+           "dmr_weighted_sum_static", "dmr_adjoint_tape_bytes_rows"]
 
 # the scalars dmr_derived returns, in its order
 DERIVED = ["omega", "lambda", "dx", "dt", "nu_m", "n_c", "eeff_fac", "E_bd",
@@ -116,6 +116,8 @@ def lib():
         L.dmr_batch_last_error.argtypes = [V]
         L.dmr_batch_last_error.restype = C.c_char_p
         L.dmr_adjoint_tape_bytes.argtypes = [P(DmrParams), C.c_int64, C.c_int, P(C.c_size_t)]
+        L.dmr_adjoint_tape_bytes_rows.argtypes = [P(DmrParams), C.c_int64, C.c_int, C.c_int32,
+                                                  P(C.c_size_t)]
         L.dmr_forward_record.argtypes = [V, C.c_int64, C.c_int, V, C.c_size_t]
         L.dmr_backward.argtypes = [V, V, V, V, V, V, P(C.c_double)]
         L.dmr_weighted_sum.argtypes = [V, C.c_int, V, P(C.c_double)]
@@ -163,6 +165,17 @@ def derived(cfg: dict) -> dict:
     if rc:
         raise DmrError("dmr_derived: %s" % ERRORS.get(rc, rc))
     return dict(zip(DERIVED, list(out)))
+
+
+def adjoint_tape_bytes(cfg: dict, steps: int, ckpt_every: int, fine_rows: int = 0) -> int:
+    """Bytes of the adjoint tape (dmr_adjoint_tape_bytes_rows)."""
+    p = make_params(cfg)
+    n = C.c_size_t()
+    rc = lib().dmr_adjoint_tape_bytes_rows(C.byref(p), int(steps), int(ckpt_every),
+                                           int(fine_rows), C.byref(n))
+    if rc:
+        raise DmrError("dmr_adjoint_tape_bytes_rows: %s" % ERRORS.get(rc, rc))
+    return n.value
 
 
 def workspace_bytes(cfg: dict) -> int:
@@ -424,14 +437,16 @@ class Sim(_Handle):
         return torch.as_tensor(np.asarray(a, np.float32) if not torch.is_tensor(a) else a,
                                dtype=torch.float32, device=self.device).contiguous()
 
-    def record(self, steps: int, ckpt_every: int = 45):
-        """Advance `steps` base steps from t = 0, recording for backward()."""
+    def record(self, steps: int, ckpt_every: int = 45, fine_rows: int = 0):
+        """Advance `steps` base steps from t = 0, recording for backward().
+        fine_rows: the most fine node rows any patch of the run spans (the
+        tape's fine slots hold only those); 0: all rows of the fine grid."""
         import torch
         n = C.c_size_t()
-        rc = lib().dmr_adjoint_tape_bytes(C.byref(self._p), int(steps), int(ckpt_every),
-                                          C.byref(n))
+        rc = lib().dmr_adjoint_tape_bytes_rows(C.byref(self._p), int(steps), int(ckpt_every),
+                                               int(fine_rows), C.byref(n))
         if rc:
-            raise DmrError("dmr_adjoint_tape_bytes: %s" % ERRORS.get(rc, rc))
+            raise DmrError("dmr_adjoint_tape_bytes_rows: %s" % ERRORS.get(rc, rc))
         with torch.cuda.device(self.device):
             self.tape = torch.empty(n.value, dtype=torch.uint8, device=self.device)
         self._check(lib().dmr_forward_record(self._h, int(steps), int(ckpt_every),

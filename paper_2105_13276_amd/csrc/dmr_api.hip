@@ -224,6 +224,7 @@ struct AdjTape {
   size_t bytes = 0;
   int64_t steps = 0;
   int every = 0, nck = 0;
+  int frows = 0;  // fine node rows of each checkpoint / stored-step slot
   std::vector<Ckpt> ck;
   Ckpt fin;
   std::vector<Growth> grow;
@@ -1590,23 +1591,33 @@ struct TapeLayout {
   size_t adj_c = 0, adj_f = 0, ck = 0, ck_size = 0, store = 0, st_size = 0, src = 0,
          src_size = 0, u = 0, part = 0, part_per_step = 0, gsum = 0, wpart = 0, total = 0;
   int nck = 0;
+  int frows = 0;      // fine node rows a checkpoint / stored-step slot holds
+  size_t fplane = 0;  // floats of one fine plane of such a slot
 };
 
 size_t node_blocks(int w, int h) {
   return (size_t)((w + 1 + 63) / 64) * (size_t)((h + 1 + 3) / 4);
 }
 
-TapeLayout tape_layout(const dmr_params* p, int64_t steps, int every) {
+// The tape for `steps` base steps, a checkpoint every `every`, when every
+// patch of the run spans at most frows fine node rows (<= 0 or more than
+// the fine grid has: all of them).  The fine planes of the checkpoints and
+// of the stored steps hold only those rows; the adjoint state spans the
+// whole fine grid.
+TapeLayout tape_layout(const dmr_params* p, int64_t steps, int every, int frows) {
   const Layout L = layout_of(p);
   const size_t f = sizeof(float);
+  const int full = refined(p) ? p->r * p->ny + 1 : 0;
   TapeLayout T;
+  T.frows = (frows <= 0 || frows > full) ? full : frows;
+  T.fplane = (size_t)T.frows * (size_t)L.pitch1;
   size_t off = 0;
   T.adj_c = off; off += align256(L.plane0 * kAdjPlanes * f);
   T.adj_f = off; off += align256(L.plane1 * kAdjPlanes * f);
   T.nck = (int)((steps + every - 1) / every);
-  T.ck_size = align256((L.plane0 * kCkC + L.plane1 * kCkF) * f);
+  T.ck_size = align256((L.plane0 * kCkC + T.fplane * kCkF) * f);
   T.ck = off; off += T.ck_size * (size_t)(T.nck + 1);
-  T.st_size = align256((L.plane0 * kStC + L.plane1 * kStF) * f);
+  T.st_size = align256((L.plane0 * kStC + T.fplane * kStF) * f);
   T.store = off; off += T.st_size * (size_t)every * 2;  // two banks: replay / reverse overlap
   T.src_size = align256((size_t)2 * p->ny * f);
   T.src = off; off += T.src_size * (size_t)every;
@@ -1650,15 +1661,21 @@ AdjLevel adj_carve(char* base, size_t plane) {
   return a;
 }
 
-StepStore store_slot(const dmr_sim* s, const TapeLayout& T, int k, int bank) {
+// stored values of step k of a segment in a bank.  The fine planes hold fine
+// rows [row0, row0 + T.frows) (row0: the first row of the segment's last
+// patch, which contains every patch of the segment); the pointers handed out
+// are offset so that entity (i, j) of the fine grid is at j * pitch + i, as
+// the kernels address it (only the patch rows are ever accessed).
+StepStore store_slot(const dmr_sim* s, const TapeLayout& T, int k, int bank, int row0) {
   float* b = (float*)(s->tape.base + T.store + T.st_size * ((size_t)bank * s->tape.every + k));
-  const size_t p0 = s->L0.plane, p1 = s->L1.plane;
+  const size_t p0 = s->L0.plane, fp = T.fplane;
   StepStore ss;
   ss.cexi = b; ss.ceyi = b + p0; ss.cexp = b + 2 * p0; ss.ceyp = b + 3 * p0;
   ss.cn = b + 4 * p0; ss.ce2 = b + 5 * p0;
-  float* f = b + kStC * p0;
-  ss.fex0 = f; ss.fey0 = f + p1; ss.fex1 = f + 2 * p1; ss.fey1 = f + 3 * p1;
-  ss.fex2 = f + 4 * p1; ss.fey2 = f + 5 * p1; ss.fn = f + 6 * p1; ss.fe2 = f + 7 * p1;
+  const uintptr_t f = (uintptr_t)(b + kStC * p0) - (uintptr_t)row0 * s->L1.pitch * sizeof(float);
+  auto pl = [&](int q) { return (float*)(f + (uintptr_t)q * fp * sizeof(float)); };
+  ss.fex0 = pl(0); ss.fey0 = pl(1); ss.fex1 = pl(2); ss.fey1 = pl(3);
+  ss.fex2 = pl(4); ss.fey2 = pl(5); ss.fn = pl(6); ss.fe2 = pl(7);
   return ss;
 }
 
@@ -1678,10 +1695,15 @@ void ck_planes(dmr_sim* s, float* live_c[9], float* live_f[15]) {
   for (int k = 0; k < kRing; k++) live_f[7 + k] = F.ring ? F.ring + (size_t)k * F.plane : nullptr;
 }
 
-int ck_copy(dmr_sim* s, float* b, bool save) {
+// copy the live planes to / from a checkpoint or saved state at b: the
+// coarse planes whole; the patch planes over the patch's rows, plane q of
+// the buffer at q * fplane floats from its fine part, its row 0 being fine
+// row rowbase (a saved state: full planes, rowbase 0; a tape checkpoint:
+// planes of the tape's rows, rowbase the patch's first row)
+int ck_copy(dmr_sim* s, float* b, bool save, size_t fplane, int rowbase) {
   float *lc[9], *lf[15];
   ck_planes(s, lc, lf);
-  const size_t p0 = s->L0.plane, p1 = s->L1.plane;
+  const size_t p0 = s->L0.plane;
   CopyJobs J{};
   for (int q = 0; q < 9; q++) {
     const size_t n = q == 8 ? kRing * p0 : p0;
@@ -1689,27 +1711,39 @@ int ck_copy(dmr_sim* s, float* b, bool save) {
     else job(&J, b + q * p0, lc[q], n);
   }
   if (s->has_patch) {
-    float* fb = b + kCkC * p0;
+    const Level& F = s->L1;
+    const int row = s->p.r * s->ext[1];
+    const size_t off = (size_t)row * F.pitch;
+    const size_t n = (size_t)(s->p.r * (s->ext[3] - s->ext[1]) + 1) * F.pitch;
+    float* fb = b + kCkC * p0 + (size_t)(row - rowbase) * F.pitch;
     for (int q = 0; q < kCkF; q++) {
-      if (save) job_rows(&J, s, lf[q], fb + q * p1);
-      else job_rows(&J, s, fb + q * p1, lf[q]);
+      if (save) job(&J, lf[q] + off, fb + q * fplane, n);
+      else job(&J, fb + q * fplane, lf[q] + off, n);
     }
   }
   return run_copies(s, J);
 }
 
+// fine node rows of the current patch (0 without one)
+int patch_rows(const dmr_sim* s) {
+  return s->has_patch ? s->p.r * (s->ext[3] - s->ext[1]) + 1 : 0;
+}
+
 int ck_save(dmr_sim* s, const TapeLayout& T, int idx, Ckpt* k) {
+  if (patch_rows(s) > T.frows)
+    return fail(s, DMR_ENOMEM, "the patch spans %d fine rows, the tape was sized for %d "
+                               "(dmr_adjoint_tape_bytes_rows)", patch_rows(s), T.frows);
   k->step = s->step; k->blocks = s->blocks; k->ccur = s->ccur; k->ncur = s->ncur;
   k->has = s->has_patch; k->ty1 = s->ty1;
   for (int q = 0; q < 4; q++) k->ext[q] = s->ext[q];
-  return ck_copy(s, ck_base(s, T, idx), true);
+  return ck_copy(s, ck_base(s, T, idx), true, T.fplane, s->p.r * s->ext[1]);
 }
 
 int ck_restore(dmr_sim* s, const TapeLayout& T, int idx, const Ckpt& k) {
   s->step = k.step; s->blocks = k.blocks; s->ccur = k.ccur; s->ncur = k.ncur;
   s->has_patch = k.has != 0; s->ty1 = k.ty1;
   for (int q = 0; q < 4; q++) s->ext[q] = k.ext[q];
-  return ck_copy(s, ck_base(s, T, idx), false);
+  return ck_copy(s, ck_base(s, T, idx), false, T.fplane, s->p.r * s->ext[1]);
 }
 
 AdjEMArgs adj_em_args(const dmr_sim* s, const Level& Lv, AdjLevel& a, bool fine,
@@ -1914,9 +1948,9 @@ uint64_t params_hash(const dmr_params& p) {
 
 // the union-of-blocks level appends its block map (one byte per block)
 size_t state_bytes(const dmr_sim* s) {
-  return kStateHeader + tape_layout(&s->p, 1, 1).ck_size + (s->uni ? align256(s->h_act.size()) : 0);
+  return kStateHeader + tape_layout(&s->p, 1, 1, 0).ck_size + (s->uni ? align256(s->h_act.size()) : 0);
 }
-size_t state_map_offset(const dmr_sim* s) { return kStateHeader + tape_layout(&s->p, 1, 1).ck_size; }
+size_t state_map_offset(const dmr_sim* s) { return kStateHeader + tape_layout(&s->p, 1, 1, 0).ck_size; }
 
 // host-side copy of the live planes to / from a host buffer b (floats after
 // the header), the patch planes over the patch's rows only
@@ -1950,11 +1984,16 @@ int state_host_copy(dmr_sim* s, float* b, bool save) {
 extern "C" {
 
 int dmr_adjoint_tape_bytes(const dmr_params* p, int64_t steps, int ckpt_every, size_t* bytes) {
+  return dmr_adjoint_tape_bytes_rows(p, steps, ckpt_every, 0, bytes);
+}
+
+int dmr_adjoint_tape_bytes_rows(const dmr_params* p, int64_t steps, int ckpt_every,
+                                int32_t fine_rows, size_t* bytes) {
   std::string why;
   const int rc = check_params(p, &why);
   if (rc) return rc;
   if (!bytes || steps < 1 || ckpt_every < 1) return DMR_EINVAL;
-  *bytes = tape_layout(p, steps, ckpt_every).total;
+  *bytes = tape_layout(p, steps, ckpt_every, fine_rows).total;
   return DMR_OK;
 }
 
@@ -1965,8 +2004,25 @@ int dmr_forward_record(dmr_sim* s, int64_t steps, int ckpt_every, void* d_tape, 
   if (refined(&s->p) && s->p.r != 2) return fail(s, DMR_EINVAL, "the adjoint supports r = 2");
   if (s->uni) return fail(s, DMR_EINVAL, "the adjoint supports the rectangular patch");
   if (!d_tape || ((uintptr_t)d_tape & 255)) return fail(s, DMR_EINVAL, "tape must be 256-byte aligned");
-  const TapeLayout T = tape_layout(&s->p, steps, ckpt_every);
-  if (bytes < T.total) return fail(s, DMR_ENOMEM, "tape needs %zu bytes", T.total);
+  // the most fine rows per slot the tape affords (its layout is linear in
+  // them; the patch must never span more)
+  const int full = refined(&s->p) ? s->p.r * s->p.ny + 1 : 0;
+  int frows = full;
+  if (tape_layout(&s->p, steps, ckpt_every, full).total > bytes) {
+    int lo = 0, hi = full;  // lo fits (0 rows: no patch), hi does not
+    if (tape_layout(&s->p, steps, ckpt_every, 1).total > bytes) hi = 1;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) / 2;
+      if (tape_layout(&s->p, steps, ckpt_every, mid).total <= bytes) lo = mid;
+      else hi = mid;
+    }
+    frows = lo;
+  }
+  if (frows < patch_rows(s) || (frows == 0 && refined(&s->p)))
+    return fail(s, DMR_ENOMEM, "tape needs %zu bytes for the current patch (%d fine rows)",
+                tape_layout(&s->p, steps, ckpt_every, std::max(patch_rows(s), 1)).total,
+                patch_rows(s));
+  const TapeLayout T = tape_layout(&s->p, steps, ckpt_every, frows);
   AdjTape& tp = s->tape;
   tp = AdjTape{};
   tp.base = (char*)d_tape;
@@ -1974,6 +2030,7 @@ int dmr_forward_record(dmr_sim* s, int64_t steps, int ckpt_every, void* d_tape, 
   tp.steps = steps;
   tp.every = ckpt_every;
   tp.nck = T.nck;
+  tp.frows = T.frows;
   tp.ck.resize(T.nck);
   for (int64_t k = 0; k < steps; k++) {
     if (k % ckpt_every == 0) {
@@ -2005,7 +2062,7 @@ int dmr_backward(dmr_sim* s, const void* d_tape, const float* d_w_coarse,
     return fail(s, DMR_EINVAL, "no recorded run on this tape");
   if (!d_w_coarse) return fail(s, DMR_EINVAL, "coarse weights are required");
   const dmr_params& p = s->p;
-  const TapeLayout T = tape_layout(&p, tp.steps, tp.every);
+  const TapeLayout T = tape_layout(&p, tp.steps, tp.every, tp.frows);
   const Level &C = s->L0, &F = s->L1;
   const int r = p.r;
   const bool ref = refined(&p);
@@ -2056,12 +2113,16 @@ int dmr_backward(dmr_sim* s, const void* d_tape, const float* d_w_coarse,
     // replay into this bank once the reverse sweep that read it is done
     if (seg + 2 <= tp.nck - 1) HIPCHK(s, hipStreamWaitEvent(rep, s->ev_adj[bank], 0));
     s->st = rep;
+    // the bank's fine rows start at the first row of the segment's last
+    // patch (growth is monotone: it contains the segment's earlier patches)
+    const Ckpt& ke = seg + 1 < tp.nck ? tp.ck[seg + 1] : tp.fin;
+    const int row0 = ke.has ? r * ke.ext[1] : 0;
     int rc = ck_restore(s, T, seg, tp.ck[seg]);
     for (int64_t k = k0; k < k1 && !rc; k++) {
       StepCtx cx;
       cx.store = true;
       cx.last = k == k1 - 1;
-      cx.ss = store_slot(s, T, (int)(k - k0), bank);
+      cx.ss = store_slot(s, T, (int)(k - k0), bank, row0);
       cx.forced = true;
       for (const Growth& g : tp.grow)
         if (g.after == k + 1) {
@@ -2078,8 +2139,8 @@ int dmr_backward(dmr_sim* s, const void* d_tape, const float* d_w_coarse,
     size_t npart = 0;
     for (int64_t k = k1 - 1; k >= k0; k--) {
       const int kk = (int)(k - k0);
-      const StepStore ss = store_slot(s, T, kk, bank);
-      const StepStore nx = store_slot(s, T, kk + 1, bank);
+      const StepStore ss = store_slot(s, T, kk, bank, row0);
+      const StepStore nx = store_slot(s, T, kk + 1, bank, row0);
       if (int rc2 = adj_step(s, T, ac, af, kk, meta[kk], ss, k == k1 - 1 ? nullptr : &nx, &npart))
         return rc2;
     }
@@ -2145,7 +2206,7 @@ int dmr_save(dmr_sim* s, void* dst, size_t bytes, int dst_on_device) {
   float* body = (float*)((char*)dst + kStateHeader);
   char* map = (char*)dst + state_map_offset(s);
   if (dst_on_device) {
-    if (int rc = ck_copy(s, body, true)) return rc;
+    if (int rc = ck_copy(s, body, true, s->L1.plane, 0)) return rc;
     HIPCHK(s, hipMemcpyAsync(dst, &h, sizeof(h), hipMemcpyHostToDevice, s->st));
     if (s->uni)
       HIPCHK(s, hipMemcpyAsync(map, s->h_act.data(), s->h_act.size(), hipMemcpyHostToDevice, s->st));
@@ -2225,7 +2286,7 @@ int dmr_load(dmr_sim* s, const void* src, size_t bytes, int src_on_device) {
   s->tape.valid = false;  // a recorded run no longer describes this state
   float* body = (float*)((char*)src + kStateHeader);
   if (src_on_device) {
-    if (int rc = ck_copy(s, body, false)) return rc;
+    if (int rc = ck_copy(s, body, false, s->L1.plane, 0)) return rc;
     HIPCHK(s, hipStreamSynchronize(s->st));
   } else {
     if (int rc = state_host_copy(s, body, false)) return rc;

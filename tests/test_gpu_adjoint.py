@@ -19,9 +19,9 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-3
 
 
-def _gpu(cfg, sb, w, every):
+def _gpu(cfg, sb, w, every, fine_rows=0):
     g = B.Sim(cfg, sb, None)
-    g.record(cfg["steps"], every)
+    g.record(cfg["steps"], every, fine_rows)
     F = g.weighted_sum(w)
     out = g.backward(w)
     out = dict(out, seed=out["seed"].cpu().numpy().astype(np.float64), F=F,
@@ -130,8 +130,18 @@ def test_config4_full_size():
     sb, _ = W.seeds(cfg, fine=False)
     w = W.window_weights(cfg)
     g = B.Sim(cfg, sb, None)
-    assert g.patch() == tuple(int(v) for v in ref["ext0"])
-    g.record(cfg["steps"], 45)
+    ext = g.patch()
+    assert ext == tuple(int(v) for v in ref["ext0"])
+    # the patch does not grow in these 2000 steps: a tape sized on its rows
+    rows = 2 * (ext[3] - ext[1]) + 1
+    g.record(cfg["steps"], 45, fine_rows=rows)
+    assert g.patch() == ext
+    full = B.adjoint_tape_bytes(cfg, cfg["steps"], 45)
+    print("config 4: tape %.3f GB (%d fine rows); full-grid tape %.3f GB"
+          % (g.tape.numel() / 1e9, rows, full / 1e9), flush=True)
+    # what is left is the coarse part of the 46 checkpoints and of the two
+    # 45-step banks, and the adjoint state
+    assert g.tape.numel() <= 0.35 * full
     F = g.weighted_sum(w)
     got = g.backward(w)
     seed = got["seed"].cpu().numpy().astype(np.float64)
@@ -141,3 +151,25 @@ def test_config4_full_size():
     print("config 4: relative errors vs FP64 %s" % errs, flush=True)
     for k, v in errs.items():
         assert v <= TOL, (k, v, errs)
+
+
+def test_row_sized_tape_gives_the_same_gradients():
+    """A tape whose fine slots hold only the rows of the run's last patch
+    (dmr_adjoint_tape_bytes_rows) gives the full-grid tape's bits, through a
+    growth; a tape with fewer rows than the patch spans is refused."""
+    cfg, sb = case("dynamic")
+    w = window(cfg, CENTRE["dynamic"])
+    o, ext0, growth = history(cfg, sb)
+    assert growth, "the case should grow"
+    last = o.patch()
+    rows = 2 * (last[3] - last[1]) + 1
+    g1, a = _gpu(cfg, sb, w, every=17)
+    g2, b = _gpu(cfg, sb, w, every=17, fine_rows=rows)
+    print("tape %d -> %d bytes (%d fine rows)" % (g1.tape.numel(), g2.tape.numel(), rows),
+          flush=True)
+    assert g2.tape.numel() < g1.tape.numel()
+    assert np.array_equal(a["seed"], b["seed"])
+    for k in ("E0", "A", "beta", "F"):
+        assert a[k] == b[k], k
+    with pytest.raises(B.DmrError, match="ENOMEM"):
+        _gpu(cfg, sb, w, every=17, fine_rows=rows - 2)
