@@ -112,7 +112,7 @@ def traffic_records():
     calibration) from the committed rocprofv3 counter summary -- only while
     the kernel source is the one that was profiled; else {}."""
     import re
-    path = os.path.join(ROOT, "profiles", "hbm_counters_large_and_config1.md")
+    path = os.path.join(ROOT, "profiles", "hbm_counters_em_stream_dmr_step_fine2_fine_union.md")
     sha = _kernel_sha()
     if not (os.path.exists(path) and sha):
         return {}
@@ -439,6 +439,7 @@ def main():
                                  "achieved": ach_l, "peak": 8000.0, "unit": "GB/s",
                                  "frac": ach_l / 8000.0, "avg_launch_us": per_l * 1e3,
                                  "traffic": rec.get("k_em_stream@4096x2048"),
+                                 "avg_launch_us_rocprofv3": trc.get("k_em_stream@4096x2048"),
                                  "alg_bytes_per_launch": em_bytes_per_cell() * cells_l}
         # DMR vs uniform-fine where the step is bandwidth-bound: config-1
         # physics on 4096x2048 coarse (8192x4096 uniform-fine), one interval

@@ -242,8 +242,8 @@ def _env_run(cfg, sb, sf, env, steps):
 
 @pytest.mark.parametrize("gamma", [1e-3, 0.0])
 def test_streamed_patch_substep_bitwise_large(gamma):
-    """The streaming form of the one-substep patch launch (used for large
-    patches) against the tile form on a patch of 192 x 96 fine cells
+    """The streaming form of the one-substep patch launch (selectable for
+    large patches, off by default) against the tile form on a patch of 192 x 96 fine cells
     (several column waves, several row segments, odd offsets of the wave
     columns against the tiles), with and without the interface filter, with
     the incident wave and the density evolving: the same bits."""
