@@ -9,6 +9,10 @@ namespace dmr {
 constexpr int kTX = 64;        // tile width in nodes: one wavefront per row
 constexpr int kThreads = 256;  // threads per tile
 constexpr int kFineThreads = 1024;  // threads per patch tile (phases run from LDS)
+// threads per block of the combined step: 512 for its 4-row patch tiles (one
+// frame position per thread on small patches, and half as many base-level
+// waves per compute unit), else the patch tile's 1024
+constexpr int step_threads(bool store, int ty) { return (!store && ty == 4) ? 512 : kFineThreads; }
 constexpr int kRing = 8;       // window blocks per period
 // union-of-blocks level: Eq. (5b) values one tile hands from substep 1 to the
 // last substep (4 block columns x (16+1) rows + 2 block rows x (kTX+1))

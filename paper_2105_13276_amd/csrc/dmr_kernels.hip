@@ -841,7 +841,9 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
     }
   }
 
-  // -- substep 1: raw E0, n, boundary values ----------------------------------
+  // -- substep 1: raw E0 first (the filter's first phase needs nothing else),
+// then n and the boundary values while the Laplacian of E0 is formed, so
+// the other loads are still in flight during that phase
 #pragma unroll
   for (int q = 0; q < NR; q++) {
     const int k = tid + q * NT;
@@ -852,6 +854,53 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
       rY[cj][ci] = ey_ok(i, j) ? pey[q] : 0.f;
     }
   }
+  __syncthreads();
+  // filter of E0: L over origin -6, filtered over origin -5
+  auto laplace = [&](const float (*rx)[R1W], const float (*ry)[R1W], int rorg, int qorg, int QW,
+                     int QH) {
+    for (int k = tid; k < QH * QW; k += NT) {
+      const int ci = k % QW, cj = k / QW;
+      const int i = i0 + qorg + ci, j = j0 + qorg + cj;
+      const int a = ci + (qorg - rorg), b = cj + (qorg - rorg);  // raw coordinates
+      // all ten reads first (the raw region reaches one entity past this
+      // one on every side), then the selects: one LDS round trip
+      const float xc = rx[b][a], xl = rx[b][a - 1], xr = rx[b][a + 1], xd = rx[b - 1][a],
+                  xu = rx[b + 1][a];
+      const float yc = ry[b][a], yl = ry[b][a - 1], yr = ry[b][a + 1], yd = ry[b - 1][a],
+                  yu = ry[b + 1][a];
+      const float lx = lap5(xc, ex_ok(i - 1, j) ? xl : xc, ex_ok(i + 1, j) ? xr : xc,
+                            ex_ok(i, j - 1) ? xd : xc, ex_ok(i, j + 1) ? xu : xc);
+      const float ly = lap5(yc, ey_ok(i - 1, j) ? yl : yc, ey_ok(i + 1, j) ? yr : yc,
+                            ey_ok(i, j - 1) ? yd : yc, ey_ok(i, j + 1) ? yu : yc);
+      qX[cj][ci] = ex_ok(i, j) ? lx : 0.f;
+      qY[cj][ci] = ey_ok(i, j) ? ly : 0.f;
+    }
+  };
+  auto filtered = [&](const float (*rx)[R1W], const float (*ry)[R1W], int rorg, int forg, int FW,
+                      int FH) {
+    for (int k = tid; k < FH * FW; k += NT) {
+      const int ci = k % FW, cj = k / FW;
+      const int i = i0 + forg + ci, j = j0 + forg + cj;
+      const int a = ci + 1, b = cj + 1;                          // Laplacian coordinates
+      const int ra = ci + (forg - rorg), rb = cj + (forg - rorg);  // raw coordinates
+      // every read first (the Laplacian region reaches one entity past this
+      // one; without the filter its values are unused), then the selects
+      const float ex = rx[rb][ra], ey = ry[rb][ra];
+      const float xc = qX[b][a], xl = qX[b][a - 1], xr = qX[b][a + 1], xd = qX[b - 1][a],
+                  xu = qX[b + 1][a];
+      const float yc = qY[b][a], yl = qY[b][a - 1], yr = qY[b][a + 1], yd = qY[b - 1][a],
+                  yu = qY[b + 1][a];
+      const float fx = filter_e(ex, A.gamma,
+                                lap5(xc, ex_ok(i - 1, j) ? xl : xc, ex_ok(i + 1, j) ? xr : xc,
+                                     ex_ok(i, j - 1) ? xd : xc, ex_ok(i, j + 1) ? xu : xc));
+      const float fy = filter_e(ey, A.gamma,
+                                lap5(yc, ey_ok(i - 1, j) ? yl : yc, ey_ok(i + 1, j) ? yr : yc,
+                                     ey_ok(i, j - 1) ? yd : yc, ey_ok(i, j + 1) ? yu : yc));
+      fX[cj][ci] = ex_ok(i, j) ? ((filt && j != B && j != T) ? fx : ex) : 0.f;
+      fY[cj][ci] = ey_ok(i, j) ? ((filt && i != L && i != R) ? fy : ey) : 0.f;
+    }
+  };
+  if (filt) laplace(rX, rY, -7, -6, Q1W, Q1H);
 #pragma unroll
   for (int q = 0; q < ND; q++) {
     const int k = tid + q * NT;
@@ -897,62 +946,6 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
     sB2[r2][g2 < 0 ? 0 : c2] = ok2 ? cfb(w2a, w2b, b2v0, b2v1, n2a, n2b, frac2) : 0.f;
   }
 
-  // filter of E0: L over origin -6, filtered over origin -5
-  auto laplace = [&](const float (*rx)[R1W], const float (*ry)[R1W], int rorg, int qorg, int QW,
-                     int QH) {
-    for (int k = tid; k < QH * QW; k += NT) {
-      const int ci = k % QW, cj = k / QW;
-      const int i = i0 + qorg + ci, j = j0 + qorg + cj;
-      const int a = ci + (qorg - rorg), b = cj + (qorg - rorg);  // raw coordinates
-      float lx = 0.f, ly = 0.f;
-      if (ex_ok(i, j)) {
-        const float c = rx[b][a];
-        lx = lap5(c, ex_ok(i - 1, j) ? rx[b][a - 1] : c, ex_ok(i + 1, j) ? rx[b][a + 1] : c,
-                  ex_ok(i, j - 1) ? rx[b - 1][a] : c, ex_ok(i, j + 1) ? rx[b + 1][a] : c);
-      }
-      if (ey_ok(i, j)) {
-        const float c = ry[b][a];
-        ly = lap5(c, ey_ok(i - 1, j) ? ry[b][a - 1] : c, ey_ok(i + 1, j) ? ry[b][a + 1] : c,
-                  ey_ok(i, j - 1) ? ry[b - 1][a] : c, ey_ok(i, j + 1) ? ry[b + 1][a] : c);
-      }
-      qX[cj][ci] = lx;
-      qY[cj][ci] = ly;
-    }
-  };
-  auto filtered = [&](const float (*rx)[R1W], const float (*ry)[R1W], int rorg, int forg, int FW,
-                      int FH) {
-    for (int k = tid; k < FH * FW; k += NT) {
-      const int ci = k % FW, cj = k / FW;
-      const int i = i0 + forg + ci, j = j0 + forg + cj;
-      const int a = ci + 1, b = cj + 1;                          // Laplacian coordinates
-      const int ra = ci + (forg - rorg), rb = cj + (forg - rorg);  // raw coordinates
-      float ex = 0.f, ey = 0.f;
-      if (ex_ok(i, j)) {
-        ex = rx[rb][ra];
-        if (filt && j != B && j != T) {
-          const float c = qX[b][a];
-          const float l2 = lap5(c, ex_ok(i - 1, j) ? qX[b][a - 1] : c, ex_ok(i + 1, j) ? qX[b][a + 1] : c,
-                                ex_ok(i, j - 1) ? qX[b - 1][a] : c, ex_ok(i, j + 1) ? qX[b + 1][a] : c);
-          ex = filter_e(ex, A.gamma, l2);
-        }
-      }
-      if (ey_ok(i, j)) {
-        ey = ry[rb][ra];
-        if (filt && i != L && i != R) {
-          const float c = qY[b][a];
-          const float l2 = lap5(c, ey_ok(i - 1, j) ? qY[b][a - 1] : c, ey_ok(i + 1, j) ? qY[b][a + 1] : c,
-                                ey_ok(i, j - 1) ? qY[b - 1][a] : c, ey_ok(i, j + 1) ? qY[b + 1][a] : c);
-          ey = filter_e(ey, A.gamma, l2);
-        }
-      }
-      fX[cj][ci] = ex;
-      fY[cj][ci] = ey;
-    }
-  };
-  if (filt) {
-    laplace(rX, rY, -7, -6, Q1W, Q1H);
-    __syncthreads();
-  }
   filtered(rX, rY, -7, -5, F1W, F1H);
   __syncthreads();
 
@@ -963,13 +956,10 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
     if (k < H1H * H1W) {
       const int ci = k % H1W, cj = k / H1W;
       const int i = i0 - 5 + ci, j = j0 - 5 + cj;
-      float h = 0.f;
-      if (hz_ok(i, j)) {
-        const float dey = fY[cj][ci + 1] - fY[cj][ci];
-        const float dex = fX[cj + 1][ci] - fX[cj][ci];
-        h = faraday(phz[q], A.S, dey, dex);
-      }
-      sH1[cj][ci] = h;
+      const float y1 = fY[cj][ci + 1], y0 = fY[cj][ci], x1 = fX[cj + 1][ci], x0 = fX[cj][ci];
+      const float dey = y1 - y0;
+      const float dex = x1 - x0;
+      sH1[cj][ci] = hz_ok(i, j) ? faraday(phz[q], A.S, dey, dex) : 0.f;
     }
   }
   __syncthreads();
@@ -983,33 +973,26 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
       const int i = i0 - 4 + ci, j = j0 - 4 + cj;
       // J1 is kept over substep 2's new-E region (origin -1)
       const bool keep = ci >= 3 && cj >= 3 && ci - 3 < N2W && cj - 3 < N2H;
-      float exn = 0.f, eyn = 0.f;
-      if (ex_ok(i, j)) {
-        const float e = fX[cj + 1][ci + 1];
-        const float ne = 0.5f * (sN[cj][ci] + sN[cj][ci + 1]);
-        const float kap = A.kn * ne;
-        const float jo = pjx[q];
-        if (j != B && j != T) {
-          const float dh = sH1[cj + 1][ci + 1] - sH1[cj][ci + 1];
-          exn = ampere(e, kap, A.S * dh, A.c1, jo);
-        } else {
-          exn = sB1[j == B ? 0 : 1][ci];
-        }
-        if (keep) j1X[cj - 3][ci - 3] = drude(A.a, jo, kap, e, exn);
-      }
-      if (ey_ok(i, j)) {
-        const float e = fY[cj + 1][ci + 1];
-        const float ne = 0.5f * (sN[cj][ci] + sN[cj + 1][ci]);
-        const float kap = A.kn * ne;
-        const float jo = pjy[q];
-        if (i != L && i != R) {
-          const float dh = sH1[cj + 1][ci + 1] - sH1[cj + 1][ci];
-          eyn = ampere(e, kap, -A.S * dh, A.c1, jo);
-        } else {
-          eyn = sB1[i == L ? 2 : 3][cj];
-        }
-        if (keep) j1Y[cj - 3][ci - 3] = drude(A.a, jo, kap, e, eyn);
-      }
+      // every read first (one LDS round trip), then the selects
+      const float ex = fX[cj + 1][ci + 1], ey = fY[cj + 1][ci + 1];
+      const float n00 = sN[cj][ci], n10 = sN[cj][ci + 1], n01 = sN[cj + 1][ci];
+      const float h11 = sH1[cj + 1][ci + 1], h10 = sH1[cj][ci + 1], h01 = sH1[cj + 1][ci];
+      const float bx = sB1[j == B ? 0 : 1][ci], by = sB1[i == L ? 2 : 3][cj];
+      const bool xok = ex_ok(i, j), yok = ey_ok(i, j);
+      const float nex = 0.5f * (n00 + n10);
+      const float kx = A.kn * nex;
+      const float jox = pjx[q];
+      const float dhx = h11 - h10;
+      const float ax = ampere(ex, kx, A.S * dhx, A.c1, jox);
+      const float exn = xok ? ((j != B && j != T) ? ax : bx) : 0.f;
+      if (keep && xok) j1X[cj - 3][ci - 3] = drude(A.a, jox, kx, ex, exn);
+      const float ney = 0.5f * (n00 + n01);
+      const float ky = A.kn * ney;
+      const float joy = pjy[q];
+      const float dhy = h11 - h01;
+      const float ay = ampere(ey, ky, -A.S * dhy, A.c1, joy);
+      const float eyn = yok ? ((i != L && i != R) ? ay : by) : 0.f;
+      if (keep && yok) j1Y[cj - 3][ci - 3] = drude(A.a, joy, ky, ey, eyn);
       e1X[cj][ci] = exn;
       e1Y[cj][ci] = eyn;
     }
@@ -1023,12 +1006,13 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
     const int r = min(ty + q * RP, TY - 1);  // rows past the tile: discarded
     const int i = i0 + tx, j = j0 + r;
     const int ci = tx + 4, cj = r + 4;
+    const float vl = e1X[cj][ci - 1], vr = e1X[cj][ci], vd = e1Y[cj - 1][ci], vu = e1Y[cj][ci];
     float sx = 0.f, sy = 0.f;
     int cx = 0, cy = 0;
-    if (i > L) { const float v = e1X[cj][ci - 1]; sx += v * v; cx++; }
-    if (i < R) { const float v = e1X[cj][ci]; sx += v * v; cx++; }
-    if (j > B) { const float v = e1Y[cj - 1][ci]; sy += v * v; cy++; }
-    if (j < T) { const float v = e1Y[cj][ci]; sy += v * v; cy++; }
+    if (i > L) { sx += vl * vl; cx++; }
+    if (i < R) { sx += vr * vr; cx++; }
+    if (j > B) { sy += vd * vd; cy++; }
+    if (j < T) { sy += vu * vu; cy++; }
     acc1[q] = pacc[q] + win_e2(sx, cx, sy, cy);
   }
 
@@ -1038,19 +1022,16 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
       const int ci = k % Q2W, cj = k / Q2W;
       const int i = i0 - 3 + ci, j = j0 - 3 + cj;
       const int a = ci + 1, b = cj + 1;
-      float lx = 0.f, ly = 0.f;
-      if (ex_ok(i, j)) {
-        const float c = e1X[b][a];
-        lx = lap5(c, ex_ok(i - 1, j) ? e1X[b][a - 1] : c, ex_ok(i + 1, j) ? e1X[b][a + 1] : c,
-                  ex_ok(i, j - 1) ? e1X[b - 1][a] : c, ex_ok(i, j + 1) ? e1X[b + 1][a] : c);
-      }
-      if (ey_ok(i, j)) {
-        const float c = e1Y[b][a];
-        ly = lap5(c, ey_ok(i - 1, j) ? e1Y[b][a - 1] : c, ey_ok(i + 1, j) ? e1Y[b][a + 1] : c,
-                  ey_ok(i, j - 1) ? e1Y[b - 1][a] : c, ey_ok(i, j + 1) ? e1Y[b + 1][a] : c);
-      }
-      qX[cj][ci] = lx;
-      qY[cj][ci] = ly;
+      const float xc = e1X[b][a], xl = e1X[b][a - 1], xr = e1X[b][a + 1], xd = e1X[b - 1][a],
+                  xu = e1X[b + 1][a];
+      const float yc = e1Y[b][a], yl = e1Y[b][a - 1], yr = e1Y[b][a + 1], yd = e1Y[b - 1][a],
+                  yu = e1Y[b + 1][a];
+      const float lx = lap5(xc, ex_ok(i - 1, j) ? xl : xc, ex_ok(i + 1, j) ? xr : xc,
+                            ex_ok(i, j - 1) ? xd : xc, ex_ok(i, j + 1) ? xu : xc);
+      const float ly = lap5(yc, ey_ok(i - 1, j) ? yl : yc, ey_ok(i + 1, j) ? yr : yc,
+                            ey_ok(i, j - 1) ? yd : yc, ey_ok(i, j + 1) ? yu : yc);
+      qX[cj][ci] = ex_ok(i, j) ? lx : 0.f;
+      qY[cj][ci] = ey_ok(i, j) ? ly : 0.f;
     }
   };
   if (filt) {
@@ -1061,27 +1042,19 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
     const int ci = k % F2W, cj = k / F2W;
     const int i = i0 - 2 + ci, j = j0 - 2 + cj;
     const int a = ci + 1, b = cj + 1;  // Laplacian coordinates (origin -3)
-    float ex = 0.f, ey = 0.f;
-    if (ex_ok(i, j)) {
-      ex = e1X[cj + 2][ci + 2];
-      if (filt && j != B && j != T) {
-        const float c = qX[b][a];
-        const float l2 = lap5(c, ex_ok(i - 1, j) ? qX[b][a - 1] : c, ex_ok(i + 1, j) ? qX[b][a + 1] : c,
-                              ex_ok(i, j - 1) ? qX[b - 1][a] : c, ex_ok(i, j + 1) ? qX[b + 1][a] : c);
-        ex = filter_e(ex, A.gamma, l2);
-      }
-    }
-    if (ey_ok(i, j)) {
-      ey = e1Y[cj + 2][ci + 2];
-      if (filt && i != L && i != R) {
-        const float c = qY[b][a];
-        const float l2 = lap5(c, ey_ok(i - 1, j) ? qY[b][a - 1] : c, ey_ok(i + 1, j) ? qY[b][a + 1] : c,
-                              ey_ok(i, j - 1) ? qY[b - 1][a] : c, ey_ok(i, j + 1) ? qY[b + 1][a] : c);
-        ey = filter_e(ey, A.gamma, l2);
-      }
-    }
-    fX[cj][ci] = ex;
-    fY[cj][ci] = ey;
+    const float ex = e1X[cj + 2][ci + 2], ey = e1Y[cj + 2][ci + 2];
+    const float xc = qX[b][a], xl = qX[b][a - 1], xr = qX[b][a + 1], xd = qX[b - 1][a],
+                xu = qX[b + 1][a];
+    const float yc = qY[b][a], yl = qY[b][a - 1], yr = qY[b][a + 1], yd = qY[b - 1][a],
+                yu = qY[b + 1][a];
+    const float fx = filter_e(ex, A.gamma,
+                              lap5(xc, ex_ok(i - 1, j) ? xl : xc, ex_ok(i + 1, j) ? xr : xc,
+                                   ex_ok(i, j - 1) ? xd : xc, ex_ok(i, j + 1) ? xu : xc));
+    const float fy = filter_e(ey, A.gamma,
+                              lap5(yc, ey_ok(i - 1, j) ? yl : yc, ey_ok(i + 1, j) ? yr : yc,
+                                   ey_ok(i, j - 1) ? yd : yc, ey_ok(i, j + 1) ? yu : yc));
+    fX[cj][ci] = ex_ok(i, j) ? ((filt && j != B && j != T) ? fx : ex) : 0.f;
+    fY[cj][ci] = ey_ok(i, j) ? ((filt && i != L && i != R) ? fy : ey) : 0.f;
   }
   __syncthreads();
 
@@ -1089,13 +1062,12 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
   for (int k = tid; k < H2H * H2W; k += NT) {
     const int ci = k % H2W, cj = k / H2W;
     const int i = i0 - 2 + ci, j = j0 - 2 + cj;
-    float h = 0.f;
-    if (hz_ok(i, j)) {
-      const float dey = fY[cj][ci + 1] - fY[cj][ci];
-      const float dex = fX[cj + 1][ci] - fX[cj][ci];
-      h = faraday(sH1[cj + 3][ci + 3], A.S, dey, dex);
-      if (ci >= 2 && cj >= 2) sto(tb.hz1, ob(i, j), h);
-    }
+    const float y1 = fY[cj][ci + 1], y0 = fY[cj][ci], x1 = fX[cj + 1][ci], x0 = fX[cj][ci];
+    const float ho = sH1[cj + 3][ci + 3];
+    const float dey = y1 - y0;
+    const float dex = x1 - x0;
+    const float h = hz_ok(i, j) ? faraday(ho, A.S, dey, dex) : 0.f;
+    if (hz_ok(i, j) && ci >= 2 && cj >= 2) sto(tb.hz1, ob(i, j), h);
     sH2[cj][ci] = h;
   }
   __syncthreads();
@@ -1106,42 +1078,33 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
     const int i = i0 - 1 + ci, j = j0 - 1 + cj;
     const bool own = ci >= 1 && cj >= 1;
     const unsigned o = ob(i, j);
-    float exn = 0.f, eyn = 0.f;
-    if (ex_ok(i, j)) {
-      const float e = fX[cj + 1][ci + 1];
-      const float ne = 0.5f * (sN[cj + 3][ci + 3] + sN[cj + 3][ci + 4]);
-      const float kap = A.kn * ne;
-      const float jo = j1X[cj][ci];
-      if (j != B && j != T) {
-        const float dh = sH2[cj + 1][ci + 1] - sH2[cj][ci + 1];
-        exn = ampere(e, kap, A.S * dh, A.c1, jo);
-      } else {
-        exn = sB2[j == B ? 0 : 1][ci];
-      }
-      if (own) {
-        const float jn = drude(A.a, jo, kap, e, exn);
-        sto(tb.ex1, o, exn);
-        sto(tb.jx1, o, jn);
-        j2X[cj - 1][ci - 1] = jn;
-      }
+    const float ex = fX[cj + 1][ci + 1], ey = fY[cj + 1][ci + 1];
+    const float n00 = sN[cj + 3][ci + 3], n10 = sN[cj + 3][ci + 4], n01 = sN[cj + 4][ci + 3];
+    const float h11 = sH2[cj + 1][ci + 1], h10 = sH2[cj][ci + 1], h01 = sH2[cj + 1][ci];
+    const float jox = j1X[cj][ci], joy = j1Y[cj][ci];
+    const float bx = sB2[j == B ? 0 : 1][ci], by = sB2[i == L ? 2 : 3][cj];
+    const bool xok = ex_ok(i, j), yok = ey_ok(i, j);
+    const float nex = 0.5f * (n00 + n10);
+    const float kx = A.kn * nex;
+    const float dhx = h11 - h10;
+    const float ax = ampere(ex, kx, A.S * dhx, A.c1, jox);
+    const float exn = xok ? ((j != B && j != T) ? ax : bx) : 0.f;
+    if (xok && own) {
+      const float jn = drude(A.a, jox, kx, ex, exn);
+      sto(tb.ex1, o, exn);
+      sto(tb.jx1, o, jn);
+      j2X[cj - 1][ci - 1] = jn;
     }
-    if (ey_ok(i, j)) {
-      const float e = fY[cj + 1][ci + 1];
-      const float ne = 0.5f * (sN[cj + 3][ci + 3] + sN[cj + 4][ci + 3]);
-      const float kap = A.kn * ne;
-      const float jo = j1Y[cj][ci];
-      if (i != L && i != R) {
-        const float dh = sH2[cj + 1][ci + 1] - sH2[cj + 1][ci];
-        eyn = ampere(e, kap, -A.S * dh, A.c1, jo);
-      } else {
-        eyn = sB2[i == L ? 2 : 3][cj];
-      }
-      if (own) {
-        const float jn = drude(A.a, jo, kap, e, eyn);
-        sto(tb.ey1, o, eyn);
-        sto(tb.jy1, o, jn);
-        j2Y[cj - 1][ci - 1] = jn;
-      }
+    const float ney = 0.5f * (n00 + n01);
+    const float ky = A.kn * ney;
+    const float dhy = h11 - h01;
+    const float ay = ampere(ey, ky, -A.S * dhy, A.c1, joy);
+    const float eyn = yok ? ((i != L && i != R) ? ay : by) : 0.f;
+    if (yok && own) {
+      const float jn = drude(A.a, joy, ky, ey, eyn);
+      sto(tb.ey1, o, eyn);
+      sto(tb.jy1, o, jn);
+      j2Y[cj - 1][ci - 1] = jn;
     }
     e2X[cj][ci] = exn;
     e2Y[cj][ci] = eyn;
@@ -1155,12 +1118,13 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
     const int i = i0 + tx, j = j0 + r;
     if (r >= TY || !nd_ok(i, j)) continue;
     const int ci = tx + 1, cj = r + 1;
+    const float vl = e2X[cj][ci - 1], vr = e2X[cj][ci], vd = e2Y[cj - 1][ci], vu = e2Y[cj][ci];
     float sx = 0.f, sy = 0.f;
     int cx = 0, cy = 0;
-    if (i > L) { const float v = e2X[cj][ci - 1]; sx += v * v; cx++; }
-    if (i < R) { const float v = e2X[cj][ci]; sx += v * v; cx++; }
-    if (j > B) { const float v = e2Y[cj - 1][ci]; sy += v * v; cy++; }
-    if (j < T) { const float v = e2Y[cj][ci]; sy += v * v; cy++; }
+    if (i > L) { sx += vl * vl; cx++; }
+    if (i < R) { sx += vr * vr; cx++; }
+    if (j > B) { sy += vd * vd; cy++; }
+    if (j < T) { sy += vu * vu; cy++; }
     sto(tb.acc, ob(i, j), acc1[q] + win_e2(sx, cx, sy, cy));
   }
 
@@ -1243,6 +1207,412 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
         A.st1y[o] = e1Y[r + 4][tx + 4];
         if (A.st2y) A.st2y[o] = e2Y[r + 1][tx + 1];
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Both patch substeps of the combined step (rectangle, r = 2, patch tiles
+// computing the coarse boundary E themselves), laid out for short phases.
+// Every array of the tile lives in one LDS frame, the raw-E region of the
+// first substep (origin (-7, -7) from the tile corner, FW x FH), and each
+// thread owns fixed frame positions for the whole launch: their coordinates,
+// validity and clamped positions are formed once, and every phase reads its
+// neighbours at constant offsets.  Entities outside the patch hold the value
+// of the nearest entity inside it: raw E and J come from clamped addresses,
+// and the Laplacians and the first substep's new E are formed at the clamped
+// position.  That is the filter's zero-gradient rule at the patch edge, so no
+// phase tests its neighbours.  Every entity is computed with the operations
+// and operands of fine2_tile (the helpers above), so the results are
+// identical to it and to two one-substep launches.
+// ---------------------------------------------------------------------------
+template <int TY, int NT, int TW>
+__device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, float cey_src,
+                                           float chz_src) {
+  constexpr int FW = TW + 13, FH = TY + 13, FN = FW * FH;
+  constexpr int NP = (FN + NT - 1) / NT;  // frame positions per thread
+  constexpr int N1W = TW + 7, N1H = TY + 7, N2W = TW + 1, N2H = TY + 1;
+  __shared__ float rX[FN], rY[FN];    // raw E0 (clamped)
+  __shared__ float qX[FN], qY[FN];    // L(E0), then L(E1) (at clamped positions)
+  __shared__ float fX[FN], fY[FN];    // filtered E0, then filtered E1
+  __shared__ float sH1[FN], sH2[FN];  // Hz after substeps 1 and 2
+  __shared__ float e1X[FN], e1Y[FN];  // E1 (at clamped positions)
+  __shared__ float e2X[FN], e2Y[FN];  // E2
+  __shared__ float j2X[FN], j2Y[FN];  // J2 of the tile's own edges
+  __shared__ float sN[FN];
+  __shared__ float sB1[5][N1W], sB2[5][N2W];  // Eq. (5b) values of substeps 1 and 2
+  constexpr int CW = TW / 2 + 6, CH = TY / 2 + 6;
+  __shared__ float sC[5][CW > CH ? CW : CH];  // coarse E on the boundary lines after the step
+  __shared__ float sO[5][CW > CH ? CW : CH];  // and before it
+
+  const int i0 = A.L + bx * TW;
+  const int j0 = A.B + by * TY;
+  const int tid = threadIdx.x;
+  const int L = A.L, R = A.R, B = A.B, T = A.T;
+  const bool filt = A.gamma > 0.f;
+  const float frac1 = A.frac, frac2 = 1.f;
+  const int ib = max(i0 - 8, L), jb = max(j0 - 8, B);
+  const TileBase tb(A, ib, jb);
+  auto cl = [=](int v, int lo, int hi) { return min(max(v, lo), hi); };
+  const int fi0 = i0 - 7, fj0 = j0 - 7;  // physical position of frame entry 0
+
+  // -- per position: frame offset, flags, clamped offsets; issue every load
+  int po[NP], ci_[NP], cj_[NP], ocx[NP], ocy[NP], cxi[NP], cxj[NP], cyi[NP], cyj[NP];
+  bool inf[NP], hzok[NP], exok[NP], eyok[NP], ndok[NP];
+  float pex[NP], pey[NP], phz[NP], pjx[NP], pjy[NP], pn[NP], pacc[NP];
+#pragma unroll
+  for (int q = 0; q < NP; q++) {
+    const int p = tid + q * NT;
+    inf[q] = p < FN;
+    const int pp = inf[q] ? p : FN - 1;
+    po[q] = pp;
+    const int ci = pp % FW, cj = pp / FW;
+    ci_[q] = ci; cj_[q] = cj;
+    const int i = fi0 + ci, j = fj0 + cj;
+    hzok[q] = i >= L && i < R && j >= B && j < T;
+    exok[q] = i >= L && i < R && j >= B && j <= T;
+    eyok[q] = i >= L && i <= R && j >= B && j < T;
+    ndok[q] = i >= L && i <= R && j >= B && j <= T;
+    const int ixc = cl(i, L, R - 1), jxc = cl(j, B, T);
+    const int iyc = cl(i, L, R), jyc = cl(j, B, T - 1);
+    ocx[q] = (jxc - fj0) * FW + (ixc - fi0);
+    ocy[q] = (jyc - fj0) * FW + (iyc - fi0);
+    cxi[q] = ixc; cxj[q] = jxc; cyi[q] = iyc; cyj[q] = jyc;
+    const unsigned ox = tb.off(ixc, jxc), oy = tb.off(iyc, jyc);
+    const unsigned oh = tb.off(cl(i, L, R - 1), cl(j, B, T - 1));
+    const unsigned on = tb.off(cl(i, L, R), cl(j, B, T));
+    pex[q] = ldo(tb.ex0, ox);
+    pey[q] = ldo(tb.ey0, oy);
+    phz[q] = ldo(tb.hz0, oh);
+    pjx[q] = ldo(tb.jx0, ox);
+    pjy[q] = ldo(tb.jy0, oy);
+    pn[q] = ldo(tb.n, on);
+    pacc[q] = 0.f;
+    if (ci >= 7 && ci < 7 + TW && cj >= 7 && cj < 7 + TY) pacc[q] = ldo(tb.acc, on);
+  }
+  // coarse state around the patch boundary lines, for the coarse E after the
+  // step there (as in fine2_tile)
+  const int cx0 = ((i0 - 4) >> 1) - 1, cy0 = ((j0 - 4) >> 1) - 1;
+  int cg = -1, cc = 0;
+  float qc[12];
+  if (tid < CW) { cg = 0; cc = tid; }
+  else if (tid < 2 * CW) { cg = 1; cc = tid - CW; }
+  else if (tid < 2 * CW + CH) { cg = 2; cc = tid - 2 * CW; }
+  else if (tid < 2 * CW + 2 * CH) { cg = 3; cc = tid - 2 * CW - CH; }
+  {
+    const unsigned cp4 = (unsigned)A.cpitch * 4u;
+    const int NXc = A.cnx, NYc = A.cny;
+    auto cidx = [=](int a, int b) {  // clamped coarse byte offset
+      const int aa = a < 0 ? 0 : (a > NXc ? NXc : a), bb = b < 0 ? 0 : (b > NYc ? NYc : b);
+      return __umul24((unsigned)bb, cp4) + ((unsigned)aa << 2);
+    };
+    if (cg <= 1) {  // x-edge (ic, J) of a boundary row (threads without a role: cg = -1)
+      const int ic = cx0 + cc, J = cg == 1 ? (T >> 1) : (B >> 1);
+      qc[0] = ldo(A.cex0, cidx(ic, J - 1)); qc[1] = ldo(A.cex0, cidx(ic, J));
+      qc[2] = ldo(A.cex0, cidx(ic, J + 1));
+      qc[3] = ldo(A.cey0, cidx(ic, J - 1)); qc[4] = ldo(A.cey0, cidx(ic + 1, J - 1));
+      qc[5] = ldo(A.cey0, cidx(ic, J)); qc[6] = ldo(A.cey0, cidx(ic + 1, J));
+      qc[7] = ldo(A.chz0, cidx(ic, J - 1)); qc[8] = ldo(A.chz0, cidx(ic, J));
+      qc[9] = ldo(A.cjx0, cidx(ic, J)); qc[10] = ldo(A.cn0, cidx(ic, J));
+      qc[11] = ldo(A.cn0, cidx(ic + 1, J));
+    } else {        // y-edge (I, jc) of a boundary column
+      const int jc = cy0 + cc, I = cg == 3 ? (R >> 1) : (L >> 1);
+      qc[0] = ldo(A.cey0, cidx(I - 1, jc)); qc[1] = ldo(A.cey0, cidx(I, jc));
+      qc[2] = ldo(A.cey0, cidx(I + 1, jc));
+      qc[3] = ldo(A.cex0, cidx(I - 1, jc)); qc[4] = ldo(A.cex0, cidx(I - 1, jc + 1));
+      qc[5] = ldo(A.cex0, cidx(I, jc)); qc[6] = ldo(A.cex0, cidx(I, jc + 1));
+      qc[7] = ldo(A.chz0, cidx(I - 1, jc)); qc[8] = ldo(A.chz0, cidx(I, jc));
+      qc[9] = ldo(A.cjy0, cidx(I, jc)); qc[10] = ldo(A.cn0, cidx(I, jc));
+      qc[11] = ldo(A.cn0, cidx(I, jc + 1));
+    }
+  }
+  // Eq. (5b) edges of both substeps, formed while the loads are in flight
+  // thread tid's boundary edge of a substep's new-E region (origin orig,
+  // NW_ x NH_): group g (x-edges of row B / T, y-edges of column L / R),
+  // position c along the region, lower coarse edge k (weights w0, w1 on
+  // coarse edges k, k + 1: offsets 1/4, 3/4), ok = it exists in the region
+  struct Bnd {
+    int g, c, k;
+    float w0, w1;
+    bool ok;
+  };
+  auto bnd = [=](int orig, int NW_, int NH_) {
+    // branch-free: group from the thread index, then both line kinds
+    // evaluated and selected (the line by arithmetic on g: a select over g
+    // can become a table in private memory)
+    const int gx = (tid >= NW_) + (tid >= 2 * NW_) + (tid >= 2 * NW_ + NH_) +
+                   (tid >= 2 * NW_ + 2 * NH_);  // 4: no edge
+    Bnd r;
+    r.g = gx < 4 ? gx : -1;
+    r.c = gx < 2 ? tid - gx * NW_ : tid - 2 * NW_ - (gx - 2) * NH_;
+    const int side = gx & 1;
+    const int xi = i0 + orig + r.c, xj = B + side * (T - B);  // x-edge (rows B, T)
+    const int yj = j0 + orig + r.c, yi = L + side * (R - L);  // y-edge (columns L, R)
+    const bool xok = xi >= L && xi < R && xj >= j0 + orig && xj < j0 + orig + NH_;
+    const bool yok = yj >= B && yj < T && yi >= i0 + orig && yi < i0 + orig + NW_;
+    r.ok = gx < 2 ? xok : (gx < 4 && yok);
+    const int e = gx < 2 ? xi : yj;
+    const bool ev = (e & 1) == 0;
+    r.k = ev ? (e >> 1) - 1 : (e >> 1);
+    r.w0 = ev ? 0.25f : 0.75f;
+    r.w1 = ev ? 0.75f : 0.25f;
+    if (!r.ok) { r.k = 0; r.w0 = 0.f; r.w1 = 0.f; }
+    return r;
+  };
+  const Bnd b1 = bnd(-4, N1W, N1H), b2 = bnd(-1, N2W, N2H);
+  const int g1 = b1.g, c1_ = b1.c, k1 = b1.k, g2 = b2.g, c2 = b2.c, k2 = b2.k;
+  const float w1a = b1.w0, w1b = b1.w1, w2a = b2.w0, w2b = b2.w1;
+  const bool ok1 = b1.ok, ok2 = b2.ok;
+  // region tests in frame coordinates (origin o, width TW + w, height TY + h)
+  auto in_reg = [](int ci, int cj, int o, int w, int h) {
+    const int a = ci - 7 - o, b = cj - 7 - o;
+    return a >= 0 && a < TW + w && b >= 0 && b < TY + h;
+  };
+  auto own = [](int ci, int cj) { return ci >= 7 && ci < 7 + TW && cj >= 7 && cj < 7 + TY; };
+
+  // -- raw E0 (clamped values: entities outside the patch hold their nearest
+  // entity's value)
+#pragma unroll
+  for (int q = 0; q < NP; q++)
+    if (inf[q]) { rX[po[q]] = pex[q]; rY[po[q]] = pey[q]; }
+  __syncthreads();
+
+  // -- L(E0) over origin -6 at the clamped positions; n; coarse E after the
+  // step on the boundary lines
+#pragma unroll
+  for (int q = 0; q < NP; q++) {
+    if (filt && inf[q] && in_reg(ci_[q], cj_[q], -6, 11, 11)) {
+      const int ox = ocx[q], oy = ocy[q];
+      qX[po[q]] = lap5(rX[ox], rX[ox - 1], rX[ox + 1], rX[ox - FW], rX[ox + FW]);
+      qY[po[q]] = lap5(rY[oy], rY[oy - 1], rY[oy + 1], rY[oy - FW], rY[oy + FW]);
+    }
+    if (inf[q]) sN[po[q]] = ndok[q] ? pn[q] : 0.f;
+  }
+  {
+    float v;
+    const float S = A.cS, c1 = A.cc1;
+    if (cg <= 1) {
+      const int ic = cx0 + cc;
+      float hp = base_hz(qc[7], S, qc[4], qc[3], qc[1], qc[0]);
+      if (ic == A.cis - 1) hp += S * cey_src;
+      float h = base_hz(qc[8], S, qc[6], qc[5], qc[2], qc[1]);
+      if (ic == A.cis - 1) h += S * cey_src;
+      const float kap = base_kap(A.ckn, qc[10], qc[11]);
+      v = base_ex(qc[1], kap, S, h, hp, c1, qc[9]);
+    } else {
+      const int I = cg == 3 ? (R >> 1) : (L >> 1);
+      float h = base_hz(qc[8], S, qc[2], qc[1], qc[6], qc[5]);
+      if (I == A.cis - 1) h += S * cey_src;
+      float hl = base_hz(qc[7], S, qc[1], qc[0], qc[4], qc[3]);
+      if (I - 1 == A.cis - 1) hl += S * cey_src;
+      float curl = -S * (h - hl);
+      if (I == A.cis) curl += S * chz_src;
+      const float kap = base_kap(A.ckn, qc[10], qc[11]);
+      v = base_ey(qc[1], kap, curl, c1, qc[9]);
+    }
+    sC[cg < 0 ? 4 : cg][cg < 0 ? 0 : cc] = v;
+    sO[cg < 0 ? 4 : cg][cg < 0 ? 0 : cc] = qc[1];  // the line's own coarse E entering
+  }
+  __syncthreads();
+
+  // -- Eq. (5b) values of both substeps; filtered E0 over origin -5
+  {
+    const int x1 = g1 >= 2 ? cy0 : cx0, x2 = g2 >= 2 ? cy0 : cx0;
+    const int r1 = g1 < 0 ? 4 : g1, r2 = g2 < 0 ? 4 : g2;
+    const float o1a = ok1 ? sO[r1][k1 - x1] : 0.f, o1b = ok1 ? sO[r1][k1 + 1 - x1] : 0.f;
+    const float n1a = ok1 ? sC[r1][k1 - x1] : 0.f, n1b = ok1 ? sC[r1][k1 + 1 - x1] : 0.f;
+    const float o2a = ok2 ? sO[r2][k2 - x2] : 0.f, o2b = ok2 ? sO[r2][k2 + 1 - x2] : 0.f;
+    const float n2a = ok2 ? sC[r2][k2 - x2] : 0.f, n2b = ok2 ? sC[r2][k2 + 1 - x2] : 0.f;
+    sB1[r1][g1 < 0 ? 0 : c1_] = ok1 ? cfb(w1a, w1b, o1a, o1b, n1a, n1b, frac1) : 0.f;
+    sB2[r2][g2 < 0 ? 0 : c2] = ok2 ? cfb(w2a, w2b, o2a, o2b, n2a, n2b, frac2) : 0.f;
+  }
+#pragma unroll
+  for (int q = 0; q < NP; q++) {
+    if (!(inf[q] && in_reg(ci_[q], cj_[q], -5, 9, 9))) continue;
+    const int p = po[q], j = fj0 + cj_[q], i = fi0 + ci_[q];
+    const float ex = rX[p], ey = rY[p];
+    const float xc = qX[p], xl = qX[p - 1], xr = qX[p + 1], xd = qX[p - FW], xu = qX[p + FW];
+    const float yc = qY[p], yl = qY[p - 1], yr = qY[p + 1], yd = qY[p - FW], yu = qY[p + FW];
+    const float fx = filter_e(ex, A.gamma, lap5(xc, xl, xr, xd, xu));
+    const float fy = filter_e(ey, A.gamma, lap5(yc, yl, yr, yd, yu));
+    fX[p] = exok[q] ? ((filt && j != B && j != T) ? fx : ex) : 0.f;
+    fY[p] = eyok[q] ? ((filt && i != L && i != R) ? fy : ey) : 0.f;
+  }
+  __syncthreads();
+
+  // -- Faraday, H1 over origin -5
+#pragma unroll
+  for (int q = 0; q < NP; q++) {
+    if (!(inf[q] && in_reg(ci_[q], cj_[q], -5, 8, 8))) continue;
+    const int p = po[q];
+    const float y1 = fY[p + 1], y0 = fY[p], x1 = fX[p + FW], x0 = fX[p];
+    const float dey = y1 - y0;
+    const float dex = x1 - x0;
+    sH1[p] = hzok[q] ? faraday(phz[q], A.S, dey, dex) : 0.f;
+  }
+  __syncthreads();
+
+  // -- Ampere + Drude, E1 over origin -4 at the clamped positions; J1 of the
+  // entities substep 2 updates (origin -1) kept in registers
+  float j1x[NP], j1y[NP];
+#pragma unroll
+  for (int q = 0; q < NP; q++) {
+    j1x[q] = 0.f; j1y[q] = 0.f;
+    if (!(inf[q] && in_reg(ci_[q], cj_[q], -4, 7, 7))) continue;
+    const int p = po[q];
+    const int ox = ocx[q], oy = ocy[q];
+    const int ixc = cxi[q], jxc = cxj[q], iyc = cyi[q], jyc = cyj[q];
+    const float ex = fX[ox], ey = fY[oy];
+    const float nx0 = sN[ox], nx1 = sN[ox + 1], ny0 = sN[oy], ny1 = sN[oy + FW];
+    const float hx1 = sH1[ox], hx0 = sH1[ox - FW], hy1 = sH1[oy], hy0 = sH1[oy - 1];
+    const float bx = sB1[jxc == B ? 0 : 1][ixc - (i0 - 4)];
+    const float by = sB1[iyc == L ? 2 : 3][jyc - (j0 - 4)];
+    const float nex = 0.5f * (nx0 + nx1);
+    const float kx = A.kn * nex;
+    const float dhx = hx1 - hx0;
+    const float ax = ampere(ex, kx, A.S * dhx, A.c1, pjx[q]);
+    const float exn = (jxc != B && jxc != T) ? ax : bx;
+    const float ney = 0.5f * (ny0 + ny1);
+    const float ky = A.kn * ney;
+    const float dhy = hy1 - hy0;
+    const float ay = ampere(ey, ky, -A.S * dhy, A.c1, pjy[q]);
+    const float eyn = (iyc != L && iyc != R) ? ay : by;
+    e1X[p] = exn;
+    e1Y[p] = eyn;
+    j1x[q] = drude(A.a, pjx[q], kx, ex, exn);
+    j1y[q] = drude(A.a, pjy[q], ky, ey, eyn);
+  }
+  __syncthreads();
+
+  // -- window after substep 1 at the tile's own nodes (registers)
+  float acc1[NP];
+#pragma unroll
+  for (int q = 0; q < NP; q++) {
+    acc1[q] = 0.f;
+    if (!(inf[q] && own(ci_[q], cj_[q]))) continue;
+    const int p = po[q], i = fi0 + ci_[q], j = fj0 + cj_[q];
+    const float vl = e1X[p - 1], vr = e1X[p], vd = e1Y[p - FW], vu = e1Y[p];
+    float sx = 0.f, sy = 0.f;
+    int cx = 0, cy = 0;
+    if (i > L) { sx += vl * vl; cx++; }
+    if (i < R) { sx += vr * vr; cx++; }
+    if (j > B) { sy += vd * vd; cy++; }
+    if (j < T) { sy += vu * vu; cy++; }
+    acc1[q] = pacc[q] + win_e2(sx, cx, sy, cy);
+  }
+  // -- substep 2: L(E1) over origin -3 at the clamped positions
+  if (filt) {
+#pragma unroll
+    for (int q = 0; q < NP; q++) {
+      if (!(inf[q] && in_reg(ci_[q], cj_[q], -3, 5, 5))) continue;
+      const int ox = ocx[q], oy = ocy[q];
+      qX[po[q]] = lap5(e1X[ox], e1X[ox - 1], e1X[ox + 1], e1X[ox - FW], e1X[ox + FW]);
+      qY[po[q]] = lap5(e1Y[oy], e1Y[oy - 1], e1Y[oy + 1], e1Y[oy - FW], e1Y[oy + FW]);
+    }
+    __syncthreads();
+  }
+  // filtered E1 over origin -2
+#pragma unroll
+  for (int q = 0; q < NP; q++) {
+    if (!(inf[q] && in_reg(ci_[q], cj_[q], -2, 3, 3))) continue;
+    const int p = po[q], j = fj0 + cj_[q], i = fi0 + ci_[q];
+    const float ex = e1X[p], ey = e1Y[p];
+    const float xc = qX[p], xl = qX[p - 1], xr = qX[p + 1], xd = qX[p - FW], xu = qX[p + FW];
+    const float yc = qY[p], yl = qY[p - 1], yr = qY[p + 1], yd = qY[p - FW], yu = qY[p + FW];
+    const float fx = filter_e(ex, A.gamma, lap5(xc, xl, xr, xd, xu));
+    const float fy = filter_e(ey, A.gamma, lap5(yc, yl, yr, yd, yu));
+    fX[p] = exok[q] ? ((filt && j != B && j != T) ? fx : ex) : 0.f;
+    fY[p] = eyok[q] ? ((filt && i != L && i != R) ? fy : ey) : 0.f;
+  }
+  __syncthreads();
+
+  // -- Faraday, H2 over origin -2; the tile's own cells are stored
+#pragma unroll
+  for (int q = 0; q < NP; q++) {
+    if (!(inf[q] && in_reg(ci_[q], cj_[q], -2, 2, 2))) continue;
+    const int p = po[q];
+    const float y1 = fY[p + 1], y0 = fY[p], x1 = fX[p + FW], x0 = fX[p];
+    const float ho = sH1[p];
+    const float dey = y1 - y0;
+    const float dex = x1 - x0;
+    const float h = hzok[q] ? faraday(ho, A.S, dey, dex) : 0.f;
+    if (hzok[q] && own(ci_[q], cj_[q])) sto(tb.hz1, tb.off(fi0 + ci_[q], fj0 + cj_[q]), h);
+    sH2[p] = h;
+  }
+  __syncthreads();
+
+  // -- Ampere + Drude, E2 / J2 over origin -1; the tile's own edges stored
+#pragma unroll
+  for (int q = 0; q < NP; q++) {
+    if (!(inf[q] && in_reg(ci_[q], cj_[q], -1, 1, 1))) continue;
+    const int p = po[q], i = fi0 + ci_[q], j = fj0 + cj_[q];
+    const bool ow = own(ci_[q], cj_[q]);
+    const unsigned o = tb.off(i, j);
+    const float ex = fX[p], ey = fY[p];
+    const float n00 = sN[p], n10 = sN[p + 1], n01 = sN[p + FW];
+    const float h11 = sH2[p], h10 = sH2[p - FW], h01 = sH2[p - 1];
+    const float bx = sB2[j == B ? 0 : 1][i - (i0 - 1)], by = sB2[i == L ? 2 : 3][j - (j0 - 1)];
+    const float nex = 0.5f * (n00 + n10);
+    const float kx = A.kn * nex;
+    const float dhx = h11 - h10;
+    const float ax = ampere(ex, kx, A.S * dhx, A.c1, j1x[q]);
+    const float exn = exok[q] ? ((j != B && j != T) ? ax : bx) : 0.f;
+    if (exok[q] && ow) {
+      const float jn = drude(A.a, j1x[q], kx, ex, exn);
+      sto(tb.ex1, o, exn);
+      sto(tb.jx1, o, jn);
+      j2X[p] = jn;
+    }
+    const float ney = 0.5f * (n00 + n01);
+    const float ky = A.kn * ney;
+    const float dhy = h11 - h01;
+    const float ay = ampere(ey, ky, -A.S * dhy, A.c1, j1y[q]);
+    const float eyn = eyok[q] ? ((i != L && i != R) ? ay : by) : 0.f;
+    if (eyok[q] && ow) {
+      const float jn = drude(A.a, j1y[q], ky, ey, eyn);
+      sto(tb.ey1, o, eyn);
+      sto(tb.jy1, o, jn);
+      j2Y[p] = jn;
+    }
+    e2X[p] = exn;
+    e2Y[p] = eyn;
+  }
+  __syncthreads();
+
+  // -- window after substep 2 and the fine -> coarse transfer, own nodes
+#pragma unroll
+  for (int q = 0; q < NP; q++) {
+    if (!(inf[q] && own(ci_[q], cj_[q]))) continue;
+    const int p = po[q], i = fi0 + ci_[q], j = fj0 + cj_[q];
+    if (ndok[q]) {
+      const float vl = e2X[p - 1], vr = e2X[p], vd = e2Y[p - FW], vu = e2Y[p];
+      float sx = 0.f, sy = 0.f;
+      int cx = 0, cy = 0;
+      if (i > L) { sx += vl * vl; cx++; }
+      if (i < R) { sx += vr * vr; cx++; }
+      if (j > B) { sy += vd * vd; cy++; }
+      if (j < T) { sy += vu * vu; cy++; }
+      sto(tb.acc, tb.off(i, j), acc1[q] + win_e2(sx, cx, sy, cy));
+    }
+    if (((i - L) | (j - B)) & 1) continue;
+    const int a = i >> 1, b = j >> 1;
+    const size_t co = (size_t)b * A.cpitch + a;
+    if (hzok[q]) {
+      float s = 0.f;
+      for (int da = 0; da < 2; da++)
+        for (int db = 0; db < 2; db++) {
+          const float hold = sH1[p + db * FW + da];
+          s += 0.5f * (hold + sH2[p + db * FW + da]);
+        }
+      A.chz[co] = 0.25f * s;
+    }
+    if (exok[q] && j > B && j < T) {
+      A.cex[co] = 0.5f * (e2X[p] + e2X[p + 1]);
+      A.cjx[co] = j2X[p] + j2X[p + 1];  // J~ scales with dt
+    }
+    if (eyok[q] && i > L && i < R) {
+      A.cey[co] = 0.5f * (e2Y[p] + e2Y[p + FW]);
+      A.cjy[co] = j2Y[p] + j2Y[p + FW];
     }
   }
 }
@@ -1717,16 +2087,44 @@ struct RowData {
 // Raw loads from clamped (always valid) addresses: nothing depends on the
 // values until the row is consumed DEPTH rows later, so the loads stay in
 // flight across iterations.
+// Addressing of the streaming kernel: 32-bit byte offsets from the uniform
+// plane bases (a plane is far below 4 GB; pitch * 4 < 2^24 is required by
+// the parameter checks) save the per-lane 64-bit address arithmetic where
+// the step is issue-bound (short segments, DEPTH 2, on grids too small to
+// fill the chip); the long-segment form keeps 64-bit indices, which streamed
+// faster (measured on 4096x2048 and 8192x4096).
+#ifndef DMR_EM_O32
+#define DMR_EM_O32(DEPTH) ((DEPTH) == 2)
+#endif
+struct RowAddr {
+  size_t o64;
+  unsigned o32;
+};
+__device__ __forceinline__ RowAddr row_addr(const EMArgs& A, int i, int j) {
+  return RowAddr{(size_t)j * A.pitch + i,
+                 __umul24((unsigned)j, (unsigned)A.pitch * 4u) + ((unsigned)i << 2)};
+}
+template <bool O32>
+__device__ __forceinline__ float ldr(const float* p, const RowAddr& a) {
+  if constexpr (O32) return ldo(p, a.o32);
+  else return p[a.o64];
+}
+template <bool O32>
+__device__ __forceinline__ void str(float* p, const RowAddr& a, float v) {
+  if constexpr (O32) sto(p, a.o32, v);
+  else p[a.o64] = v;
+}
+
+template <bool O32>
 __device__ inline RowData load_row(const EMArgs& A, int i, int j) {
   RowData r;
   const int NX = A.R, NY = A.T;
   const int ic = min(max(i, 0), NX), jc = min(max(j, 0), NY);
   const int ic1 = min(max(i + 1, 0), NX);
-  const size_t o = (size_t)jc * A.pitch + ic;
-  const size_t o1 = (size_t)jc * A.pitch + ic1;
-  r.ex = A.ex0[o]; r.jx = A.jx0[o]; r.ey = A.ey0[o]; r.jy = A.jy0[o];
-  r.ey1 = A.ey0[o1]; r.hz = A.hz0[o]; r.n = A.n[o]; r.n1 = A.n[o1];
-  r.acc = A.acc[o];
+  const RowAddr o = row_addr(A, ic, jc), o1 = row_addr(A, ic1, jc);
+  r.ex = ldr<O32>(A.ex0, o); r.jx = ldr<O32>(A.jx0, o); r.ey = ldr<O32>(A.ey0, o);
+  r.jy = ldr<O32>(A.jy0, o); r.ey1 = ldr<O32>(A.ey0, o1); r.hz = ldr<O32>(A.hz0, o);
+  r.n = ldr<O32>(A.n, o); r.n1 = ldr<O32>(A.n, o1); r.acc = ldr<O32>(A.acc, o);
   return r;
 }
 
@@ -1756,6 +2154,7 @@ __device__ inline RowData mask_row(const EMArgs& A, const RowData& q, int i, int
 template <int DEPTH, bool ST = false>
 __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, int seg,
                                                int nseg, float ey_src, float hz_src) {
+  constexpr bool O32 = DMR_EM_O32(DEPTH);
   const int NX = A.R, NY = A.T;
   const int lane = threadIdx.x & 63;
   const int c0 = cw * 62;  // first own column of this wave
@@ -1778,7 +2177,7 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, i
   // rows js .. js+DEPTH in flight; buf[0] is the current row
   RowData buf[DEPTH + 1];
 #pragma unroll
-  for (int d = 0; d <= DEPTH; d++) buf[d] = load_row(A, i, min(js + d, j1));
+  for (int d = 0; d <= DEPTH; d++) buf[d] = load_row<O32>(A, i, min(js + d, j1));
   float hzn_p = 0.f, eyn_p = 0.f, exn_p = 0.f, exo_p = 0.f;
   // row-0 Mur edge Ex(i,0) waits for Ex(i,1): its old value, current, density
   float ex0_old = 0.f, jx0_old = 0.f, kap0 = 0.f, acc0 = 0.f;
@@ -1788,11 +2187,11 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, i
     const RowData cur = mask_row(A, rc, i, j);
     const RowData nxt = mask_row(A, rn, i, j + 1);
     const bool store = j >= j0 && j < j1;
-    const size_t o = (size_t)j * A.pitch + i;
+    const RowAddr o = row_addr(A, i, j);  // used only where (i, j) is stored (exists)
     if (ST && store && own) {  // replay: the values entering the step
-      if (exv) A.stix[o] = cur.ex;
-      if (eyc && j < NY) A.stiy[o] = cur.ey;
-      if (eyc) A.stn[o] = cur.n;
+      if (exv) str<O32>(A.stix, o, cur.ex);
+      if (eyc && j < NY) str<O32>(A.stiy, o, cur.ey);
+      if (eyc) str<O32>(A.stn, o, cur.n);
     }
 
     // Faraday, Eq. (2)
@@ -1800,7 +2199,7 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, i
     if (exv && j < NY) {
       hzn = base_hz(cur.hz, S, cur.ey1, cur.ey, nxt.ex, cur.ex);
       if (i == A.is - 1) hzn += S * ey_src;
-      if (store && own && !(skc && j >= A.sB && j < A.sT)) A.hz1[o] = hzn;
+      if (store && own && !(skc && j >= A.sB && j < A.sT)) str<O32>(A.hz1, o, hzn);
     }
     const float hzl = __shfl_up(hzn, 1, 64);  // Hz(i-1, j)
 
@@ -1810,17 +2209,17 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, i
     if (exv) {
       if (j > 0 && j < NY) {
         exn = base_ex(cur.ex, kapx, S, hzn, hzn_p, c1, cur.jx);
-        if (ST && store && own) A.stox[o] = exn;
+        if (ST && store && own) str<O32>(A.stox, o, exn);
         if (store && own && !(skc && j > A.sB && j < A.sT)) {
-          A.ex1[o] = exn;
-          A.jx1[o] = a * cur.jx + 2.f * kapx * (cur.ex + exn);
+          str<O32>(A.ex1, o, exn);
+          str<O32>(A.jx1, o, a * cur.jx + 2.f * kapx * (cur.ex + exn));
         }
       } else if (j == NY) {
         exn = mur_y ? exo_p + cm * (exn_p - cur.ex) : 0.f;
-        if (ST && store && own) A.stox[o] = exn;
+        if (ST && store && own) str<O32>(A.stox, o, exn);
         if (store && own) {
-          A.ex1[o] = exn;
-          A.jx1[o] = a * cur.jx + 2.f * kapx * (cur.ex + exn);
+          str<O32>(A.ex1, o, exn);
+          str<O32>(A.jx1, o, a * cur.jx + 2.f * kapx * (cur.ex + exn));
         }
       } else if (j == 0) {  // finished with row 1
         ex0_old = cur.ex;
@@ -1842,10 +2241,10 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, i
       if (i == 0) eyn = mur_x ? orr + cm * (nr - cur.ey) : 0.f;
       if (i == NX) eyn = mur_x ? ol + cm * (nl - cur.ey) : 0.f;
     }
-    if (ST && eyc && j < NY && store && own) A.stoy[o] = eyn;
+    if (ST && eyc && j < NY && store && own) str<O32>(A.stoy, o, eyn);
     if (eyc && j < NY && store && own && !(sky && j >= A.sB && j < A.sT)) {
-      A.ey1[o] = eyn;
-      A.jy1[o] = a * cur.jy + 2.f * kapy * (cur.ey + eyn);
+      str<O32>(A.ey1, o, eyn);
+      str<O32>(A.jy1, o, a * cur.jy + 2.f * kapy * (cur.ey + eyn));
     }
 
     // deferred bottom row: Mur edge Ex(i,0) and the window at node row 0
@@ -1854,9 +2253,9 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, i
       if (exv) {
         ex0 = mur_y ? cur.ex + cm * (exn - ex0_old) : 0.f;
         if (own) {
-          if (ST) A.stox[i] = ex0;
-          A.ex1[i] = ex0;
-          A.jx1[i] = a * jx0_old + 2.f * kap0 * (ex0_old + ex0);
+          if (ST) str<O32>(A.stox, row_addr(A, i, 0), ex0);
+          str<O32>(A.ex1, row_addr(A, i, 0), ex0);
+          str<O32>(A.jx1, row_addr(A, i, 0), a * jx0_old + 2.f * kap0 * (ex0_old + ex0));
         }
       }
       const float exl0 = __shfl_up(ex0, 1, 64);
@@ -1866,7 +2265,7 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, i
         if (i > 0) { sx += exl0 * exl0; cx++; }
         if (i < NX) { sx += ex0 * ex0; cx++; }
         e2 = (cx == 2 ? 0.5f * sx : sx) + eyn_p * eyn_p;
-        A.acc[i] = acc0 + e2;
+        str<O32>(A.acc, row_addr(A, i, 0), acc0 + e2);
       }
     }
     // window at node (i, j)
@@ -1880,7 +2279,7 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, i
         sy += eyn_p * eyn_p; cy++;
         if (j < NY) { sy += eyn * eyn; cy++; }
         const float e2 = (cx == 2 ? 0.5f * sx : sx) + (cy == 2 ? 0.5f * sy : sy);
-        A.acc[o] = cur.acc + e2;
+        str<O32>(A.acc, o, cur.acc + e2);
       }
     } else {
       acc0 = cur.acc;
@@ -1901,7 +2300,7 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, i
       const int j = jb + u;
       row(j, buf[u], buf[u == DEPTH ? 0 : u + 1]);
       // rows past j1 are not needed: re-read row j1 (a cache hit)
-      buf[u] = load_row(A, i, min(j + DEPTH + 1, j1));
+      buf[u] = load_row<O32>(A, i, min(j + DEPTH + 1, j1));
     }
   }
 }
@@ -2193,25 +2592,31 @@ __global__ __launch_bounds__(kThreads) void k_fine_stream(EMArgs A, int seg, int
 
 // ---------------------------------------------------------------------------
 // Combined step: the base-level EM step and both patch substeps of a coarse
-// step in one launch.  Blocks [0, ncb) are base-level waves (16 per block,
-// column-wave w % waves_x of segment w / waves_x, blocks banded over the
-// XCDs); the rest are 64 x TY patch tiles, which compute the coarse E after
-// the step on their boundary lines themselves.  The base waves do not store
+// step in one launch.  The first blocks are TW x TY patch tiles, the last ncb
+// are base-level waves (16 per block, column-wave w % waves_x of segment
+// w / waves_x, blocks banded over the XCDs).  The tiles compute the coarse E
+// after the step on their boundary lines themselves.  The base waves do not store
 // the coarse entities the tiles' fine -> coarse transfer writes.
 // ---------------------------------------------------------------------------
 template <int DEPTH, int TY, bool ST = false, int TW = kTX>
-__global__ __launch_bounds__(kFineThreads) void k_dmr_step(EMArgs C, EMArgs F, int seg, int nseg,
-                                                           int waves_x, int ncb, int nbx_f) {
+__global__ __launch_bounds__(step_threads(ST, TY)) void k_dmr_step(EMArgs C, EMArgs F, int seg,
+                                                                   int nseg, int waves_x, int ncb,
+                                                                   int nbx_f) {
+  constexpr int NTC = step_threads(ST, TY);
+  // the patch tiles are the longer chain: they take the first blocks, which
+  // the dispatcher starts first
+  const int ntl = gridDim.x - ncb;
   const int b = blockIdx.x;
-  if (b < ncb) {
-    const int w = xcd_band(b, ncb) * (kFineThreads / 64) + (threadIdx.x >> 6);
+  if (b >= ntl) {
+    const int w = xcd_band(b - ntl, ncb) * (NTC / 64) + (threadIdx.x >> 6);
     const int k = w / waves_x;
     if (k < nseg) em_stream_body<DEPTH, ST>(C, w % waves_x, k, seg, nseg, C.ey_src, C.hz_src);
     return;
   }
-  const int t = b - ncb;
-  fine2_tile<TY, kFineThreads, true, ST, false, TW>(F, t % nbx_f, t / nbx_f, F.cey_src,
-                                                    F.chz_src);
+  if constexpr (!ST && TY == 4)
+    fine2_fast<TY, NTC, TW>(F, b % nbx_f, b / nbx_f, F.cey_src, F.chz_src);
+  else
+    fine2_tile<TY, NTC, true, ST, false, TW>(F, b % nbx_f, b / nbx_f, F.cey_src, F.chz_src);
 }
 
 // Batched combined step: blk[b] = (instance, g), g >= 0 a group of 16 base
@@ -2392,13 +2797,14 @@ hipError_t launch_dmr_step(const EMArgs& C, const EMArgs& F, int seg, int depth,
                            int tw, hipStream_t st) {
   const int waves_x = (C.R + 1 + 61) / 62;
   const int nseg = stream_segments(C.T, seg);
-  const int wpb = kFineThreads / 64;
+  const int nt = step_threads(C.stix != nullptr, ty);
+  const int wpb = nt / 64;
   const int ncb = (waves_x * nseg + wpb - 1) / wpb;
   if (ty != 4) tw = kTX;  // narrow tiles: 4-row tiles only
   else if (tw <= 0) tw = patch_tile_width(F, ncb);
   const int nbx_f = (F.R - F.L + 1 + tw - 1) / tw;
   const int nby_f = (F.T - F.B + 1 + ty - 1) / ty;
-  const dim3 g(ncb + nbx_f * nby_f), blk(kFineThreads);
+  const dim3 g(ncb + nbx_f * nby_f), blk(nt);
 #define DMR_STEP(D, T_, W_) hipLaunchKernelGGL((k_dmr_step<D, T_, false, W_>), g, blk, 0, st, C, F, seg, nseg, waves_x, ncb, nbx_f)
 #define DMR_STEP_ST(D, T_, W_) hipLaunchKernelGGL((k_dmr_step<D, T_, true, W_>), g, blk, 0, st, C, F, seg, nseg, waves_x, ncb, nbx_f)
   if (C.stix) {  // replay: stores for the adjoint
