@@ -1233,14 +1233,12 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
   constexpr int NP = (FN + NT - 1) / NT;  // frame positions per thread
   constexpr int N1W = TW + 7, N1H = TY + 7, N2W = TW + 1, N2H = TY + 1;
   __shared__ float rX[FN], rY[FN];    // raw E0 (clamped)
-  __shared__ float qX[FN], qY[FN];    // L(E0), then L(E1) (at clamped positions)
   __shared__ float fX[FN], fY[FN];    // filtered E0, then filtered E1
-  __shared__ float sH1[FN], sH2[FN];  // Hz after substeps 1 and 2
+  __shared__ float sH0[FN], sH1[FN], sH2[FN];  // Hz entering, after substeps 1 and 2
   __shared__ float e1X[FN], e1Y[FN];  // E1 (at clamped positions)
   __shared__ float e2X[FN], e2Y[FN];  // E2
   __shared__ float j2X[FN], j2Y[FN];  // J2 of the tile's own edges
   __shared__ float sN[FN];
-  __shared__ float sB1[5][N1W], sB2[5][N2W];  // Eq. (5b) values of substeps 1 and 2
   constexpr int CW = TW / 2 + 6, CH = TY / 2 + 6;
   __shared__ float sC[5][CW > CH ? CW : CH];  // coarse E on the boundary lines after the step
   __shared__ float sO[5][CW > CH ? CW : CH];  // and before it
@@ -1326,43 +1324,6 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
       qc[11] = ldo(A.cn0, cidx(I, jc + 1));
     }
   }
-  // Eq. (5b) edges of both substeps, formed while the loads are in flight
-  // thread tid's boundary edge of a substep's new-E region (origin orig,
-  // NW_ x NH_): group g (x-edges of row B / T, y-edges of column L / R),
-  // position c along the region, lower coarse edge k (weights w0, w1 on
-  // coarse edges k, k + 1: offsets 1/4, 3/4), ok = it exists in the region
-  struct Bnd {
-    int g, c, k;
-    float w0, w1;
-    bool ok;
-  };
-  auto bnd = [=](int orig, int NW_, int NH_) {
-    // branch-free: group from the thread index, then both line kinds
-    // evaluated and selected (the line by arithmetic on g: a select over g
-    // can become a table in private memory)
-    const int gx = (tid >= NW_) + (tid >= 2 * NW_) + (tid >= 2 * NW_ + NH_) +
-                   (tid >= 2 * NW_ + 2 * NH_);  // 4: no edge
-    Bnd r;
-    r.g = gx < 4 ? gx : -1;
-    r.c = gx < 2 ? tid - gx * NW_ : tid - 2 * NW_ - (gx - 2) * NH_;
-    const int side = gx & 1;
-    const int xi = i0 + orig + r.c, xj = B + side * (T - B);  // x-edge (rows B, T)
-    const int yj = j0 + orig + r.c, yi = L + side * (R - L);  // y-edge (columns L, R)
-    const bool xok = xi >= L && xi < R && xj >= j0 + orig && xj < j0 + orig + NH_;
-    const bool yok = yj >= B && yj < T && yi >= i0 + orig && yi < i0 + orig + NW_;
-    r.ok = gx < 2 ? xok : (gx < 4 && yok);
-    const int e = gx < 2 ? xi : yj;
-    const bool ev = (e & 1) == 0;
-    r.k = ev ? (e >> 1) - 1 : (e >> 1);
-    r.w0 = ev ? 0.25f : 0.75f;
-    r.w1 = ev ? 0.75f : 0.25f;
-    if (!r.ok) { r.k = 0; r.w0 = 0.f; r.w1 = 0.f; }
-    return r;
-  };
-  const Bnd b1 = bnd(-4, N1W, N1H), b2 = bnd(-1, N2W, N2H);
-  const int g1 = b1.g, c1_ = b1.c, k1 = b1.k, g2 = b2.g, c2 = b2.c, k2 = b2.k;
-  const float w1a = b1.w0, w1b = b1.w1, w2a = b2.w0, w2b = b2.w1;
-  const bool ok1 = b1.ok, ok2 = b2.ok;
   // region tests in frame coordinates (origin o, width TW + w, height TY + h)
   auto in_reg = [](int ci, int cj, int o, int w, int h) {
     const int a = ci - 7 - o, b = cj - 7 - o;
@@ -1377,83 +1338,89 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
     if (inf[q]) { rX[po[q]] = pex[q]; rY[po[q]] = pey[q]; }
   __syncthreads();
 
-  // -- L(E0) over origin -6 at the clamped positions; n; coarse E after the
-  // step on the boundary lines
+  // L(L(E)) of the filter at frame offset p of a padded field x: the
+  // Laplacian at p and at its four neighbours, a neighbour outside the patch
+  // replaced by p itself (zero gradient at the patch edge); the same
+  // Laplacians, in the same order, as forming them in a phase of their own
+  auto lap2 = [](const float* x, int p, bool lv, bool rv, bool dv, bool uv) {
+    const float c = x[p], l1 = x[p - 1], r1 = x[p + 1], d1 = x[p - FW], u1 = x[p + FW];
+    const float l2 = x[p - 2], r2 = x[p + 2], d2 = x[p - 2 * FW], u2 = x[p + 2 * FW];
+    const float ld = x[p - 1 - FW], lu = x[p - 1 + FW], rd = x[p + 1 - FW], ru = x[p + 1 + FW];
+    const float Lc = lap5(c, l1, r1, d1, u1);
+    const float Ll = lap5(l1, l2, c, ld, lu);
+    const float Lr = lap5(r1, c, r2, rd, ru);
+    const float Ld = lap5(d1, ld, rd, d2, c);
+    const float Lu = lap5(u1, lu, ru, c, u2);
+    return lap5(Lc, lv ? Ll : Lc, rv ? Lr : Lc, dv ? Ld : Lc, uv ? Lu : Lc);
+  };
+  // Eq. (5b) value of the boundary edge at position e along line g (0/1:
+  // x-edges of rows B/T, 2/3: y-edges of columns L/R) from the coarse E on
+  // the line before (sO) and after (sC) the coarse step; offsets 1/4, 3/4
+  constexpr int SW = CW > CH ? CW : CH;
+  auto cfb_at = [=](int g, int e, float fr) {
+    const bool ev = (e & 1) == 0;
+    const int k = ev ? (e >> 1) - 1 : (e >> 1);
+    const int x = min(max(k - (g >= 2 ? cy0 : cx0), 0), SW - 2);
+    return cfb(ev ? 0.25f : 0.75f, ev ? 0.75f : 0.25f, sO[g][x], sO[g][x + 1], sC[g][x],
+               sC[g][x + 1], fr);
+  };
+  const float S = A.S;
+
+  // -- phase A: n, old Hz, coarse E after the step on the boundary lines;
+  // filtered E0 over origin -5
 #pragma unroll
-  for (int q = 0; q < NP; q++) {
-    if (filt && inf[q] && in_reg(ci_[q], cj_[q], -6, 11, 11)) {
-      const int ox = ocx[q], oy = ocy[q];
-      qX[po[q]] = lap5(rX[ox], rX[ox - 1], rX[ox + 1], rX[ox - FW], rX[ox + FW]);
-      qY[po[q]] = lap5(rY[oy], rY[oy - 1], rY[oy + 1], rY[oy - FW], rY[oy + FW]);
-    }
-    if (inf[q]) sN[po[q]] = ndok[q] ? pn[q] : 0.f;
-  }
+  for (int q = 0; q < NP; q++)
+    if (inf[q]) { sN[po[q]] = ndok[q] ? pn[q] : 0.f; sH0[po[q]] = phz[q]; }
   {
     float v;
-    const float S = A.cS, c1 = A.cc1;
+    const float cS = A.cS, c1 = A.cc1;
     if (cg <= 1) {
       const int ic = cx0 + cc;
-      float hp = base_hz(qc[7], S, qc[4], qc[3], qc[1], qc[0]);
-      if (ic == A.cis - 1) hp += S * cey_src;
-      float h = base_hz(qc[8], S, qc[6], qc[5], qc[2], qc[1]);
-      if (ic == A.cis - 1) h += S * cey_src;
+      float hp = base_hz(qc[7], cS, qc[4], qc[3], qc[1], qc[0]);
+      if (ic == A.cis - 1) hp += cS * cey_src;
+      float h = base_hz(qc[8], cS, qc[6], qc[5], qc[2], qc[1]);
+      if (ic == A.cis - 1) h += cS * cey_src;
       const float kap = base_kap(A.ckn, qc[10], qc[11]);
-      v = base_ex(qc[1], kap, S, h, hp, c1, qc[9]);
+      v = base_ex(qc[1], kap, cS, h, hp, c1, qc[9]);
     } else {
       const int I = cg == 3 ? (R >> 1) : (L >> 1);
-      float h = base_hz(qc[8], S, qc[2], qc[1], qc[6], qc[5]);
-      if (I == A.cis - 1) h += S * cey_src;
-      float hl = base_hz(qc[7], S, qc[1], qc[0], qc[4], qc[3]);
-      if (I - 1 == A.cis - 1) hl += S * cey_src;
-      float curl = -S * (h - hl);
-      if (I == A.cis) curl += S * chz_src;
+      float h = base_hz(qc[8], cS, qc[2], qc[1], qc[6], qc[5]);
+      if (I == A.cis - 1) h += cS * cey_src;
+      float hl = base_hz(qc[7], cS, qc[1], qc[0], qc[4], qc[3]);
+      if (I - 1 == A.cis - 1) hl += cS * cey_src;
+      float curl = -cS * (h - hl);
+      if (I == A.cis) curl += cS * chz_src;
       const float kap = base_kap(A.ckn, qc[10], qc[11]);
       v = base_ey(qc[1], kap, curl, c1, qc[9]);
     }
     sC[cg < 0 ? 4 : cg][cg < 0 ? 0 : cc] = v;
     sO[cg < 0 ? 4 : cg][cg < 0 ? 0 : cc] = qc[1];  // the line's own coarse E entering
   }
-  __syncthreads();
-
-  // -- Eq. (5b) values of both substeps; filtered E0 over origin -5
-  {
-    const int x1 = g1 >= 2 ? cy0 : cx0, x2 = g2 >= 2 ? cy0 : cx0;
-    const int r1 = g1 < 0 ? 4 : g1, r2 = g2 < 0 ? 4 : g2;
-    const float o1a = ok1 ? sO[r1][k1 - x1] : 0.f, o1b = ok1 ? sO[r1][k1 + 1 - x1] : 0.f;
-    const float n1a = ok1 ? sC[r1][k1 - x1] : 0.f, n1b = ok1 ? sC[r1][k1 + 1 - x1] : 0.f;
-    const float o2a = ok2 ? sO[r2][k2 - x2] : 0.f, o2b = ok2 ? sO[r2][k2 + 1 - x2] : 0.f;
-    const float n2a = ok2 ? sC[r2][k2 - x2] : 0.f, n2b = ok2 ? sC[r2][k2 + 1 - x2] : 0.f;
-    sB1[r1][g1 < 0 ? 0 : c1_] = ok1 ? cfb(w1a, w1b, o1a, o1b, n1a, n1b, frac1) : 0.f;
-    sB2[r2][g2 < 0 ? 0 : c2] = ok2 ? cfb(w2a, w2b, o2a, o2b, n2a, n2b, frac2) : 0.f;
-  }
 #pragma unroll
   for (int q = 0; q < NP; q++) {
     if (!(inf[q] && in_reg(ci_[q], cj_[q], -5, 9, 9))) continue;
     const int p = po[q], j = fj0 + cj_[q], i = fi0 + ci_[q];
     const float ex = rX[p], ey = rY[p];
-    const float xc = qX[p], xl = qX[p - 1], xr = qX[p + 1], xd = qX[p - FW], xu = qX[p + FW];
-    const float yc = qY[p], yl = qY[p - 1], yr = qY[p + 1], yd = qY[p - FW], yu = qY[p + FW];
-    const float fx = filter_e(ex, A.gamma, lap5(xc, xl, xr, xd, xu));
-    const float fy = filter_e(ey, A.gamma, lap5(yc, yl, yr, yd, yu));
-    fX[p] = exok[q] ? ((filt && j != B && j != T) ? fx : ex) : 0.f;
-    fY[p] = eyok[q] ? ((filt && i != L && i != R) ? fy : ey) : 0.f;
+    float fx = ex, fy = ey;
+    if (filt) {
+      if (j != B && j != T) fx = filter_e(ex, A.gamma, lap2(rX, p, i > L, i < R - 1, j > B, j < T));
+      if (i != L && i != R) fy = filter_e(ey, A.gamma, lap2(rY, p, i > L, i < R, j > B, j < T - 1));
+    }
+    fX[p] = exok[q] ? fx : 0.f;
+    fY[p] = eyok[q] ? fy : 0.f;
   }
   __syncthreads();
 
-  // -- Faraday, H1 over origin -5
-#pragma unroll
-  for (int q = 0; q < NP; q++) {
-    if (!(inf[q] && in_reg(ci_[q], cj_[q], -5, 8, 8))) continue;
-    const int p = po[q];
-    const float y1 = fY[p + 1], y0 = fY[p], x1 = fX[p + FW], x0 = fX[p];
+  // -- phase B: substep 1, Faraday and Ampere + Drude together.  E1 over
+  // origin -4 at the clamped positions, from the H1 of the cells beside the
+  // edge (formed here); the cell's own H1 kept for substep 2 and the
+  // transfer; J1 of the entities substep 2 updates in registers
+  auto far1 = [=](int c, bool ok) {
+    const float y1 = fY[c + 1], y0 = fY[c], x1 = fX[c + FW], x0 = fX[c], ho = sH0[c];
     const float dey = y1 - y0;
     const float dex = x1 - x0;
-    sH1[p] = hzok[q] ? faraday(phz[q], A.S, dey, dex) : 0.f;
-  }
-  __syncthreads();
-
-  // -- Ampere + Drude, E1 over origin -4 at the clamped positions; J1 of the
-  // entities substep 2 updates (origin -1) kept in registers
+    return ok ? faraday(ho, S, dey, dex) : 0.f;
+  };
   float j1x[NP], j1y[NP];
 #pragma unroll
   for (int q = 0; q < NP; q++) {
@@ -1462,29 +1429,32 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
     const int p = po[q];
     const int ox = ocx[q], oy = ocy[q];
     const int ixc = cxi[q], jxc = cxj[q], iyc = cyi[q], jyc = cyj[q];
+    const float hx1 = far1(ox, jxc < T), hx0 = far1(ox - FW, jxc > B);
+    const float hy1 = far1(oy, iyc < R), hy0 = far1(oy - 1, iyc > L);
     const float ex = fX[ox], ey = fY[oy];
     const float nx0 = sN[ox], nx1 = sN[ox + 1], ny0 = sN[oy], ny1 = sN[oy + FW];
-    const float hx1 = sH1[ox], hx0 = sH1[ox - FW], hy1 = sH1[oy], hy0 = sH1[oy - 1];
-    const float bx = sB1[jxc == B ? 0 : 1][ixc - (i0 - 4)];
-    const float by = sB1[iyc == L ? 2 : 3][jyc - (j0 - 4)];
+    const float bx = cfb_at(jxc == T ? 1 : 0, ixc, frac1);
+    const float by = cfb_at(iyc == R ? 3 : 2, jyc, frac1);
     const float nex = 0.5f * (nx0 + nx1);
     const float kx = A.kn * nex;
     const float dhx = hx1 - hx0;
-    const float ax = ampere(ex, kx, A.S * dhx, A.c1, pjx[q]);
+    const float ax = ampere(ex, kx, S * dhx, A.c1, pjx[q]);
     const float exn = (jxc != B && jxc != T) ? ax : bx;
     const float ney = 0.5f * (ny0 + ny1);
     const float ky = A.kn * ney;
     const float dhy = hy1 - hy0;
-    const float ay = ampere(ey, ky, -A.S * dhy, A.c1, pjy[q]);
+    const float ay = ampere(ey, ky, -S * dhy, A.c1, pjy[q]);
     const float eyn = (iyc != L && iyc != R) ? ay : by;
     e1X[p] = exn;
     e1Y[p] = eyn;
     j1x[q] = drude(A.a, pjx[q], kx, ex, exn);
     j1y[q] = drude(A.a, pjy[q], ky, ey, eyn);
+    sH1[p] = hzok[q] ? hx1 : 0.f;  // a valid cell is its own x-edge's (ox == p)
   }
   __syncthreads();
 
-  // -- window after substep 1 at the tile's own nodes (registers)
+  // -- phase C: window after substep 1 at the tile's own nodes (registers);
+  // filtered E1 over origin -2
   float acc1[NP];
 #pragma unroll
   for (int q = 0; q < NP; q++) {
@@ -1500,62 +1470,48 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
     if (j < T) { sy += vu * vu; cy++; }
     acc1[q] = pacc[q] + win_e2(sx, cx, sy, cy);
   }
-  // -- substep 2: L(E1) over origin -3 at the clamped positions
-  if (filt) {
-#pragma unroll
-    for (int q = 0; q < NP; q++) {
-      if (!(inf[q] && in_reg(ci_[q], cj_[q], -3, 5, 5))) continue;
-      const int ox = ocx[q], oy = ocy[q];
-      qX[po[q]] = lap5(e1X[ox], e1X[ox - 1], e1X[ox + 1], e1X[ox - FW], e1X[ox + FW]);
-      qY[po[q]] = lap5(e1Y[oy], e1Y[oy - 1], e1Y[oy + 1], e1Y[oy - FW], e1Y[oy + FW]);
-    }
-    __syncthreads();
-  }
-  // filtered E1 over origin -2
 #pragma unroll
   for (int q = 0; q < NP; q++) {
     if (!(inf[q] && in_reg(ci_[q], cj_[q], -2, 3, 3))) continue;
     const int p = po[q], j = fj0 + cj_[q], i = fi0 + ci_[q];
     const float ex = e1X[p], ey = e1Y[p];
-    const float xc = qX[p], xl = qX[p - 1], xr = qX[p + 1], xd = qX[p - FW], xu = qX[p + FW];
-    const float yc = qY[p], yl = qY[p - 1], yr = qY[p + 1], yd = qY[p - FW], yu = qY[p + FW];
-    const float fx = filter_e(ex, A.gamma, lap5(xc, xl, xr, xd, xu));
-    const float fy = filter_e(ey, A.gamma, lap5(yc, yl, yr, yd, yu));
-    fX[p] = exok[q] ? ((filt && j != B && j != T) ? fx : ex) : 0.f;
-    fY[p] = eyok[q] ? ((filt && i != L && i != R) ? fy : ey) : 0.f;
+    float fx = ex, fy = ey;
+    if (filt) {
+      if (j != B && j != T) fx = filter_e(ex, A.gamma, lap2(e1X, p, i > L, i < R - 1, j > B, j < T));
+      if (i != L && i != R) fy = filter_e(ey, A.gamma, lap2(e1Y, p, i > L, i < R, j > B, j < T - 1));
+    }
+    fX[p] = exok[q] ? fx : 0.f;
+    fY[p] = eyok[q] ? fy : 0.f;
   }
   __syncthreads();
 
-  // -- Faraday, H2 over origin -2; the tile's own cells are stored
-#pragma unroll
-  for (int q = 0; q < NP; q++) {
-    if (!(inf[q] && in_reg(ci_[q], cj_[q], -2, 2, 2))) continue;
-    const int p = po[q];
-    const float y1 = fY[p + 1], y0 = fY[p], x1 = fX[p + FW], x0 = fX[p];
-    const float ho = sH1[p];
+  // -- phase D: substep 2, Faraday and Ampere + Drude together over origin
+  // -1; the tile's own entities stored
+  auto far2 = [=](int c, bool ok) {
+    const float y1 = fY[c + 1], y0 = fY[c], x1 = fX[c + FW], x0 = fX[c], ho = sH1[c];
     const float dey = y1 - y0;
     const float dex = x1 - x0;
-    const float h = hzok[q] ? faraday(ho, A.S, dey, dex) : 0.f;
-    if (hzok[q] && own(ci_[q], cj_[q])) sto(tb.hz1, tb.off(fi0 + ci_[q], fj0 + cj_[q]), h);
-    sH2[p] = h;
-  }
-  __syncthreads();
-
-  // -- Ampere + Drude, E2 / J2 over origin -1; the tile's own edges stored
+    return ok ? faraday(ho, S, dey, dex) : 0.f;
+  };
 #pragma unroll
   for (int q = 0; q < NP; q++) {
     if (!(inf[q] && in_reg(ci_[q], cj_[q], -1, 1, 1))) continue;
     const int p = po[q], i = fi0 + ci_[q], j = fj0 + cj_[q];
     const bool ow = own(ci_[q], cj_[q]);
     const unsigned o = tb.off(i, j);
+    const bool cin = i >= L && i < R;  // column of cells inside the patch
+    const float h11 = far2(p, hzok[q]);
+    const float h10 = far2(p - FW, cin && j - 1 >= B && j - 1 < T);
+    const float h01 = far2(p - 1, i - 1 >= L && i - 1 < R && j >= B && j < T);
+    if (hzok[q] && ow) sto(tb.hz1, o, h11);
+    sH2[p] = h11;
     const float ex = fX[p], ey = fY[p];
     const float n00 = sN[p], n10 = sN[p + 1], n01 = sN[p + FW];
-    const float h11 = sH2[p], h10 = sH2[p - FW], h01 = sH2[p - 1];
-    const float bx = sB2[j == B ? 0 : 1][i - (i0 - 1)], by = sB2[i == L ? 2 : 3][j - (j0 - 1)];
+    const float bx = cfb_at(j == T ? 1 : 0, i, frac2), by = cfb_at(i == R ? 3 : 2, j, frac2);
     const float nex = 0.5f * (n00 + n10);
     const float kx = A.kn * nex;
     const float dhx = h11 - h10;
-    const float ax = ampere(ex, kx, A.S * dhx, A.c1, j1x[q]);
+    const float ax = ampere(ex, kx, S * dhx, A.c1, j1x[q]);
     const float exn = exok[q] ? ((j != B && j != T) ? ax : bx) : 0.f;
     if (exok[q] && ow) {
       const float jn = drude(A.a, j1x[q], kx, ex, exn);
@@ -1566,7 +1522,7 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
     const float ney = 0.5f * (n00 + n01);
     const float ky = A.kn * ney;
     const float dhy = h11 - h01;
-    const float ay = ampere(ey, ky, -A.S * dhy, A.c1, j1y[q]);
+    const float ay = ampere(ey, ky, -S * dhy, A.c1, j1y[q]);
     const float eyn = eyok[q] ? ((i != L && i != R) ? ay : by) : 0.f;
     if (eyok[q] && ow) {
       const float jn = drude(A.a, j1y[q], ky, ey, eyn);
@@ -2294,14 +2250,67 @@ __device__ __forceinline__ void em_stream_body(const EMArgs& A, int cw, int k, i
   // the loads stay unconditional (rows past the segment are computed
   // from clamped reads and not stored), so the wait for a slot's loads is
   // exact rather than a drain of everything in flight
-  for (int jb = js; jb < j1; jb += DEPTH + 1) {
-#pragma unroll
-    for (int u = 0; u <= DEPTH; u++) {
-      const int j = jb + u;
-      row(j, buf[u], buf[u == DEPTH ? 0 : u + 1]);
-      // rows past j1 are not needed: re-read row j1 (a cache hit)
-      buf[u] = load_row<O32>(A, i, min(j + DEPTH + 1, j1));
+  // A wave whose columns and rows are all interior (no outer boundary, no
+  // source column, no patch region, rows 1 .. NY-1 with the next row inside)
+  // takes the same arithmetic without the tests for those cases: every
+  // condition the general row tests holds there, and each value is formed
+  // by the same expressions.  Short segments only, where the step is
+  // issue-bound (measured: no gain on the long-segment, bandwidth-bound form)
+  constexpr bool FAST = !ST && DEPTH == 2;
+  auto row_fast = [&](int j, const RowData& cur, const RowData& nxt) {
+    const bool store = j >= j0 && j < j1;
+    const RowAddr o = row_addr(A, i, j);
+    const float hzn = base_hz(cur.hz, S, cur.ey1, cur.ey, nxt.ex, cur.ex);
+    if (store && own) str<O32>(A.hz1, o, hzn);
+    const float hzl = __shfl_up(hzn, 1, 64);
+    const float kapx = base_kap(kn, cur.n, cur.n1);
+    const float exn = base_ex(cur.ex, kapx, S, hzn, hzn_p, c1, cur.jx);
+    if (store && own) {
+      str<O32>(A.ex1, o, exn);
+      str<O32>(A.jx1, o, a * cur.jx + 2.f * kapx * (cur.ex + exn));
     }
+    const float kapy = base_kap(kn, cur.n, nxt.n);
+    const float curl = -S * (hzn - hzl);
+    const float eyn = base_ey(cur.ey, kapy, curl, c1, cur.jy);
+    if (store && own) {
+      str<O32>(A.ey1, o, eyn);
+      str<O32>(A.jy1, o, a * cur.jy + 2.f * kapy * (cur.ey + eyn));
+    }
+    const float exl = __shfl_up(exn, 1, 64);
+    if (store && own) {
+      float sx = 0.f, sy = 0.f;
+      sx += exl * exl;
+      sx += exn * exn;
+      sy += eyn_p * eyn_p;
+      sy += eyn * eyn;
+      const float hx = 0.5f * sx;
+      const float hy = 0.5f * sy;
+      const float e2 = hx + hy;
+      str<O32>(A.acc, o, cur.acc + e2);
+    }
+    hzn_p = hzn;
+    eyn_p = eyn;
+  };
+  const bool col_in = c0 - 2 >= 1 && c0 + 61 <= NX - 1;
+  const bool no_src = A.is <= 0 || A.is < c0 - 2 || A.is - 1 > c0 + 61;
+  const bool no_skip = !A.skip_on || A.sR < c0 - 2 || A.sL > c0 + 61 || A.sT < js || A.sB > j1;
+  const bool fast = FAST && col_in && no_src && no_skip && js >= 1 && j1 <= NY - 1;
+  auto run = [&](auto&& rowf) {
+    for (int jb = js; jb < j1; jb += DEPTH + 1) {
+#pragma unroll
+      for (int u = 0; u <= DEPTH; u++) {
+        const int j = jb + u;
+        rowf(j, buf[u], buf[u == DEPTH ? 0 : u + 1]);
+        // rows past j1 are not needed: re-read row j1 (a cache hit)
+        buf[u] = load_row<O32>(A, i, min(j + DEPTH + 1, j1));
+      }
+    }
+  };
+  if constexpr (FAST) {
+    if (fast) run(row_fast);
+    else run(row);
+  } else {
+    run(row);
   }
 }
 
