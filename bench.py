@@ -356,9 +356,13 @@ def main():
                 "traffic": rec.get(key) if key else None,
                 "alg_bytes_per_launch": alg_bytes, "avg_launch_us": per_launch_ms * 1e3,
                 "avg_launch_us_rocprofv3": trc.get(key) if key else None,
+                "frac_rocprofv3": (alg_bytes / (trc[key] * 1e-6) / 1e9 / 8000.0
+                                   if (key and key in trc and alg_bytes) else None),
                 "timing": "HIP events on the library's stream, one pair per run of "
                           "consecutive launches of the class (runs of 8 between "
-                          "continuity steps), timed region = the whole DMR run",
+                          "continuity steps), timed region = the whole DMR run; "
+                          "frac_rocprofv3 uses the committed kernel trace of the "
+                          "same kernel source instead (no gaps between launches)",
                 "note": "config-1 state (7.9 MB) is cache resident and its step kernel is "
                         "latency-bound; HBM-bound figures are in roofline_large"}
 
