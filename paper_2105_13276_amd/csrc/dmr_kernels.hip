@@ -115,14 +115,48 @@ __device__ __forceinline__ void sto(float* p, unsigned b, float v) {
   *(float*)((char*)p + b) = v;
 }
 
-template <int TY, int NT, bool UN = false>
-__device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int tix = 0) {
-  constexpr int EW = kTX + 3, EH = TY + 3;  // old E (filtered)
-  constexpr int HW = kTX + 2, HH = TY + 2;  // new Hz
-  constexpr int NW = kTX + 1, NH = TY + 1;  // new E
-  constexpr int DW = kTX + 2, DH = TY + 2;  // density
-  constexpr int RW = kTX + 7, RH = TY + 7;  // raw E for the filter
-  constexpr int QW = kTX + 5, QH = TY + 5;  // Laplacian of raw E
+// LDS of one patch-substep tile (64 x TY nodes), declared by the kernel so
+// that the boundary and the interior forms of the tile share it
+template <int TY, bool UN>
+struct FineLds {
+  static constexpr int EW = kTX + 3, EH = TY + 3;  // old E (filtered)
+  static constexpr int HW = kTX + 2, HH = TY + 2;  // new Hz
+  static constexpr int NW = kTX + 1, NH = TY + 1;  // new E
+  static constexpr int DW = kTX + 2, DH = TY + 2;  // density
+  static constexpr int RW = kTX + 7, RH = TY + 7;  // raw E for the filter
+  static constexpr int QW = kTX + 5, QH = TY + 5;  // Laplacian of raw E
+  // Eq. (5b) values: Ex rows B, T; Ey columns L, R.  Union of blocks: Ey on
+  // up to 4 block columns (rows 0-3), Ex on up to 2 block rows (4-5)
+  static constexpr int NBL = UN ? 6 : 4;
+  // union of blocks: activity of the cells [i0-5, i0+kTX+3) x [j0-5, j0+TY+3)
+  static constexpr int CW = kTX + 8, CH = TY + 8;
+  float rEx[RH][RW], rEy[RH][RW];
+  float qEx[QH][QW], qEy[QH][QW];
+  float sExo[EH][EW], sEyo[EH][EW];
+  float sH[HH][HW], sHo[HH][HW];
+  float sExn[NH][NW], sEyn[NH][NW];
+  float sN[DH][DW];
+  float sJx[TY][kTX], sJy[TY][kTX];
+  float sB[NBL + 1][NW > NH ? NW : NH];
+  uint8_t sC[UN ? CH : 1][UN ? CW : 1];
+};
+
+// A tile whose every entity (raw-E halo included) lies inside the patch
+// rectangle and off its boundary lines: no neighbour is replaced, no
+// Eq. (5b) value is used, no address needs clamping.
+__device__ __forceinline__ bool fine_interior(const EMArgs& A, int i0, int j0, int ty) {
+  return i0 - 4 >= A.L && i0 + kTX + 3 <= A.R && j0 - 4 >= A.B && j0 + ty + 3 <= A.T;
+}
+
+// IN: the tile is interior (fine_interior); the entity tests below are then
+// constant and fold away, with every value computed by the same operations.
+template <int TY, int NT, bool UN = false, bool IN = false>
+__device__ __forceinline__ void fine_tile(const EMArgs& A, FineLds<TY, UN>& S, int bx, int by,
+                                          int tix = 0) {
+  static_assert(!(UN && IN), "the interior form is for the patch rectangle");
+  using FL = FineLds<TY, UN>;
+  constexpr int EW = FL::EW, EH = FL::EH, HW = FL::HW, HH = FL::HH, NW = FL::NW, NH = FL::NH;
+  constexpr int DW = FL::DW, DH = FL::DH, RW = FL::RW, RH = FL::RH, QW = FL::QW, QH = FL::QH;
   constexpr int NR = (RH * RW + NT - 1) / NT;
   constexpr int NO = (EH * EW + NT - 1) / NT;
   constexpr int ND = (DH * DW + NT - 1) / NT;
@@ -130,20 +164,16 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int t
   constexpr int NE = (NH * NW + NT - 1) / NT;
   constexpr int RP = NT / kTX;  // tile rows per pass of the block
   constexpr int NA = (TY + RP - 1) / RP;
-  __shared__ float rEx[RH][RW], rEy[RH][RW];
-  __shared__ float qEx[QH][QW], qEy[QH][QW];
-  __shared__ float sExo[EH][EW], sEyo[EH][EW];
-  __shared__ float sH[HH][HW], sHo[HH][HW];
-  __shared__ float sExn[NH][NW], sEyn[NH][NW];
-  __shared__ float sN[DH][DW];
-  __shared__ float sJx[TY][kTX], sJy[TY][kTX];
-  // Eq. (5b) values: Ex rows B, T; Ey columns L, R.  Union of blocks: Ey on
-  // up to 4 block columns (rows 0-3), Ex on up to 2 block rows (4-5)
-  constexpr int NBL = UN ? 6 : 4;
-  __shared__ float sB[NBL + 1][NW > NH ? NW : NH];
-  // union of blocks: activity of the cells [i0-5, i0+kTX+3) x [j0-5, j0+TY+3)
-  constexpr int CW = kTX + 8, CH = TY + 8;
-  __shared__ uint8_t sC[UN ? CH : 1][UN ? CW : 1];
+  constexpr int NBL = FL::NBL, CW = FL::CW, CH = FL::CH;
+  auto& rEx = S.rEx; auto& rEy = S.rEy;
+  auto& qEx = S.qEx; auto& qEy = S.qEy;
+  auto& sExo = S.sExo; auto& sEyo = S.sEyo;
+  auto& sH = S.sH; auto& sHo = S.sHo;
+  auto& sExn = S.sExn; auto& sEyn = S.sEyn;
+  auto& sN = S.sN;
+  auto& sJx = S.sJx; auto& sJy = S.sJy;
+  auto& sB = S.sB;
+  auto& sC = S.sC;
 
   const int i0 = A.L + bx * kTX;
   const int j0 = A.B + by * TY;
@@ -158,33 +188,42 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int t
   auto cact = [&](int i, int j) -> bool { return sC[UN ? j - j0 + 5 : 0][UN ? i - i0 + 5 : 0]; };
   auto hz_ok = [&](int i, int j) -> bool {
     if constexpr (UN) return cact(i, j);
+    else if constexpr (IN) return true;
     else return i >= L && i < R && j >= B && j < T;
   };
   auto ex_ok = [&](int i, int j) -> bool {
     if constexpr (UN) return cact(i, j) || cact(i, j - 1);
+    else if constexpr (IN) return true;
     else return i >= L && i < R && j >= B && j <= T;
   };
   auto ey_ok = [&](int i, int j) -> bool {
     if constexpr (UN) return cact(i, j) || cact(i - 1, j);
+    else if constexpr (IN) return true;
     else return i >= L && i <= R && j >= B && j < T;
   };
   auto nd_ok = [&](int i, int j) -> bool {
     if constexpr (UN) return cact(i, j) || cact(i - 1, j) || cact(i, j - 1) || cact(i - 1, j - 1);
+    else if constexpr (IN) return true;
     else return i >= L && i <= R && j >= B && j <= T;
   };
   auto ex_in = [&](int i, int j) -> bool {
     if constexpr (UN) return cact(i, j) && cact(i, j - 1);
+    else if constexpr (IN) return true;
     else return j != B && j != T;
   };
   auto ey_in = [&](int i, int j) -> bool {
     if constexpr (UN) return cact(i, j) && cact(i - 1, j);
+    else if constexpr (IN) return true;
     else return i != L && i != R;
   };
   // clamped (always valid) addresses of each entity kind
   // (tile-relative byte offsets from the corner (ib, jb), as in fine2_tile)
   const int ib = max(i0 - 8, L), jb = max(j0 - 8, B);
   const TileBase tb(A, ib, jb);
-  auto cl = [&](int v, int lo, int hi) { return min(max(v, lo), hi); };
+  auto cl = [&](int v, int lo, int hi) {
+    if constexpr (IN) return v;
+    else return min(max(v, lo), hi);
+  };
   auto ob = [&](int i, int j) { return tb.off(i, j); };
   auto o_hz = [&](int i, int j) { return ob(cl(i, L, R - 1), cl(j, B, T - 1)); };
   auto o_ex = [&](int i, int j) { return ob(cl(i, L, R - 1), cl(j, B, T)); };
@@ -243,7 +282,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int t
   if constexpr (UN) {
     if (tid < 4 * NH) { bg = tid / NH; bc = tid % NH; }
     else if (tid < 4 * NH + 2 * NW) { bg = 4 + (tid - 4 * NH) / NW; bc = (tid - 4 * NH) % NW; }
-  } else {
+  } else if constexpr (!IN) {
     if (tid < NW) { bg = 0; bc = tid; }
     else if (tid < 2 * NW) { bg = 1; bc = tid - NW; }
     else if (tid < 2 * NW + NH) { bg = 2; bc = tid - 2 * NW; }
@@ -337,7 +376,8 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int t
   // coarse edges next to the boundary at concave corners
   const bool from_prev = UN && A.cfb_prev != nullptr;
   if (from_prev) bco = bco2 = 0;
-  const float bo0 = bp0[bco], bo1 = bp0[bco2], bn0 = bp1[bco], bn1 = bp1[bco2];
+  float bo0 = 0.f, bo1 = 0.f, bn0 = 0.f, bn1 = 0.f;
+  if constexpr (!IN) { bo0 = bp0[bco]; bo1 = bp0[bco2]; bn0 = bp1[bco]; bn1 = bp1[bco2]; }
   float bpre = 0.f;
   if constexpr (UN) {
     if (from_prev && bg >= 0) bpre = A.cfb_prev[(size_t)tix * kCfbStride + tid];
@@ -434,7 +474,7 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int t
       sN[cj][ci] = nd_ok(i0 - 1 + ci, j0 - 1 + cj) ? pn[q] : 0.f;
     }
   }
-  {  // every thread writes (row NBL is a dummy), so the loads above stay put
+  if constexpr (!IN) {  // every thread writes (row NBL is a dummy), so the loads above stay put
     sB[bg < 0 ? NBL : bg][bg < 0 ? 0 : bc] =
         from_prev ? bpre : (bvalid ? cfb(bw0, bw1, bo0, bo1, bn0, bn1, A.frac) : 0.f);
     if constexpr (UN) {  // substep 1 hands the last substep its values (frac = 1)
@@ -536,8 +576,8 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int t
     float sx = 0.f, sy = 0.f;
     int cx = 0, cy = 0;
     // the node's own edges (rectangle: i > L is Ex(i-1, j) belonging, ...)
-    const bool xl = UN ? ex_ok(i - 1, j) : i > L, xr = UN ? ex_ok(i, j) : i < R;
-    const bool yd = UN ? ey_ok(i, j - 1) : j > B, yu = UN ? ey_ok(i, j) : j < T;
+    const bool xl = IN || (UN ? ex_ok(i - 1, j) : i > L), xr = IN || (UN ? ex_ok(i, j) : i < R);
+    const bool yd = IN || (UN ? ey_ok(i, j - 1) : j > B), yu = IN || (UN ? ey_ok(i, j) : j < T);
     if (xl) { const float v = sExn[cj][ci - 1]; sx += v * v; cx++; }
     if (xr) { const float v = sExn[cj][ci]; sx += v * v; cx++; }
     if (yd) { const float v = sEyn[cj - 1][ci]; sy += v * v; cy++; }
@@ -606,16 +646,25 @@ __device__ __forceinline__ void fine_tile(const EMArgs& A, int bx, int by, int t
   }
 }
 
+// Two 1024-thread tiles share a CU only if each wave holds at most 80
+// scalar registers (more leaves one tile per CU); the interior form would
+// otherwise take 88.
 template <int TY, int NT>
-__global__ __launch_bounds__(NT) void k_fine(EMArgs A) {
-  fine_tile<TY, NT>(A, blockIdx.x, blockIdx.y);
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_num_sgpr(kTileSgprs))) void k_fine(EMArgs A) {
+  __shared__ FineLds<TY, false> S;
+  const int bx = blockIdx.x, by = blockIdx.y;
+  if (fine_interior(A, A.L + bx * kTX, A.B + by * TY, TY))
+    fine_tile<TY, NT, false, true>(A, S, bx, by);
+  else
+    fine_tile<TY, NT>(A, S, bx, by);
 }
 
 // the fine level as a union of blocks: one listed tile per block
 template <int TY, int NT>
 __global__ __launch_bounds__(NT) void k_fine_union(EMArgs A, const int2* __restrict__ tiles) {
+  __shared__ FineLds<TY, true> S;
   const int2 t = tiles[blockIdx.x];
-  fine_tile<TY, NT, true>(A, t.x, t.y, blockIdx.x);
+  fine_tile<TY, NT, true>(A, S, t.x, t.y, blockIdx.x);
 }
 
 // batched union levels: blk[b] = (instance, index in the instance's tile list)
@@ -624,8 +673,9 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_union_batch(const EMArgs*
                                                                    const int2* __restrict__ blk) {
   const int2 bi = blk[blockIdx.x];
   const EMArgs& A = args[bi.x];
+  __shared__ FineLds<TY, true> S;
   const int2 t = A.utiles[bi.y];
-  fine_tile<TY, kFineThreads, true>(A, t.x, t.y, bi.y);
+  fine_tile<TY, kFineThreads, true>(A, S, t.x, t.y, bi.y);
 }
 
 // Eq. (5b) source of thread tid for one substep's new-E region (origin orig
@@ -1586,7 +1636,12 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_batch(const EMArgs* __res
                                                              const int2* __restrict__ blk) {
   const int2 bi = blk[blockIdx.x];
   const EMArgs& A = args[bi.x];
-  fine_tile<TY, kFineThreads>(A, bi.y % A.nbx, bi.y / A.nbx);
+  __shared__ FineLds<TY, false> S;
+  const int bx = bi.y % A.nbx, by = bi.y / A.nbx;
+  if (fine_interior(A, A.L + bx * kTX, A.B + by * TY, TY))
+    fine_tile<TY, kFineThreads, false, true>(A, S, bx, by);
+  else
+    fine_tile<TY, kFineThreads>(A, S, bx, by);
 }
 
 // batched two-substep patch launch (both substeps of r = 2, or a pair of the
