@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--only-config2-union", action="store_true",
                     help="profiling aid: run only 256 coarse steps of config 2 with the "
                          "union-of-blocks fine level, no JSON")
+    ap.add_argument("--only-config2-box", action="store_true",
+                    help="profiling aid: run only 64 coarse steps of config 2 with the "
+                         "bounding-box patch, no JSON")
     return ap.parse_args()
 
 
@@ -79,6 +82,20 @@ def only_config2_union(steps=256):
     sim.sync()
     print("only-config2-union: %d steps, %d active blocks" % (steps, sim.blocks().sum()),
           flush=True)
+
+
+def only_config2_box(steps=64):
+    """Profiling aid: config 2 (8 seeds, 4096x2048) with the bounding box of
+    the flagged blocks as the patch (4.7 M fine cells, one-substep patch
+    launches), from t = 0."""
+    from paper_2105_13276_amd import binding as B
+    from paper_2105_13276_amd import workloads as W
+    cfg = W.config2(periods=4)
+    centres, peaks = W.config2_seed_layout(cfg)
+    sim = B.Sim(cfg, *W.seeds(cfg, centres, peaks))
+    sim.step(steps)
+    sim.sync()
+    print("only-config2-box: %d steps, patch %s" % (steps, sim.patch()), flush=True)
 
 
 def only_large(steps=48):
@@ -277,6 +294,9 @@ def main():
     if args.only_config2_union:
         only_config2_union()
         return
+    if args.only_config2_box:
+        only_config2_box()
+        return
     import numpy as np
     import torch
     from paper_2105_13276_amd import binding as B
@@ -470,7 +490,16 @@ def main():
         h2d = []
         s2d, w2d, k2d = run_case(B, cfg_2, sd_2, c2k, INTERVAL, 0, False, h2d)
         ext2 = s2d.patch()
+        # the patch substep's own rate: 64 more coarse steps with per-class
+        # HIP-event timing (two one-substep launches per coarse step)
+        s2d.set_timing(True)
+        s2d.step(64)
+        ms_2, cnt_2 = s2d.timing()
+        s2d.set_timing(False)
         s2d.close()
+        fc2 = 4 * (ext2[2] - ext2[0]) * (ext2[3] - ext2[1])
+        per_f2 = ms_2[1] / max(cnt_2[1], 1)
+        ach_f2 = em_bytes_per_cell() * fc2 / (per_f2 * 1e-3) / 1e9
         cfg_2u = W.config2_uniform(periods=4 * c2k)
         sd_2u = W.seeds(cfg_2u, centres, peaks)
         s2u, w2u, k2u = run_case(B, cfg_2u, sd_2u, c2k, 2 * INTERVAL, 0, False)
@@ -523,7 +552,13 @@ def main():
             "dmr_s": w2d, "uniform_fine_s": w2u, "speedup": w2u / w2d,
             "speedup_bound_single_rectangle": 1.0 / (1.0 / 8.0 + float(np.mean(h2d))),
             "dmr_mcell_updates_per_s": k2d / w2d / 1e6,
-            "uniform_mcell_updates_per_s": k2u / w2u / 1e6}
+            "uniform_mcell_updates_per_s": k2u / w2u / 1e6,
+            "roofline_patch_substep": {
+                "bound": "hbm", "kernel": "k_fine<16,1024> (one patch substep, %d fine cells)" % fc2,
+                "achieved": ach_f2, "peak": 8000.0, "unit": "GB/s", "frac": ach_f2 / 8000.0,
+                "avg_launch_us": per_f2 * 1e3, "alg_bytes_per_launch": em_bytes_per_cell() * fc2,
+                "traffic": rec.get("k_fine@config2"),
+                "avg_launch_us_rocprofv3": trc.get("k_fine@config2")}}
 
     # ---- batched form: 64 independent DMR runs (config 3) to t_final -----
     if not args.no_batch:

@@ -1281,7 +1281,6 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
                                            float chz_src) {
   constexpr int FW = TW + 13, FH = TY + 13, FN = FW * FH;
   constexpr int NP = (FN + NT - 1) / NT;  // frame positions per thread
-  constexpr int N1W = TW + 7, N1H = TY + 7, N2W = TW + 1, N2H = TY + 1;
   __shared__ float rX[FN], rY[FN];    // raw E0 (clamped)
   __shared__ float fX[FN], fY[FN];    // filtered E0, then filtered E1
   __shared__ float sH0[FN], sH1[FN], sH2[FN];  // Hz entering, after substeps 1 and 2
