@@ -1000,30 +1000,40 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
     G->st2y = cx->last ? cx->ss.fey2 : nullptr;
     G->stn = cx->ss.fn;
   };
-  // the fused forms are bit-identical to the separate launches
-  const bool combined = fuse && s->combine;
-  if (combined) {  // base step and both patch substeps, one launch
+  // the fused forms are bit-identical to the separate launches.  r = 4
+  // (4-row tiles, no replay): the launch takes the base step and substeps
+  // (1, 2); (3, 4) and the fine -> coarse transfer follow in a launch of
+  // their own, so the base waves store every coarse entity
+  const bool r4 = p.r == 4;
+  const bool combined = fuse && s->combine && (!r4 || (s->ty1 == 4 && !kst));
+  if (combined) {  // base step and both patch substeps (r = 4: the first pair), one launch
     Level &C = s->L0, &F = s->L1;
-    A.skip_on = 1;
+    A.skip_on = r4 ? 0 : 1;
     A.sL = s->ext[0]; A.sB = s->ext[1]; A.sR = s->ext[2]; A.sT = s->ext[3];
     EMArgs G;
-    make_fine_em(s, p.r, c, s->ncur, s->ty1, &G);  // restriction targets
+    make_fine_em(s, r4 ? 2 : p.r, c, s->ncur, s->ty1, &G);  // r = 2: restriction targets
     em_args_level(&G, F, 0, 1, F.n[s->ncur], F.acc);
     G.frac = 1.f / (float)p.r;  // time fraction of substep 1
+    if (r4) {  // as the first pair of the two-launch r = 4 form
+      G.hz_save = nullptr;
+      G.hz_lo = nullptr;
+    }
     G.chz0 = C.hz[c]; G.cjx0 = C.jx[c]; G.cjy0 = C.jy[c]; G.cn0 = C.n[s->ncur];
     G.cS = C.S; G.cc1 = C.c1; G.ckn = C.kn; G.cis = p.tfsf_i;
     G.cey_src = A.ey_src; G.chz_src = A.hz_src;
     G.cnx = p.nx; G.cny = p.ny;
     fine_stores(&G);
     ev_begin(s, 0);
-    e = launch_dmr_step(A, G, s->seg0, s->depth0, s->ty1, s->tw1, s->st);
+    e = launch_dmr_step(A, G, s->seg0, s->depth0, s->ty1, s->tw1, s->st, r4);
     ev_end(s);
     if (e != hipSuccess) return hipfail(s, e, "combined step launch");
-    std::swap(F.hz[0], F.hz[1]);
-    std::swap(F.ex[0], F.ex[1]);
-    std::swap(F.ey[0], F.ey[1]);
-    std::swap(F.jx[0], F.jx[1]);
-    std::swap(F.jy[0], F.jy[1]);
+    if (!r4) {  // r = 4: the second pair writes buffer 0 again
+      std::swap(F.hz[0], F.hz[1]);
+      std::swap(F.ex[0], F.ex[1]);
+      std::swap(F.ey[0], F.ey[1]);
+      std::swap(F.jx[0], F.jx[1]);
+      std::swap(F.jy[0], F.jy[1]);
+    }
   } else {
     ev_begin(s, 0);
     e = launch_em_stream(A, s->seg0, s->depth0, s->st);
@@ -1036,11 +1046,11 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
     job(&J, s->L0.ey[1 - c], cx->ss.ceyp, s->L0.plane);
     if (int rc = run_copies(s, J)) return rc;
   }
-  if (combined) {
+  if (combined && !r4) {
     // done above
   } else if (fuse && p.r == 4) {  // substeps (1, 2) then (3, 4), one launch each
     Level& F = s->L1;
-    for (int h = 0; h < 2; h++) {
+    for (int h = combined ? 1 : 0; h < 2; h++) {
       EMArgs G;
       make_fine_em(s, 2 * h + 2, c, s->ncur, s->ty1, &G);  // the second pair restricts
       em_args_level(&G, F, h, 1 - h, F.n[s->ncur], F.acc);
@@ -1304,8 +1314,8 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   // bandwidth-bound grids the base kernel's own launch shape is faster
   s->combine = (long)p->nx * p->ny <= (1L << 21);
   if (const char* f = getenv("DMR_COMBINE")) s->combine = atoi(f) != 0;
-  // the one-launch step is r = 2; r = 4 runs its substeps as two pairs
-  if (p->r != 2) s->combine = false;
+  // r = 2: the base step and both substeps in one launch; r = 4: the base
+  // step and the first pair of substeps (4-row tiles), then the second pair
   if (const char* f = getenv("DMR_FUSE_MAX")) s->fuse_max = atol(f);
   if (const char* f = getenv("DMR_FNT")) s->nt1 = atoi(f) >= 1024 ? 1024 : 256;
   if (const char* f = getenv("DMR_TW")) { const int v = atoi(f); s->tw1 = (v == 16 || v == 32 || v == 64) ? v : 0; }

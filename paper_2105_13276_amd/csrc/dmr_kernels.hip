@@ -857,11 +857,12 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
   // combined step: the coarse E after the coarse step on the patch boundary
   // lines is computed here from the coarse state entering it (the base-level
   // waves of the same launch compute the same values).  x-lines: coarse rows
-  // B/2 and T/2 at columns [cx0, cx0 + CW); y-lines: coarse columns L/2 and
-  // R/2 at rows [cy0, cy0 + CH).
+  // B/r and T/r at columns [cx0, cx0 + CW); y-lines: coarse columns L/r and
+  // R/r at rows [cy0, cy0 + CH) (enough for r = 2; r = 4 needs fewer).
+  constexpr int RS = R4 ? 2 : 1;  // fine -> coarse index shift
   constexpr int CW = TW / 2 + 6, CH = TY / 2 + 6;
   __shared__ float sC[5][CW > CH ? CW : CH];
-  const int cx0 = ((i0 - 4) >> 1) - 1, cy0 = ((j0 - 4) >> 1) - 1;
+  const int cx0 = ((i0 - 4) >> RS) - 1, cy0 = ((j0 - 4) >> RS) - 1;
   int cg = -1, cc = 0;
   float q[12];
   if constexpr (LOCAL) {
@@ -875,14 +876,14 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
       return (size_t)bb * cp + aa;
     };
     if (cg <= 1) {  // x-edge (ic, J) of a boundary row (threads without a role: cg = -1)
-      const int ic = cx0 + cc, J = cg == 1 ? (T >> 1) : (B >> 1);
+      const int ic = cx0 + cc, J = cg == 1 ? (T >> RS) : (B >> RS);
       q[0] = A.cex0[cidx(ic, J - 1)]; q[1] = A.cex0[cidx(ic, J)]; q[2] = A.cex0[cidx(ic, J + 1)];
       q[3] = A.cey0[cidx(ic, J - 1)]; q[4] = A.cey0[cidx(ic + 1, J - 1)];
       q[5] = A.cey0[cidx(ic, J)]; q[6] = A.cey0[cidx(ic + 1, J)];
       q[7] = A.chz0[cidx(ic, J - 1)]; q[8] = A.chz0[cidx(ic, J)];
       q[9] = A.cjx0[cidx(ic, J)]; q[10] = A.cn0[cidx(ic, J)]; q[11] = A.cn0[cidx(ic + 1, J)];
     } else {        // y-edge (I, jc) of a boundary column
-      const int jc = cy0 + cc, I = cg == 3 ? (R >> 1) : (L >> 1);
+      const int jc = cy0 + cc, I = cg == 3 ? (R >> RS) : (L >> RS);
       q[0] = A.cey0[cidx(I - 1, jc)]; q[1] = A.cey0[cidx(I, jc)]; q[2] = A.cey0[cidx(I + 1, jc)];
       q[3] = A.cex0[cidx(I - 1, jc)]; q[4] = A.cex0[cidx(I - 1, jc + 1)];
       q[5] = A.cex0[cidx(I, jc)]; q[6] = A.cex0[cidx(I, jc + 1)];
@@ -971,7 +972,7 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
       const float kap = base_kap(A.ckn, q[10], q[11]);
       v = base_ex(q[1], kap, S, h, hp, c1, q[9]);
     } else {
-      const int I = cg == 3 ? (R >> 1) : (L >> 1);
+      const int I = cg == 3 ? (R >> RS) : (L >> RS);
       float h = base_hz(q[8], S, q[2], q[1], q[6], q[5]);
       if (I == A.cis - 1) h += S * cey_src;
       float hl = base_hz(q[7], S, q[1], q[0], q[4], q[3]);
@@ -2661,11 +2662,14 @@ __global__ __launch_bounds__(kThreads) void k_fine_stream(EMArgs A, int seg, int
 // after the step on their boundary lines themselves.  The base waves do not store
 // the coarse entities the tiles' fine -> coarse transfer writes.
 // ---------------------------------------------------------------------------
-template <int DEPTH, int TY, bool ST = false, int TW = kTX>
-__global__ __launch_bounds__(step_threads(ST, TY)) void k_dmr_step(EMArgs C, EMArgs F, int seg,
-                                                                   int nseg, int waves_x, int ncb,
-                                                                   int nbx_f) {
-  constexpr int NTC = step_threads(ST, TY);
+// R4: refinement factor 4, the launch runs the base step and the first pair
+// of the four substeps (the second pair, with the fine -> coarse transfer,
+// is a k_fine2 launch of its own)
+template <int DEPTH, int TY, bool ST = false, int TW = kTX, bool R4 = false>
+__global__ __launch_bounds__(step_threads(ST, TY, R4)) void k_dmr_step(EMArgs C, EMArgs F, int seg,
+                                                                       int nseg, int waves_x,
+                                                                       int ncb, int nbx_f) {
+  constexpr int NTC = step_threads(ST, TY, R4);
   // the patch tiles are the longer chain: they take the first blocks, which
   // the dispatcher starts first
   const int ntl = gridDim.x - ncb;
@@ -2676,10 +2680,10 @@ __global__ __launch_bounds__(step_threads(ST, TY)) void k_dmr_step(EMArgs C, EMA
     if (k < nseg) em_stream_body<DEPTH, ST>(C, w % waves_x, k, seg, nseg, C.ey_src, C.hz_src);
     return;
   }
-  if constexpr (!ST && TY == 4)
+  if constexpr (!ST && !R4 && TY == 4)
     fine2_fast<TY, NTC, TW>(F, b % nbx_f, b / nbx_f, F.cey_src, F.chz_src);
   else
-    fine2_tile<TY, NTC, true, ST, false, TW>(F, b % nbx_f, b / nbx_f, F.cey_src, F.chz_src);
+    fine2_tile<TY, NTC, true, ST, R4, TW>(F, b % nbx_f, b / nbx_f, F.cey_src, F.chz_src);
 }
 
 // Batched combined step: blk[b] = (instance, g), g >= 0 a group of 16 base
@@ -2857,10 +2861,11 @@ hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st) {
 }
 
 hipError_t launch_dmr_step(const EMArgs& C, const EMArgs& F, int seg, int depth, int ty,
-                           int tw, hipStream_t st) {
+                           int tw, hipStream_t st, bool r4) {
+  if (r4 && (ty != 4 || C.stix)) return hipErrorInvalidValue;  // 4-row tiles, no replay
   const int waves_x = (C.R + 1 + 61) / 62;
   const int nseg = stream_segments(C.T, seg);
-  const int nt = step_threads(C.stix != nullptr, ty);
+  const int nt = step_threads(C.stix != nullptr, ty, r4);
   const int wpb = nt / 64;
   const int ncb = (waves_x * nseg + wpb - 1) / wpb;
   if (ty != 4) tw = kTX;  // narrow tiles: 4-row tiles only
@@ -2870,7 +2875,11 @@ hipError_t launch_dmr_step(const EMArgs& C, const EMArgs& F, int seg, int depth,
   const dim3 g(ncb + nbx_f * nby_f), blk(nt);
 #define DMR_STEP(D, T_, W_) hipLaunchKernelGGL((k_dmr_step<D, T_, false, W_>), g, blk, 0, st, C, F, seg, nseg, waves_x, ncb, nbx_f)
 #define DMR_STEP_ST(D, T_, W_) hipLaunchKernelGGL((k_dmr_step<D, T_, true, W_>), g, blk, 0, st, C, F, seg, nseg, waves_x, ncb, nbx_f)
-  if (C.stix) {  // replay: stores for the adjoint
+#define DMR_STEP_R4(D, W_) hipLaunchKernelGGL((k_dmr_step<D, 4, false, W_, true>), g, blk, 0, st, C, F, seg, nseg, waves_x, ncb, nbx_f)
+  if (r4) {
+    if (depth >= 4) { if (tw == 16) DMR_STEP_R4(4, 16); else if (tw == 32) DMR_STEP_R4(4, 32); else DMR_STEP_R4(4, kTX); }
+    else { if (tw == 16) DMR_STEP_R4(2, 16); else if (tw == 32) DMR_STEP_R4(2, 32); else DMR_STEP_R4(2, kTX); }
+  } else if (C.stix) {  // replay: stores for the adjoint
     if (depth >= 4) {
       if (ty == 4) { if (tw == 16) DMR_STEP_ST(4, 4, 16); else if (tw == 32) DMR_STEP_ST(4, 4, 32); else DMR_STEP_ST(4, 4, kTX); }
       else if (ty == 8) DMR_STEP_ST(4, 8, kTX); else DMR_STEP_ST(4, 16, kTX);
@@ -2887,6 +2896,7 @@ hipError_t launch_dmr_step(const EMArgs& C, const EMArgs& F, int seg, int depth,
   }
 #undef DMR_STEP
 #undef DMR_STEP_ST
+#undef DMR_STEP_R4
   return hipGetLastError();
 }
 
