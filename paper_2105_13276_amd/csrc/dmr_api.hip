@@ -1006,6 +1006,15 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
   // their own, so the base waves store every coarse entity
   const bool r4 = p.r == 4;
   const bool combined = fuse && s->combine && (!r4 || (s->ty1 == 4 && !kst));
+  // what patch tiles need to form the coarse E after the base step on their
+  // boundary lines themselves: the coarse state entering the step
+  auto coarse_state = [&](EMArgs* G) {
+    const Level& C = s->L0;
+    G->chz0 = C.hz[c]; G->cjx0 = C.jx[c]; G->cjy0 = C.jy[c]; G->cn0 = C.n[s->ncur];
+    G->cS = C.S; G->cc1 = C.c1; G->ckn = C.kn; G->cis = p.tfsf_i;
+    G->cey_src = A.ey_src; G->chz_src = A.hz_src;
+    G->cnx = p.nx; G->cny = p.ny;
+  };
   if (combined) {  // base step and both patch substeps (r = 4: the first pair), one launch
     Level &C = s->L0, &F = s->L1;
     A.skip_on = r4 ? 0 : 1;
@@ -1018,10 +1027,7 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
       G.hz_save = nullptr;
       G.hz_lo = nullptr;
     }
-    G.chz0 = C.hz[c]; G.cjx0 = C.jx[c]; G.cjy0 = C.jy[c]; G.cn0 = C.n[s->ncur];
-    G.cS = C.S; G.cc1 = C.c1; G.ckn = C.kn; G.cis = p.tfsf_i;
-    G.cey_src = A.ey_src; G.chz_src = A.hz_src;
-    G.cnx = p.nx; G.cny = p.ny;
+    coarse_state(&G);
     fine_stores(&G);
     ev_begin(s, 0);
     e = launch_dmr_step(A, G, s->seg0, s->depth0, s->ty1, s->tw1, s->st, r4);
@@ -1058,7 +1064,12 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
       G.hz_save = nullptr;
       G.hz_lo = nullptr;
       ev_begin(s, 1);
-      e = launch_fine2(G, s->ty1, s->nt1, s->st);
+      if (combined) {  // the frame tile of the combined launch, for the second pair
+        coarse_state(&G);
+        e = launch_fine2_fast4(G, s->tw1, s->st);
+      } else {
+        e = launch_fine2(G, s->ty1, s->nt1, s->st);
+      }
       ev_end(s);
       if (e != hipSuccess) return hipfail(s, e, "fine EM launch");
     }

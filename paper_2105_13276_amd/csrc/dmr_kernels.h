@@ -13,9 +13,7 @@ constexpr int kTileSgprs = 72;  // scalar-register cap of the 1024-thread tile k
 // threads per block of the combined step: 512 for its 4-row patch tiles (one
 // frame position per thread on small patches, and half as many base-level
 // waves per compute unit), else the patch tile's 1024
-constexpr int step_threads(bool store, int ty, bool r4 = false) {
-  return (!store && !r4 && ty == 4) ? 512 : kFineThreads;
-}
+constexpr int step_threads(bool store, int ty) { return (!store && ty == 4) ? 512 : kFineThreads; }
 constexpr int kRing = 8;       // window blocks per period
 // union-of-blocks level: Eq. (5b) values one tile hands from substep 1 to the
 // last substep (4 block columns x (16+1) rows + 2 block rows x (kTX+1))
@@ -166,6 +164,7 @@ hipError_t launch_prolong_union(const ProlongArgs& A, const int2* tiles, int nti
 // both patch substeps of a coarse step in one launch: reads buffer 0 (hz0..),
 // writes buffer 1 (hz1..), A.frac = time fraction of substep 1, restriction on
 hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st);
+hipError_t launch_fine2_fast4(const EMArgs& A, int tw, hipStream_t st);
 // base-level step (C, with the patch's coarse entities skipped) and both patch
 // substeps (F, coarse boundary E computed in the tiles) in one launch
 hipError_t launch_dmr_step(const EMArgs& C, const EMArgs& F, int seg, int depth, int ty,

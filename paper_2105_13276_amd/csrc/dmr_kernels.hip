@@ -1277,7 +1277,7 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
 // and operands of fine2_tile (the helpers above), so the results are
 // identical to it and to two one-substep launches.
 // ---------------------------------------------------------------------------
-template <int TY, int NT, int TW>
+template <int TY, int NT, int TW, bool R4 = false>
 __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, float cey_src,
                                            float chz_src) {
   constexpr int FW = TW + 13, FH = TY + 13, FN = FW * FH;
@@ -1298,7 +1298,7 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
   const int tid = threadIdx.x;
   const int L = A.L, R = A.R, B = A.B, T = A.T;
   const bool filt = A.gamma > 0.f;
-  const float frac1 = A.frac, frac2 = 1.f;
+  const float frac1 = A.frac, frac2 = R4 ? A.frac + 0.25f : 1.f;
   const int ib = max(i0 - 8, L), jb = max(j0 - 8, B);
   const TileBase tb(A, ib, jb);
   auto cl = [=](int v, int lo, int hi) { return min(max(v, lo), hi); };
@@ -1340,7 +1340,8 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
   }
   // coarse state around the patch boundary lines, for the coarse E after the
   // step there (as in fine2_tile)
-  const int cx0 = ((i0 - 4) >> 1) - 1, cy0 = ((j0 - 4) >> 1) - 1;
+  constexpr int RS = R4 ? 2 : 1;  // fine -> coarse index shift
+  const int cx0 = ((i0 - 4) >> RS) - 1, cy0 = ((j0 - 4) >> RS) - 1;
   int cg = -1, cc = 0;
   float qc[12];
   if (tid < CW) { cg = 0; cc = tid; }
@@ -1355,7 +1356,7 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
       return __umul24((unsigned)bb, cp4) + ((unsigned)aa << 2);
     };
     if (cg <= 1) {  // x-edge (ic, J) of a boundary row (threads without a role: cg = -1)
-      const int ic = cx0 + cc, J = cg == 1 ? (T >> 1) : (B >> 1);
+      const int ic = cx0 + cc, J = cg == 1 ? (T >> RS) : (B >> RS);
       qc[0] = ldo(A.cex0, cidx(ic, J - 1)); qc[1] = ldo(A.cex0, cidx(ic, J));
       qc[2] = ldo(A.cex0, cidx(ic, J + 1));
       qc[3] = ldo(A.cey0, cidx(ic, J - 1)); qc[4] = ldo(A.cey0, cidx(ic + 1, J - 1));
@@ -1364,7 +1365,7 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
       qc[9] = ldo(A.cjx0, cidx(ic, J)); qc[10] = ldo(A.cn0, cidx(ic, J));
       qc[11] = ldo(A.cn0, cidx(ic + 1, J));
     } else {        // y-edge (I, jc) of a boundary column
-      const int jc = cy0 + cc, I = cg == 3 ? (R >> 1) : (L >> 1);
+      const int jc = cy0 + cc, I = cg == 3 ? (R >> RS) : (L >> RS);
       qc[0] = ldo(A.cey0, cidx(I - 1, jc)); qc[1] = ldo(A.cey0, cidx(I, jc));
       qc[2] = ldo(A.cey0, cidx(I + 1, jc));
       qc[3] = ldo(A.cex0, cidx(I - 1, jc)); qc[4] = ldo(A.cex0, cidx(I - 1, jc + 1));
@@ -1406,13 +1407,24 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
   // Eq. (5b) value of the boundary edge at position e along line g (0/1:
   // x-edges of rows B/T, 2/3: y-edges of columns L/R) from the coarse E on
   // the line before (sO) and after (sC) the coarse step; offsets 1/4, 3/4
+  // (r = 4: 1/8 ... 7/8, lower coarse edge and weights as in bnd_src)
   constexpr int SW = CW > CH ? CW : CH;
   auto cfb_at = [=](int g, int e, float fr) {
-    const bool ev = (e & 1) == 0;
-    const int k = ev ? (e >> 1) - 1 : (e >> 1);
+    int k;
+    float w0, w1;
+    if constexpr (R4) {
+      const int m = e & 3;
+      k = (e >> 2) - (m < 2 ? 1 : 0);
+      w0 = m == 0 ? 0.375f : m == 1 ? 0.125f : m == 2 ? 0.875f : 0.625f;
+      w1 = 1.f - w0;
+    } else {
+      const bool ev = (e & 1) == 0;
+      k = ev ? (e >> 1) - 1 : (e >> 1);
+      w0 = ev ? 0.25f : 0.75f;
+      w1 = ev ? 0.75f : 0.25f;
+    }
     const int x = min(max(k - (g >= 2 ? cy0 : cx0), 0), SW - 2);
-    return cfb(ev ? 0.25f : 0.75f, ev ? 0.75f : 0.25f, sO[g][x], sO[g][x + 1], sC[g][x],
-               sC[g][x + 1], fr);
+    return cfb(w0, w1, sO[g][x], sO[g][x + 1], sC[g][x], sC[g][x + 1], fr);
   };
   const float S = A.S;
 
@@ -1433,7 +1445,7 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
       const float kap = base_kap(A.ckn, qc[10], qc[11]);
       v = base_ex(qc[1], kap, cS, h, hp, c1, qc[9]);
     } else {
-      const int I = cg == 3 ? (R >> 1) : (L >> 1);
+      const int I = cg == 3 ? (R >> RS) : (L >> RS);
       float h = base_hz(qc[8], cS, qc[2], qc[1], qc[6], qc[5]);
       if (I == A.cis - 1) h += cS * cey_src;
       float hl = base_hz(qc[7], cS, qc[1], qc[0], qc[4], qc[3]);
@@ -1600,6 +1612,33 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
       if (j < T) { sy += vu * vu; cy++; }
       sto(tb.acc, tb.off(i, j), acc1[q] + win_e2(sx, cx, sy, cy));
     }
+    if constexpr (R4) {
+      // r = 4, after the second pair: 4 x 4 cells at the half levels after
+      // substeps 2 (the Hz entering) and 3; 4 edges, J~ summed
+      if (!A.restrict_on || (((i - L) | (j - B)) & 3)) continue;
+      const int a = i >> 2, b = j >> 2;
+      const size_t co = (size_t)b * A.cpitch + a;
+      if (hzok[q]) {
+        float s = 0.f;
+        for (int da = 0; da < 4; da++)
+          for (int db = 0; db < 4; db++)
+            s += 0.5f * (sH0[p + db * FW + da] + sH1[p + db * FW + da]);
+        A.chz[co] = 0.0625f * s;
+      }
+      if (exok[q] && j > B && j < T) {
+        float se = 0.f, sj = 0.f;
+        for (int da = 0; da < 4; da++) { se += e2X[p + da]; sj += j2X[p + da]; }
+        A.cex[co] = 0.25f * se;
+        A.cjx[co] = sj;
+      }
+      if (eyok[q] && i > L && i < R) {
+        float se = 0.f, sj = 0.f;
+        for (int db = 0; db < 4; db++) { se += e2Y[p + db * FW]; sj += j2Y[p + db * FW]; }
+        A.cey[co] = 0.25f * se;
+        A.cjy[co] = sj;
+      }
+      continue;
+    }
     if (((i - L) | (j - B)) & 1) continue;
     const int a = i >> 1, b = j >> 1;
     const size_t co = (size_t)b * A.cpitch + a;
@@ -1626,6 +1665,15 @@ __device__ __forceinline__ void fine2_fast(const EMArgs& A, int bx, int by, floa
 template <int TY, int NT, bool ST = false, bool R4 = false, int TW = kTX>
 __global__ __launch_bounds__(NT) void k_fine2(EMArgs A) {
   fine2_tile<TY, NT, false, ST, R4, TW>(A, blockIdx.x, blockIdx.y, 0.f, 0.f);
+}
+
+// the second pair of r = 4 substeps (3, 4) and the fine -> coarse transfer
+// in the frame tile of the combined step: the tiles form the coarse E after
+// the coarse step on their boundary lines from the coarse state entering it
+// (its buffers are still intact), as in the combined launch
+template <int TW>
+__global__ __launch_bounds__(step_threads(false, 4)) void k_fine2_fast4(EMArgs A) {
+  fine2_fast<4, step_threads(false, 4), TW, true>(A, blockIdx.x, blockIdx.y, A.cey_src, A.chz_src);
 }
 
 
@@ -2666,10 +2714,10 @@ __global__ __launch_bounds__(kThreads) void k_fine_stream(EMArgs A, int seg, int
 // of the four substeps (the second pair, with the fine -> coarse transfer,
 // is a k_fine2 launch of its own)
 template <int DEPTH, int TY, bool ST = false, int TW = kTX, bool R4 = false>
-__global__ __launch_bounds__(step_threads(ST, TY, R4)) void k_dmr_step(EMArgs C, EMArgs F, int seg,
+__global__ __launch_bounds__(step_threads(ST, TY)) void k_dmr_step(EMArgs C, EMArgs F, int seg,
                                                                        int nseg, int waves_x,
                                                                        int ncb, int nbx_f) {
-  constexpr int NTC = step_threads(ST, TY, R4);
+  constexpr int NTC = step_threads(ST, TY);
   // the patch tiles are the longer chain: they take the first blocks, which
   // the dispatcher starts first
   const int ntl = gridDim.x - ncb;
@@ -2680,8 +2728,8 @@ __global__ __launch_bounds__(step_threads(ST, TY, R4)) void k_dmr_step(EMArgs C,
     if (k < nseg) em_stream_body<DEPTH, ST>(C, w % waves_x, k, seg, nseg, C.ey_src, C.hz_src);
     return;
   }
-  if constexpr (!ST && !R4 && TY == 4)
-    fine2_fast<TY, NTC, TW>(F, b % nbx_f, b / nbx_f, F.cey_src, F.chz_src);
+  if constexpr (!ST && TY == 4)
+    fine2_fast<TY, NTC, TW, R4>(F, b % nbx_f, b / nbx_f, F.cey_src, F.chz_src);
   else
     fine2_tile<TY, NTC, true, ST, R4, TW>(F, b % nbx_f, b / nbx_f, F.cey_src, F.chz_src);
 }
@@ -2819,6 +2867,17 @@ int patch_tile_width(const EMArgs& F, int others) {
   return kTX;
 }
 
+// second r = 4 pair after a combined launch (4-row tiles of width tw)
+hipError_t launch_fine2_fast4(const EMArgs& A, int tw, hipStream_t st) {
+  if (A.rf != 4 || A.chz0 == nullptr) return hipErrorInvalidValue;
+  if (tw <= 0) tw = patch_tile_width(A, 0);
+  const dim3 g((A.R - A.L + 1 + tw - 1) / tw, (A.T - A.B + 1 + 3) / 4), b(step_threads(false, 4));
+  if (tw == 16) hipLaunchKernelGGL((k_fine2_fast4<16>), g, b, 0, st, A);
+  else if (tw == 32) hipLaunchKernelGGL((k_fine2_fast4<32>), g, b, 0, st, A);
+  else hipLaunchKernelGGL((k_fine2_fast4<kTX>), g, b, 0, st, A);
+  return hipGetLastError();
+}
+
 hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st) {
   if (A.rf == 4) {  // a pair of the four substeps, 1024 threads
     if (ty == 4) {
@@ -2865,7 +2924,7 @@ hipError_t launch_dmr_step(const EMArgs& C, const EMArgs& F, int seg, int depth,
   if (r4 && (ty != 4 || C.stix)) return hipErrorInvalidValue;  // 4-row tiles, no replay
   const int waves_x = (C.R + 1 + 61) / 62;
   const int nseg = stream_segments(C.T, seg);
-  const int nt = step_threads(C.stix != nullptr, ty, r4);
+  const int nt = step_threads(C.stix != nullptr, ty);
   const int wpb = nt / 64;
   const int ncb = (waves_x * nseg + wpb - 1) / wpb;
   if (ty != 4) tw = kTX;  // narrow tiles: 4-row tiles only
