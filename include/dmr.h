@@ -288,7 +288,8 @@ const char *dmr_last_error(const dmr_sim *s);
  * segment at a time (sqrt(N) checkpointing for ckpt_every ~ sqrt(steps)).
  *
  * Tape: caller-owned device memory (256-byte aligned) of
- * dmr_adjoint_tape_bytes; it holds the checkpoints, one segment of stored
+ * dmr_adjoint_tape_bytes; it holds the checkpoints (the coarse window planes
+ * once, plus one per window block of the run), two segments of stored
  * forward values and the adjoint state, and must stay untouched between
  * dmr_forward_record and dmr_backward. */
 int dmr_adjoint_tape_bytes(const dmr_params *p, int64_t steps, int ckpt_every,

@@ -1605,12 +1605,28 @@ const char* dmr_last_error(const dmr_sim* s) {
 namespace {
 
 constexpr int kAdjPlanes = 26;       // lam state + temporaries per level
-constexpr int kCkC = 16, kCkF = 15;  // planes per checkpoint (coarse, patch)
-constexpr int kStC = 6, kStF = 8;    // planes stored per replayed step
+// planes of the live state (coarse: Hz, Hz of the other half level, E, J, n,
+// acc, the kRing window planes; patch: Hz, E, J, n, acc, its window planes).
+// A tape checkpoint leaves out the coarse window planes: the tape logs each
+// window block's coarse plane once (the ring at a checkpoint is rebuilt from
+// that log and the ring at the start of the recording).
+constexpr int kLiveC = 8 + kRing, kCkF = 15;
+constexpr int kCkC = 8;  // coarse planes per tape checkpoint
+constexpr int kStC = 4, kStF = 4;    // planes stored per replayed step (E in, E out)
+constexpr int kBkC = 2, kBkF = 2;    // per window block of a segment (n, E_rms^2)
 
 struct TapeLayout {
   size_t adj_c = 0, adj_f = 0, ck = 0, ck_size = 0, store = 0, st_size = 0, src = 0,
          src_size = 0, u = 0, part = 0, part_per_step = 0, gsum = 0, wpart = 0, total = 0;
+  // a bank of stored steps: `every` step slots, then nbk window-block slots
+  // (the density is constant between continuity steps, E_rms^2 is taken at
+  // them), then the patch E after the last substep of the segment's last step
+  size_t bk_size = 0, last_size = 0, bank_size = 0;
+  int nbk = 0;
+  // the coarse window planes at the start of the recording, and one coarse
+  // window plane per block closed during it
+  size_t ring0 = 0, rlog = 0;
+  int nlog = 0;
   int nck = 0;
   int frows = 0;      // fine node rows a checkpoint / stored-step slot holds
   size_t fplane = 0;  // floats of one fine plane of such a slot
@@ -1638,8 +1654,17 @@ TapeLayout tape_layout(const dmr_params* p, int64_t steps, int every, int frows)
   T.nck = (int)((steps + every - 1) / every);
   T.ck_size = align256((L.plane0 * kCkC + T.fplane * kCkF) * f);
   T.ck = off; off += T.ck_size * (size_t)(T.nck + 1);
+  T.ring0 = off; off += align256(L.plane0 * kRing * f);
   T.st_size = align256((L.plane0 * kStC + T.fplane * kStF) * f);
-  T.store = off; off += T.st_size * (size_t)every * 2;  // two banks: replay / reverse overlap
+  // coarse steps per window block (as level_coeffs derives them)
+  const int spb = (int)std::lround(p->cells_per_lambda / p->courant) / kRing;
+  T.nbk = every / std::max(spb, 1) + 2;
+  T.nlog = (int)(steps / std::max(spb, 1)) + 2;
+  T.rlog = off; off += align256(L.plane0 * f) * (size_t)T.nlog;
+  T.bk_size = align256((L.plane0 * kBkC + T.fplane * kBkF) * f);
+  T.last_size = align256(T.fplane * 2 * f);
+  T.bank_size = T.st_size * (size_t)every + T.bk_size * (size_t)T.nbk + T.last_size;
+  T.store = off; off += T.bank_size * 2;  // two banks: replay / reverse overlap
   T.src_size = align256((size_t)2 * p->ny * f);
   T.src = off; off += T.src_size * (size_t)every;
   T.u = off; off += align256((size_t)2 * steps * sizeof(double));
@@ -1682,21 +1707,35 @@ AdjLevel adj_carve(char* base, size_t plane) {
   return a;
 }
 
-// stored values of step k of a segment in a bank.  The fine planes hold fine
-// rows [row0, row0 + T.frows) (row0: the first row of the segment's last
-// patch, which contains every patch of the segment); the pointers handed out
-// are offset so that entity (i, j) of the fine grid is at j * pitch + i, as
-// the kernels address it (only the patch rows are ever accessed).
-StepStore store_slot(const dmr_sim* s, const TapeLayout& T, int k, int bank, int row0) {
-  float* b = (float*)(s->tape.base + T.store + T.st_size * ((size_t)bank * s->tape.every + k));
+// stored values of step k (global index) of the segment starting at step
+// k0, in a bank.  The fine planes hold fine rows [row0, row0 + T.frows)
+// (row0: the first row of the segment's last patch, which contains every
+// patch of the segment); the pointers handed out are offset so that entity
+// (i, j) of the fine grid is at j * pitch + i, as the kernels address it
+// (only the patch rows are ever accessed).  Steps of one window block share
+// its density and E_rms^2 slot; every step of the segment shares the slot of
+// the patch E after the last substep (stored and read for the last step only).
+StepStore store_slot(const dmr_sim* s, const TapeLayout& T, int64_t k, int64_t k0, int bank,
+                     int row0) {
+  const int spb = std::max(s->L0.spb, 1);
+  const int blk = (int)(k / spb - k0 / spb);
+  char* bank0 = s->tape.base + T.store + T.bank_size * (size_t)bank;
+  float* b = (float*)(bank0 + T.st_size * (size_t)(k - k0));
+  float* bb = (float*)(bank0 + T.st_size * (size_t)s->tape.every + T.bk_size * (size_t)blk);
+  float* bl = (float*)(bank0 + T.st_size * (size_t)s->tape.every + T.bk_size * (size_t)T.nbk);
   const size_t p0 = s->L0.plane, fp = T.fplane;
+  const uintptr_t rowoff = (uintptr_t)row0 * s->L1.pitch * sizeof(float);
   StepStore ss;
   ss.cexi = b; ss.ceyi = b + p0; ss.cexp = b + 2 * p0; ss.ceyp = b + 3 * p0;
-  ss.cn = b + 4 * p0; ss.ce2 = b + 5 * p0;
-  const uintptr_t f = (uintptr_t)(b + kStC * p0) - (uintptr_t)row0 * s->L1.pitch * sizeof(float);
-  auto pl = [&](int q) { return (float*)(f + (uintptr_t)q * fp * sizeof(float)); };
-  ss.fex0 = pl(0); ss.fey0 = pl(1); ss.fex1 = pl(2); ss.fey1 = pl(3);
-  ss.fex2 = pl(4); ss.fey2 = pl(5); ss.fn = pl(6); ss.fe2 = pl(7);
+  ss.cn = bb; ss.ce2 = bb + p0;
+  auto pl = [&](float* base, int q) {
+    return (float*)((uintptr_t)base - rowoff + (uintptr_t)q * fp * sizeof(float));
+  };
+  float* fs = b + kStC * p0;
+  ss.fex0 = pl(fs, 0); ss.fey0 = pl(fs, 1); ss.fex1 = pl(fs, 2); ss.fey1 = pl(fs, 3);
+  float* fb = bb + kBkC * p0;
+  ss.fn = pl(fb, 0); ss.fe2 = pl(fb, 1);
+  ss.fex2 = pl(bl, 0); ss.fey2 = pl(bl, 1);
   return ss;
 }
 
@@ -1721,12 +1760,14 @@ void ck_planes(dmr_sim* s, float* live_c[9], float* live_f[15]) {
 // the buffer at q * fplane floats from its fine part, its row 0 being fine
 // row rowbase (a saved state: full planes, rowbase 0; a tape checkpoint:
 // planes of the tape's rows, rowbase the patch's first row)
-int ck_copy(dmr_sim* s, float* b, bool save, size_t fplane, int rowbase) {
+// ring: with the coarse window planes (the live state's layout), else
+// without them (a tape checkpoint)
+int ck_copy(dmr_sim* s, float* b, bool save, size_t fplane, int rowbase, bool ring = true) {
   float *lc[9], *lf[15];
   ck_planes(s, lc, lf);
   const size_t p0 = s->L0.plane;
   CopyJobs J{};
-  for (int q = 0; q < 9; q++) {
+  for (int q = 0; q < (ring ? 9 : 8); q++) {
     const size_t n = q == 8 ? kRing * p0 : p0;
     if (save) job(&J, lc[q], b + q * p0, n);
     else job(&J, b + q * p0, lc[q], n);
@@ -1736,7 +1777,7 @@ int ck_copy(dmr_sim* s, float* b, bool save, size_t fplane, int rowbase) {
     const int row = s->p.r * s->ext[1];
     const size_t off = (size_t)row * F.pitch;
     const size_t n = (size_t)(s->p.r * (s->ext[3] - s->ext[1]) + 1) * F.pitch;
-    float* fb = b + kCkC * p0 + (size_t)(row - rowbase) * F.pitch;
+    float* fb = b + (ring ? kLiveC : kCkC) * p0 + (size_t)(row - rowbase) * F.pitch;
     for (int q = 0; q < kCkF; q++) {
       if (save) job(&J, lf[q] + off, fb + q * fplane, n);
       else job(&J, fb + q * fplane, lf[q] + off, n);
@@ -1757,14 +1798,29 @@ int ck_save(dmr_sim* s, const TapeLayout& T, int idx, Ckpt* k) {
   k->step = s->step; k->blocks = s->blocks; k->ccur = s->ccur; k->ncur = s->ncur;
   k->has = s->has_patch; k->ty1 = s->ty1;
   for (int q = 0; q < 4; q++) k->ext[q] = s->ext[q];
-  return ck_copy(s, ck_base(s, T, idx), true, T.fplane, s->p.r * s->ext[1]);
+  return ck_copy(s, ck_base(s, T, idx), true, T.fplane, s->p.r * s->ext[1], false);
 }
 
 int ck_restore(dmr_sim* s, const TapeLayout& T, int idx, const Ckpt& k) {
   s->step = k.step; s->blocks = k.blocks; s->ccur = k.ccur; s->ncur = k.ncur;
   s->has_patch = k.has != 0; s->ty1 = k.ty1;
   for (int q = 0; q < 4; q++) s->ext[q] = k.ext[q];
-  return ck_copy(s, ck_base(s, T, idx), false, T.fplane, s->p.r * s->ext[1]);
+  if (int rc = ck_copy(s, ck_base(s, T, idx), false, T.fplane, s->p.r * s->ext[1], false)) return rc;
+  // coarse window plane q: the last block b < k.blocks with b = q (mod kRing)
+  // closed during the recording (which starts at block 0), else the ring at
+  // its start
+  const size_t p0 = s->L0.plane, lsz = align256(p0 * sizeof(float));
+  CopyJobs J{};
+  for (int q = 0; q < kRing; q++) {
+    const float* src = (const float*)(s->tape.base + T.ring0) + (size_t)q * p0;
+    if (k.blocks - 1 >= q) {
+      const int64_t b = q + (int64_t)kRing * ((k.blocks - 1 - q) / kRing);
+      if (b >= T.nlog) return fail(s, DMR_EINVAL, "window block %lld beyond the tape's log", (long long)b);
+      src = (const float*)(s->tape.base + T.rlog + lsz * (size_t)b);
+    }
+    job(&J, (float*)src, s->L0.ring + (size_t)q * p0, p0);
+  }
+  return run_copies(s, J);
 }
 
 AdjEMArgs adj_em_args(const dmr_sim* s, const Level& Lv, AdjLevel& a, bool fine,
@@ -1967,11 +2023,17 @@ uint64_t params_hash(const dmr_params& p) {
   return h;
 }
 
-// the union-of-blocks level appends its block map (one byte per block)
-size_t state_bytes(const dmr_sim* s) {
-  return kStateHeader + tape_layout(&s->p, 1, 1, 0).ck_size + (s->uni ? align256(s->h_act.size()) : 0);
+// the live planes of a saved state (the patch planes over the whole fine
+// grid); the union-of-blocks level appends its block map (one byte per block)
+size_t state_planes_bytes(const dmr_params* p) {
+  const Layout L = layout_of(p);
+  const size_t fplane = (size_t)(refined(p) ? p->r * p->ny + 1 : 0) * (size_t)L.pitch1;
+  return align256((L.plane0 * kLiveC + fplane * kCkF) * sizeof(float));
 }
-size_t state_map_offset(const dmr_sim* s) { return kStateHeader + tape_layout(&s->p, 1, 1, 0).ck_size; }
+size_t state_bytes(const dmr_sim* s) {
+  return kStateHeader + state_planes_bytes(&s->p) + (s->uni ? align256(s->h_act.size()) : 0);
+}
+size_t state_map_offset(const dmr_sim* s) { return kStateHeader + state_planes_bytes(&s->p); }
 
 // host-side copy of the live planes to / from a host buffer b (floats after
 // the header), the patch planes over the patch's rows only
@@ -1990,7 +2052,7 @@ int state_host_copy(dmr_sim* s, float* b, bool save) {
   if (s->has_patch) {
     const size_t off = (size_t)(s->p.r * s->ext[1]) * s->L1.pitch;
     const size_t n = (size_t)(s->p.r * (s->ext[3] - s->ext[1]) + 1) * s->L1.pitch;
-    float* fb = b + kCkC * p0;
+    float* fb = b + kLiveC * p0;
     for (int q = 0; q < kCkF; q++) {
       const hipError_t e = cp(lf[q] + off, fb + q * p1 + off, n);
       if (e != hipSuccess) return hipfail(s, e, "state copy");
@@ -2053,6 +2115,12 @@ int dmr_forward_record(dmr_sim* s, int64_t steps, int ckpt_every, void* d_tape, 
   tp.nck = T.nck;
   tp.frows = T.frows;
   tp.ck.resize(T.nck);
+  {  // the coarse window planes at the start
+    CopyJobs J{};
+    job(&J, s->L0.ring, (float*)(tp.base + T.ring0), kRing * s->L0.plane);
+    if (int rc = run_copies(s, J)) return rc;
+  }
+  const size_t lsz = align256(s->L0.plane * sizeof(float));
   for (int64_t k = 0; k < steps; k++) {
     if (k % ckpt_every == 0) {
       const int idx = (int)(k / ckpt_every);
@@ -2060,6 +2128,14 @@ int dmr_forward_record(dmr_sim* s, int64_t steps, int ckpt_every, void* d_tape, 
     }
     StepCtx cx;
     if (int rc = base_step(s, &cx)) return rc;
+    if (cx.meta.sync) {  // block blocks - 1 closed: log its coarse window plane
+      const int64_t b = s->blocks - 1;
+      if (b >= T.nlog) return fail(s, DMR_EINVAL, "window block %lld beyond the tape's log", (long long)b);
+      CopyJobs J{};
+      job(&J, s->L0.ring + (size_t)cx.meta.slot * s->L0.plane,
+          (float*)(tp.base + T.rlog + lsz * (size_t)b), s->L0.plane);
+      if (int rc = run_copies(s, J)) return rc;
+    }
     if (cx.meta.grow) {
       Growth g;
       g.after = k + 1;
@@ -2143,7 +2219,7 @@ int dmr_backward(dmr_sim* s, const void* d_tape, const float* d_w_coarse,
       StepCtx cx;
       cx.store = true;
       cx.last = k == k1 - 1;
-      cx.ss = store_slot(s, T, (int)(k - k0), bank, row0);
+      cx.ss = store_slot(s, T, k, k0, bank, row0);
       cx.forced = true;
       for (const Growth& g : tp.grow)
         if (g.after == k + 1) {
@@ -2160,8 +2236,8 @@ int dmr_backward(dmr_sim* s, const void* d_tape, const float* d_w_coarse,
     size_t npart = 0;
     for (int64_t k = k1 - 1; k >= k0; k--) {
       const int kk = (int)(k - k0);
-      const StepStore ss = store_slot(s, T, kk, bank, row0);
-      const StepStore nx = store_slot(s, T, kk + 1, bank, row0);
+      const StepStore ss = store_slot(s, T, k, k0, bank, row0);
+      const StepStore nx = store_slot(s, T, k + 1, k0, bank, row0);
       if (int rc2 = adj_step(s, T, ac, af, kk, meta[kk], ss, k == k1 - 1 ? nullptr : &nx, &npart))
         return rc2;
     }

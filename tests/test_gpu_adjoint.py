@@ -140,8 +140,11 @@ def test_config4_full_size():
     print("config 4: tape %.3f GB (%d fine rows); full-grid tape %.3f GB"
           % (g.tape.numel() / 1e9, rows, full / 1e9), flush=True)
     # what is left is the coarse part of the 46 checkpoints and of the two
-    # 45-step banks, and the adjoint state
+    # 45-step banks (the density and E_rms^2 once per window block, the
+    # coarse window planes once per block in a log rather than in every
+    # checkpoint), and the adjoint state
     assert g.tape.numel() <= 0.35 * full
+    assert g.tape.numel() <= 1.0e9
     F = g.weighted_sum(w)
     got = g.backward(w)
     seed = got["seed"].cpu().numpy().astype(np.float64)
