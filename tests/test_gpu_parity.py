@@ -220,6 +220,22 @@ def test_patch_tile_widths_bitwise():
             assert np.array_equal(v, runs[tw][k]) if k != "patch" else v == runs[tw][k], (tw, k)
 
 
+def test_r4_patch_tile_widths_bitwise():
+    """r = 4 with 4-row tiles runs both pairs of substeps in the frame tile of
+    the combined step; its tiles at widths 16, 32 and 64 and the four
+    one-substep launches give the same bits."""
+    cfg = W.make(64, 32, 16, "dynamic", 10, r=4, block=8, erms_over_ebd=3.0)
+    sb, sf = W.seeds(cfg, [(40 * LAM / 16, 16 * LAM / 16)], [3e17])
+    cfg["regrid_every"] = 2 * cfg["steps_per_period"]
+    runs = {tw: _env_run(cfg, sb, sf, {"DMR_TW": tw, "DMR_TY": "4"}, cfg["steps"])
+            for tw in ("16", "32", "64")}
+    runs["separate"] = _env_run(cfg, sb, sf, {"DMR_FUSE": "0"}, cfg["steps"])
+    assert np.abs(runs["16"][("ey", 1)]).max() > 0
+    for name in ("32", "64", "separate"):
+        for k, v in runs["16"].items():
+            assert np.array_equal(v, runs[name][k]) if k != "patch" else v == runs[name][k], (name, k)
+
+
 def _env_run(cfg, sb, sf, env, steps):
     import os
     old = {k: os.environ.get(k) for k in env}
