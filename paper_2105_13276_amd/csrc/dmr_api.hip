@@ -1066,7 +1066,7 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
       ev_begin(s, 1);
       if (combined) {  // the frame tile of the combined launch, for the second pair
         coarse_state(&G);
-        e = launch_fine2_fast4(G, s->tw1, s->st);
+        e = launch_fine2_fast(G, s->tw1, s->st);
       } else {
         e = launch_fine2(G, s->ty1, s->nt1, s->st);
       }
@@ -1081,7 +1081,12 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
     G.frac = 1.f / (float)p.r;  // time fraction of substep 1
     fine_stores(&G);
     ev_begin(s, 1);
-    e = launch_fine2(G, s->ty1, s->nt1, s->st);
+    if (s->ty1 == 4 && !kst) {  // 4-row tiles: the frame tile of the combined step
+      coarse_state(&G);
+      e = launch_fine2_fast(G, s->tw1, s->st);
+    } else {
+      e = launch_fine2(G, s->ty1, s->nt1, s->st);
+    }
     ev_end(s);
     if (e != hipSuccess) return hipfail(s, e, "fine EM launch");
     // the new state is in buffer 1: make it buffer 0

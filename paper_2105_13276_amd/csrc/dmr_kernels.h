@@ -164,7 +164,7 @@ hipError_t launch_prolong_union(const ProlongArgs& A, const int2* tiles, int nti
 // both patch substeps of a coarse step in one launch: reads buffer 0 (hz0..),
 // writes buffer 1 (hz1..), A.frac = time fraction of substep 1, restriction on
 hipError_t launch_fine2(const EMArgs& A, int ty, int nt, hipStream_t st);
-hipError_t launch_fine2_fast4(const EMArgs& A, int tw, hipStream_t st);
+hipError_t launch_fine2_fast(const EMArgs& A, int tw, hipStream_t st);
 // base-level step (C, with the patch's coarse entities skipped) and both patch
 // substeps (F, coarse boundary E computed in the tiles) in one launch
 hipError_t launch_dmr_step(const EMArgs& C, const EMArgs& F, int seg, int depth, int ty,

@@ -1263,8 +1263,10 @@ __device__ __forceinline__ void fine2_tile(const EMArgs& A, int bx, int by, floa
 }
 
 // ---------------------------------------------------------------------------
-// Both patch substeps of the combined step (rectangle, r = 2, patch tiles
-// computing the coarse boundary E themselves), laid out for short phases.
+// Both patch substeps of the combined step (rectangle, patch tiles computing
+// the coarse boundary E themselves), laid out for short phases.  R4: a pair
+// of the four r = 4 substeps (the first inside the base step's launch, the
+// second, with the r = 4 fine -> coarse transfer, in k_fine2_fast).
 // Every array of the tile lives in one LDS frame, the raw-E region of the
 // first substep (origin (-7, -7) from the tile corner, FW x FH), and each
 // thread owns fixed frame positions for the whole launch: their coordinates,
@@ -1667,13 +1669,15 @@ __global__ __launch_bounds__(NT) void k_fine2(EMArgs A) {
   fine2_tile<TY, NT, false, ST, R4, TW>(A, blockIdx.x, blockIdx.y, 0.f, 0.f);
 }
 
-// the second pair of r = 4 substeps (3, 4) and the fine -> coarse transfer
-// in the frame tile of the combined step: the tiles form the coarse E after
-// the coarse step on their boundary lines from the coarse state entering it
-// (its buffers are still intact), as in the combined launch
-template <int TW>
-__global__ __launch_bounds__(step_threads(false, 4)) void k_fine2_fast4(EMArgs A) {
-  fine2_fast<4, step_threads(false, 4), TW, true>(A, blockIdx.x, blockIdx.y, A.cey_src, A.chz_src);
+// Two patch substeps after the base step's own launch, in the frame tile of
+// the combined step: r = 2, both substeps and the fine -> coarse transfer;
+// R4, the second pair of r = 4 substeps (3, 4) and the transfer.  The tiles
+// form the coarse E after the coarse step on their boundary lines from the
+// coarse state entering it (its buffers are still intact), as in the
+// combined launch.
+template <int TW, bool R4>
+__global__ __launch_bounds__(step_threads(false, 4)) void k_fine2_fast(EMArgs A) {
+  fine2_fast<4, step_threads(false, 4), TW, R4>(A, blockIdx.x, blockIdx.y, A.cey_src, A.chz_src);
 }
 
 
@@ -2712,7 +2716,7 @@ __global__ __launch_bounds__(kThreads) void k_fine_stream(EMArgs A, int seg, int
 // ---------------------------------------------------------------------------
 // R4: refinement factor 4, the launch runs the base step and the first pair
 // of the four substeps (the second pair, with the fine -> coarse transfer,
-// is a k_fine2 launch of its own)
+// is a k_fine2_fast launch of its own)
 template <int DEPTH, int TY, bool ST = false, int TW = kTX, bool R4 = false>
 __global__ __launch_bounds__(step_threads(ST, TY)) void k_dmr_step(EMArgs C, EMArgs F, int seg,
                                                                        int nseg, int waves_x,
@@ -2867,14 +2871,21 @@ int patch_tile_width(const EMArgs& F, int others) {
   return kTX;
 }
 
-// second r = 4 pair after a combined launch (4-row tiles of width tw)
-hipError_t launch_fine2_fast4(const EMArgs& A, int tw, hipStream_t st) {
-  if (A.rf != 4 || A.chz0 == nullptr) return hipErrorInvalidValue;
+// two substeps in the frame tile after the base step's launch (4-row tiles
+// of width tw; r = 2: both substeps, r = 4: the second pair)
+hipError_t launch_fine2_fast(const EMArgs& A, int tw, hipStream_t st) {
+  if ((A.rf != 2 && A.rf != 4) || A.chz0 == nullptr || A.stix || A.st0x) return hipErrorInvalidValue;
   if (tw <= 0) tw = patch_tile_width(A, 0);
   const dim3 g((A.R - A.L + 1 + tw - 1) / tw, (A.T - A.B + 1 + 3) / 4), b(step_threads(false, 4));
-  if (tw == 16) hipLaunchKernelGGL((k_fine2_fast4<16>), g, b, 0, st, A);
-  else if (tw == 32) hipLaunchKernelGGL((k_fine2_fast4<32>), g, b, 0, st, A);
-  else hipLaunchKernelGGL((k_fine2_fast4<kTX>), g, b, 0, st, A);
+  if (A.rf == 4) {
+    if (tw == 16) hipLaunchKernelGGL((k_fine2_fast<16, true>), g, b, 0, st, A);
+    else if (tw == 32) hipLaunchKernelGGL((k_fine2_fast<32, true>), g, b, 0, st, A);
+    else hipLaunchKernelGGL((k_fine2_fast<kTX, true>), g, b, 0, st, A);
+  } else {
+    if (tw == 16) hipLaunchKernelGGL((k_fine2_fast<16, false>), g, b, 0, st, A);
+    else if (tw == 32) hipLaunchKernelGGL((k_fine2_fast<32, false>), g, b, 0, st, A);
+    else hipLaunchKernelGGL((k_fine2_fast<kTX, false>), g, b, 0, st, A);
+  }
   return hipGetLastError();
 }
 
