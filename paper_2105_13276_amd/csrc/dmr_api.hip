@@ -263,6 +263,9 @@ struct dmr_sim {
   int stream_force = -1;
   int fseg = 0, fdepth = 0;  // its rows per segment and load depth (0: by size)
   int nt1 = 1024;  // threads per patch tile
+  // continuity of both levels in one launch (small rectangular r = 2 patch);
+  // DMR_CONT_MERGE=0/1 forces either form
+  int cont_merge = -1;
   int tw1 = 0;     // patch tile width of the combined step (0: by patch size)
   uint8_t* d_flag = nullptr;
   int32_t *d_scan = nullptr, *d_list = nullptr;
@@ -1136,11 +1139,27 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
     ContArgs K;
     make_base_cont(s, s->ncur, &K);
     K.slot = slot; K.update = update;
-    ev_begin(s, 2);
-    e = launch_cont(K, false, s->st);
-    ev_end(s);
-    if (e != hipSuccess) return hipfail(s, e, "continuity launch");
-    if (s->has_patch) {
+    // a small rectangular r = 2 patch: both levels in one launch (its
+    // boundary lines take one block of their own)
+    const long perim = s->has_patch ? 2L * p.r * ((s->ext[2] - s->ext[0]) + (s->ext[3] - s->ext[1])) : 0;
+    const bool merge = s->has_patch && !s->uni && p.r == 2 &&
+                       (s->cont_merge >= 0 ? s->cont_merge == 1 : perim <= 2048);
+    if (merge) {
+      ContArgs G;
+      make_fine_cont(s, s->ncur, &G);
+      G.slot = slot; G.update = update;
+      K.pL = s->ext[0]; K.pB = s->ext[1]; K.pR = s->ext[2]; K.pT = s->ext[3];
+      ev_begin(s, 2);
+      e = launch_cont2(K, G, s->st);
+      ev_end(s);
+      if (e != hipSuccess) return hipfail(s, e, "continuity launch");
+    } else {
+      ev_begin(s, 2);
+      e = launch_cont(K, false, s->st);
+      ev_end(s);
+      if (e != hipSuccess) return hipfail(s, e, "continuity launch");
+    }
+    if (s->has_patch && !merge) {
       ContArgs G;
       make_fine_cont(s, s->ncur, &G);
       G.slot = slot; G.update = update;
@@ -1336,6 +1355,7 @@ int dmr_create(const dmr_params* p, const double* seed_base,
   if (const char* f = getenv("DMR_FNT")) s->nt1 = atoi(f) >= 1024 ? 1024 : 256;
   if (const char* f = getenv("DMR_TW")) { const int v = atoi(f); s->tw1 = (v == 16 || v == 32 || v == 64) ? v : 0; }
   if (const char* f = getenv("DMR_FINE_STREAM")) s->stream_force = atoi(f) != 0 ? 1 : 0;
+  if (const char* f = getenv("DMR_CONT_MERGE")) s->cont_merge = atoi(f) != 0 ? 1 : 0;
   if (const char* f = getenv("DMR_FINE_SEG")) s->fseg = atoi(f) >= 2 ? atoi(f) : 0;
   if (const char* f = getenv("DMR_FINE_DEPTH")) s->fdepth = atoi(f) >= 4 ? 4 : 2;
   s->depth0 = stream_depth(s->seg0);

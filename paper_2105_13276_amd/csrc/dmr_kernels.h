@@ -111,6 +111,10 @@ struct ContArgs {
   const uint8_t* act;
   int fbs, nbkx, nbky;
   const int2* utiles;  // batched union levels: the instance's tile list
+  // one-launch continuity of both levels (k_cont2): the patch's node extent
+  // in coarse nodes (pL < pR), whose boundary-line nodes a block of their own
+  // updates; 0 / 0: off
+  int pL, pB, pR, pT;
 };
 
 struct FlagArgs {
@@ -197,6 +201,7 @@ hipError_t launch_dmr_step_batch(const EMArgs* cargs, const EMArgs* fargs, const
 hipError_t launch_cont_batch(const ContArgs* args, const int2* blk, int nblk, bool fine,
                              int slot, int update, hipStream_t st);
 hipError_t launch_cont(const ContArgs& A, bool fine, hipStream_t st);
+hipError_t launch_cont2(const ContArgs& C, const ContArgs& F, hipStream_t st);
 hipError_t launch_regrid_test(const FlagArgs& F, const ScanArgs& S, hipStream_t st);
 hipError_t launch_prolong(const ProlongArgs& A, hipStream_t st);
 hipError_t launch_gather(const float* src, int pitch, int i0, int j0, int cols,

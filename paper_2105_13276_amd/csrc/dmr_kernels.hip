@@ -1752,12 +1752,26 @@ __device__ __forceinline__ float cont_update(const ContArgs& A, size_t o, float 
   return nn > 0.f ? nn : 0.f;
 }
 
-template <bool FINE>
+// MERGED (both levels in one launch, k_cont2): the coarse level leaves the
+// nodes on the patch boundary lines to the boundary block and does not
+// write the density of nodes strictly inside the patch (the injection
+// does); the patch level leaves its boundary nodes to the boundary block.
+template <bool FINE, bool MERGED = false, int NT = kThreads>
 __device__ __forceinline__ void cont_body(const ContArgs& A, int bx, int by, int slot,
                                           int update) {
   const int i = A.L + bx * kTX + (threadIdx.x % kTX);
-  const int j = A.B + by * (kThreads / kTX) + (threadIdx.x / kTX);
+  const int j = A.B + by * (NT / kTX) + (threadIdx.x / kTX);
   if (i > A.R || j > A.T) return;
+  bool inner = false;  // MERGED coarse level: strictly inside the patch
+  if constexpr (MERGED) {
+    if constexpr (FINE) {
+      if (i == A.L || i == A.R || j == A.B || j == A.T) return;
+    } else {
+      const bool inx = i >= A.pL && i <= A.pR, iny = j >= A.pB && j <= A.pT;
+      if ((inx && (j == A.pB || j == A.pT)) || (iny && (i == A.pL || i == A.pR))) return;
+      inner = i > A.pL && i < A.pR && j > A.pB && j < A.pT;
+    }
+  }
   const int pitch = A.pitch;
   const size_t o = (size_t)j * pitch + i;
   const float sv = A.acc[o] * A.inv_spp;
@@ -1792,8 +1806,113 @@ __device__ __forceinline__ void cont_body(const ContArgs& A, int bx, int by, int
       A.cn1[(size_t)b * A.cpitch + a] = nn;
     }
   }
+  if (inner) return;  // the injection writes it
   A.n1[o] = nn;
   if (!isfinite(nn) || !isfinite(e2)) A.err[threadIdx.x & 63] = 1;
+}
+
+// The boundary block of k_cont2 (kCont2Threads threads): thread t updates
+// the coarse node t of the patch boundary lines (as the coarse level does;
+// its new density also kept in LDS at that perimeter index) and the window
+// part of the patch's boundary nodes t and t + kCont2Threads; after the
+// barrier, their density from those coarse nodes (as the patch level
+// interpolates it).  Every load of a thread comes before its stores.
+constexpr int kCont2Threads = 1024;
+__device__ __forceinline__ void cont2_boundary(const ContArgs& C, const ContArgs& F) {
+  __shared__ float sCn[kCont2Threads];
+  const int t = threadIdx.x;
+  const int nx = C.pR - C.pL + 1, ny = C.pT - C.pB - 1;  // x-lines, y-lines (inner)
+  const int ncn = 2 * nx + 2 * (ny > 0 ? ny : 0);
+  const int fx = F.R - F.L + 1, fy = F.T - F.B - 1;
+  const int nfn = 2 * fx + 2 * (fy > 0 ? fy : 0);
+  auto cnode = [&](int k, int& i, int& j) {
+    if (k < 2 * nx) { i = C.pL + k % nx; j = k < nx ? C.pB : C.pT; }
+    else { const int q = k - 2 * nx; i = q < ny ? C.pL : C.pR; j = C.pB + 1 + q % ny; }
+  };
+  auto fnode = [&](int k, int& i, int& j) {
+    if (k < 2 * fx) { i = F.L + k % fx; j = k < fx ? F.B : F.T; }
+    else { const int q = k - 2 * fx; i = q < fy ? F.L : F.R; j = F.B + 1 + q % fy; }
+  };
+  // perimeter index of coarse node (a, b) on a boundary line
+  auto cidx = [&](int a, int b) {
+    if (b == C.pB) return a - C.pL;
+    if (b == C.pT) return nx + a - C.pL;
+    return 2 * nx + (a == C.pL ? 0 : ny) + (b - C.pB - 1);
+  };
+  // loads: the coarse node's window, the two patch nodes' windows, then the
+  // coarse update (its density stencil)
+  const bool hc = t < ncn, hf0 = t < nfn, hf1 = t + kCont2Threads < nfn;
+  int ci = C.pL, cj = C.pB, fi0 = F.L, fj0 = F.B, fi1 = F.L, fj1 = F.B;
+  if (hc) cnode(t, ci, cj);
+  if (hf0) fnode(t, fi0, fj0);
+  if (hf1) fnode(t + kCont2Threads, fi1, fj1);
+  const size_t co = (size_t)cj * C.pitch + ci;
+  const size_t fo0 = (size_t)fj0 * F.pitch + fi0, fo1 = (size_t)fj1 * F.pitch + fi1;
+  const float csv = C.acc[co] * C.inv_spp;
+  const float fsv0 = F.acc[fo0] * F.inv_spp, fsv1 = F.acc[fo1] * F.inv_spp;
+  float ce2 = 0.f, fe20 = 0.f, fe21 = 0.f;
+  if (C.update) {
+    for (int s = 0; s < kRing; s++) {
+      ce2 += (s == C.slot) ? csv : C.ring[(size_t)s * C.plane + co];
+      fe20 += (s == F.slot) ? fsv0 : F.ring[(size_t)s * F.plane + fo0];
+      fe21 += (s == F.slot) ? fsv1 : F.ring[(size_t)s * F.plane + fo1];
+    }
+  }
+  float cnn = 0.f;
+  if (C.update && hc) cnn = cont_update(C, co, ce2, ci > C.L, ci < C.R, cj > C.B, cj < C.T);
+  // stores
+  if (hc) {
+    C.ring[(size_t)C.slot * C.plane + co] = csv;
+    C.acc[co] = 0.f;
+    if (C.update) {
+      C.n1[co] = cnn;
+      sCn[t] = cnn;
+      if (!isfinite(cnn) || !isfinite(ce2)) C.err[t & 63] = 1;
+    } else if (!isfinite(csv)) {
+      C.err[t & 63] = 1;
+    }
+  }
+  if (hf0) {
+    F.ring[(size_t)F.slot * F.plane + fo0] = fsv0;
+    F.acc[fo0] = 0.f;
+    if (C.update ? !isfinite(fe20) : !isfinite(fsv0)) F.err[t & 63] = 1;
+  }
+  if (hf1) {
+    F.ring[(size_t)F.slot * F.plane + fo1] = fsv1;
+    F.acc[fo1] = 0.f;
+    if (C.update ? !isfinite(fe21) : !isfinite(fsv1)) F.err[t & 63] = 1;
+  }
+  __syncthreads();
+  if (!F.update) return;
+  auto interp = [&](int i, int j) {
+    const int a = i >> 1, b = j >> 1;
+    if (((i | j) & 1) == 0) return sCn[cidx(a, b)];
+    if (i & 1) return 0.5f * (sCn[cidx(a, b)] + sCn[cidx(a + 1, b)]);
+    return 0.5f * (sCn[cidx(a, b)] + sCn[cidx(a, b + 1)]);
+  };
+  if (hf0) {
+    const float nn = interp(fi0, fj0);
+    F.n1[fo0] = nn;
+    if (!isfinite(nn)) F.err[t & 63] = 1;
+  }
+  if (hf1) {
+    const float nn = interp(fi1, fj1);
+    F.n1[fo1] = nn;
+    if (!isfinite(nn)) F.err[t & 63] = 1;
+  }
+}
+
+// Continuity of both levels in one launch (r = 2 rectangle): blocks
+// [0, ncb) the coarse level, [ncb, ncb + nfb) the patch, the last block the
+// boundary lines.  Every node is updated by one thread; no block reads what
+// another writes.
+__global__ __launch_bounds__(kCont2Threads) void k_cont2(ContArgs C, ContArgs F, int gxc, int ncb,
+                                                         int gxf, int nfb) {
+  const int b = blockIdx.x;
+  if (b < ncb) cont_body<false, true, kCont2Threads>(C, b % gxc, b / gxc, C.slot, C.update);
+  else if (b < ncb + nfb)
+    cont_body<true, true, kCont2Threads>(F, (b - ncb) % gxf, (b - ncb) / gxf, F.slot, F.update);
+  else cont2_boundary(C, F);
 }
 
 template <bool FINE>
@@ -3093,6 +3212,21 @@ hipError_t launch_cont(const ContArgs& A, bool fine, hipStream_t st) {
   dim3 g((nx + kTX - 1) / kTX, (ny + kThreads / kTX - 1) / (kThreads / kTX));
   if (fine) hipLaunchKernelGGL(k_cont<true>, g, dim3(kThreads), 0, st, A);
   else hipLaunchKernelGGL(k_cont<false>, g, dim3(kThreads), 0, st, A);
+  return hipGetLastError();
+}
+
+// both levels' continuity in one launch (r = 2 rectangle; C.pL..C.pT set)
+hipError_t launch_cont2(const ContArgs& C, const ContArgs& F, hipStream_t st) {
+  if (F.rf == 4 || F.act || C.pR <= C.pL || C.pT <= C.pB) return hipErrorInvalidValue;
+  // the boundary block: one coarse node and two patch nodes per thread
+  const long nfn = 2L * (F.R - F.L + 1) + 2L * (F.T - F.B - 1);
+  const long ncn = 2L * (C.pR - C.pL + 1) + 2L * (C.pT - C.pB - 1);
+  if (nfn > 2L * kCont2Threads || ncn > kCont2Threads) return hipErrorInvalidValue;
+  const int rows = kCont2Threads / kTX;
+  const int gxc = (C.R - C.L + 1 + kTX - 1) / kTX, gyc = (C.T - C.B + 1 + rows - 1) / rows;
+  const int gxf = (F.R - F.L + 1 + kTX - 1) / kTX, gyf = (F.T - F.B + 1 + rows - 1) / rows;
+  hipLaunchKernelGGL(k_cont2, dim3(gxc * gyc + gxf * gyf + 1), dim3(kCont2Threads), 0, st, C, F,
+                     gxc, gxc * gyc, gxf, gxf * gyf);
   return hipGetLastError();
 }
 

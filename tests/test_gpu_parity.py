@@ -220,6 +220,23 @@ def test_patch_tile_widths_bitwise():
             assert np.array_equal(v, runs[tw][k]) if k != "patch" else v == runs[tw][k], (tw, k)
 
 
+def test_merged_continuity_bitwise():
+    """The continuity step of both levels in one launch (coarse blocks, patch
+    blocks and one block for the patch boundary lines; the default for small
+    rectangular patches) against a launch per level, over 10 periods with
+    growth (window filling, then density updates): the same bits."""
+    cfg = W.make(128, 64, 32, "dynamic", 10, erms_over_ebd=3.0)
+    sb, sf = W.seeds(cfg, [(80 * LAM / 32, 32 * LAM / 32)], [3e17])
+    cfg["regrid_every"] = 2 * cfg["steps_per_period"]
+    a = _env_run(cfg, sb, sf, {"DMR_CONT_MERGE": "1"}, cfg["steps"])
+    b = _env_run(cfg, sb, sf, {"DMR_CONT_MERGE": "0"}, cfg["steps"])
+    assert a["patch"] == b["patch"]
+    assert np.abs(a[("n", 1)]).max() > 0
+    for k, v in a.items():
+        if k != "patch":
+            assert np.array_equal(v, b[k]), k
+
+
 def test_r4_patch_tile_widths_bitwise():
     """r = 4 with 4-row tiles runs both pairs of substeps in the frame tile of
     the combined step; its tiles at widths 16, 32 and 64 and the four
