@@ -59,10 +59,12 @@ PHYSICS = dict(
     # (gamma = A p exp(-B p / E_eff), v_d = mu_e E_eff, separate attachment);
     # air A = 15 /(cm Torr), B = 365 V/(cm Torr) (the textbook fit for
     # E/p ~ 100-800); attachment = the power law's attachment part
-    # nu_m A_ion (E_cr/p)^beta; recombination beta_rec in [0, 2] (0: none)
+    # nu_m A_ion (E_cr/p)^beta; recombination beta_rec in [0, 2] (0: none).
+    # nu_att: that attachment part at 700 Torr, nu_m = 5.3e9 p (Sec. II.A),
+    # A_ion = 9.02e-14, E_cr/p = 2.5e6 / 760 / 100 V/(cm Torr), beta = 5.3
     source_model="power",
     A_town=15.0, B_town=365.0,
-    nu_att=5.3e9 * 700.0 * 9.02e-14 * (2.5e6 / 760.0 / 100.0) ** 5.3,
+    nu_att=36757879.86472408,
     beta_rec=0.0,
 )
 
