@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--only-config2-union", action="store_true",
                     help="profiling aid: run only 256 coarse steps of config 2 with the "
                          "union-of-blocks fine level, no JSON")
+    ap.add_argument("--only-large-uniform", action="store_true",
+                    help="profiling aid: run only 16 uniform steps of the 8192x4096 grid, no JSON")
     ap.add_argument("--only-config2-box", action="store_true",
                     help="profiling aid: run only 64 coarse steps of config 2 with the "
                          "bounding-box patch, no JSON")
@@ -96,6 +98,18 @@ def only_config2_box(steps=64):
     sim.step(steps)
     sim.sync()
     print("only-config2-box: %d steps, patch %s" % (steps, sim.patch()), flush=True)
+
+
+def only_large_uniform(steps=16):
+    """Profiling aid: uniform steps of the 8192x4096 grid (the uniform-fine
+    reference of the large rows), from t = 0."""
+    from paper_2105_13276_amd import binding as B
+    from paper_2105_13276_amd import workloads as W
+    cfg = W.config_large_uniform(periods=1)
+    sim = B.Sim(cfg, W.seeds(cfg, fine=False)[0], None)
+    sim.step(steps)
+    sim.sync()
+    print("only-large-uniform: %d steps of %dx%d" % (steps, cfg["nx"], cfg["ny"]), flush=True)
 
 
 def only_large(steps=48):
@@ -296,6 +310,9 @@ def main():
         return
     if args.only_config2_box:
         only_config2_box()
+        return
+    if args.only_large_uniform:
+        only_large_uniform()
         return
     import numpy as np
     import torch
