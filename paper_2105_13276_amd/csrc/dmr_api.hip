@@ -1019,7 +1019,7 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
     G->cnx = p.nx; G->cny = p.ny;
   };
   if (combined) {  // base step and both patch substeps (r = 4: the first pair), one launch
-    Level &C = s->L0, &F = s->L1;
+    Level& F = s->L1;
     A.skip_on = r4 ? 0 : 1;
     A.sL = s->ext[0]; A.sB = s->ext[1]; A.sR = s->ext[2]; A.sT = s->ext[3];
     EMArgs G;
