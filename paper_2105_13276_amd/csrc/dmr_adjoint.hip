@@ -102,12 +102,15 @@ __device__ inline float ll13(const float v[13], int i, int j, OK ok) {
 // from one buffer and written to another, so no block reads what another
 // block writes in the same launch.
 // ---------------------------------------------------------------------------
-// Tiles: patch 32 x 16 positions (phase-1 region 38 x 22, phase-2 36 x 20),
-// base level 32 x 28 (34 x 30, phase 2 = the tile); 1024 threads, so every
+// Tiles: patch 16 x 5 positions (phase-1 region 22 x 11, phase-2 20 x 9),
+// base level 32 x 5 (34 x 7, phase 2 = the tile); 256 threads, so every
 // phase is one position per thread and all of a thread's loads for both
-// phases are issued before any arithmetic.
+// phases are issued before any arithmetic.  On a 512 x 256 base level the
+// sweep is latency-bound: small blocks spread over every CU beat large
+// ones despite the recomputed halos (1024-thread 32 x 28 / 32 x 16 tiles
+// took 37% longer per reverse step, 512-thread ones 10%).
 template <bool FINE> struct AdjTile {
-  static constexpr int TX = 32, TY = FINE ? 16 : 28, NT = 1024;
+  static constexpr int TX = FINE ? 16 : 32, TY = 5, NT = 256;
   static constexpr int H1 = FINE ? 3 : 1, H2 = FINE ? 2 : 0;
   static constexpr int W1 = TX + 2 * H1, N1 = TY + 2 * H1;
   static constexpr int W2 = TX + 2 * H2, N2 = TY + 2 * H2;
@@ -955,9 +958,9 @@ __global__ __launch_bounds__(AdjTile<FINE>::NT) void k_adj_em(AdjEMArgs A) {
 
 // patch substep 1 (blocks [0, nbf)) and the base level (the rest) of a base
 // step: independent (the base level forms substep 1's boundary G itself)
-__global__ __launch_bounds__(1024) void k_adj_em_pair(AdjEMArgs F, AdjEMArgs C, int nbf,
+__global__ __launch_bounds__(AdjTile<true>::NT) void k_adj_em_pair(AdjEMArgs F, AdjEMArgs C, int nbf,
                                                       int nbfx, int nbcx) {
-  static_assert(AdjTile<true>::NT == 1024 && AdjTile<false>::NT == 1024, "one block shape");
+  static_assert(AdjTile<true>::NT == AdjTile<false>::NT, "one block shape");
   const int b = blockIdx.x;
   if (b < nbf) adj_em_tile<true>(F, b % nbfx, b / nbfx);
   else adj_em_tile<false>(C, (b - nbf) % nbcx, (b - nbf) / nbcx);
@@ -969,7 +972,7 @@ hipError_t launch_adj_em_pair(const AdjEMArgs& F, const AdjEMArgs& C, hipStream_
   const int nbfx = (F.R - F.L + TF::TX) / TF::TX, nbfy = (F.T - F.B + TF::TY) / TF::TY;
   const int nbcx = (C.R - C.L + TC::TX) / TC::TX, nbcy = (C.T - C.B + TC::TY) / TC::TY;
   const int nbf = nbfx * nbfy;
-  k_adj_em_pair<<<nbf + nbcx * nbcy, 1024, 0, st>>>(F, C, nbf, nbfx, nbcx);
+  k_adj_em_pair<<<nbf + nbcx * nbcy, TF::NT, 0, st>>>(F, C, nbf, nbfx, nbcx);
   return hipGetLastError();
 }
 
