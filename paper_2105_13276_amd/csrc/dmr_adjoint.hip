@@ -696,12 +696,14 @@ __device__ inline float d_eff_prime(const AdjContArgs& A, float n) {
   return A.inv_namb * (A.Da - A.De) / ((1.f + al) * (1.f + al));
 }
 
-constexpr int kCTX = 32, kCTY = 16, kCW = kCTX + 2, kCH = kCTY + 2;
+constexpr int kCTX = kAdjContTX, kCTY = kAdjContTY, kCW = kCTX + 2, kCH = kCTY + 2;
+constexpr int kCWaves = kAdjContThreads / 64;
+static_assert(kCW * kCH <= kAdjContThreads, "one position per thread");
 
 __device__ __forceinline__ void adj_cont_tile(const AdjContArgs& A, int bx, int by,
                                               size_t blk) {
   __shared__ float sEll[kCH][kCW], sN[kCH][kCW];
-  __shared__ double sA[16], sB[16];
+  __shared__ double sA[kCWaves], sB[kCWaves];
   const int i0 = A.L + bx * kCTX, j0 = A.B + by * kCTY;
   const int tid = threadIdx.x;
   const int p = A.pitch;
@@ -786,7 +788,7 @@ __device__ __forceinline__ void adj_cont_tile(const AdjContArgs& A, int bx, int 
   __syncthreads();
   if (tid == 0) {
     double a = 0.0, b = 0.0;
-    for (int k = 0; k < 16; k++) { a += sA[k]; b += sB[k]; }
+    for (int k = 0; k < kCWaves; k++) { a += sA[k]; b += sB[k]; }
     A.part[2 * blk] = a;
     A.part[2 * blk + 1] = b;
   }
@@ -828,7 +830,7 @@ __device__ __forceinline__ void adj_cont_tile(const AdjContArgs& A, int bx, int 
 }
 
 // blocks [0, nbf): the patch (F), the rest: the base level (C)
-__global__ __launch_bounds__(1024) void k_adj_cont(AdjContArgs F, AdjContArgs C, int nbf,
+__global__ __launch_bounds__(kAdjContThreads) void k_adj_cont(AdjContArgs F, AdjContArgs C, int nbf,
                                                    int nbfx, int nbcx) {
   const int b = blockIdx.x;
   if (b < nbf) adj_cont_tile(F, b % nbfx, b / nbfx, b);
@@ -1013,7 +1015,7 @@ hipError_t launch_adj_cont(const AdjContArgs& F, const AdjContArgs& C, int has_f
   const int nbf = has_f ? nbfx * ((F.T - F.B + kCTY) / kCTY) : 0;
   const int nbcx = (C.R - C.L + kCTX) / kCTX;
   const int nbc = nbcx * ((C.T - C.B + kCTY) / kCTY);
-  k_adj_cont<<<nbf + nbc, 1024, 0, st>>>(F, C, nbf, nbfx > 0 ? nbfx : 1, nbcx);
+  k_adj_cont<<<nbf + nbc, kAdjContThreads, 0, st>>>(F, C, nbf, nbfx > 0 ? nbfx : 1, nbcx);
   *nparts = nbf + nbc;
   return hipGetLastError();
 }

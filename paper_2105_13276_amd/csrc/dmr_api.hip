@@ -1661,8 +1661,10 @@ struct TapeLayout {
   size_t fplane = 0;  // floats of one fine plane of such a slot
 };
 
+// continuity-adjoint blocks over the nodes of a w x h-cell level (one
+// partial-sum pair each)
 size_t node_blocks(int w, int h) {
-  return (size_t)((w + 1 + 63) / 64) * (size_t)((h + 1 + 3) / 4);
+  return (size_t)((w + kAdjContTX) / kAdjContTX) * (size_t)((h + kAdjContTY) / kAdjContTY);
 }
 
 // The tape for `steps` base steps, a checkpoint every `every`, when every

@@ -10,6 +10,9 @@ constexpr int kTX = 64;        // tile width in nodes: one wavefront per row
 constexpr int kThreads = 256;  // threads per tile
 constexpr int kFineThreads = 1024;  // threads per patch tile (phases run from LDS)
 constexpr int kTileSgprs = 72;  // scalar-register cap of the 1024-thread tile kernels
+// continuity-adjoint tiles: node columns x rows per block, threads per block
+// (the tape sizes its per-block partial sums from the tile)
+constexpr int kAdjContTX = 32, kAdjContTY = 5, kAdjContThreads = 256;
 // threads per block of the combined step: 512 for its 4-row patch tiles (one
 // frame position per thread on small patches, and half as many base-level
 // waves per compute unit), else the patch tile's 1024
