@@ -890,16 +890,16 @@ __global__ __launch_bounds__(1024) void k_adj_reduce(const float* src, int nstep
                                                      const double* u, const double* part,
                                                      int nparts, double* out) {
   __shared__ double sh[16];
+  // every (step, row) pair of the segment at once: a thread's loads do not
+  // wait on one another (a loop over steps would be one memory round trip
+  // per step)
   double e0 = 0.0;
-  for (int k = 0; k < nsteps; k++) {
+  const int n = nsteps * rows;
+#pragma unroll 8
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    const int k = t / rows, q = t - k * rows;
     const float* se = src + (size_t)k * step_pitch;
-    const float* sh_ = se + rows;
-    double a = 0.0, b = 0.0;
-    for (int q = threadIdx.x; q < rows; q += blockDim.x) {
-      a += (double)se[q];
-      b += (double)sh_[q];
-    }
-    e0 += u[2 * k] * a + u[2 * k + 1] * b;
+    e0 += u[2 * k] * (double)se[q] + u[2 * k + 1] * (double)se[rows + q];
   }
   double pa = 0.0, pb = 0.0;
   for (int q = threadIdx.x; q < nparts; q += blockDim.x) {
