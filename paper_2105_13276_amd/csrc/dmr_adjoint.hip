@@ -672,8 +672,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_inj(AdjInjArgs A) {
 
 // ---------------------------------------------------------------------------
 // Window close and continuity step (Eq. (4)) transposed, one launch for both
-// levels: a block owns a 32 x 16 tile of nodes and works over the tile grown
-// by one node.
+// levels: a block owns a kAdjContTX x kAdjContTY tile of nodes (32 x 5) and
+// works over the tile grown by one node.
 // Phase 1 (tile + halo): recompute the forward update, clamp mask, ell =
 // mask * lam n'; at the own nodes also the E_rms^2 lam into the ring and the
 // accumulator (close transposed) and the dF/dA, dF/dbeta partials.  Patch
