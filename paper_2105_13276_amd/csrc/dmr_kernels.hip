@@ -50,8 +50,10 @@ __device__ inline float faraday(float ho, float S, float dey, float dex) {
   return ho - S * (dey - dex);
 }
 // Ampere + Drude, Eqs. (1), (3): new E from the old E, the curl term and J~
+// (times the hardware reciprocal of 1 + kap, as the base level: two
+// instructions where a correctly rounded division takes eleven)
 __device__ inline float ampere(float e, float kap, float curl, float c1, float jo) {
-  return ((1.f - kap) * e + curl - c1 * jo) / (1.f + kap);
+  return ((1.f - kap) * e + curl - c1 * jo) * __builtin_amdgcn_rcpf(1.f + kap);
 }
 // new J~ = a J~ + 2k (E + E+)
 __device__ inline float drude(float a, float jo, float kap, float e, float en) {
