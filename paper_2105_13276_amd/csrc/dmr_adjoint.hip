@@ -311,7 +311,7 @@ __device__ inline void p1_compute(const AdjEMArgs& A, const Reg& g, int i, int j
         const float ab = m[0] + 2.f * m[1] * (wwin(i, L, R) * m[2] + wwin(i + 1, L, R) * m[3]);
         tot += A.cmur * (ab + 2.f * kapf(m[4], m[5]) * m[6]);
       }
-      gx = (tot + 2.f * kap * xlj) / (1.f + kap);
+      gx = (tot + 2.f * kap * xlj) * __builtin_amdgcn_rcpf(1.f + kap);  // the forward's factor
       kx = (eo + v.xen) * (2.f * xlj - gx);
     } else {
       gx = tot + 2.f * kap * xlj;
@@ -330,7 +330,7 @@ __device__ inline void p1_compute(const AdjEMArgs& A, const Reg& g, int i, int j
         const float ab = m[0] + 2.f * m[1] * (wwin(j, B, T) * m[2] + wwin(j + 1, B, T) * m[3]);
         tot += A.cmur * (ab + 2.f * kapf(m[4], m[5]) * m[6]);
       }
-      gy = (tot + 2.f * kap * ylj) / (1.f + kap);
+      gy = (tot + 2.f * kap * ylj) * __builtin_amdgcn_rcpf(1.f + kap);
       ky = (eo + v.yen) * (2.f * ylj - gy);
     } else {
       gy = tot + 2.f * kap * ylj;
