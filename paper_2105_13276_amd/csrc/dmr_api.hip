@@ -1145,7 +1145,7 @@ int base_step(dmr_sim* s, StepCtx* cx = nullptr) {
     // slower on 4096 x 2048, where the coarse level streams better in the
     // plain launch)
     const long perim = s->has_patch ? 2L * p.r * ((s->ext[2] - s->ext[0]) + (s->ext[3] - s->ext[1])) : 0;
-    const bool merge = s->has_patch && !s->uni && p.r == 2 && perim <= 2048 &&
+    const bool merge = s->has_patch && !s->uni && (p.r == 2 || p.r == 4) && perim <= 2048 &&
                        s->ext[2] > s->ext[0] && s->ext[3] > s->ext[1] &&
                        (s->cont_merge >= 0 ? s->cont_merge == 1 : (long)p.nx * p.ny <= (1L << 19));
     if (merge) {

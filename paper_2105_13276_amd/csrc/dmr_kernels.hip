@@ -1816,10 +1816,12 @@ __device__ __forceinline__ void cont_body(const ContArgs& A, int bx, int by, int
 // The boundary block of k_cont2 (kCont2Threads threads): thread t updates
 // the coarse node t of the patch boundary lines (as the coarse level does;
 // its new density also kept in LDS at that perimeter index) and the window
-// part of the patch's boundary nodes t and t + kCont2Threads; after the
+// part of the patch's boundary nodes t + q kCont2Threads, q < RF; after the
 // barrier, their density from those coarse nodes (as the patch level
-// interpolates it).  Every load of a thread comes before its stores.
+// interpolates it: r = 2 copy or mean, r = 4 linear along the line).  Every
+// load of a thread comes before its stores.
 constexpr int kCont2Threads = 1024;
+template <int RF>
 __device__ __forceinline__ void cont2_boundary(const ContArgs& C, const ContArgs& F) {
   __shared__ float sCn[kCont2Threads];
   const int t = threadIdx.x;
@@ -1841,23 +1843,32 @@ __device__ __forceinline__ void cont2_boundary(const ContArgs& C, const ContArgs
     if (b == C.pT) return nx + a - C.pL;
     return 2 * nx + (a == C.pL ? 0 : ny) + (b - C.pB - 1);
   };
-  // loads: the coarse node's window, the two patch nodes' windows, then the
+  // loads: the coarse node's window, the patch nodes' windows, then the
   // coarse update (its density stencil)
-  const bool hc = t < ncn, hf0 = t < nfn, hf1 = t + kCont2Threads < nfn;
-  int ci = C.pL, cj = C.pB, fi0 = F.L, fj0 = F.B, fi1 = F.L, fj1 = F.B;
+  const bool hc = t < ncn;
+  int ci = C.pL, cj = C.pB;
   if (hc) cnode(t, ci, cj);
-  if (hf0) fnode(t, fi0, fj0);
-  if (hf1) fnode(t + kCont2Threads, fi1, fj1);
+  bool hf[RF];
+  int fi[RF], fj[RF];
+  size_t fo[RF];
+  float fsv[RF], fe2[RF];
+#pragma unroll
+  for (int q = 0; q < RF; q++) {
+    hf[q] = t + q * kCont2Threads < nfn;
+    fi[q] = F.L; fj[q] = F.B;
+    if (hf[q]) fnode(t + q * kCont2Threads, fi[q], fj[q]);
+    fo[q] = (size_t)fj[q] * F.pitch + fi[q];
+    fsv[q] = F.acc[fo[q]] * F.inv_spp;
+    fe2[q] = 0.f;
+  }
   const size_t co = (size_t)cj * C.pitch + ci;
-  const size_t fo0 = (size_t)fj0 * F.pitch + fi0, fo1 = (size_t)fj1 * F.pitch + fi1;
   const float csv = C.acc[co] * C.inv_spp;
-  const float fsv0 = F.acc[fo0] * F.inv_spp, fsv1 = F.acc[fo1] * F.inv_spp;
-  float ce2 = 0.f, fe20 = 0.f, fe21 = 0.f;
+  float ce2 = 0.f;
   if (C.update) {
     for (int s = 0; s < kRing; s++) {
       ce2 += (s == C.slot) ? csv : C.ring[(size_t)s * C.plane + co];
-      fe20 += (s == F.slot) ? fsv0 : F.ring[(size_t)s * F.plane + fo0];
-      fe21 += (s == F.slot) ? fsv1 : F.ring[(size_t)s * F.plane + fo1];
+#pragma unroll
+      for (int q = 0; q < RF; q++) fe2[q] += (s == F.slot) ? fsv[q] : F.ring[(size_t)s * F.plane + fo[q]];
     }
   }
   float cnn = 0.f;
@@ -1874,47 +1885,51 @@ __device__ __forceinline__ void cont2_boundary(const ContArgs& C, const ContArgs
       C.err[t & 63] = 1;
     }
   }
-  if (hf0) {
-    F.ring[(size_t)F.slot * F.plane + fo0] = fsv0;
-    F.acc[fo0] = 0.f;
-    if (C.update ? !isfinite(fe20) : !isfinite(fsv0)) F.err[t & 63] = 1;
-  }
-  if (hf1) {
-    F.ring[(size_t)F.slot * F.plane + fo1] = fsv1;
-    F.acc[fo1] = 0.f;
-    if (C.update ? !isfinite(fe21) : !isfinite(fsv1)) F.err[t & 63] = 1;
+#pragma unroll
+  for (int q = 0; q < RF; q++) {
+    if (!hf[q]) continue;
+    F.ring[(size_t)F.slot * F.plane + fo[q]] = fsv[q];
+    F.acc[fo[q]] = 0.f;
+    if (C.update ? !isfinite(fe2[q]) : !isfinite(fsv[q])) F.err[t & 63] = 1;
   }
   __syncthreads();
   if (!F.update) return;
   auto interp = [&](int i, int j) {
-    const int a = i >> 1, b = j >> 1;
-    if (((i | j) & 1) == 0) return sCn[cidx(a, b)];
-    if (i & 1) return 0.5f * (sCn[cidx(a, b)] + sCn[cidx(a + 1, b)]);
-    return 0.5f * (sCn[cidx(a, b)] + sCn[cidx(a, b + 1)]);
+    if constexpr (RF == 4) {
+      const int a = i >> 2, b = j >> 2;
+      const float ti = (i & 3) * 0.25f, tj = (j & 3) * 0.25f;
+      const float c00 = sCn[cidx(a, b)];
+      if ((i & 3) != 0) return (1.f - ti) * c00 + ti * sCn[cidx(a + 1, b)];
+      if ((j & 3) != 0) return (1.f - tj) * c00 + tj * sCn[cidx(a, b + 1)];
+      return c00;
+    } else {
+      const int a = i >> 1, b = j >> 1;
+      if (((i | j) & 1) == 0) return sCn[cidx(a, b)];
+      if (i & 1) return 0.5f * (sCn[cidx(a, b)] + sCn[cidx(a + 1, b)]);
+      return 0.5f * (sCn[cidx(a, b)] + sCn[cidx(a, b + 1)]);
+    }
   };
-  if (hf0) {
-    const float nn = interp(fi0, fj0);
-    F.n1[fo0] = nn;
-    if (!isfinite(nn)) F.err[t & 63] = 1;
-  }
-  if (hf1) {
-    const float nn = interp(fi1, fj1);
-    F.n1[fo1] = nn;
+#pragma unroll
+  for (int q = 0; q < RF; q++) {
+    if (!hf[q]) continue;
+    const float nn = interp(fi[q], fj[q]);
+    F.n1[fo[q]] = nn;
     if (!isfinite(nn)) F.err[t & 63] = 1;
   }
 }
 
-// Continuity of both levels in one launch (r = 2 rectangle): blocks
-// [0, ncb) the coarse level, [ncb, ncb + nfb) the patch, the last block the
-// boundary lines.  Every node is updated by one thread; no block reads what
-// another writes.
+// Continuity of both levels in one launch (rectangular patch, r = 2 or 4):
+// blocks [0, ncb) the coarse level, [ncb, ncb + nfb) the patch, the last
+// block the boundary lines.  Every node is updated by one thread; no block
+// reads what another writes.
+template <int RF>
 __global__ __launch_bounds__(kCont2Threads) void k_cont2(ContArgs C, ContArgs F, int gxc, int ncb,
                                                          int gxf, int nfb) {
   const int b = blockIdx.x;
   if (b < ncb) cont_body<false, true, kCont2Threads>(C, b % gxc, b / gxc, C.slot, C.update);
   else if (b < ncb + nfb)
     cont_body<true, true, kCont2Threads>(F, (b - ncb) % gxf, (b - ncb) / gxf, F.slot, F.update);
-  else cont2_boundary(C, F);
+  else cont2_boundary<RF>(C, F);
 }
 
 template <bool FINE>
@@ -3219,16 +3234,19 @@ hipError_t launch_cont(const ContArgs& A, bool fine, hipStream_t st) {
 
 // both levels' continuity in one launch (r = 2 rectangle; C.pL..C.pT set)
 hipError_t launch_cont2(const ContArgs& C, const ContArgs& F, hipStream_t st) {
-  if (F.rf == 4 || F.act || C.pR <= C.pL || C.pT <= C.pB) return hipErrorInvalidValue;
-  // the boundary block: one coarse node and two patch nodes per thread
+  if ((F.rf != 2 && F.rf != 4) || F.act || C.pR <= C.pL || C.pT <= C.pB) return hipErrorInvalidValue;
+  // the boundary block: one coarse node and r patch nodes per thread
   const long nfn = 2L * (F.R - F.L + 1) + 2L * (F.T - F.B - 1);
   const long ncn = 2L * (C.pR - C.pL + 1) + 2L * (C.pT - C.pB - 1);
-  if (nfn > 2L * kCont2Threads || ncn > kCont2Threads) return hipErrorInvalidValue;
+  if (nfn > (long)F.rf * kCont2Threads || ncn > kCont2Threads) return hipErrorInvalidValue;
   const int rows = kCont2Threads / kTX;
   const int gxc = (C.R - C.L + 1 + kTX - 1) / kTX, gyc = (C.T - C.B + 1 + rows - 1) / rows;
   const int gxf = (F.R - F.L + 1 + kTX - 1) / kTX, gyf = (F.T - F.B + 1 + rows - 1) / rows;
-  hipLaunchKernelGGL(k_cont2, dim3(gxc * gyc + gxf * gyf + 1), dim3(kCont2Threads), 0, st, C, F,
-                     gxc, gxc * gyc, gxf, gxf * gyf);
+  const dim3 g(gxc * gyc + gxf * gyf + 1);
+  if (F.rf == 4)
+    hipLaunchKernelGGL(k_cont2<4>, g, dim3(kCont2Threads), 0, st, C, F, gxc, gxc * gyc, gxf, gxf * gyf);
+  else
+    hipLaunchKernelGGL(k_cont2<2>, g, dim3(kCont2Threads), 0, st, C, F, gxc, gxc * gyc, gxf, gxf * gyf);
   return hipGetLastError();
 }
 

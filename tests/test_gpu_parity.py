@@ -237,6 +237,22 @@ def test_merged_continuity_bitwise():
             assert np.array_equal(v, b[k]), k
 
 
+def test_merged_continuity_bitwise_r4():
+    """The one-launch continuity step with an r = 4 patch (four patch nodes per
+    coarse node on the boundary lines, linear along them) against a launch
+    per level, over 10 periods with growth: the same bits."""
+    cfg = W.make(64, 32, 16, "dynamic", 10, r=4, block=8, erms_over_ebd=3.0)
+    sb, sf = W.seeds(cfg, [(40 * LAM / 16, 16 * LAM / 16)], [3e17])
+    cfg["regrid_every"] = 2 * cfg["steps_per_period"]
+    a = _env_run(cfg, sb, sf, {"DMR_CONT_MERGE": "1"}, cfg["steps"])
+    b = _env_run(cfg, sb, sf, {"DMR_CONT_MERGE": "0"}, cfg["steps"])
+    assert a["patch"] == b["patch"]
+    assert np.abs(a[("n", 1)]).max() > 0
+    for k, v in a.items():
+        if k != "patch":
+            assert np.array_equal(v, b[k]), k
+
+
 def test_r4_patch_tile_widths_bitwise():
     """r = 4 with 4-row tiles runs both pairs of substeps in the frame tile of
     the combined step; its tiles at widths 16, 32 and 64 and the four
